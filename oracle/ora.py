@@ -1,0 +1,130 @@
+"""ctypes binding of the C oracle (test infrastructure only).
+
+Functions take and return numpy float64 arrays in the modal layout
+[nc, k+1, ncell] (1D) used by ``paper_2503_12473_amd.inputs``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+ORA_OK = 0
+ORA_ERRORS = {-1: "EINVAL", -2: "ENOMEM", -4: "ENONFINITE", -5: "ENONPHYSICAL"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"oracle {where} failed: {ORA_ERRORS.get(code, code)}")
+        self.code = code
+
+
+class Ora1D(C.Structure):
+    _fields_ = [("k", C.c_int), ("nc", C.c_int), ("flux", C.c_int), ("bc", C.c_int), ("n", C.c_long),
+                ("xlo", C.c_double), ("xhi", C.c_double), ("a", C.c_double), ("gamma", C.c_double)]
+
+
+_lib = None
+_DP = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        P1 = C.POINTER(Ora1D)
+        L.ora_legendre.restype = C.c_double
+        L.ora_legendre.argtypes = [C.c_int, C.c_double]
+        L.ora_legendre_deriv.restype = C.c_double
+        L.ora_legendre_deriv.argtypes = [C.c_int, C.c_int, C.c_double]
+        L.ora_gauss_legendre.argtypes = [C.c_int, _DP, _DP]
+        L.ora1d_rhs.argtypes = [P1, C.c_double, _DP, _DP, _DP, _DP]
+        L.ora1d_oe.argtypes = [P1, C.c_double, _DP, _DP]
+        L.ora1d_delta.argtypes = [P1, _DP, _DP, _DP, _DP]
+        L.ora1d_stats.argtypes = [P1, _DP, _DP, _DP, _DP]
+        L.ora1d_stats.restype = None
+        L.ora1d_max_wavespeed.argtypes = [P1, _DP, _DP]
+        L.ora1d_max_wavespeed.restype = C.c_double
+        L.ora1d_step.argtypes = [P1, C.c_int, C.c_int, C.c_double, C.c_double, _DP, _DP]
+        L.ora1d_run.argtypes = [P1, C.c_double, C.c_int, C.c_int, C.c_double, C.c_long, C.c_double,
+                                _DP, _DP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
+        _lib = L
+    return _lib
+
+
+def _p1(prob):
+    return Ora1D(prob.k, prob.nc, prob.flux, prob.bc, prob.n, prob.xlo, prob.xhi, prob.a, prob.gamma)
+
+
+def _arr(u):
+    return np.ascontiguousarray(np.asarray(u, dtype=np.float64))
+
+
+def _check(rc, where):
+    if rc != ORA_OK:
+        raise OracleError(rc, where)
+
+
+def gauss_legendre(Q):
+    s = np.zeros(Q)
+    w = np.zeros(Q)
+    lib().ora_gauss_legendre(Q, s, w)
+    return s, w
+
+
+def legendre(n, x, deriv=0):
+    return lib().ora_legendre_deriv(n, deriv, float(x))
+
+
+def rhs1d(prob, tau_max, uC, uD):
+    uC, uD = _arr(uC), _arr(uD)
+    LC, LD = np.zeros_like(uC), np.zeros_like(uD)
+    _check(lib().ora1d_rhs(C.byref(_p1(prob)), tau_max, uC, uD, LC, LD), "rhs1d")
+    return LC, LD
+
+
+def oe1d(prob, tau, uC, uD):
+    uC, uD = _arr(uC).copy(), _arr(uD).copy()
+    _check(lib().ora1d_oe(C.byref(_p1(prob)), tau, uC, uD), "oe1d")
+    return uC, uD
+
+
+def delta1d(prob, uC, uD):
+    uC, uD = _arr(uC), _arr(uD)
+    dC = np.zeros((prob.k + 1, prob.n))
+    dD = np.zeros((prob.k + 1, prob.n_dual))
+    _check(lib().ora1d_delta(C.byref(_p1(prob)), uC, uD, dC, dD), "delta1d")
+    return dC, dD
+
+
+def stats1d(prob, uC, uD):
+    """avg, sigma as arrays [mesh, q] (mesh 0 primal, 1 dual)."""
+    avg = np.zeros(6)
+    sig = np.zeros(6)
+    lib().ora1d_stats(C.byref(_p1(prob)), _arr(uC), _arr(uD), avg, sig)
+    return avg.reshape(2, 3)[:, :prob.nc], sig.reshape(2, 3)[:, :prob.nc]
+
+
+def max_wavespeed1d(prob, uC, uD):
+    return lib().ora1d_max_wavespeed(C.byref(_p1(prob)), _arr(uC), _arr(uD))
+
+
+def step1d(prob, tau, tau_max, uC, uD, rk=3, oe=True):
+    uC, uD = _arr(uC).copy(), _arr(uD).copy()
+    _check(lib().ora1d_step(C.byref(_p1(prob)), rk, int(oe), tau, tau_max, uC, uD), "step1d")
+    return uC, uD
+
+
+def run1d(prob, uC, uD, t_end=float("inf"), nsteps=-1, cfl=0.3, dt_fixed=0.0, rk=3, oe=True):
+    """March to t_end (clipped last step) or nsteps steps; returns (uC, uD, t, steps)."""
+    uC, uD = _arr(uC).copy(), _arr(uD).copy()
+    t = C.c_double(0.0)
+    n = C.c_long(0)
+    _check(lib().ora1d_run(C.byref(_p1(prob)), cfl, rk, int(oe), t_end, nsteps, dt_fixed, uC, uD,
+                           C.byref(t), C.byref(n)), "run1d")
+    return uC, uD, t.value, n.value

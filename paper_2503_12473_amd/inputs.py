@@ -1,0 +1,297 @@
+"""Seeded synthetic inputs for the OECDG workloads.
+
+This module only builds problem descriptions and initial data: it draws the
+seeded random parameters, evaluates the analytic initial conditions, and
+L2-projects them onto the Legendre modal bases of the primal and dual meshes
+(the projection-based initialisation discussed after the optimal error
+theorem, Sec. 3.3).  It holds none of the method's arithmetic (no CDG
+operator, no damping, no time stepping), so both the HIP path and the CPU
+oracle can take their inputs from it.
+
+Mesh convention shared by every consumer: primal cell i of a 1D mesh of n
+cells on [xlo, xhi] is [xlo + i h, xlo + (i+1) h]; dual cell j is centred on
+the left edge of primal cell j, i.e. [xlo + (j - 1/2) h, xlo + (j + 1/2) h],
+for j = 0..n-1 (periodic) or j = 0..n (outflow).  Modal arrays are C-contiguous
+float64 of shape [nc, k+1, ncell].  In 2D, primal cell (i, j) is
+[xlo + i hx, xlo + (i+1) hx] x [ylo + j hy, ylo + (j+1) hy], dual cell (i, j)
+is centred on the primal vertex (xlo + i hx, ylo + j hy), and arrays have
+shape [nc, k+1, k+1, ny, nx] (mode a in x, mode b in y).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+from numpy.polynomial import legendre as _npleg
+
+FLUX_ADVECTION = 0
+FLUX_BURGERS = 1
+FLUX_EULER = 2
+BC_PERIODIC = 0
+BC_OUTFLOW = 1
+
+GAMMA = 1.4
+
+
+@dataclasses.dataclass(frozen=True)
+class Problem1D:
+    k: int
+    nc: int
+    flux: int
+    bc: int
+    n: int
+    xlo: float
+    xhi: float
+    a: float = 1.0          # advection speed
+    gamma: float = GAMMA    # adiabatic index
+
+    @property
+    def h(self) -> float:
+        return (self.xhi - self.xlo) / self.n
+
+    @property
+    def n_dual(self) -> int:
+        return self.n if self.bc == BC_PERIODIC else self.n + 1
+
+    def shapes(self):
+        return (self.nc, self.k + 1, self.n), (self.nc, self.k + 1, self.n_dual)
+
+    def dofs(self) -> int:
+        return self.nc * (self.k + 1) * (self.n + self.n_dual)
+
+
+@dataclasses.dataclass(frozen=True)
+class Problem2D:
+    k: int
+    nc: int
+    flux: int
+    nx: int
+    ny: int
+    xlo: float
+    xhi: float
+    ylo: float
+    yhi: float
+    a: float = 1.0
+    b: float = 1.0
+    gamma: float = GAMMA
+
+    @property
+    def hx(self) -> float:
+        return (self.xhi - self.xlo) / self.nx
+
+    @property
+    def hy(self) -> float:
+        return (self.yhi - self.ylo) / self.ny
+
+    def shape(self):
+        return (self.nc, self.k + 1, self.k + 1, self.ny, self.nx)
+
+    def dofs(self) -> int:
+        return 2 * self.nc * (self.k + 1) ** 2 * self.nx * self.ny
+
+
+# --------------------------------------------------------------------------
+# L2 projection of initial data (8 Gauss points on each half cell / quadrant)
+# --------------------------------------------------------------------------
+
+def _half_rule(nq: int = 8):
+    s, w = _npleg.leggauss(nq)
+    xi = np.concatenate([(s - 1.0) / 2.0, (s + 1.0) / 2.0])
+    wi = np.concatenate([w / 2.0, w / 2.0])
+    return xi, wi
+
+
+def _legendre_table(k: int, xi: np.ndarray) -> np.ndarray:
+    return np.stack([_npleg.legval(xi, [0.0] * m + [1.0]) for m in range(k + 1)])
+
+
+def project_1d(func, prob: Problem1D, nq: int = 8):
+    """Project func (x of any shape -> array [nc, *x.shape]) on both meshes.
+
+    Each cell is split at its centre so that jumps on primal edges or dual
+    centres are integrated exactly."""
+    xi, wi = _half_rule(nq)
+    P = _legendre_table(prob.k, xi)                       # [k+1, G]
+    norm = (2.0 * np.arange(prob.k + 1) + 1.0) / 2.0
+    h = prob.h
+
+    def proj(centres):
+        x = centres[:, None] + 0.5 * h * xi[None, :]     # [ncell, G]
+        vals = np.asarray(func(x), dtype=np.float64).reshape(prob.nc, *x.shape)
+        a = np.einsum("qcg,mg,g->qmc", vals, P, wi) * norm[None, :, None]
+        return np.ascontiguousarray(a)
+
+    cC = prob.xlo + (np.arange(prob.n) + 0.5) * h
+    cD = prob.xlo + np.arange(prob.n_dual) * h
+    return proj(cC), proj(cD)
+
+
+def project_2d(func, prob: Problem2D, nq: int = 8, chunk_rows: int = 64):
+    """Project func (x, y -> [nc, *x.shape]) on both 2D meshes (tensor Q^k modes)."""
+    xi, wi = _half_rule(nq)
+    P = _legendre_table(prob.k, xi)
+    norm = (2.0 * np.arange(prob.k + 1) + 1.0) / 2.0
+    hx, hy = prob.hx, prob.hy
+    out = []
+    for shift in (0.5, 0.0):                              # primal centres, dual centres
+        cx = prob.xlo + (np.arange(prob.nx) + shift) * hx
+        res = np.empty(prob.shape(), dtype=np.float64)
+        for j0 in range(0, prob.ny, chunk_rows):
+            j1 = min(prob.ny, j0 + chunk_rows)
+            cy = prob.ylo + (np.arange(j0, j1) + shift) * hy
+            X = cx[None, :, None, None] + 0.5 * hx * xi[None, None, :, None]
+            Y = cy[:, None, None, None] + 0.5 * hy * xi[None, None, None, :]
+            X, Y = np.broadcast_arrays(X, Y)              # [rows, nx, Gx, Gy]
+            vals = np.asarray(func(X, Y), dtype=np.float64).reshape(prob.nc, *X.shape)
+            a = np.einsum("qyxgh,ag,bh,g,h->qabyx", vals, P, P, wi, wi, optimize=True)
+            res[:, :, :, j0:j1, :] = a * norm[None, :, None, None, None] * norm[None, None, :, None, None]
+        out.append(np.ascontiguousarray(res))
+    return out[0], out[1]
+
+
+# --------------------------------------------------------------------------
+# Workloads
+# --------------------------------------------------------------------------
+
+def euler_conserved(rho, u, p, gamma=GAMMA):
+    return np.stack([rho, rho * u, p / (gamma - 1.0) + 0.5 * rho * u * u])
+
+
+def advection_sine(n: int, k: int, phase: float = 0.0, xlo=0.0, xhi=2.0 * math.pi, a=1.0, freq=1.0):
+    """u_t + a u_x = 0 on a periodic interval, u0 = sin(freq*(x - xlo)*2pi/L + phase)."""
+    prob = Problem1D(k=k, nc=1, flux=FLUX_ADVECTION, bc=BC_PERIODIC, n=n, xlo=xlo, xhi=xhi, a=a)
+    L = xhi - xlo
+    uC, uD = project_1d(lambda x: np.sin(freq * 2.0 * math.pi * (x - xlo) / L + phase)[None], prob)
+    return prob, uC, uD
+
+
+def advection_phases(seed: int, count: int = 1):
+    """Seeded phases phi ~ U[0, 2 pi) for sin(x + phi)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, 2.0 * math.pi, size=count)
+
+
+def advection_square(n: int, k: int, lo=0.5 * math.pi, hi=1.5 * math.pi, xlo=0.0, xhi=2.0 * math.pi):
+    """Square wave: 1 on [lo, hi], 0 elsewhere, periodic."""
+    prob = Problem1D(k=k, nc=1, flux=FLUX_ADVECTION, bc=BC_PERIODIC, n=n, xlo=xlo, xhi=xhi, a=1.0)
+    L = xhi - xlo
+
+    def f(x):
+        y = np.mod(x - xlo, L) + xlo
+        return ((y >= lo) & (y < hi)).astype(np.float64)[None]
+
+    uC, uD = project_1d(f, prob)
+    return prob, uC, uD
+
+
+def riemann_states(seed: int):
+    """(rho_L, p_L, rho_R, p_R), each ~ U[0.1, 1], drawn in that order; u = 0."""
+    rng = np.random.default_rng(seed)
+    rl, pl, rr, pr = rng.uniform(0.1, 1.0, size=4)
+    return float(rl), float(pl), float(rr), float(pr)
+
+
+def euler_riemann(n: int, k: int, states, x0=0.5, xlo=0.0, xhi=1.0, gamma=GAMMA):
+    """1D Euler two-state Riemann problem with outflow boundaries."""
+    rl, pl, rr, pr = states
+    prob = Problem1D(k=k, nc=3, flux=FLUX_EULER, bc=BC_OUTFLOW, n=n, xlo=xlo, xhi=xhi, gamma=gamma)
+
+    def f(x):
+        left = x < x0
+        rho = np.where(left, rl, rr)
+        p = np.where(left, pl, pr)
+        return euler_conserved(rho, np.zeros_like(rho), p, gamma)
+
+    uC, uD = project_1d(f, prob)
+    return prob, uC, uD
+
+
+def burgers_fourier_params(seed: int, modes: int = 8):
+    """A_j ~ N(0, 0.3^2) then phi_j ~ U[0, 2 pi), j = 1..modes."""
+    rng = np.random.default_rng(seed)
+    A = rng.normal(0.0, 0.3, size=modes)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=modes)
+    return A, phi
+
+
+def burgers_fourier(n: int, k: int, seed: int, modes: int = 8):
+    """Burgers on [0, 2 pi] periodic, u0 = sum_j A_j sin(j x + phi_j)."""
+    A, phi = burgers_fourier_params(seed, modes)
+    prob = Problem1D(k=k, nc=1, flux=FLUX_BURGERS, bc=BC_PERIODIC, n=n, xlo=0.0, xhi=2.0 * math.pi)
+
+    def f(x):
+        v = np.zeros_like(x)
+        for j in range(modes):
+            v = v + A[j] * np.sin((j + 1) * x + phi[j])
+        return v[None]
+
+    uC, uD = project_1d(f, prob)
+    return prob, uC, uD, (A, phi)
+
+
+def burgers_sine(n: int, k: int):
+    """Burgers on [0, 2 pi] periodic, u0 = sin x + 0.5 (smooth accuracy example)."""
+    prob = Problem1D(k=k, nc=1, flux=FLUX_BURGERS, bc=BC_PERIODIC, n=n, xlo=0.0, xhi=2.0 * math.pi)
+    uC, uD = project_1d(lambda x: (np.sin(x) + 0.5)[None], prob)
+    return prob, uC, uD
+
+
+def batch_instances(seed: int, count: int = 512, nmin=128, nmax=8192, kset=(1, 2, 3), k_fixed=None):
+    """Per instance, in order: N ~ U{nmin..nmax}, k ~ U{kset}, then the four
+    Riemann state draws (rho_L, p_L, rho_R, p_R) ~ U[0.1, 1]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(nmin, nmax + 1))
+        k = int(rng.choice(np.asarray(kset)))
+        st = tuple(float(v) for v in rng.uniform(0.1, 1.0, size=4))
+        out.append((n, k_fixed if k_fixed is not None else k, st))
+    return out
+
+
+def euler2d_quadrants(n: int, k: int, seed: int, gamma=GAMMA):
+    """2D Euler on [0,1]^2 periodic: rho = 1 + 0.2 sin(2 pi (x+y)) + rho_q and
+    (u, v, p) = (u_q, v_q, p_q) on the four quadrants split at 0.5, with
+    (rho_q, p_q) ~ U[0.2, 1] and u_q, v_q ~ U[-0.5, 0.5], drawn per quadrant in
+    the order SW, SE, NW, NE as (rho, p, u, v)."""
+    rng = np.random.default_rng(seed)
+    quads = []
+    for _ in range(4):
+        rq, pq = rng.uniform(0.2, 1.0, size=2)
+        uq, vq = rng.uniform(-0.5, 0.5, size=2)
+        quads.append((rq, pq, uq, vq))
+    quads = np.asarray(quads)
+    prob = Problem2D(k=k, nc=4, flux=FLUX_EULER, nx=n, ny=n, xlo=0.0, xhi=1.0, ylo=0.0, yhi=1.0, gamma=gamma)
+
+    def f(X, Y):
+        xm = np.mod(X, 1.0)
+        ym = np.mod(Y, 1.0)
+        qi = (xm >= 0.5).astype(np.int64) + 2 * (ym >= 0.5).astype(np.int64)
+        rq, pq, uq, vq = (quads[:, c][qi] for c in range(4))
+        rho = 1.0 + 0.2 * np.sin(2.0 * math.pi * (X + Y)) + rq
+        E = pq / (gamma - 1.0) + 0.5 * rho * (uq * uq + vq * vq)
+        return np.stack([rho, rho * uq, rho * vq, E])
+
+    uC, uD = project_2d(f, prob)
+    return prob, uC, uD, quads
+
+
+def euler2d_smooth(n: int, k: int, gamma=GAMMA):
+    """Steady smooth 2D Euler solution rho = 1 + 0.2 sin(pi (x - y)), u = v = p = 1 on [0,2]^2."""
+    prob = Problem2D(k=k, nc=4, flux=FLUX_EULER, nx=n, ny=n, xlo=0.0, xhi=2.0, ylo=0.0, yhi=2.0, gamma=gamma)
+
+    def f(X, Y):
+        rho = 1.0 + 0.2 * np.sin(math.pi * (X - Y))
+        one = np.ones_like(X)
+        return np.stack([rho, rho, rho, 1.0 / (gamma - 1.0) + rho])
+
+    uC, uD = project_2d(f, prob)
+    return prob, uC, uD
+
+
+def advection2d_sine(n: int, k: int):
+    """u_t + u_x + u_y = 0 on [0,1]^2 periodic, u0 = sin^2(pi (x + y))."""
+    prob = Problem2D(k=k, nc=1, flux=FLUX_ADVECTION, nx=n, ny=n, xlo=0.0, xhi=1.0, ylo=0.0, yhi=1.0)
+    uC, uD = project_2d(lambda X, Y: (np.sin(math.pi * (X + Y)) ** 2)[None], prob)
+    return prob, uC, uD
