@@ -1,0 +1,167 @@
+/*
+ * oecdg.h -- C ABI of the MI355X (gfx950) implementation of the
+ * oscillation-eliminating central DG (OECDG) method of Peng, Wu and Yuan,
+ * "Oscillation-eliminating central DG schemes for hyperbolic conservation
+ * laws" (arXiv 2503.12473).
+ *
+ * The library advances the pair (u^C, u^D) of piecewise polynomials on the
+ * primal mesh and the dual mesh (Sec. 2.1, the semi-discrete CDG system
+ * equcdg) with the fully discrete RK-OECDG scheme (Sec. 2.2, eq. RKCDG):
+ * an SSP-RK3 stage update followed, after every stage, by the OE step F_tau
+ * (damping ODE OEstep2D, solved exactly).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All numbers are IEEE FP64.  All state pointers are DEVICE pointers to
+ *    caller-owned memory (e.g. torch tensors on the GPU); the library never
+ *    frees them.  The library owns its scratch from oecdg_init to
+ *    oecdg_destroy.
+ *  - Modal coefficients are in the unnormalised Legendre basis P_m(xi),
+ *    xi = 2 (x - x_K)/h, so coefficient 0 is the cell average.
+ *  - 1D layout: u[(q*(k+1) + m)*ncell + i], component q, mode m, cell i
+ *    (structure of arrays, cells fastest).  Primal cell i is
+ *    [xlo + i h, xlo + (i+1) h], h = (xhi - xlo)/nx.  Dual cell j is centred
+ *    on the left edge of primal cell j: [xlo + (j-1/2) h, xlo + (j+1/2) h];
+ *    there are nx dual cells with periodic boundaries and nx+1 with outflow
+ *    boundaries (the last one centred on xhi).  Outflow ghost primal cells
+ *    (-1 and nx) are the constant extensions of the averages of cells 0 and
+ *    nx-1.
+ *  - 2D layout (tensor-product Q^k modes): u[(((q*(k+1) + a)*(k+1) + b)*ny
+ *    + iy)*nx + ix], mode a in x, b in y.  Primal cell (ix, iy) is
+ *    [xlo + ix hx, xlo + (ix+1) hx] x [ylo + iy hy, ylo + (iy+1) hy]; dual
+ *    cell (ix, iy) is centred on the primal vertex (xlo + ix hx, ylo + iy hy).
+ *    2D meshes are periodic.
+ *  - Every call is enqueued on the HIP stream given to oecdg_init.  Calls
+ *    that return host scalars synchronise that stream before returning.
+ *  - Entry points return OECDG_OK (0) or a negative error code; no C++
+ *    exception crosses the ABI.  oecdg_last_error() gives a message.
+ *  - A handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef OECDG_H
+#define OECDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque handle: library-owned scratch, tables and launch state. */
+typedef struct oecdg_handle oecdg_handle;
+
+enum {
+    OECDG_OK = 0,
+    OECDG_EINVAL = -1,          /* bad descriptor, size, pointer or argument */
+    OECDG_ENOMEM = -2,          /* device or host allocation failed */
+    OECDG_EHIP = -3,            /* HIP runtime error (message in oecdg_last_error) */
+    OECDG_ENONFINITE = -4,      /* a NaN/Inf coefficient was produced */
+    OECDG_ENONPHYSICAL = -5,    /* Euler: density or pressure <= 0 at a cell average */
+    OECDG_EUNSUPPORTED = -6,    /* valid but not implemented combination */
+    OECDG_ETIMEOUT = -7         /* a device-side grid barrier exceeded its spin limit */
+};
+
+enum { OECDG_FLUX_ADVECTION = 0, OECDG_FLUX_BURGERS = 1, OECDG_FLUX_EULER = 2 };
+enum { OECDG_BC_PERIODIC = 0, OECDG_BC_OUTFLOW = 1 };
+
+/* Execution modes of oecdg_run (oecdg_set_option(OECDG_OPT_MODE, ...)). */
+enum {
+    OECDG_MODE_AUTO = 0,        /* library choice */
+    OECDG_MODE_EAGER = 1,       /* one kernel launch per RK stage */
+    OECDG_MODE_GRAPH = 2,       /* the three stage kernels of several steps captured in a hipGraph */
+    OECDG_MODE_PERSISTENT = 3   /* one cooperative launch, grid barrier between stages */
+};
+
+/* Option keys for oecdg_set_option. */
+enum {
+    OECDG_OPT_MODE = 1,         /* OECDG_MODE_* */
+    OECDG_OPT_TILE = 2,         /* primal cells per workgroup tile: 32, 64 or 128 (1D) */
+    OECDG_OPT_GRAPH_STEPS = 3,  /* steps per captured graph (>= 1) */
+    OECDG_OPT_GRID = 4          /* workgroups of the persistent launch (0: library choice) */
+};
+
+/* Problem descriptor (one instance).  Sec. 2.1 defines the meshes and the
+ * operator; tau_max = cfl h / max|f'(u)| in 1D and
+ * cfl / (max|f_1'|/hx + max|f_2'|/hy) in 2D (Sec. 2.1 and Sec. 4), with the
+ * maxima over the cell averages of both meshes. */
+typedef struct {
+    int32_t dim;                /* 1 or 2 */
+    int32_t k;                  /* polynomial degree: 0..3 in 1D; 2 (tensor Q2) in 2D */
+    int32_t flux;               /* OECDG_FLUX_*: 1D any; 2D advection or Euler */
+    int32_t bc;                 /* OECDG_BC_*; 2D: periodic only */
+    int64_t nx, ny;             /* primal cells per direction (ny = 1 in 1D) */
+    double xlo, xhi, ylo, yhi;  /* domain (ylo, yhi ignored in 1D) */
+    double flux_param[2];       /* advection: speeds (a, b); Euler: {gamma, 0}; Burgers: unused */
+    double cfl;                 /* C_CFL */
+    int32_t oe;                 /* 1: OECDG (OE step after every stage); 0: plain CDG */
+    int32_t reserved;           /* must be 0 */
+} oecdg_desc;
+
+/* Number of doubles of the primal and dual state arrays of one instance. */
+int oecdg_state_size(const oecdg_desc *d, int64_t *n_primal, int64_t *n_dual);
+
+/* Create a handle for nbatch >= 1 instances described by d[0..nbatch-1]
+ * (nbatch > 1: 1D instances only, each with its own nx, k, flux, bc and
+ * cfl).  With nbatch > 1 the state arrays passed to the other entry points
+ * are the concatenation of the instances' arrays in order (offsets from
+ * oecdg_batch_offsets).  stream: a hipStream_t (NULL = default stream). */
+int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle **out);
+
+/* Element offsets of each instance's arrays inside the concatenated batch
+ * arrays; off_primal and off_dual each hold nbatch+1 entries (the last is the
+ * total).  Host pointers. */
+int oecdg_batch_offsets(oecdg_handle *h, int64_t *off_primal, int64_t *off_dual);
+
+int oecdg_set_option(oecdg_handle *h, int32_t key, int64_t value);
+
+/* tau_max of instance 0 for the state (uC, uD) (Sec. 2.1; cell averages of
+ * both meshes).  Device inputs, host output; synchronises the stream. */
+int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out);
+
+/* One SSP-RK3 stage of eq. RKCDG followed by the OE step (OEstep1):
+ *   u_sigma^{n,l+1} = F_tau( c_{l0} u^n + c_{ll} u_sigma^{n,l} + tau d_{ll} L(u_sigma^{n,l}) )
+ * with (c_{00}, d_{00}) = (1, 1), (c_{10}, c_{11}, d_{11}) = (3/4, 1/4, 1/4),
+ * (c_{20}, c_{22}, d_{22}) = (1/3, 2/3, 2/3).  stage in {0, 1, 2}; dt = tau,
+ * tau_max = the coupling parameter of the operator.  uC_n/uD_n = u_sigma^n,
+ * uC_l/uD_l = u_sigma^{n,l} (ignored/aliasable for stage 0); outputs must not
+ * alias inputs.  Single instance handles only.  Device pointers. */
+int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max,
+                const double *uC_n, const double *uD_n,
+                const double *uC_l, const double *uD_l,
+                double *uC_out, double *uD_out);
+
+/* Advance in place from t = 0: on entry (uC, uD) = u_sigma^0 (no OE is
+ * applied to it), on exit u_sigma^N.  Stops at t_end (the last step is
+ * shortened to land on t_end; tau_max keeps the CFL value) or after nsteps
+ * steps (nsteps < 0: no limit); t_end may be +inf when nsteps >= 0.
+ * dt_fixed > 0 replaces the CFL step (tau = tau_max = dt_fixed).  For
+ * batches every instance takes the same nsteps/t_end/dt_fixed, each with its
+ * own CFL step.  t_out/steps_out (host, may be NULL) receive instance 0's
+ * final time and step count.  Synchronises the stream. */
+int oecdg_run(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps,
+              double dt_fixed, double *t_out, int64_t *steps_out);
+
+/* Discrete adjoint of oecdg_run with a fixed step (1D, single instance):
+ * given u_sigma^0 = (uC0, uD0), nsteps steps of size dt = tau = tau_max and
+ * the gradient (gC_T, gD_T) of a loss J with respect to u_sigma^N (in modal
+ * coefficients), writes dJ/du_sigma^0 into (gC0, gD0).  The forward states
+ * are recomputed from checkpoints stored every checkpoint_every steps.
+ * Non-smooth points follow fixed conventions: d|x|/dx = 0 at x = 0, the
+ * maximum in sigma is attributed to the first maximiser in storage order, a
+ * vanishing sigma contributes no derivative.  Device pointers. */
+int oecdg_adjoint(oecdg_handle *h, const double *uC0, const double *uD0, int64_t nsteps, double dt,
+                  const double *gC_T, const double *gD_T, double *gC0, double *gD0,
+                  int32_t checkpoint_every);
+
+void oecdg_destroy(oecdg_handle *h);
+
+/* Static description of an error code. */
+const char *oecdg_strerror(int code);
+
+/* Message of the last failing call on h (library-owned, valid until the next call). */
+const char *oecdg_last_error(oecdg_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OECDG_H */

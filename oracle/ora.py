@@ -51,6 +51,7 @@ def lib():
         L.ora1d_max_wavespeed.argtypes = [P1, _DP, _DP]
         L.ora1d_max_wavespeed.restype = C.c_double
         L.ora1d_step.argtypes = [P1, C.c_int, C.c_int, C.c_double, C.c_double, _DP, _DP]
+        L.ora1d_ssprk3_stage.argtypes = [P1, C.c_int, C.c_int, C.c_double, C.c_double, _DP, _DP, _DP, _DP, _DP, _DP]
         L.ora1d_run.argtypes = [P1, C.c_double, C.c_int, C.c_int, C.c_double, C.c_long, C.c_double,
                                 _DP, _DP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
         _lib = L
@@ -118,6 +119,15 @@ def step1d(prob, tau, tau_max, uC, uD, rk=3, oe=True):
     uC, uD = _arr(uC).copy(), _arr(uD).copy()
     _check(lib().ora1d_step(C.byref(_p1(prob)), rk, int(oe), tau, tau_max, uC, uD), "step1d")
     return uC, uD
+
+
+def ssprk3_stage1d(prob, l, tau, tau_max, unC, unD, ulC, ulD, oe=True):
+    """One SSP-RK3 stage l from u^n and u^{n,l}, then F_tau (as the library's oecdg_stage)."""
+    unC, unD, ulC, ulD = _arr(unC), _arr(unD), _arr(ulC), _arr(ulD)
+    oC, oD = np.zeros_like(unC), np.zeros_like(unD)
+    _check(lib().ora1d_ssprk3_stage(C.byref(_p1(prob)), l, int(oe), tau, tau_max, unC, unD, ulC, ulD, oC, oD),
+           "ssprk3_stage1d")
+    return oC, oD
 
 
 def run1d(prob, uC, uD, t_end=float("inf"), nsteps=-1, cfl=0.3, dt_fixed=0.0, rk=3, oe=True):

@@ -1,0 +1,925 @@
+// oecdg_1d.hip -- gfx950 kernels of the 1D RK-OECDG stage update.
+//
+// One workgroup owns a tile of T primal cells [i0, i0+T) and the T dual cells
+// [i0, i0+T) that interleave with them (dual cell j is centred on the left
+// edge of primal cell j).  A stage kernel for stage l of step n
+//   1. reduces the per-tile partial statistics left by the previous stage
+//      (fixed order, so every workgroup gets bit-identical avg/sigma/beta),
+//      and at l = 0 derives tau^n and tau_max^n (Sec. 2.1, tau = C h / beta);
+//   2. stages its tile plus a two-cell halo of the pre-damping input into LDS
+//      (coalesced structure-of-arrays loads);
+//   3. applies the OE step F_tau of the previous stage in LDS (Sec. 2.2,
+//      OEstep2D: delta_K^m from the primal/dual difference at the cell edges,
+//      then the exact exponential a_j *= exp(-tau sum_{m<=j} delta^m));
+//   4. evaluates the CDG operator (equcdg): the overlap coupling with
+//      1/tau_max, the volume integral of f(w) with k+1 Gauss nodes on each
+//      half cell, and the point fluxes of the other mesh at the cell edges;
+//   5. forms the SSP-RK3 combination (eq:RKCDG) and writes the stage output;
+//   6. writes the tile's partial statistics of that output for the next stage.
+// The OE of the last stage of a run is applied by the final kernel.
+#include "oecdg_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+namespace oecdg {
+
+__constant__ Tab1D c_tab[MAXK + 1];
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------- fluxes ---
+
+template <int FLUX> struct FluxT;
+
+template <> struct FluxT<0> {          // linear advection f = a u
+    static constexpr int NC = 1;
+    __device__ static inline void f(const double *w, double *o, double a) { o[0] = a * w[0]; }
+    __device__ static inline double speed(const double *, double a) { return fabs(a); }
+    __device__ static inline bool physical(const double *, double) { return true; }
+};
+
+template <> struct FluxT<1> {          // Burgers f = u^2 / 2
+    static constexpr int NC = 1;
+    __device__ static inline void f(const double *w, double *o, double) { o[0] = 0.5 * w[0] * w[0]; }
+    __device__ static inline double speed(const double *u, double) { return fabs(u[0]); }
+    __device__ static inline bool physical(const double *, double) { return true; }
+};
+
+template <> struct FluxT<2> {          // Euler (rho, m, E), ideal gas
+    static constexpr int NC = 3;
+    __device__ static inline void f(const double *w, double *o, double g) {
+        const double v = w[1] / w[0];
+        const double p = (g - 1.0) * (w[2] - 0.5 * w[1] * v);
+        o[0] = w[1];
+        o[1] = w[1] * v + p;
+        o[2] = (w[2] + p) * v;
+    }
+    __device__ static inline double speed(const double *u, double g) {
+        const double v = u[1] / u[0];
+        const double p = (g - 1.0) * (u[2] - 0.5 * u[1] * v);
+        return fabs(v) + sqrt(g * p / u[0]);
+    }
+    __device__ static inline bool physical(const double *u, double g) {
+        if (!(u[0] > 0.0)) return false;
+        const double p = (g - 1.0) * (u[2] - 0.5 * u[1] * u[1] / u[0]);
+        return p > 0.0;
+    }
+};
+
+// ------------------------------------------------------ shared-state access ---
+// Values written by other workgroups of the same launch (persistent mode) are
+// read with device-scope atomic loads so they always go through the vector
+// memory path.
+
+__device__ inline long long ld_ll(const long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_d(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int ld_i(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------- reductions ---
+
+__device__ inline int stat_kind(int j) { return j >= ST_BETA ? 1 : j % 3; }
+
+__device__ inline double stat_identity(int kind) {
+    return kind == 0 ? 0.0 : (kind == 1 ? -INFINITY : INFINITY);
+}
+
+__device__ inline double stat_op(int kind, double x, double y) {
+    return kind == 0 ? x + y : (kind == 1 ? fmax(x, y) : fmin(x, y));
+}
+
+// Reduce the NSTAT partials of tiles [tile0, tile0 + ntiles) in a fixed order
+// (per-thread strided accumulation, butterfly within waves, waves in order).
+// Result in red[0..NSTAT) (LDS), visible to all threads on return.
+template <int NT>
+__device__ void reduce_instance(const double *part, int tile0, int ntiles, double *red, double *scratch) {
+    constexpr int NW = (NT + WAVE - 1) / WAVE;
+    const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+    double acc[NSTAT];
+#pragma unroll
+    for (int j = 0; j < NSTAT; ++j) acc[j] = stat_identity(stat_kind(j));
+    for (int t = tid; t < ntiles; t += NT) {
+        const double *row = part + (long long)(tile0 + t) * NSTAT;
+#pragma unroll
+        for (int j = 0; j < NSTAT; ++j) acc[j] = stat_op(stat_kind(j), acc[j], row[j]);
+    }
+#pragma unroll
+    for (int off = WAVE / 2; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int j = 0; j < NSTAT; ++j) acc[j] = stat_op(stat_kind(j), acc[j], __shfl_xor(acc[j], off, WAVE));
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NSTAT; ++j) scratch[wave * NSTAT + j] = acc[j];
+    }
+    __syncthreads();
+    if (tid < NSTAT) {
+        double v = scratch[tid];
+        for (int w = 1; w < NW; ++w) v = stat_op(stat_kind(tid), v, scratch[w * NSTAT + tid]);
+        red[tid] = v;
+    }
+    __syncthreads();
+}
+
+// Segmented reduction over the two halves of a 2T-thread workgroup (primal
+// threads [0, T), dual threads [T, 2T)).  NV values per thread, kinds given.
+// On return the thread with tid == 0 (primal) and tid == T (dual) hold the
+// half's result.  scratch: NV * (2T / WAVE) doubles of LDS.
+template <int T, int NV>
+__device__ void reduce_halves(double (&v)[NV], const int (&kind)[NV], double *scratch) {
+    constexpr int SEG = T < WAVE ? T : WAVE;
+    const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+#pragma unroll
+    for (int off = SEG / 2; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = stat_op(kind[j], v[j], __shfl_xor(v[j], off, WAVE));
+    }
+    if constexpr (T > WAVE) {
+        constexpr int WPH = T / WAVE;          // waves per half
+        if (lane == 0) {
+#pragma unroll
+            for (int j = 0; j < NV; ++j) scratch[wave * NV + j] = v[j];
+        }
+        __syncthreads();
+        if (tid == 0 || tid == T) {
+            const int w0 = tid / WAVE;
+            for (int w = 1; w < WPH; ++w)
+#pragma unroll
+                for (int j = 0; j < NV; ++j) v[j] = stat_op(kind[j], v[j], scratch[(w0 + w) * NV + j]);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ cell kernels ---
+
+// Damping factors of one cell: fac[j] = exp(-tau * sum_{m<=j} delta^m), j >= 1,
+// delta^m = (2m+1) 2^m / ((2k-1) m! h) * max_q beta (|dR_q| + |dL_q|) / sigma_q
+// with dR, dL the xi-derivatives of order m of (own trace - other mesh at its
+// centre) at the right and left edge; components with sigma_q = 0 are skipped.
+template <int K, int NC>
+__device__ inline void oe_factors(const double (&own)[NC][K + 1], const double (&nl)[NC][K + 1],
+                                  const double (&nr)[NC][K + 1], double beta, const double *sig, double hinv,
+                                  double tau, double (&fac)[K + 1]) {
+    const Tab1D &tb = c_tab[K];
+    fac[0] = 1.0;
+    double S = 0.0;
+#pragma unroll
+    for (int m = 0; m <= K; ++m) {
+        double dm = 0.0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            double ur = 0.0, ul = 0.0, vr = 0.0, vl = 0.0;
+#pragma unroll
+            for (int n = m; n <= K; ++n) {
+                const double d1 = tb.D1[m][n];
+                ur += own[q][n] * d1;
+                ul += own[q][n] * (((n + m) & 1) ? -d1 : d1);
+                vr += nr[q][n] * tb.D0[m][n];
+                vl += nl[q][n] * tb.D0[m][n];
+            }
+            if (sig[q] != 0.0) {
+                const double val = beta * (fabs(ur - vr) + fabs(ul - vl)) / sig[q];
+                dm = fmax(dm, val);
+            }
+        }
+        S += tb.C[m] * hinv * dm;
+        if (m >= 1) fac[m] = exp(-tau * S);
+    }
+}
+
+// Time derivative of the modal coefficients of one cell (equcdg):
+//   da_m/dt = ((2m+1)/2 int w P_m - a_m) / tau_max
+//           + (2m+1)/h (int f(w) P_m' - f(w(x_R)) + (-1)^m f(w(x_L)))
+// where w is the other mesh: nl on the left half, nr on the right half.
+template <int K, int FLUX>
+__device__ inline void cdg_rate(const double (&own)[FluxT<FLUX>::NC][K + 1],
+                                const double (&nl)[FluxT<FLUX>::NC][K + 1],
+                                const double (&nr)[FluxT<FLUX>::NC][K + 1], double p0, double inv_tm, double hinv,
+                                double (&rate)[FluxT<FLUX>::NC][K + 1]) {
+    using F = FluxT<FLUX>;
+    constexpr int NC = F::NC;
+    const Tab1D &tb = c_tab[K];
+    double accw[NC][K + 1], accf[NC][K + 1];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m <= K; ++m) accw[q][m] = accf[q][m] = 0.0;
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+#pragma unroll
+        for (int g = 0; g <= K; ++g) {
+            double w[NC], fw[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+                double v = 0.0;
+#pragma unroll
+                for (int n = 0; n <= K; ++n) v += (hf == 0 ? nl[q][n] : nr[q][n]) * tb.E[hf][g][n];
+                w[q] = v;
+            }
+            F::f(w, fw, p0);
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int m = 0; m <= K; ++m) {
+                    accw[q][m] += tb.WP[hf][g][m] * w[q];
+                    accf[q][m] += tb.WD[hf][g][m] * fw[q];
+                }
+        }
+    }
+    double wl[NC], wr[NC], fl[NC], fr[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int n = 0; n <= K; ++n) {
+            a += nl[q][n] * tb.D0[0][n];
+            b += nr[q][n] * tb.D0[0][n];
+        }
+        wl[q] = a;
+        wr[q] = b;
+    }
+    F::f(wl, fl, p0);
+    F::f(wr, fr, p0);
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m <= K; ++m) {
+            const double edge = (m & 1) ? (fr[q] + fl[q]) : (fr[q] - fl[q]);
+            rate[q][m] = inv_tm * ((m + 0.5) * accw[q][m] - own[q][m]) +
+                         (2.0 * m + 1.0) * hinv * (accf[q][m] - edge);
+        }
+}
+
+// ------------------------------------------------------------ tile pieces ---
+
+template <int K, int NC, int W>
+__device__ inline void lds_cell(const double *s, int li, double (&c)[NC][K + 1]) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m <= K; ++m) c[q][m] = s[(q * (K + 1) + m) * W + li];
+}
+
+// Stage the pre-damping input of primal and dual cells [i0-1, i0+T] into LDS
+// (periodic wrap; outflow: constant-extension ghosts for primal -1 and np,
+// zeros for dual cells that do not exist).
+template <int K, int NC, int T>
+__device__ inline void load_tile(const Inst1D &I, int i0, const double *__restrict__ inC,
+                                 const double *__restrict__ inD, double *sC, double *sD) {
+    constexpr int W = T + 2, K1 = K + 1, PER = NC * K1 * W;
+    for (int e = threadIdx.x; e < 2 * PER; e += 2 * T) {
+        const int mesh = e >= PER;
+        const int r = e - mesh * PER;
+        const int qm = r / W;
+        const int li = r - qm * W;
+        int gi = i0 - 1 + li;
+        double v = 0.0;
+        if (mesh == 0) {
+            const int np = I.np;
+            if (I.bc == 0) {
+                gi = ((gi % np) + np) % np;          // periodic (also when the mesh is shorter than a tile)
+                v = inC[(long long)qm * np + gi];
+            } else if (gi < 0 || gi >= np) {
+                v = (qm % K1 == 0) ? inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)] : 0.0;
+            } else {
+                v = inC[(long long)qm * np + gi];
+            }
+            sC[r] = v;
+        } else {
+            const int nd = I.nd;
+            if (I.bc == 0) gi = ((gi % nd) + nd) % nd;
+            if (gi >= 0 && gi < nd) v = inD[(long long)qm * nd + gi];
+            sD[r] = v;
+        }
+    }
+}
+
+// Apply F_tau in LDS to primal cells [i0-1, i0+T-1] and dual cells [i0, i0+T]
+// (the cells whose damped values the tile's operator needs), all damping
+// factors computed from the pre-damping values first.
+template <int K, int FLUX, int T>
+__device__ inline void damp_tile(const Inst1D &I, int i0, double *sC, double *sD, const double (*sig)[3],
+                                 double tau) {
+    using F = FluxT<FLUX>;
+    constexpr int NC = F::NC, W = T + 2, K1 = K + 1;
+    const double hinv = 1.0 / I.h;
+    double fac[2][K1];
+    int cell[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int w = threadIdx.x + c * 2 * T;
+        cell[c] = -1;
+        if (w >= 2 * T + 2) continue;
+        const int mesh = w < T + 1 ? 0 : 1;
+        const int li = mesh == 0 ? w : w - T;          // primal 0..T, dual 1..T+1
+        const int gi = i0 - 1 + li;
+        bool real;
+        if (mesh == 0) real = (I.bc == 0) || (gi >= 0 && gi < I.np);
+        else real = (I.bc == 0) || (gi >= 0 && gi < I.nd);
+        if (!real) continue;
+        double own[NC][K1], nl[NC][K1], nr[NC][K1];
+        if (mesh == 0) {
+            lds_cell<K, NC, W>(sC, li, own);
+            lds_cell<K, NC, W>(sD, li, nl);
+            lds_cell<K, NC, W>(sD, li + 1, nr);
+        } else {
+            lds_cell<K, NC, W>(sD, li, own);
+            lds_cell<K, NC, W>(sC, li - 1, nl);
+            lds_cell<K, NC, W>(sC, li, nr);
+        }
+        double ubar[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) ubar[q] = own[q][0];
+        const double beta = F::speed(ubar, I.p0);
+        oe_factors<K, NC>(own, nl, nr, beta, sig[mesh], hinv, tau, fac[c]);
+        cell[c] = mesh * W + li;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        if (cell[c] < 0) continue;
+        const int mesh = cell[c] / W, li = cell[c] - mesh * W;
+        double *s = mesh == 0 ? sC : sD;
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 1; m <= K; ++m) s[(q * K1 + m) * W + li] *= fac[c][m];
+    }
+    __syncthreads();
+}
+
+// Partial statistics of one output cell and their reduction over the tile
+// (primal and dual halves separately); written to prow[0..NSTAT).
+template <int K, int FLUX, int T>
+__device__ inline void tile_partials(const Inst1D &I, bool valid, int mesh,
+                                     const double (&out)[FluxT<FLUX>::NC][K + 1], double *prow, double *scratch) {
+    using F = FluxT<FLUX>;
+    constexpr int NC = F::NC, NV = 3 * NC + 1;
+    const Tab1D &tb = c_tab[K];
+    double v[NV];
+    int kind[NV];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        kind[3 * q] = 0;
+        kind[3 * q + 1] = 1;
+        kind[3 * q + 2] = 2;
+        double mx = -INFINITY, mn = INFINITY;
+#pragma unroll
+        for (int s = 0; s < 2 * K + 4; ++s) {
+            double x = 0.0;
+#pragma unroll
+            for (int n = 0; n <= K; ++n) x += out[q][n] * tb.SP[s][n];
+            mx = fmax(mx, x);
+            mn = fmin(mn, x);
+        }
+        v[3 * q] = valid ? out[q][0] : 0.0;
+        v[3 * q + 1] = valid ? mx : -INFINITY;
+        v[3 * q + 2] = valid ? mn : INFINITY;
+    }
+    double ubar[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
+    kind[NV - 1] = 1;
+    v[NV - 1] = valid ? F::speed(ubar, I.p0) : -INFINITY;
+    reduce_halves<T, NV>(v, kind, scratch);
+    if (threadIdx.x == 0 || threadIdx.x == T) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int kd = 0; kd < 3; ++kd) prow[stat_index(mesh, q, kd)] = v[3 * q + kd];
+        prow[ST_BETA + mesh] = v[NV - 1];
+    }
+}
+
+// Reduced statistics -> avg and sigma per mesh and component.
+template <int NC>
+__device__ inline void finish_stats(const Inst1D &I, const double *red, double (*sig)[3]) {
+#pragma unroll
+    for (int mesh = 0; mesh < 2; ++mesh) {
+        const double ncell = mesh == 0 ? (double)I.np : (double)I.nd;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const double avg = red[stat_index(mesh, q, 0)] / ncell;
+            sig[mesh][q] = fmax(red[stat_index(mesh, q, 1)] - avg, avg - red[stat_index(mesh, q, 2)]);
+        }
+    }
+}
+
+constexpr int lds_doubles(int K, int NC, int T) { return 2 * NC * (K + 1) * (T + 2); }
+constexpr int scratch_doubles(int T) { return NSTAT * ((2 * T + WAVE - 1) / WAVE) + NSTAT; }
+
+// ---------------------------------------------------------- stage tile ---
+
+template <int K, int FLUX, int T>
+__device__ void stage_tile(const StageArgs &a, int l, int tile, double *smem) {
+    using F = FluxT<FLUX>;
+    constexpr int NC = F::NC, K1 = K + 1, W = T + 2;
+    const int tid = threadIdx.x;
+    const Tile1D tl = a.tiles[tile];
+    const Inst1D I = a.inst[tl.inst];
+    const int i0 = tl.i0;
+    const bool lead = (tile == I.tile0) && tid == 0;
+    Slot *S = a.slots + 2 * tl.inst;
+    const bool single = a.tau_override > 0.0;
+    const long long n = single ? 0 : ld_ll(l == 0 ? &a.step[0] : &a.step[1]);
+    const int par = (int)(n & 1);
+    const int sp = (int)((n + l) & 1);      // parity of the global stage index 3n + l
+    double *sC = smem, *sD = smem + NC * K1 * W;
+    double *red = smem + lds_doubles(K, NC, T);
+    double *scratch = red + NSTAT;
+
+    const bool damp = a.damp_input && I.oe && K > 0 && !(l == 0 && n == 0);
+    if (l == 0 && !single) {
+        // a step that is not taken: carry the time over and leave at once
+        const double t = ld_d(&S[par].t);
+        if (t >= a.t_end || n >= a.nsteps_limit) {
+            if (lead) {
+                S[par].done = 1;
+                S[par ^ 1].t = t;
+            }
+            if (tile == 0 && tid == 0) a.step[1] = n;
+            return;
+        }
+    }
+    const bool need_red = damp || (l == 0 && !single && a.dt_fixed <= 0.0);
+    if (need_red) reduce_instance<2 * T>(a.part[sp ^ 1], I.tile0, I.ntiles, red, scratch);
+
+    double tau, taumax;
+    int done;
+    if (single) {
+        tau = a.tau_override;
+        taumax = a.taumax_override;
+        done = 0;
+    } else if (l == 0) {
+        const double t = ld_d(&S[par].t);
+        taumax = a.dt_fixed > 0.0 ? a.dt_fixed : I.cfl * I.h / fmax(red[ST_BETA], red[ST_BETA + 1]);
+        tau = taumax;
+        int last = 0;
+        if (t + tau >= a.t_end) {
+            tau = a.t_end - t;
+            last = 1;
+        }
+        done = 0;
+        if (lead) {
+            S[par].tau = tau;
+            S[par].tau_max = taumax;
+            S[par].done = 0;
+            S[par].last = last;
+        }
+        if (tile == 0 && tid == 0) a.step[1] = n;
+    } else {
+        tau = ld_d(&S[par].tau);
+        taumax = ld_d(&S[par].tau_max);
+        done = ld_i(&S[par].done);
+        if (l == 2 && tile == 0 && tid == 0 && n < a.nsteps_limit) a.step[0] = n + 1;
+        if (l == 2 && lead && !done) {
+            const double tnext = ld_i(&S[par].last) ? a.t_end : ld_d(&S[par].t) + tau;
+            S[par ^ 1].t = tnext;
+            a.fin[tl.inst].t = tnext;
+            a.fin[tl.inst].tau = tau;
+            a.fin[tl.inst].nexec = n + 1;
+        }
+    }
+    if (done) return;
+
+    double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    if (damp) finish_stats<NC>(I, red, sig);
+    const double tau_in = (l == 0) ? ld_d(&S[par ^ 1].tau) : tau;
+
+    load_tile<K, NC, T>(I, i0, a.BC[sp] + I.offC, a.BD[sp] + I.offD, sC, sD);
+    __syncthreads();
+    if (damp) damp_tile<K, FLUX, T>(I, i0, sC, sD, sig, tau_in);
+
+    const int mesh = tid < T ? 0 : 1;
+    const int c = tid - mesh * T;
+    const int gi = i0 + c;
+    const int ncell = mesh == 0 ? I.np : I.nd;
+    const bool valid = gi < ncell;
+    double *UM = (mesh == 0 ? a.UC + I.offC : a.UD + I.offD);
+
+    double own[NC][K1], nl[NC][K1], nr[NC][K1];
+    if (mesh == 0) {
+        lds_cell<K, NC, W>(sC, c + 1, own);
+        lds_cell<K, NC, W>(sD, c + 1, nl);
+        lds_cell<K, NC, W>(sD, c + 2, nr);
+    } else {
+        lds_cell<K, NC, W>(sD, c + 1, own);
+        lds_cell<K, NC, W>(sC, c, nl);
+        lds_cell<K, NC, W>(sC, c + 1, nr);
+    }
+    if (l == 0 && !single && valid) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 0; m < K1; ++m) UM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
+    }
+
+    double rate[NC][K1];
+    cdg_rate<K, FLUX>(own, nl, nr, I.p0, 1.0 / taumax, 1.0 / I.h, rate);
+
+    double out[NC][K1];
+    bool finite = true;
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m < K1; ++m) {
+            const double v = own[q][m] + tau * rate[q][m];
+            double o;
+            if (l == 0) {
+                o = v;
+            } else {
+                const double un = valid ? UM[(long long)(q * K1 + m) * ncell + gi] : 0.0;
+                o = (l == 1) ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v;
+            }
+            out[q][m] = o;
+            finite = finite && isfinite(o);
+        }
+    double *OM = (mesh == 0 ? a.BC[sp ^ 1] + I.offC : a.BD[sp ^ 1] + I.offD);
+    if (valid) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 0; m < K1; ++m) OM[(long long)(q * K1 + m) * ncell + gi] = out[q][m];
+        double ubar[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
+        const bool phys = F::physical(ubar, I.p0);
+        if (!finite || !phys) {
+            if (!finite) a.err[0] = 1;
+            if (!phys) a.err[1] = 1;
+            a.err[3] = (int)(n + 1);
+        }
+    }
+    tile_partials<K, FLUX, T>(I, valid, mesh, out, a.part[sp] + (long long)tile * NSTAT, scratch);
+    __syncthreads();
+}
+
+// Statistics of a given state (srcC/srcD) into part[1]: the partials that the
+// first stage of a run reads (beta for tau^0).
+template <int K, int FLUX, int T>
+__device__ void stats_tile(const StageArgs &a, int tile, double *smem) {
+    using F = FluxT<FLUX>;
+    constexpr int NC = F::NC, K1 = K + 1;
+    const Tile1D tl = a.tiles[tile];
+    const Inst1D I = a.inst[tl.inst];
+    const int tid = threadIdx.x;
+    const int mesh = tid < T ? 0 : 1;
+    const int gi = tl.i0 + tid - mesh * T;
+    const int ncell = mesh == 0 ? I.np : I.nd;
+    const bool valid = gi < ncell;
+    const double *src = mesh == 0 ? a.srcC + I.offC : a.srcD + I.offD;
+    double u[NC][K1];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m < K1; ++m) u[q][m] = valid ? src[(long long)(q * K1 + m) * ncell + gi] : 1.0;
+    tile_partials<K, FLUX, T>(I, valid, mesh, u, a.part[1] + (long long)tile * NSTAT, smem + NSTAT);
+    __syncthreads();
+}
+
+// Final OE: u_sigma^N = F_tau(u_h^{N-1,3}) into (dstC, dstD); copy if no step ran.
+template <int K, int FLUX, int T>
+__device__ void final_tile(const StageArgs &a, int tile, double *smem) {
+    using F = FluxT<FLUX>;
+    constexpr int NC = F::NC, K1 = K + 1, W = T + 2;
+    const int tid = threadIdx.x;
+    const Tile1D tl = a.tiles[tile];
+    const Inst1D I = a.inst[tl.inst];
+    const long long N = ld_ll(&a.fin[tl.inst].nexec);
+    const double tau = ld_d(&a.fin[tl.inst].tau);
+    const int bp = (int)(N & 1);            // buffer holding u_h^{N-1,3} (or the input when N = 0)
+    double *sC = smem, *sD = smem + NC * K1 * W;
+    double *red = smem + lds_doubles(K, NC, T);
+    double *scratch = red + NSTAT;
+    const bool damp = N > 0 && I.oe && K > 0;
+    double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    if (damp) {
+        reduce_instance<2 * T>(a.part[(int)((N - 1) & 1)], I.tile0, I.ntiles, red, scratch);
+        finish_stats<NC>(I, red, sig);
+    }
+    load_tile<K, NC, T>(I, tl.i0, a.BC[bp] + I.offC, a.BD[bp] + I.offD, sC, sD);
+    __syncthreads();
+    if (damp) damp_tile<K, FLUX, T>(I, tl.i0, sC, sD, sig, tau);
+    const int mesh = tid < T ? 0 : 1;
+    const int c = tid - mesh * T;
+    const int gi = tl.i0 + c;
+    const int ncell = mesh == 0 ? I.np : I.nd;
+    if (gi < ncell) {
+        const double *s = mesh == 0 ? sC : sD;
+        double *dst = mesh == 0 ? a.dstC + I.offC : a.dstD + I.offD;
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 0; m < K1; ++m) dst[(long long)(q * K1 + m) * ncell + gi] = s[(q * K1 + m) * W + c + 1];
+    }
+    __syncthreads();
+}
+
+// --------------------------------------------------------------- kernels ---
+
+// KM < 0: mixed-degree batch, dispatch on the instance's k per tile.
+template <int KM, int FLUX, int T>
+struct Disp {
+    static constexpr int KL = KM < 0 ? MAXK : KM;
+    static constexpr int LDS = lds_doubles(KL, FluxT<FLUX>::NC, T) + scratch_doubles(T);
+    template <template <int, int, int> class Fn, typename... Args>
+    __device__ static void run(int k, Args &&...args) {
+        if constexpr (KM >= 0) {
+            Fn<KM, FLUX, T>::go(args...);
+        } else {
+            switch (k) {
+            case 0: Fn<0, FLUX, T>::go(args...); break;
+            case 1: Fn<1, FLUX, T>::go(args...); break;
+            case 2: Fn<2, FLUX, T>::go(args...); break;
+            default: Fn<3, FLUX, T>::go(args...); break;
+            }
+        }
+    }
+};
+
+template <int K, int FLUX, int T> struct StageFn {
+    __device__ static void go(const StageArgs &a, int l, int tile, double *smem) { stage_tile<K, FLUX, T>(a, l, tile, smem); }
+};
+template <int K, int FLUX, int T> struct StatsFn {
+    __device__ static void go(const StageArgs &a, int tile, double *smem) { stats_tile<K, FLUX, T>(a, tile, smem); }
+};
+template <int K, int FLUX, int T> struct FinalFn {
+    __device__ static void go(const StageArgs &a, int tile, double *smem) { final_tile<K, FLUX, T>(a, tile, smem); }
+};
+
+template <int KM, int FLUX, int T>
+__global__ __launch_bounds__(2 * T) void k_stage(StageArgs a) {
+    using D = Disp<KM, FLUX, T>;
+    __shared__ double smem[D::LDS];
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int k = a.inst[a.tiles[tile].inst].k;
+        D::template run<StageFn>(k, a, a.l, tile, smem);
+    }
+}
+
+template <int KM, int FLUX, int T>
+__global__ __launch_bounds__(2 * T) void k_stats(StageArgs a) {
+    using D = Disp<KM, FLUX, T>;
+    __shared__ double smem[D::LDS];
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int k = a.inst[a.tiles[tile].inst].k;
+        D::template run<StatsFn>(k, a, tile, smem);
+    }
+}
+
+template <int KM, int FLUX, int T>
+__global__ __launch_bounds__(2 * T) void k_final(StageArgs a) {
+    using D = Disp<KM, FLUX, T>;
+    __shared__ double smem[D::LDS];
+    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+        const int k = a.inst[a.tiles[tile].inst].k;
+        D::template run<FinalFn>(k, a, tile, smem);
+    }
+}
+
+// Grid-wide barrier for the persistent launch (all workgroups co-resident by
+// cooperative launch).  Sense by generation counter; bounded spin so that every
+// workgroup always terminates (a timeout is reported through err[2]).
+__device__ inline void grid_barrier(const StageArgs &a) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned *count = a.bar, *gen = a.bar + 1;
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == gridDim.x - 1) {
+            __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long long spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > a.spin_limit) {
+                    a.err[2] = 1;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+template <int KM, int FLUX, int T>
+__global__ __launch_bounds__(2 * T) void k_persistent(StageArgs a, long long nsteps, int single_instance) {
+    using D = Disp<KM, FLUX, T>;
+    __shared__ double smem[D::LDS];
+    for (long long it = 0; it < nsteps; ++it) {
+        for (int l = 0; l < 3; ++l) {
+            for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+                const int k = a.inst[a.tiles[tile].inst].k;
+                D::template run<StageFn>(k, a, l, tile, smem);
+            }
+            grid_barrier(a);
+            if (l == 0) {
+                const long long n = ld_ll(&a.step[1]);
+                const bool stop = single_instance ? ld_i(&a.slots[n & 1].done) != 0 : n >= a.nsteps_limit;
+                if (stop) return;
+            }
+            if (ld_i(&a.err[2])) return;
+        }
+    }
+}
+
+__global__ void k_init(StageArgs a, int ninst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ninst) {
+        a.slots[2 * i].t = 0.0;
+        a.slots[2 * i].tau = 0.0;
+        a.slots[2 * i].tau_max = 0.0;
+        a.slots[2 * i].done = 0;
+        a.slots[2 * i].last = 0;
+        a.slots[2 * i + 1] = a.slots[2 * i];
+        a.fin[i].t = 0.0;
+        a.fin[i].tau = 0.0;
+        a.fin[i].nexec = 0;
+    }
+    if (i == 0) {
+        a.step[0] = 0;
+        a.step[1] = 0;
+        a.err[0] = a.err[1] = a.err[2] = a.err[3] = 0;
+        a.bar[0] = 0;
+        a.bar[1] = 0;
+    }
+}
+
+// ------------------------------------------------------------ host side ---
+
+// Gauss-Legendre nodes by Newton iteration on P_Q (library's own tables).
+static double host_leg(int n, double x, int d) {
+    // d-th derivative of P_n via the series P_n^{(d)} from repeated use of
+    // P_n' = sum_{j = n-1, n-3, ...} (2j+1) P_j.
+    if (d == 0) {
+        double p0 = 1.0, p1 = x;
+        if (n == 0) return p0;
+        for (int j = 1; j < n; ++j) {
+            double p2 = ((2 * j + 1) * x * p1 - j * p0) / (j + 1);
+            p0 = p1;
+            p1 = p2;
+        }
+        return p1;
+    }
+    double s = 0.0;
+    for (int j = n - 1; j >= 0; j -= 2) s += (2 * j + 1) * host_leg(j, x, d - 1);
+    return s;
+}
+
+static void host_gauss(int Q, double *s, double *w) {
+    for (int i = 0; i < Q; ++i) {
+        double x = cos(M_PI * (Q - i - 0.25) / (Q + 0.5));
+        for (int it = 0; it < 60; ++it) {
+            double dx = host_leg(Q, x, 0) / host_leg(Q, x, 1);
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        double dp = host_leg(Q, x, 1);
+        s[i] = x;
+        w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+}
+
+hipError_t upload_tables_1d() {
+    Tab1D tabs[MAXK + 1];
+    memset(tabs, 0, sizeof(tabs));
+    for (int K = 0; K <= MAXK; ++K) {
+        Tab1D &t = tabs[K];
+        const int Q = K + 1;
+        double s[8], w[8];
+        host_gauss(Q, s, w);
+        for (int hf = 0; hf < 2; ++hf)
+            for (int g = 0; g < Q; ++g) {
+                const double xi = hf == 0 ? 0.5 * (s[g] - 1.0) : 0.5 * (s[g] + 1.0);
+                const double xn = hf == 0 ? xi + 1.0 : xi - 1.0;
+                for (int n = 0; n <= K; ++n) {
+                    t.E[hf][g][n] = host_leg(n, xn, 0);
+                    t.WP[hf][g][n] = 0.5 * w[g] * host_leg(n, xi, 0);
+                    t.WD[hf][g][n] = 0.5 * w[g] * host_leg(n, xi, 1);
+                }
+            }
+        for (int m = 0; m <= K; ++m)
+            for (int n = 0; n <= K; ++n) {
+                t.D0[m][n] = host_leg(n, 0.0, m);
+                t.D1[m][n] = host_leg(n, 1.0, m);
+            }
+        int c = 0;
+        double pts[10];
+        pts[c++] = -1.0;
+        for (int g = 0; g < Q; ++g) pts[c++] = 0.5 * (s[g] - 1.0);
+        for (int g = 0; g < Q; ++g) pts[c++] = 0.5 * (s[g] + 1.0);
+        pts[c++] = 1.0;
+        t.nsp = c;
+        for (int j = 0; j < c; ++j)
+            for (int n = 0; n <= K; ++n) t.SP[j][n] = host_leg(n, pts[j], 0);
+        double fact = 1.0;
+        for (int m = 0; m <= K; ++m) {
+            if (m > 0) fact *= m;
+            t.C[m] = K > 0 ? (2.0 * m + 1.0) * pow(2.0, m) / ((2.0 * K - 1.0) * fact) : 0.0;
+        }
+    }
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_tab), tabs, sizeof(tabs));
+}
+
+static int tile_index(int tile) { return tile == 32 ? 0 : (tile == 64 ? 1 : (tile == 128 ? 2 : -1)); }
+
+// kernel pointer tables [kidx][flux][tile]: kidx 0..3 = fixed k, 4 = mixed
+template <int WHICH, int KM, int FLUX, int T>
+static void *kptr() {
+    if constexpr (WHICH == 0) return (void *)k_stage<KM, FLUX, T>;
+    else if constexpr (WHICH == 1) return (void *)k_stats<KM, FLUX, T>;
+    else if constexpr (WHICH == 2) return (void *)k_final<KM, FLUX, T>;
+    else return (void *)k_persistent<KM, FLUX, T>;
+}
+
+template <int WHICH, int KM, int FLUX>
+static void *pick_t(int ti) {
+    switch (ti) {
+    case 0: return kptr<WHICH, KM, FLUX, 32>();
+    case 1: return kptr<WHICH, KM, FLUX, 64>();
+    default: return kptr<WHICH, KM, FLUX, 128>();
+    }
+}
+
+template <int WHICH, int KM>
+static void *pick_f(int flux, int ti) {
+    switch (flux) {
+    case 0: return pick_t<WHICH, KM, 0>(ti);
+    case 1: return pick_t<WHICH, KM, 1>(ti);
+    default: return pick_t<WHICH, KM, 2>(ti);
+    }
+}
+
+template <int WHICH>
+static void *pick(int k, bool mixed, int flux, int ti) {
+    if (mixed) return pick_f<WHICH, -1>(flux, ti);
+    switch (k) {
+    case 0: return pick_f<WHICH, 0>(flux, ti);
+    case 1: return pick_f<WHICH, 1>(flux, ti);
+    case 2: return pick_f<WHICH, 2>(flux, ti);
+    default: return pick_f<WHICH, 3>(flux, ti);
+    }
+}
+
+static hipError_t launch(void *fn, int grid, int tile, const StageArgs &a, hipStream_t s) {
+    StageArgs copy = a;
+    void *args[] = {&copy};
+    return hipLaunchKernel(fn, dim3(grid), dim3(2 * tile), args, 0, s);
+}
+
+hipError_t launch_init_1d(const StageArgs &a, int ninst, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3((ninst + 255) / 256), dim3(256), 0, s, a, ninst);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s) {
+    int ti = tile_index(tile);
+    if (ti < 0) return hipErrorInvalidValue;
+    return launch(pick<1>(kmax, mixed, flux, ti), a.ntiles, tile, a, s);
+}
+
+hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid, hipStream_t s) {
+    int ti = tile_index(tile);
+    if (ti < 0) return hipErrorInvalidValue;
+    return launch(pick<0>(kmax, mixed, flux, ti), grid > 0 ? grid : a.ntiles, tile, a, s);
+}
+
+hipError_t launch_final_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s) {
+    int ti = tile_index(tile);
+    if (ti < 0) return hipErrorInvalidValue;
+    return launch(pick<2>(kmax, mixed, flux, ti), a.ntiles, tile, a, s);
+}
+
+int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile) {
+    int ti = tile_index(tile);
+    if (ti < 0) return 0;
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick<3>(kmax, mixed, flux, ti), 2 * tile,
+                                                     0) != hipSuccess)
+        return 0;
+    return per_cu * ncu;
+}
+
+hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid,
+                                long long nsteps, hipStream_t s) {
+    int ti = tile_index(tile);
+    if (ti < 0) return hipErrorInvalidValue;
+    StageArgs copy = a;
+    int single = a.ninst == 1;
+    void *args[] = {&copy, &nsteps, &single};
+    return hipLaunchCooperativeKernel(pick<3>(kmax, mixed, flux, ti), dim3(grid), dim3(2 * tile), args, 0, s);
+}
+
+}  // namespace oecdg

@@ -1,0 +1,557 @@
+// oecdg_api.cpp -- host implementation of the C ABI declared in include/oecdg.h.
+#include "oecdg.h"
+#include "oecdg_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace oecdg;
+
+struct oecdg_handle {
+    std::vector<oecdg_desc> desc;
+    int nbatch = 0;
+    hipStream_t stream = nullptr;
+    int dim = 1;
+
+    // 1D batch bookkeeping
+    std::vector<Inst1D> inst_h;
+    std::vector<Tile1D> tiles_h;
+    std::vector<int64_t> offC, offD;
+    int64_t totC = 0, totD = 0;
+    int kmax = 0, flux = 0;
+    bool mixed = false;
+    int tile = 64;
+    int mode = OECDG_MODE_AUTO;
+    int graph_steps = 16;
+    int grid = 0;
+
+    // device memory (library-owned)
+    Inst1D *inst_d = nullptr;
+    Tile1D *tiles_d = nullptr;
+    Slot *slots = nullptr;
+    Final *fin = nullptr;
+    double *part = nullptr;
+    double *B = nullptr;     // BC0 | BC1 | BD0 | BD1
+    double *U = nullptr;     // UC | UD
+    long long *step = nullptr;
+    int *err = nullptr;
+    unsigned *bar = nullptr;
+    // pinned host mirrors
+    Final *fin_h = nullptr;
+    int *err_h = nullptr;
+    long long *step_h = nullptr;
+
+    // captured graph of graph_steps steps
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap = nullptr;   // capture stream (the caller's stream may be the null stream)
+    double g_tend = 0, g_dt = 0;
+    long long g_limit = -1;
+    int g_tile = 0, g_steps = 0;
+
+    void *ext2d = nullptr;   // 2D state (oecdg_2d.hip)
+    std::string last;
+};
+
+namespace {
+
+int fail(oecdg_handle *h, int code, const std::string &msg) {
+    if (h) h->last = msg;
+    return code;
+}
+
+#define HIPCHK(h, expr)                                                                               \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess)                                                                         \
+            return fail((h), OECDG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+    } while (0)
+
+int nc_of(int flux, int dim) { return flux == OECDG_FLUX_EULER ? (dim == 1 ? 3 : 4) : 1; }
+
+int validate(const oecdg_desc &d, std::string &why) {
+    if (d.dim != 1 && d.dim != 2) return why = "dim must be 1 or 2", OECDG_EINVAL;
+    if (d.reserved != 0) return why = "reserved must be 0", OECDG_EINVAL;
+    if (d.flux < 0 || d.flux > 2) return why = "unknown flux", OECDG_EINVAL;
+    if (d.bc < 0 || d.bc > 1) return why = "unknown boundary condition", OECDG_EINVAL;
+    if (!(d.xhi > d.xlo)) return why = "xhi must exceed xlo", OECDG_EINVAL;
+    if (!(d.cfl > 0.0)) return why = "cfl must be positive", OECDG_EINVAL;
+    if (d.flux == OECDG_FLUX_EULER && !(d.flux_param[0] > 1.0)) return why = "Euler needs gamma > 1", OECDG_EINVAL;
+    if (d.dim == 1) {
+        if (d.k < 0 || d.k > MAXK) return why = "1D degree must be 0..3", OECDG_EINVAL;
+        if (d.nx < 2 || d.nx > (1LL << 30)) return why = "1D nx out of range", OECDG_EINVAL;
+        if (d.ny != 1 && d.ny != 0) return why = "1D ny must be 1", OECDG_EINVAL;
+    } else {
+        if (d.k != 2) return why = "2D supports the tensor Q2 space only (k = 2)", OECDG_EUNSUPPORTED;
+        if (d.flux == OECDG_FLUX_BURGERS) return why = "2D Burgers is not implemented", OECDG_EUNSUPPORTED;
+        if (d.bc != OECDG_BC_PERIODIC) return why = "2D supports periodic boundaries only", OECDG_EUNSUPPORTED;
+        if (d.nx < 2 || d.ny < 2 || d.nx > 65536 || d.ny > 65536) return why = "2D nx, ny out of range", OECDG_EINVAL;
+        if (!(d.yhi > d.ylo)) return why = "yhi must exceed ylo", OECDG_EINVAL;
+    }
+    return OECDG_OK;
+}
+
+void sizes(const oecdg_desc &d, int64_t &np, int64_t &nd) {
+    const int64_t nc = nc_of(d.flux, d.dim);
+    if (d.dim == 1) {
+        np = nc * (d.k + 1) * d.nx;
+        nd = nc * (d.k + 1) * (d.bc == OECDG_BC_PERIODIC ? d.nx : d.nx + 1);
+    } else {
+        np = nd = nc * (d.k + 1) * (d.k + 1) * d.nx * d.ny;
+    }
+}
+
+// Tables are uploaded once per device.
+int ensure_tables(oecdg_handle *h) {
+    static int done_dev[64] = {0};
+    int dev = 0;
+    HIPCHK(h, hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(h, OECDG_EHIP, "device index out of range");
+    if (!done_dev[dev]) {
+        HIPCHK(h, upload_tables_1d());
+        done_dev[dev] = 1;
+    }
+    return OECDG_OK;
+}
+
+int build_tiles(oecdg_handle *h) {
+    h->tiles_h.clear();
+    const int T = h->tile;
+    for (int b = 0; b < h->nbatch; ++b) {
+        Inst1D &I = h->inst_h[b];
+        I.tile0 = (int)h->tiles_h.size();
+        I.ntiles = (I.nd + T - 1) / T;
+        for (int t = 0; t < I.ntiles; ++t) h->tiles_h.push_back(Tile1D{b, t * T});
+    }
+    if (h->tiles_d) (void)hipFree(h->tiles_d), h->tiles_d = nullptr;
+    if (h->part) (void)hipFree(h->part), h->part = nullptr;
+    HIPCHK(h, hipMalloc(&h->tiles_d, sizeof(Tile1D) * h->tiles_h.size()));
+    HIPCHK(h, hipMemcpy(h->tiles_d, h->tiles_h.data(), sizeof(Tile1D) * h->tiles_h.size(), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->inst_d, h->inst_h.data(), sizeof(Inst1D) * h->nbatch, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMalloc(&h->part, sizeof(double) * 2 * NSTAT * h->tiles_h.size()));
+    HIPCHK(h, hipMemset(h->part, 0, sizeof(double) * 2 * NSTAT * h->tiles_h.size()));
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec), h->gexec = nullptr;
+    return OECDG_OK;
+}
+
+StageArgs base_args(oecdg_handle *h) {
+    StageArgs a;
+    memset(&a, 0, sizeof(a));
+    a.inst = h->inst_d;
+    a.tiles = h->tiles_d;
+    a.ntiles = (int)h->tiles_h.size();
+    a.slots = h->slots;
+    a.fin = h->fin;
+    const size_t ps = (size_t)NSTAT * h->tiles_h.size();
+    a.part[0] = h->part;
+    a.part[1] = h->part + ps;
+    a.BC[0] = h->B;
+    a.BC[1] = h->B + h->totC;
+    a.BD[0] = h->B + 2 * h->totC;
+    a.BD[1] = h->B + 2 * h->totC + h->totD;
+    a.UC = h->U;
+    a.UD = h->U + h->totC;
+    a.step = h->step;
+    a.err = h->err;
+    a.bar = h->bar;
+    a.spin_limit = 1LL << 25;
+    a.damp_input = 1;
+    a.ninst = h->nbatch;
+    a.t_end = INFINITY;
+    a.nsteps_limit = LLONG_MAX;
+    return a;
+}
+
+int check_errors(oecdg_handle *h) {
+    HIPCHK(h, hipMemcpyAsync(h->err_h, h->err, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->err_h[2]) return fail(h, OECDG_ETIMEOUT, "grid barrier spin limit exceeded");
+    if (h->err_h[0])
+        return fail(h, OECDG_ENONFINITE, "non-finite coefficient produced at step " + std::to_string(h->err_h[3] - 1));
+    if (h->err_h[1])
+        return fail(h, OECDG_ENONPHYSICAL,
+                    "non-positive density or pressure at a cell average at step " + std::to_string(h->err_h[3] - 1));
+    return OECDG_OK;
+}
+
+int launch_steps(oecdg_handle *h, const StageArgs &base, int nsteps) {
+    for (int s = 0; s < nsteps; ++s)
+        for (int l = 0; l < 3; ++l) {
+            StageArgs a = base;
+            a.l = l;
+            HIPCHK(h, launch_stage_1d(a, h->kmax, h->flux, h->mixed, h->tile, 0, h->stream));
+        }
+    return OECDG_OK;
+}
+
+int ensure_graph(oecdg_handle *h, const StageArgs &base) {
+    if (h->gexec && h->g_tend == base.t_end && h->g_dt == base.dt_fixed && h->g_limit == base.nsteps_limit &&
+        h->g_tile == h->tile && h->g_steps == h->graph_steps)
+        return OECDG_OK;
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec), h->gexec = nullptr;
+    hipGraph_t g = nullptr;
+    if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    hipStream_t user = h->stream;
+    h->stream = h->cap;
+    HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    int rc = launch_steps(h, base, h->graph_steps);
+    hipError_t e = hipStreamEndCapture(h->cap, &g);
+    h->stream = user;
+    if (rc != OECDG_OK) return rc;
+    if (e != hipSuccess) return fail(h, OECDG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(h, OECDG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    h->g_tend = base.t_end;
+    h->g_dt = base.dt_fixed;
+    h->g_limit = base.nsteps_limit;
+    h->g_tile = h->tile;
+    h->g_steps = h->graph_steps;
+    return OECDG_OK;
+}
+
+// Has every instance finished?  Reads the device step counter and final records.
+int all_done(oecdg_handle *h, const StageArgs &a, bool &done) {
+    HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, sizeof(Final) * h->nbatch, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->step_h, h->step, 2 * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->err_h, h->err, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    if (h->err_h[0] || h->err_h[1] || h->err_h[2]) {
+        done = true;
+        return OECDG_OK;
+    }
+    if (h->step_h[0] >= a.nsteps_limit) {
+        done = true;
+        return OECDG_OK;
+    }
+    done = true;
+    for (int b = 0; b < h->nbatch; ++b)
+        if (h->fin_h[b].t < a.t_end) done = false;
+    return OECDG_OK;
+}
+
+int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps, double dt_fixed, double *t_out,
+           int64_t *steps_out) {
+    if (nsteps < 0 && !(t_end < INFINITY)) return fail(h, OECDG_EINVAL, "run needs a finite t_end or nsteps >= 0");
+    if (!(t_end > 0.0)) return fail(h, OECDG_EINVAL, "t_end must be positive");
+    StageArgs a = base_args(h);
+    a.t_end = t_end;
+    a.nsteps_limit = nsteps >= 0 ? nsteps : LLONG_MAX;
+    a.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
+    HIPCHK(h, hipMemcpyAsync(a.BC[0], uC, sizeof(double) * h->totC, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(a.BD[0], uD, sizeof(double) * h->totD, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, launch_init_1d(a, h->nbatch, h->stream));
+    StageArgs st = a;
+    st.srcC = a.BC[0];
+    st.srcD = a.BD[0];
+    HIPCHK(h, launch_stats_1d(st, h->kmax, h->flux, h->mixed, h->tile, h->stream));
+
+    int mode = h->mode;
+    if (mode == OECDG_MODE_AUTO) mode = OECDG_MODE_GRAPH;
+    if (mode == OECDG_MODE_PERSISTENT && h->nbatch > 1 && nsteps < 0) mode = OECDG_MODE_GRAPH;
+    if (mode == OECDG_MODE_PERSISTENT) {
+        int maxg = persistent_max_grid_1d(h->kmax, h->flux, h->mixed, h->tile);
+        int grid = h->grid > 0 ? h->grid : (int)h->tiles_h.size();
+        if (grid > maxg) grid = maxg;
+        if (grid <= 0) return fail(h, OECDG_EHIP, "persistent kernel cannot be made co-resident");
+        long long ns = nsteps >= 0 ? nsteps : LLONG_MAX;
+        HIPCHK(h, launch_persistent_1d(a, h->kmax, h->flux, h->mixed, h->tile, grid, ns, h->stream));
+    } else {
+        bool done = false;
+        int rc;
+        long long prev = -1;
+        if (mode == OECDG_MODE_GRAPH && (rc = ensure_graph(h, a)) != OECDG_OK) return rc;
+        while (!done) {
+            if (mode == OECDG_MODE_GRAPH) {
+                HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
+            } else if ((rc = launch_steps(h, a, h->graph_steps)) != OECDG_OK) {
+                return rc;
+            }
+            if ((rc = all_done(h, a, done)) != OECDG_OK) return rc;
+            if (!done && h->step_h[0] == prev) return fail(h, OECDG_EINVAL, "time stepping made no progress");
+            prev = h->step_h[0];
+        }
+    }
+    StageArgs f = a;
+    f.dstC = uC;
+    f.dstD = uD;
+    HIPCHK(h, launch_final_1d(f, h->kmax, h->flux, h->mixed, h->tile, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, sizeof(Final) * h->nbatch, hipMemcpyDeviceToHost, h->stream));
+    int rc = check_errors(h);
+    if (t_out) *t_out = h->fin_h[0].t;
+    if (steps_out) *steps_out = h->fin_h[0].nexec;
+    return rc;
+}
+
+}  // namespace
+
+// ============================================================== C ABI ===
+
+extern "C" {
+
+int oecdg_state_size(const oecdg_desc *d, int64_t *n_primal, int64_t *n_dual) {
+    if (!d || !n_primal || !n_dual) return OECDG_EINVAL;
+    std::string why;
+    int rc = validate(*d, why);
+    if (rc != OECDG_OK) return rc;
+    sizes(*d, *n_primal, *n_dual);
+    return OECDG_OK;
+}
+
+int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle **out) {
+    if (!d || !out || nbatch < 1) return OECDG_EINVAL;
+    *out = nullptr;
+    oecdg_handle *h = new (std::nothrow) oecdg_handle();
+    if (!h) return OECDG_ENOMEM;
+    h->nbatch = nbatch;
+    h->stream = (hipStream_t)stream;
+    h->desc.assign(d, d + nbatch);
+    h->dim = d[0].dim;
+    for (int b = 0; b < nbatch; ++b) {
+        std::string why;
+        int rc = validate(d[b], why);
+        if (rc == OECDG_OK && d[b].dim != h->dim) rc = OECDG_EINVAL, why = "mixed dimensions in one batch";
+        if (rc == OECDG_OK && nbatch > 1 && d[b].dim != 1) rc = OECDG_EUNSUPPORTED, why = "batches are 1D only";
+        if (rc == OECDG_OK && d[b].flux != d[0].flux) rc = OECDG_EUNSUPPORTED, why = "one flux per batch";
+        if (rc != OECDG_OK) {
+            delete h;
+            return rc;
+        }
+    }
+    int rc = ensure_tables(h);
+    if (rc != OECDG_OK) {
+        delete h;
+        return rc;
+    }
+    if (h->dim == 2) {
+        rc = oecdg::create_2d(h, d);
+        if (rc != OECDG_OK) {
+            delete h;
+            return rc;
+        }
+        *out = h;
+        return OECDG_OK;
+    }
+    h->flux = d[0].flux;
+    h->offC.assign(nbatch + 1, 0);
+    h->offD.assign(nbatch + 1, 0);
+    for (int b = 0; b < nbatch; ++b) {
+        const oecdg_desc &e = d[b];
+        Inst1D I;
+        memset(&I, 0, sizeof(I));
+        I.k = e.k;
+        I.nc = nc_of(e.flux, 1);
+        I.flux = e.flux;
+        I.bc = e.bc;
+        I.np = (int)e.nx;
+        I.nd = (int)(e.bc == OECDG_BC_PERIODIC ? e.nx : e.nx + 1);
+        I.h = (e.xhi - e.xlo) / (double)e.nx;
+        I.cfl = e.cfl;
+        I.p0 = e.flux == OECDG_FLUX_EULER ? e.flux_param[0] : e.flux_param[0];
+        I.oe = e.oe;
+        int64_t np, nd;
+        sizes(e, np, nd);
+        I.offC = h->offC[b];
+        I.offD = h->offD[b];
+        h->offC[b + 1] = h->offC[b] + np;
+        h->offD[b + 1] = h->offD[b] + nd;
+        h->inst_h.push_back(I);
+        if (e.k > h->kmax) h->kmax = e.k;
+        if (e.k != d[0].k) h->mixed = true;
+    }
+    h->totC = h->offC[nbatch];
+    h->totD = h->offD[nbatch];
+    // default tile: small tiles for small problems (more workgroups), larger otherwise
+    int64_t maxn = 0;
+    for (auto &I : h->inst_h) maxn = I.nd > maxn ? I.nd : maxn;
+    h->tile = maxn * nbatch <= 65536 ? 32 : 64;
+#define ALLOC(ptr, bytes)                                                    \
+    do {                                                                     \
+        if (hipMalloc(&(ptr), (bytes)) != hipSuccess) {                      \
+            oecdg_destroy(h);                                                \
+            return OECDG_ENOMEM;                                             \
+        }                                                                    \
+    } while (0)
+    ALLOC(h->inst_d, sizeof(Inst1D) * nbatch);
+    ALLOC(h->slots, sizeof(Slot) * 2 * nbatch);
+    ALLOC(h->fin, sizeof(Final) * nbatch);
+    ALLOC(h->B, sizeof(double) * 2 * (h->totC + h->totD));
+    ALLOC(h->U, sizeof(double) * (h->totC + h->totD));
+    ALLOC(h->step, sizeof(long long) * 2);
+    ALLOC(h->err, sizeof(int) * 4);
+    ALLOC(h->bar, sizeof(unsigned) * 2);
+#undef ALLOC
+    if (hipHostMalloc((void **)&h->fin_h, sizeof(Final) * nbatch, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&h->err_h, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&h->step_h, sizeof(long long) * 2, hipHostMallocDefault) != hipSuccess) {
+        oecdg_destroy(h);
+        return OECDG_ENOMEM;
+    }
+    rc = build_tiles(h);
+    if (rc != OECDG_OK) {
+        oecdg_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return OECDG_OK;
+}
+
+int oecdg_batch_offsets(oecdg_handle *h, int64_t *off_primal, int64_t *off_dual) {
+    if (!h || !off_primal || !off_dual) return OECDG_EINVAL;
+    if (h->dim != 1) {
+        int64_t np, nd;
+        sizes(h->desc[0], np, nd);
+        off_primal[0] = off_dual[0] = 0;
+        off_primal[1] = np;
+        off_dual[1] = nd;
+        return OECDG_OK;
+    }
+    for (int b = 0; b <= h->nbatch; ++b) {
+        off_primal[b] = h->offC[b];
+        off_dual[b] = h->offD[b];
+    }
+    return OECDG_OK;
+}
+
+int oecdg_set_option(oecdg_handle *h, int32_t key, int64_t value) {
+    if (!h) return OECDG_EINVAL;
+    switch (key) {
+    case OECDG_OPT_MODE:
+        if (value < 0 || value > 3) return fail(h, OECDG_EINVAL, "unknown mode");
+        h->mode = (int)value;
+        return OECDG_OK;
+    case OECDG_OPT_TILE:
+        if (value != 32 && value != 64 && value != 128) return fail(h, OECDG_EINVAL, "tile must be 32, 64 or 128");
+        if (h->dim != 1) return OECDG_OK;
+        h->tile = (int)value;
+        return build_tiles(h);
+    case OECDG_OPT_GRAPH_STEPS:
+        if (value < 1 || value > 4096) return fail(h, OECDG_EINVAL, "graph steps must be 1..4096");
+        h->graph_steps = (int)value;
+        return OECDG_OK;
+    case OECDG_OPT_GRID:
+        if (value < 0 || value > (1 << 20)) return fail(h, OECDG_EINVAL, "grid out of range");
+        h->grid = (int)value;
+        return OECDG_OK;
+    }
+    return fail(h, OECDG_EINVAL, "unknown option");
+}
+
+int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out) {
+    if (!h || !uC || !uD || !dt_out) return OECDG_EINVAL;
+    if (h->dim != 1) {
+        return oecdg::dt_2d(h, uC, uD, dt_out);
+    }
+    StageArgs a = base_args(h);
+    a.srcC = uC;
+    a.srcD = uD;
+    HIPCHK(h, launch_stats_1d(a, h->kmax, h->flux, h->mixed, h->tile, h->stream));
+    const Inst1D &I = h->inst_h[0];
+    std::vector<double> rows((size_t)I.ntiles * NSTAT);
+    HIPCHK(h, hipMemcpyAsync(rows.data(), a.part[1] + (size_t)I.tile0 * NSTAT, rows.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    double beta = 0.0;
+    for (int t = 0; t < I.ntiles; ++t)
+        for (int j = ST_BETA; j < ST_BETA + 2; ++j) beta = std::fmax(beta, rows[(size_t)t * NSTAT + j]);
+    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(h, OECDG_ENONFINITE, "wave speed is zero or not finite");
+    *dt_out = I.cfl * I.h / beta;
+    return OECDG_OK;
+}
+
+int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max, const double *uC_n, const double *uD_n,
+                const double *uC_l, const double *uD_l, double *uC_out, double *uD_out) {
+    if (!h || !uC_n || !uD_n || !uC_out || !uD_out) return OECDG_EINVAL;
+    if (stage < 0 || stage > 2) return fail(h, OECDG_EINVAL, "stage must be 0, 1 or 2");
+    if (!(dt > 0.0) || !(tau_max > 0.0)) return fail(h, OECDG_EINVAL, "dt and tau_max must be positive");
+    if (stage > 0 && (!uC_l || !uD_l)) return fail(h, OECDG_EINVAL, "stages 1 and 2 need u_l");
+    if (h->dim != 1) {
+        return oecdg::stage_2d(h, stage, dt, tau_max, uC_n, uD_n, uC_l, uD_l, uC_out, uD_out);
+    }
+    if (h->nbatch != 1) return fail(h, OECDG_EUNSUPPORTED, "oecdg_stage takes single-instance handles");
+    StageArgs a = base_args(h);
+    const int sp = stage & 1;                 // step index 0: global stage parity = stage
+    a.l = stage;
+    a.tau_override = dt;
+    a.taumax_override = tau_max;
+    a.damp_input = 0;
+    a.BC[sp] = const_cast<double *>(stage == 0 ? uC_n : uC_l);
+    a.BD[sp] = const_cast<double *>(stage == 0 ? uD_n : uD_l);
+    a.UC = const_cast<double *>(uC_n);
+    a.UD = const_cast<double *>(uD_n);
+    // the library's stage buffers receive the undamped output
+    a.BC[sp ^ 1] = h->B + (sp ^ 1) * h->totC;
+    a.BD[sp ^ 1] = h->B + 2 * h->totC + (sp ^ 1) * h->totD;
+    HIPCHK(h, launch_init_1d(a, 1, h->stream));
+    HIPCHK(h, launch_stage_1d(a, h->kmax, h->flux, h->mixed, h->tile, 0, h->stream));
+    // final OE with (tau, executed steps) chosen so that it reads that output
+    Final f{0.0, dt, (long long)stage + 1};
+    HIPCHK(h, hipMemcpyAsync(h->fin, &f, sizeof(Final), hipMemcpyHostToDevice, h->stream));
+    a.dstC = uC_out;
+    a.dstD = uD_out;
+    HIPCHK(h, launch_final_1d(a, h->kmax, h->flux, h->mixed, h->tile, h->stream));
+    return check_errors(h);
+}
+
+int oecdg_run(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps, double dt_fixed, double *t_out,
+              int64_t *steps_out) {
+    if (!h || !uC || !uD) return OECDG_EINVAL;
+    if (h->dim != 1) {
+        return oecdg::run_2d(h, uC, uD, t_end, nsteps, dt_fixed, t_out, steps_out);
+    }
+    return run_1d(h, uC, uD, t_end, nsteps, dt_fixed, t_out, steps_out);
+}
+
+int oecdg_adjoint(oecdg_handle *h, const double *uC0, const double *uD0, int64_t nsteps, double dt,
+                  const double *gC_T, const double *gD_T, double *gC0, double *gD0, int32_t checkpoint_every) {
+    if (!h || !uC0 || !uD0 || !gC_T || !gD_T || !gC0 || !gD0) return OECDG_EINVAL;
+    if (h->dim != 1 || h->nbatch != 1) return fail(h, OECDG_EUNSUPPORTED, "adjoint: 1D single instance only");
+    if (nsteps < 0 || !(dt > 0.0) || checkpoint_every < 1) return fail(h, OECDG_EINVAL, "adjoint: bad nsteps/dt/checkpoint");
+    return oecdg::adjoint_1d(h, uC0, uD0, nsteps, dt, gC_T, gD_T, gC0, gD0, checkpoint_every);
+}
+
+void oecdg_destroy(oecdg_handle *h) {
+    if (!h) return;
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    (void)hipFree(h->inst_d);
+    (void)hipFree(h->tiles_d);
+    (void)hipFree(h->slots);
+    (void)hipFree(h->fin);
+    (void)hipFree(h->part);
+    (void)hipFree(h->B);
+    (void)hipFree(h->U);
+    (void)hipFree(h->step);
+    (void)hipFree(h->err);
+    (void)hipFree(h->bar);
+    if (h->fin_h) (void)hipHostFree(h->fin_h);
+    if (h->err_h) (void)hipHostFree(h->err_h);
+    if (h->step_h) (void)hipHostFree(h->step_h);
+    if (h->ext2d) {
+        oecdg::destroy_2d(h);
+    }
+    delete h;
+}
+
+const char *oecdg_strerror(int code) {
+    switch (code) {
+    case OECDG_OK: return "success";
+    case OECDG_EINVAL: return "invalid argument";
+    case OECDG_ENOMEM: return "out of memory";
+    case OECDG_EHIP: return "HIP runtime error";
+    case OECDG_ENONFINITE: return "non-finite value produced";
+    case OECDG_ENONPHYSICAL: return "non-physical state (density or pressure <= 0)";
+    case OECDG_EUNSUPPORTED: return "unsupported configuration";
+    case OECDG_ETIMEOUT: return "device barrier timeout";
+    }
+    return "unknown error";
+}
+
+const char *oecdg_last_error(oecdg_handle *h) { return h ? h->last.c_str() : "null handle"; }
+
+}  // extern "C"

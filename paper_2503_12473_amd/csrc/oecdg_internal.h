@@ -1,0 +1,113 @@
+// oecdg_internal.h -- device data structures and host launch interfaces of the
+// HIP implementation (library-private; the public ABI is include/oecdg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace oecdg {
+
+constexpr int MAXK = 3;
+
+// Per-tile partial statistics written by every stage kernel (and by the
+// statistics kernel) for the state it produced.  Index (mesh*3 + q)*3 + kind,
+// kind 0 = sum of cell averages, 1 = max, 2 = min of the point values at the
+// sigma sample points; ST_BETA = largest wave speed at a cell average.
+constexpr int NSTAT = 20;
+constexpr int ST_BETA = 18;
+
+__host__ __device__ constexpr int stat_index(int mesh, int q, int kind) { return (mesh * 3 + q) * 3 + kind; }
+
+// One 1D problem instance of a (possibly single-element) batch.
+struct Inst1D {
+    int k, nc, flux, bc;
+    int np, nd;              // primal / dual cell counts
+    int tile0, ntiles;       // tiles [tile0, tile0 + ntiles) of the global tile list
+    long long offC, offD;    // element offsets in the concatenated state arrays
+    double h, cfl, p0;       // cell width, C_CFL, flux parameter (speed or gamma)
+    int oe, pad;
+};
+
+// A tile: primal cells [i0, i0 + T) and dual cells [i0, i0 + T) of instance inst.
+struct Tile1D {
+    int inst, i0;
+};
+
+// Per instance and step parity: the step's start time and its tau/tau_max.
+struct Slot {
+    double t, tau, tau_max;
+    int done, last;
+};
+
+// Per instance: time reached, tau of the last executed step, executed steps.
+struct Final {
+    double t, tau;
+    long long nexec;
+};
+
+// Constant tables for degree K (computed on the host at start-up).
+struct Tab1D {
+    double E[2][4][4];   // P_n at the overlapping cell's coordinate of quadrature node g of half h: [h][g][n]
+    double WP[2][4][4];  // (w_g/2) P_m(xi_g) on half h: [h][g][m]
+    double WD[2][4][4];  // (w_g/2) P_m'(xi_g) on half h: [h][g][m]
+    double D0[4][4];     // m-th derivative of P_n at xi = 0: [m][n]
+    double D1[4][4];     // m-th derivative of P_n at xi = 1: [m][n]
+    double SP[10][4];    // P_n at the sigma sample points: [s][n]
+    double C[4];         // (2m+1) 2^m / ((2K-1) m!)
+    int nsp;
+};
+
+struct StageArgs {
+    const Inst1D *inst;
+    const Tile1D *tiles;
+    int ntiles;
+    Slot *slots;             // [ninst][2]
+    Final *fin;              // [ninst]
+    double *part[2];         // [ntiles][NSTAT] each
+    double *BC[2], *BD[2];   // rotating pre-damping stage states
+    double *UC, *UD;         // damped u^n of the current step
+    long long *step;         // step[0]: step index read at stage 0; step[1]: copy read at stages 1, 2
+    int *err;                // [0] non-finite, [1] non-physical, [2] barrier timeout, [3] step+1 of first error
+    int l;                   // stage of the step (0, 1, 2)
+    long long nsteps_limit;  // no step with index >= limit is taken
+    double t_end;
+    double dt_fixed;         // > 0: tau = tau_max = dt_fixed
+    double tau_override, taumax_override;   // > 0: single-stage call with given tau/tau_max
+    int damp_input;          // 0: the stage input is used as is (single-stage call)
+    int ninst;               // instances in the batch
+    // final / statistics kernels
+    const double *srcC, *srcD;
+    double *dstC, *dstD;
+    // persistent launch
+    unsigned *bar;           // [0] arrival count, [1] generation
+    long long spin_limit;
+};
+
+// Host-side launchers (oecdg_1d.hip).
+hipError_t upload_tables_1d();
+hipError_t launch_init_1d(const StageArgs &a, int ninst, hipStream_t s);
+hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s);
+hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid, hipStream_t s);
+hipError_t launch_final_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s);
+hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid,
+                                long long nsteps, hipStream_t s);
+int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile);
+
+}  // namespace oecdg
+
+#include "oecdg.h"
+
+namespace oecdg {
+
+// 2D path (oecdg_2d.hip) and the 1D adjoint (oecdg_adjoint.hip).
+int create_2d(oecdg_handle *h, const oecdg_desc *d);
+int dt_2d(oecdg_handle *h, const double *uC, const double *uD, double *dt_out);
+int stage_2d(oecdg_handle *h, int stage, double dt, double tau_max, const double *uCn, const double *uDn,
+             const double *uCl, const double *uDl, double *uCo, double *uDo);
+int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps, double dt_fixed, double *t_out,
+           int64_t *steps_out);
+void destroy_2d(oecdg_handle *h);
+int adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int64_t nsteps, double dt, const double *gCT,
+               const double *gDT, double *gC0, double *gD0, int ckpt);
+
+}  // namespace oecdg

@@ -1,0 +1,72 @@
+"""The C-ABI library loads and exports every symbol include/oecdg.h declares;
+host-only argument checks (no GPU needed: nothing here launches a kernel)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2503_12473_amd import _lib
+from paper_2503_12473_amd.api import make_desc
+from paper_2503_12473_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "oecdg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(oecdg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_documented_entry_points():
+    assert set(_declared()) == set(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_state_size_host_only():
+    L = _lib.lib()
+    prob = inputs.Problem1D(k=2, nc=3, flux=inputs.FLUX_EULER, bc=inputs.BC_OUTFLOW, n=100, xlo=0.0, xhi=1.0)
+    d = make_desc(prob, 0.15)
+    npr, ndu = C.c_int64(), C.c_int64()
+    assert L.oecdg_state_size(C.byref(d), C.byref(npr), C.byref(ndu)) == 0
+    assert (npr.value, ndu.value) == (3 * 3 * 100, 3 * 3 * 101)
+    p2 = inputs.Problem2D(k=2, nc=4, flux=inputs.FLUX_EULER, nx=8, ny=6, xlo=0, xhi=1, ylo=0, yhi=1)
+    d2 = make_desc(p2, 0.3)
+    assert L.oecdg_state_size(C.byref(d2), C.byref(npr), C.byref(ndu)) == 0
+    assert npr.value == ndu.value == 4 * 9 * 48
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("k", 4, _lib.EINVAL), ("nx", 1, _lib.EINVAL), ("cfl", 0.0, _lib.EINVAL), ("flux", 7, _lib.EINVAL),
+    ("reserved", 1, _lib.EINVAL), ("dim", 3, _lib.EINVAL),
+])
+def test_invalid_descriptors_are_rejected_before_any_gpu_work(field, value, code):
+    L = _lib.lib()
+    prob = inputs.Problem1D(k=2, nc=1, flux=inputs.FLUX_ADVECTION, bc=inputs.BC_PERIODIC, n=64, xlo=0.0, xhi=1.0)
+    d = make_desc(prob, 0.2)
+    setattr(d, field, value)
+    h = C.c_void_p()
+    assert L.oecdg_init(C.byref(d), 1, None, C.byref(h)) == code
+    assert not h.value
+    npr, ndu = C.c_int64(), C.c_int64()
+    assert L.oecdg_state_size(C.byref(d), C.byref(npr), C.byref(ndu)) == code
+
+
+def test_2d_degrees_other_than_two_are_unsupported():
+    L = _lib.lib()
+    p2 = inputs.Problem2D(k=1, nc=1, flux=inputs.FLUX_ADVECTION, nx=8, ny=8, xlo=0, xhi=1, ylo=0, yhi=1)
+    d2 = make_desc(p2, 0.3)
+    npr, ndu = C.c_int64(), C.c_int64()
+    assert L.oecdg_state_size(C.byref(d2), C.byref(npr), C.byref(ndu)) == _lib.EUNSUPPORTED
+
+
+def test_strerror_covers_every_code():
+    L = _lib.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert L.oecdg_strerror(code).decode() != "unknown error"

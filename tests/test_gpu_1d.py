@@ -1,0 +1,216 @@
+"""GPU parity of the 1D HIP path against the CPU oracle (through the C ABI).
+
+Floating-point bar: relative L-infinity error (max |gpu - oracle| over all
+coefficients of both meshes divided by max |oracle|) <= 1e-10 after a full
+run, <= 1e-12 for a single stage; step counts and final times equal.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ora
+from paper_2503_12473_amd import inputs
+from paper_2503_12473_amd import _lib
+from paper_2503_12473_amd.api import OECDG, to_device
+from paper_2503_12473_amd.inputs import Problem1D, BC_OUTFLOW, BC_PERIODIC, FLUX_ADVECTION, FLUX_BURGERS, FLUX_EULER
+
+pytestmark = pytest.mark.gpu
+
+RUN_TOL = 1e-10
+STAGE_TOL = 1e-12
+
+
+def _rel(gC, gD, rC, rD):
+    err = max(np.abs(gC - rC).max(), np.abs(gD - rD).max())
+    return err / max(np.abs(rC).max(), np.abs(rD).max())
+
+
+def gpu_run(prob, uC, uD, cfl, mode=None, tile=None, oe=True, **kw):
+    print(f"[gpu_run] flux={prob.flux} k={prob.k} n={prob.n} bc={prob.bc} mode={mode} tile={tile} {kw}", flush=True)
+    with OECDG(prob, cfl, oe=oe) as s:
+        if mode is not None:
+            s.set_option(_lib.OPT_MODE, mode)
+        if tile is not None:
+            s.set_option(_lib.OPT_TILE, tile)
+        gC, gD = to_device(uC), to_device(uD)
+        t, n = s.run(gC, gD, **kw)
+        return gC.cpu().numpy().reshape(uC.shape), gD.cpu().numpy().reshape(uD.shape), t, n
+
+
+def _state(prob, rng):
+    """A physical random state (Euler: positive density and pressure)."""
+    sC, sD = prob.shapes()
+    decay = (0.3 ** np.arange(prob.k + 1))[None, :, None]
+    uC = rng.normal(scale=0.1, size=sC) * decay
+    uD = rng.normal(scale=0.1, size=sD) * decay
+    if prob.flux == FLUX_EULER:
+        for u in (uC, uD):
+            u[0, 0] += 1.0
+            u[2, 0] += 2.5
+    else:
+        uC[0, 0] += 0.5
+        uD[0, 0] += 0.5
+    return np.ascontiguousarray(uC), np.ascontiguousarray(uD)
+
+
+CASES = [(FLUX_ADVECTION, BC_PERIODIC), (FLUX_BURGERS, BC_PERIODIC), (FLUX_EULER, BC_OUTFLOW), (FLUX_EULER, BC_PERIODIC),
+         (FLUX_ADVECTION, BC_OUTFLOW)]
+
+
+@pytest.mark.parametrize("flux,bc", CASES)
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("n", [37, 130])
+def test_single_stage_parity(flux, bc, k, n):
+    """oecdg_stage == one SSP-RK3 stage of eq:RKCDG followed by F_tau."""
+    rng = np.random.default_rng(100 * k + n + 7 * flux)
+    nc = 3 if flux == FLUX_EULER else 1
+    prob = Problem1D(k=k, nc=nc, flux=flux, bc=bc, n=n, xlo=0.0, xhi=1.0, a=-1.3)
+    unC, unD = _state(prob, rng)
+    ulC, ulD = _state(prob, rng)
+    tau = 0.1 * prob.h
+    with OECDG(prob, 0.2) as s:
+        gn = (to_device(unC), to_device(unD))
+        gl = (to_device(ulC), to_device(ulD))
+        for l in range(3):
+            print(f"[stage] flux={flux} bc={bc} k={k} n={n} l={l}", flush=True)
+            oC, oD = s.stage(l, tau, 1.3 * tau, gn[0], gn[1], gl[0], gl[1])
+            rC, rD = ora.ssprk3_stage1d(prob, l, tau, 1.3 * tau, unC, unD, unC if l == 0 else ulC,
+                                        unD if l == 0 else ulD)
+            e = _rel(oC.cpu().numpy().reshape(rC.shape), oD.cpu().numpy().reshape(rD.shape), rC, rD)
+            assert e <= STAGE_TOL, (l, e)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_advection_sine_full_run(seed):
+    """Linear advection, [0, 2pi] periodic, N = 256, P2, CFL 0.2, T = 1,
+    sin(x + phi) with seeded phi."""
+    phi = float(inputs.advection_phases(seed)[0])
+    prob, uC, uD = inputs.advection_sine(256, 2, phase=phi)
+    gC, gD, t, n = gpu_run(prob, uC, uD, 0.2, t_end=1.0)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, t_end=1.0, cfl=0.2)
+    assert (n, t) == (rn, rt)
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_advection_square_wave_full_run(k):
+    prob, uC, uD = inputs.advection_square(256, k)
+    gC, gD, t, n = gpu_run(prob, uC, uD, 0.2, t_end=1.0)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, t_end=1.0, cfl=0.2)
+    assert (n, t) == (rn, rt)
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("n", [1000, 2053])
+def test_euler_riemann_run(k, n):
+    """1D Euler Riemann workload states (seed 0), outflow, CFL 0.15, to T = 0.01."""
+    prob, uC, uD = inputs.euler_riemann(n, k, inputs.riemann_states(0))
+    gC, gD, t, ns = gpu_run(prob, uC, uD, 0.15, t_end=0.01)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, t_end=0.01, cfl=0.15)
+    assert (ns, t) == (rn, rt)
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_euler_riemann_full_size_steps(k):
+    """Full workload size N = 16384 for 12 steps (all tiles, ragged dual tail)."""
+    prob, uC, uD = inputs.euler_riemann(16384, k, inputs.riemann_states(1))
+    gC, gD, t, ns = gpu_run(prob, uC, uD, 0.15, nsteps=12)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, nsteps=12, cfl=0.15)
+    assert ns == rn == 12
+    assert t == pytest.approx(rt, rel=1e-14)
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
+
+
+def test_burgers_fixed_step_full_size():
+    """Burgers, [0, 2pi] periodic, N = 16384, P2, seeded Fourier modes, fixed
+    tau = 0.3 h / max|u0|, 10 steps."""
+    prob, uC, uD, _ = inputs.burgers_fourier(16384, 2, seed=0)
+    dt = 0.3 * prob.h / np.abs(uC[0, 0]).max()
+    gC, gD, t, ns = gpu_run(prob, uC, uD, 0.3, nsteps=10, dt_fixed=dt)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, nsteps=10, dt_fixed=dt)
+    assert ns == rn == 10
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
+
+
+def test_burgers_to_shock():
+    """Burgers P2 N = 256 through shock formation (t = 2.2, sin x + 0.5)."""
+    prob, uC, uD = inputs.burgers_sine(256, 2)
+    gC, gD, t, ns = gpu_run(prob, uC, uD, 0.3, t_end=2.2)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, t_end=2.2, cfl=0.3)
+    assert (ns, t) == (rn, rt)
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
+
+
+def test_plain_cdg_without_oe():
+    prob, uC, uD = inputs.advection_square(256, 2)
+    gC, gD, t, n = gpu_run(prob, uC, uD, 0.2, oe=False, t_end=0.5)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, t_end=0.5, cfl=0.2, oe=False)
+    assert (n, t) == (rn, rt)
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
+
+
+@pytest.mark.parametrize("tile", [32, 64, 128])
+def test_execution_modes_bitwise_identical(tile):
+    """Eager launches, the captured graph and the persistent cooperative
+    launch run the same tiles with the same reduction order: identical bits."""
+    prob, uC, uD = inputs.euler_riemann(3000, 2, inputs.riemann_states(2))
+    outs = [gpu_run(prob, uC, uD, 0.15, mode=m, tile=tile, t_end=0.004)
+            for m in (_lib.MODE_EAGER, _lib.MODE_GRAPH, _lib.MODE_PERSISTENT)]
+    for o in outs[1:]:
+        assert o[2] == outs[0][2] and o[3] == outs[0][3]
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, t_end=0.004, cfl=0.15)
+    assert outs[0][3] == rn
+    assert _rel(outs[0][0], outs[0][1], rC, rD) <= RUN_TOL
+
+
+def test_repeat_runs_are_deterministic():
+    prob, uC, uD = inputs.euler_riemann(4096, 3, inputs.riemann_states(3))
+    a = gpu_run(prob, uC, uD, 0.15, nsteps=40)
+    b = gpu_run(prob, uC, uD, 0.15, nsteps=40)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_dt_matches_oracle():
+    prob, uC, uD = inputs.euler_riemann(777, 2, inputs.riemann_states(4))
+    with OECDG(prob, 0.15) as s:
+        dt = s.dt(to_device(uC), to_device(uD))
+    ref = 0.15 * prob.h / ora.max_wavespeed1d(prob, uC, uD)
+    assert dt == pytest.approx(ref, rel=1e-14)
+
+
+def test_batched_instances_match_their_own_runs():
+    """Several independent instances of uneven N and k advanced together:
+    each matches the oracle run of that instance alone (each with its own
+    CFL time step), for a fixed number of steps."""
+    specs = inputs.batch_instances(seed=5, count=6, nmin=100, nmax=700)
+    probs, states = [], []
+    for n, k, st in specs:
+        p, uC, uD = inputs.euler_riemann(n, k, st)
+        probs.append(p)
+        states.append((uC, uD))
+    with OECDG(probs, 0.15) as s:
+        gC = torch.cat([to_device(u[0]) for u in states])
+        gD = torch.cat([to_device(u[1]) for u in states])
+        print("[batched] 6 instances, 25 steps", flush=True)
+        s.run(gC, gD, nsteps=25)
+        offC, offD = s.off_primal, s.off_dual
+        gC, gD = gC.cpu().numpy(), gD.cpu().numpy()
+    for b, (p, (uC, uD)) in enumerate(zip(probs, states)):
+        rC, rD, _, rn = ora.run1d(p, uC, uD, nsteps=25, cfl=0.15)
+        bC = gC[offC[b]:offC[b + 1]].reshape(rC.shape)
+        bD = gD[offD[b]:offD[b + 1]].reshape(rD.shape)
+        assert _rel(bC, bD, rC, rD) <= RUN_TOL, b
+
+
+def test_nonphysical_state_is_reported():
+    prob, uC, uD = inputs.euler_riemann(64, 1, (1.0, 1.0, 0.5, 0.5))
+    uC = uC.copy()
+    uC[2, 0, 10] = -1.0
+    with pytest.raises(_lib.OECDGError) as e:
+        gpu_run(prob, uC, uD, 0.15, nsteps=2)
+    assert e.value.code == _lib.ENONPHYSICAL
