@@ -1,0 +1,150 @@
+"""Benchmark: RK-OECDG DOF-updates/s on one MI355X.
+
+Workload (the plain P2 headline): 1D Euler (gamma = 1.4) two-state Riemann
+problem on [0, 1] with outflow boundaries, N = 16384 primal + 16385 dual
+cells, P2 Legendre modal basis, seeded states (seed 0: rho, p ~ U[0.1, 1],
+u = 0, jump at x = 0.5), SSP-RK3 + OE after every stage, CFL 0.15, run to
+T = 0.2 (33354 steps for seed 0).  A "step" is one full RK-OECDG time step:
+the time-step reduction, three stage updates on both meshes and three OE
+applications.  value = DOF-updates/s = (DOFs of both meshes) x steps / wall
+seconds, with the state resident in HBM when the timed region starts.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
+BYTES_PER_DOF_UPDATE = 64.0    # 5 reads + 3 writes of one FP64 coefficient per full SSP-RK3 step
+N_CELLS, DEGREE, CFL, T_END, SEED = 16384, 2, 0.15, 0.2, 0
+FULL_STEPS = 33354             # steps to T = 0.2 for seed 0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=FULL_STEPS, help="timed RK-OECDG steps (default: the full run to T)")
+    ap.add_argument("--warmup", type=int, default=2000, help="untimed warm-up steps")
+    ap.add_argument("--mode", type=int, default=0, help="execution mode (0 auto, 1 eager, 2 graph, 3 persistent)")
+    ap.add_argument("--tile", type=int, default=0, help="primal cells per workgroup (0: library default)")
+    ap.add_argument("--repeats", type=int, default=3, help="timed repetitions (median reported)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle sample length")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before the warm-up, copy a device buffer of this many MiB (profiler counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline(target_seconds: float):
+    """The CPU oracle, as it stands, on a bounded sample of the same workload:
+    the first S steps from the same initial data (S sized to ~target_seconds)."""
+    from oracle import ora
+    from paper_2503_12473_amd import inputs
+    prob, uC, uD = inputs.euler_riemann(N_CELLS, DEGREE, inputs.riemann_states(SEED))
+    t0 = time.perf_counter()
+    ora.run1d(prob, uC, uD, nsteps=2, cfl=CFL, t_end=T_END)
+    per_step = (time.perf_counter() - t0) / 2
+    steps = max(2, int(target_seconds / max(per_step, 1e-6)))
+    t0 = time.perf_counter()
+    _, _, _, done = ora.run1d(prob, uC, uD, nsteps=steps, cfl=CFL, t_end=T_END)
+    wall = time.perf_counter() - t0
+    return {"value": prob.dofs() * done / wall, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} of {FULL_STEPS} steps of the same workload, serial C oracle "
+                      f"(-O2, no FP contraction), {wall:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+              "multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2503_12473_amd import inputs, _lib
+    from paper_2503_12473_amd.api import OECDG, to_device
+
+    torch.cuda.init()
+    prob, uC, uD = inputs.euler_riemann(N_CELLS, DEGREE, inputs.riemann_states(SEED))
+    dofs = prob.dofs()
+    stream = torch.cuda.current_stream()
+    solver = OECDG(prob, CFL, stream=stream)
+    if args.mode:
+        solver.set_option(_lib.OPT_MODE, args.mode)
+    if args.tile:
+        solver.set_option(_lib.OPT_TILE, args.tile)
+    if args.calibrate_copy_mib > 0:
+        src = torch.ones(args.calibrate_copy_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    ic = (to_device(uC), to_device(uD))
+    work = (ic[0].clone(), ic[1].clone())
+
+    # warm-up: graph capture, code loading, caches
+    if args.warmup > 0:
+        solver.run(work[0], work[1], t_end=T_END, nsteps=args.warmup)
+    torch.cuda.synchronize()
+
+    times, steps = [], None
+    for _ in range(max(1, args.repeats)):
+        work[0].copy_(ic[0])
+        work[1].copy_(ic[1])
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        t, n = solver.run(work[0], work[1], t_end=T_END, nsteps=args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+        steps = n
+    wall = sorted(times)[len(times) // 2]
+    value = dofs * steps / wall
+
+    # dominant kernel: the stage kernel, 3 launches per step; algorithmic bytes
+    # per launch = (64 B per DOF-update / 3 stages) x DOFs
+    bytes_per_launch = BYTES_PER_DOF_UPDATE / 3.0 * dofs
+    launch_s = wall / (3 * steps)
+    achieved = bytes_per_launch / launch_s / 1e9
+    out = {
+        "metric": "DOF-updates/s at P2 (plain vs batched) and adjoint/forward time ratio",
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "1D Euler two-state Riemann problem, outflow, N=16384 primal + 16385 dual cells, "
+                               "P2 Legendre modal, SSP-RK3 + OE, CFL 0.15, T=0.2, seed 0",
+                   "dofs": dofs, "t_end": t, "mode": args.mode, "tile": args.tile},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stage (one RK stage + OE of the previous stage)",
+                     "launch_us": 1e6 * launch_s},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    solver.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

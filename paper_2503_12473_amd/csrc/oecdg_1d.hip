@@ -18,13 +18,12 @@
 //   6. writes the tile's partial statistics of that output for the next stage.
 // The OE of the last stage of a run is applied by the final kernel.
 #include "oecdg_internal.h"
+#include "oecdg_tables.h"
 
 #include <math.h>
 #include <string.h>
 
 namespace oecdg {
-
-__constant__ Tab1D c_tab[MAXK + 1];
 
 constexpr int WAVE = 64;
 
@@ -68,18 +67,27 @@ template <> struct FluxT<2> {          // Euler (rho, m, E), ideal gas
 };
 
 // ------------------------------------------------------ shared-state access ---
-// Values written by other workgroups of the same launch (persistent mode) are
-// read with device-scope atomic loads so they always go through the vector
-// memory path.
+// Between kernel launches plain loads see the previous kernel's stores.  In
+// the persistent launch, values written by other workgroups of the same
+// launch are read with device-scope atomic loads after the grid barrier.
 
-__device__ inline long long ld_ll(const long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline double ld_d(const double *p, bool coherent) {
+    return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
 }
-__device__ inline double ld_d(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline int ld_i(const int *p, bool coherent) {
+    return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
 }
-__device__ inline int ld_i(const int *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline long long ld_ll(const long long *p, bool coherent) {
+    return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+}
+__device__ inline Slot ld_slot(const Slot *p, bool coherent) {
+    Slot s;
+    s.t = ld_d(&p->t, coherent);
+    s.tau = ld_d(&p->tau, coherent);
+    s.tau_max = ld_d(&p->tau_max, coherent);
+    s.done = ld_i(&p->done, coherent);
+    s.last = ld_i(&p->last, coherent);
+    return s;
 }
 
 // ------------------------------------------------------------- reductions ---
@@ -94,35 +102,55 @@ __device__ inline double stat_op(int kind, double x, double y) {
     return kind == 0 ? x + y : (kind == 1 ? fmax(x, y) : fmin(x, y));
 }
 
-// Reduce the NSTAT partials of tiles [tile0, tile0 + ntiles) in a fixed order
-// (per-thread strided accumulation, butterfly within waves, waves in order).
-// Result in red[0..NSTAT) (LDS), visible to all threads on return.
-template <int NT>
-__device__ void reduce_instance(const double *part, int tile0, int ntiles, double *red, double *scratch) {
+// Rows of the partial statistics a consumer needs: (mesh, q, kind) for the
+// NC components, then the two wave-speed rows.
+template <int NC>
+__device__ inline int stat_row(int i) {
+    if (i >= 6 * NC) return ST_BETA + (i - 6 * NC);
+    const int mesh = i / (3 * NC), r = i - mesh * 3 * NC;
+    return stat_index(mesh, r / 3, r % 3);
+}
+
+// Reduce the partials of tiles [tile0, tile0 + ntiles) (layout [row][tile],
+// ntot tiles per row) in a fixed order: per-thread strided accumulation, a
+// butterfly within each wave, then the waves in order.  All loads of a pass
+// are issued before any is consumed.  Result in red[row] (LDS), visible to all
+// threads on return.  The wave-speed rows are reduced only if beta is set.
+template <int NT, int NC>
+__device__ void reduce_instance(const double *part, long long ntot, int tile0, int ntiles, bool beta, double *red,
+                                double *scratch) {
+    constexpr int NS = 6 * NC + 2;
     constexpr int NW = (NT + WAVE - 1) / WAVE;
     const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
-    double acc[NSTAT];
+    const int ns = beta ? NS : NS - 2;
+    double acc[NS];
 #pragma unroll
-    for (int j = 0; j < NSTAT; ++j) acc[j] = stat_identity(stat_kind(j));
+    for (int i = 0; i < NS; ++i) acc[i] = stat_identity(stat_kind(stat_row<NC>(i)));
     for (int t = tid; t < ntiles; t += NT) {
-        const double *row = part + (long long)(tile0 + t) * NSTAT;
 #pragma unroll
-        for (int j = 0; j < NSTAT; ++j) acc[j] = stat_op(stat_kind(j), acc[j], row[j]);
+        for (int i = 0; i < NS; ++i) {
+            if (i < ns) {
+                const int j = stat_row<NC>(i);
+                acc[i] = stat_op(stat_kind(j), acc[i], part[(long long)j * ntot + tile0 + t]);
+            }
+        }
     }
 #pragma unroll
     for (int off = WAVE / 2; off >= 1; off >>= 1) {
 #pragma unroll
-        for (int j = 0; j < NSTAT; ++j) acc[j] = stat_op(stat_kind(j), acc[j], __shfl_xor(acc[j], off, WAVE));
+        for (int i = 0; i < NS; ++i)
+            acc[i] = stat_op(stat_kind(stat_row<NC>(i)), acc[i], __shfl_xor(acc[i], off, WAVE));
     }
     if (lane == 0) {
 #pragma unroll
-        for (int j = 0; j < NSTAT; ++j) scratch[wave * NSTAT + j] = acc[j];
+        for (int i = 0; i < NS; ++i) scratch[wave * NS + i] = acc[i];
     }
     __syncthreads();
-    if (tid < NSTAT) {
+    if (tid < NS) {
+        const int kd = stat_kind(stat_row<NC>(tid));
         double v = scratch[tid];
-        for (int w = 1; w < NW; ++w) v = stat_op(stat_kind(tid), v, scratch[w * NSTAT + tid]);
-        red[tid] = v;
+        for (int w = 1; w < NW; ++w) v = stat_op(kd, v, scratch[w * NS + tid]);
+        red[stat_row<NC>(tid)] = v;
     }
     __syncthreads();
 }
@@ -167,7 +195,7 @@ template <int K, int NC>
 __device__ inline void oe_factors(const double (&own)[NC][K + 1], const double (&nl)[NC][K + 1],
                                   const double (&nr)[NC][K + 1], double beta, const double *sig, double hinv,
                                   double tau, double (&fac)[K + 1]) {
-    const Tab1D &tb = c_tab[K];
+    constexpr Tab<K> tb = make_tab<K>();
     fac[0] = 1.0;
     double S = 0.0;
 #pragma unroll
@@ -205,7 +233,7 @@ __device__ inline void cdg_rate(const double (&own)[FluxT<FLUX>::NC][K + 1],
                                 double (&rate)[FluxT<FLUX>::NC][K + 1]) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC;
-    const Tab1D &tb = c_tab[K];
+    constexpr Tab<K> tb = make_tab<K>();
     double accw[NC][K + 1], accf[NC][K + 1];
 #pragma unroll
     for (int q = 0; q < NC; ++q)
@@ -267,38 +295,38 @@ __device__ inline void lds_cell(const double *s, int li, double (&c)[NC][K + 1])
         for (int m = 0; m <= K; ++m) c[q][m] = s[(q * (K + 1) + m) * W + li];
 }
 
-// Stage the pre-damping input of primal and dual cells [i0-1, i0+T] into LDS
-// (periodic wrap; outflow: constant-extension ghosts for primal -1 and np,
-// zeros for dual cells that do not exist).
+// Element e of the tile's LDS image of the pre-damping input: primal cells
+// [i0-1, i0+T] (rows q*(k+1)+m of length T+2), then dual cells [i0-1, i0+T].
+// Periodic wrap; outflow: constant-extension ghosts for primal -1 and np, zeros
+// for dual cells that do not exist.
+template <int K, int NC, int T>
+__device__ inline double tile_elem(const Inst1D &I, int i0, const double *__restrict__ inC,
+                                   const double *__restrict__ inD, int e) {
+    constexpr int W = T + 2, K1 = K + 1, PER = NC * K1 * W;
+    const int mesh = e >= PER;
+    const int r = e - mesh * PER;
+    const int qm = r / W;
+    const int li = r - qm * W;
+    int gi = i0 - 1 + li;
+    if (mesh == 0) {
+        const int np = I.np;
+        if (I.bc == 0) {
+            gi = ((gi % np) + np) % np;          // periodic (also when the mesh is shorter than a tile)
+            return inC[(long long)qm * np + gi];
+        }
+        if (gi < 0 || gi >= np) return (qm % K1 == 0) ? inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)] : 0.0;
+        return inC[(long long)qm * np + gi];
+    }
+    const int nd = I.nd;
+    if (I.bc == 0) gi = ((gi % nd) + nd) % nd;
+    return (gi >= 0 && gi < nd) ? inD[(long long)qm * nd + gi] : 0.0;
+}
+
 template <int K, int NC, int T>
 __device__ inline void load_tile(const Inst1D &I, int i0, const double *__restrict__ inC,
-                                 const double *__restrict__ inD, double *sC, double *sD) {
-    constexpr int W = T + 2, K1 = K + 1, PER = NC * K1 * W;
-    for (int e = threadIdx.x; e < 2 * PER; e += 2 * T) {
-        const int mesh = e >= PER;
-        const int r = e - mesh * PER;
-        const int qm = r / W;
-        const int li = r - qm * W;
-        int gi = i0 - 1 + li;
-        double v = 0.0;
-        if (mesh == 0) {
-            const int np = I.np;
-            if (I.bc == 0) {
-                gi = ((gi % np) + np) % np;          // periodic (also when the mesh is shorter than a tile)
-                v = inC[(long long)qm * np + gi];
-            } else if (gi < 0 || gi >= np) {
-                v = (qm % K1 == 0) ? inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)] : 0.0;
-            } else {
-                v = inC[(long long)qm * np + gi];
-            }
-            sC[r] = v;
-        } else {
-            const int nd = I.nd;
-            if (I.bc == 0) gi = ((gi % nd) + nd) % nd;
-            if (gi >= 0 && gi < nd) v = inD[(long long)qm * nd + gi];
-            sD[r] = v;
-        }
-    }
+                                 const double *__restrict__ inD, double *s) {
+    constexpr int PER = NC * (K + 1) * (T + 2);
+    for (int e = threadIdx.x; e < 2 * PER; e += 2 * T) s[e] = tile_elem<K, NC, T>(I, i0, inC, inD, e);
 }
 
 // Apply F_tau in LDS to primal cells [i0-1, i0+T-1] and dual cells [i0, i0+T]
@@ -356,13 +384,14 @@ __device__ inline void damp_tile(const Inst1D &I, int i0, double *sC, double *sD
 }
 
 // Partial statistics of one output cell and their reduction over the tile
-// (primal and dual halves separately); written to prow[0..NSTAT).
+// (primal and dual halves separately); written to column tile of part[row][tile].
 template <int K, int FLUX, int T>
 __device__ inline void tile_partials(const Inst1D &I, bool valid, int mesh,
-                                     const double (&out)[FluxT<FLUX>::NC][K + 1], double *prow, double *scratch) {
+                                     const double (&out)[FluxT<FLUX>::NC][K + 1], double *part, long long ntot,
+                                     int tile, double *scratch) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, NV = 3 * NC + 1;
-    const Tab1D &tb = c_tab[K];
+    constexpr Tab<K> tb = make_tab<K>();
     double v[NV];
     int kind[NV];
 #pragma unroll
@@ -393,8 +422,8 @@ __device__ inline void tile_partials(const Inst1D &I, bool valid, int mesh,
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int kd = 0; kd < 3; ++kd) prow[stat_index(mesh, q, kd)] = v[3 * q + kd];
-        prow[ST_BETA + mesh] = v[NV - 1];
+            for (int kd = 0; kd < 3; ++kd) part[stat_index(mesh, q, kd) * ntot + tile] = v[3 * q + kd];
+        part[(ST_BETA + mesh) * ntot + tile] = v[NV - 1];
     }
 }
 
@@ -418,84 +447,43 @@ constexpr int scratch_doubles(int T) { return NSTAT * ((2 * T + WAVE - 1) / WAVE
 // ---------------------------------------------------------- stage tile ---
 
 template <int K, int FLUX, int T>
-__device__ void stage_tile(const StageArgs &a, int l, int tile, double *smem) {
+__device__ void stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem) {
     using F = FluxT<FLUX>;
-    constexpr int NC = F::NC, K1 = K + 1, W = T + 2;
+    constexpr int NC = F::NC, K1 = K + 1, W = T + 2, PER = NC * K1 * W;
+    constexpr int NLD = (2 * PER + 2 * T - 1) / (2 * T);
     const int tid = threadIdx.x;
-    const Tile1D tl = a.tiles[tile];
-    const Inst1D I = a.inst[tl.inst];
+    const bool coh = a.coherent;
+    Tile1D tl;
+    Inst1D I;
+    if (a.ninst == 1) {                      // single instance: everything from the kernel arguments
+        tl.inst = 0;
+        tl.i0 = tile * T;
+        I = a.inst0;
+    } else {
+        tl = a.tiles[tile];
+        I = a.inst[tl.inst];
+    }
     const int i0 = tl.i0;
     const bool lead = (tile == I.tile0) && tid == 0;
     Slot *S = a.slots + 2 * tl.inst;
     const bool single = a.tau_override > 0.0;
-    const long long n = single ? 0 : ld_ll(l == 0 ? &a.step[0] : &a.step[1]);
-    const int par = (int)(n & 1);
-    const int sp = (int)((n + l) & 1);      // parity of the global stage index 3n + l
-    double *sC = smem, *sD = smem + NC * K1 * W;
+    const int sp = (par + l) & 1;           // parity of the global stage index 3n + l
+    double *sC = smem, *sD = smem + PER;
     double *red = smem + lds_doubles(K, NC, T);
     double *scratch = red + NSTAT;
 
-    const bool damp = a.damp_input && I.oe && K > 0 && !(l == 0 && n == 0);
-    if (l == 0 && !single) {
-        // a step that is not taken: carry the time over and leave at once
-        const double t = ld_d(&S[par].t);
-        if (t >= a.t_end || n >= a.nsteps_limit) {
+    // this step's and the previous step's scalars, in one round trip
+    const Slot cur = ld_slot(&S[par], coh), prev = ld_slot(&S[par ^ 1], coh);
+    if (!single) {
+        if (l == 0 && cur.t >= a.t_end) {    // a step that is not taken: carry the time over
             if (lead) {
                 S[par].done = 1;
-                S[par ^ 1].t = t;
+                S[par ^ 1].t = cur.t;
             }
-            if (tile == 0 && tid == 0) a.step[1] = n;
             return;
         }
+        if (l > 0 && cur.done) return;
     }
-    const bool need_red = damp || (l == 0 && !single && a.dt_fixed <= 0.0);
-    if (need_red) reduce_instance<2 * T>(a.part[sp ^ 1], I.tile0, I.ntiles, red, scratch);
-
-    double tau, taumax;
-    int done;
-    if (single) {
-        tau = a.tau_override;
-        taumax = a.taumax_override;
-        done = 0;
-    } else if (l == 0) {
-        const double t = ld_d(&S[par].t);
-        taumax = a.dt_fixed > 0.0 ? a.dt_fixed : I.cfl * I.h / fmax(red[ST_BETA], red[ST_BETA + 1]);
-        tau = taumax;
-        int last = 0;
-        if (t + tau >= a.t_end) {
-            tau = a.t_end - t;
-            last = 1;
-        }
-        done = 0;
-        if (lead) {
-            S[par].tau = tau;
-            S[par].tau_max = taumax;
-            S[par].done = 0;
-            S[par].last = last;
-        }
-        if (tile == 0 && tid == 0) a.step[1] = n;
-    } else {
-        tau = ld_d(&S[par].tau);
-        taumax = ld_d(&S[par].tau_max);
-        done = ld_i(&S[par].done);
-        if (l == 2 && tile == 0 && tid == 0 && n < a.nsteps_limit) a.step[0] = n + 1;
-        if (l == 2 && lead && !done) {
-            const double tnext = ld_i(&S[par].last) ? a.t_end : ld_d(&S[par].t) + tau;
-            S[par ^ 1].t = tnext;
-            a.fin[tl.inst].t = tnext;
-            a.fin[tl.inst].tau = tau;
-            a.fin[tl.inst].nexec = n + 1;
-        }
-    }
-    if (done) return;
-
-    double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    if (damp) finish_stats<NC>(I, red, sig);
-    const double tau_in = (l == 0) ? ld_d(&S[par ^ 1].tau) : tau;
-
-    load_tile<K, NC, T>(I, i0, a.BC[sp] + I.offC, a.BD[sp] + I.offD, sC, sD);
-    __syncthreads();
-    if (damp) damp_tile<K, FLUX, T>(I, i0, sC, sD, sig, tau_in);
 
     const int mesh = tid < T ? 0 : 1;
     const int c = tid - mesh * T;
@@ -503,6 +491,71 @@ __device__ void stage_tile(const StageArgs &a, int l, int tile, double *smem) {
     const int ncell = mesh == 0 ? I.np : I.nd;
     const bool valid = gi < ncell;
     double *UM = (mesh == 0 ? a.UC + I.offC : a.UD + I.offD);
+
+    // issue every global load that does not depend on the statistics first:
+    // the tile's pre-damping input and this thread's cell of u^n
+    double pre[NLD];
+    {
+        const double *inC = a.BC[sp] + I.offC, *inD = a.BD[sp] + I.offD;
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int e = tid + i * 2 * T;
+            pre[i] = e < 2 * PER ? tile_elem<K, NC, T>(I, i0, inC, inD, e) : 0.0;
+        }
+    }
+    const bool damp = a.damp_input && I.oe && K > 0 && !(l == 0 && first);
+    const bool need_beta = l == 0 && !single && a.dt_fixed <= 0.0;
+    if (damp || need_beta)
+        reduce_instance<2 * T, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.ntiles, need_beta, red, scratch);
+
+    double tau, taumax;
+    if (single) {
+        tau = a.tau_override;
+        taumax = a.taumax_override;
+    } else if (l == 0) {
+        taumax = a.dt_fixed > 0.0 ? a.dt_fixed : I.cfl * I.h / fmax(red[ST_BETA], red[ST_BETA + 1]);
+        tau = taumax;
+        int last = 0;
+        if (cur.t + tau >= a.t_end) {
+            tau = a.t_end - cur.t;
+            last = 1;
+        }
+        if (lead) {
+            S[par].tau = tau;
+            S[par].tau_max = taumax;
+            S[par].done = 0;
+            S[par].last = last;
+        }
+    } else {
+        tau = cur.tau;
+        taumax = cur.tau_max;
+        if (l == 2 && lead) {
+            const double tnext = cur.last ? a.t_end : cur.t + tau;
+            S[par ^ 1].t = tnext;
+            Final *f = a.fin + tl.inst;
+            f->t = tnext;
+            f->tau = tau;
+            f->nexec = ld_ll(&f->nexec, coh) + 1;
+        }
+    }
+
+    double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    if (damp) finish_stats<NC>(I, red, sig);
+    const double tau_in = (l == 0) ? prev.tau : tau;
+
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+        const int e = tid + i * 2 * T;
+        if (e < 2 * PER) smem[e] = pre[i];
+    }
+    // u^n of this thread's cell: its latency overlaps the damping below
+    double un[NC][K1];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m < K1; ++m) un[q][m] = (l > 0 && valid) ? UM[(long long)(q * K1 + m) * ncell + gi] : 0.0;
+    __syncthreads();
+    if (damp) damp_tile<K, FLUX, T>(I, i0, sC, sD, sig, tau_in);
 
     double own[NC][K1], nl[NC][K1], nr[NC][K1];
     if (mesh == 0) {
@@ -531,13 +584,8 @@ __device__ void stage_tile(const StageArgs &a, int l, int tile, double *smem) {
 #pragma unroll
         for (int m = 0; m < K1; ++m) {
             const double v = own[q][m] + tau * rate[q][m];
-            double o;
-            if (l == 0) {
-                o = v;
-            } else {
-                const double un = valid ? UM[(long long)(q * K1 + m) * ncell + gi] : 0.0;
-                o = (l == 1) ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v;
-            }
+            const double o = (l == 0) ? v : (l == 1 ? 0.75 * un[q][m] + 0.25 * v
+                                                    : (1.0 / 3.0) * un[q][m] + (2.0 / 3.0) * v);
             out[q][m] = o;
             finite = finite && isfinite(o);
         }
@@ -554,10 +602,10 @@ __device__ void stage_tile(const StageArgs &a, int l, int tile, double *smem) {
         if (!finite || !phys) {
             if (!finite) a.err[0] = 1;
             if (!phys) a.err[1] = 1;
-            a.err[3] = (int)(n + 1);
+            a.err[3] = (int)(a.fin[tl.inst].nexec + 1);
         }
     }
-    tile_partials<K, FLUX, T>(I, valid, mesh, out, a.part[sp] + (long long)tile * NSTAT, scratch);
+    tile_partials<K, FLUX, T>(I, valid, mesh, out, a.part[sp], a.ntiles, tile, scratch);
     __syncthreads();
 }
 
@@ -567,8 +615,8 @@ template <int K, int FLUX, int T>
 __device__ void stats_tile(const StageArgs &a, int tile, double *smem) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1;
-    const Tile1D tl = a.tiles[tile];
-    const Inst1D I = a.inst[tl.inst];
+    const Tile1D tl = a.ninst == 1 ? Tile1D{0, tile * T} : a.tiles[tile];
+    const Inst1D I = a.ninst == 1 ? a.inst0 : a.inst[tl.inst];
     const int tid = threadIdx.x;
     const int mesh = tid < T ? 0 : 1;
     const int gi = tl.i0 + tid - mesh * T;
@@ -580,7 +628,7 @@ __device__ void stats_tile(const StageArgs &a, int tile, double *smem) {
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int m = 0; m < K1; ++m) u[q][m] = valid ? src[(long long)(q * K1 + m) * ncell + gi] : 1.0;
-    tile_partials<K, FLUX, T>(I, valid, mesh, u, a.part[1] + (long long)tile * NSTAT, smem + NSTAT);
+    tile_partials<K, FLUX, T>(I, valid, mesh, u, a.part[1], a.ntiles, tile, smem + NSTAT);
     __syncthreads();
 }
 
@@ -590,10 +638,10 @@ __device__ void final_tile(const StageArgs &a, int tile, double *smem) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1, W = T + 2;
     const int tid = threadIdx.x;
-    const Tile1D tl = a.tiles[tile];
-    const Inst1D I = a.inst[tl.inst];
-    const long long N = ld_ll(&a.fin[tl.inst].nexec);
-    const double tau = ld_d(&a.fin[tl.inst].tau);
+    const Tile1D tl = a.ninst == 1 ? Tile1D{0, tile * T} : a.tiles[tile];
+    const Inst1D I = a.ninst == 1 ? a.inst0 : a.inst[tl.inst];
+    const long long N = a.fin[tl.inst].nexec;
+    const double tau = a.fin[tl.inst].tau;
     const int bp = (int)(N & 1);            // buffer holding u_h^{N-1,3} (or the input when N = 0)
     double *sC = smem, *sD = smem + NC * K1 * W;
     double *red = smem + lds_doubles(K, NC, T);
@@ -601,10 +649,10 @@ __device__ void final_tile(const StageArgs &a, int tile, double *smem) {
     const bool damp = N > 0 && I.oe && K > 0;
     double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
     if (damp) {
-        reduce_instance<2 * T>(a.part[(int)((N - 1) & 1)], I.tile0, I.ntiles, red, scratch);
+        reduce_instance<2 * T, NC>(a.part[(int)((N - 1) & 1)], a.ntiles, I.tile0, I.ntiles, false, red, scratch);
         finish_stats<NC>(I, red, sig);
     }
-    load_tile<K, NC, T>(I, tl.i0, a.BC[bp] + I.offC, a.BD[bp] + I.offD, sC, sD);
+    load_tile<K, NC, T>(I, tl.i0, a.BC[bp] + I.offC, a.BD[bp] + I.offD, smem);
     __syncthreads();
     if (damp) damp_tile<K, FLUX, T>(I, tl.i0, sC, sD, sig, tau);
     const int mesh = tid < T ? 0 : 1;
@@ -645,7 +693,9 @@ struct Disp {
 };
 
 template <int K, int FLUX, int T> struct StageFn {
-    __device__ static void go(const StageArgs &a, int l, int tile, double *smem) { stage_tile<K, FLUX, T>(a, l, tile, smem); }
+    __device__ static void go(const StageArgs &a, int l, int par, int first, int tile, double *smem) {
+        stage_tile<K, FLUX, T>(a, l, par, first, tile, smem);
+    }
 };
 template <int K, int FLUX, int T> struct StatsFn {
     __device__ static void go(const StageArgs &a, int tile, double *smem) { stats_tile<K, FLUX, T>(a, tile, smem); }
@@ -659,8 +709,8 @@ __global__ __launch_bounds__(2 * T) void k_stage(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int k = a.inst[a.tiles[tile].inst].k;
-        D::template run<StageFn>(k, a, a.l, tile, smem);
+        const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
+        D::template run<StageFn>(k, a, a.l, a.par, a.first, tile, smem);
     }
 }
 
@@ -669,7 +719,7 @@ __global__ __launch_bounds__(2 * T) void k_stats(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int k = a.inst[a.tiles[tile].inst].k;
+        const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
         D::template run<StatsFn>(k, a, tile, smem);
     }
 }
@@ -679,7 +729,7 @@ __global__ __launch_bounds__(2 * T) void k_final(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-        const int k = a.inst[a.tiles[tile].inst].k;
+        const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
         D::template run<FinalFn>(k, a, tile, smem);
     }
 }
@@ -712,23 +762,23 @@ __device__ inline void grid_barrier(const StageArgs &a) {
     __syncthreads();
 }
 
+// Persistent launch: every workgroup walks all steps and stages; a grid
+// barrier separates consecutive stages.  The statistics a workgroup reads after
+// a barrier are read coherently (a.coherent).
 template <int KM, int FLUX, int T>
 __global__ __launch_bounds__(2 * T) void k_persistent(StageArgs a, long long nsteps, int single_instance) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
-    for (long long it = 0; it < nsteps; ++it) {
+    for (long long n = 0; n < nsteps; ++n) {
+        const int par = (int)(n & 1);
         for (int l = 0; l < 3; ++l) {
             for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-                const int k = a.inst[a.tiles[tile].inst].k;
-                D::template run<StageFn>(k, a, l, tile, smem);
+                const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
+                D::template run<StageFn>(k, a, l, par, n == 0, tile, smem);
             }
             grid_barrier(a);
-            if (l == 0) {
-                const long long n = ld_ll(&a.step[1]);
-                const bool stop = single_instance ? ld_i(&a.slots[n & 1].done) != 0 : n >= a.nsteps_limit;
-                if (stop) return;
-            }
-            if (ld_i(&a.err[2])) return;
+            if (l == 0 && single_instance && ld_i(&a.slots[par].done, true)) return;
+            if (ld_i(&a.err[2], true)) return;
         }
     }
 }
@@ -747,8 +797,6 @@ __global__ void k_init(StageArgs a, int ninst) {
         a.fin[i].nexec = 0;
     }
     if (i == 0) {
-        a.step[0] = 0;
-        a.step[1] = 0;
         a.err[0] = a.err[1] = a.err[2] = a.err[3] = 0;
         a.bar[0] = 0;
         a.bar[1] = 0;
@@ -757,79 +805,7 @@ __global__ void k_init(StageArgs a, int ninst) {
 
 // ------------------------------------------------------------ host side ---
 
-// Gauss-Legendre nodes by Newton iteration on P_Q (library's own tables).
-static double host_leg(int n, double x, int d) {
-    // d-th derivative of P_n via the series P_n^{(d)} from repeated use of
-    // P_n' = sum_{j = n-1, n-3, ...} (2j+1) P_j.
-    if (d == 0) {
-        double p0 = 1.0, p1 = x;
-        if (n == 0) return p0;
-        for (int j = 1; j < n; ++j) {
-            double p2 = ((2 * j + 1) * x * p1 - j * p0) / (j + 1);
-            p0 = p1;
-            p1 = p2;
-        }
-        return p1;
-    }
-    double s = 0.0;
-    for (int j = n - 1; j >= 0; j -= 2) s += (2 * j + 1) * host_leg(j, x, d - 1);
-    return s;
-}
-
-static void host_gauss(int Q, double *s, double *w) {
-    for (int i = 0; i < Q; ++i) {
-        double x = cos(M_PI * (Q - i - 0.25) / (Q + 0.5));
-        for (int it = 0; it < 60; ++it) {
-            double dx = host_leg(Q, x, 0) / host_leg(Q, x, 1);
-            x -= dx;
-            if (fabs(dx) < 1e-16) break;
-        }
-        double dp = host_leg(Q, x, 1);
-        s[i] = x;
-        w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
-    }
-}
-
-hipError_t upload_tables_1d() {
-    Tab1D tabs[MAXK + 1];
-    memset(tabs, 0, sizeof(tabs));
-    for (int K = 0; K <= MAXK; ++K) {
-        Tab1D &t = tabs[K];
-        const int Q = K + 1;
-        double s[8], w[8];
-        host_gauss(Q, s, w);
-        for (int hf = 0; hf < 2; ++hf)
-            for (int g = 0; g < Q; ++g) {
-                const double xi = hf == 0 ? 0.5 * (s[g] - 1.0) : 0.5 * (s[g] + 1.0);
-                const double xn = hf == 0 ? xi + 1.0 : xi - 1.0;
-                for (int n = 0; n <= K; ++n) {
-                    t.E[hf][g][n] = host_leg(n, xn, 0);
-                    t.WP[hf][g][n] = 0.5 * w[g] * host_leg(n, xi, 0);
-                    t.WD[hf][g][n] = 0.5 * w[g] * host_leg(n, xi, 1);
-                }
-            }
-        for (int m = 0; m <= K; ++m)
-            for (int n = 0; n <= K; ++n) {
-                t.D0[m][n] = host_leg(n, 0.0, m);
-                t.D1[m][n] = host_leg(n, 1.0, m);
-            }
-        int c = 0;
-        double pts[10];
-        pts[c++] = -1.0;
-        for (int g = 0; g < Q; ++g) pts[c++] = 0.5 * (s[g] - 1.0);
-        for (int g = 0; g < Q; ++g) pts[c++] = 0.5 * (s[g] + 1.0);
-        pts[c++] = 1.0;
-        t.nsp = c;
-        for (int j = 0; j < c; ++j)
-            for (int n = 0; n <= K; ++n) t.SP[j][n] = host_leg(n, pts[j], 0);
-        double fact = 1.0;
-        for (int m = 0; m <= K; ++m) {
-            if (m > 0) fact *= m;
-            t.C[m] = K > 0 ? (2.0 * m + 1.0) * pow(2.0, m) / ((2.0 * K - 1.0) * fact) : 0.0;
-        }
-    }
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_tab), tabs, sizeof(tabs));
-}
+hipError_t upload_tables_1d() { return hipSuccess; }   // tables are compile-time constants (oecdg_tables.h)
 
 static int tile_index(int tile) { return tile == 32 ? 0 : (tile == 64 ? 1 : (tile == 128 ? 2 : -1)); }
 

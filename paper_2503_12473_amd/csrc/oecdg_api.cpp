@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -28,7 +29,7 @@ struct oecdg_handle {
     bool mixed = false;
     int tile = 64;
     int mode = OECDG_MODE_AUTO;
-    int graph_steps = 16;
+    int graph_steps = 64;
     int grid = 0;
 
     // device memory (library-owned)
@@ -39,19 +40,16 @@ struct oecdg_handle {
     double *part = nullptr;
     double *B = nullptr;     // BC0 | BC1 | BD0 | BD1
     double *U = nullptr;     // UC | UD
-    long long *step = nullptr;
     int *err = nullptr;
     unsigned *bar = nullptr;
     // pinned host mirrors
     Final *fin_h = nullptr;
     int *err_h = nullptr;
-    long long *step_h = nullptr;
 
     // captured graph of graph_steps steps
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap = nullptr;   // capture stream (the caller's stream may be the null stream)
     double g_tend = 0, g_dt = 0;
-    long long g_limit = -1;
     int g_tile = 0, g_steps = 0;
 
     void *ext2d = nullptr;   // 2D state (oecdg_2d.hip)
@@ -156,14 +154,13 @@ StageArgs base_args(oecdg_handle *h) {
     a.BD[1] = h->B + 2 * h->totC + h->totD;
     a.UC = h->U;
     a.UD = h->U + h->totC;
-    a.step = h->step;
     a.err = h->err;
     a.bar = h->bar;
     a.spin_limit = 1LL << 25;
     a.damp_input = 1;
     a.ninst = h->nbatch;
+    if (h->nbatch == 1) a.inst0 = h->inst_h[0];
     a.t_end = INFINITY;
-    a.nsteps_limit = LLONG_MAX;
     return a;
 }
 
@@ -179,19 +176,24 @@ int check_errors(oecdg_handle *h) {
     return OECDG_OK;
 }
 
-int launch_steps(oecdg_handle *h, const StageArgs &base, int nsteps) {
-    for (int s = 0; s < nsteps; ++s)
+// Launch the stage kernels of steps n0 .. n0 + count - 1.
+int launch_steps(oecdg_handle *h, const StageArgs &base, long long n0, long long count) {
+    for (long long n = n0; n < n0 + count; ++n)
         for (int l = 0; l < 3; ++l) {
             StageArgs a = base;
             a.l = l;
+            a.par = (int)(n & 1);
+            a.first = n == 0;
             HIPCHK(h, launch_stage_1d(a, h->kmax, h->flux, h->mixed, h->tile, 0, h->stream));
         }
     return OECDG_OK;
 }
 
+// A graph of graph_steps (even) steps that starts at an odd step index: the
+// parities baked into its nodes hold for every replay after step 0.
 int ensure_graph(oecdg_handle *h, const StageArgs &base) {
-    if (h->gexec && h->g_tend == base.t_end && h->g_dt == base.dt_fixed && h->g_limit == base.nsteps_limit &&
-        h->g_tile == h->tile && h->g_steps == h->graph_steps)
+    if (h->gexec && h->g_tend == base.t_end && h->g_dt == base.dt_fixed && h->g_tile == h->tile &&
+        h->g_steps == h->graph_steps)
         return OECDG_OK;
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec), h->gexec = nullptr;
     hipGraph_t g = nullptr;
@@ -199,7 +201,7 @@ int ensure_graph(oecdg_handle *h, const StageArgs &base) {
     hipStream_t user = h->stream;
     h->stream = h->cap;
     HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    int rc = launch_steps(h, base, h->graph_steps);
+    int rc = launch_steps(h, base, 1, h->graph_steps);
     hipError_t e = hipStreamEndCapture(h->cap, &g);
     h->stream = user;
     if (rc != OECDG_OK) return rc;
@@ -209,27 +211,19 @@ int ensure_graph(oecdg_handle *h, const StageArgs &base) {
     if (e != hipSuccess) return fail(h, OECDG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     h->g_tend = base.t_end;
     h->g_dt = base.dt_fixed;
-    h->g_limit = base.nsteps_limit;
     h->g_tile = h->tile;
     h->g_steps = h->graph_steps;
     return OECDG_OK;
 }
 
-// Has every instance finished?  Reads the device step counter and final records.
-int all_done(oecdg_handle *h, const StageArgs &a, bool &done) {
+// Has every instance reached t_end (or an error been flagged)?
+int all_done(oecdg_handle *h, const StageArgs &a, bool &done, long long &exec0) {
     HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, sizeof(Final) * h->nbatch, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->step_h, h->step, 2 * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->err_h, h->err, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    if (h->err_h[0] || h->err_h[1] || h->err_h[2]) {
-        done = true;
-        return OECDG_OK;
-    }
-    if (h->step_h[0] >= a.nsteps_limit) {
-        done = true;
-        return OECDG_OK;
-    }
+    exec0 = h->fin_h[0].nexec;
     done = true;
+    if (h->err_h[0] || h->err_h[1] || h->err_h[2]) return OECDG_OK;
     for (int b = 0; b < h->nbatch; ++b)
         if (h->fin_h[b].t < a.t_end) done = false;
     return OECDG_OK;
@@ -241,8 +235,8 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
     if (!(t_end > 0.0)) return fail(h, OECDG_EINVAL, "t_end must be positive");
     StageArgs a = base_args(h);
     a.t_end = t_end;
-    a.nsteps_limit = nsteps >= 0 ? nsteps : LLONG_MAX;
     a.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
+    const long long limit = nsteps >= 0 ? nsteps : LLONG_MAX;
     HIPCHK(h, hipMemcpyAsync(a.BC[0], uC, sizeof(double) * h->totC, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(a.BD[0], uD, sizeof(double) * h->totD, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, launch_init_1d(a, h->nbatch, h->stream));
@@ -259,22 +253,29 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
         int grid = h->grid > 0 ? h->grid : (int)h->tiles_h.size();
         if (grid > maxg) grid = maxg;
         if (grid <= 0) return fail(h, OECDG_EHIP, "persistent kernel cannot be made co-resident");
-        long long ns = nsteps >= 0 ? nsteps : LLONG_MAX;
-        HIPCHK(h, launch_persistent_1d(a, h->kmax, h->flux, h->mixed, h->tile, grid, ns, h->stream));
-    } else {
-        bool done = false;
+        StageArgs p = a;
+        p.coherent = 1;
+        HIPCHK(h, launch_persistent_1d(p, h->kmax, h->flux, h->mixed, h->tile, grid, limit, h->stream));
+    } else if (limit > 0) {
         int rc;
-        long long prev = -1;
+        if ((rc = launch_steps(h, a, 0, 1)) != OECDG_OK) return rc;   // step 0: no OE on the initial data
+        long long n = 1, prev = -1;
+        const long long G = h->graph_steps;
         if (mode == OECDG_MODE_GRAPH && (rc = ensure_graph(h, a)) != OECDG_OK) return rc;
-        while (!done) {
-            if (mode == OECDG_MODE_GRAPH) {
+        while (n < limit) {
+            const long long chunk = std::min(G, limit - n);
+            if (mode == OECDG_MODE_GRAPH && chunk == G) {
                 HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
-            } else if ((rc = launch_steps(h, a, h->graph_steps)) != OECDG_OK) {
+            } else if ((rc = launch_steps(h, a, n, chunk)) != OECDG_OK) {
                 return rc;
             }
-            if ((rc = all_done(h, a, done)) != OECDG_OK) return rc;
-            if (!done && h->step_h[0] == prev) return fail(h, OECDG_EINVAL, "time stepping made no progress");
-            prev = h->step_h[0];
+            n += chunk;
+            bool done = false;
+            long long exec0 = 0;
+            if ((rc = all_done(h, a, done, exec0)) != OECDG_OK) return rc;
+            if (done) break;
+            if (exec0 == prev && h->nbatch == 1) return fail(h, OECDG_EINVAL, "time stepping made no progress");
+            prev = exec0;
         }
     }
     StageArgs f = a;
@@ -382,13 +383,11 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
     ALLOC(h->fin, sizeof(Final) * nbatch);
     ALLOC(h->B, sizeof(double) * 2 * (h->totC + h->totD));
     ALLOC(h->U, sizeof(double) * (h->totC + h->totD));
-    ALLOC(h->step, sizeof(long long) * 2);
     ALLOC(h->err, sizeof(int) * 4);
     ALLOC(h->bar, sizeof(unsigned) * 2);
 #undef ALLOC
     if (hipHostMalloc((void **)&h->fin_h, sizeof(Final) * nbatch, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&h->err_h, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&h->step_h, sizeof(long long) * 2, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void **)&h->err_h, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
         oecdg_destroy(h);
         return OECDG_ENOMEM;
     }
@@ -432,7 +431,7 @@ int oecdg_set_option(oecdg_handle *h, int32_t key, int64_t value) {
         return build_tiles(h);
     case OECDG_OPT_GRAPH_STEPS:
         if (value < 1 || value > 4096) return fail(h, OECDG_EINVAL, "graph steps must be 1..4096");
-        h->graph_steps = (int)value;
+        h->graph_steps = (int)((value + 1) / 2 * 2);       // even: parities of the captured nodes repeat
         return OECDG_OK;
     case OECDG_OPT_GRID:
         if (value < 0 || value > (1 << 20)) return fail(h, OECDG_EINVAL, "grid out of range");
@@ -452,13 +451,14 @@ int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out
     a.srcD = uD;
     HIPCHK(h, launch_stats_1d(a, h->kmax, h->flux, h->mixed, h->tile, h->stream));
     const Inst1D &I = h->inst_h[0];
-    std::vector<double> rows((size_t)I.ntiles * NSTAT);
-    HIPCHK(h, hipMemcpyAsync(rows.data(), a.part[1] + (size_t)I.tile0 * NSTAT, rows.size() * sizeof(double),
-                             hipMemcpyDeviceToHost, h->stream));
+    std::vector<double> rows((size_t)2 * I.ntiles);
+    const size_t ntot = h->tiles_h.size();
+    for (int j = 0; j < 2; ++j)
+        HIPCHK(h, hipMemcpyAsync(rows.data() + (size_t)j * I.ntiles, a.part[1] + (ST_BETA + j) * ntot + I.tile0,
+                                 sizeof(double) * I.ntiles, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     double beta = 0.0;
-    for (int t = 0; t < I.ntiles; ++t)
-        for (int j = ST_BETA; j < ST_BETA + 2; ++j) beta = std::fmax(beta, rows[(size_t)t * NSTAT + j]);
+    for (double b : rows) beta = std::fmax(beta, b);
     if (!(beta > 0.0) || !std::isfinite(beta)) return fail(h, OECDG_ENONFINITE, "wave speed is zero or not finite");
     *dt_out = I.cfl * I.h / beta;
     return OECDG_OK;
@@ -477,6 +477,8 @@ int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max, const
     StageArgs a = base_args(h);
     const int sp = stage & 1;                 // step index 0: global stage parity = stage
     a.l = stage;
+    a.par = 0;
+    a.first = 0;
     a.tau_override = dt;
     a.taumax_override = tau_max;
     a.damp_input = 0;
@@ -526,12 +528,10 @@ void oecdg_destroy(oecdg_handle *h) {
     (void)hipFree(h->part);
     (void)hipFree(h->B);
     (void)hipFree(h->U);
-    (void)hipFree(h->step);
     (void)hipFree(h->err);
     (void)hipFree(h->bar);
     if (h->fin_h) (void)hipHostFree(h->fin_h);
     if (h->err_h) (void)hipHostFree(h->err_h);
-    if (h->step_h) (void)hipHostFree(h->step_h);
     if (h->ext2d) {
         oecdg::destroy_2d(h);
     }

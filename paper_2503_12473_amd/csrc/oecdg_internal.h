@@ -10,7 +10,8 @@ namespace oecdg {
 constexpr int MAXK = 3;
 
 // Per-tile partial statistics written by every stage kernel (and by the
-// statistics kernel) for the state it produced.  Index (mesh*3 + q)*3 + kind,
+// statistics kernel) for the state it produced, stored [row][tile].  Row
+// (mesh*3 + q)*3 + kind,
 // kind 0 = sum of cell averages, 1 = max, 2 = min of the point values at the
 // sigma sample points; ST_BETA = largest wave speed at a cell average.
 constexpr int NSTAT = 20;
@@ -45,31 +46,21 @@ struct Final {
     long long nexec;
 };
 
-// Constant tables for degree K (computed on the host at start-up).
-struct Tab1D {
-    double E[2][4][4];   // P_n at the overlapping cell's coordinate of quadrature node g of half h: [h][g][n]
-    double WP[2][4][4];  // (w_g/2) P_m(xi_g) on half h: [h][g][m]
-    double WD[2][4][4];  // (w_g/2) P_m'(xi_g) on half h: [h][g][m]
-    double D0[4][4];     // m-th derivative of P_n at xi = 0: [m][n]
-    double D1[4][4];     // m-th derivative of P_n at xi = 1: [m][n]
-    double SP[10][4];    // P_n at the sigma sample points: [s][n]
-    double C[4];         // (2m+1) 2^m / ((2K-1) m!)
-    int nsp;
-};
-
 struct StageArgs {
     const Inst1D *inst;
     const Tile1D *tiles;
     int ntiles;
     Slot *slots;             // [ninst][2]
     Final *fin;              // [ninst]
-    double *part[2];         // [ntiles][NSTAT] each
+    double *part[2];         // [NSTAT][ntiles] each (row-major by statistic)
     double *BC[2], *BD[2];   // rotating pre-damping stage states
     double *UC, *UD;         // damped u^n of the current step
-    long long *step;         // step[0]: step index read at stage 0; step[1]: copy read at stages 1, 2
-    int *err;                // [0] non-finite, [1] non-physical, [2] barrier timeout, [3] step+1 of first error
+    int *err;                // [0] non-finite, [1] non-physical, [2] barrier timeout, [3] step+1 of an error
     int l;                   // stage of the step (0, 1, 2)
-    long long nsteps_limit;  // no step with index >= limit is taken
+    int par;                 // parity of the step index n
+    int first;               // 1 for step 0 (its input is the initial data: no OE)
+    int coherent;            // 1 in the persistent launch (cross-workgroup reads after a barrier)
+    Inst1D inst0;            // the instance when ninst == 1
     double t_end;
     double dt_fixed;         // > 0: tau = tau_max = dt_fixed
     double tau_override, taumax_override;   // > 0: single-stage call with given tau/tau_max
