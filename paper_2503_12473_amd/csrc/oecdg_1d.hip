@@ -102,6 +102,34 @@ __device__ inline double stat_op(int kind, double x, double y) {
     return kind == 0 ? x + y : (kind == 1 ? fmax(x, y) : fmin(x, y));
 }
 
+// Cross-lane data movement with DPP (plain VALU operations, no LDS round
+// trip).  A 64-bit value moves as two 32-bit halves; lanes that the control
+// does not write keep `old`.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ inline double dpp_d(double v, double old) {
+    const long long x = __builtin_bit_cast(long long, v), o = __builtin_bit_cast(long long, old);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, ROWMASK, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Value of the partner lane (lane ^ 1).
+__device__ inline double pair_swap(double v) { return dpp_d<0xB1>(v, v); }   // quad_perm [1,0,3,2]
+
+// Reduction over the 64 lanes of a wave in a fixed tree (pairs, quads, half
+// rows, rows, then rows 0+1 and 2+3, then all four); the result is in lane 63.
+// Every lane of the wave must be active.
+__device__ inline double wave_reduce(int kind, double v) {
+    const double id = stat_identity(kind);
+    v = stat_op(kind, v, dpp_d<0xB1>(v, id));          // quad_perm [1,0,3,2]
+    v = stat_op(kind, v, dpp_d<0x4E>(v, id));          // quad_perm [2,3,0,1]
+    v = stat_op(kind, v, dpp_d<0x141>(v, id));         // row_half_mirror
+    v = stat_op(kind, v, dpp_d<0x140>(v, id));         // row_mirror
+    v = stat_op(kind, v, dpp_d<0x142, 0xa>(v, id));    // row_bcast:15 into rows 1, 3
+    v = stat_op(kind, v, dpp_d<0x143, 0xc>(v, id));    // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 // Rows of the partial statistics a consumer needs: (mesh, q, kind) for the
 // NC components, then the two wave-speed rows.
 template <int NC>
@@ -111,22 +139,43 @@ __device__ inline int stat_row(int i) {
     return stat_index(mesh, r / 3, r % 3);
 }
 
-// Reduce the partials of tiles [tile0, tile0 + ntiles) (layout [row][tile],
-// ntot tiles per row) in a fixed order: per-thread strided accumulation, a
-// butterfly within each wave, then the waves in order.  All loads of a pass
-// are issued before any is consumed.  Result in red[row] (LDS), visible to all
-// threads on return.  The wave-speed rows are reduced only if beta is set.
+// Reduction of the per-tile partial statistics of tiles [tile0, tile0+ntiles)
+// (layout [row][tile], ntot tiles per row) in a fixed order: per-thread strided
+// accumulation over tiles, a butterfly within each wave, then the waves in
+// order.  Split in two so that the loads of the first two tiles per thread can
+// be issued together with the kernel's other independent loads.  The
+// wave-speed rows take part only when ns = 6 NC + 2.
+template <int NC>
+struct Partials {
+    static constexpr int NS = 6 * NC + 2;
+    double v[2][NS];
+};
+
 template <int NT, int NC>
-__device__ void reduce_instance(const double *part, long long ntot, int tile0, int ntiles, bool beta, double *red,
-                                double *scratch) {
-    constexpr int NS = 6 * NC + 2;
+__device__ inline void load_partials(const double *part, long long ntot, int tile0, int ntiles, int ns,
+                                     Partials<NC> &p) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int t = tid + u * NT;
+#pragma unroll
+        for (int i = 0; i < Partials<NC>::NS; ++i) {
+            const int j = stat_row<NC>(i);
+            p.v[u][i] = (i < ns && t < ntiles) ? part[(long long)j * ntot + tile0 + t] : stat_identity(stat_kind(j));
+        }
+    }
+}
+
+template <int NT, int NC>
+__device__ void finish_partials(const Partials<NC> &p, const double *part, long long ntot, int tile0, int ntiles,
+                                int ns, double *red, double *scratch) {
+    constexpr int NS = Partials<NC>::NS;
     constexpr int NW = (NT + WAVE - 1) / WAVE;
     const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
-    const int ns = beta ? NS : NS - 2;
     double acc[NS];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) acc[i] = stat_identity(stat_kind(stat_row<NC>(i)));
-    for (int t = tid; t < ntiles; t += NT) {
+    for (int i = 0; i < NS; ++i) acc[i] = stat_op(stat_kind(stat_row<NC>(i)), p.v[0][i], p.v[1][i]);
+    for (int t = tid + 2 * NT; t < ntiles; t += NT) {       // more than two tiles per thread
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
             if (i < ns) {
@@ -136,12 +185,8 @@ __device__ void reduce_instance(const double *part, long long ntot, int tile0, i
         }
     }
 #pragma unroll
-    for (int off = WAVE / 2; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < NS; ++i)
-            acc[i] = stat_op(stat_kind(stat_row<NC>(i)), acc[i], __shfl_xor(acc[i], off, WAVE));
-    }
-    if (lane == 0) {
+    for (int i = 0; i < NS; ++i) acc[i] = wave_reduce(stat_kind(stat_row<NC>(i)), acc[i]);
+    if (lane == WAVE - 1) {
 #pragma unroll
         for (int i = 0; i < NS; ++i) scratch[wave * NS + i] = acc[i];
     }
@@ -155,34 +200,46 @@ __device__ void reduce_instance(const double *part, long long ntot, int tile0, i
     __syncthreads();
 }
 
-// Segmented reduction over the two halves of a 2T-thread workgroup (primal
-// threads [0, T), dual threads [T, 2T)).  NV values per thread, kinds given.
-// On return the thread with tid == 0 (primal) and tid == T (dual) hold the
-// half's result.  scratch: NV * (2T / WAVE) doubles of LDS.
-template <int T, int NV>
+template <int NT, int NC>
+__device__ void reduce_instance(const double *part, long long ntot, int tile0, int ntiles, bool beta, double *red,
+                                double *scratch) {
+    const int ns = beta ? Partials<NC>::NS : Partials<NC>::NS - 2;
+    Partials<NC> p;
+    load_partials<NT, NC>(part, ntot, tile0, ntiles, ns, p);
+    finish_partials<NT, NC>(p, part, ntot, tile0, ntiles, ns, red, scratch);
+}
+
+// Threads per workgroup: two per cell (one per half cell) for the T primal
+// and the T dual cells of a tile.
+__host__ __device__ constexpr int nthreads(int T) { return 4 * T; }
+
+// Segmented reduction over the two halves of a workgroup (primal threads
+// [0, H), dual threads [H, 2H)), H a multiple of the wave size.  NV values per
+// thread, kinds given.  On return the threads tid == 0 (primal) and tid == H
+// (dual) hold the half's result (waves combined in order).
+// scratch: NV * (2H / WAVE) doubles of LDS.
+template <int H, int NV>
 __device__ void reduce_halves(double (&v)[NV], const int (&kind)[NV], double *scratch) {
-    constexpr int SEG = T < WAVE ? T : WAVE;
+    static_assert(H % WAVE == 0, "halves are whole waves");
+    constexpr int WPH = H / WAVE;          // waves per half
     const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
 #pragma unroll
-    for (int off = SEG / 2; off >= 1; off >>= 1) {
+    for (int j = 0; j < NV; ++j) v[j] = wave_reduce(kind[j], v[j]);
+    if (lane == WAVE - 1) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j) v[j] = stat_op(kind[j], v[j], __shfl_xor(v[j], off, WAVE));
+        for (int j = 0; j < NV; ++j) scratch[wave * NV + j] = v[j];
     }
-    if constexpr (T > WAVE) {
-        constexpr int WPH = T / WAVE;          // waves per half
-        if (lane == 0) {
+    __syncthreads();
+    if (tid == 0 || tid == H) {
+        const int w0 = tid / WAVE;
 #pragma unroll
-            for (int j = 0; j < NV; ++j) scratch[wave * NV + j] = v[j];
+        for (int j = 0; j < NV; ++j) {
+            double x = scratch[w0 * NV + j];
+            for (int w = 1; w < WPH; ++w) x = stat_op(kind[j], x, scratch[(w0 + w) * NV + j]);
+            v[j] = x;
         }
-        __syncthreads();
-        if (tid == 0 || tid == T) {
-            const int w0 = tid / WAVE;
-            for (int w = 1; w < WPH; ++w)
-#pragma unroll
-                for (int j = 0; j < NV; ++j) v[j] = stat_op(kind[j], v[j], scratch[(w0 + w) * NV + j]);
-        }
-        __syncthreads();
     }
+    __syncthreads();
 }
 
 // ------------------------------------------------------------ cell kernels ---
@@ -222,67 +279,69 @@ __device__ inline void oe_factors(const double (&own)[NC][K + 1], const double (
     }
 }
 
-// Time derivative of the modal coefficients of one cell (equcdg):
-//   da_m/dt = ((2m+1)/2 int w P_m - a_m) / tau_max
-//           + (2m+1)/h (int f(w) P_m' - f(w(x_R)) + (-1)^m f(w(x_L)))
-// where w is the other mesh: nl on the left half, nr on the right half.
+// Contribution of one half of a cell to the time derivative of its modal
+// coefficients (equcdg), without the cell's own coupling term -a_m / tau_max:
+//   (2m+1)/2/tau_max int_half w P_m + (2m+1)/h (int_half f(w) P_m' + edge term)
+// Right half (hf = 1): nb is the overlapping cell on the right, nodes
+// xi_g = (s_g+1)/2, edge term -f(w(x_R)).  Left half (hf = 0): evaluated as the
+// mirror image with the same nodes through P_n(-x) = (-1)^n P_n(x): the
+// neighbour's odd modes, the test functions P_m (odd m) and P_m' (even m) change
+// sign, and the edge term is +(-1)^m f(w(x_L)).
 template <int K, int FLUX>
-__device__ inline void cdg_rate(const double (&own)[FluxT<FLUX>::NC][K + 1],
-                                const double (&nl)[FluxT<FLUX>::NC][K + 1],
-                                const double (&nr)[FluxT<FLUX>::NC][K + 1], double p0, double inv_tm, double hinv,
-                                double (&rate)[FluxT<FLUX>::NC][K + 1]) {
+__device__ inline void cdg_rate_half(const double (&nb)[FluxT<FLUX>::NC][K + 1], int hf, double p0, double inv_tm,
+                                     double hinv, double (&r)[FluxT<FLUX>::NC][K + 1]) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC;
     constexpr Tab<K> tb = make_tab<K>();
+    const double flip = hf ? 1.0 : -1.0;
+    double c[NC][K + 1];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int n = 0; n <= K; ++n) c[q][n] = (n & 1) ? flip * nb[q][n] : nb[q][n];
     double accw[NC][K + 1], accf[NC][K + 1];
 #pragma unroll
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int m = 0; m <= K; ++m) accw[q][m] = accf[q][m] = 0.0;
 #pragma unroll
-    for (int hf = 0; hf < 2; ++hf) {
+    for (int g = 0; g <= K; ++g) {
+        double w[NC], fw[NC];
 #pragma unroll
-        for (int g = 0; g <= K; ++g) {
-            double w[NC], fw[NC];
+        for (int q = 0; q < NC; ++q) {
+            double v = 0.0;
 #pragma unroll
-            for (int q = 0; q < NC; ++q) {
-                double v = 0.0;
-#pragma unroll
-                for (int n = 0; n <= K; ++n) v += (hf == 0 ? nl[q][n] : nr[q][n]) * tb.E[hf][g][n];
-                w[q] = v;
-            }
-            F::f(w, fw, p0);
-#pragma unroll
-            for (int q = 0; q < NC; ++q)
-#pragma unroll
-                for (int m = 0; m <= K; ++m) {
-                    accw[q][m] += tb.WP[hf][g][m] * w[q];
-                    accf[q][m] += tb.WD[hf][g][m] * fw[q];
-                }
+            for (int n = 0; n <= K; ++n) v += c[q][n] * tb.E[1][g][n];
+            w[q] = v;
         }
+        F::f(w, fw, p0);
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 0; m <= K; ++m) {
+                accw[q][m] += tb.WP[1][g][m] * w[q];
+                accf[q][m] += tb.WD[1][g][m] * fw[q];
+            }
     }
-    double wl[NC], wr[NC], fl[NC], fr[NC];
+    double wc[NC], fc[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-        double a = 0.0, b = 0.0;
+        double v = 0.0;
 #pragma unroll
-        for (int n = 0; n <= K; ++n) {
-            a += nl[q][n] * tb.D0[0][n];
-            b += nr[q][n] * tb.D0[0][n];
-        }
-        wl[q] = a;
-        wr[q] = b;
+        for (int n = 0; n <= K; ++n) v += c[q][n] * tb.D0[0][n];
+        wc[q] = v;
     }
-    F::f(wl, fl, p0);
-    F::f(wr, fr, p0);
+    F::f(wc, fc, p0);
 #pragma unroll
-    for (int q = 0; q < NC; ++q)
+    for (int q = 0; q < NC; ++q) {
+        const double edge = hf ? -fc[q] : fc[q];
 #pragma unroll
         for (int m = 0; m <= K; ++m) {
-            const double edge = (m & 1) ? (fr[q] + fl[q]) : (fr[q] - fl[q]);
-            rate[q][m] = inv_tm * ((m + 0.5) * accw[q][m] - own[q][m]) +
-                         (2.0 * m + 1.0) * hinv * (accf[q][m] - edge);
+            const double sw = (m & 1) ? flip : 1.0;
+            const double sf = (m & 1) ? 1.0 : flip;
+            r[q][m] = inv_tm * ((m + 0.5) * (sw * accw[q][m])) + (2.0 * m + 1.0) * hinv * (sf * accf[q][m] + sw * edge);
         }
+    }
 }
 
 // ------------------------------------------------------------ tile pieces ---
@@ -311,14 +370,18 @@ __device__ inline double tile_elem(const Inst1D &I, int i0, const double *__rest
     if (mesh == 0) {
         const int np = I.np;
         if (I.bc == 0) {
-            gi = ((gi % np) + np) % np;          // periodic (also when the mesh is shorter than a tile)
+            gi = gi < 0 ? gi + np : (gi >= np ? gi - np : gi);
+            if (gi < 0 || gi >= np) gi = ((gi % np) + np) % np;   // mesh shorter than a tile
             return inC[(long long)qm * np + gi];
         }
         if (gi < 0 || gi >= np) return (qm % K1 == 0) ? inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)] : 0.0;
         return inC[(long long)qm * np + gi];
     }
     const int nd = I.nd;
-    if (I.bc == 0) gi = ((gi % nd) + nd) % nd;
+    if (I.bc == 0) {
+        gi = gi < 0 ? gi + nd : (gi >= nd ? gi - nd : gi);
+        if (gi < 0 || gi >= nd) gi = ((gi % nd) + nd) % nd;
+    }
     return (gi >= 0 && gi < nd) ? inD[(long long)qm * nd + gi] : 0.0;
 }
 
@@ -326,32 +389,27 @@ template <int K, int NC, int T>
 __device__ inline void load_tile(const Inst1D &I, int i0, const double *__restrict__ inC,
                                  const double *__restrict__ inD, double *s) {
     constexpr int PER = NC * (K + 1) * (T + 2);
-    for (int e = threadIdx.x; e < 2 * PER; e += 2 * T) s[e] = tile_elem<K, NC, T>(I, i0, inC, inD, e);
+    for (int e = threadIdx.x; e < 2 * PER; e += nthreads(T)) s[e] = tile_elem<K, NC, T>(I, i0, inC, inD, e);
 }
 
 // Apply F_tau in LDS to primal cells [i0-1, i0+T-1] and dual cells [i0, i0+T]
-// (the cells whose damped values the tile's operator needs), all damping
-// factors computed from the pre-damping values first.
+// (the cells whose damped values the tile's operator needs), one cell per
+// thread, all damping factors computed from the pre-damping values first.
 template <int K, int FLUX, int T>
 __device__ inline void damp_tile(const Inst1D &I, int i0, double *sC, double *sD, const double (*sig)[3],
                                  double tau) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, W = T + 2, K1 = K + 1;
+    static_assert(nthreads(T) >= 2 * T + 2, "one damping item per thread");
     const double hinv = 1.0 / I.h;
-    double fac[2][K1];
-    int cell[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int w = threadIdx.x + c * 2 * T;
-        cell[c] = -1;
-        if (w >= 2 * T + 2) continue;
-        const int mesh = w < T + 1 ? 0 : 1;
-        const int li = mesh == 0 ? w : w - T;          // primal 0..T, dual 1..T+1
-        const int gi = i0 - 1 + li;
-        bool real;
-        if (mesh == 0) real = (I.bc == 0) || (gi >= 0 && gi < I.np);
-        else real = (I.bc == 0) || (gi >= 0 && gi < I.nd);
-        if (!real) continue;
+    double fac[K1];
+    const int w = threadIdx.x;
+    const int mesh = w < T + 1 ? 0 : 1;
+    const int li = mesh == 0 ? w : w - T;          // primal 0..T, dual 1..T+1
+    const int gi = i0 - 1 + li;
+    bool active = w < 2 * T + 2;
+    if (active && I.bc != 0) active = mesh == 0 ? (gi >= 0 && gi < I.np) : (gi >= 0 && gi < I.nd);
+    if (active) {
         double own[NC][K1], nl[NC][K1], nr[NC][K1];
         if (mesh == 0) {
             lds_cell<K, NC, W>(sC, li, own);
@@ -366,32 +424,32 @@ __device__ inline void damp_tile(const Inst1D &I, int i0, double *sC, double *sD
 #pragma unroll
         for (int q = 0; q < NC; ++q) ubar[q] = own[q][0];
         const double beta = F::speed(ubar, I.p0);
-        oe_factors<K, NC>(own, nl, nr, beta, sig[mesh], hinv, tau, fac[c]);
-        cell[c] = mesh * W + li;
+        oe_factors<K, NC>(own, nl, nr, beta, sig[mesh], hinv, tau, fac);
     }
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        if (cell[c] < 0) continue;
-        const int mesh = cell[c] / W, li = cell[c] - mesh * W;
+    if (active) {
         double *s = mesh == 0 ? sC : sD;
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 1; m <= K; ++m) s[(q * K1 + m) * W + li] *= fac[c][m];
+            for (int m = 1; m <= K; ++m) s[(q * K1 + m) * W + li] *= fac[m];
     }
     __syncthreads();
 }
 
-// Partial statistics of one output cell and their reduction over the tile
-// (primal and dual halves separately); written to column tile of part[row][tile].
+// Partial statistics of the tile's output: each thread of a cell's pair takes
+// half of the sigma sample points (hf = 1: the right-half nodes and xi = 1;
+// hf = 0: their mirror images, through the sign flip of odd modes); the cell
+// average counts once (hf = 0).  Reduced over the primal and dual halves of the
+// workgroup and written to column tile of part[row][tile].
 template <int K, int FLUX, int T>
-__device__ inline void tile_partials(const Inst1D &I, bool valid, int mesh,
+__device__ inline void tile_partials(const Inst1D &I, bool valid, int mesh, int hf,
                                      const double (&out)[FluxT<FLUX>::NC][K + 1], double *part, long long ntot,
                                      int tile, double *scratch) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, NV = 3 * NC + 1;
     constexpr Tab<K> tb = make_tab<K>();
+    const double flip = hf ? 1.0 : -1.0;
     double v[NV];
     int kind[NV];
 #pragma unroll
@@ -401,14 +459,14 @@ __device__ inline void tile_partials(const Inst1D &I, bool valid, int mesh,
         kind[3 * q + 2] = 2;
         double mx = -INFINITY, mn = INFINITY;
 #pragma unroll
-        for (int s = 0; s < 2 * K + 4; ++s) {
+        for (int sidx = K + 2; sidx < 2 * K + 4; ++sidx) {
             double x = 0.0;
 #pragma unroll
-            for (int n = 0; n <= K; ++n) x += out[q][n] * tb.SP[s][n];
+            for (int n = 0; n <= K; ++n) x += ((n & 1) ? flip * out[q][n] : out[q][n]) * tb.SP[sidx][n];
             mx = fmax(mx, x);
             mn = fmin(mn, x);
         }
-        v[3 * q] = valid ? out[q][0] : 0.0;
+        v[3 * q] = (valid && hf == 0) ? out[q][0] : 0.0;
         v[3 * q + 1] = valid ? mx : -INFINITY;
         v[3 * q + 2] = valid ? mn : INFINITY;
     }
@@ -417,8 +475,8 @@ __device__ inline void tile_partials(const Inst1D &I, bool valid, int mesh,
     for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
     kind[NV - 1] = 1;
     v[NV - 1] = valid ? F::speed(ubar, I.p0) : -INFINITY;
-    reduce_halves<T, NV>(v, kind, scratch);
-    if (threadIdx.x == 0 || threadIdx.x == T) {
+    reduce_halves<2 * T, NV>(v, kind, scratch);
+    if (threadIdx.x == 0 || threadIdx.x == 2 * T) {
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
@@ -442,15 +500,17 @@ __device__ inline void finish_stats(const Inst1D &I, const double *red, double (
 }
 
 constexpr int lds_doubles(int K, int NC, int T) { return 2 * NC * (K + 1) * (T + 2); }
-constexpr int scratch_doubles(int T) { return NSTAT * ((2 * T + WAVE - 1) / WAVE) + NSTAT; }
+constexpr int scratch_doubles(int T) { return NSTAT * ((nthreads(T) + WAVE - 1) / WAVE) + NSTAT; }
 
 // ---------------------------------------------------------- stage tile ---
+// Thread tid works on cell tid/2 of the tile (primal cells first) and on the
+// half cell tid%2 of it.
 
 template <int K, int FLUX, int T>
 __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem) {
     using F = FluxT<FLUX>;
-    constexpr int NC = F::NC, K1 = K + 1, W = T + 2, PER = NC * K1 * W;
-    constexpr int NLD = (2 * PER + 2 * T - 1) / (2 * T);
+    constexpr int NC = F::NC, K1 = K + 1, W = T + 2, PER = NC * K1 * W, NT = nthreads(T);
+    constexpr int NLD = (2 * PER + NT - 1) / NT;
     const int tid = threadIdx.x;
     const bool coh = a.coherent;
     Tile1D tl;
@@ -472,8 +532,34 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     double *red = smem + lds_doubles(K, NC, T);
     double *scratch = red + NSTAT;
 
-    // this step's and the previous step's scalars, in one round trip
+    const int cidx = tid >> 1, hf = tid & 1;
+    const int mesh = cidx < T ? 0 : 1;
+    const int c = cidx - mesh * T;
+    const int gi = i0 + c;
+    const int ncell = mesh == 0 ? I.np : I.nd;
+    const bool valid = gi < ncell;
+    double *UM = (mesh == 0 ? a.UC + I.offC : a.UD + I.offD);
+    const bool damp = a.damp_input && I.oe && K > 0 && !(l == 0 && first);
+    const bool need_beta = l == 0 && !single && a.dt_fixed <= 0.0;
+    const bool need_red = damp || need_beta;
+    const int ns = need_beta ? Partials<NC>::NS : Partials<NC>::NS - 2;
+
+    // One round trip for every load that does not depend on another: this
+    // step's and the previous step's scalars, the tile's pre-damping input and
+    // the previous stage's partial statistics (issued before any test on them).
     const Slot cur = ld_slot(&S[par], coh), prev = ld_slot(&S[par ^ 1], coh);
+    double pre[NLD];
+    {
+        const double *inC = a.BC[sp] + I.offC, *inD = a.BD[sp] + I.offD;
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int e = tid + i * NT;
+            pre[i] = e < 2 * PER ? tile_elem<K, NC, T>(I, i0, inC, inD, e) : 0.0;
+        }
+    }
+    Partials<NC> pv;
+    if (need_red) load_partials<NT, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.ntiles, ns, pv);
+
     if (!single) {
         if (l == 0 && cur.t >= a.t_end) {    // a step that is not taken: carry the time over
             if (lead) {
@@ -484,29 +570,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
         }
         if (l > 0 && cur.done) return;
     }
-
-    const int mesh = tid < T ? 0 : 1;
-    const int c = tid - mesh * T;
-    const int gi = i0 + c;
-    const int ncell = mesh == 0 ? I.np : I.nd;
-    const bool valid = gi < ncell;
-    double *UM = (mesh == 0 ? a.UC + I.offC : a.UD + I.offD);
-
-    // issue every global load that does not depend on the statistics first:
-    // the tile's pre-damping input and this thread's cell of u^n
-    double pre[NLD];
-    {
-        const double *inC = a.BC[sp] + I.offC, *inD = a.BD[sp] + I.offD;
-#pragma unroll
-        for (int i = 0; i < NLD; ++i) {
-            const int e = tid + i * 2 * T;
-            pre[i] = e < 2 * PER ? tile_elem<K, NC, T>(I, i0, inC, inD, e) : 0.0;
-        }
-    }
-    const bool damp = a.damp_input && I.oe && K > 0 && !(l == 0 && first);
-    const bool need_beta = l == 0 && !single && a.dt_fixed <= 0.0;
-    if (damp || need_beta)
-        reduce_instance<2 * T, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.ntiles, need_beta, red, scratch);
+    if (need_red) finish_partials<NT, NC>(pv, a.part[sp ^ 1], a.ntiles, I.tile0, I.ntiles, ns, red, scratch);
 
     double tau, taumax;
     if (single) {
@@ -545,7 +609,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
 
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
-        const int e = tid + i * 2 * T;
+        const int e = tid + i * NT;
         if (e < 2 * PER) smem[e] = pre[i];
     }
     // u^n of this thread's cell: its latency overlaps the damping below
@@ -557,25 +621,26 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     __syncthreads();
     if (damp) damp_tile<K, FLUX, T>(I, i0, sC, sD, sig, tau_in);
 
-    double own[NC][K1], nl[NC][K1], nr[NC][K1];
+    // own cell; the overlapping cell of this thread's half
+    double own[NC][K1], nb[NC][K1];
     if (mesh == 0) {
         lds_cell<K, NC, W>(sC, c + 1, own);
-        lds_cell<K, NC, W>(sD, c + 1, nl);
-        lds_cell<K, NC, W>(sD, c + 2, nr);
+        lds_cell<K, NC, W>(sD, c + 1 + hf, nb);
     } else {
         lds_cell<K, NC, W>(sD, c + 1, own);
-        lds_cell<K, NC, W>(sC, c, nl);
-        lds_cell<K, NC, W>(sC, c + 1, nr);
+        lds_cell<K, NC, W>(sC, c + hf, nb);
     }
     if (l == 0 && !single && valid) {
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 0; m < K1; ++m) UM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
+            for (int m = 0; m < K1; ++m)
+                if (((q * K1 + m) & 1) == hf) UM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
     }
 
-    double rate[NC][K1];
-    cdg_rate<K, FLUX>(own, nl, nr, I.p0, 1.0 / taumax, 1.0 / I.h, rate);
+    const double inv_tm = 1.0 / taumax;
+    double r[NC][K1];
+    cdg_rate_half<K, FLUX>(nb, hf, I.p0, inv_tm, 1.0 / I.h, r);
 
     double out[NC][K1];
     bool finite = true;
@@ -583,7 +648,9 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int m = 0; m < K1; ++m) {
-            const double v = own[q][m] + tau * rate[q][m];
+            const double both = r[q][m] + pair_swap(r[q][m]);   // the two halves (a + b == b + a)
+            const double rate = both - inv_tm * own[q][m];
+            const double v = own[q][m] + tau * rate;
             const double o = (l == 0) ? v : (l == 1 ? 0.75 * un[q][m] + 0.25 * v
                                                     : (1.0 / 3.0) * un[q][m] + (2.0 / 3.0) * v);
             out[q][m] = o;
@@ -594,18 +661,19 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 0; m < K1; ++m) OM[(long long)(q * K1 + m) * ncell + gi] = out[q][m];
+            for (int m = 0; m < K1; ++m)
+                if (((q * K1 + m) & 1) == hf) OM[(long long)(q * K1 + m) * ncell + gi] = out[q][m];
         double ubar[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
         const bool phys = F::physical(ubar, I.p0);
-        if (!finite || !phys) {
+        if (hf == 0 && (!finite || !phys)) {
             if (!finite) a.err[0] = 1;
             if (!phys) a.err[1] = 1;
             a.err[3] = (int)(a.fin[tl.inst].nexec + 1);
         }
     }
-    tile_partials<K, FLUX, T>(I, valid, mesh, out, a.part[sp], a.ntiles, tile, scratch);
+    tile_partials<K, FLUX, T>(I, valid, mesh, hf, out, a.part[sp], a.ntiles, tile, scratch);
     __syncthreads();
 }
 
@@ -618,8 +686,9 @@ __device__ void stats_tile(const StageArgs &a, int tile, double *smem) {
     const Tile1D tl = a.ninst == 1 ? Tile1D{0, tile * T} : a.tiles[tile];
     const Inst1D I = a.ninst == 1 ? a.inst0 : a.inst[tl.inst];
     const int tid = threadIdx.x;
-    const int mesh = tid < T ? 0 : 1;
-    const int gi = tl.i0 + tid - mesh * T;
+    const int cidx = tid >> 1, hf = tid & 1;
+    const int mesh = cidx < T ? 0 : 1;
+    const int gi = tl.i0 + cidx - mesh * T;
     const int ncell = mesh == 0 ? I.np : I.nd;
     const bool valid = gi < ncell;
     const double *src = mesh == 0 ? a.srcC + I.offC : a.srcD + I.offD;
@@ -628,7 +697,7 @@ __device__ void stats_tile(const StageArgs &a, int tile, double *smem) {
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int m = 0; m < K1; ++m) u[q][m] = valid ? src[(long long)(q * K1 + m) * ncell + gi] : 1.0;
-    tile_partials<K, FLUX, T>(I, valid, mesh, u, a.part[1], a.ntiles, tile, smem + NSTAT);
+    tile_partials<K, FLUX, T>(I, valid, mesh, hf, u, a.part[1], a.ntiles, tile, smem + NSTAT);
     __syncthreads();
 }
 
@@ -649,14 +718,16 @@ __device__ void final_tile(const StageArgs &a, int tile, double *smem) {
     const bool damp = N > 0 && I.oe && K > 0;
     double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
     if (damp) {
-        reduce_instance<2 * T, NC>(a.part[(int)((N - 1) & 1)], a.ntiles, I.tile0, I.ntiles, false, red, scratch);
+        reduce_instance<nthreads(T), NC>(a.part[(int)((N - 1) & 1)], a.ntiles, I.tile0, I.ntiles, false, red,
+                                         scratch);
         finish_stats<NC>(I, red, sig);
     }
     load_tile<K, NC, T>(I, tl.i0, a.BC[bp] + I.offC, a.BD[bp] + I.offD, smem);
     __syncthreads();
     if (damp) damp_tile<K, FLUX, T>(I, tl.i0, sC, sD, sig, tau);
-    const int mesh = tid < T ? 0 : 1;
-    const int c = tid - mesh * T;
+    const int cidx = tid >> 1, hf = tid & 1;
+    const int mesh = cidx < T ? 0 : 1;
+    const int c = cidx - mesh * T;
     const int gi = tl.i0 + c;
     const int ncell = mesh == 0 ? I.np : I.nd;
     if (gi < ncell) {
@@ -665,7 +736,8 @@ __device__ void final_tile(const StageArgs &a, int tile, double *smem) {
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 0; m < K1; ++m) dst[(long long)(q * K1 + m) * ncell + gi] = s[(q * K1 + m) * W + c + 1];
+            for (int m = 0; m < K1; ++m)
+                if (((q * K1 + m) & 1) == hf) dst[(long long)(q * K1 + m) * ncell + gi] = s[(q * K1 + m) * W + c + 1];
     }
     __syncthreads();
 }
@@ -705,7 +777,7 @@ template <int K, int FLUX, int T> struct FinalFn {
 };
 
 template <int KM, int FLUX, int T>
-__global__ __launch_bounds__(2 * T) void k_stage(StageArgs a) {
+__global__ __launch_bounds__(4 * T) void k_stage(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
@@ -715,7 +787,7 @@ __global__ __launch_bounds__(2 * T) void k_stage(StageArgs a) {
 }
 
 template <int KM, int FLUX, int T>
-__global__ __launch_bounds__(2 * T) void k_stats(StageArgs a) {
+__global__ __launch_bounds__(4 * T) void k_stats(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
@@ -725,7 +797,7 @@ __global__ __launch_bounds__(2 * T) void k_stats(StageArgs a) {
 }
 
 template <int KM, int FLUX, int T>
-__global__ __launch_bounds__(2 * T) void k_final(StageArgs a) {
+__global__ __launch_bounds__(4 * T) void k_final(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
@@ -766,7 +838,7 @@ __device__ inline void grid_barrier(const StageArgs &a) {
 // barrier separates consecutive stages.  The statistics a workgroup reads after
 // a barrier are read coherently (a.coherent).
 template <int KM, int FLUX, int T>
-__global__ __launch_bounds__(2 * T) void k_persistent(StageArgs a, long long nsteps, int single_instance) {
+__global__ __launch_bounds__(4 * T) void k_persistent(StageArgs a, long long nsteps, int single_instance) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (long long n = 0; n < nsteps; ++n) {
@@ -850,7 +922,7 @@ static void *pick(int k, bool mixed, int flux, int ti) {
 static hipError_t launch(void *fn, int grid, int tile, const StageArgs &a, hipStream_t s) {
     StageArgs copy = a;
     void *args[] = {&copy};
-    return hipLaunchKernel(fn, dim3(grid), dim3(2 * tile), args, 0, s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(nthreads(tile)), args, 0, s);
 }
 
 hipError_t launch_init_1d(const StageArgs &a, int ninst, hipStream_t s) {
@@ -882,7 +954,7 @@ int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile) {
     int per_cu = 0, dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick<3>(kmax, mixed, flux, ti), 2 * tile,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick<3>(kmax, mixed, flux, ti), nthreads(tile),
                                                      0) != hipSuccess)
         return 0;
     return per_cu * ncu;
@@ -895,7 +967,7 @@ hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, bool mix
     StageArgs copy = a;
     int single = a.ninst == 1;
     void *args[] = {&copy, &nsteps, &single};
-    return hipLaunchCooperativeKernel(pick<3>(kmax, mixed, flux, ti), dim3(grid), dim3(2 * tile), args, 0, s);
+    return hipLaunchCooperativeKernel(pick<3>(kmax, mixed, flux, ti), dim3(grid), dim3(nthreads(tile)), args, 0, s);
 }
 
 }  // namespace oecdg

@@ -370,7 +370,9 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
     // default tile: small tiles for small problems (more workgroups), larger otherwise
     int64_t maxn = 0;
     for (auto &I : h->inst_h) maxn = I.nd > maxn ? I.nd : maxn;
-    h->tile = maxn * nbatch <= 65536 ? 32 : 64;
+    // tiles of 64 primal + 64 dual cells unless the mesh is small (more
+    // workgroups) or very large (fewer partial statistics to reduce)
+    h->tile = maxn <= 4096 && nbatch == 1 ? 32 : (maxn <= 65536 ? 64 : 128);
 #define ALLOC(ptr, bytes)                                                    \
     do {                                                                     \
         if (hipMalloc(&(ptr), (bytes)) != hipSuccess) {                      \
