@@ -45,6 +45,26 @@ def parse():
     return ap.parse_args()
 
 
+PROFILE_JSON = os.path.join(ROOT, "profiles", "k_stage_euler1d_p2_n16384.json")
+KERNEL_SOURCES = ["paper_2503_12473_amd/csrc/oecdg_1d.hip", "paper_2503_12473_amd/csrc/oecdg_tables.h",
+                  "paper_2503_12473_amd/csrc/oecdg_internal.h"]
+
+
+def measured_traffic():
+    """HBM bytes per stage-kernel launch from the committed counter profile
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if the kernel sources
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        meta = json.load(open(PROFILE_JSON))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return meta["traffic_bytes_per_launch"] if meta.get("source_sha256") == h.hexdigest() else None
+
+
 def cpu_baseline(target_seconds: float):
     """The CPU oracle, as it stands, on a bounded sample of the same workload:
     the first S steps from the same initial data (S sized to ~target_seconds)."""
@@ -136,7 +156,7 @@ def main():
                                "P2 Legendre modal, SSP-RK3 + OE, CFL 0.15, T=0.2, seed 0",
                    "dofs": dofs, "t_end": t, "mode": args.mode, "tile": args.tile},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_stage (one RK stage + OE of the previous stage)",
                      "launch_us": 1e6 * launch_s},
     }
