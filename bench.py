@@ -28,6 +28,7 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
 BYTES_PER_DOF_UPDATE = 64.0    # 5 reads + 3 writes of one FP64 coefficient per full SSP-RK3 step
 N_CELLS, DEGREE, CFL, T_END, SEED = 16384, 2, 0.15, 0.2, 0
 FULL_STEPS = 33354             # steps to T = 0.2 for seed 0
+BATCH_COUNT, BATCH_STEPS, LOOP_SAMPLE = 512, 1000, 24
 
 
 def parse():
@@ -40,6 +41,7 @@ def parse():
     ap.add_argument("--repeats", type=int, default=3, help="timed repetitions (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle sample length")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the warm-up, copy a device buffer of this many MiB (profiler counter calibration)")
     return ap.parse_args()
@@ -63,6 +65,60 @@ def measured_traffic():
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return meta["traffic_bytes_per_launch"] if meta.get("source_sha256") == h.hexdigest() else None
+
+
+def batched_bench(k_fixed=None):
+    """Batched form: 512 independent 1D Euler Riemann instances (seed 0: N ~
+    U{128..8192}, k ~ U{1,2,3} or k = k_fixed, seeded states), BATCH_STEPS steps
+    each with its own CFL step, advanced together (graph-captured stages, one
+    launch per degree group, autotuned tile) versus a loop of plain per-instance
+    runs (the first LOOP_SAMPLE instances, same steps and tile)."""
+    import torch
+    from paper_2503_12473_amd import inputs
+    from paper_2503_12473_amd.api import OECDG, to_device
+    from paper_2503_12473_amd.autotune import tune_tile
+    specs = inputs.batch_instances(seed=SEED, count=BATCH_COUNT, k_fixed=k_fixed)
+    probs, states = [], []
+    for n, k, st in specs:
+        p, uC, uD = inputs.euler_riemann(n, k, st)
+        probs.append(p)
+        states.append((uC, uD))
+    dofs = [p.dofs() for p in probs]
+    stream = torch.cuda.current_stream()
+
+    def timed(solver, a, b):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        solver.run(a, b, t_end=math.inf, nsteps=BATCH_STEPS)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    icC = torch.cat([to_device(u[0]) for u in states])
+    icD = torch.cat([to_device(u[1]) for u in states])
+    with OECDG(probs, CFL, stream=stream) as solver:
+        tile = tune_tile(solver, icC, icD, steps=5)
+        a, b = icC.clone(), icD.clone()
+        solver.run(a, b, t_end=math.inf, nsteps=20)
+        a.copy_(icC)
+        b.copy_(icD)
+        wall = timed(solver, a, b)
+    batched = sum(dofs) * BATCH_STEPS / wall
+    loop_wall, loop_dofs = 0.0, 0
+    for p, (uC, uD) in list(zip(probs, states))[:LOOP_SAMPLE]:
+        with OECDG(p, CFL, stream=stream) as solver:
+            solver.set_option(2, tile)
+            a, b = to_device(uC), to_device(uD)
+            solver.run(a.clone(), b.clone(), t_end=math.inf, nsteps=20)
+            loop_wall += timed(solver, a, b)
+            loop_dofs += p.dofs()
+    loop = loop_dofs * BATCH_STEPS / loop_wall
+    return {"instances": BATCH_COUNT, "steps": BATCH_STEPS, "dofs": sum(dofs), "tile": tile,
+            "k": "U{1,2,3}" if k_fixed is None else k_fixed,
+            "batched_dof_updates_per_s": batched, "batched_wall_s": wall,
+            "loop_dof_updates_per_s": loop, "loop_sample_instances": LOOP_SAMPLE,
+            "speedup_vs_loop": batched / loop}
 
 
 def cpu_baseline(target_seconds: float):
@@ -160,9 +216,12 @@ def main():
                      "kernel": "k_stage (one RK stage + OE of the previous stage)",
                      "launch_us": 1e6 * launch_s},
     }
+    solver.close()
+    if not args.no_batched:
+        out["batched"] = batched_bench()
+        out["batched_k2"] = batched_bench(k_fixed=2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
-    solver.close()
     print(json.dumps(out))
 
 

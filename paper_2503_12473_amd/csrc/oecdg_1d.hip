@@ -780,7 +780,7 @@ template <int KM, int FLUX, int T>
 __global__ __launch_bounds__(4 * T) void k_stage(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
         const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
         D::template run<StageFn>(k, a, a.l, a.par, a.first, tile, smem);
     }
@@ -790,7 +790,7 @@ template <int KM, int FLUX, int T>
 __global__ __launch_bounds__(4 * T) void k_stats(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
         const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
         D::template run<StatsFn>(k, a, tile, smem);
     }
@@ -800,7 +800,7 @@ template <int KM, int FLUX, int T>
 __global__ __launch_bounds__(4 * T) void k_final(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
-    for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
         const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
         D::template run<FinalFn>(k, a, tile, smem);
     }
@@ -844,7 +844,7 @@ __global__ __launch_bounds__(4 * T) void k_persistent(StageArgs a, long long nst
     for (long long n = 0; n < nsteps; ++n) {
         const int par = (int)(n & 1);
         for (int l = 0; l < 3; ++l) {
-            for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+            for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
                 const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
                 D::template run<StageFn>(k, a, l, par, n == 0, tile, smem);
             }
@@ -910,7 +910,7 @@ static void *pick_f(int flux, int ti) {
 
 template <int WHICH>
 static void *pick(int k, bool mixed, int flux, int ti) {
-    if (mixed) return pick_f<WHICH, -1>(flux, ti);
+    (void)mixed;   // batches of mixed degree launch one kernel per degree group
     switch (k) {
     case 0: return pick_f<WHICH, 0>(flux, ti);
     case 1: return pick_f<WHICH, 1>(flux, ti);
@@ -933,19 +933,19 @@ hipError_t launch_init_1d(const StageArgs &a, int ninst, hipStream_t s) {
 hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s) {
     int ti = tile_index(tile);
     if (ti < 0) return hipErrorInvalidValue;
-    return launch(pick<1>(kmax, mixed, flux, ti), a.ntiles, tile, a, s);
+    return launch(pick<1>(kmax, mixed, flux, ti), a.tend - a.tbeg, tile, a, s);
 }
 
 hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid, hipStream_t s) {
     int ti = tile_index(tile);
     if (ti < 0) return hipErrorInvalidValue;
-    return launch(pick<0>(kmax, mixed, flux, ti), grid > 0 ? grid : a.ntiles, tile, a, s);
+    return launch(pick<0>(kmax, mixed, flux, ti), grid > 0 ? grid : a.tend - a.tbeg, tile, a, s);
 }
 
 hipError_t launch_final_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s) {
     int ti = tile_index(tile);
     if (ti < 0) return hipErrorInvalidValue;
-    return launch(pick<2>(kmax, mixed, flux, ti), a.ntiles, tile, a, s);
+    return launch(pick<2>(kmax, mixed, flux, ti), a.tend - a.tbeg, tile, a, s);
 }
 
 int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile) {

@@ -23,6 +23,10 @@ struct oecdg_handle {
     // 1D batch bookkeeping
     std::vector<Inst1D> inst_h;
     std::vector<Tile1D> tiles_h;
+    struct Group {
+        int k, tbeg, tend;
+    };
+    std::vector<Group> groups;   // tiles ordered by degree: one launch per degree
     std::vector<int64_t> offC, offD;
     int64_t totC = 0, totD = 0;
     int kmax = 0, flux = 0;
@@ -119,12 +123,18 @@ int ensure_tables(oecdg_handle *h) {
 
 int build_tiles(oecdg_handle *h) {
     h->tiles_h.clear();
+    h->groups.clear();
     const int T = h->tile;
-    for (int b = 0; b < h->nbatch; ++b) {
-        Inst1D &I = h->inst_h[b];
-        I.tile0 = (int)h->tiles_h.size();
-        I.ntiles = (I.nd + T - 1) / T;
-        for (int t = 0; t < I.ntiles; ++t) h->tiles_h.push_back(Tile1D{b, t * T});
+    for (int k = 0; k <= MAXK; ++k) {
+        const int tbeg = (int)h->tiles_h.size();
+        for (int b = 0; b < h->nbatch; ++b) {
+            Inst1D &I = h->inst_h[b];
+            if (I.k != k) continue;
+            I.tile0 = (int)h->tiles_h.size();
+            I.ntiles = (I.nd + T - 1) / T;
+            for (int t = 0; t < I.ntiles; ++t) h->tiles_h.push_back(Tile1D{b, t * T});
+        }
+        if ((int)h->tiles_h.size() > tbeg) h->groups.push_back({k, tbeg, (int)h->tiles_h.size()});
     }
     if (h->tiles_d) (void)hipFree(h->tiles_d), h->tiles_d = nullptr;
     if (h->part) (void)hipFree(h->part), h->part = nullptr;
@@ -143,6 +153,8 @@ StageArgs base_args(oecdg_handle *h) {
     a.inst = h->inst_d;
     a.tiles = h->tiles_d;
     a.ntiles = (int)h->tiles_h.size();
+    a.tbeg = 0;
+    a.tend = a.ntiles;
     a.slots = h->slots;
     a.fin = h->fin;
     const size_t ps = (size_t)NSTAT * h->tiles_h.size();
@@ -176,6 +188,37 @@ int check_errors(oecdg_handle *h) {
     return OECDG_OK;
 }
 
+// One launch per degree group (tiles [tbeg, tend) of equal k).
+int stage_all(oecdg_handle *h, const StageArgs &a) {
+    for (const auto &g : h->groups) {
+        StageArgs b = a;
+        b.tbeg = g.tbeg;
+        b.tend = g.tend;
+        HIPCHK(h, launch_stage_1d(b, g.k, h->flux, false, h->tile, 0, h->stream));
+    }
+    return OECDG_OK;
+}
+
+int stats_all(oecdg_handle *h, const StageArgs &a) {
+    for (const auto &g : h->groups) {
+        StageArgs b = a;
+        b.tbeg = g.tbeg;
+        b.tend = g.tend;
+        HIPCHK(h, launch_stats_1d(b, g.k, h->flux, false, h->tile, h->stream));
+    }
+    return OECDG_OK;
+}
+
+int final_all(oecdg_handle *h, const StageArgs &a) {
+    for (const auto &g : h->groups) {
+        StageArgs b = a;
+        b.tbeg = g.tbeg;
+        b.tend = g.tend;
+        HIPCHK(h, launch_final_1d(b, g.k, h->flux, false, h->tile, h->stream));
+    }
+    return OECDG_OK;
+}
+
 // Launch the stage kernels of steps n0 .. n0 + count - 1.
 int launch_steps(oecdg_handle *h, const StageArgs &base, long long n0, long long count) {
     for (long long n = n0; n < n0 + count; ++n)
@@ -184,7 +227,8 @@ int launch_steps(oecdg_handle *h, const StageArgs &base, long long n0, long long
             a.l = l;
             a.par = (int)(n & 1);
             a.first = n == 0;
-            HIPCHK(h, launch_stage_1d(a, h->kmax, h->flux, h->mixed, h->tile, 0, h->stream));
+            int rc = stage_all(h, a);
+            if (rc != OECDG_OK) return rc;
         }
     return OECDG_OK;
 }
@@ -243,19 +287,21 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
     StageArgs st = a;
     st.srcC = a.BC[0];
     st.srcD = a.BD[0];
-    HIPCHK(h, launch_stats_1d(st, h->kmax, h->flux, h->mixed, h->tile, h->stream));
+    int rc0 = stats_all(h, st);
+    if (rc0 != OECDG_OK) return rc0;
 
     int mode = h->mode;
     if (mode == OECDG_MODE_AUTO) mode = OECDG_MODE_GRAPH;
-    if (mode == OECDG_MODE_PERSISTENT && h->nbatch > 1 && nsteps < 0) mode = OECDG_MODE_GRAPH;
+    if (mode == OECDG_MODE_PERSISTENT && ((h->nbatch > 1 && nsteps < 0) || h->groups.size() != 1))
+        mode = OECDG_MODE_GRAPH;   // one cooperative launch serves one degree
     if (mode == OECDG_MODE_PERSISTENT) {
-        int maxg = persistent_max_grid_1d(h->kmax, h->flux, h->mixed, h->tile);
+        int maxg = persistent_max_grid_1d(h->kmax, h->flux, false, h->tile);
         int grid = h->grid > 0 ? h->grid : (int)h->tiles_h.size();
         if (grid > maxg) grid = maxg;
         if (grid <= 0) return fail(h, OECDG_EHIP, "persistent kernel cannot be made co-resident");
         StageArgs p = a;
         p.coherent = 1;
-        HIPCHK(h, launch_persistent_1d(p, h->kmax, h->flux, h->mixed, h->tile, grid, limit, h->stream));
+        HIPCHK(h, launch_persistent_1d(p, h->kmax, h->flux, false, h->tile, grid, limit, h->stream));
     } else if (limit > 0) {
         int rc;
         if ((rc = launch_steps(h, a, 0, 1)) != OECDG_OK) return rc;   // step 0: no OE on the initial data
@@ -281,7 +327,8 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
     StageArgs f = a;
     f.dstC = uC;
     f.dstD = uD;
-    HIPCHK(h, launch_final_1d(f, h->kmax, h->flux, h->mixed, h->tile, h->stream));
+    int rcf = final_all(h, f);
+    if (rcf != OECDG_OK) return rcf;
     HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, sizeof(Final) * h->nbatch, hipMemcpyDeviceToHost, h->stream));
     int rc = check_errors(h);
     if (t_out) *t_out = h->fin_h[0].t;
@@ -451,7 +498,8 @@ int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out
     StageArgs a = base_args(h);
     a.srcC = uC;
     a.srcD = uD;
-    HIPCHK(h, launch_stats_1d(a, h->kmax, h->flux, h->mixed, h->tile, h->stream));
+    int rcs = stats_all(h, a);
+    if (rcs != OECDG_OK) return rcs;
     const Inst1D &I = h->inst_h[0];
     std::vector<double> rows((size_t)2 * I.ntiles);
     const size_t ntot = h->tiles_h.size();
@@ -492,13 +540,15 @@ int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max, const
     a.BC[sp ^ 1] = h->B + (sp ^ 1) * h->totC;
     a.BD[sp ^ 1] = h->B + 2 * h->totC + (sp ^ 1) * h->totD;
     HIPCHK(h, launch_init_1d(a, 1, h->stream));
-    HIPCHK(h, launch_stage_1d(a, h->kmax, h->flux, h->mixed, h->tile, 0, h->stream));
+    int rcs = stage_all(h, a);
+    if (rcs != OECDG_OK) return rcs;
     // final OE with (tau, executed steps) chosen so that it reads that output
     Final f{0.0, dt, (long long)stage + 1};
     HIPCHK(h, hipMemcpyAsync(h->fin, &f, sizeof(Final), hipMemcpyHostToDevice, h->stream));
     a.dstC = uC_out;
     a.dstD = uD_out;
-    HIPCHK(h, launch_final_1d(a, h->kmax, h->flux, h->mixed, h->tile, h->stream));
+    int rcf = final_all(h, a);
+    if (rcf != OECDG_OK) return rcf;
     return check_errors(h);
 }
 

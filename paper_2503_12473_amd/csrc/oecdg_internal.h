@@ -49,7 +49,8 @@ struct Final {
 struct StageArgs {
     const Inst1D *inst;
     const Tile1D *tiles;
-    int ntiles;
+    int ntiles;              // tiles in the whole batch (row length of the partials)
+    int tbeg, tend;          // tiles [tbeg, tend) handled by this launch (one degree group)
     Slot *slots;             // [ninst][2]
     Final *fin;              // [ninst]
     double *part[2];         // [NSTAT][ntiles] each (row-major by statistic)

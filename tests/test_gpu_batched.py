@@ -1,0 +1,99 @@
+"""Batched form: many independent 1D Euler instances of uneven N and degree k
+advanced together (one launch per degree group per stage, graph-captured),
+checked against the oracle instance by instance and, bitwise, against the
+same instances run one at a time on the GPU."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ora
+from paper_2503_12473_amd import inputs, _lib
+from paper_2503_12473_amd.api import OECDG, to_device
+from paper_2503_12473_amd.autotune import tune_tile
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _rel(gC, gD, rC, rD):
+    return max(np.abs(gC - rC).max(), np.abs(gD - rD).max()) / max(np.abs(rC).max(), np.abs(rD).max())
+
+
+def _build(specs):
+    probs, states = [], []
+    for n, k, st in specs:
+        p, uC, uD = inputs.euler_riemann(n, k, st)
+        probs.append(p)
+        states.append((uC, uD))
+    return probs, states
+
+
+def _run_batch(probs, states, tile=None, **kw):
+    with OECDG(probs, 0.15) as s:
+        if tile:
+            s.set_option(_lib.OPT_TILE, tile)
+        gC = torch.cat([to_device(u[0]) for u in states])
+        gD = torch.cat([to_device(u[1]) for u in states])
+        s.run(gC, gD, **kw)
+        offC, offD = s.off_primal, s.off_dual
+        gC, gD = gC.cpu().numpy(), gD.cpu().numpy()
+    return [(gC[offC[b]:offC[b + 1]].reshape(states[b][0].shape), gD[offD[b]:offD[b + 1]].reshape(states[b][1].shape))
+            for b in range(len(probs))]
+
+
+def test_workload_instances_match_oracle():
+    """The first 10 instances of the 512-instance workload draw (seed 0:
+    N ~ U{128..8192}, k ~ U{1,2,3}, Riemann states), 15 steps each with its own
+    CFL time step."""
+    specs = inputs.batch_instances(seed=0, count=512)[:10]
+    print("[batched] N,k =", [(n, k) for n, k, _ in specs], flush=True)
+    probs, states = _build(specs)
+    outs = _run_batch(probs, states, nsteps=15, t_end=float("inf"))
+    for b, (p, (uC, uD)) in enumerate(zip(probs, states)):
+        rC, rD, _, rn = ora.run1d(p, uC, uD, nsteps=15, cfl=0.15)
+        assert rn == 15
+        assert _rel(outs[b][0], outs[b][1], rC, rD) <= TOL, b
+
+
+@pytest.mark.parametrize("tile", [32, 64])
+def test_batched_equals_single_instance_runs_bitwise(tile):
+    """Same tiles, same fixed-order reductions: a batched instance and the same
+    instance on its own handle give identical bits."""
+    specs = inputs.batch_instances(seed=3, count=7, nmin=100, nmax=900)
+    probs, states = _build(specs)
+    outs = _run_batch(probs, states, tile=tile, nsteps=25, t_end=float("inf"))
+    for b, (p, (uC, uD)) in enumerate(zip(probs, states)):
+        solo = _run_batch([p], [(uC, uD)], tile=tile, nsteps=25, t_end=float("inf"))[0]
+        assert np.array_equal(solo[0], outs[b][0]) and np.array_equal(solo[1], outs[b][1]), b
+
+
+def test_batched_run_to_final_time():
+    """Run to a common final time: instances take different numbers of steps;
+    each lands on t_end like its own oracle run."""
+    specs = inputs.batch_instances(seed=9, count=5, nmin=64, nmax=300)
+    probs, states = _build(specs)
+    outs = _run_batch(probs, states, t_end=0.01)
+    for b, (p, (uC, uD)) in enumerate(zip(probs, states)):
+        rC, rD, rt, rn = ora.run1d(p, uC, uD, t_end=0.01, cfl=0.15)
+        assert _rel(outs[b][0], outs[b][1], rC, rD) <= TOL, (b, rn)
+
+
+def test_k2_variant_and_autotuned_tile():
+    """All instances at k = 2 (same N draws); the tile picked by the autotuner
+    gives oracle parity."""
+    specs = inputs.batch_instances(seed=0, count=6, nmin=150, nmax=1200, k_fixed=2)
+    probs, states = _build(specs)
+    with OECDG(probs, 0.15) as s:
+        gC = torch.cat([to_device(u[0]) for u in states])
+        gD = torch.cat([to_device(u[1]) for u in states])
+        tile = tune_tile(s, gC, gD, steps=4)
+        assert tile in (32, 64, 128)
+        s.run(gC, gD, nsteps=20)
+        offC, offD = s.off_primal, s.off_dual
+        gC, gD = gC.cpu().numpy(), gD.cpu().numpy()
+    for b, (p, (uC, uD)) in enumerate(zip(probs, states)):
+        rC, rD, _, _ = ora.run1d(p, uC, uD, nsteps=20, cfl=0.15)
+        bC = gC[offC[b]:offC[b + 1]].reshape(rC.shape)
+        bD = gD[offD[b]:offD[b + 1]].reshape(rD.shape)
+        assert _rel(bC, bD, rC, rD) <= TOL, b
