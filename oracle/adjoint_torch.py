@@ -157,9 +157,26 @@ class Scalar1D:
         return uC, uD
 
 
+class _one_thread:
+    """The tensors here are small ([k+1, n]); intra-op threading only adds
+    contention (tens of times slower with 8 threads), so run on one."""
+
+    def __enter__(self):
+        self.n = torch.get_num_threads()
+        torch.set_num_threads(1)
+
+    def __exit__(self, *exc):
+        torch.set_num_threads(self.n)
+
+
 def gradient(prob, uC0, uD0, nsteps, tau, gC_T, gD_T, checkpoint_every=20):
     """d<gT, u(T)>/du0 for the fixed-step run (numpy in, numpy out); the
     gradient of any loss J is obtained with gT = dJ/du(T)."""
+    with _one_thread():
+        return _gradient(prob, uC0, uD0, nsteps, tau, gC_T, gD_T, checkpoint_every)
+
+
+def _gradient(prob, uC0, uD0, nsteps, tau, gC_T, gD_T, checkpoint_every):
     s = Scalar1D(prob)
     a = torch.tensor(uC0[0], dtype=DT, requires_grad=True)
     b = torch.tensor(uD0[0], dtype=DT, requires_grad=True)
@@ -170,7 +187,7 @@ def gradient(prob, uC0, uD0, nsteps, tau, gC_T, gD_T, checkpoint_every=20):
 
 def forward(prob, uC0, uD0, nsteps, tau):
     s = Scalar1D(prob)
-    with torch.no_grad():
+    with torch.no_grad(), _one_thread():
         oC, oD = s.run(torch.tensor(uC0[0], dtype=DT), torch.tensor(uD0[0], dtype=DT), nsteps, tau)
     return oC.numpy()[None].copy(), oD.numpy()[None].copy()
 

@@ -56,6 +56,9 @@ struct oecdg_handle {
     double g_tend = 0, g_dt = 0;
     int g_tile = 0, g_steps = 0;
 
+    double *adj_ws = nullptr;    // adjoint workspace (checkpoints, segment states, adjoint buffers)
+    size_t adj_bytes = 0;
+
     void *ext2d = nullptr;   // 2D state (oecdg_2d.hip)
     std::string last;
 };
@@ -338,6 +341,130 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
 
 }  // namespace
 
+// Discrete adjoint of a fixed-step run (scalar periodic 1D).  Pass 1 runs the
+// forward steps and keeps the damped state every `ckpt` steps.  Then, segment
+// by segment from the end, the forward kernels recompute the segment keeping
+// every stage's undamped output h, damped input s and per-tile partial
+// statistics, and the adjoint kernels walk the stages backwards.
+int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int64_t nsteps, double dt,
+                      const double *gCT, const double *gDT, double *gC0, double *gD0, int ckpt) {
+    const Inst1D I = h->inst_h[0];
+    if (I.nc != 1 || I.bc != OECDG_BC_PERIODIC || I.flux == OECDG_FLUX_EULER)
+        return fail(h, OECDG_EUNSUPPORTED, "adjoint: scalar flux on a periodic mesh only");
+    const int n = I.np, K1 = I.k + 1;
+    const size_t S = (size_t)K1 * n, S2 = 2 * S;           // one mesh, both meshes
+    const long long nseg = nsteps > 0 ? (nsteps + ckpt - 1) / ckpt : 0;
+    const size_t ntile = h->tiles_h.size(), psz = (size_t)NSTAT * ntile;
+    const int NB = adj_block_size(), nb = (n + NB - 1) / NB;
+    // workspace: checkpoints | segment states (6 per step) | partials (3 per step) | 8 adjoint buffers | block partials
+    const size_t need = (nseg + 1) * S2 + (size_t)ckpt * 6 * S2 + (size_t)ckpt * 3 * psz + 8 * S2 +
+                        (size_t)2 * nb * adj_block_partials();
+    if (need * sizeof(double) > h->adj_bytes) {
+        (void)hipFree(h->adj_ws);
+        h->adj_ws = nullptr;
+        h->adj_bytes = 0;
+        if (hipMalloc(&h->adj_ws, need * sizeof(double)) != hipSuccess) return fail(h, OECDG_ENOMEM, "adjoint workspace");
+        h->adj_bytes = need * sizeof(double);
+    }
+    double *ck = h->adj_ws;
+    double *seg = ck + (nseg + 1) * S2;
+    double *fp = seg + (size_t)ckpt * 6 * S2;
+    double *buf = fp + (size_t)ckpt * 3 * psz;
+    double *lam = buf, *l1 = buf + S2, *l2 = buf + 2 * S2, *acc = buf + 3 * S2, *lp = buf + 4 * S2,
+           *cR = buf + 5 * S2, *cL = buf + 6 * S2;
+    double *bp = buf + 8 * S2;
+    auto st = [&](long long j, int which) { return seg + ((size_t)j * 6 + which) * S2; };   // 0 s0,1 h1,2 s1,3 h2,4 s2,5 h3
+    auto pp = [&](long long j, int l) { return fp + ((size_t)j * 3 + l) * psz; };
+
+    StageArgs base = base_args(h);
+    base.dt_fixed = dt;
+    base.t_end = INFINITY;
+    // pass 1: forward, keeping u^n at n = 0, ckpt, 2 ckpt, ...
+    HIPCHK(h, hipMemcpyAsync(ck, uC0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(ck + S, uD0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(base.BC[0], uC0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(base.BD[0], uD0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, launch_init_1d(base, 1, h->stream));
+    int rc;
+    for (long long nn = 0; nn < nsteps; ++nn)
+        for (int l = 0; l < 3; ++l) {
+            StageArgs a = base;
+            a.l = l;
+            a.par = (int)(nn & 1);
+            a.first = nn == 0;
+            if (nn % ckpt == 0) {                            // u^n is read back by stages 1 and 2
+                a.UC = ck + (nn / ckpt) * S2;
+                a.UD = a.UC + S;
+            }
+            if ((rc = stage_all(h, a)) != OECDG_OK) return rc;
+        }
+    // backward
+    HIPCHK(h, hipMemcpyAsync(lam, gCT, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(lam + S, gDT, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    AdjArgs q;
+    memset(&q, 0, sizeof(q));
+    q.k = I.k;
+    q.flux = I.flux;
+    q.n = n;
+    q.nb = nb;
+    q.hinv = 1.0 / I.h;
+    q.p0 = I.p0;
+    q.tau = dt;
+    q.inv_tm = 1.0 / dt;
+    q.fntot = (long long)ntile;
+    q.ftile0 = I.tile0;
+    q.fntiles = I.ntiles;
+    q.lpC = lp, q.lpD = lp + S, q.cRC = cR, q.cRD = cR + S, q.cLC = cL, q.cLD = cL + S;
+    q.bp = bp;
+    q.accC = acc, q.accD = acc + S;
+    q.oe = I.oe && I.k > 0;
+    static const double AL[3] = {0.0, 0.75, 1.0 / 3.0}, BL[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (long long sg = nseg - 1; sg >= 0; --sg) {
+        const long long n0 = sg * ckpt, m = std::min<long long>(ckpt, nsteps - n0);
+        for (long long j = 0; j < m; ++j)                    // recompute the segment
+            for (int l = 0; l < 3; ++l) {
+                const long long nn = n0 + j;
+                StageArgs a = base;
+                a.l = l;
+                a.par = (int)(nn & 1);
+                a.first = j == 0;                           // the checkpoint is already damped
+                const int sp = (a.par + l) & 1;
+                double *in = l == 0 ? (j == 0 ? ck + sg * S2 : st(j - 1, 5)) : st(j, 2 * l - 1);
+                double *out = st(j, 2 * l + 1);
+                a.BC[sp] = in;
+                a.BD[sp] = in + S;
+                a.BC[sp ^ 1] = out;
+                a.BD[sp ^ 1] = out + S;
+                a.UC = st(j, 0);
+                a.UD = st(j, 0) + S;
+                a.DC = l == 0 ? nullptr : st(j, 2 * l);
+                a.DD = l == 0 ? nullptr : st(j, 2 * l) + S;
+                a.part[sp] = pp(j, l);
+                a.part[sp ^ 1] = l > 0 ? pp(j, l - 1) : (j > 0 ? pp(j - 1, 2) : pp(j, 2));
+                if ((rc = stage_all(h, a)) != OECDG_OK) return rc;
+            }
+        for (long long j = m - 1; j >= 0; --j)
+            for (int l = 2; l >= 0; --l) {
+                double *lin = l == 2 ? lam : (l == 1 ? l1 : l2);
+                double *lout = l == 2 ? l1 : (l == 1 ? l2 : lam);
+                q.hC = st(j, 2 * l + 1), q.hD = st(j, 2 * l + 1) + S;
+                q.lamC = lin, q.lamD = lin + S;
+                q.fpart = pp(j, l);
+                q.sC = st(j, 2 * l), q.sD = st(j, 2 * l) + S;
+                q.outC = lout, q.outD = lout + S;
+                q.al = AL[l];
+                q.bl = BL[l];
+                q.stage0 = l == 0;
+                q.acc_init = l == 2;
+                if (q.oe) HIPCHK(h, launch_adj_oe(q, h->stream));
+                HIPCHK(h, launch_adj_rk(q, h->stream));
+            }
+    }
+    HIPCHK(h, hipMemcpyAsync(gC0, lam, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(gD0, lam + S, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    return check_errors(h);
+}
+
 // ============================================================== C ABI ===
 
 extern "C" {
@@ -573,6 +700,7 @@ void oecdg_destroy(oecdg_handle *h) {
     if (!h) return;
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->cap) (void)hipStreamDestroy(h->cap);
+    (void)hipFree(h->adj_ws);
     (void)hipFree(h->inst_d);
     (void)hipFree(h->tiles_d);
     (void)hipFree(h->slots);

@@ -1,0 +1,196 @@
+// oecdg_device.h -- device helpers shared by the forward and adjoint kernels:
+// flux functions, shared-state loads, order-fixed DPP reductions and the
+// reduction of per-tile partial statistics.
+#pragma once
+
+#include "oecdg_internal.h"
+
+#include <math.h>
+
+namespace oecdg {
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------- fluxes ---
+
+template <int FLUX> struct FluxT;
+
+template <> struct FluxT<0> {          // linear advection f = a u
+    static constexpr int NC = 1;
+    __device__ static inline void f(const double *w, double *o, double a) { o[0] = a * w[0]; }
+    __device__ static inline double speed(const double *, double a) { return fabs(a); }
+    __device__ static inline bool physical(const double *, double) { return true; }
+};
+
+template <> struct FluxT<1> {          // Burgers f = u^2 / 2
+    static constexpr int NC = 1;
+    __device__ static inline void f(const double *w, double *o, double) { o[0] = 0.5 * w[0] * w[0]; }
+    __device__ static inline double speed(const double *u, double) { return fabs(u[0]); }
+    __device__ static inline bool physical(const double *, double) { return true; }
+};
+
+template <> struct FluxT<2> {          // Euler (rho, m, E), ideal gas
+    static constexpr int NC = 3;
+    __device__ static inline void f(const double *w, double *o, double g) {
+        const double v = w[1] / w[0];
+        const double p = (g - 1.0) * (w[2] - 0.5 * w[1] * v);
+        o[0] = w[1];
+        o[1] = w[1] * v + p;
+        o[2] = (w[2] + p) * v;
+    }
+    __device__ static inline double speed(const double *u, double g) {
+        const double v = u[1] / u[0];
+        const double p = (g - 1.0) * (u[2] - 0.5 * u[1] * v);
+        return fabs(v) + sqrt(g * p / u[0]);
+    }
+    __device__ static inline bool physical(const double *u, double g) {
+        if (!(u[0] > 0.0)) return false;
+        const double p = (g - 1.0) * (u[2] - 0.5 * u[1] * u[1] / u[0]);
+        return p > 0.0;
+    }
+};
+
+// ------------------------------------------------------ shared-state access ---
+// Between kernel launches plain loads see the previous kernel's stores.  In
+// the persistent launch, values written by other workgroups of the same
+// launch are read with device-scope atomic loads after the grid barrier.
+
+__device__ inline double ld_d(const double *p, bool coherent) {
+    return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+}
+__device__ inline int ld_i(const int *p, bool coherent) {
+    return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+}
+__device__ inline long long ld_ll(const long long *p, bool coherent) {
+    return coherent ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
+}
+__device__ inline Slot ld_slot(const Slot *p, bool coherent) {
+    Slot s;
+    s.t = ld_d(&p->t, coherent);
+    s.tau = ld_d(&p->tau, coherent);
+    s.tau_max = ld_d(&p->tau_max, coherent);
+    s.done = ld_i(&p->done, coherent);
+    s.last = ld_i(&p->last, coherent);
+    return s;
+}
+
+// ------------------------------------------------------------- reductions ---
+
+__device__ inline int stat_kind(int j) { return j >= ST_BETA ? 1 : j % 3; }
+
+__device__ inline double stat_identity(int kind) {
+    return kind == 0 ? 0.0 : (kind == 1 ? -INFINITY : INFINITY);
+}
+
+__device__ inline double stat_op(int kind, double x, double y) {
+    return kind == 0 ? x + y : (kind == 1 ? fmax(x, y) : fmin(x, y));
+}
+
+// Cross-lane data movement with DPP (plain VALU operations, no LDS round
+// trip).  A 64-bit value moves as two 32-bit halves; lanes that the control
+// does not write keep `old`.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ inline double dpp_d(double v, double old) {
+    const long long x = __builtin_bit_cast(long long, v), o = __builtin_bit_cast(long long, old);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)x, CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(x >> 32), CTRL, ROWMASK, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Value of the partner lane (lane ^ 1).
+__device__ inline double pair_swap(double v) { return dpp_d<0xB1>(v, v); }   // quad_perm [1,0,3,2]
+
+// Reduction over the 64 lanes of a wave in a fixed tree (pairs, quads, half
+// rows, rows, then rows 0+1 and 2+3, then all four); the result is in lane 63.
+// Every lane of the wave must be active.
+__device__ inline double wave_reduce(int kind, double v) {
+    const double id = stat_identity(kind);
+    v = stat_op(kind, v, dpp_d<0xB1>(v, id));          // quad_perm [1,0,3,2]
+    v = stat_op(kind, v, dpp_d<0x4E>(v, id));          // quad_perm [2,3,0,1]
+    v = stat_op(kind, v, dpp_d<0x141>(v, id));         // row_half_mirror
+    v = stat_op(kind, v, dpp_d<0x140>(v, id));         // row_mirror
+    v = stat_op(kind, v, dpp_d<0x142, 0xa>(v, id));    // row_bcast:15 into rows 1, 3
+    v = stat_op(kind, v, dpp_d<0x143, 0xc>(v, id));    // row_bcast:31 into rows 2, 3
+    return v;
+}
+
+// Rows of the partial statistics a consumer needs: (mesh, q, kind) for the
+// NC components, then the two wave-speed rows.
+template <int NC>
+__device__ inline int stat_row(int i) {
+    if (i >= 6 * NC) return ST_BETA + (i - 6 * NC);
+    const int mesh = i / (3 * NC), r = i - mesh * 3 * NC;
+    return stat_index(mesh, r / 3, r % 3);
+}
+
+// Reduction of the per-tile partial statistics of tiles [tile0, tile0+ntiles)
+// (layout [row][tile], ntot tiles per row) in a fixed order: per-thread strided
+// accumulation over tiles, a butterfly within each wave, then the waves in
+// order.  Split in two so that the loads of the first two tiles per thread can
+// be issued together with the kernel's other independent loads.  The
+// wave-speed rows take part only when ns = 6 NC + 2.
+template <int NC>
+struct Partials {
+    static constexpr int NS = 6 * NC + 2;
+    double v[2][NS];
+};
+
+template <int NT, int NC>
+__device__ inline void load_partials(const double *part, long long ntot, int tile0, int ntiles, int ns,
+                                     Partials<NC> &p) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int t = tid + u * NT;
+#pragma unroll
+        for (int i = 0; i < Partials<NC>::NS; ++i) {
+            const int j = stat_row<NC>(i);
+            p.v[u][i] = (i < ns && t < ntiles) ? part[(long long)j * ntot + tile0 + t] : stat_identity(stat_kind(j));
+        }
+    }
+}
+
+template <int NT, int NC>
+__device__ void finish_partials(const Partials<NC> &p, const double *part, long long ntot, int tile0, int ntiles,
+                                int ns, double *red, double *scratch) {
+    constexpr int NS = Partials<NC>::NS;
+    constexpr int NW = (NT + WAVE - 1) / WAVE;
+    const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+    double acc[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) acc[i] = stat_op(stat_kind(stat_row<NC>(i)), p.v[0][i], p.v[1][i]);
+    for (int t = tid + 2 * NT; t < ntiles; t += NT) {       // more than two tiles per thread
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            if (i < ns) {
+                const int j = stat_row<NC>(i);
+                acc[i] = stat_op(stat_kind(j), acc[i], part[(long long)j * ntot + tile0 + t]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) acc[i] = wave_reduce(stat_kind(stat_row<NC>(i)), acc[i]);
+    if (lane == WAVE - 1) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) scratch[wave * NS + i] = acc[i];
+    }
+    __syncthreads();
+    if (tid < NS) {
+        const int kd = stat_kind(stat_row<NC>(tid));
+        double v = scratch[tid];
+        for (int w = 1; w < NW; ++w) v = stat_op(kd, v, scratch[w * NS + tid]);
+        red[stat_row<NC>(tid)] = v;
+    }
+    __syncthreads();
+}
+
+template <int NT, int NC>
+__device__ void reduce_instance(const double *part, long long ntot, int tile0, int ntiles, bool beta, double *red,
+                                double *scratch) {
+    const int ns = beta ? Partials<NC>::NS : Partials<NC>::NS - 2;
+    Partials<NC> p;
+    load_partials<NT, NC>(part, ntot, tile0, ntiles, ns, p);
+    finish_partials<NT, NC>(p, part, ntot, tile0, ntiles, ns, red, scratch);
+}
+
+}  // namespace oecdg

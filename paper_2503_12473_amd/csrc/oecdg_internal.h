@@ -56,6 +56,7 @@ struct StageArgs {
     double *part[2];         // [NSTAT][ntiles] each (row-major by statistic)
     double *BC[2], *BD[2];   // rotating pre-damping stage states
     double *UC, *UD;         // damped u^n of the current step
+    double *DC, *DD;         // optional: damped input of stages 1 and 2 (adjoint recomputation)
     int *err;                // [0] non-finite, [1] non-physical, [2] barrier timeout, [3] step+1 of an error
     int l;                   // stage of the step (0, 1, 2)
     int par;                 // parity of the step index n
@@ -74,6 +75,30 @@ struct StageArgs {
     unsigned *bar;           // [0] arrival count, [1] generation
     long long spin_limit;
 };
+
+// Arguments of the adjoint kernels (oecdg_adjoint.hip): scalar periodic 1D,
+// n cells per mesh, modal arrays [m][cell].
+struct AdjArgs {
+    int k, flux, n, nb;            // degree, flux id, cells per mesh, workgroups per mesh
+    double hinv, p0, tau, inv_tm;  // 1/h, flux parameter, tau, 1/tau_max
+    const double *fpart;           // forward per-tile partial statistics of the damped stage output
+    long long fntot;
+    int ftile0, fntiles;
+    const double *hC, *hD;         // undamped stage output h
+    const double *lamC, *lamD;     // adjoint of F(h)
+    double *lpC, *lpD;             // local part of F'(h)^T lambda
+    double *cRC, *cRD, *cLC, *cLD; // coefficients scattered to the right / left neighbours
+    double *bp;                    // block partials
+    const double *sC, *sD;         // damped stage input s_l
+    double *outC, *outD;           // adjoint of s_l
+    double *accC, *accD;           // adjoint of s_0 accumulated over the stages
+    double al, bl;                 // h = al s_0 + bl (s_l + tau L(s_l))
+    int stage0, acc_init, oe, pad;
+};
+hipError_t launch_adj_oe(const AdjArgs &a, hipStream_t s);
+hipError_t launch_adj_rk(const AdjArgs &a, hipStream_t s);
+int adj_block_size();
+int adj_block_partials();
 
 // Host-side launchers (oecdg_1d.hip).
 hipError_t upload_tables_1d();

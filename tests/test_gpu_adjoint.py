@@ -1,0 +1,138 @@
+"""GPU discrete adjoint (oecdg_adjoint) against the CPU adjoint oracle
+(PyTorch autograd of the same scheme) and central finite differences.
+
+Bar: relative L-infinity error <= 1e-6 against the CPU FP64 adjoint (the
+Burgers cases land near 1e-12; smooth advection near 2e-8, where the first
+maximiser of |u - avg| sits on a near-tie between sample points that rounding
+can flip); directional derivatives within 1e-6 of central differences."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint_torch as adj
+from paper_2503_12473_amd import inputs
+from paper_2503_12473_amd.api import OECDG, to_device
+from paper_2503_12473_amd.autograd import run_differentiable
+
+pytestmark = pytest.mark.gpu
+
+ADJ_TOL = 1e-6
+
+
+def _setup(n, k, steps, seed=0):
+    prob, uC, uD, _ = inputs.burgers_fourier(n, k, seed=seed)
+    tau = 0.3 * prob.h / np.abs(uC[0, 0]).max()
+    _, tC, tD, _ = inputs.burgers_fourier(n, k, seed=seed + 1)
+    return prob, uC, uD, tC, tD, tau, steps
+
+
+def _gpu_grad(prob, uC, uD, steps, tau, gC, gD, ckpt):
+    with OECDG(prob, 0.3) as s:
+        a, b = s.adjoint(to_device(uC), to_device(uD), steps, tau, to_device(gC), to_device(gD), ckpt)
+        return a.cpu().numpy().reshape(uC.shape), b.cpu().numpy().reshape(uD.shape)
+
+
+def _gpu_final(prob, uC, uD, steps, tau):
+    with OECDG(prob, 0.3) as s:
+        a, b = to_device(uC), to_device(uD)
+        s.run(a, b, nsteps=steps, dt_fixed=tau)
+        return a.cpu().numpy().reshape(uC.shape), b.cpu().numpy().reshape(uD.shape)
+
+
+def _rel(a, b, ra, rb):
+    return max(np.abs(a - ra).max(), np.abs(b - rb).max()) / max(np.abs(ra).max(), np.abs(rb).max())
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_adjoint_matches_cpu_adjoint(k):
+    """Burgers, N = 256, 50 steps, checkpoints every 20 (ragged last segment)."""
+    prob, uC, uD, tC, tD, tau, steps = _setup(256, k, 50)
+    oC, oD = _gpu_final(prob, uC, uD, steps, tau)
+    _, gC, gD = adj.misfit_loss_grad(prob, oC, oD, tC, tD)
+    print(f"[adjoint] k={k} n=256 steps={steps}", flush=True)
+    g = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 20)
+    r = adj.gradient(prob, uC, uD, steps, tau, gC, gD, checkpoint_every=20)
+    e = _rel(g[0], g[1], r[0], r[1])
+    print(f"[adjoint] k={k} rel err vs CPU adjoint {e:.3e}", flush=True)
+    assert e <= ADJ_TOL
+
+
+def test_adjoint_advection():
+    prob, uC, uD = inputs.advection_sine(128, 2, phase=0.4)
+    rng = np.random.default_rng(3)
+    gC, gD = rng.normal(size=uC.shape), rng.normal(size=uD.shape)
+    tau = 0.2 * prob.h
+    g = _gpu_grad(prob, uC, uD, 30, tau, gC, gD, 8)
+    r = adj.gradient(prob, uC, uD, 30, tau, gC, gD, checkpoint_every=8)
+    e = _rel(g[0], g[1], r[0], r[1])
+    print(f"[adjoint] advection rel err vs CPU adjoint {e:.3e}", flush=True)
+    assert e <= ADJ_TOL
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    prob, uC, uD, tC, tD, tau, steps = _setup(192, 2, 33)
+    rng = np.random.default_rng(5)
+    gC, gD = rng.normal(size=uC.shape), rng.normal(size=uD.shape)
+    a = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 20)
+    b = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 7)
+    c = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 1000)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+
+
+def test_adjoint_is_linear_in_the_seed():
+    prob, uC, uD, tC, tD, tau, steps = _setup(128, 2, 20)
+    rng = np.random.default_rng(6)
+    gC, gD = rng.normal(size=uC.shape), rng.normal(size=uD.shape)
+    a = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 20)
+    b = _gpu_grad(prob, uC, uD, steps, tau, 2.0 * gC, 2.0 * gD, 20)
+    assert np.array_equal(2.0 * a[0], b[0]) and np.array_equal(2.0 * a[1], b[1])
+
+
+def test_adjoint_matches_finite_differences():
+    """Directional derivatives of J(u0) = misfit(u(T)) from GPU forward runs."""
+    prob, uC, uD, tC, tD, tau, steps = _setup(256, 2, 40)
+    oC, oD = _gpu_final(prob, uC, uD, steps, tau)
+    _, gC, gD = adj.misfit_loss_grad(prob, oC, oD, tC, tD)
+    dC, dD = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 20)
+    rng = np.random.default_rng(11)
+    J = lambda a, b: adj.misfit_loss_grad(prob, *_gpu_final(prob, a, b, steps, tau), tC, tD)[0]
+    for _ in range(2):
+        vC = rng.normal(size=uC.shape) * (0.3 ** np.arange(3))[None, :, None]
+        vD = rng.normal(size=uD.shape) * (0.3 ** np.arange(3))[None, :, None]
+        exact = float((dC * vC).sum() + (dD * vD).sum())
+        errs = [abs((J(uC + e * vC, uD + e * vD) - J(uC - e * vC, uD - e * vD)) / (2 * e) - exact) / abs(exact)
+                for e in (1e-5, 1e-6, 1e-7, 1e-8)]
+        assert min(errs) <= 1e-6, errs
+
+
+def test_autograd_function():
+    prob, uC, uD, tC, tD, tau, steps = _setup(128, 2, 25)
+    with OECDG(prob, 0.3) as s:
+        a = to_device(uC).requires_grad_(True)
+        b = to_device(uD).requires_grad_(True)
+        oC, oD = run_differentiable(s, a, b, steps, tau, checkpoint_every=10)
+        w = torch.tensor((prob.h / (2.0 * np.arange(3) + 1.0)), dtype=torch.float64, device="cuda")
+        w = w[:, None].expand(3, prob.n).reshape(-1)
+        loss = 0.5 * ((w * (oC - to_device(tC)) ** 2).sum() + (w * (oD - to_device(tD)) ** 2).sum())
+        loss.backward()
+        g = (a.grad.cpu().numpy().reshape(uC.shape), b.grad.cpu().numpy().reshape(uD.shape))
+    oCn, oDn = oC.detach().cpu().numpy().reshape(uC.shape), oD.detach().cpu().numpy().reshape(uD.shape)
+    _, gC, gD = adj.misfit_loss_grad(prob, oCn, oDn, tC, tD)
+    r = adj.gradient(prob, uC, uD, steps, tau, gC, gD, checkpoint_every=10)
+    assert _rel(g[0], g[1], r[0], r[1]) <= ADJ_TOL
+
+
+@pytest.mark.timeout(900)
+def test_full_size_adjoint():
+    """Burgers workload size: N = 16384, P2, 400 steps, checkpoints every 20."""
+    prob, uC, uD, tC, tD, tau, steps = _setup(16384, 2, 400)
+    oC, oD = _gpu_final(prob, uC, uD, steps, tau)
+    _, gC, gD = adj.misfit_loss_grad(prob, oC, oD, tC, tD)
+    print("[adjoint] full size GPU", flush=True)
+    g = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 20)
+    print("[adjoint] full size CPU oracle", flush=True)
+    r = adj.gradient(prob, uC, uD, steps, tau, gC, gD, checkpoint_every=20)
+    e = _rel(g[0], g[1], r[0], r[1])
+    print(f"[adjoint] full size rel err {e:.3e}", flush=True)
+    assert e <= ADJ_TOL
