@@ -29,6 +29,7 @@ BYTES_PER_DOF_UPDATE = 64.0    # 5 reads + 3 writes of one FP64 coefficient per 
 N_CELLS, DEGREE, CFL, T_END, SEED = 16384, 2, 0.15, 0.2, 0
 FULL_STEPS = 33354             # steps to T = 0.2 for seed 0
 BATCH_COUNT, BATCH_STEPS, LOOP_SAMPLE = 512, 1000, 24
+ADJ_N, ADJ_K, ADJ_STEPS, ADJ_CKPT = 16384, 2, 400, 20
 
 
 def parse():
@@ -42,6 +43,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle sample length")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-form measurement")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the warm-up, copy a device buffer of this many MiB (profiler counter calibration)")
     return ap.parse_args()
@@ -119,6 +121,49 @@ def batched_bench(k_fixed=None):
             "batched_dof_updates_per_s": batched, "batched_wall_s": wall,
             "loop_dof_updates_per_s": loop, "loop_sample_instances": LOOP_SAMPLE,
             "speedup_vs_loop": batched / loop}
+
+
+def adjoint_bench(repeats: int = 3):
+    """Adjoint form: periodic Burgers, N = 16384, P2, seeded 8-mode Fourier
+    initial data (seed 0), ADJ_STEPS fixed steps (dt = 0.3 h / max|u0|),
+    checkpoints every ADJ_CKPT steps.  Times one forward run and one full
+    gradient (checkpointing forward pass, segment recomputation, reverse
+    stages); ratio = gradient time / forward time."""
+    import numpy as np
+    import torch
+    from paper_2503_12473_amd import inputs
+    from paper_2503_12473_amd.api import OECDG, to_device
+    prob, uC, uD, _ = inputs.burgers_fourier(ADJ_N, ADJ_K, seed=SEED)
+    dt = 0.3 * prob.h / float(np.abs(uC[0, 0]).max())
+    stream = torch.cuda.current_stream()
+    ic = (to_device(uC), to_device(uD))
+    rng = np.random.default_rng(SEED + 1)
+    gT = (to_device(rng.normal(size=uC.shape)), to_device(rng.normal(size=uD.shape)))
+
+    def ev(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    with OECDG(prob, 0.3, stream=stream) as solver:
+        a, b = ic[0].clone(), ic[1].clone()
+        solver.run(a, b, nsteps=ADJ_STEPS, dt_fixed=dt)                       # warm-up (graph capture)
+        solver.adjoint(ic[0], ic[1], ADJ_STEPS, dt, gT[0], gT[1], ADJ_CKPT)   # warm-up (workspace)
+        fwd, bwd = [], []
+        for _ in range(repeats):
+            a.copy_(ic[0])
+            b.copy_(ic[1])
+            fwd.append(ev(lambda: solver.run(a, b, nsteps=ADJ_STEPS, dt_fixed=dt)))
+            bwd.append(ev(lambda: solver.adjoint(ic[0], ic[1], ADJ_STEPS, dt, gT[0], gT[1], ADJ_CKPT)))
+    f, g = sorted(fwd)[len(fwd) // 2], sorted(bwd)[len(bwd) // 2]
+    return {"workload": f"periodic Burgers, N={ADJ_N} primal + dual cells, P{ADJ_K}, {ADJ_STEPS} fixed steps, "
+                        f"checkpoints every {ADJ_CKPT}, seed {SEED}",
+            "forward_s": f, "gradient_s": g, "gradient_over_forward": g / f,
+            "forward_dof_updates_per_s": prob.dofs() * ADJ_STEPS / f}
 
 
 def cpu_baseline(target_seconds: float):
@@ -220,6 +265,8 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_bench()
         out["batched_k2"] = batched_bench(k_fixed=2)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

@@ -1,27 +1,38 @@
 // oecdg_adjoint.hip -- discrete adjoint of the 1D scalar RK-OECDG step
 // (periodic mesh, fixed tau), the transpose of the forward kernels' map.
 //
-// Forward stage l of a step (eq:RKCDG with SSP-RK3, then OEstep1):
+// Forward stage l of a step (eq:RKCDG with SSP-RK3, then the OE step):
 //   h_{l+1} = a_l s_0 + b_l (s_l + tau L(s_l)),   s_{l+1} = F_tau(h_{l+1}),
 //   (a_l, b_l) = (0, 1), (3/4, 1/4), (1/3, 2/3); u^{n+1} = s_3.
-// F_tau(h)_j = h_j exp(-tau sum_{m<=j} delta^m(h)) for j >= 1 (OEstep2D),
-// delta^m_K = C_m / h * beta_K (|dR_m| + |dL_m|) / sigma (Sec. 2.2).
-// Given lambda = dJ/ds_{l+1} the reverse stage computes
-//   mu = F'(h)^T lambda                                   (k_adj_oe + gather),
-//   dJ/ds_l = b_l (mu + tau L'(s_l)^T mu),  dJ/ds_0 += a_l mu  (k_adj_rk).
-// Both transposes are evaluated in gather form: a cell collects what its two
-// overlapping neighbours on the other mesh scattered to it.  Non-smooth points
-// follow fixed conventions: d|x|/dx = 0 at x = 0, the L-infinity norm in sigma
-// is attributed to the first maximiser in (cell, sample point) order, and a
-// vanishing sigma contributes nothing.
+// F_tau(h)_j = h_j exp(-tau sum_{m<=j} delta^m(h)) for j >= 1 (the exact
+// solution of the damping ODE), delta^m_K = C_m / h * beta_K (|dR_m| + |dL_m|)
+// / sigma (Sec. 2.2).  Given lambda = dJ/ds_{l+1}, the reverse of stage l is
+//   mu = F'(h_{l+1})^T lambda,
+//   dJ/ds_l = b_l (mu + tau L'(s_l)^T mu),   dJ/ds_0 += a_l mu.
+//
+// One launch per reverse stage.  F'(h)^T lambda splits into a part local to
+// each cell (diagonal, the cell's own traces in delta, beta), coefficients
+// scattered to the two overlapping cells of the other mesh, and two global
+// terms (sigma and the mesh average).  The local part for stage l-1 needs
+// lambda = dJ/ds_l only at the cell itself, so the launch that finishes
+// dJ/ds_l also "prepares" stage l-1: it writes that local part, the scattered
+// coefficients and per-workgroup partials of the global terms, which the next
+// launch gathers.  A prepare-only launch starts each chain.
+//
+// Non-smooth points follow fixed conventions: d|x|/dx = 0 at x = 0, the
+// L-infinity norm in sigma is attributed to the first maximiser in (cell,
+// sample point) order, and a vanishing sigma contributes nothing.
 #include "oecdg_device.h"
 #include "oecdg_internal.h"
 #include "oecdg_tables.h"
 
 namespace oecdg {
 
-constexpr int ADJ_NT = 256;          // threads (= cells) per workgroup
-constexpr int ADJ_BP = 5;            // block partials: sigma-bar, max, first argmax, min, first argmin
+constexpr int ADJ_NT = 128;          // threads (= cells) per workgroup
+constexpr int ADJ_NW = ADJ_NT / WAVE;
+// per-workgroup partials: sigma adjoint, sample max, its first index, sample
+// min, its first index, and the forward average / max / min of the mesh
+constexpr int ADJ_BP = 8;
 
 // Cells of the other mesh that overlap cell c (periodic, n cells per mesh):
 // primal i: left dual i, right dual i+1; dual j: left primal j-1, right primal j.
@@ -37,241 +48,117 @@ __device__ inline void load_cell(const double *u, int n, int c, double (&v)[K + 
     for (int m = 0; m <= K; ++m) v[m] = u[(long long)m * n + c];
 }
 
-// Forward statistics of the stage output (avg, sigma, max, min per mesh) from
-// the forward kernels' per-tile partials, reduced in their fixed order.
-struct MeshStats {
-    double avg[2], sig[2], mx[2], mn[2];
-};
-
-template <int NT>
-__device__ inline MeshStats forward_stats(const AdjArgs &a, double *red, double *scratch) {
-    static_assert(((NT + WAVE - 1) / WAVE) * Partials<1>::NS <= 64, "scratch holds one row per wave");
-    Partials<1> p;
-    const int ns = Partials<1>::NS - 2;
-    load_partials<NT, 1>(a.fpart, a.fntot, a.ftile0, a.fntiles, ns, p);
-    finish_partials<NT, 1>(p, a.fpart, a.fntot, a.ftile0, a.fntiles, ns, red, scratch);
-    MeshStats s;
-#pragma unroll
-    for (int mesh = 0; mesh < 2; ++mesh) {
-        s.avg[mesh] = red[stat_index(mesh, 0, 0)] / (double)a.n;
-        s.mx[mesh] = red[stat_index(mesh, 0, 1)];
-        s.mn[mesh] = red[stat_index(mesh, 0, 2)];
-        s.sig[mesh] = fmax(s.mx[mesh] - s.avg[mesh], s.avg[mesh] - s.mn[mesh]);
-    }
-    return s;
+// Broadcast lane 63 (where wave_reduce leaves its result) to the wave.
+__device__ inline double bcast_last(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffLL), WAVE - 1);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), WAVE - 1);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Block-wide reduction (256 threads, 4 waves, fixed order); result broadcast.
-__device__ inline double block_reduce(int kind, double v, double *scratch) {
+// Wave part of a block reduction: plain values (sum/max/min) and extremum
+// pairs (value, first index); lane 63 stores them into this wave's row of
+// `scratch`.  After one barrier, combine_* fold the rows of all waves.
+template <int NV, int NP>
+__device__ inline void wave_stage(const int (&kind)[NV], double (&v)[NV], const int (&pkind)[NP], double (&pv)[NP],
+                                  double (&pi)[NP], double *scratch) {
+    constexpr int ROW = NV + 2 * NP;
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
-    v = wave_reduce(kind, v);
-    __syncthreads();
-    if (lane == WAVE - 1) scratch[wave] = v;
-    __syncthreads();
-    double r = scratch[0];
-    for (int w = 1; w < ADJ_NT / WAVE; ++w) r = stat_op(kind, r, scratch[w]);
-    __syncthreads();
-    return r;
-}
-
-// ---------------------------------------------------------------- OE pass ---
-// Per cell K of the damped mesh: recompute delta, the damping factors and
-// F(h); write the local part of F'(h)^T lambda (diagonal, own traces, beta),
-// the coefficients scattered to the right/left neighbours through dR/dL, and
-// the block partials of the sigma adjoint and of the first maximiser/minimiser.
-template <int K, int FLUX>
-__global__ __launch_bounds__(ADJ_NT) void k_adj_oe(AdjArgs a) {
-    using F = FluxT<FLUX>;
-    constexpr Tab<K> tb = make_tab<K>();
-    constexpr int NSP = 2 * K + 4;
-    __shared__ double red[NSTAT], scratch[64];
-    const MeshStats st = forward_stats<ADJ_NT>(a, red, scratch);
-    const int mesh = blockIdx.x >= (unsigned)a.nb;
-    const int c = (blockIdx.x - mesh * a.nb) * ADJ_NT + threadIdx.x;
-    const bool valid = c < a.n;
-    const int cc = valid ? c : 0;
-    const double *hM = mesh == 0 ? a.hC : a.hD, *hO = mesh == 0 ? a.hD : a.hC;
-    const double *lam = mesh == 0 ? a.lamC : a.lamD;
-    double own[K + 1], nl[K + 1], nr[K + 1], lm[K + 1];
-    load_cell<K>(hM, a.n, cc, own);
-    load_cell<K>(hO, a.n, nb_left(mesh, cc, a.n), nl);
-    load_cell<K>(hO, a.n, nb_right(mesh, cc, a.n), nr);
-    load_cell<K>(lam, a.n, cc, lm);
-    const double sig = st.sig[mesh];
-    const double beta = F::speed(own, a.p0);
-    double dR[K + 1], dL[K + 1], del[K + 1];
 #pragma unroll
-    for (int m = 0; m <= K; ++m) {
-        double ur = 0.0, ul = 0.0, vr = 0.0, vl = 0.0;
+    for (int i = 0; i < NV; ++i) v[i] = wave_reduce(kind[i], v[i]);
 #pragma unroll
-        for (int q = m; q <= K; ++q) {
-            const double d1 = tb.D1[m][q];
-            ur += own[q] * d1;
-            ul += own[q] * (((q + m) & 1) ? -d1 : d1);
-            vr += nr[q] * tb.D0[m][q];
-            vl += nl[q] * tb.D0[m][q];
-        }
-        dR[m] = ur - vr;
-        dL[m] = ul - vl;
-        del[m] = sig != 0.0 ? tb.C[m] * a.hinv * (beta * (fabs(dR[m]) + fabs(dL[m])) / sig) : 0.0;
+    for (int i = 0; i < NP; ++i) {
+        const double m = bcast_last(wave_reduce(pkind[i], pv[i]));
+        pi[i] = wave_reduce(2, pv[i] == m ? pi[i] : INFINITY);
+        pv[i] = m;
     }
-    double lp[K + 1], out[K + 1];
-    double S = 0.0;
-    lp[0] = lm[0];
-    out[0] = own[0];
+    if (lane == WAVE - 1) {
+        double *row = scratch + wave * ROW;
 #pragma unroll
-    for (int j = 1; j <= K; ++j) {
-        S = (j == 1 ? del[0] : S) + del[j];
-        const double fac = exp(-a.tau * S);
-        out[j] = own[j] * fac;
-        lp[j] = lm[j] * fac;
-    }
-    double cR[K + 1], cL[K + 1], sbar = 0.0;
+        for (int i = 0; i < NV; ++i) row[i] = v[i];
 #pragma unroll
-    for (int m = 0; m <= K; ++m) cR[m] = cL[m] = 0.0;
-    if (sig != 0.0 && K > 0) {
-        double dbeta = 0.0;
-#pragma unroll
-        for (int m = 0; m <= K; ++m) {
-            double g = 0.0;
-#pragma unroll
-            for (int j = (m > 1 ? m : 1); j <= K; ++j) g += lm[j] * out[j];
-            g *= -a.tau;                                    // dJ/d delta^m
-            const double w = g * tb.C[m] * a.hinv / sig;
-            const double sR = (dR[m] > 0.0) - (dR[m] < 0.0), sL = (dL[m] > 0.0) - (dL[m] < 0.0);
-            cR[m] = w * beta * sR;
-            cL[m] = w * beta * sL;
-            dbeta += w * (fabs(dR[m]) + fabs(dL[m]));
-            sbar -= g * del[m] / sig;
-        }
-#pragma unroll
-        for (int q = 0; q <= K; ++q) {
-            double acc = 0.0;
-#pragma unroll
-            for (int m = 0; m <= q; ++m) {
-                const double d1 = tb.D1[m][q];
-                acc += cR[m] * d1 + cL[m] * (((q + m) & 1) ? -d1 : d1);
-            }
-            lp[q] += acc;
-        }
-        if constexpr (FLUX == 1) lp[0] += dbeta * ((own[0] > 0.0) - (own[0] < 0.0));   // beta = |u_bar|
-    }
-    if (valid) {
-        double *LP = mesh == 0 ? a.lpC : a.lpD, *CR = mesh == 0 ? a.cRC : a.cRD, *CL = mesh == 0 ? a.cLC : a.cLD;
-#pragma unroll
-        for (int m = 0; m <= K; ++m) {
-            LP[(long long)m * a.n + c] = lp[m];
-            CR[(long long)m * a.n + c] = cR[m];
-            CL[(long long)m * a.n + c] = cL[m];
-        }
-    }
-    // sample values of h (edges and half-cell nodes, natural order)
-    double vmax = -INFINITY, vmin = INFINITY, imax = INFINITY, imin = INFINITY;
-    if (valid) {
-#pragma unroll
-        for (int sidx = 0; sidx < NSP; ++sidx) {
-            double v = 0.0;
-#pragma unroll
-            for (int q = 0; q <= K; ++q) v += own[q] * tb.SP[sidx][q];
-            const double idx = (double)c * NSP + sidx;
-            if (v > vmax) vmax = v, imax = idx;
-            if (v < vmin) vmin = v, imin = idx;
-        }
-    }
-    const double bsum = block_reduce(0, valid ? sbar : 0.0, scratch);
-    const double bmax = block_reduce(1, vmax, scratch);
-    const double bimax = block_reduce(2, vmax == bmax ? imax : INFINITY, scratch);
-    const double bmin = block_reduce(2, vmin, scratch);
-    const double bimin = block_reduce(2, vmin == bmin ? imin : INFINITY, scratch);
-    if (threadIdx.x == 0) {
-        double *bp = a.bp + (long long)blockIdx.x * ADJ_BP;
-        bp[0] = bsum;
-        bp[1] = bmax;
-        bp[2] = bimax;
-        bp[3] = bmin;
-        bp[4] = bimin;
+        for (int i = 0; i < NP; ++i) row[NV + 2 * i] = pv[i], row[NV + 2 * i + 1] = pi[i];
     }
 }
 
-// ------------------------------------------------------------ fused pass ---
+template <int NV, int NP>
+__device__ inline void combine_rows(const int (&kind)[NV], double (&v)[NV], const int (&pkind)[NP], double (&pv)[NP],
+                                    double (&pi)[NP], const double *scratch) {
+    constexpr int ROW = NV + 2 * NP;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double r = scratch[i];
+        for (int w = 1; w < ADJ_NW; ++w) r = stat_op(kind[i], r, scratch[w * ROW + i]);
+        v[i] = r;
+    }
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        double m = scratch[NV + 2 * i], id = scratch[NV + 2 * i + 1];
+        for (int w = 1; w < ADJ_NW; ++w) {
+            const double mw = scratch[w * ROW + NV + 2 * i], iw = scratch[w * ROW + NV + 2 * i + 1];
+            const bool better = pkind[i] == 1 ? mw > m : mw < m;
+            if (better || (mw == m && iw < id)) m = mw, id = iw;
+        }
+        pv[i] = m;
+        pi[i] = id;
+    }
+}
 
-// The sigma adjoint of each mesh and the sample point it acts on.
+// The global terms of F'(h)^T lambda on each mesh: sign x sigma adjoint (0 if
+// sigma vanished) and the sample point the L-infinity norm is attributed to.
 struct SigmaTerm {
-    double sbar[2], sgn[2];
+    double w[2];
     long long cell[2];
     int sidx[2];
 };
 
+// Operands of mu = F'(h)^T lambda at cell c of mesh X: its local part (or
+// lambda itself when OE is off) and the coefficients scattered to it by the
+// two overlapping cells of the other mesh.
 template <int K>
-__device__ inline SigmaTerm sigma_terms(const AdjArgs &a, const MeshStats &st, double *scratch) {
-    constexpr int NSP = 2 * K + 4;
-    SigmaTerm t;
-    for (int mesh = 0; mesh < 2; ++mesh) {
-        double s = 0.0, mx = -INFINITY, mn = INFINITY;
-        for (int b = threadIdx.x; b < a.nb; b += ADJ_NT) {
-            const double *bp = a.bp + (long long)(mesh * a.nb + b) * ADJ_BP;
-            s += bp[0];
-            mx = fmax(mx, bp[1]);
-            mn = fmin(mn, bp[3]);
-        }
-        const double ssum = block_reduce(0, s, scratch);
-        const double gmx = block_reduce(1, mx, scratch);
-        const double gmn = block_reduce(2, mn, scratch);
-        double imx = INFINITY, imn = INFINITY;
-        for (int b = threadIdx.x; b < a.nb; b += ADJ_NT) {
-            const double *bp = a.bp + (long long)(mesh * a.nb + b) * ADJ_BP;
-            if (bp[1] == gmx) imx = fmin(imx, bp[2]);
-            if (bp[3] == gmn) imn = fmin(imn, bp[4]);
-        }
-        imx = block_reduce(2, imx, scratch);
-        imn = block_reduce(2, imn, scratch);
-        // sigma = max(max - avg, avg - min): the branch of the first maximiser
-        const double up = st.mx[mesh] - st.avg[mesh], dn = st.avg[mesh] - st.mn[mesh];
-        const bool use_max = up > dn || (up == dn && imx <= imn);
-        const double idx = use_max ? imx : imn;
-        t.sbar[mesh] = st.sig[mesh] != 0.0 ? ssum : 0.0;
-        t.sgn[mesh] = use_max ? 1.0 : -1.0;
-        t.cell[mesh] = (long long)(idx / NSP);
-        t.sidx[mesh] = (int)(idx - (double)t.cell[mesh] * NSP);
+struct MuIn {
+    double lp[K + 1], cr[K + 1], cl[K + 1];
+};
+
+template <int K, bool OE>
+__device__ inline void load_mu(const AdjArgs &a, int X, int c, MuIn<K> &in) {
+    const int n = a.n;
+    if constexpr (!OE) {
+        load_cell<K>(a.lam + X * a.S, n, c, in.lp);
+    } else {
+        load_cell<K>(a.lp_in + X * a.S, n, c, in.lp);
+        load_cell<K>(a.cr_in + (1 - X) * a.S, n, user_right(X, c, n), in.cr);
+        load_cell<K>(a.cl_in + (1 - X) * a.S, n, user_left(X, c, n), in.cl);
     }
-    return t;
 }
 
-// mu = F'(h)^T lambda at cell c of mesh X: local part, the coefficients its
-// overlapping neighbours scattered to it, and the sigma terms.
-template <int K>
-__device__ inline void oe_adjoint_at(const AdjArgs &a, const SigmaTerm &t, int X, int c, double (&mu)[K + 1]) {
+// mu from its operands and the global terms (sigma, mesh average).
+template <int K, bool OE>
+__device__ inline void finish_mu(const AdjArgs &a, const SigmaTerm &t, int X, int c, const MuIn<K> &in,
+                                 double (&mu)[K + 1]) {
     constexpr Tab<K> tb = make_tab<K>();
-    const int n = a.n;
-    if (!a.oe || K == 0) {
-        load_cell<K>(X == 0 ? a.lamC : a.lamD, n, c, mu);
-        return;
-    }
-    double cr[K + 1], cl[K + 1];
-    load_cell<K>(X == 0 ? a.lpC : a.lpD, n, c, mu);
-    // the other-mesh cell with c as right neighbour scattered -cR D0; the one with c as left neighbour -cL D0
-    load_cell<K>(X == 0 ? a.cRD : a.cRC, n, user_right(X, c, n), cr);
-    load_cell<K>(X == 0 ? a.cLD : a.cLC, n, user_left(X, c, n), cl);
+#pragma unroll
+    for (int q = 0; q <= K; ++q) mu[q] = in.lp[q];
+    if constexpr (!OE) return;
 #pragma unroll
     for (int q = 0; q <= K; ++q) {
         double s = 0.0;
 #pragma unroll
-        for (int m = 0; m <= q; ++m) s += (cr[m] + cl[m]) * tb.D0[m][q];
+        for (int m = 0; m <= q; ++m) s += (in.cr[m] + in.cl[m]) * tb.D0[m][q];
         mu[q] -= s;
     }
-    if (t.sbar[X] != 0.0) {
-        const double w = t.sgn[X] * t.sbar[X];
+    if (t.w[X] != 0.0) {
         if ((long long)c == t.cell[X]) {
 #pragma unroll
-            for (int q = 0; q <= K; ++q) mu[q] += w * tb.SP[t.sidx[X]][q];
+            for (int q = 0; q <= K; ++q) mu[q] += t.w[X] * tb.SP[t.sidx[X]][q];
         }
-        mu[0] -= w / (double)n;
+        mu[0] -= t.w[X] * a.inv_n;
     }
 }
 
-// Transpose of the CDG operator's dependence on an overlapping neighbour:
-// the part of (L'(s)^T mu_K) that lands on cell J (coefficients sJ), for the
-// half hf of K that J overlaps.
+// Transpose of the CDG operator's dependence on an overlapping cell J of the
+// other mesh (coefficients sJ) for the half hf of cell K that J overlaps:
+// the 1/tau_max coupling, the volume quadrature of f and the edge flux.
 template <int K, int FLUX>
 __device__ inline void neighbour_transpose(const AdjArgs &a, const double (&sJ)[K + 1], const double (&muK)[K + 1],
                                            int hf, double (&acc)[K + 1]) {
@@ -300,74 +187,315 @@ __device__ inline void neighbour_transpose(const AdjArgs &a, const double (&sJ)[
     for (int q = 0; q <= K; ++q) acc[q] += e * fp0 * tb.D0[0][q];
 }
 
-template <int K, int FLUX>
-__global__ __launch_bounds__(ADJ_NT) void k_adj_rk(AdjArgs a) {
-    __shared__ double red[NSTAT], scratch[64];
-    MeshStats st;
-    SigmaTerm t;
-    if (a.oe && K > 0) {
-        st = forward_stats<ADJ_NT>(a, red, scratch);
-        t = sigma_terms<K>(a, st, scratch);
-    }
+// Launch modes: the reverse of a stage without OE (lambda gathered directly),
+// with OE (gathering the preparation of the stage above), prepare-only, and
+// reverse with OE plus preparation of the stage below.
+enum { ADJ_RK_PLAIN = 0, ADJ_RK = 1, ADJ_PREP = 2, ADJ_RK_PREP = 3 };
+
+template <int K, int FLUX, int MODE>
+__global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
+    using F = FluxT<FLUX>;
+    constexpr Tab<K> tb = make_tab<K>();
+    constexpr int NSP = 2 * K + 4;
+    constexpr bool RK = MODE != ADJ_PREP, OE = MODE != ADJ_RK_PLAIN;
+    constexpr bool PREP = MODE == ADJ_PREP || MODE == ADJ_RK_PREP, GSIG = MODE == ADJ_RK || MODE == ADJ_RK_PREP;
+    constexpr int ROW1 = 5 + 2 * 4, ROW2 = 1 + 2 * 2;
+    static_assert(ADJ_NW * (ROW1 + ROW2) <= 64, "scratch holds one row per wave and round");
+    __shared__ double scratch[64];
+    const int n = a.n, tid = threadIdx.x;
     const int mesh = blockIdx.x >= (unsigned)a.nb;
-    const int c = (blockIdx.x - mesh * a.nb) * ADJ_NT + threadIdx.x;
-    if (c >= a.n) return;
-    const int n = a.n, other = 1 - mesh;
-    double muJ[K + 1], muL[K + 1], muR[K + 1], sJ[K + 1];
-    oe_adjoint_at<K>(a, t, mesh, c, muJ);
-    oe_adjoint_at<K>(a, t, other, user_left(mesh, c, n), muL);    // J overlaps its left half
-    oe_adjoint_at<K>(a, t, other, user_right(mesh, c, n), muR);   // J overlaps its right half
-    load_cell<K>(mesh == 0 ? a.sC : a.sD, n, c, sJ);
-    double lt[K + 1];
+    const int blk = blockIdx.x - mesh * a.nb;
+    const int c = blk * ADJ_NT + tid;
+    const bool valid = c < n;
+    const int cc = valid ? c : 0;
+    const int other = 1 - mesh;
+
+    // ---- every load that does not depend on another, issued before any wait
+    // (no loads under divergent branches: clamped indices, then selects); one
+    // entry per thread of the workgroup and tile partials, larger grids loop below
+    MuIn<K> inJ, inL, inR;
+    double sJ[K + 1], accv[K + 1], own[K + 1], nl[K + 1], nr[K + 1], lam[K + 1];
+    if constexpr (RK) {
+        load_mu<K, OE>(a, mesh, cc, inJ);
+        load_mu<K, OE>(a, other, user_left(mesh, cc, n), inL);     // cc overlaps its left half
+        load_mu<K, OE>(a, other, user_right(mesh, cc, n), inR);    // cc overlaps its right half
+        load_cell<K>(a.s + mesh * a.S, n, cc, sJ);
+        load_cell<K>(a.acc + mesh * a.S, n, cc, accv);            // unused when acc_init
+    } else {
+        load_cell<K>(a.lam + mesh * a.S, n, cc, lam);
+    }
+    if constexpr (PREP) {
+        load_cell<K>(a.h + mesh * a.S, n, cc, own);
+        load_cell<K>(a.h + other * a.S, n, nb_left(mesh, cc, n), nl);
+        load_cell<K>(a.h + other * a.S, n, nb_right(mesh, cc, n), nr);
+    }
+    double bsum[2], bmx[2], bmn[2], bimx[2], bimn[2], fav[2], fmx[2], fmn[2];
+    if constexpr (GSIG) {
+        const int b0 = tid < a.nb ? tid : 0;
 #pragma unroll
-    for (int q = 0; q <= K; ++q) lt[q] = -a.inv_tm * muJ[q];
-    neighbour_transpose<K, FLUX>(a, sJ, muL, 0, lt);
-    neighbour_transpose<K, FLUX>(a, sJ, muR, 1, lt);
-    double *out = mesh == 0 ? a.outC : a.outD, *acc = mesh == 0 ? a.accC : a.accD;
-#pragma unroll
-    for (int q = 0; q <= K; ++q) {
-        const long long e = (long long)q * n + c;
-        const double v = a.bl * (muJ[q] + a.tau * lt[q]);
-        if (a.stage0) {
-            out[e] = acc[e] + v;
-        } else {
-            out[e] = v;
-            acc[e] = a.acc_init ? a.al * muJ[q] : acc[e] + a.al * muJ[q];
+        for (int Y = 0; Y < 2; ++Y) {
+            const double *f0 = a.bp_in + (long long)(Y * a.nb) * ADJ_BP;
+            const double *bp = a.bp_in + (long long)(Y * a.nb + b0) * ADJ_BP;
+            fav[Y] = f0[5];
+            fmx[Y] = f0[6];
+            fmn[Y] = f0[7];
+            bsum[Y] = bp[0];
+            bmx[Y] = bp[1];
+            bimx[Y] = bp[2];
+            bmn[Y] = bp[3];
+            bimn[Y] = bp[4];
         }
+    }
+    // forward statistics of h on this workgroup's mesh: sum, max, min over its tiles
+    double fs[3];
+    if constexpr (PREP) {
+        const int t0 = tid < a.fntiles ? tid : 0;
+#pragma unroll
+        for (int kd = 0; kd < 3; ++kd) fs[kd] = a.fpart[(long long)stat_index(mesh, 0, kd) * a.fntot + a.ftile0 + t0];
+    }
+    if constexpr (GSIG) {
+        if (tid >= a.nb) {
+#pragma unroll
+            for (int Y = 0; Y < 2; ++Y) {
+                bsum[Y] = 0.0;
+                bmx[Y] = -INFINITY;
+                bmn[Y] = INFINITY;
+                bimx[Y] = bimn[Y] = INFINITY;
+            }
+        }
+        if (a.nb > ADJ_NT) {
+#pragma unroll
+            for (int Y = 0; Y < 2; ++Y)
+                for (int b = tid + ADJ_NT; b < a.nb; b += ADJ_NT) {
+                    const double *bp = a.bp_in + (long long)(Y * a.nb + b) * ADJ_BP;
+                    bsum[Y] += bp[0];
+                    if (bp[1] > bmx[Y] || (bp[1] == bmx[Y] && bp[2] < bimx[Y])) bmx[Y] = bp[1], bimx[Y] = bp[2];
+                    if (bp[3] < bmn[Y] || (bp[3] == bmn[Y] && bp[4] < bimn[Y])) bmn[Y] = bp[3], bimn[Y] = bp[4];
+                }
+        }
+    } else {
+#pragma unroll
+        for (int Y = 0; Y < 2; ++Y) {
+            bsum[Y] = fav[Y] = fmx[Y] = fmn[Y] = 0.0;
+            bmx[Y] = -INFINITY;
+            bmn[Y] = bimx[Y] = bimn[Y] = INFINITY;
+        }
+    }
+    if constexpr (PREP) {
+        if (tid >= a.fntiles) fs[0] = 0.0, fs[1] = -INFINITY, fs[2] = INFINITY;
+        if (a.fntiles > ADJ_NT) {
+#pragma unroll
+            for (int kd = 0; kd < 3; ++kd) {
+                const double *row = a.fpart + (long long)stat_index(mesh, 0, kd) * a.fntot + a.ftile0;
+                for (int t = tid + ADJ_NT; t < a.fntiles; t += ADJ_NT) fs[kd] = stat_op(kd, fs[kd], row[t]);
+            }
+        }
+    } else {
+        fs[0] = 0.0, fs[1] = -INFINITY, fs[2] = INFINITY;
+    }
+
+    // ---- round 1: global terms of the stage above and the forward statistics of h
+    SigmaTerm t;
+    t.w[0] = t.w[1] = 0.0;
+    t.cell[0] = t.cell[1] = -1;
+    t.sidx[0] = t.sidx[1] = 0;
+    double sig = 0.0, avg = 0.0;
+    if constexpr (GSIG || PREP) {
+        const int k1[5] = {0, 0, 0, 1, 2};
+        double v1[5] = {bsum[0], bsum[1], fs[0], fs[1], fs[2]};
+        const int pk1[4] = {1, 1, 2, 2};
+        double pv1[4] = {bmx[0], bmx[1], bmn[0], bmn[1]};
+        double pi1[4] = {bimx[0], bimx[1], bimn[0], bimn[1]};
+        wave_stage<5, 4>(k1, v1, pk1, pv1, pi1, scratch);
+        __syncthreads();
+        combine_rows<5, 4>(k1, v1, pk1, pv1, pi1, scratch);
+        if constexpr (GSIG) {
+#pragma unroll
+            for (int Y = 0; Y < 2; ++Y) {
+                // sigma = max(max - avg, avg - min): the branch of the first maximiser
+                const double up = fmx[Y] - fav[Y], dn = fav[Y] - fmn[Y];
+                const bool use_max = up > dn || (up == dn && pi1[Y] <= pi1[2 + Y]);
+                const double idx = use_max ? pi1[Y] : pi1[2 + Y];
+                const bool live = fmax(up, dn) != 0.0 && idx < INFINITY;
+                t.w[Y] = live ? (use_max ? v1[Y] : -v1[Y]) : 0.0;
+                const long long li = live ? (long long)idx : 0;     // an exact integer below 2^53
+                t.cell[Y] = live ? li / NSP : -1;
+                t.sidx[Y] = (int)(li % NSP);
+            }
+        }
+        avg = v1[2] / (double)n;                     // the forward kernels' average, same division
+        fs[1] = v1[3];
+        fs[2] = v1[4];
+        sig = fmax(fs[1] - avg, avg - fs[2]);
+    }
+
+    // ---- reverse of stage l: dJ/ds_l and the a_l share of dJ/ds_0
+    if constexpr (RK) {
+        double muJ[K + 1], muL[K + 1], muR[K + 1];
+        finish_mu<K, OE>(a, t, mesh, cc, inJ, muJ);
+        finish_mu<K, OE>(a, t, other, user_left(mesh, cc, n), inL, muL);
+        finish_mu<K, OE>(a, t, other, user_right(mesh, cc, n), inR, muR);
+        double lt[K + 1];
+#pragma unroll
+        for (int q = 0; q <= K; ++q) lt[q] = -a.inv_tm * muJ[q];
+        neighbour_transpose<K, FLUX>(a, sJ, muL, 0, lt);
+        neighbour_transpose<K, FLUX>(a, sJ, muR, 1, lt);
+#pragma unroll
+        for (int q = 0; q <= K; ++q) {
+            const double v = a.bl * (muJ[q] + a.tau * lt[q]);
+            if (a.stage0) {
+                lam[q] = accv[q] + v;
+            } else {
+                lam[q] = v;
+                accv[q] = a.acc_init ? a.al * muJ[q] : accv[q] + a.al * muJ[q];
+            }
+        }
+        if (valid) {
+            double *out = a.out + mesh * a.S, *acc = a.acc + mesh * a.S;
+#pragma unroll
+            for (int q = 0; q <= K; ++q) {
+                out[(long long)q * n + c] = lam[q];
+                if (!a.stage0) acc[(long long)q * n + c] = accv[q];
+            }
+        }
+    }
+    if constexpr (!PREP) return;
+
+    // ---- preparation of the stage below: the local part of F'(h)^T lambda
+    const double beta = F::speed(own, a.p0);
+    const double isig = sig != 0.0 ? 1.0 / sig : 0.0;
+    double dR[K + 1], dL[K + 1], del[K + 1];
+#pragma unroll
+    for (int m = 0; m <= K; ++m) {
+        double ur = 0.0, ul = 0.0, vr = 0.0, vl = 0.0;
+#pragma unroll
+        for (int q = m; q <= K; ++q) {
+            const double d1 = tb.D1[m][q];
+            ur += own[q] * d1;
+            ul += own[q] * (((q + m) & 1) ? -d1 : d1);
+            vr += nr[q] * tb.D0[m][q];
+            vl += nl[q] * tb.D0[m][q];
+        }
+        dR[m] = ur - vr;
+        dL[m] = ul - vl;
+        del[m] = tb.C[m] * a.hinv * (beta * (fabs(dR[m]) + fabs(dL[m])) * isig);
+    }
+    double lp[K + 1], fo[K + 1];
+    double S = 0.0;
+    lp[0] = lam[0];
+    fo[0] = own[0];
+#pragma unroll
+    for (int j = 1; j <= K; ++j) {
+        S = (j == 1 ? del[0] : S) + del[j];
+        const double fac = exp(-a.tau * S);
+        fo[j] = own[j] * fac;
+        lp[j] = lam[j] * fac;
+    }
+    double cR[K + 1], cL[K + 1], sbar = 0.0;
+#pragma unroll
+    for (int m = 0; m <= K; ++m) cR[m] = cL[m] = 0.0;
+    if (sig != 0.0) {
+        double dbeta = 0.0;
+#pragma unroll
+        for (int m = 0; m <= K; ++m) {
+            double g = 0.0;
+#pragma unroll
+            for (int j = (m > 1 ? m : 1); j <= K; ++j) g += lam[j] * fo[j];
+            g *= -a.tau;                                    // dJ/d delta^m
+            const double w = g * tb.C[m] * a.hinv * isig;
+            const double sR = (dR[m] > 0.0) - (dR[m] < 0.0), sL = (dL[m] > 0.0) - (dL[m] < 0.0);
+            cR[m] = w * beta * sR;
+            cL[m] = w * beta * sL;
+            dbeta += w * (fabs(dR[m]) + fabs(dL[m]));
+            sbar -= g * del[m] * isig;
+        }
+#pragma unroll
+        for (int q = 0; q <= K; ++q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int m = 0; m <= q; ++m) {
+                const double d1 = tb.D1[m][q];
+                acc += cR[m] * d1 + cL[m] * (((q + m) & 1) ? -d1 : d1);
+            }
+            lp[q] += acc;
+        }
+        if constexpr (FLUX == 1) lp[0] += dbeta * ((own[0] > 0.0) - (own[0] < 0.0));   // beta = |u_bar|
+    }
+    // sample values of h (edges and half-cell nodes, natural order)
+    double vmax = -INFINITY, vmin = INFINITY, imax = INFINITY, imin = INFINITY;
+    if (valid) {
+        double *LP = a.lp + mesh * a.S, *CR = a.cr + mesh * a.S, *CL = a.cl + mesh * a.S;
+#pragma unroll
+        for (int m = 0; m <= K; ++m) {
+            LP[(long long)m * n + c] = lp[m];
+            CR[(long long)m * n + c] = cR[m];
+            CL[(long long)m * n + c] = cL[m];
+        }
+#pragma unroll
+        for (int sidx = 0; sidx < NSP; ++sidx) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q <= K; ++q) v += own[q] * tb.SP[sidx][q];
+            const double idx = (double)c * NSP + sidx;
+            if (v > vmax) vmax = v, imax = idx;
+            if (v < vmin) vmin = v, imin = idx;
+        }
+    }
+    // ---- round 2: this workgroup's partials of the prepared stage
+    double *sc2 = scratch + ADJ_NW * ROW1;
+    const int k2[1] = {0};
+    double v2[1] = {valid ? sbar : 0.0};
+    const int pk2[2] = {1, 2};
+    double pv2[2] = {vmax, vmin}, pi2[2] = {imax, imin};
+    wave_stage<1, 2>(k2, v2, pk2, pv2, pi2, sc2);
+    __syncthreads();
+    if (tid == 0) {
+        combine_rows<1, 2>(k2, v2, pk2, pv2, pi2, sc2);
+        double *bp = a.bp + (long long)blockIdx.x * ADJ_BP;
+        bp[0] = v2[0];
+        bp[1] = pv2[0];
+        bp[2] = pi2[0];
+        bp[3] = pv2[1];
+        bp[4] = pi2[1];
+        bp[5] = avg;
+        bp[6] = fs[1];
+        bp[7] = fs[2];
     }
 }
 
 // ------------------------------------------------------------ host side ---
 
-template <template <int, int> class Kern>
-static void *adj_pick(int k, int flux) {
-    switch (k * 2 + (flux == 1)) {
-    case 0: return Kern<0, 0>::ptr();
-    case 1: return Kern<0, 1>::ptr();
-    case 2: return Kern<1, 0>::ptr();
-    case 3: return Kern<1, 1>::ptr();
-    case 4: return Kern<2, 0>::ptr();
-    case 5: return Kern<2, 1>::ptr();
-    case 6: return Kern<3, 0>::ptr();
-    default: return Kern<3, 1>::ptr();
+template <int K, int FLUX>
+static void *adj_kernel(int mode) {
+    switch (mode) {
+    case ADJ_RK_PLAIN: return (void *)k_adj<K, FLUX, ADJ_RK_PLAIN>;
+    case ADJ_RK: return (void *)k_adj<K, FLUX, ADJ_RK>;
+    case ADJ_PREP: return (void *)k_adj<K, FLUX, ADJ_PREP>;
+    default: return (void *)k_adj<K, FLUX, ADJ_RK_PREP>;
     }
 }
 
-template <int K, int FLUX> struct OeK {
-    static void *ptr() { return (void *)k_adj_oe<K, FLUX>; }
-};
-template <int K, int FLUX> struct RkK {
-    static void *ptr() { return (void *)k_adj_rk<K, FLUX>; }
-};
-
-static hipError_t adj_launch(void *fn, const AdjArgs &a, hipStream_t s) {
-    AdjArgs copy = a;
-    void *args[] = {&copy};
-    return hipLaunchKernel(fn, dim3(2 * a.nb), dim3(ADJ_NT), args, 0, s);
+static void *adj_pick(int k, int flux, int mode) {
+    switch (k * 2 + (flux == 1)) {
+    case 0: return adj_kernel<0, 0>(ADJ_RK_PLAIN);
+    case 1: return adj_kernel<0, 1>(ADJ_RK_PLAIN);
+    case 2: return adj_kernel<1, 0>(mode);
+    case 3: return adj_kernel<1, 1>(mode);
+    case 4: return adj_kernel<2, 0>(mode);
+    case 5: return adj_kernel<2, 1>(mode);
+    case 6: return adj_kernel<3, 0>(mode);
+    default: return adj_kernel<3, 1>(mode);
+    }
 }
 
-hipError_t launch_adj_oe(const AdjArgs &a, hipStream_t s) { return adj_launch(adj_pick<OeK>(a.k, a.flux), a, s); }
-hipError_t launch_adj_rk(const AdjArgs &a, hipStream_t s) { return adj_launch(adj_pick<RkK>(a.k, a.flux), a, s); }
+hipError_t launch_adj(const AdjArgs &a, hipStream_t s) {
+    AdjArgs copy = a;
+    void *args[] = {&copy};
+    const bool oe = a.oe && a.k > 0;
+    const int mode = !oe ? ADJ_RK_PLAIN : (!a.do_rk ? ADJ_PREP : (a.do_prep ? ADJ_RK_PREP : ADJ_RK));
+    if (!oe && !a.do_rk) return hipSuccess;          // nothing to prepare without OE
+    return hipLaunchKernel(adj_pick(a.k, a.flux, mode), dim3(2 * a.nb), dim3(ADJ_NT), args, 0, s);
+}
 int adj_block_size() { return ADJ_NT; }
 int adj_block_partials() { return ADJ_BP; }
 

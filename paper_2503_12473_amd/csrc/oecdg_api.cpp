@@ -354,11 +354,14 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
     const int n = I.np, K1 = I.k + 1;
     const size_t S = (size_t)K1 * n, S2 = 2 * S;           // one mesh, both meshes
     const long long nseg = nsteps > 0 ? (nsteps + ckpt - 1) / ckpt : 0;
+    const long long n0L = nseg > 0 ? (nseg - 1) * ckpt : 0;  // first step of the last segment
     const size_t ntile = h->tiles_h.size(), psz = (size_t)NSTAT * ntile;
     const int NB = adj_block_size(), nb = (n + NB - 1) / NB;
-    // workspace: checkpoints | segment states (6 per step) | partials (3 per step) | 8 adjoint buffers | block partials
-    const size_t need = (nseg + 1) * S2 + (size_t)ckpt * 6 * S2 + (size_t)ckpt * 3 * psz + 8 * S2 +
-                        (size_t)2 * nb * adj_block_partials();
+    const size_t bpsz = (size_t)2 * nb * adj_block_partials();
+    // workspace: checkpoints | segment states (6 per step) | partials (3 per step) |
+    //            2 adjoints | acc | 2 x (lp, cR, cL) | 2 x block partials
+    const size_t need = (size_t)std::max<long long>(nseg, 1) * S2 + (size_t)ckpt * 6 * S2 + (size_t)ckpt * 3 * psz +
+                        9 * S2 + 2 * bpsz;
     if (need * sizeof(double) > h->adj_bytes) {
         (void)hipFree(h->adj_ws);
         h->adj_ws = nullptr;
@@ -367,27 +370,63 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
         h->adj_bytes = need * sizeof(double);
     }
     double *ck = h->adj_ws;
-    double *seg = ck + (nseg + 1) * S2;
+    double *seg = ck + (size_t)std::max<long long>(nseg, 1) * S2;
     double *fp = seg + (size_t)ckpt * 6 * S2;
     double *buf = fp + (size_t)ckpt * 3 * psz;
-    double *lam = buf, *l1 = buf + S2, *l2 = buf + 2 * S2, *acc = buf + 3 * S2, *lp = buf + 4 * S2,
-           *cR = buf + 5 * S2, *cL = buf + 6 * S2;
-    double *bp = buf + 8 * S2;
+    double *lamA = buf, *lamB = buf + S2, *acc = buf + 2 * S2;
+    double *prepv[2][3] = {{buf + 3 * S2, buf + 4 * S2, buf + 5 * S2}, {buf + 6 * S2, buf + 7 * S2, buf + 8 * S2}};
+    double *bpv[2] = {buf + 9 * S2, buf + 9 * S2 + bpsz};
     auto st = [&](long long j, int which) { return seg + ((size_t)j * 6 + which) * S2; };   // 0 s0,1 h1,2 s1,3 h2,4 s2,5 h3
     auto pp = [&](long long j, int l) { return fp + ((size_t)j * 3 + l) * psz; };
 
     StageArgs base = base_args(h);
     base.dt_fixed = dt;
     base.t_end = INFINITY;
-    // pass 1: forward, keeping u^n at n = 0, ckpt, 2 ckpt, ...
+    int rc;
+    // Stage l of step j of a segment, keeping every stage state and its partial
+    // statistics; (inC, inD, inP) is the undamped input and its partials.
+    auto seg_stage = [&](long long nn, long long j, int l, const double *inC, const double *inD, double *inP,
+                         bool first) {
+        StageArgs a = base;
+        a.l = l;
+        a.par = (int)(nn & 1);
+        a.first = first;
+        const int sp = (a.par + l) & 1;
+        double *out = st(j, 2 * l + 1);
+        a.BC[sp] = const_cast<double *>(inC);
+        a.BD[sp] = const_cast<double *>(inD);
+        a.BC[sp ^ 1] = out;
+        a.BD[sp ^ 1] = out + S;
+        a.UC = st(j, 0);
+        a.UD = st(j, 0) + S;
+        a.DC = l == 0 ? nullptr : st(j, 2 * l);
+        a.DD = l == 0 ? nullptr : st(j, 2 * l) + S;
+        a.part[sp] = pp(j, l);
+        a.part[sp ^ 1] = inP;
+        return stage_all(h, a);
+    };
+    // pass 1: forward from u^0, keeping u^n at n = 0, ckpt, 2 ckpt, ... and
+    // every stage of the last segment (which then needs no recomputation)
     HIPCHK(h, hipMemcpyAsync(ck, uC0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(ck + S, uD0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(base.BC[0], uC0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(base.BD[0], uD0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, launch_init_1d(base, 1, h->stream));
-    int rc;
     for (long long nn = 0; nn < nsteps; ++nn)
         for (int l = 0; l < 3; ++l) {
+            if (nn >= n0L) {
+                const long long j = nn - n0L;
+                if (l > 0)
+                    rc = seg_stage(nn, j, l, st(j, 2 * l - 1), st(j, 2 * l - 1) + S, pp(j, l - 1), false);
+                else if (j > 0)
+                    rc = seg_stage(nn, j, 0, st(j - 1, 5), st(j - 1, 5) + S, pp(j - 1, 2), false);
+                else {
+                    const int sp = (int)(nn & 1);
+                    rc = seg_stage(nn, 0, 0, base.BC[sp], base.BD[sp], base.part[sp ^ 1], nn == 0);
+                }
+                if (rc != OECDG_OK) return rc;
+                continue;
+            }
             StageArgs a = base;
             a.l = l;
             a.par = (int)(nn & 1);
@@ -399,65 +438,77 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
             if ((rc = stage_all(h, a)) != OECDG_OK) return rc;
         }
     // backward
-    HIPCHK(h, hipMemcpyAsync(lam, gCT, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(lam + S, gDT, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(lamA, gCT, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(lamA + S, gDT, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    double *lam = lamA, *lam_next = lamB;
     AdjArgs q;
     memset(&q, 0, sizeof(q));
     q.k = I.k;
     q.flux = I.flux;
     q.n = n;
     q.nb = nb;
+    q.S = (long long)S;
     q.hinv = 1.0 / I.h;
     q.p0 = I.p0;
     q.tau = dt;
     q.inv_tm = 1.0 / dt;
+    q.inv_n = 1.0 / n;
     q.fntot = (long long)ntile;
     q.ftile0 = I.tile0;
     q.fntiles = I.ntiles;
-    q.lpC = lp, q.lpD = lp + S, q.cRC = cR, q.cRD = cR + S, q.cLC = cL, q.cLD = cL + S;
-    q.bp = bp;
-    q.accC = acc, q.accD = acc + S;
+    q.acc = acc;
     q.oe = I.oe && I.k > 0;
     static const double AL[3] = {0.0, 0.75, 1.0 / 3.0}, BL[3] = {1.0, 0.25, 2.0 / 3.0};
+    int cur = 0;                                             // the preparation set the next launch reads
+    auto set_out = [&](AdjArgs &a, int w) {
+        a.lp = prepv[w][0], a.cr = prepv[w][1], a.cl = prepv[w][2], a.bp = bpv[w];
+    };
+    auto set_in = [&](AdjArgs &a, int r) {
+        a.lp_in = prepv[r][0], a.cr_in = prepv[r][1], a.cl_in = prepv[r][2], a.bp_in = bpv[r];
+    };
     for (long long sg = nseg - 1; sg >= 0; --sg) {
         const long long n0 = sg * ckpt, m = std::min<long long>(ckpt, nsteps - n0);
-        for (long long j = 0; j < m; ++j)                    // recompute the segment
-            for (int l = 0; l < 3; ++l) {
-                const long long nn = n0 + j;
-                StageArgs a = base;
-                a.l = l;
-                a.par = (int)(nn & 1);
-                a.first = j == 0;                           // the checkpoint is already damped
-                const int sp = (a.par + l) & 1;
-                double *in = l == 0 ? (j == 0 ? ck + sg * S2 : st(j - 1, 5)) : st(j, 2 * l - 1);
-                double *out = st(j, 2 * l + 1);
-                a.BC[sp] = in;
-                a.BD[sp] = in + S;
-                a.BC[sp ^ 1] = out;
-                a.BD[sp ^ 1] = out + S;
-                a.UC = st(j, 0);
-                a.UD = st(j, 0) + S;
-                a.DC = l == 0 ? nullptr : st(j, 2 * l);
-                a.DD = l == 0 ? nullptr : st(j, 2 * l) + S;
-                a.part[sp] = pp(j, l);
-                a.part[sp ^ 1] = l > 0 ? pp(j, l - 1) : (j > 0 ? pp(j - 1, 2) : pp(j, 2));
-                if ((rc = stage_all(h, a)) != OECDG_OK) return rc;
-            }
+        if (sg != nseg - 1)                                  // recompute the segment from its checkpoint
+            for (long long j = 0; j < m; ++j)
+                for (int l = 0; l < 3; ++l) {
+                    const long long nn = n0 + j;
+                    if (l > 0)
+                        rc = seg_stage(nn, j, l, st(j, 2 * l - 1), st(j, 2 * l - 1) + S, pp(j, l - 1), false);
+                    else if (j > 0)
+                        rc = seg_stage(nn, j, 0, st(j - 1, 5), st(j - 1, 5) + S, pp(j - 1, 2), false);
+                    else                                     // the checkpoint is already damped
+                        rc = seg_stage(nn, 0, 0, ck + sg * S2, ck + sg * S2 + S, pp(0, 2), true);
+                    if (rc != OECDG_OK) return rc;
+                }
+        if (q.oe) {                                          // prepare the OE of the segment's last stage
+            AdjArgs a = q;
+            a.do_rk = 0;
+            a.do_prep = 1;
+            a.lam = lam;
+            a.h = st(m - 1, 5);
+            a.fpart = pp(m - 1, 2);
+            set_out(a, cur);
+            HIPCHK(h, launch_adj(a, h->stream));
+        }
         for (long long j = m - 1; j >= 0; --j)
             for (int l = 2; l >= 0; --l) {
-                double *lin = l == 2 ? lam : (l == 1 ? l1 : l2);
-                double *lout = l == 2 ? l1 : (l == 1 ? l2 : lam);
-                q.hC = st(j, 2 * l + 1), q.hD = st(j, 2 * l + 1) + S;
-                q.lamC = lin, q.lamD = lin + S;
-                q.fpart = pp(j, l);
-                q.sC = st(j, 2 * l), q.sD = st(j, 2 * l) + S;
-                q.outC = lout, q.outD = lout + S;
-                q.al = AL[l];
-                q.bl = BL[l];
-                q.stage0 = l == 0;
-                q.acc_init = l == 2;
-                if (q.oe) HIPCHK(h, launch_adj_oe(q, h->stream));
-                HIPCHK(h, launch_adj_rk(q, h->stream));
+                AdjArgs a = q;
+                a.do_rk = 1;
+                a.s = st(j, 2 * l);
+                a.lam = lam;
+                a.out = lam_next;
+                a.al = AL[l];
+                a.bl = BL[l];
+                a.stage0 = l == 0;
+                a.acc_init = l == 2;
+                set_in(a, cur);
+                set_out(a, cur ^ 1);
+                a.do_prep = l > 0 || j > 0;
+                a.h = l > 0 ? st(j, 2 * l - 1) : (j > 0 ? st(j - 1, 5) : nullptr);
+                a.fpart = l > 0 ? pp(j, l - 1) : (j > 0 ? pp(j - 1, 2) : nullptr);
+                HIPCHK(h, launch_adj(a, h->stream));
+                cur ^= 1;
+                std::swap(lam, lam_next);
             }
     }
     HIPCHK(h, hipMemcpyAsync(gC0, lam, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));

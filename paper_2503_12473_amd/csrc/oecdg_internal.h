@@ -80,23 +80,22 @@ struct StageArgs {
 // n cells per mesh, modal arrays [m][cell].
 struct AdjArgs {
     int k, flux, n, nb;            // degree, flux id, cells per mesh, workgroups per mesh
+    long long S;                   // (k+1) n: offset of the dual mesh in every field below
     double hinv, p0, tau, inv_tm;  // 1/h, flux parameter, tau, 1/tau_max
-    const double *fpart;           // forward per-tile partial statistics of the damped stage output
+    double inv_n;                  // 1/n (derivative of the mesh average)
+    const double *fpart;           // forward per-tile partial statistics of h (the stage prepared here)
     long long fntot;
     int ftile0, fntiles;
-    const double *hC, *hD;         // undamped stage output h
-    const double *lamC, *lamD;     // adjoint of F(h)
-    double *lpC, *lpD;             // local part of F'(h)^T lambda
-    double *cRC, *cRD, *cLC, *cLD; // coefficients scattered to the right / left neighbours
-    double *bp;                    // block partials
-    const double *sC, *sD;         // damped stage input s_l
-    double *outC, *outD;           // adjoint of s_l
-    double *accC, *accD;           // adjoint of s_0 accumulated over the stages
-    double al, bl;                 // h = al s_0 + bl (s_l + tau L(s_l))
-    int stage0, acc_init, oe, pad;
+    const double *h;               // undamped output h_l of the stage prepared here
+    const double *s;               // damped input s_l of the stage reversed here
+    const double *lam;             // adjoint of s_{l+1} (OE off) or of F(h) (prepare-only launch)
+    const double *lp_in, *cr_in, *cl_in, *bp_in;   // preparation of the stage above
+    double *lp, *cr, *cl, *bp;                      // preparation of this stage
+    double *out, *acc;             // adjoint of s_l; adjoint of s_0 accumulated over the stages
+    double al, bl;                 // h_{l+1} = al s_0 + bl (s_l + tau L(s_l))
+    int stage0, acc_init, oe, do_rk, do_prep, pad;
 };
-hipError_t launch_adj_oe(const AdjArgs &a, hipStream_t s);
-hipError_t launch_adj_rk(const AdjArgs &a, hipStream_t s);
+hipError_t launch_adj(const AdjArgs &a, hipStream_t s);
 int adj_block_size();
 int adj_block_partials();
 
