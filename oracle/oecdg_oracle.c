@@ -433,6 +433,9 @@ static int rk_table(int rk, double c[4][4], double d[4][4])
     return 0;
 }
 
+/* The same tables for the 2D oracle. */
+int ora_rk_table(int rk, double c[4][4], double d[4][4]) { return rk_table(rk, c, d); }
+
 static int check_state(const ora1d *p, const double *uC, const double *uD)
 {
     const int K1 = p->k + 1;

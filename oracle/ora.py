@@ -1,7 +1,8 @@
 """ctypes binding of the C oracle (test infrastructure only).
 
-Functions take and return numpy float64 arrays in the modal layout
-[nc, k+1, ncell] (1D) used by ``paper_2503_12473_amd.inputs``.
+Functions take and return numpy float64 arrays in the modal layouts
+[nc, k+1, ncell] (1D) and [nc, k+1, k+1, ny, nx] (2D) used by
+``paper_2503_12473_amd.inputs``.
 """
 from __future__ import annotations
 
@@ -25,6 +26,12 @@ class OracleError(RuntimeError):
 class Ora1D(C.Structure):
     _fields_ = [("k", C.c_int), ("nc", C.c_int), ("flux", C.c_int), ("bc", C.c_int), ("n", C.c_long),
                 ("xlo", C.c_double), ("xhi", C.c_double), ("a", C.c_double), ("gamma", C.c_double)]
+
+
+class Ora2D(C.Structure):
+    _fields_ = [("k", C.c_int), ("nc", C.c_int), ("flux", C.c_int), ("nx", C.c_long), ("ny", C.c_long),
+                ("xlo", C.c_double), ("xhi", C.c_double), ("ylo", C.c_double), ("yhi", C.c_double),
+                ("ax", C.c_double), ("ay", C.c_double), ("gamma", C.c_double)]
 
 
 _lib = None
@@ -53,6 +60,19 @@ def lib():
         L.ora1d_step.argtypes = [P1, C.c_int, C.c_int, C.c_double, C.c_double, _DP, _DP]
         L.ora1d_ssprk3_stage.argtypes = [P1, C.c_int, C.c_int, C.c_double, C.c_double, _DP, _DP, _DP, _DP, _DP, _DP]
         L.ora1d_run.argtypes = [P1, C.c_double, C.c_int, C.c_int, C.c_double, C.c_long, C.c_double,
+                                _DP, _DP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
+        P2 = C.POINTER(Ora2D)
+        L.ora2d_rhs.argtypes = [P2, C.c_double, _DP, _DP, _DP, _DP]
+        L.ora2d_oe.argtypes = [P2, C.c_double, _DP, _DP]
+        L.ora2d_delta.argtypes = [P2, _DP, _DP, _DP, _DP]
+        L.ora2d_stats.argtypes = [P2, _DP, _DP, _DP, _DP]
+        L.ora2d_stats.restype = None
+        L.ora2d_max_wavespeeds.argtypes = [P2, _DP, _DP, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.ora2d_max_wavespeeds.restype = None
+        L.ora2d_wavespeed.argtypes = [P2, C.c_int, _DP]
+        L.ora2d_wavespeed.restype = C.c_double
+        L.ora2d_step.argtypes = [P2, C.c_int, C.c_int, C.c_double, C.c_double, _DP, _DP]
+        L.ora2d_run.argtypes = [P2, C.c_double, C.c_int, C.c_int, C.c_double, C.c_long, C.c_double,
                                 _DP, _DP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
         _lib = L
     return _lib
@@ -137,4 +157,63 @@ def run1d(prob, uC, uD, t_end=float("inf"), nsteps=-1, cfl=0.3, dt_fixed=0.0, rk
     n = C.c_long(0)
     _check(lib().ora1d_run(C.byref(_p1(prob)), cfl, rk, int(oe), t_end, nsteps, dt_fixed, uC, uD,
                            C.byref(t), C.byref(n)), "run1d")
+    return uC, uD, t.value, n.value
+
+
+# ---------------------------------------------------------------- 2D ---
+
+def _p2(prob):
+    return Ora2D(prob.k, prob.nc, prob.flux, prob.nx, prob.ny, prob.xlo, prob.xhi, prob.ylo, prob.yhi,
+                 prob.a, prob.b, prob.gamma)
+
+
+def rhs2d(prob, tau_max, uC, uD):
+    uC, uD = _arr(uC), _arr(uD)
+    LC, LD = np.zeros_like(uC), np.zeros_like(uD)
+    _check(lib().ora2d_rhs(C.byref(_p2(prob)), tau_max, uC, uD, LC, LD), "rhs2d")
+    return LC, LD
+
+
+def oe2d(prob, tau, uC, uD):
+    uC, uD = _arr(uC).copy(), _arr(uD).copy()
+    _check(lib().ora2d_oe(C.byref(_p2(prob)), tau, uC, uD), "oe2d")
+    return uC, uD
+
+
+def delta2d(prob, uC, uD):
+    """delta^m of every cell: arrays [k+1, ny, nx] for the primal and dual meshes."""
+    uC, uD = _arr(uC), _arr(uD)
+    dC = np.zeros((prob.k + 1, prob.ny, prob.nx))
+    dD = np.zeros((prob.k + 1, prob.ny, prob.nx))
+    _check(lib().ora2d_delta(C.byref(_p2(prob)), uC, uD, dC, dD), "delta2d")
+    return dC, dD
+
+
+def stats2d(prob, uC, uD):
+    """avg, sigma as arrays [mesh, q]."""
+    avg = np.zeros(8)
+    sig = np.zeros(8)
+    lib().ora2d_stats(C.byref(_p2(prob)), _arr(uC), _arr(uD), avg, sig)
+    return avg.reshape(2, 4)[:, :prob.nc], sig.reshape(2, 4)[:, :prob.nc]
+
+
+def max_wavespeeds2d(prob, uC, uD):
+    bx, by = C.c_double(0.0), C.c_double(0.0)
+    lib().ora2d_max_wavespeeds(C.byref(_p2(prob)), _arr(uC), _arr(uD), C.byref(bx), C.byref(by))
+    return bx.value, by.value
+
+
+def step2d(prob, tau, tau_max, uC, uD, rk=3, oe=True):
+    uC, uD = _arr(uC).copy(), _arr(uD).copy()
+    _check(lib().ora2d_step(C.byref(_p2(prob)), rk, int(oe), tau, tau_max, uC, uD), "step2d")
+    return uC, uD
+
+
+def run2d(prob, uC, uD, t_end=float("inf"), nsteps=-1, cfl=0.3, dt_fixed=0.0, rk=3, oe=True):
+    """March to t_end (clipped last step) or nsteps steps; returns (uC, uD, t, steps)."""
+    uC, uD = _arr(uC).copy(), _arr(uD).copy()
+    t = C.c_double(0.0)
+    n = C.c_long(0)
+    _check(lib().ora2d_run(C.byref(_p2(prob)), cfl, rk, int(oe), t_end, nsteps, dt_fixed, uC, uD,
+                           C.byref(t), C.byref(n)), "run2d")
     return uC, uD, t.value, n.value
