@@ -1,18 +1,1163 @@
-// oecdg_2d.hip -- 2D (tensor Q2) path.  Not yet implemented: every entry
-// point reports OECDG_EUNSUPPORTED.
+// oecdg_2d.hip -- 2D RK-OECDG on periodic Cartesian primal and dual meshes,
+// tensor-product Q^k Legendre modes (k = 2), linear advection or Euler.
+//
+// Per RK stage (eq:RKCDG) one tile kernel and one statistics kernel:
+//   k_reduce2d  one workgroup folds the per-tile partial statistics of the
+//               stage input into the global scalars: per mesh and component
+//               the domain average and sigma (Sec. 2.2), the largest x and y
+//               wave speeds, and at a step start tau and tau_max
+//               (tau_max = C_CFL / (beta_x/h_x + beta_y/h_y), Sec. 2.1);
+//   k_stage2d   one workgroup per tile of TX x TY primal cells and the dual
+//               cells with the same indices.  It stages both meshes'
+//               pre-damping input with a one-cell halo in LDS, applies the
+//               OE step of the previous stage in place (OEstep2D solved
+//               exactly, delta_K^m from the edge integrals of Sec. 2.2),
+//               evaluates the operator of eq:2D_H on its cells, takes the
+//               SSP-RK3 combination, writes the undamped stage output and
+//               the tile's partial statistics of it.
+// The same tile kernel, in other modes, damps a state without a stage (the
+// end of a run or of a single stage) or only computes statistics.
+//
+// Work split inside a tile: four lanes (a quad) per cell.  For the operator
+// lane t takes quadrant t (coupling and volume integrals against the one
+// overlapping cell of the other mesh) and edge t (half-edge flux integrals
+// on the other mesh's centre line); for the damping coefficients lane t takes
+// edge t.  The quad sums with order-fixed DPP exchanges.  Lanes run the same
+// instructions; what differs per lane (quadrant, edge direction) is chosen by
+// selects, so the quad never diverges.
+//
+// Layout (global): u[(((q*(k+1) + a)*(k+1) + b)*ny + iy)*nx + ix]; dual cell
+// (ix, iy) is centred on the lower-left vertex of primal cell (ix, iy), so
+// primal (i, j) overlaps dual (i..i+1, j..j+1) and dual (i, j) overlaps
+// primal (i-1..i, j-1..j).
+#include "oecdg_device.h"
 #include "oecdg_internal.h"
+#include "oecdg_tables.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
 
 namespace oecdg {
 
-int create_2d(oecdg_handle *, const oecdg_desc *) { return OECDG_EUNSUPPORTED; }
-int dt_2d(oecdg_handle *, const double *, const double *, double *) { return OECDG_EUNSUPPORTED; }
-int stage_2d(oecdg_handle *, int, double, double, const double *, const double *, const double *, const double *,
-             double *, double *) {
-    return OECDG_EUNSUPPORTED;
+// ---------------------------------------------------------------- fluxes ---
+
+struct FPar2 {
+    double a, b, gamma;      // advection velocity (a, b); ideal-gas gamma
+};
+
+template <int FLUX> struct Flux2D;
+
+template <> struct Flux2D<OECDG_FLUX_ADVECTION> {
+    static constexpr int NC = 1;
+    // flux along direction dir (0 = x, 1 = y), selected per lane
+    __device__ static inline void f(int dir, const double *w, double *o, const FPar2 &p) {
+        o[0] = (dir ? p.b : p.a) * w[0];
+    }
+    __device__ static inline double speed(int dir, const double *, const FPar2 &p) { return fabs(dir ? p.b : p.a); }
+    __device__ static inline bool physical(const double *, const FPar2 &) { return true; }
+};
+
+template <> struct Flux2D<OECDG_FLUX_EULER> {
+    static constexpr int NC = 4;    // rho, rho u, rho v, E
+    __device__ static inline void f(int dir, const double *w, double *o, const FPar2 &p) {
+        const double ir = 1.0 / w[0];
+        const double u = w[1] * ir, v = w[2] * ir;
+        const double pr = (p.gamma - 1.0) * (w[3] - 0.5 * (w[1] * u + w[2] * v));
+        const double un = dir ? v : u;
+        o[0] = dir ? w[2] : w[1];
+        o[1] = w[1] * un + (dir ? 0.0 : pr);
+        o[2] = w[2] * un + (dir ? pr : 0.0);
+        o[3] = (w[3] + pr) * un;
+    }
+    __device__ static inline double speed(int dir, const double *w, const FPar2 &p) {
+        const double ir = 1.0 / w[0];
+        const double u = w[1] * ir, v = w[2] * ir;
+        const double pr = (p.gamma - 1.0) * (w[3] - 0.5 * (w[1] * u + w[2] * v));
+        return fabs(dir ? v : u) + sqrt(p.gamma * pr * ir);
+    }
+    __device__ static inline bool physical(const double *w, const FPar2 &p) {
+        if (!(w[0] > 0.0)) return false;
+        const double pr = (p.gamma - 1.0) * (w[3] - 0.5 * (w[1] * w[1] + w[2] * w[2]) / w[0]);
+        return pr > 0.0;
+    }
+};
+
+// ---------------------------------------------------------------- tables ---
+
+template <int K>
+struct Tab2 {
+    static constexpr int K1 = K + 1, Q = K + 1, NSP = 2 * K + 4;
+    double w[Q];                  // Gauss-Legendre weights on [-1, 1]
+    double own[K1][2][Q][K1];     // [d][half][g][n]: P_n^(d) at node g of the half, own coordinate
+    double nb[K1][2][Q][K1];      // the same point in the overlapping cell's coordinate (+1 / -1)
+    double e1[K1][K1];            // [d][n]: P_n^(d)(1)
+    double e0[K1][K1];            // [d][n]: P_n^(d)(0)
+    double sp[NSP][K1];           // P_n at the sigma sample points (-1, half nodes, +1)
+    double cdel[K1];              // (2m+1) / ((2K-1) m!)
+};
+
+template <int K>
+constexpr Tab2<K> make_tab2() {
+    Tab2<K> t{};
+    constexpr int K1 = K + 1, Q = K + 1;
+    constexpr auto g = ct::gauss<Q>();
+    for (int i = 0; i < Q; ++i) t.w[i] = g.w[i];
+    for (int d = 0; d < K1; ++d)
+        for (int hf = 0; hf < 2; ++hf)
+            for (int i = 0; i < Q; ++i) {
+                const double xi = hf == 0 ? 0.5 * (g.s[i] - 1.0) : 0.5 * (g.s[i] + 1.0);
+                const double xn = hf == 0 ? xi + 1.0 : xi - 1.0;
+                for (int n = 0; n < K1; ++n) {
+                    t.own[d][hf][i][n] = ct::legd(n, d, xi);
+                    t.nb[d][hf][i][n] = ct::legd(n, d, xn);
+                }
+            }
+    for (int d = 0; d < K1; ++d)
+        for (int n = 0; n < K1; ++n) {
+            t.e1[d][n] = ct::legd(n, d, 1.0);
+            t.e0[d][n] = ct::legd(n, d, 0.0);
+        }
+    double pts[2 * K + 4] = {};
+    pts[0] = -1.0;
+    for (int i = 0; i < Q; ++i) pts[1 + i] = 0.5 * (g.s[i] - 1.0);
+    for (int i = 0; i < Q; ++i) pts[1 + Q + i] = 0.5 * (g.s[i] + 1.0);
+    pts[2 * K + 3] = 1.0;
+    for (int j = 0; j < 2 * K + 4; ++j)
+        for (int n = 0; n < K1; ++n) t.sp[j][n] = ct::leg(n, pts[j]);
+    double fact = 1.0;
+    for (int m = 0; m < K1; ++m) {
+        if (m > 1) fact *= m;
+        t.cdel[m] = K > 0 ? (2.0 * m + 1.0) / ((2.0 * K - 1.0) * fact) : 0.0;
+    }
+    return t;
 }
-int run_2d(oecdg_handle *, double *, double *, double, int64_t, double, double *, int64_t *) {
-    return OECDG_EUNSUPPORTED;
+
+// ------------------------------------------------------- device structs ---
+
+// Global scalars of the current stage (written by k_reduce2d).
+struct Stats2 {
+    double avg[2][4], sig[2][4];  // per mesh and component
+    double bx, by;                // largest x / y wave speeds at cell averages (both meshes)
+    double t;                     // start time of the current step
+    double tau, tau_max;          // the current step
+    double tau_damp;              // tau of the OE step applied to the next tile kernel's input
+    long long nexec;              // completed steps
+    int done, pending, last, bad; // bad: no admissible time step
+};
+
+enum { M2_STAGE = 0, M2_FINAL = 1, M2_STATS = 2 };
+enum { R2_STEP = 0, R2_STAGE = 1, R2_FINAL = 2, R2_SINGLE = 3, R2_STATS = 4 };
+
+struct Stage2Args {
+    int nx, ny, ntx, nty;
+    long long plane;              // nx * ny
+    double hx, hy;
+    FPar2 fp;
+    const double *inC, *inD;      // tile input (pre-damping, or damped when damp == 0)
+    double *outC, *outD;          // stage output (undamped) or damped state (final mode)
+    double *UC, *UD;              // damped u^n: written at stage 0 (write_u), read at stages 1, 2
+    double *part;                 // [row][tile] partial statistics of the output (stage / stats modes)
+    const Stats2 *st;
+    int *err;                     // [0] non-finite, [1] non-physical, [2] no admissible step
+    int l, mode, damp, write_u;
+};
+
+struct Red2Args {
+    const double *part;
+    int ntiles, mode;
+    long long ncell;
+    double t_end, dt_fixed, cfl, hx, hy;
+    double tau_o, taumax_o;       // single-stage call
+    Stats2 *st;
+    int *err;
+};
+
+template <int NC> __host__ __device__ constexpr int nrow2() { return 2 * NC * 3 + 2; }
+__host__ __device__ constexpr int row2(int nc, int mesh, int q, int kind) { return (mesh * nc + q) * 3 + kind; }
+
+// ------------------------------------------------------------ helpers ---
+
+// Sum over the four lanes of a quad; every lane gets ((l0 + l1) + (l2 + l3)).
+__device__ inline double quad_sum(double v) {
+    v += dpp_d<0xB1>(v, 0.0);     // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v, 0.0);     // quad_perm [2,3,0,1]
+    return v;
 }
-void destroy_2d(oecdg_handle *) {}
+
+__device__ inline double quad_max(double v) {
+    v = fmax(v, dpp_d<0xB1>(v, -INFINITY));
+    v = fmax(v, dpp_d<0x4E>(v, -INFINITY));
+    return v;
+}
+
+__device__ inline int wrap_idx(int i, int n, bool small) {
+    if (small) return ((i % n) + n) % n;
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// (-1)^(n+d) P_n^(d)(1) = P_n^(d)(-1)
+__device__ inline double edge_val(double v1, int n, int d, int side) { return (side || !((n + d) & 1)) ? v1 : -v1; }
+
+// ---------------------------------------------------------- tile kernel ---
+
+template <int K, int FLUX, int TX, int TY>
+__global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
+    using F = Flux2D<FLUX>;
+    constexpr int NC = F::NC, K1 = K + 1, Q = K + 1, NE = NC * K1 * K1, NSP = 2 * K + 4;
+    constexpr int W = TX + 2, H = TY + 2, NCELL = W * H, NT = 8 * TX * TY, NW = NT / WAVE;
+    constexpr int ND1 = (TX + 1) * (TY + 1), NDAMP = 2 * ND1;
+    constexpr int NR = nrow2<NC>();
+    constexpr Tab2<K> tb = make_tab2<K>();
+    static_assert(NT % WAVE == 0 && NT <= 1024, "whole waves, at most 1024 threads");
+    __shared__ double tile[2 * NE * NCELL];      // [mesh][entry][cell]
+    __shared__ double fac[2 * K * NCELL];        // [mesh][j-1][cell]: exp(-tau sum_{m<=j} delta^m)
+    __shared__ double red[NW * NR];
+
+    const int tid = threadIdx.x, lane4 = tid & 3;
+    const int nt = a.ntx * a.nty, b = blockIdx.x;
+    const int tileid = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;   // a band of tiles per XCD
+    const int i0 = (tileid % a.ntx) * TX, j0 = (tileid / a.ntx) * TY;
+    const Stats2 *st = a.st;
+    if (a.mode == M2_STAGE && st->done) return;
+    const bool small = a.nx < W || a.ny < H;
+
+    // ---- stage both meshes' input with a one-cell halo
+    {
+        constexpr int TOT = 2 * NE * NCELL, NL = (TOT + NT - 1) / NT;
+        double v[NL];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tid + i * NT;
+            v[i] = 0.0;
+            if (e < TOT) {
+                const int cell = e % NCELL, rest = e / NCELL;
+                const int mesh = rest / NE, ent = rest % NE;
+                const int gx = wrap_idx(i0 - 1 + cell % W, a.nx, small);
+                const int gy = wrap_idx(j0 - 1 + cell / W, a.ny, small);
+                const double *src = mesh == 0 ? a.inC : a.inD;
+                v[i] = src[ent * a.plane + (long long)gy * a.nx + gx];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int e = tid + i * NT;
+            if (e < TOT) tile[e] = v[i];
+        }
+    }
+    __syncthreads();
+
+    // ---- OE step of the previous stage, in place (damped set: owned cells and one ring)
+    if (a.damp && a.mode != M2_STATS) {
+        const double tau = st->tau_damp;
+        for (int r = 0; r < (NDAMP * 4 + NT - 1) / NT; ++r) {
+            const int cs = r * (NT / 4) + (tid >> 2);
+            if (cs >= NDAMP) break;                   // whole quads leave together
+            const int mesh = cs / ND1, rr = cs % ND1;
+            const int lx = rr % (TX + 1) + mesh, ly = rr / (TX + 1) + mesh;
+            const int cell = ly * W + lx;
+            const double *own = tile + mesh * NE * NCELL;
+            const double *oth = tile + (1 - mesh) * NE * NCELL;
+            const int dir = lane4 >> 1, side = lane4 & 1;
+            const double hn = dir ? a.hy : a.hx, ht = dir ? a.hx : a.hy;
+            double ubar[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) ubar[q] = own[(q * K1 * K1) * NCELL + cell];
+            const double beta = F::speed(dir, ubar, a.fp);
+            // the other mesh's cells of the two half-edges
+            int oc[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ox = (dir ? lx + h : lx + side) - mesh, oy = (dir ? ly + side : ly + h) - mesh;
+                oc[h] = oy * W + ox;
+            }
+            double dmax[K1];
+#pragma unroll
+            for (int m = 0; m < K1; ++m) dmax[m] = 0.0;
+#pragma unroll 1
+            for (int q = 0; q < NC; ++q) {
+                const double sg = st->sig[mesh][q];
+                const double isq = sg != 0.0 ? 1.0 / sg : 0.0;
+                // traces restricted to the edge, by normal derivative order:
+                // own at the edge (normal coordinate +-1), other at its centre line (0)
+                double ro[K1][K1], rt[2][K1][K1];
+#pragma unroll
+                for (int dn = 0; dn < K1; ++dn)
+#pragma unroll
+                    for (int t = 0; t < K1; ++t) {
+                        double so = 0.0, s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                        for (int n = 0; n < K1; ++n) {
+                            const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
+                            const double ev = edge_val(tb.e1[dn][n], n, dn, side);
+                            so += own[ent * NCELL + cell] * ev;
+                            s0 += oth[ent * NCELL + oc[0]] * tb.e0[dn][n];
+                            s1 += oth[ent * NCELL + oc[1]] * tb.e0[dn][n];
+                        }
+                        ro[dn][t] = so;
+                        rt[0][dn][t] = s0;
+                        rt[1][dn][t] = s1;
+                    }
+#pragma unroll
+                for (int m = 0; m < K1; ++m) {
+                    double mean = 0.0;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int g = 0; g < Q; ++g) {
+                            double ss = 0.0;
+                            double scn = 1.0;
+#pragma unroll
+                            for (int dn = 0; dn <= m; ++dn) {
+                                const int dt = m - dn;
+                                double sct = scn;
+#pragma unroll
+                                for (int j = 0; j < dt; ++j) sct *= 2.0 / ht;
+                                double vo = 0.0, vt = 0.0;
+#pragma unroll
+                                for (int t = 0; t < K1; ++t) {
+                                    vo += ro[dn][t] * tb.own[dt][h][g][t];
+                                    vt += rt[h][dn][t] * tb.nb[dt][h][g][t];
+                                }
+                                const double d = sct * (vo - vt);
+                                ss += d * d;
+                                scn *= 2.0 / hn;
+                            }
+                            mean += 0.25 * tb.w[g] * sqrt(ss);
+                        }
+                    double hm = 1.0;                      // h_e^(m-1)
+                    if (m == 0) hm = 1.0 / hn;
+#pragma unroll
+                    for (int j = 1; j < m; ++j) hm *= hn;
+                    // sum over the four edges, divide by sigma, max over components
+                    dmax[m] = fmax(dmax[m], quad_sum(beta * tb.cdel[m] * hm * mean) * isq);
+                }
+            }
+            double S = 0.0;
+#pragma unroll
+            for (int m = 0; m < K1; ++m) {
+                S += dmax[m];
+                if (m >= 1 && lane4 == m - 1) fac[(mesh * K + (m - 1)) * NCELL + cell] = exp(-tau * S);
+            }
+        }
+        __syncthreads();
+        // damp: mode (a, b) != (0, 0) by the factor of total degree min(a + b, K)
+        for (int e = tid; e < NDAMP * NE; e += NT) {
+            const int cs = e % NDAMP, ent = e / NDAMP;
+            const int mesh = cs / ND1, rr = cs % ND1;
+            const int cell = (rr / (TX + 1) + mesh) * W + rr % (TX + 1) + mesh;
+            const int ab = ent % (K1 * K1), da = ab / K1, db = ab % K1;
+            const int deg = da + db;
+            if (deg > 0) {
+                const int j = (deg < K ? deg : K) - 1;
+                tile[(mesh * NE + ent) * NCELL + cell] *= fac[(mesh * K + j) * NCELL + cell];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- owned cells: quad lanes per cell
+    const int cs = tid >> 2;
+    const int mesh = cs / (TX * TY), rr = cs % (TX * TY);
+    const int lx = rr % TX + 1, ly = rr / TX + 1;
+    const int cell = ly * W + lx;
+    const int gx = i0 + lx - 1, gy = j0 + ly - 1;
+    const bool valid = gx < a.nx && gy < a.ny;
+    const long long gofs = (long long)gy * a.nx + gx;
+    double *town = tile + mesh * NE * NCELL;
+
+    if (a.mode == M2_FINAL) {
+        double *dst = mesh == 0 ? a.outC : a.outD;
+        if (valid)
+            for (int e = lane4; e < NE; e += 4) dst[e * a.plane + gofs] = town[e * NCELL + cell];
+        return;
+    }
+
+    // The statistics below take, per lane, component cq of this cell: the
+    // lane's own component when there are four lanes per component set
+    // (Euler), component 0 otherwise.
+    constexpr bool LANE_COMP = NC == 4;
+    const int cq = LANE_COMP ? lane4 : 0;
+    double cst[K1][K1];
+
+    if (a.mode == M2_STAGE) {
+        if (a.write_u && valid) {
+            double *UM = mesh == 0 ? a.UC : a.UD;
+            for (int e = lane4; e < NE; e += 4) UM[e * a.plane + gofs] = town[e * NCELL + cell];
+        }
+        const double *toth = tile + (1 - mesh) * NE * NCELL;
+        const double tau = st->tau, itm = 1.0 / st->tau_max;
+        const double hx = a.hx, hy = a.hy;
+        const double *UM = mesh == 0 ? a.UC : a.UD;
+        double *OM = mesh == 0 ? a.outC : a.outD;
+        bool finite = true;
+        if constexpr (LANE_COMP) {
+            // lane q accumulates component q over all quadrants and edges; the
+            // quad shares the point values of w so every lane can form its flux
+            const int q = lane4;
+            double Rq[K1][K1];
+#pragma unroll
+            for (int i = 0; i < K1; ++i)
+#pragma unroll
+                for (int j = 0; j < K1; ++j) Rq[i][j] = 0.0;
+            const double gm1 = a.fp.gamma - 1.0;
+            // coupling and volume, quadrant (sx, sy)
+#pragma unroll 1
+            for (int qd = 0; qd < 4; ++qd) {
+                    const int sx = qd & 1, sy = qd >> 1;
+                    const int oc = (ly + sy - mesh) * W + (lx + sx - mesh);
+                    double d[K1][K1];
+#pragma unroll
+                    for (int c = 0; c < K1; ++c)
+#pragma unroll
+                        for (int e = 0; e < K1; ++e) d[c][e] = toth[((q * K1 + c) * K1 + e) * NCELL + oc];
+#pragma unroll
+                    for (int p = 0; p < Q; ++p) {
+                        double cx[K1];
+#pragma unroll
+                        for (int e = 0; e < K1; ++e) {
+                            double t = 0.0;
+#pragma unroll
+                            for (int c = 0; c < K1; ++c) t += d[c][e] * tb.nb[0][sx][p][c];
+                            cx[e] = t;
+                        }
+                        double A[K1], B[K1];
+#pragma unroll
+                        for (int j = 0; j < K1; ++j) A[j] = B[j] = 0.0;
+#pragma unroll
+                        for (int g = 0; g < Q; ++g) {
+                            double wq = 0.0;
+#pragma unroll
+                            for (int e = 0; e < K1; ++e) wq += cx[e] * tb.nb[0][sy][g][e];
+                            const double w0 = dpp_d<0x00>(wq, wq), w1 = dpp_d<0x55>(wq, wq);
+                            const double w2 = dpp_d<0xAA>(wq, wq), w3 = dpp_d<0xFF>(wq, wq);
+                            const double ir = 1.0 / w0, u = w1 * ir, v = w2 * ir;
+                            const double pr = gm1 * (w3 - 0.5 * (w1 * u + w2 * v));
+                            const double base = q == 3 ? w3 + pr : wq;
+                            const double f1 = base * u + (q == 1 ? pr : 0.0);
+                            const double f2 = base * v + (q == 2 ? pr : 0.0);
+#pragma unroll
+                            for (int j = 0; j < K1; ++j) {
+                                A[j] += tb.w[g] * (wq * itm * tb.own[0][sy][g][j] + (2.0 / hy) * f2 * tb.own[1][sy][g][j]);
+                                B[j] += tb.w[g] * f1 * tb.own[0][sy][g][j];
+                            }
+                        }
+                        const double wp = hx * hy / 16.0 * tb.w[p];
+#pragma unroll
+                        for (int i = 0; i < K1; ++i)
+#pragma unroll
+                            for (int j = 0; j < K1; ++j)
+                                Rq[i][j] += wp * (tb.own[0][sx][p][i] * A[j] + (2.0 / hx) * tb.own[1][sx][p][i] * B[j]);
+                    }
+                }
+            // edges: (dir, side) = W, E (f_1 on vertical centre lines), S, N (f_2)
+#pragma unroll 1
+            for (int ed = 0; ed < 4; ++ed) {
+                    const int dir = ed >> 1, side = ed & 1;
+                    const double ht = dir ? hx : hy, sgn = side ? 1.0 : -1.0;
+                    double Y[K1];
+#pragma unroll
+                    for (int t = 0; t < K1; ++t) Y[t] = 0.0;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int ox = (dir ? lx + h : lx + side) - mesh, oy = (dir ? ly + side : ly + h) - mesh;
+                        const int oc = oy * W + ox;
+                        double r[K1];
+#pragma unroll
+                        for (int t = 0; t < K1; ++t) {
+                            double sum = 0.0;
+#pragma unroll
+                            for (int n = 0; n < K1; ++n) {
+                                const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
+                                sum += toth[ent * NCELL + oc] * tb.e0[0][n];
+                            }
+                            r[t] = sum;
+                        }
+#pragma unroll
+                        for (int g = 0; g < Q; ++g) {
+                            double wq = 0.0;
+#pragma unroll
+                            for (int t = 0; t < K1; ++t) wq += r[t] * tb.nb[0][h][g][t];
+                            const double w0 = dpp_d<0x00>(wq, wq), w1 = dpp_d<0x55>(wq, wq);
+                            const double w2 = dpp_d<0xAA>(wq, wq), w3 = dpp_d<0xFF>(wq, wq);
+                            const double ir = 1.0 / w0, un = (dir ? w2 : w1) * ir;
+                            const double pr = gm1 * (w3 - 0.5 * (w1 * w1 + w2 * w2) * ir);
+                            const double base = q == 3 ? w3 + pr : wq;
+                            const double fn = base * un + (q == 1 + dir ? pr : 0.0);
+#pragma unroll
+                            for (int t = 0; t < K1; ++t) Y[t] += tb.w[g] * fn * tb.own[0][h][g][t];
+                        }
+                    }
+#pragma unroll
+                    for (int n = 0; n < K1; ++n)
+#pragma unroll
+                        for (int t = 0; t < K1; ++t) {
+                            const double x = sgn * 0.25 * ht * edge_val(1.0, n, 0, side) * Y[t];
+                            if (dir) Rq[t][n] -= x;
+                            else Rq[n][t] -= x;
+                        }
+                }
+            // own part of the coupling, mass inverse, SSP-RK3
+#pragma unroll
+            for (int i = 0; i < K1; ++i)
+#pragma unroll
+                for (int j = 0; j < K1; ++j) {
+                    const int e = (q * K1 + i) * K1 + j;
+                    const double mass = hx * hy / ((2.0 * i + 1.0) * (2.0 * j + 1.0));
+                    const double s0 = town[e * NCELL + cell];
+                    const double Lv = (Rq[i][j] - mass * itm * s0) / mass;
+                    const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
+                    const double v = s0 + tau * Lv;
+                    const double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
+                    cst[i][j] = o;
+                    finite = finite && isfinite(o);
+                    if (valid) OM[e * a.plane + gofs] = o;
+                }
+        } else {
+            // one component: lane t takes quadrant t and edge t, the quad sums
+            double R[NC][K1][K1];
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int i = 0; i < K1; ++i)
+#pragma unroll
+                    for (int j = 0; j < K1; ++j) R[q][i][j] = 0.0;
+            {
+                const int sx = lane4 & 1, sy = lane4 >> 1;
+                const int oc = (ly + sy - mesh) * W + (lx + sx - mesh);
+#pragma unroll
+                for (int p = 0; p < Q; ++p) {
+                    double cx[NC][K1];
+#pragma unroll
+                    for (int q = 0; q < NC; ++q)
+#pragma unroll
+                        for (int d = 0; d < K1; ++d) {
+                            double sum = 0.0;
+#pragma unroll
+                            for (int c = 0; c < K1; ++c)
+                                sum += toth[((q * K1 + c) * K1 + d) * NCELL + oc] * (sx ? tb.nb[0][1][p][c] : tb.nb[0][0][p][c]);
+                            cx[q][d] = sum;
+                        }
+                    double A[NC][K1], B[NC][K1];
+#pragma unroll
+                    for (int q = 0; q < NC; ++q)
+#pragma unroll
+                        for (int j = 0; j < K1; ++j) A[q][j] = B[q][j] = 0.0;
+#pragma unroll
+                    for (int g = 0; g < Q; ++g) {
+                        double w[NC], f1[NC], f2[NC];
+#pragma unroll
+                        for (int q = 0; q < NC; ++q) {
+                            double sum = 0.0;
+#pragma unroll
+                            for (int d = 0; d < K1; ++d) sum += cx[q][d] * (sy ? tb.nb[0][1][g][d] : tb.nb[0][0][g][d]);
+                            w[q] = sum;
+                        }
+                        F::f(0, w, f1, a.fp);
+                        F::f(1, w, f2, a.fp);
+#pragma unroll
+                        for (int q = 0; q < NC; ++q)
+#pragma unroll
+                            for (int j = 0; j < K1; ++j) {
+                                const double pb = sy ? tb.own[0][1][g][j] : tb.own[0][0][g][j];
+                                const double dpb = sy ? tb.own[1][1][g][j] : tb.own[1][0][g][j];
+                                A[q][j] += tb.w[g] * (w[q] * itm * pb + (2.0 / hy) * f2[q] * dpb);
+                                B[q][j] += tb.w[g] * f1[q] * pb;
+                            }
+                    }
+                    const double wp = hx * hy / 16.0 * tb.w[p];
+#pragma unroll
+                    for (int i = 0; i < K1; ++i) {
+                        const double pa = sx ? tb.own[0][1][p][i] : tb.own[0][0][p][i];
+                        const double dpa = sx ? tb.own[1][1][p][i] : tb.own[1][0][p][i];
+#pragma unroll
+                        for (int q = 0; q < NC; ++q)
+#pragma unroll
+                            for (int j = 0; j < K1; ++j) R[q][i][j] += wp * (pa * A[q][j] + (2.0 / hx) * dpa * B[q][j]);
+                    }
+                }
+            }
+            {
+                const int dir = lane4 >> 1, side = lane4 & 1;
+                const double ht = dir ? hx : hy, sgn = side ? 1.0 : -1.0;
+                double Y[NC][K1];
+#pragma unroll
+                for (int q = 0; q < NC; ++q)
+#pragma unroll
+                    for (int t = 0; t < K1; ++t) Y[q][t] = 0.0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int ox = (dir ? lx + h : lx + side) - mesh, oy = (dir ? ly + side : ly + h) - mesh;
+                    const int oc = oy * W + ox;
+                    double r[NC][K1];
+#pragma unroll
+                    for (int q = 0; q < NC; ++q)
+#pragma unroll
+                        for (int t = 0; t < K1; ++t) {
+                            double sum = 0.0;
+#pragma unroll
+                            for (int n = 0; n < K1; ++n) {
+                                const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
+                                sum += toth[ent * NCELL + oc] * tb.e0[0][n];
+                            }
+                            r[q][t] = sum;
+                        }
+#pragma unroll
+                    for (int g = 0; g < Q; ++g) {
+                        double w[NC], fn[NC];
+#pragma unroll
+                        for (int q = 0; q < NC; ++q) {
+                            double sum = 0.0;
+#pragma unroll
+                            for (int t = 0; t < K1; ++t) sum += r[q][t] * tb.nb[0][h][g][t];
+                            w[q] = sum;
+                        }
+                        F::f(dir, w, fn, a.fp);
+#pragma unroll
+                        for (int q = 0; q < NC; ++q)
+#pragma unroll
+                            for (int t = 0; t < K1; ++t) Y[q][t] += tb.w[g] * fn[q] * tb.own[0][h][g][t];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < NC; ++q)
+#pragma unroll
+                    for (int i = 0; i < K1; ++i)
+#pragma unroll
+                        for (int j = 0; j < K1; ++j) {
+                            const double x_ij = sgn * 0.25 * ht * edge_val(1.0, i, 0, side) * Y[q][j];
+                            const double x_ji = sgn * 0.25 * ht * edge_val(1.0, j, 0, side) * Y[q][i];
+                            R[q][i][j] -= dir ? x_ji : x_ij;
+                        }
+            }
+            double outv[(NE + 3) / 4];
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int i = 0; i < K1; ++i)
+#pragma unroll
+                    for (int j = 0; j < K1; ++j) {
+                        const int e = (q * K1 + i) * K1 + j;
+                        const double mass = hx * hy / ((2.0 * i + 1.0) * (2.0 * j + 1.0));
+                        const double s0 = town[e * NCELL + cell];
+                        const double Lv = (quad_sum(R[q][i][j]) - mass * itm * s0) / mass;
+                        if ((e & 3) == lane4) {
+                            const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
+                            const double v = s0 + tau * Lv;
+                            const double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
+                            outv[e >> 2] = o;
+                            finite = finite && isfinite(o);
+                        }
+                    }
+            if (valid) {
+#pragma unroll
+                for (int e4 = 0; e4 < (NE + 3) / 4; ++e4) {
+                    const int e = e4 * 4 + lane4;
+                    if (e < NE) OM[e * a.plane + gofs] = outv[e4];
+                }
+            }
+            __syncthreads();                 // every lane has read the tile: reuse it for the output
+#pragma unroll
+            for (int e4 = 0; e4 < (NE + 3) / 4; ++e4) {
+                const int e = e4 * 4 + lane4;
+                if (e < NE) town[e * NCELL + cell] = outv[e4];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < K1; ++i)
+#pragma unroll
+                for (int j = 0; j < K1; ++j) cst[i][j] = town[((cq * K1 + i) * K1 + j) * NCELL + cell];
+        }
+        if (valid && !finite) a.err[0] = 1;
+    } else {
+#pragma unroll
+        for (int i = 0; i < K1; ++i)
+#pragma unroll
+            for (int j = 0; j < K1; ++j) cst[i][j] = town[((cq * K1 + i) * K1 + j) * NCELL + cell];
+    }
+
+    // ---- partial statistics of the output (stage) or of the input (stats mode)
+    double ubar[NC];
+    if constexpr (LANE_COMP) {
+        const double c0 = cst[0][0];
+        ubar[0] = dpp_d<0x00>(c0, c0);
+        ubar[1] = dpp_d<0x55>(c0, c0);
+        ubar[2] = dpp_d<0xAA>(c0, c0);
+        ubar[3] = dpp_d<0xFF>(c0, c0);
+    } else {
+        ubar[0] = cst[0][0];
+    }
+    double vals[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        vals[j] = j < 2 * NC * 3 ? stat_identity(j % 3) : -INFINITY;
+    if (valid) {
+        // sample values of component cq: rows i of the S x S grid (all rows
+        // for a component lane, rows i = lane (mod 4) for one component)
+        double mx = -INFINITY, mn = INFINITY;
+#pragma unroll
+        for (int i = 0; i < NSP; ++i) {
+            if (!LANE_COMP && (i & 3) != lane4) continue;
+            double rb[K1];
+#pragma unroll
+            for (int j = 0; j < K1; ++j) {
+                double sum = 0.0;
+#pragma unroll
+                for (int c = 0; c < K1; ++c) sum += cst[c][j] * tb.sp[i][c];
+                rb[j] = sum;
+            }
+#pragma unroll
+            for (int jj = 0; jj < NSP; ++jj) {
+                double v = 0.0;
+#pragma unroll
+                for (int j = 0; j < K1; ++j) v += rb[j] * tb.sp[jj][j];
+                mx = fmax(mx, v);
+                mn = fmin(mn, v);
+            }
+        }
+#pragma unroll
+        for (int m2 = 0; m2 < 2; ++m2)
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+                if (m2 != mesh || q != cq) continue;
+                vals[row2(NC, m2, q, 0)] = (LANE_COMP || lane4 == 0) ? cst[0][0] : 0.0;
+                vals[row2(NC, m2, q, 1)] = mx;
+                vals[row2(NC, m2, q, 2)] = mn;
+            }
+        if (lane4 == 0) {
+            vals[2 * NC * 3] = F::speed(0, ubar, a.fp);
+            vals[2 * NC * 3 + 1] = F::speed(1, ubar, a.fp);
+            if (!F::physical(ubar, a.fp)) a.err[1] = 1;
+        }
+    }
+    {
+        const int lane = tid % WAVE, wave = tid / WAVE;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            const int kind = j < 2 * NC * 3 ? j % 3 : 1;
+            const double v = wave_reduce(kind, vals[j]);
+            if (lane == WAVE - 1) red[wave * NR + j] = v;
+        }
+        __syncthreads();
+        if (tid < NR) {
+            const int kind = tid < 2 * NC * 3 ? tid % 3 : 1;
+            double v = red[tid];
+            for (int w2 = 1; w2 < NW; ++w2) v = stat_op(kind, v, red[w2 * NR + tid]);
+            a.part[(long long)tid * nt + tileid] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------- reduce kernels ---
+// Two levels, both in a fixed order: k_fold2d folds contiguous ranges of
+// tiles into one partial per workgroup; k_reduce2d folds those in one
+// workgroup and updates the step scalars.
+
+constexpr int RED2_NT = 256;
+constexpr int FOLD2_MAXB = 64;
+
+template <int NC>
+__global__ __launch_bounds__(RED2_NT) void k_fold2d(const double *part, int ntiles, int per, double *out, int nb) {
+    constexpr int NR = nrow2<NC>(), NW = RED2_NT / WAVE;
+    __shared__ double red[NW * NR];
+    const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+    const int t0 = blockIdx.x * per, t1 = min(ntiles, t0 + per);
+    double acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] = stat_identity(j < 2 * NC * 3 ? j % 3 : 1);
+    for (int t = t0 + tid; t < t1; t += RED2_NT)
+#pragma unroll
+        for (int j = 0; j < NR; ++j) acc[j] = stat_op(j < 2 * NC * 3 ? j % 3 : 1, acc[j], part[(long long)j * ntiles + t]);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const double v = wave_reduce(j < 2 * NC * 3 ? j % 3 : 1, acc[j]);
+        if (lane == WAVE - 1) red[wave * NR + j] = v;
+    }
+    __syncthreads();
+    if (tid < NR) {
+        const int kind = tid < 2 * NC * 3 ? tid % 3 : 1;
+        double v = red[tid];
+        for (int w = 1; w < NW; ++w) v = stat_op(kind, v, red[w * NR + tid]);
+        out[(long long)tid * nb + blockIdx.x] = v;
+    }
+}
+
+template <int NC>
+__global__ __launch_bounds__(RED2_NT) void k_reduce2d(Red2Args r) {
+    constexpr int NR = nrow2<NC>(), NW = RED2_NT / WAVE;
+    __shared__ double red[NW * NR];
+    const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+    Stats2 *st = r.st;
+    if ((r.mode == R2_STAGE) && st->done) return;
+    double acc[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) acc[j] = stat_identity(j < 2 * NC * 3 ? j % 3 : 1);
+    for (int t = tid; t < r.ntiles; t += RED2_NT)
+#pragma unroll
+        for (int j = 0; j < NR; ++j) acc[j] = stat_op(j < 2 * NC * 3 ? j % 3 : 1, acc[j], r.part[(long long)j * r.ntiles + t]);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const double v = wave_reduce(j < 2 * NC * 3 ? j % 3 : 1, acc[j]);
+        if (lane == WAVE - 1) red[wave * NR + j] = v;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    double tot[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int kind = j < 2 * NC * 3 ? j % 3 : 1;
+        double v = red[j];
+        for (int w = 1; w < NW; ++w) v = stat_op(kind, v, red[w * NR + j]);
+        tot[j] = v;
+    }
+    for (int mesh = 0; mesh < 2; ++mesh)
+        for (int q = 0; q < NC; ++q) {
+            const double avg = tot[row2(NC, mesh, q, 0)] / (double)r.ncell;
+            st->avg[mesh][q] = avg;
+            st->sig[mesh][q] = fmax(tot[row2(NC, mesh, q, 1)] - avg, avg - tot[row2(NC, mesh, q, 2)]);
+        }
+    st->bx = tot[2 * NC * 3];
+    st->by = tot[2 * NC * 3 + 1];
+    if (r.mode == R2_STEP || r.mode == R2_FINAL) {
+        if (st->pending) {                       // complete the previous step
+            st->t = st->last ? r.t_end : st->t + st->tau;
+            st->nexec += 1;
+            st->pending = 0;
+        }
+        st->tau_damp = st->tau;
+    }
+    if (r.mode == R2_STEP) {
+        if (!(st->t < r.t_end)) {
+            st->done = 1;
+            return;
+        }
+        double tm = r.dt_fixed;
+        if (!(tm > 0.0)) {
+            const double rate = st->bx / r.hx + st->by / r.hy;
+            if (!(rate > 0.0) || !isfinite(rate)) {
+                st->done = 1;
+                st->bad = 1;
+                r.err[2] = 1;
+                return;
+            }
+            tm = r.cfl / rate;
+        }
+        double tau = tm;
+        int last = 0;
+        if (st->t + tau >= r.t_end) {
+            tau = r.t_end - st->t;
+            last = 1;
+        }
+        st->tau = tau;
+        st->tau_max = tm;
+        st->last = last;
+        st->done = 0;
+        st->pending = 1;
+    } else if (r.mode == R2_STAGE) {
+        st->tau_damp = st->tau;
+    } else if (r.mode == R2_SINGLE) {
+        st->tau = r.tau_o;
+        st->tau_max = r.taumax_o;
+        st->tau_damp = r.tau_o;
+        st->done = 0;
+    }
+}
+
+// ------------------------------------------------------------ host side ---
+
+namespace {
+
+constexpr int TX2 = 8, TY2 = 8;
+
+struct Ext2D {
+    int k, nc, flux, oe;
+    int nx, ny, ntx, nty, ntiles;
+    double hx, hy, cfl;
+    FPar2 fp;
+    long long S1;                // doubles of one mesh
+    double *B[2] = {nullptr, nullptr};      // stage states, both meshes each
+    double *U = nullptr;
+    double *part[2] = {nullptr, nullptr};
+    double *fold = nullptr;      // [row][FOLD2_MAXB] first-level partials
+    int nfold = 1, fold_per = 1;
+    Stats2 *st = nullptr;
+    Stats2 *st_h = nullptr;      // pinned
+    int *err = nullptr, *err_h = nullptr;
+};
+
+Ext2D *ext(oecdg_handle *h) { return static_cast<Ext2D *>(handle_ext2d(h)); }
+
+#define HIPCHK2(h, expr)                                                                                      \
+    do {                                                                                                      \
+        hipError_t e_ = (expr);                                                                               \
+        if (e_ != hipSuccess) return handle_fail((h), OECDG_EHIP, hipGetErrorString(e_));                     \
+    } while (0)
+
+template <int K, int FLUX>
+void *stage_kernel() {
+    return (void *)k_stage2d<K, FLUX, TX2, TY2>;
+}
+
+hipError_t launch_stage2d(const Ext2D &x, const Stage2Args &a, hipStream_t s) {
+    void *fn = x.flux == OECDG_FLUX_EULER ? stage_kernel<2, OECDG_FLUX_EULER>() : stage_kernel<2, OECDG_FLUX_ADVECTION>();
+    Stage2Args copy = a;
+    void *args[] = {&copy};
+    return hipLaunchKernel(fn, dim3(x.ntiles), dim3(8 * TX2 * TY2), args, 0, s);
+}
+
+// Fold r.part (per-tile partials) into the global scalars: first level into
+// x.fold, then the single-workgroup finish.
+hipError_t launch_reduce2d(const Ext2D &x, const Red2Args &r, hipStream_t s) {
+    const double *part = r.part;
+    int n = r.ntiles, per = x.fold_per, nb = x.nfold;
+    double *out = x.fold;
+    void *args1[] = {&part, &n, &per, &out, &nb};
+    void *fold = x.nc == 4 ? (void *)k_fold2d<4> : (void *)k_fold2d<1>;
+    hipError_t e = hipLaunchKernel(fold, dim3(nb), dim3(RED2_NT), args1, 0, s);
+    if (e != hipSuccess) return e;
+    void *fn = x.nc == 4 ? (void *)k_reduce2d<4> : (void *)k_reduce2d<1>;
+    Red2Args copy = r;
+    copy.part = x.fold;
+    copy.ntiles = nb;
+    void *args[] = {&copy};
+    return hipLaunchKernel(fn, dim3(1), dim3(RED2_NT), args, 0, s);
+}
+
+Stage2Args stage_args(const Ext2D &x) {
+    Stage2Args a;
+    memset(&a, 0, sizeof(a));
+    a.nx = x.nx;
+    a.ny = x.ny;
+    a.ntx = x.ntx;
+    a.nty = x.nty;
+    a.plane = (long long)x.nx * x.ny;
+    a.hx = x.hx;
+    a.hy = x.hy;
+    a.fp = x.fp;
+    a.st = x.st;
+    a.err = x.err;
+    return a;
+}
+
+Red2Args red_args(const Ext2D &x, const double *part, int mode) {
+    Red2Args r;
+    memset(&r, 0, sizeof(r));
+    r.part = part;
+    r.ntiles = x.ntiles;
+    r.mode = mode;
+    r.ncell = (long long)x.nx * x.ny;
+    r.t_end = INFINITY;
+    r.cfl = x.cfl;
+    r.hx = x.hx;
+    r.hy = x.hy;
+    r.st = x.st;
+    r.err = x.err;
+    return r;
+}
+
+int check2d(oecdg_handle *h, const Ext2D &x) {
+    hipStream_t s = handle_stream(h);
+    HIPCHK2(h, hipMemcpyAsync(x.err_h, x.err, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK2(h, hipStreamSynchronize(s));
+    if (x.err_h[2]) return handle_fail(h, OECDG_ENONFINITE, "no admissible time step (wave speed zero or not finite)");
+    if (x.err_h[0]) return handle_fail(h, OECDG_ENONFINITE, "non-finite coefficient produced");
+    if (x.err_h[1]) return handle_fail(h, OECDG_ENONPHYSICAL, "non-positive density or pressure at a cell average");
+    return OECDG_OK;
+}
+
+int reset2d(oecdg_handle *h, Ext2D &x) {
+    hipStream_t s = handle_stream(h);
+    memset(x.st_h, 0, sizeof(Stats2));
+    HIPCHK2(h, hipMemcpyAsync(x.st, x.st_h, sizeof(Stats2), hipMemcpyHostToDevice, s));
+    HIPCHK2(h, hipMemsetAsync(x.err, 0, 4 * sizeof(int), s));
+    return OECDG_OK;
+}
+
+}  // namespace
+
+int create_2d(oecdg_handle *h, const oecdg_desc *d) {
+    Ext2D *x = new (std::nothrow) Ext2D();
+    if (!x) return OECDG_ENOMEM;
+    handle_ext2d(h) = x;
+    x->k = d->k;
+    x->flux = d->flux;
+    x->nc = d->flux == OECDG_FLUX_EULER ? 4 : 1;
+    x->oe = d->oe;
+    x->nx = (int)d->nx;
+    x->ny = (int)d->ny;
+    x->ntx = (x->nx + TX2 - 1) / TX2;
+    x->nty = (x->ny + TY2 - 1) / TY2;
+    x->ntiles = x->ntx * x->nty;
+    x->hx = (d->xhi - d->xlo) / d->nx;
+    x->hy = (d->yhi - d->ylo) / d->ny;
+    x->cfl = d->cfl;
+    x->fp.a = d->flux_param[0];
+    x->fp.b = d->flux_param[1];
+    x->fp.gamma = d->flux_param[0];
+    x->S1 = (long long)x->nc * (x->k + 1) * (x->k + 1) * x->nx * x->ny;
+    const size_t nrow = x->nc == 4 ? nrow2<4>() : nrow2<1>();
+    HIPCHK2(h, hipMalloc(&x->B[0], sizeof(double) * 2 * x->S1));
+    HIPCHK2(h, hipMalloc(&x->B[1], sizeof(double) * 2 * x->S1));
+    HIPCHK2(h, hipMalloc(&x->U, sizeof(double) * 2 * x->S1));
+    HIPCHK2(h, hipMalloc(&x->part[0], sizeof(double) * nrow * x->ntiles));
+    HIPCHK2(h, hipMalloc(&x->part[1], sizeof(double) * nrow * x->ntiles));
+    x->nfold = x->ntiles < FOLD2_MAXB ? x->ntiles : FOLD2_MAXB;
+    x->fold_per = (x->ntiles + x->nfold - 1) / x->nfold;
+    HIPCHK2(h, hipMalloc(&x->fold, sizeof(double) * nrow * x->nfold));
+    HIPCHK2(h, hipMalloc(&x->st, sizeof(Stats2)));
+    HIPCHK2(h, hipHostMalloc((void **)&x->st_h, sizeof(Stats2), hipHostMallocDefault));
+    HIPCHK2(h, hipMalloc(&x->err, 4 * sizeof(int)));
+    HIPCHK2(h, hipHostMalloc((void **)&x->err_h, 4 * sizeof(int), hipHostMallocDefault));
+    return OECDG_OK;
+}
+
+void destroy_2d(oecdg_handle *h) {
+    Ext2D *x = ext(h);
+    if (!x) return;
+    for (int i = 0; i < 2; ++i) {
+        if (x->B[i]) (void)hipFree(x->B[i]);
+        if (x->part[i]) (void)hipFree(x->part[i]);
+    }
+    if (x->U) (void)hipFree(x->U);
+    if (x->fold) (void)hipFree(x->fold);
+    if (x->st) (void)hipFree(x->st);
+    if (x->st_h) (void)hipHostFree(x->st_h);
+    if (x->err) (void)hipFree(x->err);
+    if (x->err_h) (void)hipHostFree(x->err_h);
+    delete x;
+    handle_ext2d(h) = nullptr;
+}
+
+// Statistics of a state (both meshes) into part[0], reduced with `mode`.
+static int stats_of(oecdg_handle *h, Ext2D &x, const double *uC, const double *uD, int mode) {
+    hipStream_t s = handle_stream(h);
+    Stage2Args a = stage_args(x);
+    a.mode = M2_STATS;
+    a.inC = uC;
+    a.inD = uD;
+    a.part = x.part[0];
+    HIPCHK2(h, launch_stage2d(x, a, s));
+    Red2Args r = red_args(x, x.part[0], mode);
+    HIPCHK2(h, launch_reduce2d(x, r, s));
+    return OECDG_OK;
+}
+
+int dt_2d(oecdg_handle *h, const double *uC, const double *uD, double *dt_out) {
+    Ext2D &x = *ext(h);
+    int rc = reset2d(h, x);
+    if (rc == OECDG_OK) rc = stats_of(h, x, uC, uD, R2_STATS);
+    if (rc != OECDG_OK) return rc;
+    hipStream_t s = handle_stream(h);
+    HIPCHK2(h, hipMemcpyAsync(x.st_h, x.st, sizeof(Stats2), hipMemcpyDeviceToHost, s));
+    HIPCHK2(h, hipStreamSynchronize(s));
+    const double rate = x.st_h->bx / x.hx + x.st_h->by / x.hy;
+    if (!(rate > 0.0) || !std::isfinite(rate)) return handle_fail(h, OECDG_ENONFINITE, "wave speed is zero or not finite");
+    *dt_out = x.cfl / rate;
+    return OECDG_OK;
+}
+
+int stage_2d(oecdg_handle *h, int stage, double dt, double tau_max, const double *uCn, const double *uDn,
+             const double *uCl, const double *uDl, double *uCo, double *uDo) {
+    Ext2D &x = *ext(h);
+    hipStream_t s = handle_stream(h);
+    int rc = reset2d(h, x);
+    if (rc != OECDG_OK) return rc;
+    Red2Args r = red_args(x, x.part[1], R2_SINGLE);
+    r.tau_o = dt;
+    r.taumax_o = tau_max;
+    HIPCHK2(h, hipMemsetAsync(x.part[1], 0, sizeof(double) * (x.nc == 4 ? nrow2<4>() : nrow2<1>()) * x.ntiles, s));
+    HIPCHK2(h, launch_reduce2d(x, r, s));
+    Stage2Args a = stage_args(x);
+    a.mode = M2_STAGE;
+    a.l = stage;
+    a.damp = 0;
+    a.write_u = 0;
+    a.inC = stage == 0 ? uCn : uCl;
+    a.inD = stage == 0 ? uDn : uDl;
+    a.UC = const_cast<double *>(uCn);
+    a.UD = const_cast<double *>(uDn);
+    a.outC = x.B[0];
+    a.outD = x.B[0] + x.S1;
+    a.part = x.part[0];
+    HIPCHK2(h, launch_stage2d(x, a, s));
+    Red2Args rf = red_args(x, x.part[0], R2_STAGE);
+    HIPCHK2(h, launch_reduce2d(x, rf, s));
+    Stage2Args f = stage_args(x);
+    f.mode = M2_FINAL;
+    f.damp = x.oe && x.k > 0;
+    f.inC = x.B[0];
+    f.inD = x.B[0] + x.S1;
+    f.outC = uCo;
+    f.outD = uDo;
+    HIPCHK2(h, launch_stage2d(x, f, s));
+    return check2d(h, x);
+}
+
+int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps, double dt_fixed, double *t_out,
+           int64_t *steps_out) {
+    Ext2D &x = *ext(h);
+    hipStream_t s = handle_stream(h);
+    if (nsteps < 0 && !std::isfinite(t_end)) return handle_fail(h, OECDG_EINVAL, "give a finite t_end or nsteps >= 0");
+    int rc = reset2d(h, x);
+    if (rc != OECDG_OK) return rc;
+    HIPCHK2(h, hipMemcpyAsync(x.B[0], uC, sizeof(double) * x.S1, hipMemcpyDeviceToDevice, s));
+    HIPCHK2(h, hipMemcpyAsync(x.B[0] + x.S1, uD, sizeof(double) * x.S1, hipMemcpyDeviceToDevice, s));
+    {   // statistics of the initial data (wave speeds for the first step) into part[0]
+        Stage2Args a = stage_args(x);
+        a.mode = M2_STATS;
+        a.inC = x.B[0];
+        a.inD = x.B[0] + x.S1;
+        a.part = x.part[0];
+        HIPCHK2(h, launch_stage2d(x, a, s));
+    }
+    const int chunk = 16;
+    long long n = 0;
+    while (nsteps < 0 || n < nsteps) {
+        const long long m = nsteps < 0 ? chunk : std::min<long long>(chunk, nsteps - n);
+        for (long long j = 0; j < m; ++j)
+            for (int l = 0; l < 3; ++l) {
+                const long long g = 3 * (n + j) + l;
+                Red2Args r = red_args(x, x.part[g & 1], l == 0 ? R2_STEP : R2_STAGE);
+                r.t_end = t_end;
+                r.dt_fixed = dt_fixed;
+                HIPCHK2(h, launch_reduce2d(x, r, s));
+                Stage2Args a = stage_args(x);
+                a.mode = M2_STAGE;
+                a.l = l;
+                a.damp = x.oe && x.k > 0 && !(n + j == 0 && l == 0);
+                a.write_u = l == 0;
+                a.inC = x.B[g & 1];
+                a.inD = x.B[g & 1] + x.S1;
+                a.outC = x.B[(g + 1) & 1];
+                a.outD = x.B[(g + 1) & 1] + x.S1;
+                a.UC = x.U;
+                a.UD = x.U + x.S1;
+                a.part = x.part[(g + 1) & 1];
+                HIPCHK2(h, launch_stage2d(x, a, s));
+            }
+        n += m;
+        HIPCHK2(h, hipMemcpyAsync(x.st_h, x.st, sizeof(Stats2), hipMemcpyDeviceToHost, s));
+        HIPCHK2(h, hipStreamSynchronize(s));
+        if (x.st_h->done) break;
+    }
+    const long long N = x.st_h->nexec + x.st_h->pending;   // executed steps
+    Red2Args r = red_args(x, x.part[N & 1], R2_FINAL);
+    r.t_end = t_end;
+    HIPCHK2(h, launch_reduce2d(x, r, s));
+    Stage2Args f = stage_args(x);
+    f.mode = M2_FINAL;
+    f.damp = x.oe && x.k > 0 && N > 0;
+    f.inC = x.B[N & 1];
+    f.inD = x.B[N & 1] + x.S1;
+    f.outC = uC;
+    f.outD = uD;
+    HIPCHK2(h, launch_stage2d(x, f, s));
+    HIPCHK2(h, hipMemcpyAsync(x.st_h, x.st, sizeof(Stats2), hipMemcpyDeviceToHost, s));
+    rc = check2d(h, x);
+    if (t_out) *t_out = x.st_h->t;
+    if (steps_out) *steps_out = N;
+    return rc;
+}
 
 }  // namespace oecdg

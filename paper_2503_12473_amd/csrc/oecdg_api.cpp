@@ -516,6 +516,11 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
     return check_errors(h);
 }
 
+hipStream_t oecdg::handle_stream(oecdg_handle *h) { return h->stream; }
+const oecdg_desc &oecdg::handle_desc(oecdg_handle *h) { return h->desc[0]; }
+void *&oecdg::handle_ext2d(oecdg_handle *h) { return h->ext2d; }
+int oecdg::handle_fail(oecdg_handle *h, int code, const char *msg) { return fail(h, code, msg); }
+
 // ============================================================== C ABI ===
 
 extern "C" {
@@ -557,6 +562,7 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
     if (h->dim == 2) {
         rc = oecdg::create_2d(h, d);
         if (rc != OECDG_OK) {
+            oecdg::destroy_2d(h);
             delete h;
             return rc;
         }

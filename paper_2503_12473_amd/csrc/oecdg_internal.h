@@ -115,6 +115,12 @@ int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile);
 
 namespace oecdg {
 
+// Handle accessors for the 2D path (defined in oecdg_api.cpp).
+hipStream_t handle_stream(oecdg_handle *h);
+const oecdg_desc &handle_desc(oecdg_handle *h);
+void *&handle_ext2d(oecdg_handle *h);
+int handle_fail(oecdg_handle *h, int code, const char *msg);
+
 // 2D path (oecdg_2d.hip) and the 1D adjoint (oecdg_adjoint.hip).
 int create_2d(oecdg_handle *h, const oecdg_desc *d);
 int dt_2d(oecdg_handle *h, const double *uC, const double *uD, double *dt_out);
