@@ -30,6 +30,7 @@ N_CELLS, DEGREE, CFL, T_END, SEED = 16384, 2, 0.15, 0.2, 0
 FULL_STEPS = 33354             # steps to T = 0.2 for seed 0
 BATCH_COUNT, BATCH_STEPS, LOOP_SAMPLE = 512, 1000, 24
 ADJ_N, ADJ_K, ADJ_STEPS, ADJ_CKPT = 16384, 2, 400, 20
+E2D_N, E2D_STEPS, E2D_CFL = 1024, 500, 0.3
 
 
 def parse():
@@ -44,6 +45,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle sample length")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-form measurement")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D Euler measurement")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the warm-up, copy a device buffer of this many MiB (profiler counter calibration)")
     return ap.parse_args()
@@ -166,6 +168,48 @@ def adjoint_bench(repeats: int = 3):
             "forward_dof_updates_per_s": prob.dofs() * ADJ_STEPS / f}
 
 
+def euler2d_bench(repeats: int = 3, steps: int = E2D_STEPS):
+    """2D form: Euler on [0,1]^2 periodic, 1024^2 primal + 1024^2 dual cells,
+    tensor Q2 (9 modes x 4 components), seeded quadrant states (seed 0) plus
+    0.2 sin(2 pi (x+y)) in the density, CFL 0.3, 500 steps.  Times whole runs
+    of oecdg_run from the initial data (median of `repeats`)."""
+    import torch
+    from paper_2503_12473_amd import inputs
+    from paper_2503_12473_amd.api import OECDG, to_device
+    prob, uC, uD, _ = inputs.euler2d_quadrants(E2D_N, 2, seed=SEED)
+    dofs = prob.dofs()
+    stream = torch.cuda.current_stream()
+    ic = (to_device(uC), to_device(uD))
+    del uC, uD
+    with OECDG(prob, E2D_CFL, stream=stream) as solver:
+        a, b = ic[0].clone(), ic[1].clone()
+        solver.run(a, b, nsteps=10)                                     # warm-up
+        times = []
+        for _ in range(repeats):
+            a.copy_(ic[0])
+            b.copy_(ic[1])
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            t, n = solver.run(a, b, nsteps=steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+    wall = sorted(times)[len(times) // 2]
+    launch_s = wall / (3 * n)
+    bytes_per_launch = BYTES_PER_DOF_UPDATE / 3.0 * dofs
+    achieved = bytes_per_launch / launch_s / 1e9
+    return {"workload": f"2D Euler, [0,1]^2 periodic, {E2D_N}^2 primal + {E2D_N}^2 dual cells, Q2, CFL {E2D_CFL}, "
+                        f"{steps} steps, seeded quadrant states (seed {SEED})",
+            "dofs": dofs, "steps": n, "t_end": t, "wall_s": wall, "ms_per_step": 1e3 * wall / n,
+            "dof_updates_per_s": dofs * n / wall,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_stage2d (one RK stage + OE of the previous stage) + statistics folds",
+                         "launch_us": 1e6 * launch_s}}
+
+
 def cpu_baseline(target_seconds: float):
     """The CPU oracle, as it stands, on a bounded sample of the same workload:
     the first S steps from the same initial data (S sized to ~target_seconds)."""
@@ -267,6 +311,8 @@ def main():
         out["batched_k2"] = batched_bench(k_fixed=2)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench()
+    if not args.no_2d:
+        out["euler2d"] = euler2d_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))

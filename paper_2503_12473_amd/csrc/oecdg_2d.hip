@@ -147,7 +147,7 @@ struct Stats2 {
     int done, pending, last, bad; // bad: no admissible time step
 };
 
-enum { M2_STAGE = 0, M2_FINAL = 1, M2_STATS = 2 };
+enum { M2_STAGE = 0, M2_FINAL = 1 };
 enum { R2_STEP = 0, R2_STAGE = 1, R2_FINAL = 2, R2_SINGLE = 3, R2_STATS = 4 };
 
 struct Stage2Args {
@@ -158,7 +158,8 @@ struct Stage2Args {
     const double *inC, *inD;      // tile input (pre-damping, or damped when damp == 0)
     double *outC, *outD;          // stage output (undamped) or damped state (final mode)
     double *UC, *UD;              // damped u^n: written at stage 0 (write_u), read at stages 1, 2
-    double *part;                 // [row][tile] partial statistics of the output (stage / stats modes)
+    double *part;                 // [row][tile] partial statistics (k_delta2d)
+    double *numC, *numD;          // damping numerators [m*NC + q][ny][nx]: written by k_delta2d, read by k_stage2d
     const Stats2 *st;
     int *err;                     // [0] non-finite, [1] non-physical, [2] no admissible step
     int l, mode, damp, write_u;
@@ -200,162 +201,114 @@ __device__ inline int wrap_idx(int i, int n, bool small) {
 // (-1)^(n+d) P_n^(d)(1) = P_n^(d)(-1)
 __device__ inline double edge_val(double v1, int n, int d, int side) { return (side || !((n + d) & 1)) ? v1 : -v1; }
 
-// ---------------------------------------------------------- tile kernel ---
+// ---------------------------------------------------------- tile kernels ---
 
+// Tile of primal cells [i0, i0+TX) x [j0, j0+TY) and the dual cells with the
+// same indices; a band of consecutive tiles per XCD (workgroups are dealt to
+// the 8 XCDs round robin, neighbouring tiles then share an L2).
+__device__ inline int tile_of_block(int nt) {
+    const int b = blockIdx.x;
+    return (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
+}
+
+// Both meshes' state of a tile with a one-cell halo into LDS:
+// tile[(mesh*NE + entry)*NCELL + ly*W + lx], global cell (i0-1+lx, j0-1+ly).
+template <int NE, int TX, int TY, int NT>
+__device__ inline void stage_tile2d(double *tile, const double *inC, const double *inD, int i0, int j0, int nx,
+                                    int ny, long long plane) {
+    constexpr int W = TX + 2, H = TY + 2, NCELL = W * H, TOT = 2 * NE * NCELL, NL = (TOT + NT - 1) / NT;
+    const bool small = nx < W || ny < H;
+    double v[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int e = threadIdx.x + i * NT;
+        v[i] = 0.0;
+        if (e < TOT) {
+            const int cell = e % NCELL, rest = e / NCELL;
+            const int mesh = rest / NE, ent = rest % NE;
+            const int gx = wrap_idx(i0 - 1 + cell % W, nx, small);
+            const int gy = wrap_idx(j0 - 1 + cell / W, ny, small);
+            const double *src = mesh == 0 ? inC : inD;
+            v[i] = src[ent * plane + (long long)gy * nx + gx];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (e < TOT) tile[e] = v[i];
+    }
+}
+
+// Stage kernel: OE step of the previous stage on the staged input (from the
+// damping numerators of k_delta2d and sigma), then the operator of eq:2D_H
+// and the SSP-RK3 combination on the owned cells (stage mode), or only the
+// damped owned cells (final mode).
 template <int K, int FLUX, int TX, int TY>
 __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
     using F = Flux2D<FLUX>;
-    constexpr int NC = F::NC, K1 = K + 1, Q = K + 1, NE = NC * K1 * K1, NSP = 2 * K + 4;
-    constexpr int W = TX + 2, H = TY + 2, NCELL = W * H, NT = 8 * TX * TY, NW = NT / WAVE;
+    constexpr int NC = F::NC, K1 = K + 1, Q = K + 1, NE = NC * K1 * K1;
+    constexpr int W = TX + 2, H = TY + 2, NCELL = W * H, NT = 8 * TX * TY;
     constexpr int ND1 = (TX + 1) * (TY + 1), NDAMP = 2 * ND1;
-    constexpr int NR = nrow2<NC>();
     constexpr Tab2<K> tb = make_tab2<K>();
-    static_assert(NT % WAVE == 0 && NT <= 1024, "whole waves, at most 1024 threads");
+    static_assert(NT % WAVE == 0 && NT <= 1024 && NDAMP <= NT, "one damped cell per thread");
     __shared__ double tile[2 * NE * NCELL];      // [mesh][entry][cell]
     __shared__ double fac[2 * K * NCELL];        // [mesh][j-1][cell]: exp(-tau sum_{m<=j} delta^m)
-    __shared__ double red[NW * NR];
 
     const int tid = threadIdx.x, lane4 = tid & 3;
-    const int nt = a.ntx * a.nty, b = blockIdx.x;
-    const int tileid = (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;   // a band of tiles per XCD
+    const int nt = a.ntx * a.nty, tileid = tile_of_block(nt);
     const int i0 = (tileid % a.ntx) * TX, j0 = (tileid / a.ntx) * TY;
     const Stats2 *st = a.st;
     if (a.mode == M2_STAGE && st->done) return;
-    const bool small = a.nx < W || a.ny < H;
 
-    // ---- stage both meshes' input with a one-cell halo
-    {
-        constexpr int TOT = 2 * NE * NCELL, NL = (TOT + NT - 1) / NT;
-        double v[NL];
+    // damping factors of the damped set (owned cells and one ring): one
+    // thread per cell, delta^m = max_q N^m_q / sigma_q
+    double fj[K];
+    int fcell = -1, fmesh = 0;
+    if (a.damp && tid < NDAMP) {
+        fmesh = tid / ND1;
+        const int rr = tid % ND1;
+        const int lx = rr % (TX + 1) + fmesh, ly = rr / (TX + 1) + fmesh;
+        fcell = ly * W + lx;
+        const bool small = a.nx < W || a.ny < H;
+        const int gx = wrap_idx(i0 - 1 + lx, a.nx, small), gy = wrap_idx(j0 - 1 + ly, a.ny, small);
+        const double *N = fmesh == 0 ? a.numC : a.numD;
+        const long long g = (long long)gy * a.nx + gx;
+        double nv[K1][NC];
 #pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int e = tid + i * NT;
-            v[i] = 0.0;
-            if (e < TOT) {
-                const int cell = e % NCELL, rest = e / NCELL;
-                const int mesh = rest / NE, ent = rest % NE;
-                const int gx = wrap_idx(i0 - 1 + cell % W, a.nx, small);
-                const int gy = wrap_idx(j0 - 1 + cell / W, a.ny, small);
-                const double *src = mesh == 0 ? a.inC : a.inD;
-                v[i] = src[ent * a.plane + (long long)gy * a.nx + gx];
+        for (int m = 0; m < K1; ++m)
+#pragma unroll
+            for (int q = 0; q < NC; ++q) nv[m][q] = N[(m * NC + q) * a.plane + g];
+        const double tau = st->tau_damp;
+        double S = 0.0;
+#pragma unroll
+        for (int m = 0; m < K1; ++m) {
+            double dm = 0.0;
+#pragma unroll
+            for (int q = 0; q < NC; ++q) {
+                const double sg = st->sig[fmesh][q];
+                dm = fmax(dm, sg != 0.0 ? nv[m][q] / sg : 0.0);
             }
-        }
-#pragma unroll
-        for (int i = 0; i < NL; ++i) {
-            const int e = tid + i * NT;
-            if (e < TOT) tile[e] = v[i];
+            S += dm;
+            if (m >= 1) fj[m - 1] = exp(-tau * S);
         }
     }
-    __syncthreads();
-
-    // ---- OE step of the previous stage, in place (damped set: owned cells and one ring)
-    if (a.damp && a.mode != M2_STATS) {
-        const double tau = st->tau_damp;
-        for (int r = 0; r < (NDAMP * 4 + NT - 1) / NT; ++r) {
-            const int cs = r * (NT / 4) + (tid >> 2);
-            if (cs >= NDAMP) break;                   // whole quads leave together
-            const int mesh = cs / ND1, rr = cs % ND1;
-            const int lx = rr % (TX + 1) + mesh, ly = rr / (TX + 1) + mesh;
-            const int cell = ly * W + lx;
-            const double *own = tile + mesh * NE * NCELL;
-            const double *oth = tile + (1 - mesh) * NE * NCELL;
-            const int dir = lane4 >> 1, side = lane4 & 1;
-            const double hn = dir ? a.hy : a.hx, ht = dir ? a.hx : a.hy;
-            double ubar[NC];
+    stage_tile2d<NE, TX, TY, NT>(tile, a.inC, a.inD, i0, j0, a.nx, a.ny, a.plane);
+    if (a.damp) {
+        if (fcell >= 0) {
 #pragma unroll
-            for (int q = 0; q < NC; ++q) ubar[q] = own[(q * K1 * K1) * NCELL + cell];
-            const double beta = F::speed(dir, ubar, a.fp);
-            // the other mesh's cells of the two half-edges
-            int oc[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int ox = (dir ? lx + h : lx + side) - mesh, oy = (dir ? ly + side : ly + h) - mesh;
-                oc[h] = oy * W + ox;
-            }
-            double dmax[K1];
-#pragma unroll
-            for (int m = 0; m < K1; ++m) dmax[m] = 0.0;
-#pragma unroll 1
-            for (int q = 0; q < NC; ++q) {
-                const double sg = st->sig[mesh][q];
-                const double isq = sg != 0.0 ? 1.0 / sg : 0.0;
-                // traces restricted to the edge, by normal derivative order:
-                // own at the edge (normal coordinate +-1), other at its centre line (0)
-                double ro[K1][K1], rt[2][K1][K1];
-#pragma unroll
-                for (int dn = 0; dn < K1; ++dn)
-#pragma unroll
-                    for (int t = 0; t < K1; ++t) {
-                        double so = 0.0, s0 = 0.0, s1 = 0.0;
-#pragma unroll
-                        for (int n = 0; n < K1; ++n) {
-                            const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
-                            const double ev = edge_val(tb.e1[dn][n], n, dn, side);
-                            so += own[ent * NCELL + cell] * ev;
-                            s0 += oth[ent * NCELL + oc[0]] * tb.e0[dn][n];
-                            s1 += oth[ent * NCELL + oc[1]] * tb.e0[dn][n];
-                        }
-                        ro[dn][t] = so;
-                        rt[0][dn][t] = s0;
-                        rt[1][dn][t] = s1;
-                    }
-#pragma unroll
-                for (int m = 0; m < K1; ++m) {
-                    double mean = 0.0;
-#pragma unroll
-                    for (int h = 0; h < 2; ++h)
-#pragma unroll
-                        for (int g = 0; g < Q; ++g) {
-                            double ss = 0.0;
-                            double scn = 1.0;
-#pragma unroll
-                            for (int dn = 0; dn <= m; ++dn) {
-                                const int dt = m - dn;
-                                double sct = scn;
-#pragma unroll
-                                for (int j = 0; j < dt; ++j) sct *= 2.0 / ht;
-                                double vo = 0.0, vt = 0.0;
-#pragma unroll
-                                for (int t = 0; t < K1; ++t) {
-                                    vo += ro[dn][t] * tb.own[dt][h][g][t];
-                                    vt += rt[h][dn][t] * tb.nb[dt][h][g][t];
-                                }
-                                const double d = sct * (vo - vt);
-                                ss += d * d;
-                                scn *= 2.0 / hn;
-                            }
-                            mean += 0.25 * tb.w[g] * sqrt(ss);
-                        }
-                    double hm = 1.0;                      // h_e^(m-1)
-                    if (m == 0) hm = 1.0 / hn;
-#pragma unroll
-                    for (int j = 1; j < m; ++j) hm *= hn;
-                    // sum over the four edges, divide by sigma, max over components
-                    dmax[m] = fmax(dmax[m], quad_sum(beta * tb.cdel[m] * hm * mean) * isq);
-                }
-            }
-            double S = 0.0;
-#pragma unroll
-            for (int m = 0; m < K1; ++m) {
-                S += dmax[m];
-                if (m >= 1 && lane4 == m - 1) fac[(mesh * K + (m - 1)) * NCELL + cell] = exp(-tau * S);
-            }
+            for (int j = 0; j < K; ++j) fac[(fmesh * K + j) * NCELL + fcell] = fj[j];
         }
         __syncthreads();
-        // damp: mode (a, b) != (0, 0) by the factor of total degree min(a + b, K)
+        // mode (a, b) != (0, 0) takes the factor of total degree min(a + b, K)
         for (int e = tid; e < NDAMP * NE; e += NT) {
             const int cs = e % NDAMP, ent = e / NDAMP;
             const int mesh = cs / ND1, rr = cs % ND1;
             const int cell = (rr / (TX + 1) + mesh) * W + rr % (TX + 1) + mesh;
-            const int ab = ent % (K1 * K1), da = ab / K1, db = ab % K1;
-            const int deg = da + db;
-            if (deg > 0) {
-                const int j = (deg < K ? deg : K) - 1;
-                tile[(mesh * NE + ent) * NCELL + cell] *= fac[(mesh * K + j) * NCELL + cell];
-            }
+            const int ab = ent % (K1 * K1), deg = ab / K1 + ab % K1;
+            if (deg > 0) tile[(mesh * NE + ent) * NCELL + cell] *= fac[(mesh * K + (deg < K ? deg : K) - 1) * NCELL + cell];
         }
-        __syncthreads();
     }
+    __syncthreads();
 
     // ---- owned cells: quad lanes per cell
     const int cs = tid >> 2;
@@ -365,7 +318,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
     const int gx = i0 + lx - 1, gy = j0 + ly - 1;
     const bool valid = gx < a.nx && gy < a.ny;
     const long long gofs = (long long)gy * a.nx + gx;
-    double *town = tile + mesh * NE * NCELL;
+    const double *town = tile + mesh * NE * NCELL;
 
     if (a.mode == M2_FINAL) {
         double *dst = mesh == 0 ? a.outC : a.outD;
@@ -373,132 +326,256 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
             for (int e = lane4; e < NE; e += 4) dst[e * a.plane + gofs] = town[e * NCELL + cell];
         return;
     }
-
-    // The statistics below take, per lane, component cq of this cell: the
-    // lane's own component when there are four lanes per component set
-    // (Euler), component 0 otherwise.
-    constexpr bool LANE_COMP = NC == 4;
-    const int cq = LANE_COMP ? lane4 : 0;
-    double cst[K1][K1];
-
-    if (a.mode == M2_STAGE) {
-        if (a.write_u && valid) {
-            double *UM = mesh == 0 ? a.UC : a.UD;
-            for (int e = lane4; e < NE; e += 4) UM[e * a.plane + gofs] = town[e * NCELL + cell];
+    if (a.write_u && valid) {
+        double *UM = mesh == 0 ? a.UC : a.UD;
+        for (int e = lane4; e < NE; e += 4) UM[e * a.plane + gofs] = town[e * NCELL + cell];
+    }
+    const double *toth = tile + (1 - mesh) * NE * NCELL;
+    const double tau = st->tau, itm = 1.0 / st->tau_max;
+    const double hx = a.hx, hy = a.hy;
+    const double *UM = mesh == 0 ? a.UC : a.UD;
+    double *OM = mesh == 0 ? a.outC : a.outD;
+    bool finite = true;
+    if constexpr (NC == 4) {
+        // lane q accumulates component q over all quadrants and edges; the
+        // quad shares the point values of w so every lane can form its flux
+        const int q = lane4;
+        double Rq[K1][K1];
+#pragma unroll
+        for (int i = 0; i < K1; ++i)
+#pragma unroll
+            for (int j = 0; j < K1; ++j) Rq[i][j] = 0.0;
+        const double gm1 = a.fp.gamma - 1.0;
+        // coupling and volume, quadrant (sx, sy)
+#pragma unroll 1
+        for (int qd = 0; qd < 4; ++qd) {
+            const int sx = qd & 1, sy = qd >> 1;
+            const int oc = (ly + sy - mesh) * W + (lx + sx - mesh);
+            double d[K1][K1];
+#pragma unroll
+            for (int c = 0; c < K1; ++c)
+#pragma unroll
+                for (int e = 0; e < K1; ++e) d[c][e] = toth[((q * K1 + c) * K1 + e) * NCELL + oc];
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                double cx[K1];
+#pragma unroll
+                for (int e = 0; e < K1; ++e) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int c = 0; c < K1; ++c) t += d[c][e] * tb.nb[0][sx][p][c];
+                    cx[e] = t;
+                }
+                double A[K1], B[K1];
+#pragma unroll
+                for (int j = 0; j < K1; ++j) A[j] = B[j] = 0.0;
+#pragma unroll
+                for (int g = 0; g < Q; ++g) {
+                    double wq = 0.0;
+#pragma unroll
+                    for (int e = 0; e < K1; ++e) wq += cx[e] * tb.nb[0][sy][g][e];
+                    const double w0 = dpp_d<0x00>(wq, wq), w1 = dpp_d<0x55>(wq, wq);
+                    const double w2 = dpp_d<0xAA>(wq, wq), w3 = dpp_d<0xFF>(wq, wq);
+                    const double ir = 1.0 / w0, u = w1 * ir, v = w2 * ir;
+                    const double pr = gm1 * (w3 - 0.5 * (w1 * u + w2 * v));
+                    const double base = q == 3 ? w3 + pr : wq;
+                    const double f1 = base * u + (q == 1 ? pr : 0.0);
+                    const double f2 = base * v + (q == 2 ? pr : 0.0);
+#pragma unroll
+                    for (int j = 0; j < K1; ++j) {
+                        A[j] += tb.w[g] * (wq * itm * tb.own[0][sy][g][j] + (2.0 / hy) * f2 * tb.own[1][sy][g][j]);
+                        B[j] += tb.w[g] * f1 * tb.own[0][sy][g][j];
+                    }
+                }
+                const double wp = hx * hy / 16.0 * tb.w[p];
+#pragma unroll
+                for (int i = 0; i < K1; ++i)
+#pragma unroll
+                    for (int j = 0; j < K1; ++j)
+                        Rq[i][j] += wp * (tb.own[0][sx][p][i] * A[j] + (2.0 / hx) * tb.own[1][sx][p][i] * B[j]);
+            }
         }
-        const double *toth = tile + (1 - mesh) * NE * NCELL;
-        const double tau = st->tau, itm = 1.0 / st->tau_max;
-        const double hx = a.hx, hy = a.hy;
-        const double *UM = mesh == 0 ? a.UC : a.UD;
-        double *OM = mesh == 0 ? a.outC : a.outD;
-        bool finite = true;
-        if constexpr (LANE_COMP) {
-            // lane q accumulates component q over all quadrants and edges; the
-            // quad shares the point values of w so every lane can form its flux
-            const int q = lane4;
-            double Rq[K1][K1];
+        // edges: (dir, side) = W, E (f_1 on vertical centre lines), S, N (f_2)
+#pragma unroll 1
+        for (int ed = 0; ed < 4; ++ed) {
+            const int dir = ed >> 1, side = ed & 1;
+            const double ht = dir ? hx : hy, sgn = side ? 1.0 : -1.0;
+            double Y[K1];
+#pragma unroll
+            for (int t = 0; t < K1; ++t) Y[t] = 0.0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ox = (dir ? lx + h : lx + side) - mesh, oy = (dir ? ly + side : ly + h) - mesh;
+                const int oc = oy * W + ox;
+                double r[K1];
+#pragma unroll
+                for (int t = 0; t < K1; ++t) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int n = 0; n < K1; ++n) {
+                        const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
+                        sum += toth[ent * NCELL + oc] * tb.e0[0][n];
+                    }
+                    r[t] = sum;
+                }
+#pragma unroll
+                for (int g = 0; g < Q; ++g) {
+                    double wq = 0.0;
+#pragma unroll
+                    for (int t = 0; t < K1; ++t) wq += r[t] * tb.nb[0][h][g][t];
+                    const double w0 = dpp_d<0x00>(wq, wq), w1 = dpp_d<0x55>(wq, wq);
+                    const double w2 = dpp_d<0xAA>(wq, wq), w3 = dpp_d<0xFF>(wq, wq);
+                    const double ir = 1.0 / w0, un = (dir ? w2 : w1) * ir;
+                    const double pr = gm1 * (w3 - 0.5 * (w1 * w1 + w2 * w2) * ir);
+                    const double base = q == 3 ? w3 + pr : wq;
+                    const double fn = base * un + (q == 1 + dir ? pr : 0.0);
+#pragma unroll
+                    for (int t = 0; t < K1; ++t) Y[t] += tb.w[g] * fn * tb.own[0][h][g][t];
+                }
+            }
+#pragma unroll
+            for (int n = 0; n < K1; ++n)
+#pragma unroll
+                for (int t = 0; t < K1; ++t) {
+                    const double x = sgn * 0.25 * ht * edge_val(1.0, n, 0, side) * Y[t];
+                    if (dir) Rq[t][n] -= x;
+                    else Rq[n][t] -= x;
+                }
+        }
+        // own part of the coupling, mass inverse, SSP-RK3
+#pragma unroll
+        for (int i = 0; i < K1; ++i)
+#pragma unroll
+            for (int j = 0; j < K1; ++j) {
+                const int e = (q * K1 + i) * K1 + j;
+                const double mass = hx * hy / ((2.0 * i + 1.0) * (2.0 * j + 1.0));
+                const double s0 = town[e * NCELL + cell];
+                const double Lv = (Rq[i][j] - mass * itm * s0) / mass;
+                const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
+                const double v = s0 + tau * Lv;
+                const double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
+                finite = finite && isfinite(o);
+                if (valid) OM[e * a.plane + gofs] = o;
+            }
+    } else {
+        // one component: lane t takes quadrant t and edge t, the quad sums
+        double R[NC][K1][K1];
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
 #pragma unroll
             for (int i = 0; i < K1; ++i)
 #pragma unroll
-                for (int j = 0; j < K1; ++j) Rq[i][j] = 0.0;
-            const double gm1 = a.fp.gamma - 1.0;
-            // coupling and volume, quadrant (sx, sy)
-#pragma unroll 1
-            for (int qd = 0; qd < 4; ++qd) {
-                    const int sx = qd & 1, sy = qd >> 1;
-                    const int oc = (ly + sy - mesh) * W + (lx + sx - mesh);
-                    double d[K1][K1];
+                for (int j = 0; j < K1; ++j) R[q][i][j] = 0.0;
+        {
+            const int sx = lane4 & 1, sy = lane4 >> 1;
+            const int oc = (ly + sy - mesh) * W + (lx + sx - mesh);
 #pragma unroll
-                    for (int c = 0; c < K1; ++c)
+            for (int p = 0; p < Q; ++p) {
+                double cx[NC][K1];
 #pragma unroll
-                        for (int e = 0; e < K1; ++e) d[c][e] = toth[((q * K1 + c) * K1 + e) * NCELL + oc];
+                for (int q = 0; q < NC; ++q)
 #pragma unroll
-                    for (int p = 0; p < Q; ++p) {
-                        double cx[K1];
+                    for (int d = 0; d < K1; ++d) {
+                        double sum = 0.0;
 #pragma unroll
-                        for (int e = 0; e < K1; ++e) {
-                            double t = 0.0;
-#pragma unroll
-                            for (int c = 0; c < K1; ++c) t += d[c][e] * tb.nb[0][sx][p][c];
-                            cx[e] = t;
-                        }
-                        double A[K1], B[K1];
-#pragma unroll
-                        for (int j = 0; j < K1; ++j) A[j] = B[j] = 0.0;
-#pragma unroll
-                        for (int g = 0; g < Q; ++g) {
-                            double wq = 0.0;
-#pragma unroll
-                            for (int e = 0; e < K1; ++e) wq += cx[e] * tb.nb[0][sy][g][e];
-                            const double w0 = dpp_d<0x00>(wq, wq), w1 = dpp_d<0x55>(wq, wq);
-                            const double w2 = dpp_d<0xAA>(wq, wq), w3 = dpp_d<0xFF>(wq, wq);
-                            const double ir = 1.0 / w0, u = w1 * ir, v = w2 * ir;
-                            const double pr = gm1 * (w3 - 0.5 * (w1 * u + w2 * v));
-                            const double base = q == 3 ? w3 + pr : wq;
-                            const double f1 = base * u + (q == 1 ? pr : 0.0);
-                            const double f2 = base * v + (q == 2 ? pr : 0.0);
-#pragma unroll
-                            for (int j = 0; j < K1; ++j) {
-                                A[j] += tb.w[g] * (wq * itm * tb.own[0][sy][g][j] + (2.0 / hy) * f2 * tb.own[1][sy][g][j]);
-                                B[j] += tb.w[g] * f1 * tb.own[0][sy][g][j];
-                            }
-                        }
-                        const double wp = hx * hy / 16.0 * tb.w[p];
-#pragma unroll
-                        for (int i = 0; i < K1; ++i)
-#pragma unroll
-                            for (int j = 0; j < K1; ++j)
-                                Rq[i][j] += wp * (tb.own[0][sx][p][i] * A[j] + (2.0 / hx) * tb.own[1][sx][p][i] * B[j]);
+                        for (int c = 0; c < K1; ++c)
+                            sum += toth[((q * K1 + c) * K1 + d) * NCELL + oc] * (sx ? tb.nb[0][1][p][c] : tb.nb[0][0][p][c]);
+                        cx[q][d] = sum;
                     }
-                }
-            // edges: (dir, side) = W, E (f_1 on vertical centre lines), S, N (f_2)
-#pragma unroll 1
-            for (int ed = 0; ed < 4; ++ed) {
-                    const int dir = ed >> 1, side = ed & 1;
-                    const double ht = dir ? hx : hy, sgn = side ? 1.0 : -1.0;
-                    double Y[K1];
+                double A[NC][K1], B[NC][K1];
 #pragma unroll
-                    for (int t = 0; t < K1; ++t) Y[t] = 0.0;
+                for (int q = 0; q < NC; ++q)
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int ox = (dir ? lx + h : lx + side) - mesh, oy = (dir ? ly + side : ly + h) - mesh;
-                        const int oc = oy * W + ox;
-                        double r[K1];
+                    for (int j = 0; j < K1; ++j) A[q][j] = B[q][j] = 0.0;
 #pragma unroll
-                        for (int t = 0; t < K1; ++t) {
-                            double sum = 0.0;
+                for (int g = 0; g < Q; ++g) {
+                    double w[NC], f1[NC], f2[NC];
 #pragma unroll
-                            for (int n = 0; n < K1; ++n) {
-                                const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
-                                sum += toth[ent * NCELL + oc] * tb.e0[0][n];
-                            }
-                            r[t] = sum;
-                        }
+                    for (int q = 0; q < NC; ++q) {
+                        double sum = 0.0;
 #pragma unroll
-                        for (int g = 0; g < Q; ++g) {
-                            double wq = 0.0;
-#pragma unroll
-                            for (int t = 0; t < K1; ++t) wq += r[t] * tb.nb[0][h][g][t];
-                            const double w0 = dpp_d<0x00>(wq, wq), w1 = dpp_d<0x55>(wq, wq);
-                            const double w2 = dpp_d<0xAA>(wq, wq), w3 = dpp_d<0xFF>(wq, wq);
-                            const double ir = 1.0 / w0, un = (dir ? w2 : w1) * ir;
-                            const double pr = gm1 * (w3 - 0.5 * (w1 * w1 + w2 * w2) * ir);
-                            const double base = q == 3 ? w3 + pr : wq;
-                            const double fn = base * un + (q == 1 + dir ? pr : 0.0);
-#pragma unroll
-                            for (int t = 0; t < K1; ++t) Y[t] += tb.w[g] * fn * tb.own[0][h][g][t];
-                        }
+                        for (int d = 0; d < K1; ++d) sum += cx[q][d] * (sy ? tb.nb[0][1][g][d] : tb.nb[0][0][g][d]);
+                        w[q] = sum;
                     }
+                    F::f(0, w, f1, a.fp);
+                    F::f(1, w, f2, a.fp);
 #pragma unroll
-                    for (int n = 0; n < K1; ++n)
+                    for (int q = 0; q < NC; ++q)
 #pragma unroll
-                        for (int t = 0; t < K1; ++t) {
-                            const double x = sgn * 0.25 * ht * edge_val(1.0, n, 0, side) * Y[t];
-                            if (dir) Rq[t][n] -= x;
-                            else Rq[n][t] -= x;
+                        for (int j = 0; j < K1; ++j) {
+                            const double pb = sy ? tb.own[0][1][g][j] : tb.own[0][0][g][j];
+                            const double dpb = sy ? tb.own[1][1][g][j] : tb.own[1][0][g][j];
+                            A[q][j] += tb.w[g] * (w[q] * itm * pb + (2.0 / hy) * f2[q] * dpb);
+                            B[q][j] += tb.w[g] * f1[q] * pb;
                         }
                 }
-            // own part of the coupling, mass inverse, SSP-RK3
+                const double wp = hx * hy / 16.0 * tb.w[p];
+#pragma unroll
+                for (int i = 0; i < K1; ++i) {
+                    const double pa = sx ? tb.own[0][1][p][i] : tb.own[0][0][p][i];
+                    const double dpa = sx ? tb.own[1][1][p][i] : tb.own[1][0][p][i];
+#pragma unroll
+                    for (int q = 0; q < NC; ++q)
+#pragma unroll
+                        for (int j = 0; j < K1; ++j) R[q][i][j] += wp * (pa * A[q][j] + (2.0 / hx) * dpa * B[q][j]);
+                }
+            }
+        }
+        {
+            const int dir = lane4 >> 1, side = lane4 & 1;
+            const double ht = dir ? hx : hy, sgn = side ? 1.0 : -1.0;
+            double Y[NC][K1];
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int t = 0; t < K1; ++t) Y[q][t] = 0.0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ox = (dir ? lx + h : lx + side) - mesh, oy = (dir ? ly + side : ly + h) - mesh;
+                const int oc = oy * W + ox;
+                double r[NC][K1];
+#pragma unroll
+                for (int q = 0; q < NC; ++q)
+#pragma unroll
+                    for (int t = 0; t < K1; ++t) {
+                        double sum = 0.0;
+#pragma unroll
+                        for (int n = 0; n < K1; ++n) {
+                            const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
+                            sum += toth[ent * NCELL + oc] * tb.e0[0][n];
+                        }
+                        r[q][t] = sum;
+                    }
+#pragma unroll
+                for (int g = 0; g < Q; ++g) {
+                    double w[NC], fn[NC];
+#pragma unroll
+                    for (int q = 0; q < NC; ++q) {
+                        double sum = 0.0;
+#pragma unroll
+                        for (int t = 0; t < K1; ++t) sum += r[q][t] * tb.nb[0][h][g][t];
+                        w[q] = sum;
+                    }
+                    F::f(dir, w, fn, a.fp);
+#pragma unroll
+                    for (int q = 0; q < NC; ++q)
+#pragma unroll
+                        for (int t = 0; t < K1; ++t) Y[q][t] += tb.w[g] * fn[q] * tb.own[0][h][g][t];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int i = 0; i < K1; ++i)
+#pragma unroll
+                    for (int j = 0; j < K1; ++j) {
+                        const double x_ij = sgn * 0.25 * ht * edge_val(1.0, i, 0, side) * Y[q][j];
+                        const double x_ji = sgn * 0.25 * ht * edge_val(1.0, j, 0, side) * Y[q][i];
+                        R[q][i][j] -= dir ? x_ji : x_ij;
+                    }
+        }
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
 #pragma unroll
             for (int i = 0; i < K1; ++i)
 #pragma unroll
@@ -506,195 +583,138 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                     const int e = (q * K1 + i) * K1 + j;
                     const double mass = hx * hy / ((2.0 * i + 1.0) * (2.0 * j + 1.0));
                     const double s0 = town[e * NCELL + cell];
-                    const double Lv = (Rq[i][j] - mass * itm * s0) / mass;
-                    const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
-                    const double v = s0 + tau * Lv;
-                    const double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
-                    cst[i][j] = o;
-                    finite = finite && isfinite(o);
-                    if (valid) OM[e * a.plane + gofs] = o;
-                }
-        } else {
-            // one component: lane t takes quadrant t and edge t, the quad sums
-            double R[NC][K1][K1];
-#pragma unroll
-            for (int q = 0; q < NC; ++q)
-#pragma unroll
-                for (int i = 0; i < K1; ++i)
-#pragma unroll
-                    for (int j = 0; j < K1; ++j) R[q][i][j] = 0.0;
-            {
-                const int sx = lane4 & 1, sy = lane4 >> 1;
-                const int oc = (ly + sy - mesh) * W + (lx + sx - mesh);
-#pragma unroll
-                for (int p = 0; p < Q; ++p) {
-                    double cx[NC][K1];
-#pragma unroll
-                    for (int q = 0; q < NC; ++q)
-#pragma unroll
-                        for (int d = 0; d < K1; ++d) {
-                            double sum = 0.0;
-#pragma unroll
-                            for (int c = 0; c < K1; ++c)
-                                sum += toth[((q * K1 + c) * K1 + d) * NCELL + oc] * (sx ? tb.nb[0][1][p][c] : tb.nb[0][0][p][c]);
-                            cx[q][d] = sum;
-                        }
-                    double A[NC][K1], B[NC][K1];
-#pragma unroll
-                    for (int q = 0; q < NC; ++q)
-#pragma unroll
-                        for (int j = 0; j < K1; ++j) A[q][j] = B[q][j] = 0.0;
-#pragma unroll
-                    for (int g = 0; g < Q; ++g) {
-                        double w[NC], f1[NC], f2[NC];
-#pragma unroll
-                        for (int q = 0; q < NC; ++q) {
-                            double sum = 0.0;
-#pragma unroll
-                            for (int d = 0; d < K1; ++d) sum += cx[q][d] * (sy ? tb.nb[0][1][g][d] : tb.nb[0][0][g][d]);
-                            w[q] = sum;
-                        }
-                        F::f(0, w, f1, a.fp);
-                        F::f(1, w, f2, a.fp);
-#pragma unroll
-                        for (int q = 0; q < NC; ++q)
-#pragma unroll
-                            for (int j = 0; j < K1; ++j) {
-                                const double pb = sy ? tb.own[0][1][g][j] : tb.own[0][0][g][j];
-                                const double dpb = sy ? tb.own[1][1][g][j] : tb.own[1][0][g][j];
-                                A[q][j] += tb.w[g] * (w[q] * itm * pb + (2.0 / hy) * f2[q] * dpb);
-                                B[q][j] += tb.w[g] * f1[q] * pb;
-                            }
-                    }
-                    const double wp = hx * hy / 16.0 * tb.w[p];
-#pragma unroll
-                    for (int i = 0; i < K1; ++i) {
-                        const double pa = sx ? tb.own[0][1][p][i] : tb.own[0][0][p][i];
-                        const double dpa = sx ? tb.own[1][1][p][i] : tb.own[1][0][p][i];
-#pragma unroll
-                        for (int q = 0; q < NC; ++q)
-#pragma unroll
-                            for (int j = 0; j < K1; ++j) R[q][i][j] += wp * (pa * A[q][j] + (2.0 / hx) * dpa * B[q][j]);
+                    const double Lv = (quad_sum(R[q][i][j]) - mass * itm * s0) / mass;
+                    if ((e & 3) == lane4) {
+                        const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
+                        const double v = s0 + tau * Lv;
+                        const double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
+                        finite = finite && isfinite(o);
+                        if (valid) OM[e * a.plane + gofs] = o;
                     }
                 }
-            }
-            {
-                const int dir = lane4 >> 1, side = lane4 & 1;
-                const double ht = dir ? hx : hy, sgn = side ? 1.0 : -1.0;
-                double Y[NC][K1];
+    }
+    if (valid && !finite) a.err[0] = 1;
+}
+
+// Damping numerators and statistics of a state (the undamped output of a
+// stage, or initial data): per owned cell and component q
+//   N^m_q = sum_{e in {W,E,S,N}} beta_{e,K} (2m+1) h_e^(m-1) / ((2k-1) m!)
+//           (1/|e|) int_e ( sum_{alpha1+alpha2=m} (d^alpha (u_K - w)_q)^2 )^(1/2) ds
+// (delta^m_K = max_q N^m_q / sigma_q once sigma is known, Sec. 2.2), with one
+// lane per edge; then the tile's partial statistics (sums of averages, sample
+// max / min per component, largest wave speeds) with one lane per component.
+template <int K, int FLUX, int TX, int TY>
+__global__ __launch_bounds__(8 * TX * TY) void k_delta2d(Stage2Args a) {
+    using F = Flux2D<FLUX>;
+    constexpr int NC = F::NC, K1 = K + 1, Q = K + 1, NE = NC * K1 * K1, NSP = 2 * K + 4;
+    constexpr int W = TX + 2, NCELL = W * (TY + 2), NT = 8 * TX * TY, NW = NT / WAVE;
+    constexpr int NR = nrow2<NC>();
+    constexpr Tab2<K> tb = make_tab2<K>();
+    __shared__ double tile[2 * NE * NCELL];
+    __shared__ double red[NW * NR];
+
+    const int tid = threadIdx.x, lane4 = tid & 3;
+    const int nt = a.ntx * a.nty, tileid = tile_of_block(nt);
+    const int i0 = (tileid % a.ntx) * TX, j0 = (tileid / a.ntx) * TY;
+    if (a.mode == M2_STAGE && a.st->done) return;
+    stage_tile2d<NE, TX, TY, NT>(tile, a.inC, a.inD, i0, j0, a.nx, a.ny, a.plane);
+    __syncthreads();
+
+    const int cs = tid >> 2;
+    const int mesh = cs / (TX * TY), rr = cs % (TX * TY);
+    const int lx = rr % TX + 1, ly = rr / TX + 1;
+    const int cell = ly * W + lx;
+    const int gx = i0 + lx - 1, gy = j0 + ly - 1;
+    const bool valid = gx < a.nx && gy < a.ny;
+    const long long gofs = (long long)gy * a.nx + gx;
+    const double *own = tile + mesh * NE * NCELL, *oth = tile + (1 - mesh) * NE * NCELL;
+    double ubar[NC];
 #pragma unroll
-                for (int q = 0; q < NC; ++q)
+    for (int q = 0; q < NC; ++q) ubar[q] = own[(q * K1 * K1) * NCELL + cell];
+
+    if (a.numC) {
+        const int dir = lane4 >> 1, side = lane4 & 1;
+        const double hn = dir ? a.hy : a.hx, ht = dir ? a.hx : a.hy;
+        const double beta = F::speed(dir, ubar, a.fp);
+        int oc[2];
 #pragma unroll
-                    for (int t = 0; t < K1; ++t) Y[q][t] = 0.0;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int ox = (dir ? lx + h : lx + side) - mesh, oy = (dir ? ly + side : ly + h) - mesh;
-                    const int oc = oy * W + ox;
-                    double r[NC][K1];
-#pragma unroll
-                    for (int q = 0; q < NC; ++q)
-#pragma unroll
-                        for (int t = 0; t < K1; ++t) {
-                            double sum = 0.0;
-#pragma unroll
-                            for (int n = 0; n < K1; ++n) {
-                                const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
-                                sum += toth[ent * NCELL + oc] * tb.e0[0][n];
-                            }
-                            r[q][t] = sum;
-                        }
-#pragma unroll
-                    for (int g = 0; g < Q; ++g) {
-                        double w[NC], fn[NC];
-#pragma unroll
-                        for (int q = 0; q < NC; ++q) {
-                            double sum = 0.0;
-#pragma unroll
-                            for (int t = 0; t < K1; ++t) sum += r[q][t] * tb.nb[0][h][g][t];
-                            w[q] = sum;
-                        }
-                        F::f(dir, w, fn, a.fp);
-#pragma unroll
-                        for (int q = 0; q < NC; ++q)
-#pragma unroll
-                            for (int t = 0; t < K1; ++t) Y[q][t] += tb.w[g] * fn[q] * tb.own[0][h][g][t];
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < NC; ++q)
-#pragma unroll
-                    for (int i = 0; i < K1; ++i)
-#pragma unroll
-                        for (int j = 0; j < K1; ++j) {
-                            const double x_ij = sgn * 0.25 * ht * edge_val(1.0, i, 0, side) * Y[q][j];
-                            const double x_ji = sgn * 0.25 * ht * edge_val(1.0, j, 0, side) * Y[q][i];
-                            R[q][i][j] -= dir ? x_ji : x_ij;
-                        }
-            }
-            double outv[(NE + 3) / 4];
-#pragma unroll
-            for (int q = 0; q < NC; ++q)
-#pragma unroll
-                for (int i = 0; i < K1; ++i)
-#pragma unroll
-                    for (int j = 0; j < K1; ++j) {
-                        const int e = (q * K1 + i) * K1 + j;
-                        const double mass = hx * hy / ((2.0 * i + 1.0) * (2.0 * j + 1.0));
-                        const double s0 = town[e * NCELL + cell];
-                        const double Lv = (quad_sum(R[q][i][j]) - mass * itm * s0) / mass;
-                        if ((e & 3) == lane4) {
-                            const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
-                            const double v = s0 + tau * Lv;
-                            const double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
-                            outv[e >> 2] = o;
-                            finite = finite && isfinite(o);
-                        }
-                    }
-            if (valid) {
-#pragma unroll
-                for (int e4 = 0; e4 < (NE + 3) / 4; ++e4) {
-                    const int e = e4 * 4 + lane4;
-                    if (e < NE) OM[e * a.plane + gofs] = outv[e4];
-                }
-            }
-            __syncthreads();                 // every lane has read the tile: reuse it for the output
-#pragma unroll
-            for (int e4 = 0; e4 < (NE + 3) / 4; ++e4) {
-                const int e = e4 * 4 + lane4;
-                if (e < NE) town[e * NCELL + cell] = outv[e4];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < K1; ++i)
-#pragma unroll
-                for (int j = 0; j < K1; ++j) cst[i][j] = town[((cq * K1 + i) * K1 + j) * NCELL + cell];
+        for (int h = 0; h < 2; ++h) {
+            const int ox = (dir ? lx + h : lx + side) - mesh, oy = (dir ? ly + side : ly + h) - mesh;
+            oc[h] = oy * W + ox;
         }
-        if (valid && !finite) a.err[0] = 1;
-    } else {
+        double* N = mesh == 0 ? a.numC : a.numD;
+#pragma unroll 1
+        for (int q = 0; q < NC; ++q) {
+            // traces restricted to the edge, by normal derivative order:
+            // own at the edge (normal coordinate +-1), other at its centre line (0)
+            double ro[K1][K1], rt[2][K1][K1];
+#pragma unroll
+            for (int dn = 0; dn < K1; ++dn)
+#pragma unroll
+                for (int t = 0; t < K1; ++t) {
+                    double so = 0.0, s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                    for (int n = 0; n < K1; ++n) {
+                        const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
+                        const double ev = edge_val(tb.e1[dn][n], n, dn, side);
+                        so += own[ent * NCELL + cell] * ev;
+                        s0 += oth[ent * NCELL + oc[0]] * tb.e0[dn][n];
+                        s1 += oth[ent * NCELL + oc[1]] * tb.e0[dn][n];
+                    }
+                    ro[dn][t] = so;
+                    rt[0][dn][t] = s0;
+                    rt[1][dn][t] = s1;
+                }
+#pragma unroll
+            for (int m = 0; m < K1; ++m) {
+                double mean = 0.0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int g = 0; g < Q; ++g) {
+                        double ss = 0.0;
+                        double scn = 1.0;
+#pragma unroll
+                        for (int dn = 0; dn <= m; ++dn) {
+                            const int dt = m - dn;
+                            double sct = scn;
+#pragma unroll
+                            for (int j = 0; j < dt; ++j) sct *= 2.0 / ht;
+                            double vo = 0.0, vt = 0.0;
+#pragma unroll
+                            for (int t = 0; t < K1; ++t) {
+                                vo += ro[dn][t] * tb.own[dt][h][g][t];
+                                vt += rt[h][dn][t] * tb.nb[dt][h][g][t];
+                            }
+                            const double d = sct * (vo - vt);
+                            ss += d * d;
+                            scn *= 2.0 / hn;
+                        }
+                        mean += 0.25 * tb.w[g] * sqrt(ss);
+                    }
+                double hm = 1.0;                          // h_e^(m-1)
+                if (m == 0) hm = 1.0 / hn;
+#pragma unroll
+                for (int j = 1; j < m; ++j) hm *= hn;
+                const double num = quad_sum(beta * tb.cdel[m] * hm * mean);
+                if (valid && lane4 == (m & 3)) N[(m * NC + q) * a.plane + gofs] = num;
+            }
+        }
+    }
+
+    // ---- partial statistics: component cq of this cell, all sample rows for
+    // a component lane (Euler), rows i = lane (mod 4) for one component
+    constexpr bool LANE_COMP = NC == 4;
+    const int cq = LANE_COMP ? lane4 : 0;
+    double vals[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) vals[j] = j < 2 * NC * 3 ? stat_identity(j % 3) : -INFINITY;
+    if (valid) {
+        double cst[K1][K1];
 #pragma unroll
         for (int i = 0; i < K1; ++i)
 #pragma unroll
-            for (int j = 0; j < K1; ++j) cst[i][j] = town[((cq * K1 + i) * K1 + j) * NCELL + cell];
-    }
-
-    // ---- partial statistics of the output (stage) or of the input (stats mode)
-    double ubar[NC];
-    if constexpr (LANE_COMP) {
-        const double c0 = cst[0][0];
-        ubar[0] = dpp_d<0x00>(c0, c0);
-        ubar[1] = dpp_d<0x55>(c0, c0);
-        ubar[2] = dpp_d<0xAA>(c0, c0);
-        ubar[3] = dpp_d<0xFF>(c0, c0);
-    } else {
-        ubar[0] = cst[0][0];
-    }
-    double vals[NR];
-#pragma unroll
-    for (int j = 0; j < NR; ++j)
-        vals[j] = j < 2 * NC * 3 ? stat_identity(j % 3) : -INFINITY;
-    if (valid) {
-        // sample values of component cq: rows i of the S x S grid (all rows
-        // for a component lane, rows i = lane (mod 4) for one component)
+            for (int j = 0; j < K1; ++j) cst[i][j] = own[((cq * K1 + i) * K1 + j) * NCELL + cell];
         double mx = -INFINITY, mn = INFINITY;
 #pragma unroll
         for (int i = 0; i < NSP; ++i) {
@@ -876,10 +896,12 @@ struct Ext2D {
     double hx, hy, cfl;
     FPar2 fp;
     long long S1;                // doubles of one mesh
+    long long SN;                // damping numerators of one mesh: (k+1) nc nx ny
     double *B[2] = {nullptr, nullptr};      // stage states, both meshes each
+    double *num[2] = {nullptr, nullptr};    // damping numerators of B[i], both meshes each
     double *U = nullptr;
     double *part[2] = {nullptr, nullptr};
-    double *fold = nullptr;      // [row][FOLD2_MAXB] first-level partials
+    double *fold = nullptr;      // [row][nfold] first-level partials
     int nfold = 1, fold_per = 1;
     Stats2 *st = nullptr;
     Stats2 *st_h = nullptr;      // pinned
@@ -894,16 +916,22 @@ Ext2D *ext(oecdg_handle *h) { return static_cast<Ext2D *>(handle_ext2d(h)); }
         if (e_ != hipSuccess) return handle_fail((h), OECDG_EHIP, hipGetErrorString(e_));                     \
     } while (0)
 
-template <int K, int FLUX>
-void *stage_kernel() {
-    return (void *)k_stage2d<K, FLUX, TX2, TY2>;
-}
-
-hipError_t launch_stage2d(const Ext2D &x, const Stage2Args &a, hipStream_t s) {
-    void *fn = x.flux == OECDG_FLUX_EULER ? stage_kernel<2, OECDG_FLUX_EULER>() : stage_kernel<2, OECDG_FLUX_ADVECTION>();
+hipError_t launch_tile(void *fn, const Ext2D &x, const Stage2Args &a, hipStream_t s) {
     Stage2Args copy = a;
     void *args[] = {&copy};
     return hipLaunchKernel(fn, dim3(x.ntiles), dim3(8 * TX2 * TY2), args, 0, s);
+}
+
+hipError_t launch_stage2d(const Ext2D &x, const Stage2Args &a, hipStream_t s) {
+    void *fn = x.flux == OECDG_FLUX_EULER ? (void *)k_stage2d<2, OECDG_FLUX_EULER, TX2, TY2>
+                                          : (void *)k_stage2d<2, OECDG_FLUX_ADVECTION, TX2, TY2>;
+    return launch_tile(fn, x, a, s);
+}
+
+hipError_t launch_delta2d(const Ext2D &x, const Stage2Args &a, hipStream_t s) {
+    void *fn = x.flux == OECDG_FLUX_EULER ? (void *)k_delta2d<2, OECDG_FLUX_EULER, TX2, TY2>
+                                          : (void *)k_delta2d<2, OECDG_FLUX_ADVECTION, TX2, TY2>;
+    return launch_tile(fn, x, a, s);
 }
 
 // Fold r.part (per-tile partials) into the global scalars: first level into
@@ -956,6 +984,21 @@ Red2Args red_args(const Ext2D &x, const double *part, int mode) {
     return r;
 }
 
+// Damping numerators (when OE is on) and partial statistics of a state into
+// num[i] / part[i]; mode M2_STAGE skips the work once the run is done.
+hipError_t delta_of(const Ext2D &x, const double *uC, const double *uD, int i, int mode, hipStream_t s) {
+    Stage2Args a = stage_args(x);
+    a.mode = mode;
+    a.inC = uC;
+    a.inD = uD;
+    a.part = x.part[i];
+    if (x.oe && x.k > 0) {
+        a.numC = x.num[i];
+        a.numD = x.num[i] + x.SN;
+    }
+    return launch_delta2d(x, a, s);
+}
+
 int check2d(oecdg_handle *h, const Ext2D &x) {
     hipStream_t s = handle_stream(h);
     HIPCHK2(h, hipMemcpyAsync(x.err_h, x.err, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -996,12 +1039,14 @@ int create_2d(oecdg_handle *h, const oecdg_desc *d) {
     x->fp.b = d->flux_param[1];
     x->fp.gamma = d->flux_param[0];
     x->S1 = (long long)x->nc * (x->k + 1) * (x->k + 1) * x->nx * x->ny;
+    x->SN = (long long)x->nc * (x->k + 1) * x->nx * x->ny;
     const size_t nrow = x->nc == 4 ? nrow2<4>() : nrow2<1>();
-    HIPCHK2(h, hipMalloc(&x->B[0], sizeof(double) * 2 * x->S1));
-    HIPCHK2(h, hipMalloc(&x->B[1], sizeof(double) * 2 * x->S1));
+    for (int i = 0; i < 2; ++i) {
+        HIPCHK2(h, hipMalloc(&x->B[i], sizeof(double) * 2 * x->S1));
+        HIPCHK2(h, hipMalloc(&x->num[i], sizeof(double) * 2 * x->SN));
+        HIPCHK2(h, hipMalloc(&x->part[i], sizeof(double) * nrow * x->ntiles));
+    }
     HIPCHK2(h, hipMalloc(&x->U, sizeof(double) * 2 * x->S1));
-    HIPCHK2(h, hipMalloc(&x->part[0], sizeof(double) * nrow * x->ntiles));
-    HIPCHK2(h, hipMalloc(&x->part[1], sizeof(double) * nrow * x->ntiles));
     x->nfold = x->ntiles < FOLD2_MAXB ? x->ntiles : FOLD2_MAXB;
     x->fold_per = (x->ntiles + x->nfold - 1) / x->nfold;
     HIPCHK2(h, hipMalloc(&x->fold, sizeof(double) * nrow * x->nfold));
@@ -1017,6 +1062,7 @@ void destroy_2d(oecdg_handle *h) {
     if (!x) return;
     for (int i = 0; i < 2; ++i) {
         if (x->B[i]) (void)hipFree(x->B[i]);
+        if (x->num[i]) (void)hipFree(x->num[i]);
         if (x->part[i]) (void)hipFree(x->part[i]);
     }
     if (x->U) (void)hipFree(x->U);
@@ -1029,26 +1075,13 @@ void destroy_2d(oecdg_handle *h) {
     handle_ext2d(h) = nullptr;
 }
 
-// Statistics of a state (both meshes) into part[0], reduced with `mode`.
-static int stats_of(oecdg_handle *h, Ext2D &x, const double *uC, const double *uD, int mode) {
-    hipStream_t s = handle_stream(h);
-    Stage2Args a = stage_args(x);
-    a.mode = M2_STATS;
-    a.inC = uC;
-    a.inD = uD;
-    a.part = x.part[0];
-    HIPCHK2(h, launch_stage2d(x, a, s));
-    Red2Args r = red_args(x, x.part[0], mode);
-    HIPCHK2(h, launch_reduce2d(x, r, s));
-    return OECDG_OK;
-}
-
 int dt_2d(oecdg_handle *h, const double *uC, const double *uD, double *dt_out) {
     Ext2D &x = *ext(h);
-    int rc = reset2d(h, x);
-    if (rc == OECDG_OK) rc = stats_of(h, x, uC, uD, R2_STATS);
-    if (rc != OECDG_OK) return rc;
     hipStream_t s = handle_stream(h);
+    int rc = reset2d(h, x);
+    if (rc != OECDG_OK) return rc;
+    HIPCHK2(h, delta_of(x, uC, uD, 0, M2_FINAL, s));
+    HIPCHK2(h, launch_reduce2d(x, red_args(x, x.part[0], R2_STATS), s));
     HIPCHK2(h, hipMemcpyAsync(x.st_h, x.st, sizeof(Stats2), hipMemcpyDeviceToHost, s));
     HIPCHK2(h, hipStreamSynchronize(s));
     const double rate = x.st_h->bx / x.hx + x.st_h->by / x.hy;
@@ -1063,6 +1096,7 @@ int stage_2d(oecdg_handle *h, int stage, double dt, double tau_max, const double
     hipStream_t s = handle_stream(h);
     int rc = reset2d(h, x);
     if (rc != OECDG_OK) return rc;
+    // the step scalars only (the partials read here are discarded by mode)
     Red2Args r = red_args(x, x.part[1], R2_SINGLE);
     r.tau_o = dt;
     r.taumax_o = tau_max;
@@ -1079,15 +1113,16 @@ int stage_2d(oecdg_handle *h, int stage, double dt, double tau_max, const double
     a.UD = const_cast<double *>(uDn);
     a.outC = x.B[0];
     a.outD = x.B[0] + x.S1;
-    a.part = x.part[0];
     HIPCHK2(h, launch_stage2d(x, a, s));
-    Red2Args rf = red_args(x, x.part[0], R2_STAGE);
-    HIPCHK2(h, launch_reduce2d(x, rf, s));
+    HIPCHK2(h, delta_of(x, x.B[0], x.B[0] + x.S1, 0, M2_FINAL, s));
+    HIPCHK2(h, launch_reduce2d(x, red_args(x, x.part[0], R2_STAGE), s));
     Stage2Args f = stage_args(x);
     f.mode = M2_FINAL;
     f.damp = x.oe && x.k > 0;
     f.inC = x.B[0];
     f.inD = x.B[0] + x.S1;
+    f.numC = x.num[0];
+    f.numD = x.num[0] + x.SN;
     f.outC = uCo;
     f.outD = uDo;
     HIPCHK2(h, launch_stage2d(x, f, s));
@@ -1103,14 +1138,8 @@ int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
     if (rc != OECDG_OK) return rc;
     HIPCHK2(h, hipMemcpyAsync(x.B[0], uC, sizeof(double) * x.S1, hipMemcpyDeviceToDevice, s));
     HIPCHK2(h, hipMemcpyAsync(x.B[0] + x.S1, uD, sizeof(double) * x.S1, hipMemcpyDeviceToDevice, s));
-    {   // statistics of the initial data (wave speeds for the first step) into part[0]
-        Stage2Args a = stage_args(x);
-        a.mode = M2_STATS;
-        a.inC = x.B[0];
-        a.inD = x.B[0] + x.S1;
-        a.part = x.part[0];
-        HIPCHK2(h, launch_stage2d(x, a, s));
-    }
+    // statistics of the initial data (wave speeds for the first step) into part[0]
+    HIPCHK2(h, delta_of(x, x.B[0], x.B[0] + x.S1, 0, M2_FINAL, s));
     const int chunk = 16;
     long long n = 0;
     while (nsteps < 0 || n < nsteps) {
@@ -1118,7 +1147,8 @@ int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
         for (long long j = 0; j < m; ++j)
             for (int l = 0; l < 3; ++l) {
                 const long long g = 3 * (n + j) + l;
-                Red2Args r = red_args(x, x.part[g & 1], l == 0 ? R2_STEP : R2_STAGE);
+                const int ib = (int)(g & 1), ob = (int)((g + 1) & 1);
+                Red2Args r = red_args(x, x.part[ib], l == 0 ? R2_STEP : R2_STAGE);
                 r.t_end = t_end;
                 r.dt_fixed = dt_fixed;
                 HIPCHK2(h, launch_reduce2d(x, r, s));
@@ -1127,14 +1157,16 @@ int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
                 a.l = l;
                 a.damp = x.oe && x.k > 0 && !(n + j == 0 && l == 0);
                 a.write_u = l == 0;
-                a.inC = x.B[g & 1];
-                a.inD = x.B[g & 1] + x.S1;
-                a.outC = x.B[(g + 1) & 1];
-                a.outD = x.B[(g + 1) & 1] + x.S1;
+                a.inC = x.B[ib];
+                a.inD = x.B[ib] + x.S1;
+                a.numC = x.num[ib];
+                a.numD = x.num[ib] + x.SN;
+                a.outC = x.B[ob];
+                a.outD = x.B[ob] + x.S1;
                 a.UC = x.U;
                 a.UD = x.U + x.S1;
-                a.part = x.part[(g + 1) & 1];
                 HIPCHK2(h, launch_stage2d(x, a, s));
+                HIPCHK2(h, delta_of(x, x.B[ob], x.B[ob] + x.S1, ob, M2_STAGE, s));
             }
         n += m;
         HIPCHK2(h, hipMemcpyAsync(x.st_h, x.st, sizeof(Stats2), hipMemcpyDeviceToHost, s));
@@ -1142,14 +1174,17 @@ int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
         if (x.st_h->done) break;
     }
     const long long N = x.st_h->nexec + x.st_h->pending;   // executed steps
-    Red2Args r = red_args(x, x.part[N & 1], R2_FINAL);
+    const int fb = (int)(N & 1);
+    Red2Args r = red_args(x, x.part[fb], R2_FINAL);
     r.t_end = t_end;
     HIPCHK2(h, launch_reduce2d(x, r, s));
     Stage2Args f = stage_args(x);
     f.mode = M2_FINAL;
     f.damp = x.oe && x.k > 0 && N > 0;
-    f.inC = x.B[N & 1];
-    f.inD = x.B[N & 1] + x.S1;
+    f.inC = x.B[fb];
+    f.inD = x.B[fb] + x.S1;
+    f.numC = x.num[fb];
+    f.numD = x.num[fb] + x.SN;
     f.outC = uC;
     f.outD = uD;
     HIPCHK2(h, launch_stage2d(x, f, s));

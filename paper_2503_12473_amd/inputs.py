@@ -132,6 +132,9 @@ def project_2d(func, prob: Problem2D, nq: int = 8, chunk_rows: int = 64):
     xi, wi = _half_rule(nq)
     P = _legendre_table(prob.k, xi)
     norm = (2.0 * np.arange(prob.k + 1) + 1.0) / 2.0
+    K1 = prob.k + 1
+    # M[(g, h), (a, b)] = w_g w_h P_a(xi_g) P_b(xi_h) (2a+1)(2b+1)/4
+    M = np.einsum("ag,bh,g,h,a,b->ghab", P, P, wi, wi, norm, norm).reshape(-1, K1 * K1)
     hx, hy = prob.hx, prob.hy
     out = []
     for shift in (0.5, 0.0):                              # primal centres, dual centres
@@ -144,8 +147,10 @@ def project_2d(func, prob: Problem2D, nq: int = 8, chunk_rows: int = 64):
             Y = cy[:, None, None, None] + 0.5 * hy * xi[None, None, None, :]
             X, Y = np.broadcast_arrays(X, Y)              # [rows, nx, Gx, Gy]
             vals = np.asarray(func(X, Y), dtype=np.float64).reshape(prob.nc, *X.shape)
-            a = np.einsum("qyxgh,ag,bh,g,h->qabyx", vals, P, P, wi, wi, optimize=True)
-            res[:, :, :, j0:j1, :] = a * norm[None, :, None, None, None] * norm[None, None, :, None, None]
+            G = X.shape[2]
+            # one matrix product: point values [.., Gx*Gy] -> modes [.., a*b]
+            a = (vals.reshape(-1, G * G) @ M).reshape(prob.nc, j1 - j0, prob.nx, K1, K1)
+            res[:, :, :, j0:j1, :] = a.transpose(0, 3, 4, 1, 2)
         out.append(np.ascontiguousarray(res))
     return out[0], out[1]
 
@@ -250,11 +255,59 @@ def batch_instances(seed: int, count: int = 512, nmin=128, nmax=8192, kset=(1, 2
     return out
 
 
-def euler2d_quadrants(n: int, k: int, seed: int, gamma=GAMMA):
+def _project_quadrants_sine(prob: Problem2D, cst, sin_amp, nq: int = 8):
+    """Both meshes' projections of f(x, y) = cst[Q] + sin_amp[Q] sin(2 pi (x + y))
+    where Q is the domain quadrant (split at the middle of [xlo, xhi] x [ylo, yhi],
+    periodic) of the point; cst, sin_amp: [4, nc] in the order SW, SE, NW, NE.
+    The same Gauss rule as project_2d (nq points per direction on each quarter
+    of a cell), factorised with sin(a + b) = sin a cos b + cos a sin b, so it
+    costs O(cells) instead of O(cells * nq^2)."""
+    xi, wi = _half_rule(nq)
+    G = nq
+    P = _legendre_table(prob.k, xi)                           # [K1, 2G]
+    K1 = prob.k + 1
+    norm = (2.0 * np.arange(K1) + 1.0) / 2.0
+    Lx, Ly = prob.xhi - prob.xlo, prob.yhi - prob.ylo
+    out = []
+    for shift in (0.5, 0.0):                                  # primal centres, dual centres
+        cx = prob.xlo + (np.arange(prob.nx) + shift) * prob.hx
+        cy = prob.ylo + (np.arange(prob.ny) + shift) * prob.hy
+        res = np.zeros(prob.shape())
+        # per column / row and quarter side s: I[s][a] (constant), S[.., s, a], C[.., s, a]
+        def sums(c, h):
+            x = c[:, None] + 0.5 * h * xi[None, :]                # [n, 2G]
+            wP = (wi[None, :] * P)                                # [K1, 2G]
+            I = np.stack([wP[:, :G].sum(axis=1), wP[:, G:].sum(axis=1)]) * norm[None, :]
+            sn, cs = np.sin(2.0 * math.pi * x), np.cos(2.0 * math.pi * x)
+            S = np.stack([sn[:, :G] @ wP[:, :G].T, sn[:, G:] @ wP[:, G:].T], axis=1) * norm[None, None, :]
+            C = np.stack([cs[:, :G] @ wP[:, :G].T, cs[:, G:] @ wP[:, G:].T], axis=1) * norm[None, None, :]
+            mid = np.stack([c - 0.25 * h, c + 0.25 * h], axis=1)   # quarter centres [n, 2]
+            return I, S, C, mid
+        Ix, Sx, Cx, mx = sums(cx, prob.hx)
+        Iy, Sy, Cy, my = sums(cy, prob.hy)
+        qx = (np.mod(mx - prob.xlo, Lx) >= 0.5 * Lx).astype(np.int64)   # [nx, 2]
+        qy = (np.mod(my - prob.ylo, Ly) >= 0.5 * Ly).astype(np.int64)   # [ny, 2]
+        for sx in range(2):
+            for sy in range(2):
+                qd = qx[None, :, sx] + 2 * qy[:, sy, None]         # [ny, nx]
+                Cq = np.asarray(cst)[qd].transpose(2, 0, 1)        # [nc, ny, nx]
+                Sq = np.asarray(sin_amp)[qd].transpose(2, 0, 1)
+                for a in range(K1):
+                    for b in range(K1):
+                        res[:, a, b] += Cq * (Ix[sx, a] * Iy[sy, b])
+                        res[:, a, b] += Sq * (Cy[:, sy, b][:, None] * Sx[:, sx, a][None, :]
+                                              + Sy[:, sy, b][:, None] * Cx[:, sx, a][None, :])
+        out.append(np.ascontiguousarray(res))
+    return out[0], out[1]
+
+
+def euler2d_quadrants(n: int, k: int, seed: int, gamma=GAMMA, fast: bool = True):
     """2D Euler on [0,1]^2 periodic: rho = 1 + 0.2 sin(2 pi (x+y)) + rho_q and
     (u, v, p) = (u_q, v_q, p_q) on the four quadrants split at 0.5, with
     (rho_q, p_q) ~ U[0.2, 1] and u_q, v_q ~ U[-0.5, 0.5], drawn per quadrant in
-    the order SW, SE, NW, NE as (rho, p, u, v)."""
+    the order SW, SE, NW, NE as (rho, p, u, v).  The conserved variables are
+    affine in sin(2 pi (x+y)) on each quadrant; fast=True projects them with
+    the factorised rule, fast=False with the generic point-value projection."""
     rng = np.random.default_rng(seed)
     quads = []
     for _ in range(4):
@@ -263,6 +316,14 @@ def euler2d_quadrants(n: int, k: int, seed: int, gamma=GAMMA):
         quads.append((rq, pq, uq, vq))
     quads = np.asarray(quads)
     prob = Problem2D(k=k, nc=4, flux=FLUX_EULER, nx=n, ny=n, xlo=0.0, xhi=1.0, ylo=0.0, yhi=1.0, gamma=gamma)
+    if fast:
+        rq, pq, uq, vq = quads.T
+        r0 = 1.0 + rq
+        ke = uq * uq + vq * vq
+        cst = np.stack([r0, r0 * uq, r0 * vq, pq / (gamma - 1.0) + 0.5 * r0 * ke], axis=1)
+        amp = np.stack([0.2 + 0 * rq, 0.2 * uq, 0.2 * vq, 0.1 * ke], axis=1)
+        uC, uD = _project_quadrants_sine(prob, cst, amp)
+        return prob, uC, uD, quads
 
     def f(X, Y):
         xm = np.mod(X, 1.0)
