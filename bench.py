@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-form measurement")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D Euler measurement")
+    ap.add_argument("--e2d-steps", type=int, default=E2D_STEPS, help="steps of the 2D Euler measurement")
+    ap.add_argument("--e2d-repeats", type=int, default=3, help="timed repetitions of the 2D Euler measurement")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before the warm-up, copy a device buffer of this many MiB (profiler counter calibration)")
     return ap.parse_args()
@@ -69,6 +71,25 @@ def measured_traffic():
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return meta["traffic_bytes_per_launch"] if meta.get("source_sha256") == h.hexdigest() else None
+
+
+PROFILE2D_JSON = os.path.join(ROOT, "profiles", "k_stage2d_euler2d_q2_n1024.json")
+KERNEL2D_SOURCES = ["paper_2503_12473_amd/csrc/oecdg_2d.hip", "paper_2503_12473_amd/csrc/oecdg_tables.h",
+                    "paper_2503_12473_amd/csrc/oecdg_device.h"]
+
+
+def measured_traffic_2d():
+    """HBM bytes per 2D RK stage (k_stage2d + k_delta2d) from the committed
+    counter profile, or None if the kernel sources changed since."""
+    import hashlib
+    try:
+        meta = json.load(open(PROFILE2D_JSON))
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL2D_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return meta["traffic_bytes_per_stage"] if meta.get("source_sha256") == h.hexdigest() else None
 
 
 def batched_bench(k_fixed=None):
@@ -205,8 +226,9 @@ def euler2d_bench(repeats: int = 3, steps: int = E2D_STEPS):
             "dofs": dofs, "steps": n, "t_end": t, "wall_s": wall, "ms_per_step": 1e3 * wall / n,
             "dof_updates_per_s": dofs * n / wall,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "k_stage2d (one RK stage + OE of the previous stage) + statistics folds",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic_2d(),
+                         "kernel": "per RK stage: k_stage2d (OE of the previous stage + operator + SSP-RK3) "
+                                   "+ k_delta2d (damping numerators, statistics) + statistics folds",
                          "launch_us": 1e6 * launch_s}}
 
 
@@ -312,7 +334,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench()
     if not args.no_2d:
-        out["euler2d"] = euler2d_bench()
+        out["euler2d"] = euler2d_bench(repeats=args.e2d_repeats, steps=args.e2d_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))
