@@ -76,14 +76,42 @@ static double coef2(const ora2d *p, const double *u, long ix, long iy, int q, in
     return u[((((long)q * K1 + a) * K1 + b) * p->ny + iy) * p->nx + ix];
 }
 
+/* P_n^(d)(x) for the few distinct arguments the oracle uses (quadrature
+ * nodes, their shifts, 0, +-1, sample points), memoised by the exact value of
+ * x: the same numbers as calling ora_legendre_deriv each time. */
+static double leg_cached(int n, int d, double x)
+{
+    enum { NX = 128 };
+    static double xs[NX], val[NX][KMAX + 1][KMAX + 1];
+    static int count = 0;
+    static int last = 0;
+    int i = (last < count && xs[last] == x) ? last : 0;
+    while (i < count && xs[i] != x) ++i;
+    last = i;
+    if (i == count) {
+        if (count == NX) return ora_legendre_deriv(n, d, x);
+        xs[i] = x;
+        for (int nn = 0; nn <= KMAX; ++nn)
+            for (int dd = 0; dd <= KMAX; ++dd) val[i][nn][dd] = ora_legendre_deriv(nn, dd, x);
+        ++count;
+    }
+    return val[i][n][d];
+}
+
 /* Value of component q of cell (ix, iy) of u, derivative order (da, db) in
  * the reference coordinates, at (xi, eta). */
 static double eval2(const ora2d *p, const double *u, long ix, long iy, int q, int da, int db, double xi, double eta)
 {
+    const int K1 = p->k + 1;
+    const long plane = p->nx * p->ny;
+    const long c = wrap(iy, p->ny) * p->nx + wrap(ix, p->nx);
+    double bx[KMAX + 1], by[KMAX + 1];
+    for (int a = 0; a <= p->k; ++a) bx[a] = leg_cached(a, da, xi);
+    for (int b = 0; b <= p->k; ++b) by[b] = leg_cached(b, db, eta);
     double v = 0.0;
     for (int a = 0; a <= p->k; ++a)
         for (int b = 0; b <= p->k; ++b)
-            v += coef2(p, u, ix, iy, q, a, b) * ora_legendre_deriv(a, da, xi) * ora_legendre_deriv(b, db, eta);
+            v += u[(((long)q * K1 + a) * K1 + b) * plane + c] * bx[a] * by[b];
     return v;
 }
 
@@ -190,12 +218,19 @@ int ora2d_rhs(const ora2d *p, double tau_max, const double *uC, const double *uD
                                 }
                                 flux2d(p, 0, w, f1);
                                 flux2d(p, 1, w, f2);
+                                double Pa[KMAX + 1], dPa[KMAX + 1], Pb[KMAX + 1], dPb[KMAX + 1];
+                                for (int j = 0; j <= k; ++j) {
+                                    Pa[j] = leg_cached(j, 0, xi);
+                                    dPa[j] = leg_cached(j, 1, xi);
+                                    Pb[j] = leg_cached(j, 0, eta);
+                                    dPb[j] = leg_cached(j, 1, eta);
+                                }
                                 for (int q = 0; q < nc; ++q)
                                     for (int a = 0; a <= k; ++a)
                                         for (int b = 0; b <= k; ++b) {
-                                            double phi = ora_legendre(a, xi) * ora_legendre(b, eta);
-                                            double phx = (2.0 / hx) * ora_legendre_deriv(a, 1, xi) * ora_legendre(b, eta);
-                                            double phy = (2.0 / hy) * ora_legendre(a, xi) * ora_legendre_deriv(b, 1, eta);
+                                            double phi = Pa[a] * Pb[b];
+                                            double phx = (2.0 / hx) * dPa[a] * Pb[b];
+                                            double phy = (2.0 / hy) * Pa[a] * dPb[b];
                                             R[q][a][b] += wt * ((w[q] - uk[q]) * phi / tau_max + f1[q] * phx + f2[q] * phy);
                                         }
                             }
@@ -215,7 +250,7 @@ int ora2d_rhs(const ora2d *p, double tau_max, const double *uC, const double *uD
                             for (int q = 0; q < nc; ++q)
                                 for (int a = 0; a <= k; ++a)
                                     for (int b = 0; b <= k; ++b)
-                                        R[q][a][b] -= wt * sgn_out * f1[q] * ora_legendre(a, xi_e) * ora_legendre(b, eta);
+                                        R[q][a][b] -= wt * sgn_out * f1[q] * leg_cached(a, 0, xi_e) * leg_cached(b, 0, eta);
                         }
                     }
                 /* north / south edges (eta = +1 / -1): f_2 on horizontal centre lines */
@@ -232,7 +267,7 @@ int ora2d_rhs(const ora2d *p, double tau_max, const double *uC, const double *uD
                             for (int q = 0; q < nc; ++q)
                                 for (int a = 0; a <= k; ++a)
                                     for (int b = 0; b <= k; ++b)
-                                        R[q][a][b] -= wt * sgn_out * f2[q] * ora_legendre(a, xi) * ora_legendre(b, eta_e);
+                                        R[q][a][b] -= wt * sgn_out * f2[q] * leg_cached(a, 0, xi) * leg_cached(b, 0, eta_e);
                         }
                     }
                 for (int q = 0; q < nc; ++q)

@@ -1,0 +1,68 @@
+"""Full-horizon parity at the benchmark sizes against stored oracle results.
+
+The files under tests/golden/ are written by the committed scripts there,
+which call only the CPU oracle (about an hour of CPU each).  The GPU runs the
+same workload in the library's default (graph) mode and is compared on the
+stored cells: relative L-infinity <= 1e-10 (max |diff| / max |oracle| over all
+stored coefficients of both meshes), equal step counts and final times."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2503_12473_amd import inputs
+from paper_2503_12473_amd.api import OECDG, to_device
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = 1e-10
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated yet (tests/golden/ scripts, about an hour of CPU)")
+    return np.load(path)
+
+
+def _rel(gC, gD, rC, rD):
+    return max(np.abs(gC - rC).max(), np.abs(gD - rD).max()) / max(np.abs(rC).max(), np.abs(rD).max())
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_riemann_full_run_matches_golden(k):
+    """1D Euler Riemann, N = 16384, P_k, CFL 0.15, to T = 0.2 (about 33k-50k steps)."""
+    g = _golden(f"riemann_seed0_N16384_k{k}_T0.2.npz")
+    prob, uC, uD = inputs.euler_riemann(16384, k, inputs.riemann_states(0))
+    print(f"[golden] riemann k={k}", flush=True)
+    with OECDG(prob, 0.15) as s:
+        a, b = to_device(uC), to_device(uD)
+        t, n = s.run(a, b, t_end=0.2)
+        oC, oD = a.cpu().numpy().reshape(uC.shape), b.cpu().numpy().reshape(uD.shape)
+    st = int(g["stride"])
+    assert n == int(g["steps"]) and t == float(g["t"])
+    e = _rel(oC[..., ::st], oD[..., ::st], g["uC"], g["uD"])
+    print(f"[golden] k={k} steps={n} rel err {e:.3e}", flush=True)
+    assert e <= TOL
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n,steps", [(128, 500), (1024, 3)])
+def test_euler2d_matches_golden(n, steps):
+    """2D Euler quadrant workload, Q2, CFL 0.3: 128^2 x 500 steps and the
+    full 1024^2 mesh x 3 steps."""
+    g = _golden(f"euler2d_seed0_N{n}_{steps}steps.npz")
+    prob, uC, uD, _ = inputs.euler2d_quadrants(n, 2, seed=0)
+    print(f"[golden] euler2d n={n} steps={steps}", flush=True)
+    with OECDG(prob, 0.3) as s:
+        a, b = to_device(uC), to_device(uD)
+        t, done = s.run(a, b, nsteps=steps)
+        st = int(g["stride"])
+        oC = a.reshape(uC.shape)[..., ::st, ::st].cpu().numpy()
+        oD = b.reshape(uD.shape)[..., ::st, ::st].cpu().numpy()
+    assert done == int(g["steps"]) and t == pytest.approx(float(g["t"]), rel=1e-13)
+    e = _rel(oC, oD, g["uC"], g["uD"])
+    print(f"[golden] euler2d n={n} rel err {e:.3e}", flush=True)
+    assert e <= TOL
