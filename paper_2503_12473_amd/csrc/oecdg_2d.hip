@@ -193,6 +193,17 @@ __device__ inline double quad_max(double v) {
     return v;
 }
 
+// 1/x from the hardware estimate and two Newton steps (within an ulp or so of
+// the correctly rounded quotient; the flux divisions do not need the full
+// IEEE division sequence).
+__device__ inline double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 __device__ inline int wrap_idx(int i, int n, bool small) {
     if (small) return ((i % n) + n) % n;
     return i < 0 ? i + n : (i >= n ? i - n : i);
@@ -376,7 +387,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                     for (int e = 0; e < K1; ++e) wq += cx[e] * tb.nb[0][sy][g][e];
                     const double w0 = dpp_d<0x00>(wq, wq), w1 = dpp_d<0x55>(wq, wq);
                     const double w2 = dpp_d<0xAA>(wq, wq), w3 = dpp_d<0xFF>(wq, wq);
-                    const double ir = 1.0 / w0, u = w1 * ir, v = w2 * ir;
+                    const double ir = rcp_nr(w0), u = w1 * ir, v = w2 * ir;
                     const double pr = gm1 * (w3 - 0.5 * (w1 * u + w2 * v));
                     const double base = q == 3 ? w3 + pr : wq;
                     const double f1 = base * u + (q == 1 ? pr : 0.0);
@@ -425,7 +436,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                     for (int t = 0; t < K1; ++t) wq += r[t] * tb.nb[0][h][g][t];
                     const double w0 = dpp_d<0x00>(wq, wq), w1 = dpp_d<0x55>(wq, wq);
                     const double w2 = dpp_d<0xAA>(wq, wq), w3 = dpp_d<0xFF>(wq, wq);
-                    const double ir = 1.0 / w0, un = (dir ? w2 : w1) * ir;
+                    const double ir = rcp_nr(w0), un = (dir ? w2 : w1) * ir;
                     const double pr = gm1 * (w3 - 0.5 * (w1 * w1 + w2 * w2) * ir);
                     const double base = q == 3 ? w3 + pr : wq;
                     const double fn = base * un + (q == 1 + dir ? pr : 0.0);
@@ -687,10 +698,10 @@ __global__ __launch_bounds__(8 * TX * TY) void k_delta2d(Stage2Args a) {
                                 vt += rt[h][dn][t] * tb.nb[dt][h][g][t];
                             }
                             const double d = sct * (vo - vt);
-                            ss += d * d;
+                            ss = m == 0 ? fabs(d) : ss + d * d;
                             scn *= 2.0 / hn;
                         }
-                        mean += 0.25 * tb.w[g] * sqrt(ss);
+                        mean += 0.25 * tb.w[g] * (m == 0 ? ss : sqrt(ss));   // |d| = (d^2)^(1/2) for m = 0
                     }
                 double hm = 1.0;                          // h_e^(m-1)
                 if (m == 0) hm = 1.0 / hn;
