@@ -30,6 +30,7 @@ namespace oecdg {
 
 constexpr int ADJ_NT = 128;          // threads (= cells) per workgroup
 constexpr int ADJ_NW = ADJ_NT / WAVE;
+constexpr int ADJ_PRE = 4;           // partial entries per thread issued before the first wait
 // per-workgroup partials: sigma adjoint, sample max, its first index, sample
 // min, its first index, and the forward average / max / min of the mesh
 constexpr int ADJ_BP = 8;
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
         load_mu<K, OE>(a, mesh, cc, inJ);
         load_mu<K, OE>(a, other, user_left(mesh, cc, n), inL);     // cc overlaps its left half
         load_mu<K, OE>(a, other, user_right(mesh, cc, n), inR);    // cc overlaps its right half
-        load_cell<K>(a.s + mesh * a.S, n, cc, sJ);
+        if constexpr (!PREP) load_cell<K>(a.s + mesh * a.S, n, cc, sJ);   // else s_l = F(h_l), formed below
         load_cell<K>(a.acc + mesh * a.S, n, cc, accv);            // unused when acc_init
     } else {
         load_cell<K>(a.lam + mesh * a.S, n, cc, lam);
@@ -229,69 +230,77 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
         load_cell<K>(a.h + other * a.S, n, nb_left(mesh, cc, n), nl);
         load_cell<K>(a.h + other * a.S, n, nb_right(mesh, cc, n), nr);
     }
+    // up to ADJ_PRE entries per thread of the per-wave partials of the stage
+    // above and of the forward tile partials, loaded unconditionally (clamped
+    // indices) before any wait and folded afterwards; larger grids loop
     double bsum[2], bmx[2], bmn[2], bimx[2], bimn[2], fav[2], fmx[2], fmn[2];
+    double ebp[2][ADJ_PRE][5], efs[3][ADJ_PRE];
     if constexpr (GSIG) {
-        const int b0 = tid < a.nb ? tid : 0;
 #pragma unroll
         for (int Y = 0; Y < 2; ++Y) {
-            const double *f0 = a.bp_in + (long long)(Y * a.nb) * ADJ_BP;
-            const double *bp = a.bp_in + (long long)(Y * a.nb + b0) * ADJ_BP;
+            const double *f0 = a.bp_in + (long long)(Y * a.nbp) * ADJ_BP;
             fav[Y] = f0[5];
             fmx[Y] = f0[6];
             fmn[Y] = f0[7];
-            bsum[Y] = bp[0];
-            bmx[Y] = bp[1];
-            bimx[Y] = bp[2];
-            bmn[Y] = bp[3];
-            bimn[Y] = bp[4];
+#pragma unroll
+            for (int r = 0; r < ADJ_PRE; ++r) {
+                const int bb = tid + r * ADJ_NT;
+                const double *bp = a.bp_in + (long long)(Y * a.nbp + (bb < a.nbp ? bb : 0)) * ADJ_BP;
+#pragma unroll
+                for (int c = 0; c < 5; ++c) ebp[Y][r][c] = bp[c];
+            }
         }
     }
-    // forward statistics of h on this workgroup's mesh: sum, max, min over its tiles
-    double fs[3];
     if constexpr (PREP) {
-        const int t0 = tid < a.fntiles ? tid : 0;
 #pragma unroll
-        for (int kd = 0; kd < 3; ++kd) fs[kd] = a.fpart[(long long)stat_index(mesh, 0, kd) * a.fntot + a.ftile0 + t0];
+        for (int kd = 0; kd < 3; ++kd) {
+            const double *row = a.fpart + (long long)stat_index(mesh, 0, kd) * a.fntot + a.ftile0;
+#pragma unroll
+            for (int r = 0; r < ADJ_PRE; ++r) {
+                const int tt = tid + r * ADJ_NT;
+                efs[kd][r] = row[tt < a.fntiles ? tt : 0];
+            }
+        }
+    }
+#pragma unroll
+    for (int Y = 0; Y < 2; ++Y) {
+        bsum[Y] = 0.0;
+        bmx[Y] = -INFINITY;
+        bmn[Y] = bimx[Y] = bimn[Y] = INFINITY;
     }
     if constexpr (GSIG) {
-        if (tid >= a.nb) {
-#pragma unroll
-            for (int Y = 0; Y < 2; ++Y) {
-                bsum[Y] = 0.0;
-                bmx[Y] = -INFINITY;
-                bmn[Y] = INFINITY;
-                bimx[Y] = bimn[Y] = INFINITY;
-            }
-        }
-        if (a.nb > ADJ_NT) {
-#pragma unroll
-            for (int Y = 0; Y < 2; ++Y)
-                for (int b = tid + ADJ_NT; b < a.nb; b += ADJ_NT) {
-                    const double *bp = a.bp_in + (long long)(Y * a.nb + b) * ADJ_BP;
-                    bsum[Y] += bp[0];
-                    if (bp[1] > bmx[Y] || (bp[1] == bmx[Y] && bp[2] < bimx[Y])) bmx[Y] = bp[1], bimx[Y] = bp[2];
-                    if (bp[3] < bmn[Y] || (bp[3] == bmn[Y] && bp[4] < bimn[Y])) bmn[Y] = bp[3], bimn[Y] = bp[4];
-                }
-        }
-    } else {
 #pragma unroll
         for (int Y = 0; Y < 2; ++Y) {
-            bsum[Y] = fav[Y] = fmx[Y] = fmn[Y] = 0.0;
-            bmx[Y] = -INFINITY;
-            bmn[Y] = bimx[Y] = bimn[Y] = INFINITY;
-        }
-    }
-    if constexpr (PREP) {
-        if (tid >= a.fntiles) fs[0] = 0.0, fs[1] = -INFINITY, fs[2] = INFINITY;
-        if (a.fntiles > ADJ_NT) {
 #pragma unroll
-            for (int kd = 0; kd < 3; ++kd) {
-                const double *row = a.fpart + (long long)stat_index(mesh, 0, kd) * a.fntot + a.ftile0;
-                for (int t = tid + ADJ_NT; t < a.fntiles; t += ADJ_NT) fs[kd] = stat_op(kd, fs[kd], row[t]);
+            for (int r = 0; r < ADJ_PRE; ++r) {
+                if (tid + r * ADJ_NT >= a.nbp) continue;
+                const double *v = ebp[Y][r];
+                bsum[Y] += v[0];
+                if (v[1] > bmx[Y] || (v[1] == bmx[Y] && v[2] < bimx[Y])) bmx[Y] = v[1], bimx[Y] = v[2];
+                if (v[3] < bmn[Y] || (v[3] == bmn[Y] && v[4] < bimn[Y])) bmn[Y] = v[3], bimn[Y] = v[4];
+            }
+            for (int bb = tid + ADJ_PRE * ADJ_NT; bb < a.nbp; bb += ADJ_NT) {
+                const double *bp = a.bp_in + (long long)(Y * a.nbp + bb) * ADJ_BP;
+                bsum[Y] += bp[0];
+                if (bp[1] > bmx[Y] || (bp[1] == bmx[Y] && bp[2] < bimx[Y])) bmx[Y] = bp[1], bimx[Y] = bp[2];
+                if (bp[3] < bmn[Y] || (bp[3] == bmn[Y] && bp[4] < bimn[Y])) bmn[Y] = bp[3], bimn[Y] = bp[4];
             }
         }
     } else {
-        fs[0] = 0.0, fs[1] = -INFINITY, fs[2] = INFINITY;
+#pragma unroll
+        for (int Y = 0; Y < 2; ++Y) fav[Y] = fmx[Y] = fmn[Y] = 0.0;
+    }
+    // forward statistics of h on this workgroup's mesh: sum, max, min over its tiles
+    double fs[3] = {0.0, -INFINITY, INFINITY};
+    if constexpr (PREP) {
+#pragma unroll
+        for (int kd = 0; kd < 3; ++kd) {
+#pragma unroll
+            for (int r = 0; r < ADJ_PRE; ++r)
+                if (tid + r * ADJ_NT < a.fntiles) fs[kd] = stat_op(kd, fs[kd], efs[kd][r]);
+            const double *row = a.fpart + (long long)stat_index(mesh, 0, kd) * a.fntot + a.ftile0;
+            for (int tt = tid + ADJ_PRE * ADJ_NT; tt < a.fntiles; tt += ADJ_NT) fs[kd] = stat_op(kd, fs[kd], row[tt]);
+        }
     }
 
     // ---- round 1: global terms of the stage above and the forward statistics of h
@@ -329,6 +338,40 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
         sig = fmax(fs[1] - avg, avg - fs[2]);
     }
 
+    // ---- the damping of h_l at this cell (the lambda-independent part of the
+    // preparation); the reverse stage then uses s_l = F_tau(h_l) at the cell
+    double beta = 0.0, isig = 0.0, dR[K + 1], dL[K + 1], del[K + 1], facj[K + 1];
+    if constexpr (PREP) {
+        beta = F::speed(own, a.p0);
+        isig = sig != 0.0 ? 1.0 / sig : 0.0;
+#pragma unroll
+        for (int m = 0; m <= K; ++m) {
+            double ur = 0.0, ul = 0.0, vr = 0.0, vl = 0.0;
+#pragma unroll
+            for (int q = m; q <= K; ++q) {
+                const double d1 = tb.D1[m][q];
+                ur += own[q] * d1;
+                ul += own[q] * (((q + m) & 1) ? -d1 : d1);
+                vr += nr[q] * tb.D0[m][q];
+                vl += nl[q] * tb.D0[m][q];
+            }
+            dR[m] = ur - vr;
+            dL[m] = ul - vl;
+            del[m] = tb.C[m] * a.hinv * (beta * (fabs(dR[m]) + fabs(dL[m])) * isig);
+        }
+        double S = 0.0;
+        facj[0] = 1.0;
+#pragma unroll
+        for (int j = 1; j <= K; ++j) {
+            S = (j == 1 ? del[0] : S) + del[j];
+            facj[j] = exp(-a.tau * S);
+        }
+        if constexpr (RK) {
+#pragma unroll
+            for (int q = 0; q <= K; ++q) sJ[q] = own[q] * facj[q];
+        }
+    }
+
     // ---- reverse of stage l: dJ/ds_l and the a_l share of dJ/ds_0
     if constexpr (RK) {
         double muJ[K + 1], muL[K + 1], muR[K + 1];
@@ -362,34 +405,11 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
     if constexpr (!PREP) return;
 
     // ---- preparation of the stage below: the local part of F'(h)^T lambda
-    const double beta = F::speed(own, a.p0);
-    const double isig = sig != 0.0 ? 1.0 / sig : 0.0;
-    double dR[K + 1], dL[K + 1], del[K + 1];
-#pragma unroll
-    for (int m = 0; m <= K; ++m) {
-        double ur = 0.0, ul = 0.0, vr = 0.0, vl = 0.0;
-#pragma unroll
-        for (int q = m; q <= K; ++q) {
-            const double d1 = tb.D1[m][q];
-            ur += own[q] * d1;
-            ul += own[q] * (((q + m) & 1) ? -d1 : d1);
-            vr += nr[q] * tb.D0[m][q];
-            vl += nl[q] * tb.D0[m][q];
-        }
-        dR[m] = ur - vr;
-        dL[m] = ul - vl;
-        del[m] = tb.C[m] * a.hinv * (beta * (fabs(dR[m]) + fabs(dL[m])) * isig);
-    }
     double lp[K + 1], fo[K + 1];
-    double S = 0.0;
-    lp[0] = lam[0];
-    fo[0] = own[0];
 #pragma unroll
-    for (int j = 1; j <= K; ++j) {
-        S = (j == 1 ? del[0] : S) + del[j];
-        const double fac = exp(-a.tau * S);
-        fo[j] = own[j] * fac;
-        lp[j] = lam[j] * fac;
+    for (int j = 0; j <= K; ++j) {
+        fo[j] = own[j] * facj[j];
+        lp[j] = lam[j] * facj[j];
     }
     double cR[K + 1], cL[K + 1], sbar = 0.0;
 #pragma unroll
@@ -441,17 +461,16 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
             if (v < vmin) vmin = v, imin = idx;
         }
     }
-    // ---- round 2: this workgroup's partials of the prepared stage
+    // ---- this wave's partials of the prepared stage (no barrier: one entry
+    // per wave, entry (mesh, workgroup, wave) in that order)
     double *sc2 = scratch + ADJ_NW * ROW1;
     const int k2[1] = {0};
     double v2[1] = {valid ? sbar : 0.0};
     const int pk2[2] = {1, 2};
     double pv2[2] = {vmax, vmin}, pi2[2] = {imax, imin};
     wave_stage<1, 2>(k2, v2, pk2, pv2, pi2, sc2);
-    __syncthreads();
-    if (tid == 0) {
-        combine_rows<1, 2>(k2, v2, pk2, pv2, pi2, sc2);
-        double *bp = a.bp + (long long)blockIdx.x * ADJ_BP;
+    if (tid % WAVE == WAVE - 1) {
+        double *bp = a.bp + ((long long)blockIdx.x * ADJ_NW + tid / WAVE) * ADJ_BP;
         bp[0] = v2[0];
         bp[1] = pv2[0];
         bp[2] = pi2[0];
@@ -497,6 +516,7 @@ hipError_t launch_adj(const AdjArgs &a, hipStream_t s) {
     return hipLaunchKernel(adj_pick(a.k, a.flux, mode), dim3(2 * a.nb), dim3(ADJ_NT), args, 0, s);
 }
 int adj_block_size() { return ADJ_NT; }
-int adj_block_partials() { return ADJ_BP; }
+int adj_block_partials() { return ADJ_BP * ADJ_NW; }
+int adj_waves() { return ADJ_NW; }
 
 }  // namespace oecdg

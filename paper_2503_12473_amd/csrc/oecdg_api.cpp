@@ -399,8 +399,8 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
         a.BD[sp ^ 1] = out + S;
         a.UC = st(j, 0);
         a.UD = st(j, 0) + S;
-        a.DC = l == 0 ? nullptr : st(j, 2 * l);
-        a.DD = l == 0 ? nullptr : st(j, 2 * l) + S;
+        a.DC = nullptr;                                      // s_1, s_2 are formed again by the reverse stages
+        a.DD = nullptr;
         a.part[sp] = pp(j, l);
         a.part[sp ^ 1] = inP;
         return stage_all(h, a);
@@ -447,6 +447,7 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
     q.flux = I.flux;
     q.n = n;
     q.nb = nb;
+    q.nbp = nb * adj_waves();
     q.S = (long long)S;
     q.hinv = 1.0 / I.h;
     q.p0 = I.p0;
@@ -494,7 +495,9 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
             for (int l = 2; l >= 0; --l) {
                 AdjArgs a = q;
                 a.do_rk = 1;
-                a.s = st(j, 2 * l);
+                // s_l: read for the first stage of a segment (its u^n) and without OE
+                // (s_l = h_l); otherwise formed from h_l inside the reverse stage
+                a.s = l == 0 ? st(j, 0) : (q.oe ? st(j, 2 * l - 1) : st(j, 2 * l - 1));
                 a.lam = lam;
                 a.out = lam_next;
                 a.al = AL[l];

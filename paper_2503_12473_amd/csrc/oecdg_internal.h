@@ -80,6 +80,7 @@ struct StageArgs {
 // n cells per mesh, modal arrays [m][cell].
 struct AdjArgs {
     int k, flux, n, nb;            // degree, flux id, cells per mesh, workgroups per mesh
+    int nbp, pad0;                 // per-wave partial entries per mesh (nb x waves per workgroup)
     long long S;                   // (k+1) n: offset of the dual mesh in every field below
     double hinv, p0, tau, inv_tm;  // 1/h, flux parameter, tau, 1/tau_max
     double inv_n;                  // 1/n (derivative of the mesh average)
@@ -98,6 +99,7 @@ struct AdjArgs {
 hipError_t launch_adj(const AdjArgs &a, hipStream_t s);
 int adj_block_size();
 int adj_block_partials();
+int adj_waves();
 
 // Host-side launchers (oecdg_1d.hip).
 hipError_t upload_tables_1d();
