@@ -58,6 +58,8 @@ struct oecdg_handle {
 
     double *adj_ws = nullptr;    // adjoint workspace (checkpoints, segment states, adjoint buffers)
     size_t adj_bytes = 0;
+    hipStream_t aux = nullptr;   // adjoint: segment recomputation, overlapped with the reverse stages
+    hipEvent_t adj_ev[5] = {};   // adjoint: segment buffer ready (2), buffer free (2), checkpoint written
 
     void *ext2d = nullptr;   // 2D state (oecdg_2d.hip)
     std::string last;
@@ -344,8 +346,11 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
 // Discrete adjoint of a fixed-step run (scalar periodic 1D).  Pass 1 runs the
 // forward steps and keeps the damped state every `ckpt` steps.  Then, segment
 // by segment from the end, the forward kernels recompute the segment keeping
-// every stage's undamped output h, damped input s and per-tile partial
-// statistics, and the adjoint kernels walk the stages backwards.
+// every stage's undamped output h and its per-tile partial statistics, and the
+// adjoint kernels walk the stages backwards.  The segment states live in two
+// buffers (segment sg in buffer sg & 1): the recomputation of segment sg - 1
+// runs on a second stream while the reverse stages of segment sg run on the
+// caller's stream, and events order the buffer hand-overs.
 int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int64_t nsteps, double dt,
                       const double *gCT, const double *gDT, double *gC0, double *gD0, int ckpt) {
     const Inst1D I = h->inst_h[0];
@@ -358,11 +363,17 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
     const size_t ntile = h->tiles_h.size(), psz = (size_t)NSTAT * ntile;
     const int NB = adj_block_size(), nb = (n + NB - 1) / NB;
     const size_t bpsz = (size_t)2 * nb * adj_block_partials();
-    // workspace: checkpoints | segment states (6 per step) | partials (3 per step) |
-    //            2 adjoints | acc | 2 x (lp, cR, cL) | 2 x block partials
-    const size_t need = (size_t)std::max<long long>(nseg, 1) * S2 + (size_t)ckpt * 6 * S2 + (size_t)ckpt * 3 * psz +
-                        9 * S2 + 2 * bpsz;
+    const size_t segsz = (size_t)ckpt * 6 * S2 + (size_t)ckpt * 3 * psz;
+    const size_t slotsz = (2 * sizeof(Slot) + sizeof(Final) + sizeof(double) - 1) / sizeof(double);
+    // workspace: checkpoints | 2 x segment (states, 6 per step | partials, 3 per step) |
+    //            2 adjoints | acc | 2 x (lp, cR, cL) | 2 x block partials | step slots of the second stream
+    const size_t need = (size_t)std::max<long long>(nseg, 1) * S2 + 2 * segsz + 9 * S2 + 2 * bpsz + slotsz;
+    if (!h->aux) HIPCHK(h, hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+    for (hipEvent_t &e : h->adj_ev)
+        if (!e) HIPCHK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     if (need * sizeof(double) > h->adj_bytes) {
+        HIPCHK(h, hipStreamSynchronize(h->aux));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
         (void)hipFree(h->adj_ws);
         h->adj_ws = nullptr;
         h->adj_bytes = 0;
@@ -370,59 +381,79 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
         h->adj_bytes = need * sizeof(double);
     }
     double *ck = h->adj_ws;
-    double *seg = ck + (size_t)std::max<long long>(nseg, 1) * S2;
-    double *fp = seg + (size_t)ckpt * 6 * S2;
-    double *buf = fp + (size_t)ckpt * 3 * psz;
+    double *segb[2] = {ck + (size_t)std::max<long long>(nseg, 1) * S2, nullptr};
+    segb[1] = segb[0] + segsz;
+    double *buf = segb[1] + segsz;
     double *lamA = buf, *lamB = buf + S2, *acc = buf + 2 * S2;
     double *prepv[2][3] = {{buf + 3 * S2, buf + 4 * S2, buf + 5 * S2}, {buf + 6 * S2, buf + 7 * S2, buf + 8 * S2}};
     double *bpv[2] = {buf + 9 * S2, buf + 9 * S2 + bpsz};
-    auto st = [&](long long j, int which) { return seg + ((size_t)j * 6 + which) * S2; };   // 0 s0,1 h1,2 s1,3 h2,4 s2,5 h3
-    auto pp = [&](long long j, int l) { return fp + ((size_t)j * 3 + l) * psz; };
+    double *slotmem = bpv[1] + bpsz;
+    // stage states and partials of step j of the segment in buffer b
+    auto st = [&](int b, long long j, int which) {           // 0 s0,1 h1,2 s1,3 h2,4 s2,5 h3
+        return segb[b] + ((size_t)j * 6 + which) * S2;
+    };
+    auto pp = [&](int b, long long j, int l) { return segb[b] + (size_t)ckpt * 6 * S2 + ((size_t)j * 3 + l) * psz; };
+    hipEvent_t *ready = h->adj_ev, *freed = h->adj_ev + 2, ckdone = h->adj_ev[4];
 
     StageArgs base = base_args(h);
     base.dt_fixed = dt;
     base.t_end = INFINITY;
+    StageArgs baux = base;                                   // the second stream keeps its own step slots
+    baux.slots = (Slot *)slotmem;
+    baux.fin = (Final *)((Slot *)slotmem + 2);
     int rc;
-    // Stage l of step j of a segment, keeping every stage state and its partial
-    // statistics; (inC, inD, inP) is the undamped input and its partials.
-    auto seg_stage = [&](long long nn, long long j, int l, const double *inC, const double *inD, double *inP,
-                         bool first) {
-        StageArgs a = base;
+    // Stage l of step nn (step j of the segment in buffer b), keeping every
+    // stage state and its partial statistics; (inC, inD, inP) is the undamped
+    // input and its partials.
+    auto seg_stage = [&](const StageArgs &sa, int b, long long nn, long long j, int l, const double *inC,
+                         const double *inD, double *inP, bool first, hipStream_t s) {
+        StageArgs a = sa;
         a.l = l;
         a.par = (int)(nn & 1);
         a.first = first;
         const int sp = (a.par + l) & 1;
-        double *out = st(j, 2 * l + 1);
+        double *out = st(b, j, 2 * l + 1);
         a.BC[sp] = const_cast<double *>(inC);
         a.BD[sp] = const_cast<double *>(inD);
         a.BC[sp ^ 1] = out;
         a.BD[sp ^ 1] = out + S;
-        a.UC = st(j, 0);
-        a.UD = st(j, 0) + S;
+        a.UC = st(b, j, 0);
+        a.UD = st(b, j, 0) + S;
         a.DC = nullptr;                                      // s_1, s_2 are formed again by the reverse stages
         a.DD = nullptr;
-        a.part[sp] = pp(j, l);
+        a.part[sp] = pp(b, j, l);
         a.part[sp ^ 1] = inP;
-        return stage_all(h, a);
+        for (const auto &g : h->groups) {
+            StageArgs c = a;
+            c.tbeg = g.tbeg;
+            c.tend = g.tend;
+            HIPCHK(h, launch_stage_1d(c, g.k, h->flux, false, h->tile, 0, s));
+        }
+        return (int)OECDG_OK;
     };
     // pass 1: forward from u^0, keeping u^n at n = 0, ckpt, 2 ckpt, ... and
     // every stage of the last segment (which then needs no recomputation)
+    const int bL = (int)((nseg - 1) & 1);
     HIPCHK(h, hipMemcpyAsync(ck, uC0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(ck + S, uD0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(base.BC[0], uC0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(base.BD[0], uD0, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, launch_init_1d(base, 1, h->stream));
-    for (long long nn = 0; nn < nsteps; ++nn)
+    HIPCHK(h, launch_init_1d(baux, 1, h->stream));
+    for (long long nn = 0; nn < nsteps; ++nn) {
         for (int l = 0; l < 3; ++l) {
             if (nn >= n0L) {
                 const long long j = nn - n0L;
                 if (l > 0)
-                    rc = seg_stage(nn, j, l, st(j, 2 * l - 1), st(j, 2 * l - 1) + S, pp(j, l - 1), false);
+                    rc = seg_stage(base, bL, nn, j, l, st(bL, j, 2 * l - 1), st(bL, j, 2 * l - 1) + S, pp(bL, j, l - 1),
+                                   false, h->stream);
                 else if (j > 0)
-                    rc = seg_stage(nn, j, 0, st(j - 1, 5), st(j - 1, 5) + S, pp(j - 1, 2), false);
+                    rc = seg_stage(base, bL, nn, j, 0, st(bL, j - 1, 5), st(bL, j - 1, 5) + S, pp(bL, j - 1, 2), false,
+                                   h->stream);
                 else {
                     const int sp = (int)(nn & 1);
-                    rc = seg_stage(nn, 0, 0, base.BC[sp], base.BD[sp], base.part[sp ^ 1], nn == 0);
+                    rc = seg_stage(base, bL, nn, 0, 0, base.BC[sp], base.BD[sp], base.part[sp ^ 1], nn == 0,
+                                   h->stream);
                 }
                 if (rc != OECDG_OK) return rc;
                 continue;
@@ -437,6 +468,33 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
             }
             if ((rc = stage_all(h, a)) != OECDG_OK) return rc;
         }
+        if (nseg >= 2 && nn == (nseg - 2) * ckpt)           // the last checkpoint a recomputation reads
+            HIPCHK(h, hipEventRecord(ckdone, h->stream));
+    }
+    // Recompute segment sg (all of its steps are whole) into buffer sg & 1 on
+    // the second stream, once the reverse stages have released that buffer.
+    auto recompute = [&](long long sg) -> int {
+        const int b = (int)(sg & 1);
+        if (sg == nseg - 2) HIPCHK(h, hipStreamWaitEvent(h->aux, ckdone, 0));
+        else HIPCHK(h, hipStreamWaitEvent(h->aux, freed[b], 0));
+        const long long n0 = sg * ckpt;
+        for (long long j = 0; j < ckpt; ++j)
+            for (int l = 0; l < 3; ++l) {
+                const long long nn = n0 + j;
+                int r;
+                if (l > 0)
+                    r = seg_stage(baux, b, nn, j, l, st(b, j, 2 * l - 1), st(b, j, 2 * l - 1) + S, pp(b, j, l - 1),
+                                  false, h->aux);
+                else if (j > 0)
+                    r = seg_stage(baux, b, nn, j, 0, st(b, j - 1, 5), st(b, j - 1, 5) + S, pp(b, j - 1, 2), false,
+                                  h->aux);
+                else                                         // the checkpoint is already damped
+                    r = seg_stage(baux, b, nn, 0, 0, ck + sg * S2, ck + sg * S2 + S, pp(b, 0, 2), true, h->aux);
+                if (r != OECDG_OK) return r;
+            }
+        HIPCHK(h, hipEventRecord(ready[b], h->aux));
+        return OECDG_OK;
+    };
     // backward
     HIPCHK(h, hipMemcpyAsync(lamA, gCT, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(lamA + S, gDT, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
@@ -467,27 +525,18 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
     auto set_in = [&](AdjArgs &a, int r) {
         a.lp_in = prepv[r][0], a.cr_in = prepv[r][1], a.cl_in = prepv[r][2], a.bp_in = bpv[r];
     };
-    for (long long sg = nseg - 1; sg >= 0; --sg) {
-        const long long n0 = sg * ckpt, m = std::min<long long>(ckpt, nsteps - n0);
-        if (sg != nseg - 1)                                  // recompute the segment from its checkpoint
-            for (long long j = 0; j < m; ++j)
-                for (int l = 0; l < 3; ++l) {
-                    const long long nn = n0 + j;
-                    if (l > 0)
-                        rc = seg_stage(nn, j, l, st(j, 2 * l - 1), st(j, 2 * l - 1) + S, pp(j, l - 1), false);
-                    else if (j > 0)
-                        rc = seg_stage(nn, j, 0, st(j - 1, 5), st(j - 1, 5) + S, pp(j - 1, 2), false);
-                    else                                     // the checkpoint is already damped
-                        rc = seg_stage(nn, 0, 0, ck + sg * S2, ck + sg * S2 + S, pp(0, 2), true);
-                    if (rc != OECDG_OK) return rc;
-                }
+    // the reverse stages of segment sg, from buffer sg & 1
+    auto reverse = [&](long long sg) -> int {
+        const int b = (int)(sg & 1);
+        const long long m = std::min<long long>(ckpt, nsteps - sg * ckpt);
+        if (sg != nseg - 1) HIPCHK(h, hipStreamWaitEvent(h->stream, ready[b], 0));
         if (q.oe) {                                          // prepare the OE of the segment's last stage
             AdjArgs a = q;
             a.do_rk = 0;
             a.do_prep = 1;
             a.lam = lam;
-            a.h = st(m - 1, 5);
-            a.fpart = pp(m - 1, 2);
+            a.h = st(b, m - 1, 5);
+            a.fpart = pp(b, m - 1, 2);
             set_out(a, cur);
             HIPCHK(h, launch_adj(a, h->stream));
         }
@@ -495,9 +544,9 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
             for (int l = 2; l >= 0; --l) {
                 AdjArgs a = q;
                 a.do_rk = 1;
-                // s_l: read for the first stage of a segment (its u^n) and without OE
-                // (s_l = h_l); otherwise formed from h_l inside the reverse stage
-                a.s = l == 0 ? st(j, 0) : (q.oe ? st(j, 2 * l - 1) : st(j, 2 * l - 1));
+                // s_l is read for the first stage of a step (u^n, damped); for
+                // l > 0 the pointer is h_l, damped inside the reverse stage
+                a.s = l == 0 ? st(b, j, 0) : st(b, j, 2 * l - 1);
                 a.lam = lam;
                 a.out = lam_next;
                 a.al = AL[l];
@@ -507,12 +556,25 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
                 set_in(a, cur);
                 set_out(a, cur ^ 1);
                 a.do_prep = l > 0 || j > 0;
-                a.h = l > 0 ? st(j, 2 * l - 1) : (j > 0 ? st(j - 1, 5) : nullptr);
-                a.fpart = l > 0 ? pp(j, l - 1) : (j > 0 ? pp(j - 1, 2) : nullptr);
+                a.h = l > 0 ? st(b, j, 2 * l - 1) : (j > 0 ? st(b, j - 1, 5) : nullptr);
+                a.fpart = l > 0 ? pp(b, j, l - 1) : (j > 0 ? pp(b, j - 1, 2) : nullptr);
                 HIPCHK(h, launch_adj(a, h->stream));
                 cur ^= 1;
                 std::swap(lam, lam_next);
             }
+        HIPCHK(h, hipEventRecord(freed[b], h->stream));
+        return OECDG_OK;
+    };
+    // recompute(sg - 1) is issued before reverse(sg): the two run side by side
+    rc = OECDG_OK;
+    if (nseg >= 2) rc = recompute(nseg - 2);
+    for (long long sg = nseg - 1; sg >= 0 && rc == OECDG_OK; --sg) {
+        if ((rc = reverse(sg)) != OECDG_OK) break;
+        if (sg >= 2) rc = recompute(sg - 2);
+    }
+    if (rc != OECDG_OK) {                                    // nothing may still write the workspace
+        (void)hipStreamSynchronize(h->aux);
+        return rc;
     }
     HIPCHK(h, hipMemcpyAsync(gC0, lam, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(gD0, lam + S, S * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
@@ -760,6 +822,9 @@ void oecdg_destroy(oecdg_handle *h) {
     if (!h) return;
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->cap) (void)hipStreamDestroy(h->cap);
+    if (h->aux) (void)hipStreamSynchronize(h->aux), (void)hipStreamDestroy(h->aux);
+    for (hipEvent_t e : h->adj_ev)
+        if (e) (void)hipEventDestroy(e);
     (void)hipFree(h->adj_ws);
     (void)hipFree(h->inst_d);
     (void)hipFree(h->tiles_d);
