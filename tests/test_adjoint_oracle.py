@@ -54,3 +54,27 @@ def test_checkpointing_does_not_change_the_gradient():
     a = adj.gradient(prob, uC, uD, steps, tau, gC, gD, checkpoint_every=0)
     b = adj.gradient(prob, uC, uD, steps, tau, gC, gD, checkpoint_every=7)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("flux", ["burgers", "advection"])
+def test_tangent_linear_and_adjoint_are_transposes(flux):
+    """Dot-product test: <J v, w> with J v from forward-mode differentiation of
+    the run equals <v, J^T w> from the checkpointed reverse sweep, to 1e-12
+    (exact transposition; only the summation order differs).  30 steps at
+    n = 48 run well past the Burgers shock onset (about 4 steps here)."""
+    import torch
+    import torch.autograd.forward_ad as fwAD
+    prob, uC, uD, _, _, tau, steps = _setup(n=48, k=2, steps=30)
+    if flux == "advection":
+        prob, uC, uD = inputs.advection_sine(48, 2, phase=1.3)
+        tau = 0.2 * prob.h
+    rng = np.random.default_rng(11)
+    vC, vD, wC, wD = (rng.normal(size=uC.shape) for _ in range(4))
+    s = adj.Scalar1D(prob)
+    t = lambda x: torch.tensor(x[0], dtype=torch.float64)
+    with fwAD.dual_level():
+        oC, oD = s.run(fwAD.make_dual(t(uC), t(vC)), fwAD.make_dual(t(uD), t(vD)), steps, tau)
+        tl = float((fwAD.unpack_dual(oC).tangent * t(wC)).sum() + (fwAD.unpack_dual(oD).tangent * t(wD)).sum())
+    gC, gD = adj.gradient(prob, uC, uD, steps, tau, wC, wD, checkpoint_every=7)
+    ad = float((gC * vC).sum() + (gD * vD).sum())
+    assert abs(tl - ad) <= 1e-12 * max(abs(tl), abs(ad)), (tl, ad)
