@@ -182,14 +182,14 @@ __host__ __device__ constexpr int row2(int nc, int mesh, int q, int kind) { retu
 
 // Sum over the four lanes of a quad; every lane gets ((l0 + l1) + (l2 + l3)).
 __device__ inline double quad_sum(double v) {
-    v += dpp_d<0xB1>(v, 0.0);     // quad_perm [1,0,3,2]
-    v += dpp_d<0x4E>(v, 0.0);     // quad_perm [2,3,0,1]
+    v += dpp_all<0xB1>(v);          // quad_perm [1,0,3,2]
+    v += dpp_all<0x4E>(v);          // quad_perm [2,3,0,1]
     return v;
 }
 
 __device__ inline double quad_max(double v) {
-    v = fmax(v, dpp_d<0xB1>(v, -INFINITY));
-    v = fmax(v, dpp_d<0x4E>(v, -INFINITY));
+    v = fmax(v, dpp_all<0xB1>(v));
+    v = fmax(v, dpp_all<0x4E>(v));
     return v;
 }
 
@@ -358,15 +358,27 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
             for (int j = 0; j < K1; ++j) Rq[i][j] = 0.0;
         const double gm1 = a.fp.gamma - 1.0;
         // coupling and volume, quadrant (sx, sy)
+//
+        // Quadrant (sx, sy) is evaluated in its mirror image on the upper
+        // right quadrant: with P_n(-x) = (-1)^n P_n(x) and the symmetric Gauss
+        // rule, mirroring a direction flips the sign of the odd modes of the
+        // overlapping cell and of the odd test functions (the even ones for a
+        // derivative, and the flux along that direction), so every quadrant
+        // uses the same compile-time tables.
 #pragma unroll 1
         for (int qd = 0; qd < 4; ++qd) {
             const int sx = qd & 1, sy = qd >> 1;
+            const double sgx = sx ? 1.0 : -1.0, sgy = sy ? 1.0 : -1.0;
             const int oc = (ly + sy - mesh) * W + (lx + sx - mesh);
             double d[K1][K1];
 #pragma unroll
             for (int c = 0; c < K1; ++c)
 #pragma unroll
-                for (int e = 0; e < K1; ++e) d[c][e] = toth[((q * K1 + c) * K1 + e) * NCELL + oc];
+                for (int e = 0; e < K1; ++e) {
+                    const double x = toth[((q * K1 + c) * K1 + e) * NCELL + oc];
+                    const double xs = (c & 1) ? sgx * x : x;
+                    d[c][e] = (e & 1) ? sgy * xs : xs;
+                }
 #pragma unroll
             for (int p = 0; p < Q; ++p) {
                 double cx[K1];
@@ -374,7 +386,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                 for (int e = 0; e < K1; ++e) {
                     double t = 0.0;
 #pragma unroll
-                    for (int c = 0; c < K1; ++c) t += d[c][e] * tb.nb[0][sx][p][c];
+                    for (int c = 0; c < K1; ++c) t += d[c][e] * tb.nb[0][1][p][c];
                     cx[e] = t;
                 }
                 double A[K1], B[K1];
@@ -384,26 +396,34 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                 for (int g = 0; g < Q; ++g) {
                     double wq = 0.0;
 #pragma unroll
-                    for (int e = 0; e < K1; ++e) wq += cx[e] * tb.nb[0][sy][g][e];
-                    const double w0 = dpp_d<0x00>(wq, wq), w1 = dpp_d<0x55>(wq, wq);
-                    const double w2 = dpp_d<0xAA>(wq, wq), w3 = dpp_d<0xFF>(wq, wq);
+                    for (int e = 0; e < K1; ++e) wq += cx[e] * tb.nb[0][1][g][e];
+                    const double w0 = dpp_all<0x00>(wq), w1 = dpp_all<0x55>(wq);
+                    const double w2 = dpp_all<0xAA>(wq), w3 = dpp_all<0xFF>(wq);
                     const double ir = rcp_nr(w0), u = w1 * ir, v = w2 * ir;
                     const double pr = gm1 * (w3 - 0.5 * (w1 * u + w2 * v));
                     const double base = q == 3 ? w3 + pr : wq;
                     const double f1 = base * u + (q == 1 ? pr : 0.0);
-                    const double f2 = base * v + (q == 2 ? pr : 0.0);
+                    const double f2 = sgy * (base * v + (q == 2 ? pr : 0.0));
 #pragma unroll
                     for (int j = 0; j < K1; ++j) {
-                        A[j] += tb.w[g] * (wq * itm * tb.own[0][sy][g][j] + (2.0 / hy) * f2 * tb.own[1][sy][g][j]);
-                        B[j] += tb.w[g] * f1 * tb.own[0][sy][g][j];
+                        A[j] += tb.w[g] * (wq * itm * tb.own[0][1][g][j] + (2.0 / hy) * f2 * tb.own[1][1][g][j]);
+                        B[j] += tb.w[g] * f1 * tb.own[0][1][g][j];
                     }
+                }
+                double Ax[K1], Bx[K1];
+#pragma unroll
+                for (int j = 0; j < K1; ++j) {
+                    if (j & 1) A[j] *= sgy, B[j] *= sgy;
+                    Ax[j] = sgx * A[j];
+                    Bx[j] = sgx * B[j];
                 }
                 const double wp = hx * hy / 16.0 * tb.w[p];
 #pragma unroll
                 for (int i = 0; i < K1; ++i)
 #pragma unroll
                     for (int j = 0; j < K1; ++j)
-                        Rq[i][j] += wp * (tb.own[0][sx][p][i] * A[j] + (2.0 / hx) * tb.own[1][sx][p][i] * B[j]);
+                        Rq[i][j] += wp * (tb.own[0][1][p][i] * ((i & 1) ? Ax[j] : A[j]) +
+                                          (2.0 / hx) * tb.own[1][1][p][i] * ((i & 1) ? B[j] : Bx[j]));
             }
         }
         // edges: (dir, side) = W, E (f_1 on vertical centre lines), S, N (f_2)
@@ -434,8 +454,8 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                     double wq = 0.0;
 #pragma unroll
                     for (int t = 0; t < K1; ++t) wq += r[t] * tb.nb[0][h][g][t];
-                    const double w0 = dpp_d<0x00>(wq, wq), w1 = dpp_d<0x55>(wq, wq);
-                    const double w2 = dpp_d<0xAA>(wq, wq), w3 = dpp_d<0xFF>(wq, wq);
+                    const double w0 = dpp_all<0x00>(wq), w1 = dpp_all<0x55>(wq);
+                    const double w2 = dpp_all<0xAA>(wq), w3 = dpp_all<0xFF>(wq);
                     const double ir = rcp_nr(w0), un = (dir ? w2 : w1) * ir;
                     const double pr = gm1 * (w3 - 0.5 * (w1 * w1 + w2 * w2) * ir);
                     const double base = q == 3 ? w3 + pr : wq;
@@ -763,11 +783,15 @@ __global__ __launch_bounds__(8 * TX * TY) void k_delta2d(Stage2Args a) {
         }
     }
     {
-        const int lane = tid % WAVE, wave = tid / WAVE;
+        // a wave holds cells of one mesh only: the other mesh's rows are the
+        // identity there and are not reduced
+        static_assert((4 * TX * TY) % WAVE == 0, "waves do not straddle the meshes");
+        const int lane = tid % WAVE, wave = tid / WAVE, wmesh = wave / (4 * TX * TY / WAVE);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             const int kind = j < 2 * NC * 3 ? j % 3 : 1;
-            const double v = wave_reduce(kind, vals[j]);
+            const bool mine = j >= 2 * NC * 3 || j / (NC * 3) == wmesh;
+            const double v = mine ? wave_reduce(kind, vals[j]) : stat_identity(kind);
             if (lane == WAVE - 1) red[wave * NR + j] = v;
         }
         __syncthreads();

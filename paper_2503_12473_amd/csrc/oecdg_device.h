@@ -97,18 +97,28 @@ __device__ inline double dpp_d(double v, double old) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// A lane permutation that writes every lane (quad_perm, row mirrors): no
+// "old" operand, so none is copied.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ inline double dpp_all(double v) {
+    const long long x = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)x, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Value of the partner lane (lane ^ 1).
-__device__ inline double pair_swap(double v) { return dpp_d<0xB1>(v, v); }   // quad_perm [1,0,3,2]
+__device__ inline double pair_swap(double v) { return dpp_all<0xB1>(v); }   // quad_perm [1,0,3,2]
 
 // Reduction over the 64 lanes of a wave in a fixed tree (pairs, quads, half
 // rows, rows, then rows 0+1 and 2+3, then all four); the result is in lane 63.
 // Every lane of the wave must be active.
 __device__ inline double wave_reduce(int kind, double v) {
     const double id = stat_identity(kind);
-    v = stat_op(kind, v, dpp_d<0xB1>(v, id));          // quad_perm [1,0,3,2]
-    v = stat_op(kind, v, dpp_d<0x4E>(v, id));          // quad_perm [2,3,0,1]
-    v = stat_op(kind, v, dpp_d<0x141>(v, id));         // row_half_mirror
-    v = stat_op(kind, v, dpp_d<0x140>(v, id));         // row_mirror
+    v = stat_op(kind, v, dpp_all<0xB1>(v));            // quad_perm [1,0,3,2]
+    v = stat_op(kind, v, dpp_all<0x4E>(v));            // quad_perm [2,3,0,1]
+    v = stat_op(kind, v, dpp_all<0x141>(v));           // row_half_mirror
+    v = stat_op(kind, v, dpp_all<0x140>(v));           // row_mirror
     v = stat_op(kind, v, dpp_d<0x142, 0xa>(v, id));    // row_bcast:15 into rows 1, 3
     v = stat_op(kind, v, dpp_d<0x143, 0xc>(v, id));    // row_bcast:31 into rows 2, 3
     return v;
@@ -145,7 +155,10 @@ __device__ inline void load_partials(const double *part, long long ntot, int til
 #pragma unroll
         for (int i = 0; i < Partials<NC>::NS; ++i) {
             const int j = stat_row<NC>(i);
-            p.v[u][i] = (i < ns && t < ntiles) ? part[(long long)j * ntot + tile0 + t] : stat_identity(stat_kind(j));
+            // unconditional load of a valid element, then a select: no branch
+            // (and no wait) between the loads
+            const double x = part[(long long)j * ntot + tile0 + min(t, ntiles - 1)];
+            p.v[u][i] = (i < ns && t < ntiles) ? x : stat_identity(stat_kind(j));
         }
     }
 }
