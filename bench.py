@@ -55,7 +55,7 @@ def parse():
 
 PROFILE_JSON = os.path.join(ROOT, "profiles", "k_stage_euler1d_p2_n16384.json")
 KERNEL_SOURCES = ["paper_2503_12473_amd/csrc/oecdg_1d.hip", "paper_2503_12473_amd/csrc/oecdg_tables.h",
-                  "paper_2503_12473_amd/csrc/oecdg_internal.h"]
+                  "paper_2503_12473_amd/csrc/oecdg_internal.h", "paper_2503_12473_amd/csrc/oecdg_device.h"]
 
 
 def measured_traffic():
@@ -78,18 +78,19 @@ KERNEL2D_SOURCES = ["paper_2503_12473_amd/csrc/oecdg_2d.hip", "paper_2503_12473_
                     "paper_2503_12473_amd/csrc/oecdg_device.h"]
 
 
-def measured_traffic_2d():
-    """HBM bytes per 2D RK stage (k_stage2d + k_delta2d) from the committed
-    counter profile, or None if the kernel sources changed since."""
+def profile_2d():
+    """Counter results per 2D RK stage (k_stage2d + k_delta2d) from the
+    committed profile: HBM bytes and executed FP64 flops, or {} if the kernel
+    sources changed since."""
     import hashlib
     try:
         meta = json.load(open(PROFILE2D_JSON))
     except OSError:
-        return None
+        return {}
     h = hashlib.sha256()
     for f in KERNEL2D_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    return meta["traffic_bytes_per_stage"] if meta.get("source_sha256") == h.hexdigest() else None
+    return meta if meta.get("source_sha256") == h.hexdigest() else {}
 
 
 def batched_bench(k_fixed=None):
@@ -218,15 +219,25 @@ def euler2d_bench(repeats: int = 3, steps: int = E2D_STEPS):
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1) / 1e3)
     wall = sorted(times)[len(times) // 2]
-    launch_s = wall / (3 * n)
+    launch_s = wall / (3 * n)                    # one RK stage: fold + reduce + k_stage2d + k_delta2d
     bytes_per_launch = BYTES_PER_DOF_UPDATE / 3.0 * dofs
     achieved = bytes_per_launch / launch_s / 1e9
+    prof = profile_2d()
+    flops = prof.get("fp64_flops_per_stage")
+    tflops = flops / launch_s / 1e12 if flops else None
+    # The binding resource is FP64 vector issue (the counters show the SIMDs
+    # issuing most of the time): the roofline is FP64 flops executed per stage
+    # (SQ counters of the committed profile) over the live stage time, with the
+    # algorithmic-bytes HBM figure beside it.
     return {"workload": f"2D Euler, [0,1]^2 periodic, {E2D_N}^2 primal + {E2D_N}^2 dual cells, Q2, CFL {E2D_CFL}, "
                         f"{steps} steps, seeded quadrant states (seed {SEED})",
             "dofs": dofs, "steps": n, "t_end": t, "wall_s": wall, "ms_per_step": 1e3 * wall / n,
             "dof_updates_per_s": dofs * n / wall,
-            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic_2d(),
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / FP64_PEAK_TFLOPS if tflops else None,
+                         "flops": "executed FP64 (counted wave instructions x 64 lanes, FMA = 2)",
+                         "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": achieved / HBM_PEAK_GBS, "traffic": prof.get("traffic_bytes_per_stage")},
                          "kernel": "per RK stage: k_stage2d (OE of the previous stage + operator + SSP-RK3) "
                                    "+ k_delta2d (damping numerators, statistics) + statistics folds",
                          "launch_us": 1e6 * launch_s}}
