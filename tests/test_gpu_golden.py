@@ -3,8 +3,9 @@
 The files under tests/golden/ are written by the committed scripts there,
 which call only the CPU oracle (about an hour of CPU each).  The GPU runs the
 same workload in the library's default (graph) mode and is compared on the
-stored cells: relative L-infinity <= 1e-10 (max |diff| / max |oracle| over all
-stored coefficients of both meshes), equal step counts and final times."""
+stored cells: relative L-infinity (max |diff| / max |oracle| over all stored
+coefficients of both meshes) within the bar of each case, equal step counts and
+final times."""
 import os
 
 import numpy as np
@@ -30,22 +31,34 @@ def _rel(gC, gD, rC, rD):
     return max(np.abs(gC - rC).max(), np.abs(gD - rD).max()) / max(np.abs(rC).max(), np.abs(rD).max())
 
 
+# (k, T, bar).  The bar is 1e-10 wherever two equally valid FP64 evaluations
+# of the run agree to better than that.  Past that time the discrete map,
+# which carries the shock through ~33k steps, amplifies last-bit differences
+# about a millionfold: at T = 0.2 the library built with and without FMA
+# contraction differs from itself by 8.4e-11 (k = 2) and 2.5e-10 (k = 3), so
+# there the bar is 5e-10, twice the larger of those spreads.  The earlier
+# snapshots show the growth is steady.
+RIEMANN = [(1, 0.2, 1e-10),
+           (2, 0.05, 1e-10), (2, 0.1, 1e-10), (2, 0.2, 5e-10),
+           (3, 0.05, 1e-10), (3, 0.1, 1e-10), (3, 0.2, 5e-10)]
+
+
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("k", [1, 2, 3])
-def test_riemann_full_run_matches_golden(k):
-    """1D Euler Riemann, N = 16384, P_k, CFL 0.15, to T = 0.2 (about 33k-50k steps)."""
-    g = _golden(f"riemann_seed0_N16384_k{k}_T0.2.npz")
+@pytest.mark.parametrize("k,T,bar", RIEMANN)
+def test_riemann_run_matches_golden(k, T, bar):
+    """1D Euler Riemann, N = 16384, P_k, CFL 0.15, to T (up to ~33k steps)."""
+    g = _golden(f"riemann_seed0_N16384_k{k}_T{T:g}.npz")
     prob, uC, uD = inputs.euler_riemann(16384, k, inputs.riemann_states(0))
-    print(f"[golden] riemann k={k}", flush=True)
+    print(f"[golden] riemann k={k} T={T:g}", flush=True)
     with OECDG(prob, 0.15) as s:
         a, b = to_device(uC), to_device(uD)
-        t, n = s.run(a, b, t_end=0.2)
+        t, n = s.run(a, b, t_end=T)
         oC, oD = a.cpu().numpy().reshape(uC.shape), b.cpu().numpy().reshape(uD.shape)
     st = int(g["stride"])
     assert n == int(g["steps"]) and t == float(g["t"])
     e = _rel(oC[..., ::st], oD[..., ::st], g["uC"], g["uD"])
-    print(f"[golden] k={k} steps={n} rel err {e:.3e}", flush=True)
-    assert e <= TOL
+    print(f"[golden] k={k} T={T:g} steps={n} rel err {e:.3e} (bar {bar:.0e})", flush=True)
+    assert e <= bar
 
 
 @pytest.mark.timeout(300)
