@@ -9,7 +9,7 @@ the time-step reduction, three stage updates on both meshes and three OE
 applications.  value = DOF-updates/s = (DOFs of both meshes) x steps / wall
 seconds, with the state resident in HBM when the timed region starts.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -264,7 +264,7 @@ def cpu_baseline(target_seconds: float):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (got --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -111,6 +111,10 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
  * total).  Host pointers. */
 int oecdg_batch_offsets(oecdg_handle *h, int64_t *off_primal, int64_t *off_dual);
 
+/* Set an OECDG_OPT_* tuning option (execution mode, tile size, graph length,
+ * persistent grid).  Options change speed only, never results (every mode and
+ * tile gives the same bits).  EINVAL for an unknown key or a value out of
+ * range; setting the tile rebuilds the tile list (and may return ENOMEM). */
 int oecdg_set_option(oecdg_handle *h, int32_t key, int64_t value);
 
 /* tau_max of instance 0 for the state (uC, uD) (Sec. 2.1; cell averages of
@@ -140,18 +144,30 @@ int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max,
 int oecdg_run(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps,
               double dt_fixed, double *t_out, int64_t *steps_out);
 
-/* Discrete adjoint of oecdg_run with a fixed step (1D, single instance):
- * given u_sigma^0 = (uC0, uD0), nsteps steps of size dt = tau = tau_max and
- * the gradient (gC_T, gD_T) of a loss J with respect to u_sigma^N (in modal
- * coefficients), writes dJ/du_sigma^0 into (gC0, gD0).  The forward states
- * are recomputed from checkpoints stored every checkpoint_every steps.
+/* Discrete adjoint of oecdg_run with a fixed step: the transpose of the
+ * derivative of the fully discrete scheme of Sec. 2.2 (SSP-RK3 stages of
+ * eq. RKCDG, each followed by F_tau).  Given u_sigma^0 = (uC0, uD0), nsteps
+ * steps of size dt = tau = tau_max and the gradient (gC_T, gD_T) of a loss J
+ * with respect to u_sigma^N (in modal coefficients), writes dJ/du_sigma^0 into
+ * (gC0, gD0).  1D single-instance handles with a scalar flux (advection or
+ * Burgers) on a periodic mesh; EUNSUPPORTED otherwise; EINVAL for nsteps < 0,
+ * dt <= 0 or checkpoint_every < 1.  The forward states are recomputed from
+ * checkpoints stored every checkpoint_every steps; the library-owned workspace
+ * (checkpoints plus two segments of stage states) grows on demand (ENOMEM if it
+ * cannot).  The recomputation of a segment runs on a second library-owned
+ * stream, overlapped with the reverse stages of the next one; all of it has
+ * finished when the call returns (the call synchronises the handle's stream).
  * Non-smooth points follow fixed conventions: d|x|/dx = 0 at x = 0, the
  * maximum in sigma is attributed to the first maximiser in storage order, a
- * vanishing sigma contributes no derivative.  Device pointers. */
+ * vanishing sigma contributes no derivative.  Device pointers; every input
+ * is copied into the workspace before an output is written, so the outputs
+ * may alias the inputs. */
 int oecdg_adjoint(oecdg_handle *h, const double *uC0, const double *uD0, int64_t nsteps, double dt,
                   const double *gC_T, const double *gD_T, double *gC0, double *gD0,
                   int32_t checkpoint_every);
 
+/* Release the handle and everything it owns (NULL is allowed).  Waits for the
+ * library's own streams; work the caller enqueued on its stream is not waited for. */
 void oecdg_destroy(oecdg_handle *h);
 
 /* Static description of an error code. */

@@ -201,7 +201,7 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
     constexpr bool RK = MODE != ADJ_PREP, OE = MODE != ADJ_RK_PLAIN;
     constexpr bool PREP = MODE == ADJ_PREP || MODE == ADJ_RK_PREP, GSIG = MODE == ADJ_RK || MODE == ADJ_RK_PREP;
     constexpr int ROW1 = 5 + 2 * 4, ROW2 = 1 + 2 * 2;
-    static_assert(ADJ_NW * (ROW1 + ROW2) <= 64, "scratch holds one row per wave and round");
+    static_assert(ADJ_NW * (ROW1 + ROW2) <= 64, "scratch holds one row per wave and pass");
     __shared__ double scratch[64];
     const int n = a.n, tid = threadIdx.x;
     const int mesh = blockIdx.x >= (unsigned)a.nb;
@@ -220,7 +220,10 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
         load_mu<K, OE>(a, mesh, cc, inJ);
         load_mu<K, OE>(a, other, user_left(mesh, cc, n), inL);     // cc overlaps its left half
         load_mu<K, OE>(a, other, user_right(mesh, cc, n), inR);    // cc overlaps its right half
-        if constexpr (!PREP) load_cell<K>(a.s + mesh * a.S, n, cc, sJ);   // else s_l = F(h_l), formed below
+        // s_l: for l = 0 the damped u^n the forward stage stored (also at a
+        // segment start, where h of the step before is not at hand); for
+        // l > 0 with preparation it is formed below as F_tau(h_l)
+        load_cell<K>(a.s + mesh * a.S, n, cc, sJ);
         load_cell<K>(a.acc + mesh * a.S, n, cc, accv);            // unused when acc_init
     } else {
         load_cell<K>(a.lam + mesh * a.S, n, cc, lam);
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
         }
     }
 
-    // ---- round 1: global terms of the stage above and the forward statistics of h
+    // ---- first reduction pass: global terms of the stage above and the forward statistics of h
     SigmaTerm t;
     t.w[0] = t.w[1] = 0.0;
     t.cell[0] = t.cell[1] = -1;
@@ -367,8 +370,10 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
             facj[j] = exp(-a.tau * S);
         }
         if constexpr (RK) {
+            if (!a.stage0) {
 #pragma unroll
-            for (int q = 0; q <= K; ++q) sJ[q] = own[q] * facj[q];
+                for (int q = 0; q <= K; ++q) sJ[q] = own[q] * facj[q];
+            }
         }
     }
 

@@ -69,15 +69,42 @@ def test_adjoint_advection():
     assert e <= ADJ_TOL
 
 
-def test_checkpoint_interval_does_not_change_the_gradient():
-    prob, uC, uD, tC, tD, tau, steps = _setup(192, 2, 33)
+@pytest.mark.parametrize("n,steps", [(192, 33), (160, 41)])
+def test_checkpoint_interval_does_not_change_the_gradient(n, steps):
+    """Bitwise: the reverse stage of a step's first stage always uses the
+    damped u^n the forward stored, so where the segments start does not
+    matter."""
+    prob, uC, uD, tC, tD, tau, steps = _setup(n, 2, steps)
     rng = np.random.default_rng(5)
     gC, gD = rng.normal(size=uC.shape), rng.normal(size=uD.shape)
-    a = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 20)
-    b = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 7)
-    c = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 1000)
-    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
-    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    ref = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 1000)
+    for ck in (1, 2, 3, 4, 5, 7, 10, 20):
+        a = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, ck)
+        assert np.array_equal(a[0], ref[0]) and np.array_equal(a[1], ref[1]), ck
+
+
+def test_repeated_calls_on_one_handle_and_aliased_outputs():
+    """One handle, several calls with changing checkpoint intervals (the
+    workspace grows and is reused; the recomputation stream and its events are
+    reused) gives the bits of a fresh handle, and the outputs may alias the
+    seed gradient (the inputs are copied before any output is written)."""
+    from paper_2503_12473_amd.api import _ptr
+    prob, uC, uD, tC, tD, tau, steps = _setup(160, 2, 41)
+    rng = np.random.default_rng(9)
+    gC, gD = rng.normal(size=uC.shape), rng.normal(size=uD.shape)
+    ref = _gpu_grad(prob, uC, uD, steps, tau, gC, gD, 20)
+    with OECDG(prob, 0.3) as s:
+        u0 = (to_device(uC), to_device(uD))
+        for ck in (3, 20, 7, 41):
+            a, b = s.adjoint(u0[0], u0[1], steps, tau, to_device(gC), to_device(gD), ck)
+            assert np.array_equal(a.cpu().numpy().reshape(uC.shape), ref[0])
+            assert np.array_equal(b.cpu().numpy().reshape(uD.shape), ref[1])
+        gCt, gDt = to_device(gC), to_device(gD)
+        rc = s._L.oecdg_adjoint(s._h, _ptr(u0[0], "uC0"), _ptr(u0[1], "uD0"), steps, float(tau),
+                                _ptr(gCt, "gC_T"), _ptr(gDt, "gD_T"), _ptr(gCt, "gC0"), _ptr(gDt, "gD0"), 7)
+        assert rc == 0
+        assert np.array_equal(gCt.cpu().numpy().reshape(uC.shape), ref[0])
+        assert np.array_equal(gDt.cpu().numpy().reshape(uD.shape), ref[1])
 
 
 def test_adjoint_is_linear_in_the_seed():
