@@ -142,3 +142,26 @@ def test_conservation_and_positivity_64():
         s1 = u1[:, 0, 0].sum(axis=(1, 2))
         assert np.all(np.abs(s1 - s0) <= 1e-12 * np.abs(u0[:, 0, 0]).sum(axis=(1, 2)))
         assert np.all(u1[0, 0, 0] > 0.0)
+
+
+@pytest.mark.timeout(300)
+def test_full_workload_conserves_stays_physical_and_repeats():
+    """The 2D workload at full size (1024^2 primal + dual, Q2, CFL 0.3, 500
+    steps), beyond what the oracle can run: the cell averages of every
+    component sum to their initial values on each mesh (the operator is
+    conservative and OE keeps the averages), density and pressure stay
+    positive at every cell average, and a second run gives the same bits."""
+    prob, uC, uD = _quadrants(1024, 0)
+    g, t, n = _gpu_run(prob, uC, uD, 0.3, nsteps=500)
+    assert n == 500 and np.isfinite(t)
+    g2, t2, n2 = _gpu_run(prob, uC, uD, 0.3, nsteps=500)
+    assert n2 == n and t2 == t and np.array_equal(g[0], g2[0]) and np.array_equal(g[1], g2[1])
+    gamma = prob.gamma
+    for u0, u1 in ((uC, g[0]), (uD, g[1])):
+        assert np.isfinite(u1).all()
+        s0 = u0[:, 0, 0].sum(axis=(1, 2))
+        s1 = u1[:, 0, 0].sum(axis=(1, 2))
+        assert np.all(np.abs(s1 - s0) <= 1e-11 * np.abs(u0[:, 0, 0]).sum(axis=(1, 2))), (s0, s1)
+        rho, mx, my, E = u1[0, 0, 0], u1[1, 0, 0], u1[2, 0, 0], u1[3, 0, 0]
+        p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / rho)
+        assert rho.min() > 0.0 and p.min() > 0.0
