@@ -97,3 +97,39 @@ def test_k2_variant_and_autotuned_tile():
         bC = gC[offC[b]:offC[b + 1]].reshape(rC.shape)
         bD = gD[offD[b]:offD[b + 1]].reshape(rD.shape)
         assert _rel(bC, bD, rC, rD) <= TOL, b
+
+
+@pytest.mark.timeout(900)
+def test_full_workload_sampled():
+    """The 512-instance workload at full length (seed 0, 1000 steps, autotuned
+    tile), as the benchmark runs it: sampled instances (the smallest, the
+    largest, the first of each degree, fixed positions) are bitwise equal to
+    the same instance advanced alone with the same tile, and the two smallest
+    match their own oracle runs over all 1000 steps."""
+    specs = inputs.batch_instances(seed=0, count=512)
+    probs, states = _build(specs)
+    inf = float("inf")
+    with OECDG(probs, 0.15) as s:
+        gC = torch.cat([to_device(u[0]) for u in states])
+        gD = torch.cat([to_device(u[1]) for u in states])
+        tile = tune_tile(s, gC, gD, steps=5)
+        s.run(gC, gD, nsteps=1000, t_end=inf)
+        offC, offD = s.off_primal, s.off_dual
+        gC, gD = gC.cpu().numpy(), gD.cpu().numpy()
+    out = lambda b: (gC[offC[b]:offC[b + 1]].reshape(states[b][0].shape),
+                     gD[offD[b]:offD[b + 1]].reshape(states[b][1].shape))
+    order = np.argsort([n for n, _, _ in specs], kind="stable")
+    picks = {int(order[0]), int(order[1]), int(order[-1]), 0, 255, 511}
+    for kk in (1, 2, 3):
+        picks.add(next(b for b, (_, k, _) in enumerate(specs) if k == kk))
+    print(f"[batched] tile {tile}, sampled instances {sorted(picks)}", flush=True)
+    for b in sorted(picks):
+        solo = _run_batch([probs[b]], [states[b]], tile=tile, nsteps=1000, t_end=inf)[0]
+        o = out(b)
+        assert np.array_equal(solo[0], o[0]) and np.array_equal(solo[1], o[1]), b
+    for b in (int(order[0]), int(order[1])):
+        rC, rD, _, rn = ora.run1d(probs[b], states[b][0], states[b][1], nsteps=1000, cfl=0.15)
+        assert rn == 1000
+        e = _rel(*out(b), rC, rD)
+        print(f"[batched] instance {b} (N={specs[b][0]}, k={specs[b][1]}) vs oracle {e:.3e}", flush=True)
+        assert e <= TOL, b
