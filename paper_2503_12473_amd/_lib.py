@@ -1,7 +1,8 @@
 """ctypes binding of liboecdg.so (the C ABI in include/oecdg.h).
 
 Argument marshalling only: every step of the method runs in the HIP
-library.  Importing this module fails loudly if the library is not built.
+library.  The first use (lib(), hence every solver handle) fails loudly if
+the library is not built; there is no other implementation to fall back on.
 """
 from __future__ import annotations
 

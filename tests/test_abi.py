@@ -70,3 +70,16 @@ def test_strerror_covers_every_code():
     L = _lib.lib()
     for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert L.oecdg_strerror(code).decode() != "unknown error"
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library a solver handle cannot be made: the binding
+    raises instead of computing anything another way."""
+    from paper_2503_12473_amd import api, inputs
+    monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(os.path.dirname(_lib.LIB_PATH), "missing", "liboecdg.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError, match="missing"):
+        _lib.lib()
+    prob, _, _ = inputs.advection_sine(16, 2)
+    with pytest.raises(ImportError):
+        api.OECDG(prob, 0.2)
