@@ -224,29 +224,32 @@ __device__ inline int tile_of_block(int nt) {
 
 // Both meshes' state of a tile with a one-cell halo into LDS:
 // tile[(mesh*NE + entry)*NCELL + ly*W + lx], global cell (i0-1+lx, j0-1+ly).
+// A thread keeps one cell of the tile (its wrapped global index computed
+// once) and walks the rows (mesh, entry) in steps of NT / NCELL, so that each
+// load costs a pointer select and one multiply-add.
 template <int NE, int TX, int TY, int NT>
 __device__ inline void stage_tile2d(double *tile, const double *inC, const double *inD, int i0, int j0, int nx,
                                     int ny, long long plane) {
-    constexpr int W = TX + 2, H = TY + 2, NCELL = W * H, TOT = 2 * NE * NCELL, NL = (TOT + NT - 1) / NT;
+    constexpr int W = TX + 2, H = TY + 2, NCELL = W * H, NROW = 2 * NE;
+    constexpr int RPT = NT / NCELL, NIT = (NROW + RPT - 1) / RPT;    // rows per pass, passes
+    static_assert(RPT >= 1, "one pass covers every cell of the tile");
+    const int tid = threadIdx.x;
+    if (tid >= RPT * NCELL) return;
+    const int cell = tid % NCELL, r0 = tid / NCELL;
     const bool small = nx < W || ny < H;
-    double v[NL];
+    const int gx = wrap_idx(i0 - 1 + cell % W, nx, small);
+    const int gy = wrap_idx(j0 - 1 + cell / W, ny, small);
+    const long long g = (long long)gy * nx + gx;
+    double v[NIT];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int e = threadIdx.x + i * NT;
-        v[i] = 0.0;
-        if (e < TOT) {
-            const int cell = e % NCELL, rest = e / NCELL;
-            const int mesh = rest / NE, ent = rest % NE;
-            const int gx = wrap_idx(i0 - 1 + cell % W, nx, small);
-            const int gy = wrap_idx(j0 - 1 + cell / W, ny, small);
-            const double *src = mesh == 0 ? inC : inD;
-            v[i] = src[ent * plane + (long long)gy * nx + gx];
-        }
+    for (int i = 0; i < NIT; ++i) {
+        const int r = min(r0 + i * RPT, NROW - 1);                   // past the last row: a valid duplicate
+        v[i] = (r < NE ? inC + r * plane : inD + (r - NE) * plane)[g];
     }
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int e = threadIdx.x + i * NT;
-        if (e < TOT) tile[e] = v[i];
+    for (int i = 0; i < NIT; ++i) {
+        const int r = r0 + i * RPT;
+        if (r < NROW) tile[r * NCELL + cell] = v[i];
     }
 }
 
@@ -310,13 +313,23 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
             for (int j = 0; j < K; ++j) fac[(fmesh * K + j) * NCELL + fcell] = fj[j];
         }
         __syncthreads();
-        // mode (a, b) != (0, 0) takes the factor of total degree min(a + b, K)
-        for (int e = tid; e < NDAMP * NE; e += NT) {
-            const int cs = e % NDAMP, ent = e / NDAMP;
+        // mode (a, b) != (0, 0) takes the factor of total degree min(a + b, K);
+        // a thread keeps one damped cell and walks its entries
+        constexpr int RD = NT / NDAMP, NID = (NE + RD - 1) / RD;
+        static_assert(RD >= 1, "one pass covers every damped cell");
+        if (tid < RD * NDAMP) {
+            const int cs = tid % NDAMP, e0 = tid / NDAMP;
             const int mesh = cs / ND1, rr = cs % ND1;
             const int cell = (rr / (TX + 1) + mesh) * W + rr % (TX + 1) + mesh;
-            const int ab = ent % (K1 * K1), deg = ab / K1 + ab % K1;
-            if (deg > 0) tile[(mesh * NE + ent) * NCELL + cell] *= fac[(mesh * K + (deg < K ? deg : K) - 1) * NCELL + cell];
+            double f[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) f[j] = fac[(mesh * K + j) * NCELL + cell];
+#pragma unroll
+            for (int i = 0; i < NID; ++i) {
+                const int ent = e0 + i * RD;
+                const int ab = ent % (K1 * K1), deg = ab / K1 + ab % K1;
+                if (ent < NE && deg > 0) tile[(mesh * NE + ent) * NCELL + cell] *= f[(deg < K ? deg : K) - 1];
+            }
         }
     }
     __syncthreads();
