@@ -648,7 +648,10 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
 // lane per edge; then the tile's partial statistics (sums of averages, sample
 // max / min per component, largest wave speeds) with one lane per component.
 template <int K, int FLUX, int TX, int TY>
-__global__ __launch_bounds__(8 * TX * TY) void k_delta2d(Stage2Args a) {
+// Two workgroups per CU (4 waves per SIMD; the LDS tile allows no more): the
+// register cap spills a few values to scratch, which costs less than running
+// one workgroup per CU (6.86 -> 6.32 ms per step on the 1024^2 workload).
+__global__ __launch_bounds__(8 * TX * TY, 4) void k_delta2d(Stage2Args a) {
     using F = Flux2D<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1, Q = K + 1, NE = NC * K1 * K1, NSP = 2 * K + 4;
     constexpr int W = TX + 2, NCELL = W * (TY + 2), NT = 8 * TX * TY, NW = NT / WAVE;
@@ -689,31 +692,43 @@ __global__ __launch_bounds__(8 * TX * TY) void k_delta2d(Stage2Args a) {
         double* N = mesh == 0 ? a.numC : a.numD;
 #pragma unroll 1
         for (int q = 0; q < NC; ++q) {
-            // traces restricted to the edge, by normal derivative order:
-            // own at the edge (normal coordinate +-1), other at its centre line (0)
-            double ro[K1][K1], rt[2][K1][K1];
+            // traces restricted to the edge, by normal derivative order: own at
+            // the edge (normal coordinate +-1); the other mesh at its centre
+            // line (0), one half-edge at a time (each mean[m] still sums the
+            // half-edges in order)
+            double ro[K1][K1];
 #pragma unroll
             for (int dn = 0; dn < K1; ++dn)
 #pragma unroll
                 for (int t = 0; t < K1; ++t) {
-                    double so = 0.0, s0 = 0.0, s1 = 0.0;
+                    double so = 0.0;
 #pragma unroll
                     for (int n = 0; n < K1; ++n) {
                         const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
-                        const double ev = edge_val(tb.e1[dn][n], n, dn, side);
-                        so += own[ent * NCELL + cell] * ev;
-                        s0 += oth[ent * NCELL + oc[0]] * tb.e0[dn][n];
-                        s1 += oth[ent * NCELL + oc[1]] * tb.e0[dn][n];
+                        so += own[ent * NCELL + cell] * edge_val(tb.e1[dn][n], n, dn, side);
                     }
                     ro[dn][t] = so;
-                    rt[0][dn][t] = s0;
-                    rt[1][dn][t] = s1;
                 }
+            double mean[K1];
 #pragma unroll
-            for (int m = 0; m < K1; ++m) {
-                double mean = 0.0;
+            for (int m = 0; m < K1; ++m) mean[m] = 0.0;
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < 2; ++h) {
+                double rt[K1][K1];
+#pragma unroll
+                for (int dn = 0; dn < K1; ++dn)
+#pragma unroll
+                    for (int t = 0; t < K1; ++t) {
+                        double sh = 0.0;
+#pragma unroll
+                        for (int n = 0; n < K1; ++n) {
+                            const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
+                            sh += oth[ent * NCELL + oc[h]] * tb.e0[dn][n];
+                        }
+                        rt[dn][t] = sh;
+                    }
+#pragma unroll
+                for (int m = 0; m < K1; ++m)
 #pragma unroll
                     for (int g = 0; g < Q; ++g) {
                         double ss = 0.0;
@@ -728,19 +743,22 @@ __global__ __launch_bounds__(8 * TX * TY) void k_delta2d(Stage2Args a) {
 #pragma unroll
                             for (int t = 0; t < K1; ++t) {
                                 vo += ro[dn][t] * tb.own[dt][h][g][t];
-                                vt += rt[h][dn][t] * tb.nb[dt][h][g][t];
+                                vt += rt[dn][t] * tb.nb[dt][h][g][t];
                             }
                             const double d = sct * (vo - vt);
                             ss = m == 0 ? fabs(d) : ss + d * d;
                             scn *= 2.0 / hn;
                         }
-                        mean += 0.25 * tb.w[g] * (m == 0 ? ss : sqrt(ss));   // |d| = (d^2)^(1/2) for m = 0
+                        mean[m] += 0.25 * tb.w[g] * (m == 0 ? ss : sqrt(ss));   // |d| = (d^2)^(1/2) for m = 0
                     }
+            }
+#pragma unroll
+            for (int m = 0; m < K1; ++m) {
                 double hm = 1.0;                          // h_e^(m-1)
                 if (m == 0) hm = 1.0 / hn;
 #pragma unroll
                 for (int j = 1; j < m; ++j) hm *= hn;
-                const double num = quad_sum(beta * tb.cdel[m] * hm * mean);
+                const double num = quad_sum(beta * tb.cdel[m] * hm * mean[m]);
                 if (valid && lane4 == (m & 3)) N[(m * NC + q) * a.plane + gofs] = num;
             }
         }
@@ -748,11 +766,14 @@ __global__ __launch_bounds__(8 * TX * TY) void k_delta2d(Stage2Args a) {
 
     // ---- partial statistics: component cq of this cell, all sample rows for
     // a component lane (Euler), rows i = lane (mod 4) for one component
+    // (a wave holds cells of one mesh only, so a thread keeps the rows of its
+    // own mesh, (sum, max, min) per component, and the two wave-speed rows)
     constexpr bool LANE_COMP = NC == 4;
+    constexpr int NM = 3 * NC;
     const int cq = LANE_COMP ? lane4 : 0;
-    double vals[NR];
+    double vals[NM + 2];
 #pragma unroll
-    for (int j = 0; j < NR; ++j) vals[j] = j < 2 * NC * 3 ? stat_identity(j % 3) : -INFINITY;
+    for (int j = 0; j < NM + 2; ++j) vals[j] = j < NM ? stat_identity(j % 3) : -INFINITY;
     if (valid) {
         double cst[K1][K1];
 #pragma unroll
@@ -781,31 +802,32 @@ __global__ __launch_bounds__(8 * TX * TY) void k_delta2d(Stage2Args a) {
             }
         }
 #pragma unroll
-        for (int m2 = 0; m2 < 2; ++m2)
-#pragma unroll
-            for (int q = 0; q < NC; ++q) {
-                if (m2 != mesh || q != cq) continue;
-                vals[row2(NC, m2, q, 0)] = (LANE_COMP || lane4 == 0) ? cst[0][0] : 0.0;
-                vals[row2(NC, m2, q, 1)] = mx;
-                vals[row2(NC, m2, q, 2)] = mn;
-            }
+        for (int q = 0; q < NC; ++q) {
+            if (q != cq) continue;
+            vals[3 * q] = (LANE_COMP || lane4 == 0) ? cst[0][0] : 0.0;
+            vals[3 * q + 1] = mx;
+            vals[3 * q + 2] = mn;
+        }
         if (lane4 == 0) {
-            vals[2 * NC * 3] = F::speed(0, ubar, a.fp);
-            vals[2 * NC * 3 + 1] = F::speed(1, ubar, a.fp);
+            vals[NM] = F::speed(0, ubar, a.fp);
+            vals[NM + 1] = F::speed(1, ubar, a.fp);
             if (!F::physical(ubar, a.fp)) a.err[1] = 1;
         }
     }
     {
-        // a wave holds cells of one mesh only: the other mesh's rows are the
-        // identity there and are not reduced
+        // the wave's own mesh rows and the wave speeds are reduced; the other
+        // mesh's rows are the identity in this wave
         static_assert((4 * TX * TY) % WAVE == 0, "waves do not straddle the meshes");
         const int lane = tid % WAVE, wave = tid / WAVE, wmesh = wave / (4 * TX * TY / WAVE);
 #pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            const int kind = j < 2 * NC * 3 ? j % 3 : 1;
-            const bool mine = j >= 2 * NC * 3 || j / (NC * 3) == wmesh;
-            const double v = mine ? wave_reduce(kind, vals[j]) : stat_identity(kind);
-            if (lane == WAVE - 1) red[wave * NR + j] = v;
+        for (int j = 0; j < NM + 2; ++j) {
+            const int kind = j < NM ? j % 3 : 1;
+            const double v = wave_reduce(kind, vals[j]);
+            if (lane == WAVE - 1) red[wave * NR + (j < NM ? row2(NC, wmesh, j / 3, j % 3) : 2 * NM + (j - NM))] = v;
+        }
+        if (lane == WAVE - 1) {
+#pragma unroll
+            for (int j = 0; j < NM; ++j) red[wave * NR + row2(NC, 1 - wmesh, j / 3, j % 3)] = stat_identity(j % 3);
         }
         __syncthreads();
         if (tid < NR) {
