@@ -214,3 +214,35 @@ def test_nonphysical_state_is_reported():
     with pytest.raises(_lib.OECDGError) as e:
         gpu_run(prob, uC, uD, 0.15, nsteps=2)
     assert e.value.code == _lib.ENONPHYSICAL
+
+
+def test_many_handles_create_and_destroy():
+    """Handles release what they own: creating, running and destroying many
+    (1D single, 1D batch, 2D, with graph capture and the adjoint's second
+    stream) leaves device memory where it was and every call succeeds."""
+    import gc
+    prob1, uC1, uD1 = inputs.euler_riemann(20000, 2, inputs.riemann_states(0))   # ~10 MB of handle memory
+    prob2, uC2, uD2, _ = inputs.euler2d_quadrants(64, 2, seed=0)
+    probb, uCb, uDb, _ = inputs.burgers_fourier(64, 2, seed=0)
+    tau = 0.3 * probb.h / np.abs(uCb[0, 0]).max()
+
+    def cycle():
+        with OECDG(prob1, 0.15) as s:
+            s.run(to_device(uC1), to_device(uD1), nsteps=70)          # graph capture (64-step chunks)
+        with OECDG([prob1, prob1], 0.15) as s:
+            s.run(torch.cat([to_device(uC1)] * 2), torch.cat([to_device(uD1)] * 2), nsteps=5)
+        with OECDG(prob2, 0.3) as s:
+            s.run(to_device(uC2), to_device(uD2), nsteps=3)
+        with OECDG(probb, 0.3) as s:
+            s.adjoint(to_device(uCb), to_device(uDb), 9, tau, to_device(uCb), to_device(uDb), 4)
+
+    cycle()
+    torch.cuda.synchronize()
+    gc.collect()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(20):
+        cycle()
+    torch.cuda.synchronize()
+    gc.collect()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert free0 - free1 < 16 << 20, (free0, free1)          # a leak would be >= 200 MB here
