@@ -136,18 +136,19 @@ class Scalar1D:
         LC, LD = self.rhs(*s2, tm)
         return F(uC / 3.0 + (2.0 / 3.0) * (s2[0] + tau * LC), uD / 3.0 + (2.0 / 3.0) * (s2[1] + tau * LD))
 
-    def run(self, uC, uD, nsteps, tau, checkpoint_every=0):
-        """nsteps fixed steps; with checkpoint_every > 0 each segment is
-        recomputed in the backward pass (torch.utils.checkpoint)."""
+    def run(self, uC, uD, nsteps, tau, checkpoint_every=0, oe=True):
+        """nsteps fixed steps (oe=False: plain CDG, no OE step); with
+        checkpoint_every > 0 each segment is recomputed in the backward pass
+        (torch.utils.checkpoint)."""
         if checkpoint_every <= 0:
             for _ in range(nsteps):
-                uC, uD = self.step(uC, uD, tau)
+                uC, uD = self.step(uC, uD, tau, oe=oe)
             return uC, uD
         from torch.utils.checkpoint import checkpoint
 
         def seg(a, b, m):
             for _ in range(m):
-                a, b = self.step(a, b, tau)
+                a, b = self.step(a, b, tau, oe=oe)
             return a, b
         done = 0
         while done < nsteps:
@@ -169,18 +170,19 @@ class _one_thread:
         torch.set_num_threads(self.n)
 
 
-def gradient(prob, uC0, uD0, nsteps, tau, gC_T, gD_T, checkpoint_every=20):
+def gradient(prob, uC0, uD0, nsteps, tau, gC_T, gD_T, checkpoint_every=20, oe=True):
     """d<gT, u(T)>/du0 for the fixed-step run (numpy in, numpy out); the
-    gradient of any loss J is obtained with gT = dJ/du(T)."""
+    gradient of any loss J is obtained with gT = dJ/du(T).  oe=False: the
+    plain CDG scheme."""
     with _one_thread():
-        return _gradient(prob, uC0, uD0, nsteps, tau, gC_T, gD_T, checkpoint_every)
+        return _gradient(prob, uC0, uD0, nsteps, tau, gC_T, gD_T, checkpoint_every, oe)
 
 
-def _gradient(prob, uC0, uD0, nsteps, tau, gC_T, gD_T, checkpoint_every):
+def _gradient(prob, uC0, uD0, nsteps, tau, gC_T, gD_T, checkpoint_every, oe=True):
     s = Scalar1D(prob)
     a = torch.tensor(uC0[0], dtype=DT, requires_grad=True)
     b = torch.tensor(uD0[0], dtype=DT, requires_grad=True)
-    oC, oD = s.run(a, b, nsteps, tau, checkpoint_every)
+    oC, oD = s.run(a, b, nsteps, tau, checkpoint_every, oe=oe)
     (oC * torch.tensor(gC_T[0], dtype=DT)).sum().add((oD * torch.tensor(gD_T[0], dtype=DT)).sum()).backward()
     return a.grad.numpy()[None].copy(), b.grad.numpy()[None].copy()
 

@@ -78,3 +78,27 @@ def test_tangent_linear_and_adjoint_are_transposes(flux):
     gC, gD = adj.gradient(prob, uC, uD, steps, tau, wC, wD, checkpoint_every=7)
     ad = float((gC * vC).sum() + (gD * vD).sum())
     assert abs(tl - ad) <= 1e-12 * max(abs(tl), abs(ad)), (tl, ad)
+
+
+def test_plain_cdg_forward_and_gradient():
+    """oe=False (plain CDG, the adjoint's mode without OE): the forward equals
+    the C oracle's plain run and the gradient matches central differences."""
+    prob, uC, uD, tC, tD, tau, steps = _setup(k=2, steps=25)
+    s = adj.Scalar1D(prob)
+    import torch
+    with torch.no_grad():
+        a, b = s.run(torch.tensor(uC[0]), torch.tensor(uD[0]), steps, tau, oe=False)
+    rC, rD, _, _ = ora.run1d(prob, uC, uD, nsteps=steps, dt_fixed=tau, oe=False)
+    scale = max(np.abs(rC).max(), np.abs(rD).max())
+    assert max(np.abs(a.numpy() - rC[0]).max(), np.abs(b.numpy() - rD[0]).max()) <= 1e-13 * scale
+    _, gC, gD = adj.misfit_loss_grad(prob, rC, rD, tC, tD)
+    dC, dD = adj.gradient(prob, uC, uD, steps, tau, gC, gD, checkpoint_every=6, oe=False)
+    rng = np.random.default_rng(8)
+    vC, vD = rng.normal(size=uC.shape), rng.normal(size=uD.shape)
+    exact = float((dC * vC).sum() + (dD * vD).sum())
+    errs = []
+    for eps in (1e-5, 1e-6, 1e-7):
+        J = lambda sgn: adj.misfit_loss_grad(prob, *ora.run1d(prob, uC + sgn * eps * vC, uD + sgn * eps * vD,
+                                                               nsteps=steps, dt_fixed=tau, oe=False)[:2], tC, tD)[0]
+        errs.append(abs((J(1) - J(-1)) / (2 * eps) - exact) / abs(exact))
+    assert min(errs) <= 1e-6, errs

@@ -57,6 +57,22 @@ def test_adjoint_matches_cpu_adjoint(k):
     assert e <= ADJ_TOL
 
 
+@pytest.mark.parametrize("k,oe", [(0, True), (2, False)])
+def test_adjoint_without_oe_matches_cpu_adjoint(k, oe):
+    """The reverse stage without OE (k = 0 has nothing to damp; k = 2 with OE
+    switched off): Burgers, N = 256, 30 steps, checkpoints every 7."""
+    prob, uC, uD, tC, tD, tau, steps = _setup(256, k, 30)
+    rng = np.random.default_rng(12)
+    gC, gD = rng.normal(size=uC.shape), rng.normal(size=uD.shape)
+    with OECDG(prob, 0.3, oe=oe) as s:
+        a, b = s.adjoint(to_device(uC), to_device(uD), steps, tau, to_device(gC), to_device(gD), 7)
+        g = a.cpu().numpy().reshape(uC.shape), b.cpu().numpy().reshape(uD.shape)
+    r = adj.gradient(prob, uC, uD, steps, tau, gC, gD, checkpoint_every=7, oe=oe and k > 0)
+    e = _rel(g[0], g[1], r[0], r[1])
+    print(f"[adjoint] k={k} oe={oe} rel err vs CPU adjoint {e:.3e}", flush=True)
+    assert e <= ADJ_TOL
+
+
 def test_adjoint_advection():
     prob, uC, uD = inputs.advection_sine(128, 2, phase=0.4)
     rng = np.random.default_rng(3)
