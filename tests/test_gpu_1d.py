@@ -246,3 +246,37 @@ def test_many_handles_create_and_destroy():
     gc.collect()
     free1 = torch.cuda.mem_get_info()[0]
     assert free0 - free1 < 16 << 20, (free0, free1)          # a leak would be >= 200 MB here
+
+
+def test_nonfinite_input_is_reported():
+    """A NaN in a higher mode of one cell (the wave speeds, from averages, stay
+    finite): the run stops with ENONFINITE instead of returning NaNs."""
+    prob, uC, uD = inputs.euler_riemann(64, 2, (1.0, 1.0, 0.5, 0.5))
+    uC = uC.copy()
+    uC[1, 2, 20] = float("nan")
+    with pytest.raises(_lib.OECDGError) as e:
+        gpu_run(prob, uC, uD, 0.15, nsteps=3)
+    assert e.value.code == _lib.ENONFINITE
+
+
+def test_adjoint_rejects_what_it_does_not_cover():
+    """oecdg_adjoint: scalar flux on a periodic mesh, one instance, valid
+    arguments; anything else is refused before any work."""
+    rng = np.random.default_rng(0)
+    prob, uC, uD, _ = inputs.burgers_fourier(64, 2, seed=0)
+    g = (to_device(rng.normal(size=uC.shape)), to_device(rng.normal(size=uD.shape)))
+    with OECDG(prob, 0.3) as s:
+        for nsteps, dt, ck in ((-1, 0.01, 4), (5, 0.0, 4), (5, 0.01, 0)):
+            with pytest.raises(_lib.OECDGError) as e:
+                s.adjoint(to_device(uC), to_device(uD), nsteps, dt, g[0], g[1], ck)
+            assert e.value.code == _lib.EINVAL
+    pe, eC, eD = inputs.euler_riemann(64, 2, (1.0, 1.0, 0.5, 0.5))
+    with OECDG(pe, 0.15) as s:
+        with pytest.raises(_lib.OECDGError) as e:
+            s.adjoint(to_device(eC), to_device(eD), 3, 0.001, to_device(eC), to_device(eD), 2)
+        assert e.value.code == _lib.EUNSUPPORTED
+    with OECDG([prob, prob], 0.3) as s:
+        two = (torch.cat([to_device(uC)] * 2), torch.cat([to_device(uD)] * 2))
+        with pytest.raises(_lib.OECDGError) as e:
+            s.adjoint(two[0], two[1], 3, 0.01, two[0], two[1], 2)
+        assert e.value.code == _lib.EUNSUPPORTED

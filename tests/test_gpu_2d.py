@@ -165,3 +165,14 @@ def test_full_workload_conserves_stays_physical_and_repeats():
         rho, mx, my, E = u1[0, 0, 0], u1[1, 0, 0], u1[2, 0, 0], u1[3, 0, 0]
         p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / rho)
         assert rho.min() > 0.0 and p.min() > 0.0
+
+
+def test_nonfinite_input_is_reported():
+    """A NaN in a higher mode of one cell: the 2D run stops with ENONFINITE."""
+    from paper_2503_12473_amd import _lib
+    prob, uC, uD = _quadrants(16, 0)
+    uC = uC.copy()
+    uC[2, 1, 1, 5, 7] = float("nan")
+    with pytest.raises(_lib.OECDGError) as e:
+        _gpu_run(prob, uC, uD, 0.3, nsteps=3)
+    assert e.value.code == _lib.ENONFINITE
