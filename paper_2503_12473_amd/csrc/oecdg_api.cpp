@@ -389,7 +389,7 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
     double *bpv[2] = {buf + 9 * S2, buf + 9 * S2 + bpsz};
     double *slotmem = bpv[1] + bpsz;
     // stage states and partials of step j of the segment in buffer b
-    auto st = [&](int b, long long j, int which) {           // 0 s0,1 h1,2 s1,3 h2,4 s2,5 h3
+    auto st = [&](int b, long long j, int which) {           // 0 s0 (damped u^n), 1 h1, 3 h2, 5 h3 (2, 4 unused)
         return segb[b] + ((size_t)j * 6 + which) * S2;
     };
     auto pp = [&](int b, long long j, int l) { return segb[b] + (size_t)ckpt * 6 * S2 + ((size_t)j * 3 + l) * psz; };
