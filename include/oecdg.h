@@ -7,8 +7,9 @@
  * The library advances the pair (u^C, u^D) of piecewise polynomials on the
  * primal mesh and the dual mesh (Sec. 2.1, the semi-discrete CDG system
  * equcdg) with the fully discrete RK-OECDG scheme (Sec. 2.2, eq. RKCDG):
- * an SSP-RK3 stage update followed, after every stage, by the OE step F_tau
- * (damping ODE OEstep2D, solved exactly).
+ * an RK stage update (SSP-RK3 unless the descriptor asks for another method)
+ * followed, after every stage, by the OE step F_tau (damping ODE OEstep2D,
+ * solved exactly).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -93,7 +94,13 @@ typedef struct {
     double flux_param[2];       /* advection: speeds (a, b); Euler: {gamma, 0}; Burgers: unused */
     double cfl;                 /* C_CFL */
     int32_t oe;                 /* 1: OECDG (OE step after every stage); 0: plain CDG */
-    int32_t reserved;           /* must be 0 */
+    int32_t rk;                 /* time integrator, as the c/d table of eq. RKCDG (Sec. 4 runs accuracy
+                                 * tests with an RK method of order k+1):
+                                 * 0 or 3: SSP-RK3 (Shu-Osher), 1: forward Euler, 2: SSP-RK2 (Heun),
+                                 * 4: classical fourth-order RK, whose last stage
+                                 * -u^n/3 + u^1/3 + 2u^2/3 + u^3/3 + tau/6 L(u^3) uses the damped stage
+                                 * values (library-owned buffer of one state).  2D: 0 or 3 only
+                                 * (EUNSUPPORTED otherwise); all instances of a batch use one method. */
 } oecdg_desc;
 
 /* Number of doubles of the primal and dual state arrays of one instance. */
@@ -121,7 +128,8 @@ int oecdg_set_option(oecdg_handle *h, int32_t key, int64_t value);
  * both meshes).  Device inputs, host output; synchronises the stream. */
 int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out);
 
-/* One SSP-RK3 stage of eq. RKCDG followed by the OE step (OEstep1):
+/* One SSP-RK3 stage of eq. RKCDG followed by the OE step (OEstep1), whatever
+ * the descriptor's rk:
  *   u_sigma^{n,l+1} = F_tau( c_{l0} u^n + c_{ll} u_sigma^{n,l} + tau d_{ll} L(u_sigma^{n,l}) )
  * with (c_{00}, d_{00}) = (1, 1), (c_{10}, c_{11}, d_{11}) = (3/4, 1/4, 1/4),
  * (c_{20}, c_{22}, d_{22}) = (1/3, 2/3, 2/3).  stage in {0, 1, 2}; dt = tau,
@@ -139,7 +147,8 @@ int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max,
  * steps (nsteps < 0: no limit); t_end may be +inf when nsteps >= 0.
  * dt_fixed > 0 replaces the CFL step (tau = tau_max = dt_fixed).  For
  * batches every instance takes the same nsteps/t_end/dt_fixed, each with its
- * own CFL step.  t_out/steps_out (host, may be NULL) receive instance 0's
+ * own CFL step.  Each step runs the stages of the descriptor's RK method, each
+ * followed by F_tau.  t_out/steps_out (host, may be NULL) receive instance 0's
  * final time and step count.  Synchronises the stream. */
 int oecdg_run(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps,
               double dt_fixed, double *t_out, int64_t *steps_out);
@@ -150,7 +159,7 @@ int oecdg_run(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nst
  * steps of size dt = tau = tau_max and the gradient (gC_T, gD_T) of a loss J
  * with respect to u_sigma^N (in modal coefficients), writes dJ/du_sigma^0 into
  * (gC0, gD0).  1D single-instance handles with a scalar flux (advection or
- * Burgers) on a periodic mesh; EUNSUPPORTED otherwise; EINVAL for nsteps < 0,
+ * Burgers) on a periodic mesh and SSP-RK3; EUNSUPPORTED otherwise; EINVAL for nsteps < 0,
  * dt <= 0 or checkpoint_every < 1.  The forward states are recomputed from
  * checkpoints stored every checkpoint_every steps; the library-owned workspace
  * (checkpoints plus two segments of stage states) grows on demand (ENOMEM if it

@@ -17,7 +17,7 @@ from ._lib import Desc, OECDGError, check
 from .inputs import Problem1D, Problem2D, FLUX_EULER
 
 
-def make_desc(prob, cfl: float, oe: bool = True) -> Desc:
+def make_desc(prob, cfl: float, oe: bool = True, rk: int = 3) -> Desc:
     d = Desc()
     if isinstance(prob, Problem1D):
         d.dim, d.ny, d.ylo, d.yhi = 1, 1, 0.0, 1.0
@@ -37,7 +37,7 @@ def make_desc(prob, cfl: float, oe: bool = True) -> Desc:
     d.k, d.flux, d.xlo, d.xhi = prob.k, prob.flux, prob.xlo, prob.xhi
     d.cfl = float(cfl)
     d.oe = 1 if oe else 0
-    d.reserved = 0
+    d.rk = int(rk)
     return d
 
 
@@ -50,15 +50,18 @@ def _ptr(t: torch.Tensor | None, name: str) -> int | None:
 
 
 class OECDG:
-    """A handle of the C library for one problem or a batch of 1D problems."""
+    """A handle of the C library for one problem or a batch of 1D problems.
 
-    def __init__(self, probs, cfl, oe: bool = True, stream: torch.cuda.Stream | None = None):
+    rk selects the time integrator: 3 SSP-RK3 (default), 1 forward Euler,
+    2 SSP-RK2, 4 classical RK4 (1D only for rk != 3)."""
+
+    def __init__(self, probs, cfl, oe: bool = True, stream: torch.cuda.Stream | None = None, rk: int = 3):
         if not isinstance(probs, (list, tuple)):
             probs = [probs]
         cfls = cfl if isinstance(cfl, (list, tuple)) else [cfl] * len(probs)
         self.probs = list(probs)
         self._L = _lib.lib()
-        arr = (Desc * len(probs))(*[make_desc(p, c, oe) for p, c in zip(probs, cfls)])
+        arr = (Desc * len(probs))(*[make_desc(p, c, oe, rk) for p, c in zip(probs, cfls)])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         rc = self._L.oecdg_init(arr, len(probs), C.c_void_p(self.stream.cuda_stream), C.byref(h))

@@ -14,7 +14,8 @@
 //   4. evaluates the CDG operator (equcdg): the overlap coupling with
 //      1/tau_max, the volume integral of f(w) with k+1 Gauss nodes on each
 //      half cell, and the point fluxes of the other mesh at the cell edges;
-//   5. forms the SSP-RK3 combination (eq:RKCDG) and writes the stage output;
+//   5. forms the RK combination of eq:RKCDG (SSP-RK3 by default; forward
+//      Euler, SSP-RK2 or classical RK4 on request) and writes the stage output;
 //   6. writes the tile's partial statistics of that output for the next stage.
 // The OE of the last stage of a run is applied by the final kernel.
 #include "oecdg_device.h"
@@ -344,7 +345,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     const bool lead = (tile == I.tile0) && tid == 0;
     Slot *S = a.slots + 2 * tl.inst;
     const bool single = a.tau_override > 0.0;
-    const int sp = (par + l) & 1;           // parity of the global stage index 3n + l
+    const int sp = ((a.ns & 1 ? par : 0) + l) & 1;   // parity of the global stage index ns n + l
     double *sC = smem, *sD = smem + PER;
     double *red = smem + lds_doubles(K, NC, T);
     double *scratch = red + NSTAT;
@@ -390,13 +391,13 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     if (need_red) finish_partials<NT, NC>(pv, a.part[sp ^ 1], a.ntiles, I.tile0, I.ntiles, ns, red, scratch);
 
     double tau, taumax;
+    int last = 0;
     if (single) {
         tau = a.tau_override;
         taumax = a.taumax_override;
     } else if (l == 0) {
         taumax = a.dt_fixed > 0.0 ? a.dt_fixed : I.cfl * I.h / fmax(red[ST_BETA], red[ST_BETA + 1]);
         tau = taumax;
-        int last = 0;
         if (cur.t + tau >= a.t_end) {
             tau = a.t_end - cur.t;
             last = 1;
@@ -410,14 +411,15 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     } else {
         tau = cur.tau;
         taumax = cur.tau_max;
-        if (l == 2 && lead) {
-            const double tnext = cur.last ? a.t_end : cur.t + tau;
-            S[par ^ 1].t = tnext;
-            Final *f = a.fin + tl.inst;
-            f->t = tnext;
-            f->tau = tau;
-            f->nexec = ld_ll(&f->nexec, coh) + 1;
-        }
+        last = cur.last;
+    }
+    if (!single && l == a.ns - 1 && lead) {   // the step's last stage: time and step count
+        const double tnext = last ? a.t_end : cur.t + tau;
+        S[par ^ 1].t = tnext;
+        Final *f = a.fin + tl.inst;
+        f->t = tnext;
+        f->tau = tau;
+        f->nexec = ld_ll(&f->nexec, coh) + 1;
     }
 
     double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
@@ -467,6 +469,11 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     double r[NC][K1];
     cdg_rate_half<K, FLUX>(nb, hf, I.p0, inv_tm, 1.0 / I.h, r);
 
+    // eq:RKCDG: out = c_{l0} u^n [+ accumulated earlier stages] + c_{ll} u^l + tau d_{ll} L(u^l)
+    const RKStage rs = rk_stage(a.rk, l);
+    const double td = tau * rs.d;
+    double *AM = nullptr;
+    if (rs.acc_read || rs.ca != 0.0) AM = mesh == 0 ? a.AC + I.offC : a.AD + I.offD;
     double out[NC][K1];
     bool finite = true;
 #pragma unroll
@@ -475,12 +482,26 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
         for (int m = 0; m < K1; ++m) {
             const double both = r[q][m] + pair_swap(r[q][m]);   // the two halves (a + b == b + a)
             const double rate = both - inv_tm * own[q][m];
-            const double v = own[q][m] + tau * rate;
-            const double o = (l == 0) ? v : (l == 1 ? 0.75 * un[q][m] + 0.25 * v
-                                                    : (1.0 / 3.0) * un[q][m] + (2.0 / 3.0) * v);
+            const double v = fma(td, rate, rs.cw * own[q][m]);
+            double o = v;
+            if (l > 0) {
+                double base = rs.cn * un[q][m];
+                if (rs.acc_read) base += valid ? AM[(long long)(q * K1 + m) * ncell + gi] : 0.0;
+                o = base + v;
+            }
             out[q][m] = o;
             finite = finite && isfinite(o);
         }
+    if (rs.ca != 0.0 && valid) {           // classical RK4: this stage's damped input joins the sum
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 0; m < K1; ++m)
+                if (((q * K1 + m) & 1) == hf) {
+                    double *p = AM + (long long)(q * K1 + m) * ncell + gi;
+                    *p = rs.acc_first ? rs.ca * own[q][m] : fma(rs.ca, own[q][m], *p);
+                }
+    }
     double *OM = (mesh == 0 ? a.BC[sp ^ 1] + I.offC : a.BD[sp ^ 1] + I.offD);
     if (valid) {
 #pragma unroll
@@ -526,7 +547,7 @@ __device__ void stats_tile(const StageArgs &a, int tile, double *smem) {
     __syncthreads();
 }
 
-// Final OE: u_sigma^N = F_tau(u_h^{N-1,3}) into (dstC, dstD); copy if no step ran.
+// Final OE: u_sigma^N = F_tau(output of the last stage of step N-1) into (dstC, dstD); copy if no step ran.
 template <int K, int FLUX, int T>
 __device__ void final_tile(const StageArgs &a, int tile, double *smem) {
     using F = FluxT<FLUX>;
@@ -536,14 +557,14 @@ __device__ void final_tile(const StageArgs &a, int tile, double *smem) {
     const Inst1D I = a.ninst == 1 ? a.inst0 : a.inst[tl.inst];
     const long long N = a.fin[tl.inst].nexec;
     const double tau = a.fin[tl.inst].tau;
-    const int bp = (int)(N & 1);            // buffer holding u_h^{N-1,3} (or the input when N = 0)
+    const int bp = (int)((a.ns * N) & 1);   // buffer holding the last stage's output (or the input when N = 0)
     double *sC = smem, *sD = smem + NC * K1 * W;
     double *red = smem + lds_doubles(K, NC, T);
     double *scratch = red + NSTAT;
     const bool damp = N > 0 && I.oe && K > 0;
     double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
     if (damp) {
-        reduce_instance<nthreads(T), NC>(a.part[(int)((N - 1) & 1)], a.ntiles, I.tile0, I.ntiles, false, red,
+        reduce_instance<nthreads(T), NC>(a.part[(int)((a.ns * N - 1) & 1)], a.ntiles, I.tile0, I.ntiles, false, red,
                                          scratch);
         finish_stats<NC>(I, red, sig);
     }
@@ -668,7 +689,7 @@ __global__ __launch_bounds__(4 * T) void k_persistent(StageArgs a, long long nst
     __shared__ double smem[D::LDS];
     for (long long n = 0; n < nsteps; ++n) {
         const int par = (int)(n & 1);
-        for (int l = 0; l < 3; ++l) {
+        for (int l = 0; l < a.ns; ++l) {
             for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
                 const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
                 D::template run<StageFn>(k, a, l, par, n == 0, tile, smem);

@@ -30,6 +30,7 @@ struct oecdg_handle {
     std::vector<int64_t> offC, offD;
     int64_t totC = 0, totD = 0;
     int kmax = 0, flux = 0;
+    int rk = 3;              // RK method of every instance (rk_stage)
     bool mixed = false;
     int tile = 64;
     int mode = OECDG_MODE_AUTO;
@@ -44,6 +45,7 @@ struct oecdg_handle {
     double *part = nullptr;
     double *B = nullptr;     // BC0 | BC1 | BD0 | BD1
     double *U = nullptr;     // UC | UD
+    double *A = nullptr;     // AC | AD: classical RK4 only (sum of earlier stages for the last one)
     int *err = nullptr;
     unsigned *bar = nullptr;
     // pinned host mirrors
@@ -83,7 +85,7 @@ int nc_of(int flux, int dim) { return flux == OECDG_FLUX_EULER ? (dim == 1 ? 3 :
 
 int validate(const oecdg_desc &d, std::string &why) {
     if (d.dim != 1 && d.dim != 2) return why = "dim must be 1 or 2", OECDG_EINVAL;
-    if (d.reserved != 0) return why = "reserved must be 0", OECDG_EINVAL;
+    if (d.rk < 0 || d.rk > 4) return why = "rk must be 0 (SSP-RK3), 1, 2, 3 or 4", OECDG_EINVAL;
     if (d.flux < 0 || d.flux > 2) return why = "unknown flux", OECDG_EINVAL;
     if (d.bc < 0 || d.bc > 1) return why = "unknown boundary condition", OECDG_EINVAL;
     if (!(d.xhi > d.xlo)) return why = "xhi must exceed xlo", OECDG_EINVAL;
@@ -97,6 +99,7 @@ int validate(const oecdg_desc &d, std::string &why) {
         if (d.k != 2) return why = "2D supports the tensor Q2 space only (k = 2)", OECDG_EUNSUPPORTED;
         if (d.flux == OECDG_FLUX_BURGERS) return why = "2D Burgers is not implemented", OECDG_EUNSUPPORTED;
         if (d.bc != OECDG_BC_PERIODIC) return why = "2D supports periodic boundaries only", OECDG_EUNSUPPORTED;
+        if (d.rk != 0 && d.rk != 3) return why = "2D runs SSP-RK3 only", OECDG_EUNSUPPORTED;
         if (d.nx < 2 || d.ny < 2 || d.nx > 65536 || d.ny > 65536) return why = "2D nx, ny out of range", OECDG_EINVAL;
         if (!(d.yhi > d.ylo)) return why = "yhi must exceed ylo", OECDG_EINVAL;
     }
@@ -171,6 +174,12 @@ StageArgs base_args(oecdg_handle *h) {
     a.BD[1] = h->B + 2 * h->totC + h->totD;
     a.UC = h->U;
     a.UD = h->U + h->totC;
+    if (h->A) {
+        a.AC = h->A;
+        a.AD = h->A + h->totC;
+    }
+    a.rk = h->rk;
+    a.ns = rk_stages(h->rk);
     a.err = h->err;
     a.bar = h->bar;
     a.spin_limit = 1LL << 25;
@@ -227,7 +236,7 @@ int final_all(oecdg_handle *h, const StageArgs &a) {
 // Launch the stage kernels of steps n0 .. n0 + count - 1.
 int launch_steps(oecdg_handle *h, const StageArgs &base, long long n0, long long count) {
     for (long long n = n0; n < n0 + count; ++n)
-        for (int l = 0; l < 3; ++l) {
+        for (int l = 0; l < base.ns; ++l) {
             StageArgs a = base;
             a.l = l;
             a.par = (int)(n & 1);
@@ -614,6 +623,8 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
         if (rc == OECDG_OK && d[b].dim != h->dim) rc = OECDG_EINVAL, why = "mixed dimensions in one batch";
         if (rc == OECDG_OK && nbatch > 1 && d[b].dim != 1) rc = OECDG_EUNSUPPORTED, why = "batches are 1D only";
         if (rc == OECDG_OK && d[b].flux != d[0].flux) rc = OECDG_EUNSUPPORTED, why = "one flux per batch";
+        if (rc == OECDG_OK && (d[b].rk == 0 ? 3 : d[b].rk) != (d[0].rk == 0 ? 3 : d[0].rk))
+            rc = OECDG_EUNSUPPORTED, why = "one RK method per batch";
         if (rc != OECDG_OK) {
             delete h;
             return rc;
@@ -635,6 +646,7 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
         return OECDG_OK;
     }
     h->flux = d[0].flux;
+    h->rk = d[0].rk == 0 ? 3 : d[0].rk;
     h->offC.assign(nbatch + 1, 0);
     h->offD.assign(nbatch + 1, 0);
     for (int b = 0; b < nbatch; ++b) {
@@ -681,6 +693,7 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
     ALLOC(h->fin, sizeof(Final) * nbatch);
     ALLOC(h->B, sizeof(double) * 2 * (h->totC + h->totD));
     ALLOC(h->U, sizeof(double) * (h->totC + h->totD));
+    if (h->rk == 4) ALLOC(h->A, sizeof(double) * (h->totC + h->totD));
     ALLOC(h->err, sizeof(int) * 4);
     ALLOC(h->bar, sizeof(unsigned) * 2);
 #undef ALLOC
@@ -776,6 +789,8 @@ int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max, const
     StageArgs a = base_args(h);
     const int sp = stage & 1;                 // step index 0: global stage parity = stage
     a.l = stage;
+    a.rk = 3;                                 // a single stage is always an SSP-RK3 stage
+    a.ns = 3;
     a.par = 0;
     a.first = 0;
     a.tau_override = dt;
@@ -814,6 +829,7 @@ int oecdg_adjoint(oecdg_handle *h, const double *uC0, const double *uD0, int64_t
                   const double *gC_T, const double *gD_T, double *gC0, double *gD0, int32_t checkpoint_every) {
     if (!h || !uC0 || !uD0 || !gC_T || !gD_T || !gC0 || !gD0) return OECDG_EINVAL;
     if (h->dim != 1 || h->nbatch != 1) return fail(h, OECDG_EUNSUPPORTED, "adjoint: 1D single instance only");
+    if (h->rk != 3) return fail(h, OECDG_EUNSUPPORTED, "adjoint: SSP-RK3 only");
     if (nsteps < 0 || !(dt > 0.0) || checkpoint_every < 1) return fail(h, OECDG_EINVAL, "adjoint: bad nsteps/dt/checkpoint");
     return oecdg::adjoint_1d(h, uC0, uD0, nsteps, dt, gC_T, gD_T, gC0, gD0, checkpoint_every);
 }
@@ -833,6 +849,7 @@ void oecdg_destroy(oecdg_handle *h) {
     (void)hipFree(h->part);
     (void)hipFree(h->B);
     (void)hipFree(h->U);
+    (void)hipFree(h->A);
     (void)hipFree(h->err);
     (void)hipFree(h->bar);
     if (h->fin_h) (void)hipHostFree(h->fin_h);

@@ -46,6 +46,42 @@ struct Final {
     long long nexec;
 };
 
+// One stage of an RK method in the c/d form of eq:RKCDG,
+//   u_h^{n,l+1} = sum_{m<=l} c_{lm} u_sigma^{n,m} + tau d_{lm} L(u_sigma^{n,m}).
+// Every supported table has d_{lm} = 0 for m < l and, apart from u^n, earlier
+// stages enter only the last stage of classical RK4; that stage reads their
+// weighted sum, accumulated by the stages that produce them.
+struct RKStage {
+    double cn;        // c_{l0}, l > 0 (at l = 0 the input is u^n and c_{00} is cw)
+    double cw;        // c_{ll}
+    double d;         // d_{ll}
+    double ca;        // weight of this stage's input in the accumulated sum (0: not part of it)
+    int acc_first;    // this stage starts the sum (otherwise it adds to it)
+    int acc_read;     // this stage adds the accumulated sum
+};
+
+// rk: 1 forward Euler, 2 SSP-RK2 (Heun), 3 SSP-RK3 (Shu-Osher), 4 classical
+// fourth-order RK.  Stages per step:
+__host__ __device__ inline int rk_stages(int rk) { return rk == 1 ? 1 : (rk == 2 ? 2 : (rk == 4 ? 4 : 3)); }
+
+__host__ __device__ inline RKStage rk_stage(int rk, int l) {
+    RKStage s{0.0, 1.0, 1.0, 0.0, 0, 0};
+    if (rk == 2) {
+        if (l == 1) s.cn = 0.5, s.cw = 0.5, s.d = 0.5;
+    } else if (rk == 4) {
+        // u^1 = u^n + tau/2 L(u^n), u^2 = u^n + tau/2 L(u^1), u^3 = u^n + tau L(u^2),
+        // u^4 = -u^n/3 + u^1/3 + 2u^2/3 + u^3/3 + tau/6 L(u^3)
+        if (l == 0) s.d = 0.5;
+        if (l == 1) s.cn = 1.0, s.cw = 0.0, s.d = 0.5, s.ca = 1.0 / 3.0, s.acc_first = 1;
+        if (l == 2) s.cn = 1.0, s.cw = 0.0, s.d = 1.0, s.ca = 2.0 / 3.0;
+        if (l == 3) s.cn = -1.0 / 3.0, s.cw = 1.0 / 3.0, s.d = 1.0 / 6.0, s.acc_read = 1;
+    } else if (rk != 1) {
+        if (l == 1) s.cn = 0.75, s.cw = 0.25, s.d = 0.25;
+        if (l == 2) s.cn = 1.0 / 3.0, s.cw = 2.0 / 3.0, s.d = 2.0 / 3.0;
+    }
+    return s;
+}
+
 struct StageArgs {
     const Inst1D *inst;
     const Tile1D *tiles;
@@ -57,8 +93,10 @@ struct StageArgs {
     double *BC[2], *BD[2];   // rotating pre-damping stage states
     double *UC, *UD;         // damped u^n of the current step
     double *DC, *DD;         // optional: damped input of stages 1 and 2 (adjoint recomputation)
+    double *AC, *AD;         // classical RK4: weighted sum of the damped inputs of stages 1 and 2
     int *err;                // [0] non-finite, [1] non-physical, [2] barrier timeout, [3] step+1 of an error
-    int l;                   // stage of the step (0, 1, 2)
+    int rk, ns;              // RK method (rk_stage) and its stages per step
+    int l;                   // stage of the step (0 .. ns-1)
     int par;                 // parity of the step index n
     int first;               // 1 for step 0 (its input is the initial data: no OE)
     int coherent;            // 1 in the persistent launch (cross-workgroup reads after a barrier)

@@ -44,7 +44,7 @@ def test_state_size_host_only():
 
 @pytest.mark.parametrize("field,value,code", [
     ("k", 4, _lib.EINVAL), ("nx", 1, _lib.EINVAL), ("cfl", 0.0, _lib.EINVAL), ("flux", 7, _lib.EINVAL),
-    ("reserved", 1, _lib.EINVAL), ("dim", 3, _lib.EINVAL),
+    ("rk", 5, _lib.EINVAL), ("rk", -1, _lib.EINVAL), ("dim", 3, _lib.EINVAL),
 ])
 def test_invalid_descriptors_are_rejected_before_any_gpu_work(field, value, code):
     L = _lib.lib()
@@ -64,6 +64,24 @@ def test_2d_degrees_other_than_two_are_unsupported():
     d2 = make_desc(p2, 0.3)
     npr, ndu = C.c_int64(), C.c_int64()
     assert L.oecdg_state_size(C.byref(d2), C.byref(npr), C.byref(ndu)) == _lib.EUNSUPPORTED
+
+
+def test_2d_runs_ssp_rk3_only():
+    L = _lib.lib()
+    p2 = inputs.Problem2D(k=2, nc=1, flux=inputs.FLUX_ADVECTION, nx=8, ny=8, xlo=0, xhi=1, ylo=0, yhi=1)
+    npr, ndu = C.c_int64(), C.c_int64()
+    for rk, code in ((0, 0), (3, 0), (1, _lib.EUNSUPPORTED), (2, _lib.EUNSUPPORTED), (4, _lib.EUNSUPPORTED)):
+        d2 = make_desc(p2, 0.3, rk=rk)
+        assert L.oecdg_state_size(C.byref(d2), C.byref(npr), C.byref(ndu)) == code, rk
+
+
+def test_batch_with_two_rk_methods_is_refused_before_any_gpu_work():
+    L = _lib.lib()
+    prob = inputs.Problem1D(k=2, nc=1, flux=inputs.FLUX_ADVECTION, bc=inputs.BC_PERIODIC, n=64, xlo=0.0, xhi=1.0)
+    arr = (_lib.Desc * 2)(make_desc(prob, 0.2, rk=3), make_desc(prob, 0.2, rk=4))
+    h = C.c_void_p()
+    assert L.oecdg_init(arr, 2, None, C.byref(h)) == _lib.EUNSUPPORTED
+    assert not h.value
 
 
 def test_strerror_covers_every_code():

@@ -27,9 +27,10 @@ def _rel(gC, gD, rC, rD):
     return err / max(np.abs(rC).max(), np.abs(rD).max())
 
 
-def gpu_run(prob, uC, uD, cfl, mode=None, tile=None, oe=True, **kw):
-    print(f"[gpu_run] flux={prob.flux} k={prob.k} n={prob.n} bc={prob.bc} mode={mode} tile={tile} {kw}", flush=True)
-    with OECDG(prob, cfl, oe=oe) as s:
+def gpu_run(prob, uC, uD, cfl, mode=None, tile=None, oe=True, rk=3, **kw):
+    print(f"[gpu_run] flux={prob.flux} k={prob.k} n={prob.n} bc={prob.bc} mode={mode} tile={tile} rk={rk} {kw}",
+          flush=True)
+    with OECDG(prob, cfl, oe=oe, rk=rk) as s:
         if mode is not None:
             s.set_option(_lib.OPT_MODE, mode)
         if tile is not None:

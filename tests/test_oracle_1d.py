@@ -138,6 +138,35 @@ def test_p0_forward_euler_is_staggered_lax_friedrichs(bc):
     np.testing.assert_allclose(outD[:, 0], refD, rtol=1e-14, atol=1e-14)
 
 
+@pytest.mark.parametrize("rk", [1, 2, 3, 4])
+@pytest.mark.parametrize("k", [1, 3])
+def test_rk_step_is_the_stability_polynomial(rk, k):
+    """eq:RKCDG with the c/d tables of forward Euler, SSP-RK2, SSP-RK3 and
+    classical RK4, F_tau = identity, on linear advection: an s-stage method of
+    order s (s <= 4) advances a linear autonomous system by the truncated
+    exponential sum_{j<=s} (tau A)^j / j!.  A is assembled column by column
+    from the oracle's right-hand side."""
+    prob = Problem1D(k=k, nc=1, flux=FLUX_ADVECTION, bc=BC_PERIODIC, n=6, xlo=0.0, xhi=1.0, a=0.8)
+    sC, sD = prob.shapes()
+    nC, nD = int(np.prod(sC)), int(np.prod(sD))
+    tau_max = 0.2 * prob.h / 0.8
+    tau = 0.7 * tau_max
+    A = np.zeros((nC + nD, nC + nD))
+    for j in range(nC + nD):
+        e = np.zeros(nC + nD)
+        e[j] = 1.0
+        LC, LD = ora.rhs1d(prob, tau_max, e[:nC].reshape(sC), e[nC:].reshape(sD))
+        A[:, j] = np.concatenate([np.ravel(LC), np.ravel(LD)])
+    u = RNG.normal(size=nC + nD)
+    ref, term = u.copy(), u.copy()
+    for j in range(1, rk + 1):
+        term = tau * (A @ term) / j
+        ref += term
+    oC, oD = ora.step1d(prob, tau, tau_max, u[:nC].reshape(sC).copy(), u[nC:].reshape(sD).copy(), rk=rk, oe=False)
+    got = np.concatenate([np.ravel(oC), np.ravel(oD)])
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
 def _poly_problem(k, nc, flux, n=16):
     return Problem1D(k=k, nc=nc, flux=flux, bc=BC_OUTFLOW, n=n, xlo=-1.0, xhi=1.0, a=0.7)
 
