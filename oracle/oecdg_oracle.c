@@ -23,9 +23,12 @@
  * in the unnormalised Legendre basis P_m(xi), xi = 2(x - x_K)/h.  Primal cell i
  * is [xlo + i h, xlo + (i+1) h].  Dual cell j is centred on the left edge of
  * primal cell j: [xlo + (j-1/2) h, xlo + (j+1/2) h]; there are n of them with
- * periodic boundaries and n+1 with outflow boundaries.  Outflow ghost primal
- * cells -1 and n are the constant extensions of the cell averages of cells 0
- * and n-1.
+ * periodic boundaries and n+1 with outflow or reflective boundaries.  Outflow
+ * ghost primal cells -1 and n are the constant extensions of the cell averages
+ * of cells 0 and n-1.  Reflective walls (Euler only; the two-blast-wave example
+ * of Sec. 4) make the ghosts the mirror images of cells 0 and n-1 about the
+ * wall: the polynomial u(2 x_wall - x) with the momentum negated, i.e. mode m
+ * of component q times (-1)^m, and times -1 more for the momentum.
  *
  * Compile: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math).
  */
@@ -35,7 +38,7 @@
 
 enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENOMEM = -2, ORA_ENONFINITE = -4, ORA_ENONPHYSICAL = -5 };
 enum { FLUX_ADVECTION = 0, FLUX_BURGERS = 1, FLUX_EULER = 2 };
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECTIVE = 2 };
 
 typedef struct {
     int k;          /* polynomial degree */
@@ -113,13 +116,19 @@ long ora1d_ncell(const ora1d *p, int mesh)
 }
 
 /* Coefficient (q, m) of cell idx of mesh (0 primal, 1 dual), with the
- * periodic wrap or the outflow ghost rule for primal cells -1 and n. */
+ * periodic wrap or the outflow / reflective ghost rule for primal cells -1
+ * and n. */
 static double coef(const ora1d *p, const double *uC, const double *uD, int mesh, long idx, int q, int m)
 {
     const int K1 = p->k + 1;
     if (mesh == 0) {
         if (p->bc == BC_PERIODIC) {
             idx = ((idx % p->n) + p->n) % p->n;
+        } else if (p->bc == BC_REFLECTIVE && (idx < 0 || idx >= p->n)) {
+            long src = idx < 0 ? -1 - idx : 2 * p->n - 1 - idx;      /* the mirror cell */
+            double sign = (m % 2 == 1) ? -1.0 : 1.0;
+            if (q == 1) sign = -sign;                                 /* momentum */
+            return sign * uC[(long)(q * K1 + m) * p->n + src];
         } else if (idx < 0 || idx >= p->n) {
             long src = idx < 0 ? 0 : p->n - 1;
             return m == 0 ? uC[(long)(q * K1) * p->n + src] : 0.0;
@@ -214,6 +223,7 @@ int ora1d_rhs(const ora1d *p, double tau_max, const double *uC, const double *uD
     double s[16], wq[16];
     double w[3], uk[3], fw[3], fl[3], fr[3], vl[3], vr[3];
     if (k < 0 || k > 6 || nc < 1 || nc > 3) return ORA_EINVAL;
+    if (p->bc == BC_REFLECTIVE && p->flux != FLUX_EULER) return ORA_EINVAL;
     ora_gauss_legendre(Q, s, wq);
 
     /* basis values at the quadrature nodes of both halves: own cell at xi,
@@ -325,6 +335,7 @@ int ora1d_delta(const ora1d *p, const double *uC, const double *uD, double *dC, 
     const double h = cell_width(p);
     double avg[6], sigma[6], ubar[3], ownL[3], ownR[3], nbL[3], nbR[3];
     double bm1[8][8], bp1[8][8], b0[8][8];          /* [order][mode] at xi = -1, +1, 0 */
+    if (p->bc == BC_REFLECTIVE && p->flux != FLUX_EULER) return ORA_EINVAL;
     ora1d_stats(p, uC, uD, avg, sigma);
     for (int m = 0; m <= k; ++m) {
         basis_at(k, m, -1.0, bm1[m]);
@@ -373,7 +384,8 @@ int ora1d_oe(const ora1d *p, double tau, double *uC, double *uD)
     double *dC = malloc(sizeof(double) * K1 * nC);
     double *dD = malloc(sizeof(double) * K1 * nD);
     if (!dC || !dD) { free(dC); free(dD); return ORA_ENOMEM; }
-    ora1d_delta(p, uC, uD, dC, dD);                 /* all deltas before any damping */
+    int rc = ora1d_delta(p, uC, uD, dC, dD);        /* all deltas before any damping */
+    if (rc != ORA_OK) { free(dC); free(dD); return rc; }
     for (int mesh = 0; mesh < 2; ++mesh) {
         long nk = mesh == 0 ? nC : nD;
         double *u = mesh == 0 ? uC : uD;

@@ -30,6 +30,7 @@ FLUX_BURGERS = 1
 FLUX_EULER = 2
 BC_PERIODIC = 0
 BC_OUTFLOW = 1
+BC_REFLECTIVE = 2
 
 GAMMA = 1.4
 
@@ -207,6 +208,52 @@ def euler_riemann(n: int, k: int, states, x0=0.5, xlo=0.0, xhi=1.0, gamma=GAMMA)
         rho = np.where(left, rl, rr)
         p = np.where(left, pl, pr)
         return euler_conserved(rho, np.zeros_like(rho), p, gamma)
+
+    uC, uD = project_1d(f, prob)
+    return prob, uC, uD
+
+
+def mirror_extend(func, xlo: float, xhi: float):
+    """Euler initial data continued past reflective walls at xlo and xhi:
+    density and energy mirrored, momentum mirrored and negated (the dual cells
+    centred on the walls reach half a cell outside the domain)."""
+    def g(x):
+        x = np.asarray(x, dtype=np.float64)
+        lo, hi = x < xlo, x > xhi
+        xr = np.where(lo, 2.0 * xlo - x, np.where(hi, 2.0 * xhi - x, x))
+        v = np.array(func(xr), dtype=np.float64)
+        v[1] = np.where(lo | hi, -v[1], v[1])
+        return v
+    return g
+
+
+def euler_blast_waves(n: int, k: int, pressures=(1000.0, 0.01, 100.0), gamma=GAMMA):
+    """Two interacting blast waves (Sec. 4): [0, 1] with reflective walls,
+    rho = 1, u = 0 and p = pressures[0] on x < 0.1, pressures[1] on
+    0.1 < x < 0.9, pressures[2] on x > 0.9 (the paper's 1000, 0.01, 100 by
+    default)."""
+    prob = Problem1D(k=k, nc=3, flux=FLUX_EULER, bc=BC_REFLECTIVE, n=n, xlo=0.0, xhi=1.0, gamma=gamma)
+    pl, pm, pr = (float(v) for v in pressures)
+
+    def f(x):
+        p = np.where(x < 0.1, pl, np.where(x > 0.9, pr, pm))
+        return euler_conserved(np.ones_like(x), np.zeros_like(x), p, gamma)
+
+    uC, uD = project_1d(mirror_extend(f, 0.0, 1.0), prob)
+    return prob, uC, uD
+
+
+def euler_walls_smooth(n: int, k: int, xlo=0.0, xhi=1.0, bc=BC_REFLECTIVE, gamma=GAMMA):
+    """Smooth Euler data that are symmetric about x = 0 and periodic with
+    period 2: rho = 1.2 + 0.3 cos(pi x), u = 0.4 sin(pi x),
+    p = 1 + 0.2 cos(2 pi x).  On [0, 1] with walls they are their own mirror
+    extension; on [-1, 1] with periodic boundaries they give the doubled
+    problem whose right half the walled one reproduces."""
+    prob = Problem1D(k=k, nc=3, flux=FLUX_EULER, bc=bc, n=n, xlo=xlo, xhi=xhi, gamma=gamma)
+
+    def f(x):
+        return euler_conserved(1.2 + 0.3 * np.cos(np.pi * x), 0.4 * np.sin(np.pi * x),
+                               1.0 + 0.2 * np.cos(2.0 * np.pi * x), gamma)
 
     uC, uD = project_1d(f, prob)
     return prob, uC, uD

@@ -379,6 +379,81 @@ def test_conservation_each_mesh():
         np.testing.assert_allclose(oD[:, 0].sum(axis=-1), tD0, atol=1e-13 * scale)
 
 
+# ------------------------------------------------------ reflective walls ---
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_reflective_walls_are_half_of_the_doubled_periodic_problem(k):
+    """Walls at 0 and 1 with mirror ghosts (momentum negated) against the
+    periodic problem on [-1, 1] whose data are even in rho, E and odd in the
+    momentum: with F_tau = identity the walled run reproduces that problem's
+    right half (primal cells n..2n-1, dual cells n..2n-1 and the dual cell on
+    x = +-1), step by step."""
+    n = 24
+    pr, uCr, uDr = inputs.euler_walls_smooth(n, k)
+    pd, uCd, uDd = inputs.euler_walls_smooth(2 * n, k, xlo=-1.0, xhi=1.0, bc=BC_PERIODIC)
+    np.testing.assert_allclose(uCd[:, :, n:], uCr, atol=1e-13)
+    np.testing.assert_allclose(uDd[:, :, n:], uDr[:, :, :n], atol=1e-13)
+    np.testing.assert_allclose(uDd[:, :, 0], uDr[:, :, n], atol=1e-13)
+    dt = 0.2 * pr.h / 2.5
+    oCr, oDr, _, _ = ora.run1d(pr, uCr, uDr, nsteps=25, dt_fixed=dt, oe=False)
+    oCd, oDd, _, _ = ora.run1d(pd, uCd, uDd, nsteps=25, dt_fixed=dt, oe=False)
+    scale = np.abs(oCr).max()
+    np.testing.assert_allclose(oCr, oCd[:, :, n:], atol=1e-12 * scale)
+    np.testing.assert_allclose(oDr[:, :, :n], oDd[:, :, n:], atol=1e-12 * scale)
+    np.testing.assert_allclose(oDr[:, :, n], oDd[:, :, 0], atol=1e-12 * scale)
+
+
+def test_reflective_walls_conserve_mass_and_energy_with_oe():
+    """With OE: no mass or energy crosses a wall.  The dual cells on the walls
+    keep even density and energy and odd momentum, so the wall fluxes (the
+    dual polynomial at the wall) carry no mass, and the integrals over [0, 1]
+    of both meshes (the wall dual cells count half) stay constant."""
+    prob, uC, uD = inputs.euler_blast_waves(60, 2, pressures=(100.0, 1.0, 10.0))
+    oC, oD, _, steps = ora.run1d(prob, uC, uD, nsteps=40, cfl=0.3)
+    assert steps == 40
+
+    def integrals(c, d):
+        dual = d[:, 0, 1:-1].sum(axis=-1) + 0.5 * (d[:, 0, 0] + d[:, 0, -1])
+        return c[:, 0].sum(axis=-1), dual
+
+    (c0, d0), (c1, d1) = integrals(uC, uD), integrals(oC, oD)
+    for q in (0, 2):                                   # density, energy
+        assert c1[q] == pytest.approx(c0[q], rel=1e-13)
+        assert d1[q] == pytest.approx(d0[q], rel=1e-13)
+    scale = np.abs(oD).max()
+    for j in (0, prob.n_dual - 1):
+        for q in range(3):
+            parity = 1 if q == 1 else 0                # momentum: odd modes only; rho, E: even modes only
+            for m in range(prob.k + 1):
+                if m % 2 != parity:
+                    assert abs(oD[q, m, j]) <= 1e-13 * scale, (j, q, m)
+
+
+def test_reflective_walls_keep_a_mirror_symmetric_solution_symmetric():
+    """Data symmetric about x = 1/2 (rho, E even, momentum odd) between two
+    walls stay symmetric, OE included (the statistics of symmetric data are
+    symmetric): both walls follow the same rule."""
+    prob = Problem1D(k=2, nc=3, flux=FLUX_EULER, bc=inputs.BC_REFLECTIVE, n=50, xlo=0.0, xhi=1.0)
+
+    def f(x):
+        p = np.where(np.abs(x - 0.5) > 0.4, 50.0, 0.5)
+        return inputs.euler_conserved(1.0 + 0.5 * np.cos(2 * np.pi * x), 0.6 * np.sin(2 * np.pi * x), p)
+
+    uC, uD = inputs.project_1d(inputs.mirror_extend(f, 0.0, 1.0), prob)
+    oC, oD, _, _ = ora.run1d(prob, uC, uD, nsteps=60, cfl=0.3)
+    sign = np.array([1.0, -1.0, 1.0])[:, None, None] * ((-1.0) ** np.arange(3))[None, :, None]
+    scale = np.abs(oC).max()
+    np.testing.assert_allclose(oC, sign * oC[:, :, ::-1], atol=1e-11 * scale)
+    np.testing.assert_allclose(oD, sign * oD[:, :, ::-1], atol=1e-11 * scale)
+
+
+def test_reflective_walls_need_the_euler_flux():
+    prob = Problem1D(k=1, nc=1, flux=FLUX_ADVECTION, bc=inputs.BC_REFLECTIVE, n=16, xlo=0.0, xhi=1.0)
+    uC, uD = np.ones(prob.shapes()[0]), np.ones(prob.shapes()[1])
+    with pytest.raises(RuntimeError):
+        ora.run1d(prob, uC, uD, nsteps=1, cfl=0.2)
+
+
 def test_linear_equivariance():
     """For linear advection the whole RK-OECDG step commutes with u -> lam u + c
     (the operator is linear and kills constants; delta is invariant)."""
