@@ -24,9 +24,13 @@
  *    [xlo + i h, xlo + (i+1) h], h = (xhi - xlo)/nx.  Dual cell j is centred
  *    on the left edge of primal cell j: [xlo + (j-1/2) h, xlo + (j+1/2) h];
  *    there are nx dual cells with periodic boundaries and nx+1 with outflow
- *    boundaries (the last one centred on xhi).  Outflow ghost primal cells
- *    (-1 and nx) are the constant extensions of the averages of cells 0 and
- *    nx-1.
+ *    or reflective boundaries (the last one centred on xhi).  Outflow ghost
+ *    primal cells (-1 and nx) are the constant extensions of the averages of
+ *    cells 0 and nx-1.  Reflective walls (1D Euler only; the two-blast-wave
+ *    example of Sec. 4) make them the mirror images of cells 0 and nx-1 about
+ *    the wall: mode m times (-1)^m, the momentum negated once more.  The dual
+ *    cells on the walls then reach half a cell outside the domain; their
+ *    initial data are the mirror extension of the data inside.
  *  - 2D layout (tensor-product Q^k modes): u[(((q*(k+1) + a)*(k+1) + b)*ny
  *    + iy)*nx + ix], mode a in x, b in y.  Primal cell (ix, iy) is
  *    [xlo + ix hx, xlo + (ix+1) hx] x [ylo + iy hy, ylo + (iy+1) hy]; dual
@@ -62,7 +66,7 @@ enum {
 };
 
 enum { OECDG_FLUX_ADVECTION = 0, OECDG_FLUX_BURGERS = 1, OECDG_FLUX_EULER = 2 };
-enum { OECDG_BC_PERIODIC = 0, OECDG_BC_OUTFLOW = 1 };
+enum { OECDG_BC_PERIODIC = 0, OECDG_BC_OUTFLOW = 1, OECDG_BC_REFLECTIVE = 2 };
 
 /* Execution modes of oecdg_run (oecdg_set_option(OECDG_OPT_MODE, ...)). */
 enum {

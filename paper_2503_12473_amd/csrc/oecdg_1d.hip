@@ -174,8 +174,15 @@ __device__ inline void lds_cell(const double *s, int li, double (&c)[NC][K + 1])
 
 // Element e of the tile's LDS image of the pre-damping input: primal cells
 // [i0-1, i0+T] (rows q*(k+1)+m of length T+2), then dual cells [i0-1, i0+T].
-// Periodic wrap; outflow: constant-extension ghosts for primal -1 and np, zeros
+// Periodic wrap; outflow: constant-extension ghosts for primal -1 and np;
+// reflective (Euler): ghosts -1 and np are the mirror images of cells 0 and
+// np-1, mode m times (-1)^m and the momentum negated (these hold the undamped
+// values; damp_tile replaces them by the mirror of the damped cells).  Zeros
 // for dual cells that do not exist.
+// Sign of coefficient (q, m) of a reflective ghost: (-1)^m, and -1 more for
+// the momentum (q = 1 of the Euler system).
+__device__ inline double mirror_sign(int q, int m) { return ((m & 1) ^ (q == 1)) ? -1.0 : 1.0; }
+
 template <int K, int NC, int T>
 __device__ inline double tile_elem(const Inst1D &I, int i0, const double *__restrict__ inC,
                                    const double *__restrict__ inD, int e) {
@@ -192,7 +199,11 @@ __device__ inline double tile_elem(const Inst1D &I, int i0, const double *__rest
             if (gi < 0 || gi >= np) gi = ((gi % np) + np) % np;   // mesh shorter than a tile
             return inC[(long long)qm * np + gi];
         }
-        if (gi < 0 || gi >= np) return (qm % K1 == 0) ? inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)] : 0.0;
+        if (gi < 0 || gi >= np) {
+            const double v = inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)];
+            if (I.bc == 2) return mirror_sign(qm / K1, qm % K1) * v;
+            return (qm % K1 == 0) ? v : 0.0;
+        }
         return inC[(long long)qm * np + gi];
     }
     const int nd = I.nd;
@@ -247,10 +258,16 @@ __device__ inline void damp_tile(const Inst1D &I, int i0, double *sC, double *sD
     __syncthreads();
     if (active) {
         double *s = mesh == 0 ? sC : sD;
+        // reflective walls: the ghost next to an end cell mirrors its damped values
+        const int lg = (I.bc == 2 && mesh == 0) ? (gi == 0 ? li - 1 : (gi == I.np - 1 ? li + 1 : -1)) : -1;
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 1; m <= K; ++m) s[(q * K1 + m) * W + li] *= fac[m];
+            for (int m = 1; m <= K; ++m) {
+                const double v = s[(q * K1 + m) * W + li] * fac[m];
+                s[(q * K1 + m) * W + li] = v;
+                if (lg >= 0) s[(q * K1 + m) * W + lg] = mirror_sign(q, m) * v;
+            }
     }
     __syncthreads();
 }

@@ -87,7 +87,9 @@ int validate(const oecdg_desc &d, std::string &why) {
     if (d.dim != 1 && d.dim != 2) return why = "dim must be 1 or 2", OECDG_EINVAL;
     if (d.rk < 0 || d.rk > 4) return why = "rk must be 0 (SSP-RK3), 1, 2, 3 or 4", OECDG_EINVAL;
     if (d.flux < 0 || d.flux > 2) return why = "unknown flux", OECDG_EINVAL;
-    if (d.bc < 0 || d.bc > 1) return why = "unknown boundary condition", OECDG_EINVAL;
+    if (d.bc < 0 || d.bc > 2) return why = "unknown boundary condition", OECDG_EINVAL;
+    if (d.bc == OECDG_BC_REFLECTIVE && d.flux != OECDG_FLUX_EULER)
+        return why = "reflective walls need the Euler flux", OECDG_EUNSUPPORTED;
     if (!(d.xhi > d.xlo)) return why = "xhi must exceed xlo", OECDG_EINVAL;
     if (!(d.cfl > 0.0)) return why = "cfl must be positive", OECDG_EINVAL;
     if (d.flux == OECDG_FLUX_EULER && !(d.flux_param[0] > 1.0)) return why = "Euler needs gamma > 1", OECDG_EINVAL;

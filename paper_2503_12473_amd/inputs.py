@@ -227,17 +227,20 @@ def mirror_extend(func, xlo: float, xhi: float):
     return g
 
 
-def euler_blast_waves(n: int, k: int, pressures=(1000.0, 0.01, 100.0), gamma=GAMMA):
+def euler_blast_waves(n: int, k: int, pressures=(1000.0, 0.01, 100.0), densities=(1.0, 1.0, 1.0), gamma=GAMMA):
     """Two interacting blast waves (Sec. 4): [0, 1] with reflective walls,
-    rho = 1, u = 0 and p = pressures[0] on x < 0.1, pressures[1] on
-    0.1 < x < 0.9, pressures[2] on x > 0.9 (the paper's 1000, 0.01, 100 by
+    u = 0 and (rho, p) = (densities[0], pressures[0]) on x < 0.1,
+    (densities[1], pressures[1]) on 0.1 < x < 0.9, (densities[2],
+    pressures[2]) on x > 0.9 (the paper's rho = 1 and p = 1000, 0.01, 100 by
     default)."""
     prob = Problem1D(k=k, nc=3, flux=FLUX_EULER, bc=BC_REFLECTIVE, n=n, xlo=0.0, xhi=1.0, gamma=gamma)
     pl, pm, pr = (float(v) for v in pressures)
+    rl, rm, rr = (float(v) for v in densities)
 
     def f(x):
         p = np.where(x < 0.1, pl, np.where(x > 0.9, pr, pm))
-        return euler_conserved(np.ones_like(x), np.zeros_like(x), p, gamma)
+        rho = np.where(x < 0.1, rl, np.where(x > 0.9, rr, rm))
+        return euler_conserved(rho, np.zeros_like(x), p, gamma)
 
     uC, uD = project_1d(mirror_extend(f, 0.0, 1.0), prob)
     return prob, uC, uD
