@@ -20,7 +20,12 @@
  *     average, sigma_K = the L-infinity distance from the domain average, and
  *     the maximum over components for systems (Sec. 2.2 and its remarks).
  * Readings where the paper leaves a choice:
- *   - the space is the tensor product Q^k (modes P_a(xi) P_b(eta), a, b <= k);
+ *   - the space is the tensor product Q^k (modes P_a(xi) P_b(eta), a, b <= k)
+ *     or, with space = 1, the paper's own P^k (total degree a + b <= k, Sec.
+ *     2.1): the products of Legendre polynomials are L2-orthogonal on a cell,
+ *     so the P^k Galerkin equations are the Q^k ones for the modes a + b <= k
+ *     and every stage's combination is truncated to those modes (the layout
+ *     keeps all (k+1)^2 slots, the others zero);
  *     P^{m-1} u keeps the modes of total degree a + b <= m - 1, so mode (a,b)
  *     decays with rate sum_{m=0}^{min(a+b,k)} delta^m, mode (0,0) not at all;
  *   - integrals: Gauss-Legendre with k+1 nodes per direction on each quadrant
@@ -58,6 +63,7 @@ typedef struct {
     double xlo, xhi, ylo, yhi;
     double ax, ay;  /* advection velocity */
     double gamma;
+    int space;      /* 0: tensor Q^k, 1: total degree P^k */
 } ora2d;
 
 #define KMAX 3
@@ -467,6 +473,19 @@ static int check_state(const ora2d *p, const double *uC, const double *uD)
     return ORA_OK;
 }
 
+/* P^k space: zero the modes of total degree above k (the L2 projection onto
+ * P^k in an orthogonal basis). */
+static void truncate_pk(const ora2d *p, double *u)
+{
+    const int K1 = p->k + 1;
+    const long plane = p->nx * p->ny;
+    for (int q = 0; q < p->nc; ++q)
+        for (int a = 0; a <= p->k; ++a)
+            for (int b = 0; b <= p->k; ++b)
+                if (a + b > p->k)
+                    for (long e = 0; e < plane; ++e) u[(((long)q * K1 + a) * K1 + b) * plane + e] = 0.0;
+}
+
 /* One RK-OECDG step (eq:RKCDG) of size tau with coupling parameter tau_max. */
 int ora2d_step(const ora2d *p, int rk, int oe, double tau, double tau_max, double *uC, double *uD)
 {
@@ -487,6 +506,10 @@ int ora2d_step(const ora2d *p, int rk, int oe, double tau, double tau_max, doubl
             double v = 0.0;
             for (int m = 0; m <= l; ++m) v += c[l][m] * us[sz * m + e] + tau * d[l][m] * Ls[sz * m + e];
             un[e] = v;
+        }
+        if (p->space == 1) {
+            truncate_pk(p, un);
+            truncate_pk(p, un + sz1);
         }
         if (oe && rc == ORA_OK) rc = ora2d_oe(p, tau, un, un + sz1);
         if (rc == ORA_OK) rc = check_state(p, un, un + sz1);

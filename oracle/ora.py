@@ -31,7 +31,7 @@ class Ora1D(C.Structure):
 class Ora2D(C.Structure):
     _fields_ = [("k", C.c_int), ("nc", C.c_int), ("flux", C.c_int), ("nx", C.c_long), ("ny", C.c_long),
                 ("xlo", C.c_double), ("xhi", C.c_double), ("ylo", C.c_double), ("yhi", C.c_double),
-                ("ax", C.c_double), ("ay", C.c_double), ("gamma", C.c_double)]
+                ("ax", C.c_double), ("ay", C.c_double), ("gamma", C.c_double), ("space", C.c_int)]
 
 
 _lib = None
@@ -164,7 +164,7 @@ def run1d(prob, uC, uD, t_end=float("inf"), nsteps=-1, cfl=0.3, dt_fixed=0.0, rk
 
 def _p2(prob):
     return Ora2D(prob.k, prob.nc, prob.flux, prob.nx, prob.ny, prob.xlo, prob.xhi, prob.ylo, prob.yhi,
-                 prob.a, prob.b, prob.gamma)
+                 prob.a, prob.b, prob.gamma, prob.space)
 
 
 def rhs2d(prob, tau_max, uC, uD):

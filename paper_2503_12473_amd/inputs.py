@@ -76,6 +76,7 @@ class Problem2D:
     a: float = 1.0
     b: float = 1.0
     gamma: float = GAMMA
+    space: int = 0          # 0: tensor Q^k; 1: total degree P^k (modes a + b > k are zero)
 
     @property
     def hx(self) -> float:
@@ -152,6 +153,8 @@ def project_2d(func, prob: Problem2D, nq: int = 8, chunk_rows: int = 64):
             # one matrix product: point values [.., Gx*Gy] -> modes [.., a*b]
             a = (vals.reshape(-1, G * G) @ M).reshape(prob.nc, j1 - j0, prob.nx, K1, K1)
             res[:, :, :, j0:j1, :] = a.transpose(0, 3, 4, 1, 2)
+        if prob.space == 1:                               # P^k: the orthogonal projection drops a + b > k
+            res = to_pk(prob, res)
         out.append(np.ascontiguousarray(res))
     return out[0], out[1]
 
@@ -351,7 +354,18 @@ def _project_quadrants_sine(prob: Problem2D, cst, sin_amp, nq: int = 8):
     return out[0], out[1]
 
 
-def euler2d_quadrants(n: int, k: int, seed: int, gamma=GAMMA, fast: bool = True):
+def to_pk(prob: Problem2D, u: np.ndarray) -> np.ndarray:
+    """The P^k part of a tensor-mode array: modes a + b > k set to zero (the
+    L2 projection onto P^k, the basis being orthogonal)."""
+    u = np.array(u, dtype=np.float64, copy=True)
+    for ia in range(prob.k + 1):
+        for ib in range(prob.k + 1):
+            if ia + ib > prob.k:
+                u[:, ia, ib] = 0.0
+    return u
+
+
+def euler2d_quadrants(n: int, k: int, seed: int, gamma=GAMMA, fast: bool = True, space: int = 0):
     """2D Euler on [0,1]^2 periodic: rho = 1 + 0.2 sin(2 pi (x+y)) + rho_q and
     (u, v, p) = (u_q, v_q, p_q) on the four quadrants split at 0.5, with
     (rho_q, p_q) ~ U[0.2, 1] and u_q, v_q ~ U[-0.5, 0.5], drawn per quadrant in
@@ -365,7 +379,8 @@ def euler2d_quadrants(n: int, k: int, seed: int, gamma=GAMMA, fast: bool = True)
         uq, vq = rng.uniform(-0.5, 0.5, size=2)
         quads.append((rq, pq, uq, vq))
     quads = np.asarray(quads)
-    prob = Problem2D(k=k, nc=4, flux=FLUX_EULER, nx=n, ny=n, xlo=0.0, xhi=1.0, ylo=0.0, yhi=1.0, gamma=gamma)
+    prob = Problem2D(k=k, nc=4, flux=FLUX_EULER, nx=n, ny=n, xlo=0.0, xhi=1.0, ylo=0.0, yhi=1.0, gamma=gamma,
+                     space=space)
     if fast:
         rq, pq, uq, vq = quads.T
         r0 = 1.0 + rq
@@ -373,6 +388,8 @@ def euler2d_quadrants(n: int, k: int, seed: int, gamma=GAMMA, fast: bool = True)
         cst = np.stack([r0, r0 * uq, r0 * vq, pq / (gamma - 1.0) + 0.5 * r0 * ke], axis=1)
         amp = np.stack([0.2 + 0 * rq, 0.2 * uq, 0.2 * vq, 0.1 * ke], axis=1)
         uC, uD = _project_quadrants_sine(prob, cst, amp)
+        if space == 1:
+            uC, uD = np.ascontiguousarray(to_pk(prob, uC)), np.ascontiguousarray(to_pk(prob, uD))
         return prob, uC, uD, quads
 
     def f(X, Y):
@@ -401,8 +418,9 @@ def euler2d_smooth(n: int, k: int, gamma=GAMMA):
     return prob, uC, uD
 
 
-def advection2d_sine(n: int, k: int):
-    """u_t + u_x + u_y = 0 on [0,1]^2 periodic, u0 = sin^2(pi (x + y))."""
-    prob = Problem2D(k=k, nc=1, flux=FLUX_ADVECTION, nx=n, ny=n, xlo=0.0, xhi=1.0, ylo=0.0, yhi=1.0)
+def advection2d_sine(n: int, k: int, space: int = 0):
+    """u_t + u_x + u_y = 0 on [0,1]^2 periodic, u0 = sin^2(pi (x + y))
+    (Sec. 4, the data of Table 2Dlinear_accuracy); space 1 = P^k."""
+    prob = Problem2D(k=k, nc=1, flux=FLUX_ADVECTION, nx=n, ny=n, xlo=0.0, xhi=1.0, ylo=0.0, yhi=1.0, space=space)
     uC, uD = project_2d(lambda X, Y: (np.sin(math.pi * (X + Y)) ** 2)[None], prob)
     return prob, uC, uD

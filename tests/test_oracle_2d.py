@@ -343,3 +343,70 @@ def test_steady_smooth_euler_converges_soft():
         errs.append(np.abs(oC[0, 0, 0] - uC[0, 0, 0]).mean())
     rate = math.log2(errs[0] / errs[1])
     assert rate >= 2.5, (errs, rate)
+
+
+# ------------------------------------------------- P^k space ---
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_pk_step_is_the_galerkin_restriction(k):
+    """The total-degree space P^k (Sec. 2.1), OE off, linear advection: the
+    P^k Galerkin operator is T A T, with A the tensor-space operator (columns
+    from the oracle's right-hand side with space 0) and T the projection onto
+    the modes a + b <= k (the basis is orthogonal); one SSP-RK3 step with
+    space 1 equals the third-order stability polynomial of tau T A T."""
+    prob_q = _adv(k, nx=4, ny=3)
+    prob_p = Problem2D(**{**prob_q.__dict__, "space": 1})
+    shape = prob_q.shape()
+    n1 = int(np.prod(shape))
+    keep = np.zeros(shape, dtype=bool)
+    for a in range(k + 1):
+        for b in range(k + 1):
+            keep[:, a, b] = a + b <= k
+    T = np.diag(np.concatenate([keep.ravel(), keep.ravel()]).astype(float))
+    tau_max = 0.05
+    A = np.zeros((2 * n1, 2 * n1))
+    for j in range(2 * n1):
+        e = np.zeros(2 * n1)
+        e[j] = 1.0
+        LC, LD = ora.rhs2d(prob_q, tau_max, e[:n1].reshape(shape), e[n1:].reshape(shape))
+        A[:, j] = np.concatenate([LC.ravel(), LD.ravel()])
+    Ap = T @ A @ T
+    u = T @ np.random.default_rng(k).normal(size=2 * n1)
+    tau = 0.8 * tau_max
+    ref, term = u.copy(), u.copy()
+    for j in range(1, 4):
+        term = tau * (Ap @ term) / j
+        ref += term
+    oC, oD = ora.step2d(prob_p, tau, tau_max, u[:n1].reshape(shape), u[n1:].reshape(shape), rk=3, oe=False)
+    got = np.concatenate([oC.ravel(), oD.ravel()])
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+def test_pk_run_keeps_the_space_and_conserves():
+    prob, uC, uD, _ = inputs.euler2d_quadrants(8, 2, seed=4, space=1)
+    oC, oD, _, _ = ora.run2d(prob, uC, uD, nsteps=4, cfl=0.3)
+    for a, b in ((1, 2), (2, 1), (2, 2)):
+        assert np.all(oC[:, a, b] == 0.0) and np.all(oD[:, a, b] == 0.0)
+    for u0, u1 in ((uC, oC), (uD, oD)):
+        np.testing.assert_allclose(u1[:, 0, 0].sum(axis=(-1, -2)), u0[:, 0, 0].sum(axis=(-1, -2)), rtol=1e-13)
+
+
+@pytest.mark.parametrize("k,rk", [(1, 2), (2, 3)])
+def test_pk_advection_converges_at_order_k_plus_1(k, rk):
+    """Table 2Dlinear_accuracy's problem (sin^2(pi (x + y)), velocity (1, 1)),
+    P^k with an RK method of order k+1, to t = 0.2 on 8^2 -> 16^2 (k = 1) or
+    16^2 -> 32^2 (k = 2): rate >= k + 1 - 0.25 in the l2 norm."""
+    s, w = L.leggauss(8)
+    errs = []
+    for n in ((8, 16) if k == 1 else (16, 32)):
+        prob, uC, uD = inputs.advection2d_sine(n, k, space=1)
+        oC, _, t, _ = ora.run2d(prob, uC, uD, t_end=0.2, cfl=0.45 if k == 1 else 0.33, rk=rk)
+        P = np.stack([L.legval(s, [0.0] * m + [1.0]) for m in range(k + 1)])
+        vals = np.einsum("abyx,ag,bh->yxgh", oC[0], P, P)
+        xc = (np.arange(n) + 0.5) / n
+        X = xc[None, :, None, None] + 0.5 / n * s[None, None, :, None]
+        Y = xc[:, None, None, None] + 0.5 / n * s[None, None, None, :]
+        e = vals - np.sin(np.pi * (X + Y - 2 * t)) ** 2
+        errs.append(math.sqrt((e ** 2 * (w[:, None] * w[None, :] / 4)).sum() / n ** 2))
+    rate = math.log2(errs[0] / errs[1])
+    assert rate >= k + 1 - 0.25, (errs, rate)
