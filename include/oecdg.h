@@ -31,7 +31,8 @@
  *    the wall: mode m times (-1)^m, the momentum negated once more.  The dual
  *    cells on the walls then reach half a cell outside the domain; their
  *    initial data are the mirror extension of the data inside.
- *  - 2D layout (tensor-product Q^k modes): u[(((q*(k+1) + a)*(k+1) + b)*ny
+ *  - 2D layout (tensor-product modes; a P^k state keeps the same slots with
+ *    the modes a + b > k zero): u[(((q*(k+1) + a)*(k+1) + b)*ny
  *    + iy)*nx + ix], mode a in x, b in y.  Primal cell (ix, iy) is
  *    [xlo + ix hx, xlo + (ix+1) hx] x [ylo + iy hy, ylo + (iy+1) hy]; dual
  *    cell (ix, iy) is centred on the primal vertex (xlo + ix hx, ylo + iy hy).
@@ -105,6 +106,11 @@ typedef struct {
                                  * -u^n/3 + u^1/3 + 2u^2/3 + u^3/3 + tau/6 L(u^3) uses the damped stage
                                  * values (library-owned buffer of one state).  2D: 0 or 3 only
                                  * (EUNSUPPORTED otherwise); all instances of a batch use one method. */
+    int32_t space;              /* 2D space: 0 = tensor Q^k, 1 = the paper's total-degree P^k (Sec. 2.1):
+                                 * same layout, the modes with a + b > k are zero on output and ignored
+                                 * on input by oecdg_run (oecdg_stage reads them as given: pass zeros).
+                                 * 1D: either value (the spaces coincide). */
+    int32_t reserved;           /* must be 0 */
 } oecdg_desc;
 
 /* Number of doubles of the primal and dual state arrays of one instance. */

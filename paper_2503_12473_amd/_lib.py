@@ -26,7 +26,8 @@ class Desc(C.Structure):
                 ("nx", C.c_int64), ("ny", C.c_int64),
                 ("xlo", C.c_double), ("xhi", C.c_double), ("ylo", C.c_double), ("yhi", C.c_double),
                 ("flux_param", C.c_double * 2), ("cfl", C.c_double),
-                ("oe", C.c_int32), ("rk", C.c_int32)]
+                ("oe", C.c_int32), ("rk", C.c_int32),
+                ("space", C.c_int32), ("reserved", C.c_int32)]
 
 
 class OECDGError(RuntimeError):

@@ -38,6 +38,8 @@ def make_desc(prob, cfl: float, oe: bool = True, rk: int = 3) -> Desc:
     d.cfl = float(cfl)
     d.oe = 1 if oe else 0
     d.rk = int(rk)
+    d.space = int(getattr(prob, "space", 0))
+    d.reserved = 0
     return d
 
 

@@ -163,6 +163,8 @@ struct Stage2Args {
     const Stats2 *st;
     int *err;                     // [0] non-finite, [1] non-physical, [2] no admissible step
     int l, mode, damp, write_u;
+    int pk;                       // 1: total-degree space P^k, stage outputs keep the modes a + b <= k only
+    int pad;
 };
 
 struct Red2Args {
@@ -497,7 +499,8 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                 const double Lv = (Rq[i][j] - mass * itm * s0) / mass;
                 const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
                 const double v = s0 + tau * Lv;
-                const double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
+                double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
+                if (i + j > K && a.pk) o = 0.0;
                 finite = finite && isfinite(o);
                 if (valid) OM[e * a.plane + gofs] = o;
             }
@@ -631,7 +634,8 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                     if ((e & 3) == lane4) {
                         const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
                         const double v = s0 + tau * Lv;
-                        const double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
+                        double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
+                        if (i + j > K && a.pk) o = 0.0;
                         finite = finite && isfinite(o);
                         if (valid) OM[e * a.plane + gofs] = o;
                     }
@@ -962,6 +966,7 @@ constexpr int TX2 = 8, TY2 = 8;
 
 struct Ext2D {
     int k, nc, flux, oe;
+    int pk;                      // total-degree space P^k
     int nx, ny, ntx, nty, ntiles;
     double hx, hy, cfl;
     FPar2 fp;
@@ -1035,6 +1040,7 @@ Stage2Args stage_args(const Ext2D &x) {
     a.fp = x.fp;
     a.st = x.st;
     a.err = x.err;
+    a.pk = x.pk;
     return a;
 }
 
@@ -1097,6 +1103,7 @@ int create_2d(oecdg_handle *h, const oecdg_desc *d) {
     x->flux = d->flux;
     x->nc = d->flux == OECDG_FLUX_EULER ? 4 : 1;
     x->oe = d->oe;
+    x->pk = d->space == 1;
     x->nx = (int)d->nx;
     x->ny = (int)d->ny;
     x->ntx = (x->nx + TX2 - 1) / TX2;
@@ -1208,6 +1215,16 @@ int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
     if (rc != OECDG_OK) return rc;
     HIPCHK2(h, hipMemcpyAsync(x.B[0], uC, sizeof(double) * x.S1, hipMemcpyDeviceToDevice, s));
     HIPCHK2(h, hipMemcpyAsync(x.B[0] + x.S1, uD, sizeof(double) * x.S1, hipMemcpyDeviceToDevice, s));
+    if (x.pk) {   // P^k: the modes of total degree above k are not part of the state
+        const long long plane = (long long)x.nx * x.ny;
+        for (int mesh = 0; mesh < 2; ++mesh)
+            for (int q = 0; q < x.nc; ++q)
+                for (int i = 0; i <= x.k; ++i)
+                    for (int j = 0; j <= x.k; ++j)
+                        if (i + j > x.k)
+                            HIPCHK2(h, hipMemsetAsync(x.B[0] + mesh * x.S1 + ((q * (x.k + 1) + i) * (x.k + 1) + j) * plane,
+                                                      0, sizeof(double) * plane, s));
+    }
     // statistics of the initial data (wave speeds for the first step) into part[0]
     HIPCHK2(h, delta_of(x, x.B[0], x.B[0] + x.S1, 0, M2_FINAL, s));
     const int chunk = 16;

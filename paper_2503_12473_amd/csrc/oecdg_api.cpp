@@ -14,6 +14,8 @@
 
 using namespace oecdg;
 
+static_assert(sizeof(oecdg_desc) == 104, "oecdg_desc layout is part of the ABI");
+
 struct oecdg_handle {
     std::vector<oecdg_desc> desc;
     int nbatch = 0;
@@ -86,6 +88,8 @@ int nc_of(int flux, int dim) { return flux == OECDG_FLUX_EULER ? (dim == 1 ? 3 :
 int validate(const oecdg_desc &d, std::string &why) {
     if (d.dim != 1 && d.dim != 2) return why = "dim must be 1 or 2", OECDG_EINVAL;
     if (d.rk < 0 || d.rk > 4) return why = "rk must be 0 (SSP-RK3), 1, 2, 3 or 4", OECDG_EINVAL;
+    if (d.space != 0 && d.space != 1) return why = "space must be 0 (Q^k) or 1 (P^k)", OECDG_EINVAL;
+    if (d.reserved != 0) return why = "reserved must be 0", OECDG_EINVAL;
     if (d.flux < 0 || d.flux > 2) return why = "unknown flux", OECDG_EINVAL;
     if (d.bc < 0 || d.bc > 2) return why = "unknown boundary condition", OECDG_EINVAL;
     if (d.bc == OECDG_BC_REFLECTIVE && d.flux != OECDG_FLUX_EULER)

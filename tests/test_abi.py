@@ -44,7 +44,8 @@ def test_state_size_host_only():
 
 @pytest.mark.parametrize("field,value,code", [
     ("k", 4, _lib.EINVAL), ("nx", 1, _lib.EINVAL), ("cfl", 0.0, _lib.EINVAL), ("flux", 7, _lib.EINVAL),
-    ("rk", 5, _lib.EINVAL), ("rk", -1, _lib.EINVAL), ("dim", 3, _lib.EINVAL),
+    ("rk", 5, _lib.EINVAL), ("rk", -1, _lib.EINVAL), ("dim", 3, _lib.EINVAL), ("space", 2, _lib.EINVAL),
+    ("reserved", 1, _lib.EINVAL),
 ])
 def test_invalid_descriptors_are_rejected_before_any_gpu_work(field, value, code):
     L = _lib.lib()
@@ -64,6 +65,11 @@ def test_2d_degrees_other_than_two_are_unsupported():
     d2 = make_desc(p2, 0.3)
     npr, ndu = C.c_int64(), C.c_int64()
     assert L.oecdg_state_size(C.byref(d2), C.byref(npr), C.byref(ndu)) == _lib.EUNSUPPORTED
+
+
+def test_descriptor_layout_matches_the_header():
+    assert C.sizeof(_lib.Desc) == 104
+    assert _lib.Desc.rk.offset == 92 and _lib.Desc.space.offset == 96
 
 
 def test_2d_runs_ssp_rk3_only():
