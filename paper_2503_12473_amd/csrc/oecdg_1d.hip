@@ -174,10 +174,8 @@ __device__ inline void lds_cell(const double *s, int li, double (&c)[NC][K + 1])
 
 // Element e of the tile's LDS image of the pre-damping input: primal cells
 // [i0-1, i0+T] (rows q*(k+1)+m of length T+2), then dual cells [i0-1, i0+T].
-// Periodic wrap; outflow: constant-extension ghosts for primal -1 and np;
-// reflective (Euler): ghosts -1 and np are the mirror images of cells 0 and
-// np-1, mode m times (-1)^m and the momentum negated (these hold the undamped
-// values; damp_tile replaces them by the mirror of the damped cells).  Zeros
+// Periodic wrap; outflow: constant-extension ghosts for primal -1 and np
+// (reflective walls load the same and mirror_ghosts overwrites them); zeros
 // for dual cells that do not exist.
 // Sign of coefficient (q, m) of a reflective ghost: (-1)^m, and -1 more for
 // the momentum (q = 1 of the Euler system).
@@ -199,11 +197,7 @@ __device__ inline double tile_elem(const Inst1D &I, int i0, const double *__rest
             if (gi < 0 || gi >= np) gi = ((gi % np) + np) % np;   // mesh shorter than a tile
             return inC[(long long)qm * np + gi];
         }
-        if (gi < 0 || gi >= np) {
-            const double v = inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)];
-            if (I.bc == 2) return mirror_sign(qm / K1, qm % K1) * v;
-            return (qm % K1 == 0) ? v : 0.0;
-        }
+        if (gi < 0 || gi >= np) return (qm % K1 == 0) ? inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)] : 0.0;
         return inC[(long long)qm * np + gi];
     }
     const int nd = I.nd;
@@ -212,6 +206,28 @@ __device__ inline double tile_elem(const Inst1D &I, int i0, const double *__rest
         if (gi < 0 || gi >= nd) gi = ((gi % nd) + nd) % nd;
     }
     return (gi >= 0 && gi < nd) ? inD[(long long)qm * nd + gi] : 0.0;
+}
+
+// Reflective walls (Euler): primal ghosts -1 and np in the LDS tile become the
+// mirror images of cells 0 and np-1 (mode m times (-1)^m, the momentum
+// negated).  Only kernels of the walled Euler flux (FluxT<3>) contain this,
+// and only their tiles that hold a ghost call it (a workgroup-uniform test),
+// followed by a barrier; damp_tile mirrors the damped end cells again.
+template <int K, int NC, int T>
+__device__ inline bool has_wall_ghost(const Inst1D &I, int i0) {
+    return I.bc == 2 && (i0 == 0 || I.np - i0 <= T);
+}
+
+template <int K, int NC, int T>
+__device__ inline void mirror_ghosts(const Inst1D &I, int i0, double *sC) {
+    constexpr int W = T + 2, K1 = K + 1;
+    const int t = threadIdx.x;
+    if (t < NC * K1) {
+        const double sg = mirror_sign(t / K1, t % K1);
+        if (i0 == 0) sC[t * W] = sg * sC[t * W + 1];
+        const int lr = I.np - i0;                  // LDS column of cell np-1; its ghost is the next one
+        if (lr >= 0 && lr <= T) sC[t * W + lr + 1] = sg * sC[t * W + lr];
+    }
 }
 
 template <int K, int NC, int T>
@@ -258,16 +274,21 @@ __device__ inline void damp_tile(const Inst1D &I, int i0, double *sC, double *sD
     __syncthreads();
     if (active) {
         double *s = mesh == 0 ? sC : sD;
-        // reflective walls: the ghost next to an end cell mirrors its damped values
-        const int lg = (I.bc == 2 && mesh == 0) ? (gi == 0 ? li - 1 : (gi == I.np - 1 ? li + 1 : -1)) : -1;
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 1; m <= K; ++m) {
-                const double v = s[(q * K1 + m) * W + li] * fac[m];
-                s[(q * K1 + m) * W + li] = v;
-                if (lg >= 0) s[(q * K1 + m) * W + lg] = mirror_sign(q, m) * v;
+            for (int m = 1; m <= K; ++m) s[(q * K1 + m) * W + li] *= fac[m];
+        // reflective walls: the ghost next to an end cell mirrors its damped values
+        if constexpr (FLUX == 3) {
+            if (I.bc == 2 && mesh == 0 && (gi == 0 || gi == I.np - 1)) {
+                const int lg = gi == 0 ? li - 1 : li + 1;
+#pragma unroll
+                for (int q = 0; q < NC; ++q)
+#pragma unroll
+                    for (int m = 1; m <= K; ++m)
+                        s[(q * K1 + m) * W + lg] = mirror_sign(q, m) * s[(q * K1 + m) * W + li];
             }
+        }
     }
     __syncthreads();
 }
@@ -455,6 +476,12 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
 #pragma unroll
         for (int m = 0; m < K1; ++m) un[q][m] = (l > 0 && valid) ? UM[(long long)(q * K1 + m) * ncell + gi] : 0.0;
     __syncthreads();
+    if constexpr (FLUX == 3) {
+        if (has_wall_ghost<K, NC, T>(I, i0)) {
+            mirror_ghosts<K, NC, T>(I, i0, sC);
+            __syncthreads();
+        }
+    }
     if (damp) damp_tile<K, FLUX, T>(I, i0, sC, sD, sig, tau_in);
 
     // own cell; the overlapping cell of this thread's half
@@ -587,6 +614,12 @@ __device__ void final_tile(const StageArgs &a, int tile, double *smem) {
     }
     load_tile<K, NC, T>(I, tl.i0, a.BC[bp] + I.offC, a.BD[bp] + I.offD, smem);
     __syncthreads();
+    if constexpr (FLUX == 3) {
+        if (has_wall_ghost<K, NC, T>(I, tl.i0)) {
+            mirror_ghosts<K, NC, T>(I, tl.i0, sC);
+            __syncthreads();
+        }
+    }
     if (damp) damp_tile<K, FLUX, T>(I, tl.i0, sC, sD, sig, tau);
     const int cidx = tid >> 1, hf = tid & 1;
     const int mesh = cidx < T ? 0 : 1;
@@ -767,7 +800,8 @@ static void *pick_f(int flux, int ti) {
     switch (flux) {
     case 0: return pick_t<WHICH, KM, 0>(ti);
     case 1: return pick_t<WHICH, KM, 1>(ti);
-    default: return pick_t<WHICH, KM, 2>(ti);
+    case 2: return pick_t<WHICH, KM, 2>(ti);
+    default: return pick_t<WHICH, KM, 3>(ti);   // Euler with reflective walls
     }
 }
 

@@ -31,7 +31,7 @@ struct oecdg_handle {
     std::vector<Group> groups;   // tiles ordered by degree: one launch per degree
     std::vector<int64_t> offC, offD;
     int64_t totC = 0, totD = 0;
-    int kmax = 0, flux = 0;
+    int kmax = 0, flux = 0;  // flux: kernel flux id (OECDG_FLUX_*, or 3 = Euler with reflective walls)
     int rk = 3;              // RK method of every instance (rk_stage)
     bool mixed = false;
     int tile = 64;
@@ -652,6 +652,8 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
         return OECDG_OK;
     }
     h->flux = d[0].flux;
+    for (int b = 0; b < nbatch; ++b)       // kernels with the wall-ghost code only where an instance has walls
+        if (d[b].bc == OECDG_BC_REFLECTIVE) h->flux = 3;
     h->rk = d[0].rk == 0 ? 3 : d[0].rk;
     h->offC.assign(nbatch + 1, 0);
     h->offD.assign(nbatch + 1, 0);

@@ -50,6 +50,10 @@ template <> struct FluxT<2> {          // Euler (rho, m, E), ideal gas
     }
 };
 
+// Euler between reflective walls: the same flux; 1D kernels instantiated with
+// it also carry the wall-ghost code (the others carry none).
+template <> struct FluxT<3> : FluxT<2> {};
+
 // ------------------------------------------------------ shared-state access ---
 // Between kernel launches plain loads see the previous kernel's stores.  In
 // the persistent launch, values written by other workgroups of the same
