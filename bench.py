@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-form measurement")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D Euler measurement")
+    ap.add_argument("--no-widened", action="store_true",
+                    help="skip the classical-RK4, reflective-wall and 2D P^2 measurements")
     ap.add_argument("--e2d-steps", type=int, default=E2D_STEPS, help="steps of the 2D Euler measurement")
     ap.add_argument("--e2d-repeats", type=int, default=3, help="timed repetitions of the 2D Euler measurement")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -243,6 +245,78 @@ def euler2d_bench(repeats: int = 3, steps: int = E2D_STEPS):
                          "launch_us": 1e6 * launch_s}}
 
 
+def _timed_1d(prob, uC, uD, cfl, steps, rk=3, warmup=200):
+    """Median of 3 oecdg_run calls of `steps` steps from the same initial data."""
+    import torch
+    from paper_2503_12473_amd.api import OECDG, to_device
+    stream = torch.cuda.current_stream()
+    ic = (to_device(uC), to_device(uD))
+    with OECDG(prob, cfl, stream=stream, rk=rk) as solver:
+        a, b = ic[0].clone(), ic[1].clone()
+        solver.run(a, b, nsteps=warmup)
+        times = []
+        for _ in range(3):
+            a.copy_(ic[0])
+            b.copy_(ic[1])
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            _, n = solver.run(a, b, nsteps=steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+    wall = sorted(times)[1]
+    return n, wall
+
+
+def widened_bench():
+    """The forms beyond the SSP-RK3 plain path: classical RK4 (four stages per
+    step) at P3 on the Riemann workload, reflective walls (the walled-Euler
+    kernels) on blast-wave data, and the 2D total-degree space P^2 on the 2D
+    Euler workload.  A DOF-update is one DOF advanced by one full step."""
+    import torch
+    from paper_2503_12473_amd import inputs
+    from paper_2503_12473_amd.api import OECDG, to_device
+    out = {}
+    prob, uC, uD = inputs.euler_riemann(N_CELLS, 3, inputs.riemann_states(SEED))
+    for rk, name in ((4, "rk4_p3"), (3, "ssprk3_p3")):
+        n, wall = _timed_1d(prob, uC, uD, 0.2, 2000, rk=rk)
+        stages = 4 if rk == 4 else 3
+        out[name] = {"workload": f"1D Euler Riemann N={N_CELLS}, P3, {'classical RK4' if rk == 4 else 'SSP-RK3'}, "
+                                 f"CFL 0.2, {n} steps", "dofs": prob.dofs(), "dof_updates_per_s": prob.dofs() * n / wall,
+                     "ms_per_step": 1e3 * wall / n, "us_per_stage_launch": 1e6 * wall / (stages * n)}
+    prob, uC, uD = inputs.euler_blast_waves(16000, 2, pressures=(100.0, 1.0, 10.0), densities=(1.0, 0.5, 0.8))
+    n, wall = _timed_1d(prob, uC, uD, 0.3, 2000)
+    out["walls_p2"] = {"workload": "1D Euler blast waves between reflective walls, N=16000, P2, SSP-RK3, CFL 0.3, "
+                                   f"p = (100, 1, 10), rho = (1, 0.5, 0.8), {n} steps",
+                       "dofs": prob.dofs(), "dof_updates_per_s": prob.dofs() * n / wall,
+                       "ms_per_step": 1e3 * wall / n, "us_per_stage_launch": 1e6 * wall / (3 * n)}
+    prob, uC, uD, _ = inputs.euler2d_quadrants(E2D_N, 2, seed=SEED, space=1)
+    stream = torch.cuda.current_stream()
+    ic = (to_device(uC), to_device(uD))
+    del uC, uD
+    steps = 100
+    with OECDG(prob, E2D_CFL, stream=stream) as solver:
+        a, b = ic[0].clone(), ic[1].clone()
+        solver.run(a, b, nsteps=5)
+        a.copy_(ic[0])
+        b.copy_(ic[1])
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        _, n = solver.run(a, b, nsteps=steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = e0.elapsed_time(e1) / 1e3
+    pk_dofs = 2 * 4 * 6 * E2D_N * E2D_N
+    out["euler2d_p2"] = {"workload": f"2D Euler {E2D_N}^2, total-degree P^2 (6 modes; the tensor kernel with the "
+                                     f"other 3 slots zeroed), CFL {E2D_CFL}, {n} steps, seed {SEED}",
+                         "dofs": pk_dofs, "dof_updates_per_s": pk_dofs * n / wall, "ms_per_step": 1e3 * wall / n}
+    return out
+
+
 def cpu_baseline(target_seconds: float):
     """The CPU oracle, as it stands, on a bounded sample of the same workload:
     the first S steps from the same initial data (S sized to ~target_seconds)."""
@@ -349,6 +423,8 @@ def main():
         out["adjoint"] = adjoint_bench()
     if not args.no_2d:
         out["euler2d"] = euler2d_bench(repeats=args.e2d_repeats, steps=args.e2d_steps)
+    if not args.no_widened:
+        out["widened"] = widened_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out))
