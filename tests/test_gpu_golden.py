@@ -79,3 +79,28 @@ def test_euler2d_matches_golden(n, steps):
     e = _rel(oC, oD, g["uC"], g["uD"])
     print(f"[golden] euler2d n={n} rel err {e:.3e}", flush=True)
     assert e <= TOL
+
+
+@pytest.mark.timeout(300)
+def test_advection2d_p2_matches_golden():
+    """2D linear advection in the total-degree space P^2, 128^2, sin^2(pi (x + y)),
+    CFL 0.33, to t = 1.1 (the setting of Table 2Dlinear_accuracy): the stored
+    cells, and the error norms against the exact solution within 1e-8 relative
+    of the oracle's."""
+    g = _golden("advection2d_p2_N128_T1.1.npz")
+    prob, uC, uD = inputs.advection2d_sine(128, 2, space=1)
+    print("[golden] advection2d P2 n=128 T=1.1", flush=True)
+    with OECDG(prob, 0.33) as s:
+        a, b = to_device(uC), to_device(uD)
+        t, n = s.run(a, b, t_end=1.1)
+        full = a.reshape(uC.shape).cpu().numpy()
+        st = int(g["stride"])
+        oC = full[..., ::st, ::st]
+        oD = b.reshape(uD.shape)[..., ::st, ::st].cpu().numpy()
+    assert n == int(g["steps"]) and t == float(g["t"])
+    e = _rel(oC, oD, g["uC"], g["uD"])
+    print(f"[golden] advection2d P2 steps={n} rel err {e:.3e}", flush=True)
+    assert e <= TOL
+    from tests.golden.make_pk_advection_golden import error_norms
+    for got, ref in zip(error_norms(prob, full, t), (g["l1"], g["l2"], g["linf"])):
+        assert got == pytest.approx(float(ref), rel=1e-8)
