@@ -163,8 +163,6 @@ struct Stage2Args {
     const Stats2 *st;
     int *err;                     // [0] non-finite, [1] non-physical, [2] no admissible step
     int l, mode, damp, write_u;
-    int pk;                       // 1: total-degree space P^k, stage outputs keep the modes a + b <= k only
-    int pad;
 };
 
 struct Red2Args {
@@ -259,7 +257,12 @@ __device__ inline void stage_tile2d(double *tile, const double *inC, const doubl
 // damping numerators of k_delta2d and sigma), then the operator of eq:2D_H
 // and the SSP-RK3 combination on the owned cells (stage mode), or only the
 // damped owned cells (final mode).
-template <int K, int FLUX, int TX, int TY>
+// PK: the total-degree space P^K.  Modes with a + b > K are zero in every
+// state, so the unrolled loops skip them at compile time (kept()).
+template <int K, bool PK>
+__device__ constexpr bool kept(int a, int b) { return !PK || a + b <= K; }
+
+template <int K, int FLUX, int TX, int TY, bool PK>
 __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
     using F = Flux2D<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1, Q = K + 1, NE = NC * K1 * K1;
@@ -390,6 +393,10 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
             for (int c = 0; c < K1; ++c)
 #pragma unroll
                 for (int e = 0; e < K1; ++e) {
+                    if (!kept<K, PK>(c, e)) {
+                        d[c][e] = 0.0;
+                        continue;
+                    }
                     const double x = toth[((q * K1 + c) * K1 + e) * NCELL + oc];
                     const double xs = (c & 1) ? sgx * x : x;
                     d[c][e] = (e & 1) ? sgy * xs : xs;
@@ -401,7 +408,8 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                 for (int e = 0; e < K1; ++e) {
                     double t = 0.0;
 #pragma unroll
-                    for (int c = 0; c < K1; ++c) t += d[c][e] * tb.nb[0][1][p][c];
+                    for (int c = 0; c < K1; ++c)
+                        if (kept<K, PK>(c, e)) t += d[c][e] * tb.nb[0][1][p][c];
                     cx[e] = t;
                 }
                 double A[K1], B[K1];
@@ -437,8 +445,9 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                 for (int i = 0; i < K1; ++i)
 #pragma unroll
                     for (int j = 0; j < K1; ++j)
-                        Rq[i][j] += wp * (tb.own[0][1][p][i] * ((i & 1) ? Ax[j] : A[j]) +
-                                          (2.0 / hx) * tb.own[1][1][p][i] * ((i & 1) ? B[j] : Bx[j]));
+                        if (kept<K, PK>(i, j))
+                            Rq[i][j] += wp * (tb.own[0][1][p][i] * ((i & 1) ? Ax[j] : A[j]) +
+                                              (2.0 / hx) * tb.own[1][1][p][i] * ((i & 1) ? B[j] : Bx[j]));
             }
         }
         // edges: (dir, side) = W, E (f_1 on vertical centre lines), S, N (f_2)
@@ -459,6 +468,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                     double sum = 0.0;
 #pragma unroll
                     for (int n = 0; n < K1; ++n) {
+                        if (!kept<K, PK>(t, n)) continue;
                         const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
                         sum += toth[ent * NCELL + oc] * tb.e0[0][n];
                     }
@@ -483,6 +493,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
             for (int n = 0; n < K1; ++n)
 #pragma unroll
                 for (int t = 0; t < K1; ++t) {
+                    if (!kept<K, PK>(n, t)) continue;
                     const double x = sgn * 0.25 * ht * edge_val(1.0, n, 0, side) * Y[t];
                     if (dir) Rq[t][n] -= x;
                     else Rq[n][t] -= x;
@@ -500,7 +511,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                 const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
                 const double v = s0 + tau * Lv;
                 double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
-                if (i + j > K && a.pk) o = 0.0;
+                if (!kept<K, PK>(i, j)) o = 0.0;
                 finite = finite && isfinite(o);
                 if (valid) OM[e * a.plane + gofs] = o;
             }
@@ -526,7 +537,9 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                         double sum = 0.0;
 #pragma unroll
                         for (int c = 0; c < K1; ++c)
-                            sum += toth[((q * K1 + c) * K1 + d) * NCELL + oc] * (sx ? tb.nb[0][1][p][c] : tb.nb[0][0][p][c]);
+                            if (kept<K, PK>(c, d))
+                                sum += toth[((q * K1 + c) * K1 + d) * NCELL + oc] *
+                                       (sx ? tb.nb[0][1][p][c] : tb.nb[0][0][p][c]);
                         cx[q][d] = sum;
                     }
                 double A[NC][K1], B[NC][K1];
@@ -564,7 +577,8 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
 #pragma unroll
                     for (int q = 0; q < NC; ++q)
 #pragma unroll
-                        for (int j = 0; j < K1; ++j) R[q][i][j] += wp * (pa * A[q][j] + (2.0 / hx) * dpa * B[q][j]);
+                        for (int j = 0; j < K1; ++j)
+                            if (kept<K, PK>(i, j)) R[q][i][j] += wp * (pa * A[q][j] + (2.0 / hx) * dpa * B[q][j]);
                 }
             }
         }
@@ -588,6 +602,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                         double sum = 0.0;
 #pragma unroll
                         for (int n = 0; n < K1; ++n) {
+                            if (!kept<K, PK>(t, n)) continue;
                             const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
                             sum += toth[ent * NCELL + oc] * tb.e0[0][n];
                         }
@@ -616,6 +631,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                 for (int i = 0; i < K1; ++i)
 #pragma unroll
                     for (int j = 0; j < K1; ++j) {
+                        if (!kept<K, PK>(i, j)) continue;
                         const double x_ij = sgn * 0.25 * ht * edge_val(1.0, i, 0, side) * Y[q][j];
                         const double x_ji = sgn * 0.25 * ht * edge_val(1.0, j, 0, side) * Y[q][i];
                         R[q][i][j] -= dir ? x_ji : x_ij;
@@ -628,6 +644,10 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
 #pragma unroll
                 for (int j = 0; j < K1; ++j) {
                     const int e = (q * K1 + i) * K1 + j;
+                    if (!kept<K, PK>(i, j)) {
+                        if ((e & 3) == lane4 && valid) OM[e * a.plane + gofs] = 0.0;
+                        continue;
+                    }
                     const double mass = hx * hy / ((2.0 * i + 1.0) * (2.0 * j + 1.0));
                     const double s0 = town[e * NCELL + cell];
                     const double Lv = (quad_sum(R[q][i][j]) - mass * itm * s0) / mass;
@@ -635,7 +655,6 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                         const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
                         const double v = s0 + tau * Lv;
                         double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
-                        if (i + j > K && a.pk) o = 0.0;
                         finite = finite && isfinite(o);
                         if (valid) OM[e * a.plane + gofs] = o;
                     }
@@ -651,7 +670,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
 // (delta^m_K = max_q N^m_q / sigma_q once sigma is known, Sec. 2.2), with one
 // lane per edge; then the tile's partial statistics (sums of averages, sample
 // max / min per component, largest wave speeds) with one lane per component.
-template <int K, int FLUX, int TX, int TY>
+template <int K, int FLUX, int TX, int TY, bool PK>
 // Two workgroups per CU (4 waves per SIMD; the LDS tile allows no more): the
 // register cap spills a few values to scratch, which costs less than running
 // one workgroup per CU (6.86 -> 6.32 ms per step on the 1024^2 workload).
@@ -708,6 +727,7 @@ __global__ __launch_bounds__(8 * TX * TY, 4) void k_delta2d(Stage2Args a) {
                     double so = 0.0;
 #pragma unroll
                     for (int n = 0; n < K1; ++n) {
+                        if (!kept<K, PK>(t, n)) continue;
                         const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
                         so += own[ent * NCELL + cell] * edge_val(tb.e1[dn][n], n, dn, side);
                     }
@@ -726,6 +746,7 @@ __global__ __launch_bounds__(8 * TX * TY, 4) void k_delta2d(Stage2Args a) {
                         double sh = 0.0;
 #pragma unroll
                         for (int n = 0; n < K1; ++n) {
+                            if (!kept<K, PK>(t, n)) continue;
                             const int ent = dir ? (q * K1 + t) * K1 + n : (q * K1 + n) * K1 + t;
                             sh += oth[ent * NCELL + oc[h]] * tb.e0[dn][n];
                         }
@@ -783,7 +804,7 @@ __global__ __launch_bounds__(8 * TX * TY, 4) void k_delta2d(Stage2Args a) {
 #pragma unroll
         for (int i = 0; i < K1; ++i)
 #pragma unroll
-            for (int j = 0; j < K1; ++j) cst[i][j] = own[((cq * K1 + i) * K1 + j) * NCELL + cell];
+            for (int j = 0; j < K1; ++j) cst[i][j] = kept<K, PK>(i, j) ? own[((cq * K1 + i) * K1 + j) * NCELL + cell] : 0.0;
         double mx = -INFINITY, mn = INFINITY;
 #pragma unroll
         for (int i = 0; i < NSP; ++i) {
@@ -793,7 +814,8 @@ __global__ __launch_bounds__(8 * TX * TY, 4) void k_delta2d(Stage2Args a) {
             for (int j = 0; j < K1; ++j) {
                 double sum = 0.0;
 #pragma unroll
-                for (int c = 0; c < K1; ++c) sum += cst[c][j] * tb.sp[i][c];
+                for (int c = 0; c < K1; ++c)
+                    if (kept<K, PK>(c, j)) sum += cst[c][j] * tb.sp[i][c];
                 rb[j] = sum;
             }
 #pragma unroll
@@ -998,14 +1020,20 @@ hipError_t launch_tile(void *fn, const Ext2D &x, const Stage2Args &a, hipStream_
 }
 
 hipError_t launch_stage2d(const Ext2D &x, const Stage2Args &a, hipStream_t s) {
-    void *fn = x.flux == OECDG_FLUX_EULER ? (void *)k_stage2d<2, OECDG_FLUX_EULER, TX2, TY2>
-                                          : (void *)k_stage2d<2, OECDG_FLUX_ADVECTION, TX2, TY2>;
+    void *fn = x.flux == OECDG_FLUX_EULER
+                   ? (x.pk ? (void *)k_stage2d<2, OECDG_FLUX_EULER, TX2, TY2, true>
+                           : (void *)k_stage2d<2, OECDG_FLUX_EULER, TX2, TY2, false>)
+                   : (x.pk ? (void *)k_stage2d<2, OECDG_FLUX_ADVECTION, TX2, TY2, true>
+                           : (void *)k_stage2d<2, OECDG_FLUX_ADVECTION, TX2, TY2, false>);
     return launch_tile(fn, x, a, s);
 }
 
 hipError_t launch_delta2d(const Ext2D &x, const Stage2Args &a, hipStream_t s) {
-    void *fn = x.flux == OECDG_FLUX_EULER ? (void *)k_delta2d<2, OECDG_FLUX_EULER, TX2, TY2>
-                                          : (void *)k_delta2d<2, OECDG_FLUX_ADVECTION, TX2, TY2>;
+    void *fn = x.flux == OECDG_FLUX_EULER
+                   ? (x.pk ? (void *)k_delta2d<2, OECDG_FLUX_EULER, TX2, TY2, true>
+                           : (void *)k_delta2d<2, OECDG_FLUX_EULER, TX2, TY2, false>)
+                   : (x.pk ? (void *)k_delta2d<2, OECDG_FLUX_ADVECTION, TX2, TY2, true>
+                           : (void *)k_delta2d<2, OECDG_FLUX_ADVECTION, TX2, TY2, false>);
     return launch_tile(fn, x, a, s);
 }
 
@@ -1040,7 +1068,6 @@ Stage2Args stage_args(const Ext2D &x) {
     a.fp = x.fp;
     a.st = x.st;
     a.err = x.err;
-    a.pk = x.pk;
     return a;
 }
 
