@@ -107,9 +107,8 @@ typedef struct {
                                  * values (library-owned buffer of one state).  2D: 0 or 3 only
                                  * (EUNSUPPORTED otherwise); all instances of a batch use one method. */
     int32_t space;              /* 2D space: 0 = tensor Q^k, 1 = the paper's total-degree P^k (Sec. 2.1):
-                                 * same layout, the modes with a + b > k are zero on output and ignored
-                                 * on input by oecdg_run (oecdg_stage reads them as given: pass zeros).
-                                 * 1D: either value (the spaces coincide). */
+                                 * same layout; the modes with a + b > k are ignored on input and zero on
+                                 * output (oecdg_run, oecdg_stage).  1D: either value (the spaces coincide). */
     int32_t reserved;           /* must be 0 */
 } oecdg_desc;
 

@@ -92,3 +92,22 @@ def test_full_mesh_p2_properties():
         p = 0.4 * (u1[3, 0, 0] - 0.5 * (u1[1, 0, 0] ** 2 + u1[2, 0, 0] ** 2) / rho)
         assert rho.min() > 0 and p.min() > 0
         assert _high_modes_zero(u1)
+
+
+def test_single_stage_ignores_high_slots():
+    """oecdg_stage with P^2: the slots a + b > 2 of u^n and u^l are not read,
+    and the output's are zero."""
+    prob, uC, uD, _ = inputs.euler2d_quadrants(16, 2, seed=2, space=1)
+    rng = np.random.default_rng(5)
+    nC, nD = uC.copy(), uD.copy()
+    for i, j in HIGH:
+        nC[:, i, j] = rng.normal(size=nC[:, i, j].shape)
+        nD[:, i, j] = rng.normal(size=nD[:, i, j].shape)
+    outs = []
+    for c, d in ((uC, uD), (nC, nD)):
+        with OECDG(prob, 0.3) as s:
+            dt = s.dt(to_device(c), to_device(d))
+            o = s.stage(1, 0.8 * dt, dt, to_device(c), to_device(d), to_device(c), to_device(d))
+            outs.append((o[0].cpu().numpy().reshape(uC.shape), o[1].cpu().numpy().reshape(uD.shape)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert _high_modes_zero(outs[0][0]) and _high_modes_zero(outs[0][1])
