@@ -62,6 +62,7 @@ class OECDG:
             probs = [probs]
         cfls = cfl if isinstance(cfl, (list, tuple)) else [cfl] * len(probs)
         self.probs = list(probs)
+        self.rk = 3 if rk == 0 else int(rk)
         self._L = _lib.lib()
         arr = (Desc * len(probs))(*[make_desc(p, c, oe, rk) for p, c in zip(probs, cfls)])
         self.stream = stream if stream is not None else torch.cuda.current_stream()

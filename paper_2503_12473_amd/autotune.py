@@ -22,13 +22,14 @@ CANDIDATES = (32, 64, 128)
 _memory: dict = {}
 
 
-def _key(probs) -> str:
+def _key(probs, rk: int = 3) -> str:
     ns = [p.n for p in probs]
     ks = sorted({p.k for p in probs})
     arch = torch.cuda.get_device_properties(0).gcnArchName if torch.cuda.is_available() else "none"
     nb = int(round(math.log2(max(1.0, sum(ns) / len(ns)))))
     bb = int(round(math.log2(len(probs))))
-    return f"{arch}|flux{probs[0].flux}|k{''.join(map(str, ks))}|n2^{nb}|b2^{bb}"
+    walls = "|walls" if any(getattr(p, "bc", 0) == 2 for p in probs) else ""
+    return f"{arch}|flux{probs[0].flux}{walls}|rk{rk}|k{''.join(map(str, ks))}|n2^{nb}|b2^{bb}"
 
 
 def _load_file():
@@ -52,7 +53,7 @@ def tune_tile(solver, uC: torch.Tensor, uD: torch.Tensor, steps: int = 12, candi
               t_end: float = math.inf) -> int:
     """Pick the fastest tile size for `solver` (an api.OECDG handle) on this
     state, set it on the handle and return it.  The state is not modified."""
-    key = _key(solver.probs)
+    key = _key(solver.probs, getattr(solver, "rk", 3))
     cache = _memory or _load_file()
     _memory.update(cache)
     if key in _memory:
