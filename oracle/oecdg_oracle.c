@@ -534,16 +534,21 @@ int ora1d_run(const ora1d *p, double cfl, int rk, int oe, double t_end, long nst
     return rc;
 }
 
-/* One SSP-RK3 stage l in the c/d form of eq:RKCDG given u_sigma^n and
- * u_sigma^{n,l} (the other c_{lm}, d_{lm} of SSP-RK3 vanish), followed by
- * F_tau:  out = F_tau( c_{l0} u^n + c_{ll} u^l + tau d_{ll} L(u^l) ). */
-int ora1d_ssprk3_stage(const ora1d *p, int l, int oe, double tau, double tau_max,
-                       const double *unC, const double *unD, const double *ulC, const double *ulD,
-                       double *outC, double *outD)
+/* One stage l of the RK table rk in the c/d form of eq:RKCDG given u_sigma^n
+ * and u_sigma^{n,l}, followed by F_tau:
+ *   out = F_tau( c_{l0} u^n + c_{ll} u^l + tau d_{ll} L(u^l) ),
+ * for the stages whose other c_{lm}, d_{lm} vanish (every stage of forward
+ * Euler, SSP-RK2 and SSP-RK3, the first three of classical RK4); EINVAL for
+ * the others. */
+int ora1d_rk_stage(const ora1d *p, int rk, int l, int oe, double tau, double tau_max,
+                   const double *unC, const double *unD, const double *ulC, const double *ulD,
+                   double *outC, double *outD)
 {
     double c[4][4], d[4][4];
-    rk_table(3, c, d);
-    if (l < 0 || l > 2) return ORA_EINVAL;
+    const int s = rk_table(rk, c, d);
+    if (s == 0 || l < 0 || l >= s) return ORA_EINVAL;
+    for (int m = 0; m < l; ++m)             /* only u^n, u^{n,l} and L(u^{n,l}) may enter */
+        if ((m > 0 && c[l][m] != 0.0) || d[l][m] != 0.0) return ORA_EINVAL;
     const long sz_C = (long)p->nc * (p->k + 1) * ora1d_ncell(p, 0);
     const long sz_D = (long)p->nc * (p->k + 1) * ora1d_ncell(p, 1);
     double *LC = malloc(sizeof(double) * sz_C), *LD = malloc(sizeof(double) * sz_D);
@@ -551,13 +556,20 @@ int ora1d_ssprk3_stage(const ora1d *p, int l, int oe, double tau, double tau_max
     int rc = ora1d_rhs(p, tau_max, ulC, ulD, LC, LD);
     for (long e = 0; e < sz_C; ++e) outC[e] = c[l][0] * unC[e] + (c[l][l] * ulC[e] + tau * d[l][l] * LC[e]);
     for (long e = 0; e < sz_D; ++e) outD[e] = c[l][0] * unD[e] + (c[l][l] * ulD[e] + tau * d[l][l] * LD[e]);
-    if (l == 0) {   /* c_{00} = 1 multiplies u^n = u^{n,0} itself */
-        for (long e = 0; e < sz_C; ++e) outC[e] = ulC[e] + tau * d[0][0] * LC[e];
-        for (long e = 0; e < sz_D; ++e) outD[e] = ulD[e] + tau * d[0][0] * LD[e];
+    if (l == 0) {   /* c_{00} multiplies u^n = u^{n,0} itself */
+        for (long e = 0; e < sz_C; ++e) outC[e] = c[0][0] * ulC[e] + tau * d[0][0] * LC[e];
+        for (long e = 0; e < sz_D; ++e) outD[e] = c[0][0] * ulD[e] + tau * d[0][0] * LD[e];
     }
     if (oe && rc == ORA_OK) rc = ora1d_oe(p, tau, outC, outD);
     if (rc == ORA_OK) rc = check_state(p, outC, outD);
     free(LC);
     free(LD);
     return rc;
+}
+
+int ora1d_ssprk3_stage(const ora1d *p, int l, int oe, double tau, double tau_max,
+                       const double *unC, const double *unD, const double *ulC, const double *ulD,
+                       double *outC, double *outD)
+{
+    return ora1d_rk_stage(p, 3, l, oe, tau, tau_max, unC, unD, ulC, ulD, outC, outD);
 }

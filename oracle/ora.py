@@ -59,6 +59,8 @@ def lib():
         L.ora1d_max_wavespeed.restype = C.c_double
         L.ora1d_step.argtypes = [P1, C.c_int, C.c_int, C.c_double, C.c_double, _DP, _DP]
         L.ora1d_ssprk3_stage.argtypes = [P1, C.c_int, C.c_int, C.c_double, C.c_double, _DP, _DP, _DP, _DP, _DP, _DP]
+        L.ora1d_rk_stage.argtypes = [P1, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                     _DP, _DP, _DP, _DP, _DP, _DP]
         L.ora1d_run.argtypes = [P1, C.c_double, C.c_int, C.c_int, C.c_double, C.c_long, C.c_double,
                                 _DP, _DP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
         P2 = C.POINTER(Ora2D)
@@ -147,6 +149,16 @@ def ssprk3_stage1d(prob, l, tau, tau_max, unC, unD, ulC, ulD, oe=True):
     oC, oD = np.zeros_like(unC), np.zeros_like(unD)
     _check(lib().ora1d_ssprk3_stage(C.byref(_p1(prob)), l, int(oe), tau, tau_max, unC, unD, ulC, ulD, oC, oD),
            "ssprk3_stage1d")
+    return oC, oD
+
+
+def rk_stage1d(prob, rk, l, tau, tau_max, unC, unD, ulC, ulD, oe=True):
+    """One stage l of RK table rk from u^n and u^{n,l}, then F_tau (stages that
+    read only u^n, u^{n,l} and L(u^{n,l}))."""
+    unC, unD, ulC, ulD = _arr(unC), _arr(unD), _arr(ulC), _arr(ulD)
+    oC, oD = np.zeros_like(unC), np.zeros_like(unD)
+    _check(lib().ora1d_rk_stage(C.byref(_p1(prob)), rk, l, int(oe), tau, tau_max, unC, unD, ulC, ulD, oC, oD),
+           "rk_stage1d")
     return oC, oD
 
 

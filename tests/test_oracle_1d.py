@@ -585,3 +585,24 @@ def test_nonphysical_state_is_reported():
     with pytest.raises(ora.OracleError) as e:
         ora.run1d(prob, uC, uD, nsteps=1, cfl=0.15)
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("rk", [1, 2, 3, 4])
+def test_single_stages_compose_to_a_step(rk):
+    """eq:RKCDG stage by stage: chaining the single-stage function over the
+    stages of forward Euler, SSP-RK2 and SSP-RK3 gives the oracle's step; the
+    last stage of classical RK4, which reads earlier stages, is refused."""
+    prob, uC, uD = inputs.euler_riemann(120, 2, inputs.riemann_states(1))
+    tau_max = 0.15 * prob.h / ora.max_wavespeed1d(prob, uC, uD)
+    tau = 0.9 * tau_max
+    s = {1: 1, 2: 2, 3: 3, 4: 4}[rk]
+    ul = (uC, uD)
+    for l in range(s):
+        if rk == 4 and l == 3:
+            with pytest.raises(ora.OracleError):
+                ora.rk_stage1d(prob, rk, l, tau, tau_max, uC, uD, *ul)
+            return
+        ul = ora.rk_stage1d(prob, rk, l, tau, tau_max, uC, uD, *ul)
+    rC, rD = ora.step1d(prob, tau, tau_max, uC, uD, rk=rk)
+    np.testing.assert_allclose(ul[0], rC, rtol=1e-14, atol=1e-14 * np.abs(rC).max())
+    np.testing.assert_allclose(ul[1], rD, rtol=1e-14, atol=1e-14 * np.abs(rD).max())
