@@ -137,11 +137,14 @@ int oecdg_set_option(oecdg_handle *h, int32_t key, int64_t value);
  * both meshes).  Device inputs, host output; synchronises the stream. */
 int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out);
 
-/* One SSP-RK3 stage of eq. RKCDG followed by the OE step (OEstep1), whatever
- * the descriptor's rk:
+/* One stage l of the handle's RK method (eq. RKCDG) followed by the OE step
+ * (OEstep1):
  *   u_sigma^{n,l+1} = F_tau( c_{l0} u^n + c_{ll} u_sigma^{n,l} + tau d_{ll} L(u_sigma^{n,l}) )
- * with (c_{00}, d_{00}) = (1, 1), (c_{10}, c_{11}, d_{11}) = (3/4, 1/4, 1/4),
- * (c_{20}, c_{22}, d_{22}) = (1/3, 2/3, 2/3).  stage in {0, 1, 2}; dt = tau,
+ * e.g. SSP-RK3: (c_{00}, d_{00}) = (1, 1), (c_{10}, c_{11}, d_{11}) = (3/4, 1/4, 1/4),
+ * (c_{20}, c_{22}, d_{22}) = (1/3, 2/3, 2/3); at stage 0, u^n is u_sigma^{n,0}
+ * and c_{00} multiplies it once.  stage in 0 .. s-1 (EINVAL otherwise); the last
+ * stage of classical RK4, which reads the earlier stages, is EUNSUPPORTED.  2D
+ * handles run SSP-RK3 stages.  dt = tau,
  * tau_max = the coupling parameter of the operator.  uC_n/uD_n = u_sigma^n,
  * uC_l/uD_l = u_sigma^{n,l} (ignored/aliasable for stage 0); outputs must not
  * alias inputs.  Single instance handles only.  Device pointers. */

@@ -787,18 +787,19 @@ int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out
 int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max, const double *uC_n, const double *uD_n,
                 const double *uC_l, const double *uD_l, double *uC_out, double *uD_out) {
     if (!h || !uC_n || !uD_n || !uC_out || !uD_out) return OECDG_EINVAL;
-    if (stage < 0 || stage > 2) return fail(h, OECDG_EINVAL, "stage must be 0, 1 or 2");
+    const int ns = h->dim == 1 ? rk_stages(h->rk) : 3;
+    if (stage < 0 || stage >= ns) return fail(h, OECDG_EINVAL, "stage out of range for the RK method");
+    if (h->dim == 1 && h->rk == 4 && stage == 3)
+        return fail(h, OECDG_EUNSUPPORTED, "the last stage of classical RK4 reads the earlier stages");
     if (!(dt > 0.0) || !(tau_max > 0.0)) return fail(h, OECDG_EINVAL, "dt and tau_max must be positive");
-    if (stage > 0 && (!uC_l || !uD_l)) return fail(h, OECDG_EINVAL, "stages 1 and 2 need u_l");
+    if (stage > 0 && (!uC_l || !uD_l)) return fail(h, OECDG_EINVAL, "stages after the first need u_l");
     if (h->dim != 1) {
         return oecdg::stage_2d(h, stage, dt, tau_max, uC_n, uD_n, uC_l, uD_l, uC_out, uD_out);
     }
     if (h->nbatch != 1) return fail(h, OECDG_EUNSUPPORTED, "oecdg_stage takes single-instance handles");
     StageArgs a = base_args(h);
     const int sp = stage & 1;                 // step index 0: global stage parity = stage
-    a.l = stage;
-    a.rk = 3;                                 // a single stage is always an SSP-RK3 stage
-    a.ns = 3;
+    a.l = stage;                              // a.rk, a.ns: the handle's method (base_args)
     a.par = 0;
     a.first = 0;
     a.tau_override = dt;
@@ -814,9 +815,12 @@ int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max, const
     HIPCHK(h, launch_init_1d(a, 1, h->stream));
     int rcs = stage_all(h, a);
     if (rcs != OECDG_OK) return rcs;
-    // final OE with (tau, executed steps) chosen so that it reads that output
+    // final OE with (tau, executed steps) chosen so that it reads that output:
+    // counted as stage + 1 steps of a three-stage method, the buffer parity of
+    // the final kernel is that of the stage's output
     Final f{0.0, dt, (long long)stage + 1};
     HIPCHK(h, hipMemcpyAsync(h->fin, &f, sizeof(Final), hipMemcpyHostToDevice, h->stream));
+    a.ns = 3;
     a.dstC = uC_out;
     a.dstD = uD_out;
     int rcf = final_all(h, a);

@@ -108,18 +108,33 @@ def test_batched_instances_match_their_own_runs(rk):
         assert _rel(bC, bD, rC, rD) <= RUN_TOL, b
 
 
-def test_single_stage_call_stays_ssp_rk3():
-    """oecdg_stage computes an SSP-RK3 stage whatever the handle's method."""
+@pytest.mark.parametrize("rk", [1, 2, 3, 4])
+def test_single_stage_follows_the_rk_method(rk):
+    """oecdg_stage computes stage l of the handle's method (1e-12 against the
+    oracle's single stage); the last stage of classical RK4 is refused, and a
+    stage index past the method's stages is invalid."""
     prob, uC, uD = inputs.euler_riemann(130, 2, inputs.riemann_states(0))
+    rng = np.random.default_rng(rk)
+    lC = uC * (1.0 + 0.01 * rng.standard_normal(uC.shape))
+    lD = uD * (1.0 + 0.01 * rng.standard_normal(uD.shape))
     tau = 0.1 * prob.h
-    outs = []
-    for rk in (3, 4):
-        with OECDG(prob, 0.15, rk=rk) as s:
-            o = s.stage(1, tau, 1.3 * tau, to_device(uC), to_device(uD), to_device(uC), to_device(uD))
-            outs.append((o[0].cpu().numpy(), o[1].cpu().numpy()))
-    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
-    rC, rD = ora.ssprk3_stage1d(prob, 1, tau, 1.3 * tau, uC, uD, uC, uD)
-    assert _rel(outs[1][0].reshape(rC.shape), outs[1][1].reshape(rD.shape), rC, rD) <= 1e-12
+    s = {1: 1, 2: 2, 3: 3, 4: 4}[rk]
+    with OECDG(prob, 0.15, rk=rk) as h:
+        for l in range(s):
+            print(f"[stage] rk={rk} l={l}", flush=True)
+            if rk == 4 and l == 3:
+                with pytest.raises(_lib.OECDGError) as e:
+                    h.stage(l, tau, 1.3 * tau, to_device(uC), to_device(uD), to_device(lC), to_device(lD))
+                assert e.value.code == _lib.EUNSUPPORTED
+                continue
+            ulC, ulD = (uC, uD) if l == 0 else (lC, lD)
+            o = h.stage(l, tau, 1.3 * tau, to_device(uC), to_device(uD), to_device(ulC), to_device(ulD))
+            rC, rD = ora.rk_stage1d(prob, rk, l, tau, 1.3 * tau, uC, uD, ulC, ulD)
+            gC, gD = o[0].cpu().numpy().reshape(rC.shape), o[1].cpu().numpy().reshape(rD.shape)
+            assert _rel(gC, gD, rC, rD) <= 1e-12, l
+        with pytest.raises(_lib.OECDGError) as e:
+            h.stage(s, tau, 1.3 * tau, to_device(uC), to_device(uD), to_device(lC), to_device(lD))
+        assert e.value.code == _lib.EINVAL
 
 
 def test_adjoint_refuses_other_rk_methods():

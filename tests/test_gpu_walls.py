@@ -128,3 +128,14 @@ def test_walls_need_the_euler_flux():
     with pytest.raises(_lib.OECDGError) as e:
         OECDG(prob, 0.2)
     assert e.value.code == _lib.EUNSUPPORTED
+
+
+@pytest.mark.parametrize("rk,k,cfl", [(4, 3, 0.2), (2, 1, 0.45)])
+def test_walls_with_other_rk_methods(rk, k, cfl):
+    """Walls combined with classical RK4 (the accumulated damped stages) and
+    SSP-RK2, blast-wave data, N = 640, to T = 0.004."""
+    prob, uC, uD = inputs.euler_blast_waves(640, k, **BLAST)
+    gC, gD, t, ns = gpu_run(prob, uC, uD, cfl, rk=rk, t_end=0.004)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, t_end=0.004, cfl=cfl, rk=rk)
+    assert (ns, t) == (rn, rt)
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
