@@ -30,22 +30,33 @@ namespace oecdg {
 // Threads per workgroup: two per cell (one per half cell) for the T primal
 // and the T dual cells of a tile.
 __host__ __device__ constexpr int nthreads(int T) { return 4 * T; }
+// A mesh with nd = np + 1 dual cells and np a multiple of T has one dual cell
+// (np) beyond np / T full tiles.  Rather than a tile of its own (one
+// workgroup more than there are CUs for the 16384-cell workload: 15.0 instead
+// of 12.8 us per stage), launches of such handles carry one more wave, whose
+// first lane pair updates that cell in the instance's last tile.  Tiles of
+// 128 keep the extra tile (a fifth wave per SIMD would cap the registers).
+__host__ __device__ constexpr int max_threads(int T) { return nthreads(T) + tail_threads(T); }
 
 // Segmented reduction over the two halves of a workgroup (primal threads
 // [0, H), dual threads [H, 2H)), H a multiple of the wave size.  NV values per
 // thread, kinds given.  On return the threads tid == 0 (primal) and tid == H
-// (dual) hold the half's result (waves combined in order).
-// scratch: NV * (2H / WAVE) doubles of LDS.
+// (dual) hold the half's result (waves combined in order).  xwave: the
+// launch's extra wave (threads [2H, 2H + WAVE)) carries a cell and reduces its
+// own values, left in scratch at wave 2H / WAVE; otherwise it does no work here.
+// scratch: NV * (2H / WAVE + 1) doubles of LDS.
 template <int H, int NV>
-__device__ void reduce_halves(double (&v)[NV], const int (&kind)[NV], double *scratch) {
+__device__ void reduce_halves(double (&v)[NV], const int (&kind)[NV], double *scratch, bool xwave, bool xwl) {
     static_assert(H % WAVE == 0, "halves are whole waves");
     constexpr int WPH = H / WAVE;          // waves per half
     const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+    if (!xwl || tid < 2 * H || xwave) {
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = wave_reduce(kind[j], v[j]);
-    if (lane == WAVE - 1) {
+        for (int j = 0; j < NV; ++j) v[j] = wave_reduce(kind[j], v[j]);
+        if (lane == WAVE - 1) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j) scratch[wave * NV + j] = v[j];
+            for (int j = 0; j < NV; ++j) scratch[wave * NV + j] = v[j];
+        }
     }
     __syncthreads();
     if (tid == 0 || tid == H) {
@@ -232,9 +243,10 @@ __device__ inline void mirror_ghosts(const Inst1D &I, int i0, double *sC) {
 
 template <int K, int NC, int T>
 __device__ inline void load_tile(const Inst1D &I, int i0, const double *__restrict__ inC,
-                                 const double *__restrict__ inD, double *s) {
+                                 const double *__restrict__ inD, double *s, bool xwl) {
     constexpr int PER = NC * (K + 1) * (T + 2);
-    for (int e = threadIdx.x; e < 2 * PER; e += nthreads(T)) s[e] = tile_elem<K, NC, T>(I, i0, inC, inD, e);
+    if (!xwl || threadIdx.x < nthreads(T))
+        for (int e = threadIdx.x; e < 2 * PER; e += nthreads(T)) s[e] = tile_elem<K, NC, T>(I, i0, inC, inD, e);
 }
 
 // Apply F_tau in LDS to primal cells [i0-1, i0+T-1] and dual cells [i0, i0+T]
@@ -301,7 +313,7 @@ __device__ inline void damp_tile(const Inst1D &I, int i0, double *sC, double *sD
 template <int K, int FLUX, int T>
 __device__ inline void tile_partials(const Inst1D &I, bool valid, int mesh, int hf,
                                      const double (&out)[FluxT<FLUX>::NC][K + 1], double *part, long long ntot,
-                                     int tile, double *scratch) {
+                                     int tile, double *scratch, bool xwave, bool xwl) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, NV = 3 * NC + 1;
     constexpr Tab<K> tb = make_tab<K>();
@@ -331,13 +343,27 @@ __device__ inline void tile_partials(const Inst1D &I, bool valid, int mesh, int 
     for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
     kind[NV - 1] = 1;
     v[NV - 1] = valid ? F::speed(ubar, I.p0) : -INFINITY;
-    reduce_halves<2 * T, NV>(v, kind, scratch);
+    reduce_halves<2 * T, NV>(v, kind, scratch, xwave, xwl);
     if (threadIdx.x == 0 || threadIdx.x == 2 * T) {
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
             for (int kd = 0; kd < 3; ++kd) part[stat_index(mesh, q, kd) * ntot + tile] = v[3 * q + kd];
         part[(ST_BETA + mesh) * ntot + tile] = v[NV - 1];
+    }
+    // the extra wave's dual cell np gets the next column, as the separate
+    // tile of that cell would have written it (no primal cells: identities)
+    if (xwave && threadIdx.x == 4 * T) {
+        const double *xs = scratch + (4 * T / WAVE) * NV;
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int kd = 0; kd < 3; ++kd) {
+                part[stat_index(0, q, kd) * ntot + tile + 1] = stat_identity(kd);
+                part[stat_index(1, q, kd) * ntot + tile + 1] = xs[3 * q + kd];
+            }
+        part[ST_BETA * ntot + tile + 1] = -INFINITY;
+        part[(ST_BETA + 1) * ntot + tile + 1] = xs[NV - 1];
     }
 }
 
@@ -356,14 +382,33 @@ __device__ inline void finish_stats(const Inst1D &I, const double *red, double (
 }
 
 constexpr int lds_doubles(int K, int NC, int T) { return 2 * NC * (K + 1) * (T + 2); }
-constexpr int scratch_doubles(int T) { return NSTAT * ((nthreads(T) + WAVE - 1) / WAVE) + NSTAT; }
+constexpr int scratch_doubles(int T) { return NSTAT * ((max_threads(T) + WAVE - 1) / WAVE) + NSTAT; }
+
+// Cell of thread tid in a tile: primal cell tid/2 < T, dual cell tid/2 - T < T
+// (both relative to i0); the extra wave's first lane pair takes dual cell T of
+// a tail tile (the instance's dual cell np), its other lanes no cell.  c is
+// kept within the LDS tile; returns whether the thread has a cell.
+template <int T>
+__device__ inline bool cell_of(const Inst1D &I, int tile, int i0, int tid, int &mesh, int &c, int &gi, bool xwl) {
+    const int cidx = tid >> 1;
+    mesh = cidx < T ? 0 : 1;
+    c = cidx - mesh * T;
+    if (xwl && c >= T) {
+        const bool tail = I.tail && tile == I.tile0 + I.ntiles - 1 && c == T;
+        c = T;
+        gi = i0 + T;
+        return tail && gi < I.nd;
+    }
+    gi = i0 + c;
+    return gi < (mesh == 0 ? I.np : I.nd);
+}
 
 // ---------------------------------------------------------- stage tile ---
 // Thread tid works on cell tid/2 of the tile (primal cells first) and on the
 // half cell tid%2 of it.
 
 template <int K, int FLUX, int T>
-__device__ void stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem) {
+__device__ void stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1, W = T + 2, PER = NC * K1 * W, NT = nthreads(T);
     constexpr int NLD = (2 * PER + NT - 1) / NT;
@@ -388,12 +433,11 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     double *red = smem + lds_doubles(K, NC, T);
     double *scratch = red + NSTAT;
 
-    const int cidx = tid >> 1, hf = tid & 1;
-    const int mesh = cidx < T ? 0 : 1;
-    const int c = cidx - mesh * T;
-    const int gi = i0 + c;
+    const int hf = tid & 1;
+    int mesh, c, gi;
+    const bool valid = cell_of<T>(I, tile, i0, tid, mesh, c, gi, xwl);
+    const bool mainthr = !xwl || tid < NT;      // not the launch's extra wave
     const int ncell = mesh == 0 ? I.np : I.nd;
-    const bool valid = gi < ncell;
     double *UM = (mesh == 0 ? a.UC + I.offC : a.UD + I.offD);
     const bool damp = a.damp_input && I.oe && K > 0 && !(l == 0 && first);
     const bool need_beta = l == 0 && !single && a.dt_fixed <= 0.0;
@@ -410,11 +454,11 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
 #pragma unroll
         for (int i = 0; i < NLD; ++i) {
             const int e = tid + i * NT;
-            pre[i] = e < 2 * PER ? tile_elem<K, NC, T>(I, i0, inC, inD, e) : 0.0;
+            pre[i] = (e < 2 * PER && mainthr) ? tile_elem<K, NC, T>(I, i0, inC, inD, e) : 0.0;
         }
     }
     Partials<NC> pv;
-    if (need_red) load_partials<NT, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.ntiles, ns, pv);
+    if (need_red) load_partials<NT, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, pv, xwl);
 
     if (!single) {
         if (l == 0 && cur.t >= a.t_end) {    // a step that is not taken: carry the time over
@@ -426,7 +470,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
         }
         if (l > 0 && cur.done) return;
     }
-    if (need_red) finish_partials<NT, NC>(pv, a.part[sp ^ 1], a.ntiles, I.tile0, I.ntiles, ns, red, scratch);
+    if (need_red) finish_partials<NT, NC>(pv, a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, red, scratch, xwl);
 
     double tau, taumax;
     int last = 0;
@@ -467,7 +511,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
         const int e = tid + i * NT;
-        if (e < 2 * PER) smem[e] = pre[i];
+        if (e < 2 * PER && mainthr) smem[e] = pre[i];
     }
     // u^n of this thread's cell: its latency overlaps the damping below
     double un[NC][K1];
@@ -484,116 +528,123 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     }
     if (damp) damp_tile<K, FLUX, T>(I, i0, sC, sD, sig, tau_in);
 
-    // own cell; the overlapping cell of this thread's half
-    double own[NC][K1], nb[NC][K1];
-    if (mesh == 0) {
-        lds_cell<K, NC, W>(sC, c + 1, own);
-        lds_cell<K, NC, W>(sD, c + 1 + hf, nb);
-    } else {
-        lds_cell<K, NC, W>(sD, c + 1, own);
-        lds_cell<K, NC, W>(sC, c + hf, nb);
-    }
-    if (l == 0 && !single && valid) {
-#pragma unroll
-        for (int q = 0; q < NC; ++q)
-#pragma unroll
-            for (int m = 0; m < K1; ++m)
-                if (((q * K1 + m) & 1) == hf) UM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
-    }
-    if (l > 0 && a.DC && valid) {          // damped stage input, kept for the adjoint
-        double *DM = mesh == 0 ? a.DC + I.offC : a.DD + I.offD;
-#pragma unroll
-        for (int q = 0; q < NC; ++q)
-#pragma unroll
-            for (int m = 0; m < K1; ++m)
-                if (((q * K1 + m) & 1) == hf) DM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
-    }
-
-    const double inv_tm = 1.0 / taumax;
-    double r[NC][K1];
-    cdg_rate_half<K, FLUX>(nb, hf, I.p0, inv_tm, 1.0 / I.h, r);
-
-    // eq:RKCDG: out = c_{l0} u^n [+ accumulated earlier stages] + c_{ll} u^l + tau d_{ll} L(u^l)
-    const RKStage rs = rk_stage(a.rk, l);
-    const double td = tau * rs.d;
-    double *AM = nullptr;
-    if (rs.acc_read || rs.ca != 0.0) AM = mesh == 0 ? a.AC + I.offC : a.AD + I.offD;
+    // A launch's extra wave computes only in the tile that carries dual cell np.
+    const bool tail_tile = I.tail && tile == I.tile0 + I.ntiles - 1;
     double out[NC][K1];
-    bool finite = true;
 #pragma unroll
     for (int q = 0; q < NC; ++q)
 #pragma unroll
-        for (int m = 0; m < K1; ++m) {
-            const double both = r[q][m] + pair_swap(r[q][m]);   // the two halves (a + b == b + a)
-            const double rate = both - inv_tm * own[q][m];
-            const double v = fma(td, rate, rs.cw * own[q][m]);
-            double o = v;
-            if (l > 0) {
-                double base = rs.cn * un[q][m];
-                if (rs.acc_read) base += valid ? AM[(long long)(q * K1 + m) * ncell + gi] : 0.0;
-                o = base + v;
-            }
-            out[q][m] = o;
-            finite = finite && isfinite(o);
+        for (int m = 0; m < K1; ++m) out[q][m] = 0.0;
+    if (mainthr || tail_tile) {
+        // own cell; the overlapping cell of this thread's half
+        double own[NC][K1], nb[NC][K1];
+        if (mesh == 0) {
+            lds_cell<K, NC, W>(sC, c + 1, own);
+            lds_cell<K, NC, W>(sD, c + 1 + hf, nb);
+        } else {
+            lds_cell<K, NC, W>(sD, c + 1, own);
+            lds_cell<K, NC, W>(sC, c + hf, nb);
         }
-    if (rs.ca != 0.0 && valid) {           // classical RK4: this stage's damped input joins the sum
+        if (l == 0 && !single && valid) {
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int m = 0; m < K1; ++m)
+                    if (((q * K1 + m) & 1) == hf) UM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
+        }
+        if (l > 0 && a.DC && valid) {          // damped stage input, kept for the adjoint
+            double *DM = mesh == 0 ? a.DC + I.offC : a.DD + I.offD;
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int m = 0; m < K1; ++m)
+                    if (((q * K1 + m) & 1) == hf) DM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
+        }
+
+        const double inv_tm = 1.0 / taumax;
+        double r[NC][K1];
+        cdg_rate_half<K, FLUX>(nb, hf, I.p0, inv_tm, 1.0 / I.h, r);
+
+        // eq:RKCDG: out = c_{l0} u^n [+ accumulated earlier stages] + c_{ll} u^l + tau d_{ll} L(u^l)
+        const RKStage rs = rk_stage(a.rk, l);
+        const double td = tau * rs.d;
+        double *AM = nullptr;
+        if (rs.acc_read || rs.ca != 0.0) AM = mesh == 0 ? a.AC + I.offC : a.AD + I.offD;
+        bool finite = true;
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 0; m < K1; ++m)
-                if (((q * K1 + m) & 1) == hf) {
-                    double *p = AM + (long long)(q * K1 + m) * ncell + gi;
-                    *p = rs.acc_first ? rs.ca * own[q][m] : fma(rs.ca, own[q][m], *p);
+            for (int m = 0; m < K1; ++m) {
+                const double both = r[q][m] + pair_swap(r[q][m]);   // the two halves (a + b == b + a)
+                const double rate = both - inv_tm * own[q][m];
+                const double v = fma(td, rate, rs.cw * own[q][m]);
+                double o = v;
+                if (l > 0) {
+                    double base = rs.cn * un[q][m];
+                    if (rs.acc_read) base += valid ? AM[(long long)(q * K1 + m) * ncell + gi] : 0.0;
+                    o = base + v;
                 }
-    }
-    double *OM = (mesh == 0 ? a.BC[sp ^ 1] + I.offC : a.BD[sp ^ 1] + I.offD);
-    if (valid) {
+                out[q][m] = o;
+                finite = finite && isfinite(o);
+            }
+        if (rs.ca != 0.0 && valid) {           // classical RK4: this stage's damped input joins the sum
 #pragma unroll
-        for (int q = 0; q < NC; ++q)
+            for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 0; m < K1; ++m)
-                if (((q * K1 + m) & 1) == hf) OM[(long long)(q * K1 + m) * ncell + gi] = out[q][m];
-        double ubar[NC];
+                for (int m = 0; m < K1; ++m)
+                    if (((q * K1 + m) & 1) == hf) {
+                        double *p = AM + (long long)(q * K1 + m) * ncell + gi;
+                        *p = rs.acc_first ? rs.ca * own[q][m] : fma(rs.ca, own[q][m], *p);
+                    }
+        }
+        double *OM = (mesh == 0 ? a.BC[sp ^ 1] + I.offC : a.BD[sp ^ 1] + I.offD);
+        if (valid) {
 #pragma unroll
-        for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
-        const bool phys = F::physical(ubar, I.p0);
-        if (hf == 0 && (!finite || !phys)) {
-            if (!finite) a.err[0] = 1;
-            if (!phys) a.err[1] = 1;
-            a.err[3] = (int)(a.fin[tl.inst].nexec + 1);
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int m = 0; m < K1; ++m)
+                    if (((q * K1 + m) & 1) == hf) OM[(long long)(q * K1 + m) * ncell + gi] = out[q][m];
+            double ubar[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
+            const bool phys = F::physical(ubar, I.p0);
+            if (hf == 0 && (!finite || !phys)) {
+                if (!finite) a.err[0] = 1;
+                if (!phys) a.err[1] = 1;
+                a.err[3] = (int)(a.fin[tl.inst].nexec + 1);
+            }
         }
     }
-    tile_partials<K, FLUX, T>(I, valid, mesh, hf, out, a.part[sp], a.ntiles, tile, scratch);
+    tile_partials<K, FLUX, T>(I, valid, mesh, hf, out, a.part[sp], a.ntiles, tile, scratch, xwl && tail_tile, xwl);
     __syncthreads();
 }
 
 // Statistics of a given state (srcC/srcD) into part[1]: the partials that the
 // first stage of a run reads (beta for tau^0).
 template <int K, int FLUX, int T>
-__device__ void stats_tile(const StageArgs &a, int tile, double *smem) {
+__device__ void stats_tile(const StageArgs &a, int tile, double *smem, bool xwl) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1;
     const Tile1D tl = a.ninst == 1 ? Tile1D{0, tile * T} : a.tiles[tile];
     const Inst1D I = a.ninst == 1 ? a.inst0 : a.inst[tl.inst];
-    const int tid = threadIdx.x;
-    const int cidx = tid >> 1, hf = tid & 1;
-    const int mesh = cidx < T ? 0 : 1;
-    const int gi = tl.i0 + cidx - mesh * T;
+    const int tid = threadIdx.x, hf = tid & 1;
+    int mesh, c, gi;
+    const bool valid = cell_of<T>(I, tile, tl.i0, tid, mesh, c, gi, xwl);
     const int ncell = mesh == 0 ? I.np : I.nd;
-    const bool valid = gi < ncell;
     const double *src = mesh == 0 ? a.srcC + I.offC : a.srcD + I.offD;
     double u[NC][K1];
 #pragma unroll
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int m = 0; m < K1; ++m) u[q][m] = valid ? src[(long long)(q * K1 + m) * ncell + gi] : 1.0;
-    tile_partials<K, FLUX, T>(I, valid, mesh, hf, u, a.part[1], a.ntiles, tile, smem + NSTAT);
+    tile_partials<K, FLUX, T>(I, valid, mesh, hf, u, a.part[1], a.ntiles, tile, smem + NSTAT,
+                              xwl && I.tail && tile == I.tile0 + I.ntiles - 1, xwl);
     __syncthreads();
 }
 
 // Final OE: u_sigma^N = F_tau(output of the last stage of step N-1) into (dstC, dstD); copy if no step ran.
 template <int K, int FLUX, int T>
-__device__ void final_tile(const StageArgs &a, int tile, double *smem) {
+__device__ void final_tile(const StageArgs &a, int tile, double *smem, bool xwl) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1, W = T + 2;
     const int tid = threadIdx.x;
@@ -608,11 +659,11 @@ __device__ void final_tile(const StageArgs &a, int tile, double *smem) {
     const bool damp = N > 0 && I.oe && K > 0;
     double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
     if (damp) {
-        reduce_instance<nthreads(T), NC>(a.part[(int)((a.ns * N - 1) & 1)], a.ntiles, I.tile0, I.ntiles, false, red,
-                                         scratch);
+        reduce_instance<nthreads(T), NC>(a.part[(int)((a.ns * N - 1) & 1)], a.ntiles, I.tile0, I.npart, false, red,
+                                         scratch, xwl);
         finish_stats<NC>(I, red, sig);
     }
-    load_tile<K, NC, T>(I, tl.i0, a.BC[bp] + I.offC, a.BD[bp] + I.offD, smem);
+    load_tile<K, NC, T>(I, tl.i0, a.BC[bp] + I.offC, a.BD[bp] + I.offD, smem, xwl);
     __syncthreads();
     if constexpr (FLUX == 3) {
         if (has_wall_ghost<K, NC, T>(I, tl.i0)) {
@@ -621,12 +672,11 @@ __device__ void final_tile(const StageArgs &a, int tile, double *smem) {
         }
     }
     if (damp) damp_tile<K, FLUX, T>(I, tl.i0, sC, sD, sig, tau);
-    const int cidx = tid >> 1, hf = tid & 1;
-    const int mesh = cidx < T ? 0 : 1;
-    const int c = cidx - mesh * T;
-    const int gi = tl.i0 + c;
+    const int hf = tid & 1;
+    int mesh, c, gi;
+    const bool valid = cell_of<T>(I, tile, tl.i0, tid, mesh, c, gi, xwl);
     const int ncell = mesh == 0 ? I.np : I.nd;
-    if (gi < ncell) {
+    if (valid) {
         const double *s = mesh == 0 ? sC : sD;
         double *dst = mesh == 0 ? a.dstC + I.offC : a.dstD + I.offD;
 #pragma unroll
@@ -661,44 +711,48 @@ struct Disp {
 };
 
 template <int K, int FLUX, int T> struct StageFn {
-    __device__ static void go(const StageArgs &a, int l, int par, int first, int tile, double *smem) {
-        stage_tile<K, FLUX, T>(a, l, par, first, tile, smem);
+    __device__ static void go(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl) {
+        stage_tile<K, FLUX, T>(a, l, par, first, tile, smem, xwl);
     }
 };
 template <int K, int FLUX, int T> struct StatsFn {
-    __device__ static void go(const StageArgs &a, int tile, double *smem) { stats_tile<K, FLUX, T>(a, tile, smem); }
+    __device__ static void go(const StageArgs &a, int tile, double *smem, bool xwl) {
+        stats_tile<K, FLUX, T>(a, tile, smem, xwl);
+    }
 };
 template <int K, int FLUX, int T> struct FinalFn {
-    __device__ static void go(const StageArgs &a, int tile, double *smem) { final_tile<K, FLUX, T>(a, tile, smem); }
+    __device__ static void go(const StageArgs &a, int tile, double *smem, bool xwl) {
+        final_tile<K, FLUX, T>(a, tile, smem, xwl);
+    }
 };
 
-template <int KM, int FLUX, int T>
-__global__ __launch_bounds__(4 * T) void k_stage(StageArgs a) {
+template <int KM, int FLUX, int T, bool XW>
+__global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_stage(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
         const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-        D::template run<StageFn>(k, a, a.l, a.par, a.first, tile, smem);
+        D::template run<StageFn>(k, a, a.l, a.par, a.first, tile, smem, XW);
     }
 }
 
-template <int KM, int FLUX, int T>
-__global__ __launch_bounds__(4 * T) void k_stats(StageArgs a) {
+template <int KM, int FLUX, int T, bool XW>
+__global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_stats(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
         const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-        D::template run<StatsFn>(k, a, tile, smem);
+        D::template run<StatsFn>(k, a, tile, smem, XW);
     }
 }
 
-template <int KM, int FLUX, int T>
-__global__ __launch_bounds__(4 * T) void k_final(StageArgs a) {
+template <int KM, int FLUX, int T, bool XW>
+__global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_final(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
         const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-        D::template run<FinalFn>(k, a, tile, smem);
+        D::template run<FinalFn>(k, a, tile, smem, XW);
     }
 }
 
@@ -733,8 +787,8 @@ __device__ inline void grid_barrier(const StageArgs &a) {
 // Persistent launch: every workgroup walks all steps and stages; a grid
 // barrier separates consecutive stages.  The statistics a workgroup reads after
 // a barrier are read coherently (a.coherent).
-template <int KM, int FLUX, int T>
-__global__ __launch_bounds__(4 * T) void k_persistent(StageArgs a, long long nsteps, int single_instance) {
+template <int KM, int FLUX, int T, bool XW>
+__global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_persistent(StageArgs a, long long nsteps, int single_instance) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (long long n = 0; n < nsteps; ++n) {
@@ -742,7 +796,7 @@ __global__ __launch_bounds__(4 * T) void k_persistent(StageArgs a, long long nst
         for (int l = 0; l < a.ns; ++l) {
             for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
                 const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-                D::template run<StageFn>(k, a, l, par, n == 0, tile, smem);
+                D::template run<StageFn>(k, a, l, par, n == 0, tile, smem, XW);
             }
             grid_barrier(a);
             if (l == 0 && single_instance && ld_i(&a.slots[par].done, true)) return;
@@ -776,22 +830,31 @@ __global__ void k_init(StageArgs a, int ninst) {
 hipError_t upload_tables_1d() { return hipSuccess; }   // tables are compile-time constants (oecdg_tables.h)
 
 static int tile_index(int tile) { return tile == 32 ? 0 : (tile == 64 ? 1 : (tile == 128 ? 2 : -1)); }
+// kernel table index: the tile, or 3 / 4 for tiles of 32 / 64 launched with the extra wave
+static int kernel_index(int tile, bool tailwave) {
+    const int ti = tile_index(tile);
+    return (ti >= 0 && tailwave && tail_threads(tile) > 0) ? ti + 3 : ti;
+}
 
 // kernel pointer tables [kidx][flux][tile]: kidx 0..3 = fixed k, 4 = mixed
-template <int WHICH, int KM, int FLUX, int T>
+// XW: launches with the extra wave (tail tiles) use kernels whose launch bounds
+// allow it; the others keep the bounds of four waves per tile of T.
+template <int WHICH, int KM, int FLUX, int T, bool XW>
 static void *kptr() {
-    if constexpr (WHICH == 0) return (void *)k_stage<KM, FLUX, T>;
-    else if constexpr (WHICH == 1) return (void *)k_stats<KM, FLUX, T>;
-    else if constexpr (WHICH == 2) return (void *)k_final<KM, FLUX, T>;
-    else return (void *)k_persistent<KM, FLUX, T>;
+    if constexpr (WHICH == 0) return (void *)k_stage<KM, FLUX, T, XW>;
+    else if constexpr (WHICH == 1) return (void *)k_stats<KM, FLUX, T, XW>;
+    else if constexpr (WHICH == 2) return (void *)k_final<KM, FLUX, T, XW>;
+    else return (void *)k_persistent<KM, FLUX, T, XW>;
 }
 
 template <int WHICH, int KM, int FLUX>
 static void *pick_t(int ti) {
     switch (ti) {
-    case 0: return kptr<WHICH, KM, FLUX, 32>();
-    case 1: return kptr<WHICH, KM, FLUX, 64>();
-    default: return kptr<WHICH, KM, FLUX, 128>();
+    case 0: return kptr<WHICH, KM, FLUX, 32, false>();
+    case 1: return kptr<WHICH, KM, FLUX, 64, false>();
+    case 3: return kptr<WHICH, KM, FLUX, 32, true>();
+    case 4: return kptr<WHICH, KM, FLUX, 64, true>();
+    default: return kptr<WHICH, KM, FLUX, 128, false>();
     }
 }
 
@@ -819,7 +882,7 @@ static void *pick(int k, bool mixed, int flux, int ti) {
 static hipError_t launch(void *fn, int grid, int tile, const StageArgs &a, hipStream_t s) {
     StageArgs copy = a;
     void *args[] = {&copy};
-    return hipLaunchKernel(fn, dim3(grid), dim3(nthreads(tile)), args, 0, s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(nthreads(tile) + (a.tailwave ? tail_threads(tile) : 0)), args, 0, s);
 }
 
 hipError_t launch_init_1d(const StageArgs &a, int ninst, hipStream_t s) {
@@ -828,43 +891,45 @@ hipError_t launch_init_1d(const StageArgs &a, int ninst, hipStream_t s) {
 }
 
 hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s) {
-    int ti = tile_index(tile);
+    int ti = kernel_index(tile, a.tailwave);
     if (ti < 0) return hipErrorInvalidValue;
     return launch(pick<1>(kmax, mixed, flux, ti), a.tend - a.tbeg, tile, a, s);
 }
 
 hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid, hipStream_t s) {
-    int ti = tile_index(tile);
+    int ti = kernel_index(tile, a.tailwave);
     if (ti < 0) return hipErrorInvalidValue;
     return launch(pick<0>(kmax, mixed, flux, ti), grid > 0 ? grid : a.tend - a.tbeg, tile, a, s);
 }
 
 hipError_t launch_final_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s) {
-    int ti = tile_index(tile);
+    int ti = kernel_index(tile, a.tailwave);
     if (ti < 0) return hipErrorInvalidValue;
     return launch(pick<2>(kmax, mixed, flux, ti), a.tend - a.tbeg, tile, a, s);
 }
 
-int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile) {
-    int ti = tile_index(tile);
+int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile, bool tailwave) {
+    int ti = kernel_index(tile, tailwave);
     if (ti < 0) return 0;
     int per_cu = 0, dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick<3>(kmax, mixed, flux, ti), nthreads(tile),
-                                                     0) != hipSuccess)
+    const int nthr = nthreads(tile) + (tailwave ? tail_threads(tile) : 0);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick<3>(kmax, mixed, flux, ti), nthr, 0) !=
+        hipSuccess)
         return 0;
     return per_cu * ncu;
 }
 
 hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid,
                                 long long nsteps, hipStream_t s) {
-    int ti = tile_index(tile);
+    int ti = kernel_index(tile, a.tailwave);
     if (ti < 0) return hipErrorInvalidValue;
     StageArgs copy = a;
     int single = a.ninst == 1;
     void *args[] = {&copy, &nsteps, &single};
-    return hipLaunchCooperativeKernel(pick<3>(kmax, mixed, flux, ti), dim3(grid), dim3(nthreads(tile)), args, 0, s);
+    const int nthr = nthreads(tile) + (a.tailwave ? tail_threads(tile) : 0);
+    return hipLaunchCooperativeKernel(pick<3>(kmax, mixed, flux, ti), dim3(grid), dim3(nthr), args, 0, s);
 }
 
 }  // namespace oecdg

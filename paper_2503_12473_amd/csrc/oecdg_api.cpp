@@ -34,6 +34,8 @@ struct oecdg_handle {
     int kmax = 0, flux = 0;  // flux: kernel flux id (OECDG_FLUX_*, or 3 = Euler with reflective walls)
     int rk = 3;              // RK method of every instance (rk_stage)
     bool mixed = false;
+    bool tailwave = false;   // some instance's last tile updates the extra dual cell (launches carry one more wave)
+    int ncol = 0;            // partial-statistics columns (the tiles, plus one per tail)
     int tile = 64;
     int mode = OECDG_MODE_AUTO;
     int graph_steps = 64;
@@ -138,14 +140,38 @@ int ensure_tables(oecdg_handle *h) {
 int build_tiles(oecdg_handle *h) {
     h->tiles_h.clear();
     h->groups.clear();
+    h->tailwave = false;
     const int T = h->tile;
+    // nd = np + 1 with np a multiple of T leaves dual cell np beyond np / T full
+    // tiles.  When that extra tile would take the workgroup count past the
+    // number of CUs, the last tile takes the cell instead, with one more wave
+    // in every workgroup of the launch (a workgroup of five waves cannot share
+    // a CU with another, so this is used only when all tiles then fit one per
+    // CU, and for single instances).  The cell's statistics keep a partial
+    // column of their own, so the results are those of the separate tile.
+    int ncu = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        ncu = 0;
+    long long plain = 0, merged = 0;
+    for (const Inst1D &I : h->inst_h) {
+        const bool t = I.nd == I.np + 1 && I.np % T == 0 && tail_threads(T) > 0;
+        plain += (I.nd + T - 1) / T;
+        merged += t ? I.np / T : (I.nd + T - 1) / T;
+    }
+    const bool use_tail = h->nbatch == 1 && plain > ncu && merged <= ncu && merged < plain;
+    int ncol = 0;
     for (int k = 0; k <= MAXK; ++k) {
         const int tbeg = (int)h->tiles_h.size();
         for (int b = 0; b < h->nbatch; ++b) {
             Inst1D &I = h->inst_h[b];
             if (I.k != k) continue;
             I.tile0 = (int)h->tiles_h.size();
-            I.ntiles = (I.nd + T - 1) / T;
+            I.tail = use_tail && I.nd == I.np + 1 && I.np % T == 0 && tail_threads(T) > 0;
+            if (I.tail) h->tailwave = true;
+            I.ntiles = I.tail ? I.np / T : (I.nd + T - 1) / T;
+            I.npart = I.ntiles + (I.tail ? 1 : 0);
+            ncol += I.npart;
             for (int t = 0; t < I.ntiles; ++t) h->tiles_h.push_back(Tile1D{b, t * T});
         }
         if ((int)h->tiles_h.size() > tbeg) h->groups.push_back({k, tbeg, (int)h->tiles_h.size()});
@@ -155,8 +181,9 @@ int build_tiles(oecdg_handle *h) {
     HIPCHK(h, hipMalloc(&h->tiles_d, sizeof(Tile1D) * h->tiles_h.size()));
     HIPCHK(h, hipMemcpy(h->tiles_d, h->tiles_h.data(), sizeof(Tile1D) * h->tiles_h.size(), hipMemcpyHostToDevice));
     HIPCHK(h, hipMemcpy(h->inst_d, h->inst_h.data(), sizeof(Inst1D) * h->nbatch, hipMemcpyHostToDevice));
-    HIPCHK(h, hipMalloc(&h->part, sizeof(double) * 2 * NSTAT * h->tiles_h.size()));
-    HIPCHK(h, hipMemset(h->part, 0, sizeof(double) * 2 * NSTAT * h->tiles_h.size()));
+    h->ncol = ncol;
+    HIPCHK(h, hipMalloc(&h->part, sizeof(double) * 2 * NSTAT * ncol));
+    HIPCHK(h, hipMemset(h->part, 0, sizeof(double) * 2 * NSTAT * ncol));
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec), h->gexec = nullptr;
     return OECDG_OK;
 }
@@ -166,12 +193,12 @@ StageArgs base_args(oecdg_handle *h) {
     memset(&a, 0, sizeof(a));
     a.inst = h->inst_d;
     a.tiles = h->tiles_d;
-    a.ntiles = (int)h->tiles_h.size();
+    a.ntiles = h->ncol;
     a.tbeg = 0;
-    a.tend = a.ntiles;
+    a.tend = (int)h->tiles_h.size();
     a.slots = h->slots;
     a.fin = h->fin;
-    const size_t ps = (size_t)NSTAT * h->tiles_h.size();
+    const size_t ps = (size_t)NSTAT * h->ncol;
     a.part[0] = h->part;
     a.part[1] = h->part + ps;
     a.BC[0] = h->B;
@@ -186,6 +213,7 @@ StageArgs base_args(oecdg_handle *h) {
     }
     a.rk = h->rk;
     a.ns = rk_stages(h->rk);
+    a.tailwave = h->tailwave;
     a.err = h->err;
     a.bar = h->bar;
     a.spin_limit = 1LL << 25;
@@ -315,7 +343,7 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
     if (mode == OECDG_MODE_PERSISTENT && ((h->nbatch > 1 && nsteps < 0) || h->groups.size() != 1))
         mode = OECDG_MODE_GRAPH;   // one cooperative launch serves one degree
     if (mode == OECDG_MODE_PERSISTENT) {
-        int maxg = persistent_max_grid_1d(h->kmax, h->flux, false, h->tile);
+        int maxg = persistent_max_grid_1d(h->kmax, h->flux, false, h->tile, h->tailwave);
         int grid = h->grid > 0 ? h->grid : (int)h->tiles_h.size();
         if (grid > maxg) grid = maxg;
         if (grid <= 0) return fail(h, OECDG_EHIP, "persistent kernel cannot be made co-resident");
@@ -375,7 +403,7 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
     const size_t S = (size_t)K1 * n, S2 = 2 * S;           // one mesh, both meshes
     const long long nseg = nsteps > 0 ? (nsteps + ckpt - 1) / ckpt : 0;
     const long long n0L = nseg > 0 ? (nseg - 1) * ckpt : 0;  // first step of the last segment
-    const size_t ntile = h->tiles_h.size(), psz = (size_t)NSTAT * ntile;
+    const size_t ntile = h->ncol, psz = (size_t)NSTAT * ntile;   // partial columns (periodic: one per tile)
     const int NB = adj_block_size(), nb = (n + NB - 1) / NB;
     const size_t bpsz = (size_t)2 * nb * adj_block_partials();
     const size_t segsz = (size_t)ckpt * 6 * S2 + (size_t)ckpt * 3 * psz;
@@ -529,7 +557,7 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
     q.inv_n = 1.0 / n;
     q.fntot = (long long)ntile;
     q.ftile0 = I.tile0;
-    q.fntiles = I.ntiles;
+    q.fntiles = I.npart;
     q.acc = acc;
     q.oe = I.oe && I.k > 0;
     static const double AL[3] = {0.0, 0.75, 1.0 / 3.0}, BL[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -771,11 +799,11 @@ int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out
     int rcs = stats_all(h, a);
     if (rcs != OECDG_OK) return rcs;
     const Inst1D &I = h->inst_h[0];
-    std::vector<double> rows((size_t)2 * I.ntiles);
-    const size_t ntot = h->tiles_h.size();
+    std::vector<double> rows((size_t)2 * I.npart);
+    const size_t ntot = h->ncol;
     for (int j = 0; j < 2; ++j)
-        HIPCHK(h, hipMemcpyAsync(rows.data() + (size_t)j * I.ntiles, a.part[1] + (ST_BETA + j) * ntot + I.tile0,
-                                 sizeof(double) * I.ntiles, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpyAsync(rows.data() + (size_t)j * I.npart, a.part[1] + (ST_BETA + j) * ntot + I.tile0,
+                                 sizeof(double) * I.npart, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     double beta = 0.0;
     for (double b : rows) beta = std::fmax(beta, b);

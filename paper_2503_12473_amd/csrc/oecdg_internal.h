@@ -26,7 +26,10 @@ struct Inst1D {
     int tile0, ntiles;       // tiles [tile0, tile0 + ntiles) of the global tile list
     long long offC, offD;    // element offsets in the concatenated state arrays
     double h, cfl, p0;       // cell width, C_CFL, flux parameter (speed or gamma)
-    int oe, pad;
+    int oe;
+    int tail;                // the last tile also updates dual cell np (outflow/walls, np a multiple of T)
+    int npart;               // partial-statistics columns [tile0, tile0 + npart): ntiles, plus one with a tail
+    int pad;
 };
 
 // A tile: primal cells [i0, i0 + T) and dual cells [i0, i0 + T) of instance inst.
@@ -45,6 +48,10 @@ struct Final {
     double t, tau;
     long long nexec;
 };
+
+// Threads of the extra wave that 1D launches carry when an instance's last
+// tile also updates its dual cell np (one wave; none for tiles of 128).
+__host__ __device__ constexpr int tail_threads(int T) { return T <= 64 ? 64 : 0; }
 
 // One stage of an RK method in the c/d form of eq:RKCDG,
 //   u_h^{n,l+1} = sum_{m<=l} c_{lm} u_sigma^{n,m} + tau d_{lm} L(u_sigma^{n,m}).
@@ -85,7 +92,7 @@ __host__ __device__ inline RKStage rk_stage(int rk, int l) {
 struct StageArgs {
     const Inst1D *inst;
     const Tile1D *tiles;
-    int ntiles;              // tiles in the whole batch (row length of the partials)
+    int ntiles;              // partial-statistics columns of the whole batch (row length of the partials)
     int tbeg, tend;          // tiles [tbeg, tend) handled by this launch (one degree group)
     Slot *slots;             // [ninst][2]
     Final *fin;              // [ninst]
@@ -96,6 +103,7 @@ struct StageArgs {
     double *AC, *AD;         // classical RK4: weighted sum of the damped inputs of stages 1 and 2
     int *err;                // [0] non-finite, [1] non-physical, [2] barrier timeout, [3] step+1 of an error
     int rk, ns;              // RK method (rk_stage) and its stages per step
+    int tailwave;            // launches carry one more wave, for the dual cell np of tail tiles
     int l;                   // stage of the step (0 .. ns-1)
     int par;                 // parity of the step index n
     int first;               // 1 for step 0 (its input is the initial data: no OE)
@@ -147,7 +155,7 @@ hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, bool mixed, i
 hipError_t launch_final_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s);
 hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid,
                                 long long nsteps, hipStream_t s);
-int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile);
+int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile, bool tailwave);
 
 }  // namespace oecdg
 

@@ -281,3 +281,37 @@ def test_adjoint_rejects_what_it_does_not_cover():
         with pytest.raises(_lib.OECDGError) as e:
             s.adjoint(two[0], two[1], 3, 0.01, two[0], two[1], 2)
         assert e.value.code == _lib.EUNSUPPORTED
+
+
+def test_execution_modes_bitwise_identical_with_tail_tile():
+    """N = 16384 outflow with tiles of 64: dual cell 16384 is carried by the
+    last tile's extra wave (256 workgroups instead of 257).  Eager, graph and
+    persistent launches give the same bits; the run matches the oracle."""
+    prob, uC, uD = inputs.euler_riemann(16384, 2, inputs.riemann_states(4))
+    outs = [gpu_run(prob, uC, uD, 0.15, mode=m, tile=64, nsteps=30)
+            for m in (_lib.MODE_EAGER, _lib.MODE_GRAPH, _lib.MODE_PERSISTENT)]
+    for o in outs[1:]:
+        assert o[2] == outs[0][2] and o[3] == outs[0][3]
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+    rC, rD, _, rn = ora.run1d(prob, uC, uD, nsteps=30, cfl=0.15)
+    assert outs[0][3] == rn == 30
+    assert _rel(outs[0][0], outs[0][1], rC, rD) <= RUN_TOL
+
+
+def test_tail_tile_gives_the_bits_of_the_separate_tile():
+    """N = 8192 outflow with tiles of 32: run alone, dual cell 8192 rides on the
+    last tile's extra wave (256 workgroups); in a batch it has a tile of its
+    own.  Its statistics keep their own column either way: identical bits."""
+    prob, uC, uD = inputs.euler_riemann(8192, 2, inputs.riemann_states(3))
+    other, oC, oD = inputs.euler_riemann(300, 1, inputs.riemann_states(1))
+    solo = gpu_run(prob, uC, uD, 0.15, tile=32, nsteps=40)
+    with OECDG([prob, other], 0.15) as s:
+        s.set_option(_lib.OPT_TILE, 32)
+        gC = torch.cat([to_device(uC), to_device(oC)])
+        gD = torch.cat([to_device(uD), to_device(oD)])
+        print("[tail] batch of 2, 40 steps", flush=True)
+        s.run(gC, gD, nsteps=40)
+        offC, offD = s.off_primal, s.off_dual
+        bC = gC.cpu().numpy()[offC[0]:offC[1]].reshape(uC.shape)
+        bD = gD.cpu().numpy()[offD[0]:offD[1]].reshape(uD.shape)
+    assert np.array_equal(solo[0], bC) and np.array_equal(solo[1], bD)

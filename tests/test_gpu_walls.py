@@ -139,3 +139,13 @@ def test_walls_with_other_rk_methods(rk, k, cfl):
     rC, rD, rt, rn = ora.run1d(prob, uC, uD, t_end=0.004, cfl=cfl, rk=rk)
     assert (ns, t) == (rn, rt)
     assert _rel(gC, gD, rC, rD) <= RUN_TOL
+
+
+def test_walls_with_tail_tile():
+    """Walls on N = 16384 (dual cell 16384, on the right wall, carried by the
+    last tile's extra wave), smooth data, 15 steps against the oracle."""
+    prob, uC, uD = inputs.euler_walls_smooth(16384, 2)
+    gC, gD, t, ns = gpu_run(prob, uC, uD, 0.3, nsteps=15)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, nsteps=15, cfl=0.3)
+    assert ns == rn == 15
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
