@@ -128,9 +128,11 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
 int oecdg_batch_offsets(oecdg_handle *h, int64_t *off_primal, int64_t *off_dual);
 
 /* Set an OECDG_OPT_* tuning option (execution mode, tile size, graph length,
- * persistent grid).  Options change speed only, never results (every mode and
- * tile gives the same bits).  EINVAL for an unknown key or a value out of
- * range; setting the tile rebuilds the tile list (and may return ENOMEM). */
+ * persistent grid).  The execution mode, graph length and persistent grid
+ * change speed only (the same bits); the tile also sets the order in which the
+ * per-tile statistics are summed, so results for different tiles agree to
+ * rounding.  EINVAL for an unknown key or a value out of range; setting the
+ * tile rebuilds the tile list (and may return ENOMEM). */
 int oecdg_set_option(oecdg_handle *h, int32_t key, int64_t value);
 
 /* tau_max of instance 0 for the state (uC, uD) (Sec. 2.1; cell averages of
