@@ -5,8 +5,9 @@
 Calls only the CPU oracle; stores every `stride`-th cell in each direction of
 both meshes (all components and modes) plus the final time and step count.
 
-    python tests/golden/make_euler2d_golden.py N STEPS STRIDE
-(the committed files: 128 500 4 and 1024 3 32; about an hour of serial CPU each)
+    python tests/golden/make_euler2d_golden.py N STEPS STRIDE [SPACE]
+(the committed files: 128 500 4 and 1024 3 32, about an hour of serial CPU
+each; with SPACE = 1 the total-degree space P^2: 128 200 4)
 """
 import os
 import sys
@@ -23,16 +24,17 @@ from paper_2503_12473_amd import inputs  # noqa: E402
 SEED, CFL = 0, 0.3
 
 
-def main(n: int, steps: int, stride: int):
-    prob, uC, uD, _ = inputs.euler2d_quadrants(n, 2, seed=SEED)
+def main(n: int, steps: int, stride: int, space: int = 0):
+    prob, uC, uD, _ = inputs.euler2d_quadrants(n, 2, seed=SEED, space=space)
     t0 = time.time()
     oC, oD, t, done = ora.run2d(prob, uC, uD, nsteps=steps, cfl=CFL)
     wall = time.time() - t0
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"euler2d_seed{SEED}_N{n}_{steps}steps.npz")
+    tag = "_p2" if space == 1 else ""
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"euler2d{tag}_seed{SEED}_N{n}_{steps}steps.npz")
     np.savez_compressed(out, uC=oC[..., ::stride, ::stride], uD=oD[..., ::stride, ::stride], t=t, steps=done,
                         stride=stride, n=n, cfl=CFL, seed=SEED, oracle_seconds=wall)
     print(out, done, t, wall)
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]), int(sys.argv[2]), int(sys.argv[3]))
+    main(int(sys.argv[1]), int(sys.argv[2]), int(sys.argv[3]), int(sys.argv[4]) if len(sys.argv) > 4 else 0)

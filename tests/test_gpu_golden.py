@@ -82,6 +82,25 @@ def test_euler2d_matches_golden(n, steps):
 
 
 @pytest.mark.timeout(300)
+def test_euler2d_p2_matches_golden():
+    """2D Euler quadrant workload in the total-degree space P^2, 128^2, CFL 0.3,
+    200 steps (shocks and contacts from the quadrant jumps, OE active)."""
+    g = _golden("euler2d_p2_seed0_N128_200steps.npz")
+    prob, uC, uD, _ = inputs.euler2d_quadrants(128, 2, seed=0, space=1)
+    print("[golden] euler2d P2 n=128 steps=200", flush=True)
+    with OECDG(prob, 0.3) as s:
+        a, b = to_device(uC), to_device(uD)
+        t, done = s.run(a, b, nsteps=200)
+        st = int(g["stride"])
+        oC = a.reshape(uC.shape)[..., ::st, ::st].cpu().numpy()
+        oD = b.reshape(uD.shape)[..., ::st, ::st].cpu().numpy()
+    assert done == int(g["steps"]) and t == pytest.approx(float(g["t"]), rel=1e-13)
+    e = _rel(oC, oD, g["uC"], g["uD"])
+    print(f"[golden] euler2d P2 rel err {e:.3e}", flush=True)
+    assert e <= TOL
+
+
+@pytest.mark.timeout(300)
 def test_advection2d_p2_matches_golden():
     """2D linear advection in the total-degree space P^2, 128^2, sin^2(pi (x + y)),
     CFL 0.33, to t = 1.1 (the setting of Table 2Dlinear_accuracy): the stored
