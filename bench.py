@@ -330,9 +330,16 @@ def cpu_baseline(target_seconds: float):
     t0 = time.perf_counter()
     _, _, _, done = ora.run1d(prob, uC, uD, nsteps=steps, cfl=CFL, t_end=T_END)
     wall = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": prob.dofs() * done / wall, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"first {done} of {FULL_STEPS} steps of the same workload, serial C oracle "
-                      f"(-O2, no FP contraction), {wall:.1f} s"}
+                      f"(-O2, no FP contraction), {wall:.1f} s",
+            "cpu": model, "host_cpus": os.cpu_count()}
 
 
 def main():
