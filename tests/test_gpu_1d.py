@@ -315,3 +315,23 @@ def test_tail_tile_gives_the_bits_of_the_separate_tile():
         bC = gC.cpu().numpy()[offC[0]:offC[1]].reshape(uC.shape)
         bD = gD.cpu().numpy()[offD[0]:offD[1]].reshape(uD.shape)
     assert np.array_equal(solo[0], bC) and np.array_equal(solo[1], bD)
+
+
+def test_single_stage_and_dt_with_tail_tile():
+    """N = 16384 outflow (tail tile): oecdg_dt reads the wave speeds of all
+    partial columns, oecdg_stage computes every SSP-RK3 stage, against the oracle."""
+    prob, uC, uD = inputs.euler_riemann(16384, 2, inputs.riemann_states(2))
+    rng = np.random.default_rng(11)
+    lC = uC * (1.0 + 0.01 * rng.standard_normal(uC.shape))
+    lD = uD * (1.0 + 0.01 * rng.standard_normal(uD.shape))
+    with OECDG(prob, 0.15) as s:
+        dt = s.dt(to_device(uC), to_device(uD))
+        assert dt == pytest.approx(0.15 * prob.h / ora.max_wavespeed1d(prob, uC, uD), rel=1e-14)
+        tau = 0.9 * dt
+        for l in range(3):
+            print(f"[tail stage] l={l}", flush=True)
+            ulC, ulD = (uC, uD) if l == 0 else (lC, lD)
+            o = s.stage(l, tau, dt, to_device(uC), to_device(uD), to_device(ulC), to_device(ulD))
+            rC, rD = ora.ssprk3_stage1d(prob, l, tau, dt, uC, uD, ulC, ulD)
+            gC, gD = o[0].cpu().numpy().reshape(rC.shape), o[1].cpu().numpy().reshape(rD.shape)
+            assert _rel(gC, gD, rC, rD) <= STAGE_TOL, l
