@@ -5,7 +5,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oecdg_oracle.c", "oecdg_oracle_2d.c"]
+SOURCES = ["oecdg_oracle.c", "oecdg_oracle_2d.c", "oecdg_oracle_nu.c"]
 LIB = os.path.join(HERE, "liboecdg_oracle.so")
 
 

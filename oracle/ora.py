@@ -63,6 +63,13 @@ def lib():
                                      _DP, _DP, _DP, _DP, _DP, _DP]
         L.ora1d_run.argtypes = [P1, C.c_double, C.c_int, C.c_int, C.c_double, C.c_long, C.c_double,
                                 _DP, _DP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
+        L.ora1n_rhs.argtypes = [P1, _DP, C.c_double, _DP, _DP, _DP, _DP]
+        L.ora1n_stats.argtypes = [P1, _DP, _DP, _DP, _DP, _DP]
+        L.ora1n_delta.argtypes = [P1, _DP, _DP, _DP, _DP, _DP]
+        L.ora1n_oe.argtypes = [P1, _DP, C.c_double, _DP, _DP]
+        L.ora1n_step.argtypes = [P1, _DP, C.c_int, C.c_int, C.c_double, C.c_double, _DP, _DP]
+        L.ora1n_run.argtypes = [P1, _DP, C.c_double, C.c_int, C.c_int, C.c_double, C.c_long, C.c_double,
+                                _DP, _DP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
         P2 = C.POINTER(Ora2D)
         L.ora2d_rhs.argtypes = [P2, C.c_double, _DP, _DP, _DP, _DP]
         L.ora2d_oe.argtypes = [P2, C.c_double, _DP, _DP]
@@ -169,6 +176,50 @@ def run1d(prob, uC, uD, t_end=float("inf"), nsteps=-1, cfl=0.3, dt_fixed=0.0, rk
     n = C.c_long(0)
     _check(lib().ora1d_run(C.byref(_p1(prob)), cfl, rk, int(oe), t_end, nsteps, dt_fixed, uC, uD,
                            C.byref(t), C.byref(n)), "run1d")
+    return uC, uD, t.value, n.value
+
+
+# ------------------------------------------------ 1D, non-uniform mesh ---
+# edges: the n+1 primal cell edges x_{i-1/2} (edges[0] = xlo, edges[n] = xhi);
+# periodic problems only; dual cell j is [x_{j-1}, x_j].
+
+def rhs1n(prob, edges, tau_max, uC, uD):
+    uC, uD = _arr(uC), _arr(uD)
+    LC, LD = np.zeros_like(uC), np.zeros_like(uD)
+    _check(lib().ora1n_rhs(C.byref(_p1(prob)), _arr(edges), tau_max, uC, uD, LC, LD), "rhs1n")
+    return LC, LD
+
+
+def stats1n(prob, edges, uC, uD):
+    avg, sig = np.zeros(6), np.zeros(6)
+    _check(lib().ora1n_stats(C.byref(_p1(prob)), _arr(edges), _arr(uC), _arr(uD), avg, sig), "stats1n")
+    return avg.reshape(2, 3)[:, :prob.nc], sig.reshape(2, 3)[:, :prob.nc]
+
+
+def delta1n(prob, edges, uC, uD):
+    dC, dD = np.zeros((prob.k + 1, prob.n)), np.zeros((prob.k + 1, prob.n))
+    _check(lib().ora1n_delta(C.byref(_p1(prob)), _arr(edges), _arr(uC), _arr(uD), dC, dD), "delta1n")
+    return dC, dD
+
+
+def oe1n(prob, edges, tau, uC, uD):
+    uC, uD = _arr(uC).copy(), _arr(uD).copy()
+    _check(lib().ora1n_oe(C.byref(_p1(prob)), _arr(edges), tau, uC, uD), "oe1n")
+    return uC, uD
+
+
+def step1n(prob, edges, tau, tau_max, uC, uD, rk=3, oe=True):
+    uC, uD = _arr(uC).copy(), _arr(uD).copy()
+    _check(lib().ora1n_step(C.byref(_p1(prob)), _arr(edges), rk, int(oe), tau, tau_max, uC, uD), "step1n")
+    return uC, uD
+
+
+def run1n(prob, edges, uC, uD, t_end=float("inf"), nsteps=-1, cfl=0.3, dt_fixed=0.0, rk=3, oe=True):
+    uC, uD = _arr(uC).copy(), _arr(uD).copy()
+    t = C.c_double(0.0)
+    n = C.c_long(0)
+    _check(lib().ora1n_run(C.byref(_p1(prob)), _arr(edges), cfl, rk, int(oe), t_end, nsteps, dt_fixed, uC, uD,
+                           C.byref(t), C.byref(n)), "run1n")
     return uC, uD, t.value, n.value
 
 

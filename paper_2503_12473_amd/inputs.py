@@ -194,6 +194,66 @@ def advection_square(n: int, k: int, lo=0.5 * math.pi, hi=1.5 * math.pi, xlo=0.0
     return prob, uC, uD
 
 
+def quasi_uniform_edges(n: int, xlo: float, xhi: float, ratio: float = 1.5, seed: int = 0):
+    """Edges x_{i-1/2}, i = 0..n, of a seeded non-uniform mesh of [xlo, xhi]:
+    widths proportional to 1 + r_i with r_i ~ U[0, ratio - 1], so that the
+    largest width is at most ratio times the smallest."""
+    rng = np.random.default_rng(seed)
+    w = 1.0 + rng.uniform(0.0, ratio - 1.0, size=n)
+    e = np.concatenate([[0.0], np.cumsum(w)])
+    e = xlo + (xhi - xlo) * (e / e[-1])
+    e[0], e[-1] = xlo, xhi
+    return e
+
+
+def smooth_graded_edges(n: int, xlo: float, xhi: float, amp: float = 0.3):
+    """Edges of a smoothly graded mesh: the image of a uniform mesh of [0, 1]
+    under s -> s + amp sin(2 pi s) / (2 pi), scaled to [xlo, xhi] (widths vary
+    between (1 - amp) and (1 + amp) times L/n; amp < 1)."""
+    s = np.arange(n + 1) / n
+    e = xlo + (xhi - xlo) * (s + amp * np.sin(2.0 * math.pi * s) / (2.0 * math.pi))
+    e[0], e[-1] = xlo, xhi
+    return e
+
+
+def project_1d_edges(func, nc: int, k: int, edges: np.ndarray, nq: int = 8):
+    """Project a periodic func (x -> [nc, *x.shape]) onto the primal cells
+    [edges[i], edges[i+1]] and the dual cells [x_{j-1}, x_j] between primal
+    centres (dual cell 0 starts at x_{n-1} minus the period).  Each cell is
+    split where the other mesh has an edge, so jumps there are integrated
+    exactly.  Returns arrays [nc, k+1, n]."""
+    edges = np.asarray(edges, dtype=np.float64)
+    n, L = edges.size - 1, edges[-1] - edges[0]
+    s, wq = _npleg.leggauss(nq)
+    norm = (2.0 * np.arange(k + 1) + 1.0) / 2.0
+    c = 0.5 * (edges[:-1] + edges[1:])
+    cm1 = np.concatenate([[c[-1] - L], c[:-1]])
+
+    def proj(lo, split, hi):
+        cen, wid = 0.5 * (lo + hi), hi - lo
+        out = np.zeros((nc, k + 1, n))
+        for a, b in ((lo, split), (split, hi)):
+            x = 0.5 * (a + b)[:, None] + 0.5 * (b - a)[:, None] * s[None, :]
+            xi = 2.0 * (x - cen[:, None]) / wid[:, None]
+            vals = np.asarray(func(x), dtype=np.float64).reshape(nc, *x.shape)
+            P = np.stack([_npleg.legval(xi, [0.0] * m + [1.0]) for m in range(k + 1)])   # [k+1, n, G]
+            jac = (0.5 * (b - a) / wid)[:, None] * wq[None, :] * 2.0                     # dx / (w/2) weights
+            out += np.einsum("qcg,mcg,cg->qmc", vals, P, jac)
+        return np.ascontiguousarray(out * norm[None, :, None])
+
+    return proj(edges[:-1], c, edges[1:]), proj(cm1, edges[:-1], c)
+
+
+def advection_sine_edges(edges: np.ndarray, k: int, a: float = 1.0, freq: int = 1):
+    """u_t + a u_x = 0, u0 = sin(2 pi freq (x - xlo)/L), on the periodic mesh given by its edges."""
+    edges = np.asarray(edges, dtype=np.float64)
+    xlo, xhi = float(edges[0]), float(edges[-1])
+    prob = Problem1D(k=k, nc=1, flux=FLUX_ADVECTION, bc=BC_PERIODIC, n=edges.size - 1, xlo=xlo, xhi=xhi, a=a)
+    L = xhi - xlo
+    uC, uD = project_1d_edges(lambda x: np.sin(freq * 2.0 * math.pi * (x - xlo) / L)[None], 1, k, edges)
+    return prob, uC, uD
+
+
 def riemann_states(seed: int):
     """(rho_L, p_L, rho_R, p_R), each ~ U[0.1, 1], drawn in that order; u = 0."""
     rng = np.random.default_rng(seed)
