@@ -167,6 +167,23 @@ int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max,
 int oecdg_run(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps,
               double dt_fixed, double *t_out, int64_t *steps_out);
 
+/* oecdg_run on a non-uniform periodic 1D mesh (Sec. 2.1: primal cells
+ * [x_{i-1/2}, x_{i+1/2}] of width h_i, dual cells [x_{i-1}, x_i] between
+ * neighbouring primal centres; h = max_i h_i in tau_max = cfl h / beta).  The
+ * damping of Sec. 2.2 takes h_{e,K} = the width of K and avg = the domain
+ * mean (width-weighted cell averages).  edges: host array of the nx+1 primal
+ * edges, edges[0] = xlo, edges[nx] = xhi, strictly increasing (EINVAL
+ * otherwise); copied at each call.  (uC, uD): device arrays [nc][k+1][nx]
+ * each, primal cell i and dual cell j = [x_{j-1}, x_j] (dual cell 0 starts
+ * at x_{nx-1} minus the period).  The handle must hold one periodic 1D
+ * instance with rk 0..3 (EUNSUPPORTED otherwise); the library allocates the
+ * mesh's buffers at the first call and keeps them with the handle (the
+ * handle's nx, k and flux fix their sizes).  Other arguments and errors as
+ * oecdg_run; the execution-mode and tile options do not apply.  Synchronises
+ * the stream. */
+int oecdg_run_nonuniform(oecdg_handle *h, const double *edges, double *uC, double *uD, double t_end,
+                         int64_t nsteps, double dt_fixed, double *t_out, int64_t *steps_out);
+
 /* Discrete adjoint of oecdg_run with a fixed step: the transpose of the
  * derivative of the fully discrete scheme of Sec. 2.2 (SSP-RK3 stages of
  * eq. RKCDG, each followed by F_tau).  Given u_sigma^0 = (uC0, uD0), nsteps

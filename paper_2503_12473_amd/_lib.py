@@ -18,7 +18,8 @@ OPT_MODE, OPT_TILE, OPT_GRAPH_STEPS, OPT_GRID = 1, 2, 3, 4
 
 # every symbol include/oecdg.h declares
 EXPORTS = ("oecdg_state_size", "oecdg_init", "oecdg_batch_offsets", "oecdg_set_option", "oecdg_dt",
-           "oecdg_stage", "oecdg_run", "oecdg_adjoint", "oecdg_destroy", "oecdg_strerror", "oecdg_last_error")
+           "oecdg_stage", "oecdg_run", "oecdg_run_nonuniform", "oecdg_adjoint", "oecdg_destroy", "oecdg_strerror",
+           "oecdg_last_error")
 
 
 class Desc(C.Structure):
@@ -57,6 +58,8 @@ def lib():
     L.oecdg_stage.argtypes = [H, C.c_int32, C.c_double, C.c_double, D, D, D, D, D, D]
     L.oecdg_run.argtypes = [H, D, D, C.c_double, C.c_int64, C.c_double, C.POINTER(C.c_double),
                             C.POINTER(C.c_int64)]
+    L.oecdg_run_nonuniform.argtypes = [H, D, D, D, C.c_double, C.c_int64, C.c_double, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int64)]
     L.oecdg_adjoint.argtypes = [H, D, D, C.c_int64, C.c_double, D, D, D, D, C.c_int32]
     L.oecdg_destroy.argtypes = [H]
     L.oecdg_destroy.restype = None

@@ -130,6 +130,19 @@ class OECDG:
         check(rc, self._h, "oecdg_run")
         return t.value, n.value
 
+    def run_nonuniform(self, edges, uC: torch.Tensor, uD: torch.Tensor, t_end: float = math.inf, nsteps: int = -1,
+                       dt_fixed: float = 0.0):
+        """oecdg_run on the periodic mesh with primal edges `edges` (host, nx+1
+        values); advances in place and returns (t, steps)."""
+        import numpy as np
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+        t = C.c_double()
+        n = C.c_int64()
+        rc = self._L.oecdg_run_nonuniform(self._h, C.c_void_p(e.ctypes.data), _ptr(uC, "uC"), _ptr(uD, "uD"),
+                                          float(t_end), int(nsteps), float(dt_fixed), C.byref(t), C.byref(n))
+        check(rc, self._h, "oecdg_run_nonuniform")
+        return t.value, n.value
+
     def adjoint(self, uC0, uD0, nsteps: int, dt: float, gC_T, gD_T, checkpoint_every: int = 20):
         gC0 = torch.empty_like(uC0)
         gD0 = torch.empty_like(uD0)

@@ -68,6 +68,7 @@ struct oecdg_handle {
     hipEvent_t adj_ev[5] = {};   // adjoint: segment buffer ready (2), buffer free (2), checkpoint written
 
     void *ext2d = nullptr;   // 2D state (oecdg_2d.hip)
+    void *extnu = nullptr;   // non-uniform 1D mesh state (oecdg_nu.hip)
     std::string last;
 };
 
@@ -627,6 +628,8 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
 hipStream_t oecdg::handle_stream(oecdg_handle *h) { return h->stream; }
 const oecdg_desc &oecdg::handle_desc(oecdg_handle *h) { return h->desc[0]; }
 void *&oecdg::handle_ext2d(oecdg_handle *h) { return h->ext2d; }
+void *&oecdg::handle_extnu(oecdg_handle *h) { return h->extnu; }
+int oecdg::handle_nbatch(oecdg_handle *h) { return h->nbatch; }
 int oecdg::handle_fail(oecdg_handle *h, int code, const char *msg) { return fail(h, code, msg); }
 
 // ============================================================== C ABI ===
@@ -865,6 +868,12 @@ int oecdg_run(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nst
     return run_1d(h, uC, uD, t_end, nsteps, dt_fixed, t_out, steps_out);
 }
 
+int oecdg_run_nonuniform(oecdg_handle *h, const double *edges, double *uC, double *uD, double t_end, int64_t nsteps,
+                         double dt_fixed, double *t_out, int64_t *steps_out) {
+    if (!h) return OECDG_EINVAL;
+    return oecdg::run_nonuniform(h, edges, uC, uD, t_end, nsteps, dt_fixed, t_out, steps_out);
+}
+
 int oecdg_adjoint(oecdg_handle *h, const double *uC0, const double *uD0, int64_t nsteps, double dt,
                   const double *gC_T, const double *gD_T, double *gC0, double *gD0, int32_t checkpoint_every) {
     if (!h || !uC0 || !uD0 || !gC_T || !gD_T || !gC0 || !gD0) return OECDG_EINVAL;
@@ -897,6 +906,7 @@ void oecdg_destroy(oecdg_handle *h) {
     if (h->ext2d) {
         oecdg::destroy_2d(h);
     }
+    if (h->extnu) oecdg::destroy_nu(h);
     delete h;
 }
 

@@ -177,6 +177,13 @@ int stage_2d(oecdg_handle *h, int stage, double dt, double tau_max, const double
 int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps, double dt_fixed, double *t_out,
            int64_t *steps_out);
 void destroy_2d(oecdg_handle *h);
+int handle_nbatch(oecdg_handle *h);
+void *&handle_extnu(oecdg_handle *h);
+
+// Non-uniform periodic 1D meshes (oecdg_nu.hip).
+int run_nonuniform(oecdg_handle *h, const double *edges, double *uC, double *uD, double t_end, int64_t nsteps,
+                   double dt_fixed, double *t_out, int64_t *steps_out);
+void destroy_nu(oecdg_handle *h);
 int adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int64_t nsteps, double dt, const double *gCT,
                const double *gDT, double *gC0, double *gD0, int ckpt);
 
