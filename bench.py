@@ -274,11 +274,48 @@ def _timed_1d(prob, uC, uD, cfl, steps, rk=3, warmup=200):
     return n, wall
 
 
+def _timed_nu(prob, edges, uC, uD, cfl, steps, warmup=50):
+    """Median of 5 oecdg_run_nonuniform calls of `steps` steps from the same initial data."""
+    import torch
+    from paper_2503_12473_amd.api import OECDG, to_device
+    stream = torch.cuda.current_stream()
+    ic = (to_device(uC), to_device(uD))
+    with OECDG(prob, cfl, stream=stream) as solver:
+        a, b = ic[0].clone(), ic[1].clone()
+        solver.run_nonuniform(edges, a, b, nsteps=warmup)
+        times = []
+        for _ in range(5):
+            a.copy_(ic[0])
+            b.copy_(ic[1])
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            _, n = solver.run_nonuniform(edges, a, b, nsteps=steps)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+    return n, sorted(times)[2]
+
+
+def _euler_wave(edges, k):
+    """Periodic Euler density wave rho = 1 + 0.2 sin(2 pi x), v = 0.5, p = 1 on [0, 1]."""
+    import numpy as np
+    from paper_2503_12473_amd import inputs
+    prob = inputs.Problem1D(k=k, nc=3, flux=inputs.FLUX_EULER, bc=inputs.BC_PERIODIC, n=len(edges) - 1,
+                            xlo=0.0, xhi=1.0)
+    f = lambda x: inputs.euler_conserved(1.0 + 0.2 * np.sin(2 * np.pi * x), 0.5 + 0 * x, 1.0 + 0 * x)
+    uC, uD = inputs.project_1d_edges(f, 3, k, edges)
+    return prob, uC, uD
+
+
 def widened_bench():
     """The forms beyond the SSP-RK3 plain path: classical RK4 (four stages per
     step) at P3 on the Riemann workload, reflective walls (the walled-Euler
-    kernels) on blast-wave data, and the 2D total-degree space P^2 on the 2D
-    Euler workload.  A DOF-update is one DOF advanced by one full step."""
+    kernels) on blast-wave data, the 2D total-degree space P^2 on the 2D
+    Euler workload, and a non-uniform periodic mesh (beside the uniform path on
+    the same data and a uniform mesh).  A DOF-update is one DOF advanced by one
+    full step."""
     import torch
     from paper_2503_12473_amd import inputs
     from paper_2503_12473_amd.api import OECDG, to_device
@@ -318,6 +355,18 @@ def widened_bench():
     out["euler2d_p2"] = {"workload": f"2D Euler {E2D_N}^2, total-degree P^2 (6 modes in the tensor layout, the P^2 "
                                      f"kernel instantiation), CFL {E2D_CFL}, {n} steps, seed {SEED}",
                          "dofs": pk_dofs, "dof_updates_per_s": pk_dofs * n / wall, "ms_per_step": 1e3 * wall / n}
+    import numpy as np
+    edges = inputs.quasi_uniform_edges(N_CELLS, 0.0, 1.0, 1.5, seed=SEED)
+    prob, uC, uD = _euler_wave(edges, 2)
+    n, wall = _timed_nu(prob, edges, uC, uD, 0.1, 1000)
+    out["nonuniform_p2"] = {"workload": f"1D Euler density wave, periodic, random mesh N={N_CELLS} (width ratio <= 1.5, "
+                                        f"seed {SEED}), P2, SSP-RK3, CFL 0.1, {n} steps",
+                            "dofs": prob.dofs(), "dof_updates_per_s": prob.dofs() * n / wall,
+                            "ms_per_step": 1e3 * wall / n, "us_per_stage": 1e6 * wall / (3 * n)}
+    uni = np.linspace(0.0, 1.0, N_CELLS + 1)
+    prob, uC, uD = _euler_wave(uni, 2)
+    n, wall = _timed_1d(prob, uC, uD, 0.1, 1000)
+    out["nonuniform_p2"]["uniform_path_same_data_ms_per_step"] = 1e3 * wall / n
     return out
 
 

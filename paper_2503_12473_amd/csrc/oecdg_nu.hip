@@ -10,9 +10,11 @@
 //   per stage:
 //     k_nu_stage             operator of eq:1D_H + the c/d combination of eq:RKCDG,
 //                            and per-block statistics of the undamped result
-//     k_nu_stats             avg (domain mean: width-weighted) and sigma per mesh
-//     k_nu_oe                delta_K^m (Sec. 2.2, h_{e,K} = the width of K) and
-//                            the exact damping F_tau into the stage's output
+//     k_nu_oe                every workgroup first reduces the block statistics
+//                            (the same fixed order everywhere: avg = domain mean,
+//                            width-weighted, and sigma per mesh), then delta_K^m
+//                            (Sec. 2.2, h_{e,K} = the width of K) and the exact
+//                            damping F_tau into the stage's output
 //   k_nu_advance             t += tau
 // No host synchronisation inside a step; the host polls the slot every few
 // steps when it marches to a final time.
@@ -49,7 +51,6 @@ struct NuArgs {
     double *oC, *oD;                     // damped stage output
     double cn, cw, dd;                   // c_{l0}, c_{ll}, d_{ll} (l = 0: cn = 0)
     double *part;                        // [mesh][3 NC][nblk]
-    double *stat;                        // [mesh][3] avg, [mesh][3] sigma
     double *wpart;                       // wave-speed partials [2 nblk]
     Slot *slot;
     long long *nexec;                    // steps executed
@@ -140,15 +141,18 @@ __global__ void __launch_bounds__(NB) k_nu_wave(NuArgs a) {
     if (threadIdx.x == 0) a.wpart[M * a.nblk + blockIdx.x] = v[0];
 }
 
-// One thread: beta, tau_max and tau of this step (a.slot->t is its start time).
-__global__ void k_nu_dt(NuArgs a) {
+// One wave: beta (max over the wave-speed partials), then tau_max and tau of
+// this step (a.slot->t is its start time), written by the last lane.
+__global__ void __launch_bounds__(WAVE) k_nu_dt(NuArgs a) {
     Slot *s = a.slot;
-    if (s->done) return;
+    if (s->done) return;                 // uniform over the wave
+    double b = 0.0;
+    for (int j = threadIdx.x; j < 2 * a.nblk; j += WAVE) b = fmax(b, a.wpart[j]);
+    b = wave_reduce(1, b);
+    if (threadIdx.x != WAVE - 1) return;
     if (s->t >= a.t_end) { s->done = 1; return; }
     double tau_max = a.dt_fixed;
     if (!(a.dt_fixed > 0.0)) {
-        double b = 0.0;
-        for (int j = 0; j < 2 * a.nblk; ++j) b = fmax(b, a.wpart[j]);
         if (!(b > 0.0) || !isfinite(b)) { a.err[2] = 1; s->done = 1; return; }
         tau_max = a.cfl * a.hmax / b;
     }
@@ -271,33 +275,38 @@ __global__ void __launch_bounds__(NB) k_nu_stage(NuArgs a) {
     }
 }
 
-// One workgroup: avg and sigma of both meshes from the block partials.
+// avg and sigma of both meshes ([mesh][q] in avg, sig) from the block
+// partials: strided accumulation, a DPP tree per wave, then the waves in
+// order; every workgroup gets the same bits.  All threads must take part.
 template <int NC>
-__global__ void __launch_bounds__(NB) k_nu_stats(NuArgs a) {
-    constexpr int NV = 3 * NC;
-    __shared__ double sh[NV * NB];
-    if (a.slot->done) return;
-    for (int M = 0; M < 2; ++M) {
-        double v[NV];
-        int kind[NV];
+__device__ inline void nu_statistics(const NuArgs &a, double *sh, double (&avg)[2][NC], double (&sig)[2][NC]) {
+    constexpr int NV = 3 * NC, NW = NB / WAVE;
+    const int t = threadIdx.x, lane = t % WAVE, wave = t / WAVE;
+#pragma unroll
+    for (int M = 0; M < 2; ++M)
 #pragma unroll
         for (int r = 0; r < NV; ++r) {
-            kind[r] = r % 3;
-            v[r] = stat_identity(kind[r]);
-            for (int b = threadIdx.x; b < a.nblk; b += NB)
-                v[r] = stat_op(kind[r], v[r], a.part[((long long)M * NV + r) * a.nblk + b]);
+            const int kd = r % 3;
+            double v = stat_identity(kd);
+            for (int b = t; b < a.nblk; b += NB) v = stat_op(kd, v, a.part[((long long)M * NV + r) * a.nblk + b]);
+            v = wave_reduce(kd, v);
+            if (lane == WAVE - 1) sh[(M * NV + r) * NW + wave] = v;
         }
-        block_reduce<NV>(v, kind, sh);
-        if (threadIdx.x == 0) {
+    __syncthreads();
 #pragma unroll
-            for (int q = 0; q < NC; ++q) {
-                const double avg = v[3 * q] / a.L;
-                a.stat[M * 6 + q] = avg;
-                a.stat[M * 6 + 3 + q] = fmax(v[3 * q + 1] - avg, avg - v[3 * q + 2]);
+    for (int M = 0; M < 2; ++M)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            double v[3];
+#pragma unroll
+            for (int kd = 0; kd < 3; ++kd) {
+                const int r = 3 * q + kd;
+                v[kd] = sh[(M * NV + r) * NW];
+                for (int w = 1; w < NW; ++w) v[kd] = stat_op(kd, v[kd], sh[(M * NV + r) * NW + w]);
             }
+            avg[M][q] = v[0] / a.L;
+            sig[M][q] = fmax(v[1] - avg[M][q], avg[M][q] - v[2]);
         }
-        __syncthreads();
-    }
 }
 
 // delta_K^m from the undamped stage output, then F_tau into the stage output.
@@ -305,8 +314,12 @@ template <int K, int FLUX>
 __global__ void __launch_bounds__(NB) k_nu_oe(NuArgs a) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1;
+    __shared__ double sh[2 * 3 * NC * (NB / WAVE)];
     const int M = blockIdx.y, i = blockIdx.x * NB + threadIdx.x;
-    if (i >= a.n || a.slot->done) return;
+    if (a.slot->done) return;            // uniform over the grid
+    double avg[2][NC], sigall[2][NC];
+    if (a.oe && K > 0) nu_statistics<NC>(a, sh, avg, sigall);
+    if (i >= a.n) return;
     const double *own = M == 0 ? a.tC : a.tD, *oth = M == 0 ? a.tD : a.tC;
     double *dst = M == 0 ? a.oC : a.oD;
     double u[NC][K1];
@@ -325,7 +338,7 @@ __global__ void __launch_bounds__(NB) k_nu_oe(NuArgs a) {
         }
         double ub[NC], sig[NC];
 #pragma unroll
-        for (int q = 0; q < NC; ++q) ub[q] = u[q][0], sig[q] = a.stat[M * 6 + 3 + q];
+        for (int q = 0; q < NC; ++q) ub[q] = u[q][0], sig[q] = sigall[M][q];
         const double beta = F::speed(ub, a.p0);
         double S = 0.0, fact = 1.0, wp = 1.0 / w;         // w^{m-1}
 #pragma unroll
@@ -373,7 +386,7 @@ struct NuState {
     int n = 0, nc = 0, k = 0;
     double *geo = nullptr;          // edges [n+1] | cC | wC | cD | wD
     double *buf = nullptr;          // S1 (C|D) | S2 (C|D) | T (C|D)
-    double *part = nullptr, *stat = nullptr, *wpart = nullptr;
+    double *part = nullptr, *wpart = nullptr;
     Slot *slot = nullptr;
     long long *nexec = nullptr;
     int *err = nullptr;
@@ -387,7 +400,6 @@ void free_state(NuState *s) {
     (void)hipFree(s->geo);
     (void)hipFree(s->buf);
     (void)hipFree(s->part);
-    (void)hipFree(s->stat);
     (void)hipFree(s->wpart);
     (void)hipFree(s->slot);
     (void)hipFree(s->nexec);
@@ -430,10 +442,6 @@ void launch_wave(const NuArgs &a, dim3 grid, hipStream_t st) {
     else hipLaunchKernelGGL(k_nu_wave<2>, grid, dim3(NB), 0, st, a);
 }
 
-void launch_stats(const NuArgs &a, hipStream_t st) {
-    if (a.flux == OECDG_FLUX_EULER) hipLaunchKernelGGL(k_nu_stats<3>, dim3(1), dim3(NB), 0, st, a);
-    else hipLaunchKernelGGL(k_nu_stats<1>, dim3(1), dim3(NB), 0, st, a);
-}
 
 }  // namespace
 
@@ -478,7 +486,6 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
         if (hipMalloc(&s->geo, sizeof(double) * (5 * (size_t)n + 1)) != hipSuccess ||
             hipMalloc(&s->buf, sizeof(double) * 6 * S1) != hipSuccess ||
             hipMalloc(&s->part, sizeof(double) * 2 * 9 * (size_t)nblk) != hipSuccess ||
-            hipMalloc(&s->stat, sizeof(double) * 12) != hipSuccess ||
             hipMalloc(&s->wpart, sizeof(double) * 2 * (size_t)nblk) != hipSuccess ||
             hipMalloc(&s->slot, sizeof(Slot)) != hipSuccess || hipMalloc(&s->err, sizeof(int) * 4) != hipSuccess ||
             hipMalloc(&s->nexec, sizeof(long long)) != hipSuccess ||
@@ -510,7 +517,7 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
     a.L = L, a.hmax = hmax, a.cfl = d.cfl, a.t_end = t_end, a.dt_fixed = dt_fixed;
     a.p0 = d.flux_param[0];                      // advection speed or gamma
     a.edges = s->geo, a.cC = s->geo + n + 1, a.wC = a.cC + n, a.cD = a.wC + n, a.wD = a.cD + n;
-    a.part = s->part, a.stat = s->stat, a.wpart = s->wpart, a.slot = s->slot, a.nexec = s->nexec, a.err = s->err, a.nblk = nblk;
+    a.part = s->part, a.wpart = s->wpart, a.slot = s->slot, a.nexec = s->nexec, a.err = s->err, a.nblk = nblk;
     double *S1C = s->buf, *S1D = S1C + S1, *S2C = S1D + S1, *S2D = S2C + S1, *TC = S2D + S1, *TD = TC + S1;
     a.tC = TC, a.tD = TD;
     const dim3 grid(nblk, 2);
@@ -524,7 +531,7 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
         }
         a.unC = uC, a.unD = uD;
         launch_wave(a, grid, st);
-        hipLaunchKernelGGL(k_nu_dt, dim3(1), dim3(1), 0, st, a);
+        hipLaunchKernelGGL(k_nu_dt, dim3(1), dim3(WAVE), 0, st, a);
         for (int l = 0; l < ns; ++l) {
             const RKStage r = rk_stage(rk, l);
             a.cn = l == 0 ? 0.0 : r.cn, a.cw = r.cw, a.dd = r.d;
@@ -534,7 +541,6 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
             a.oC = lastst ? uC : (l == 0 ? S1C : S2C);
             a.oD = lastst ? uD : (l == 0 ? S1D : S2D);
             launch_kind(0, a, grid, st);
-            launch_stats(a, st);
             launch_kind(1, a, grid, st);
         }
         hipLaunchKernelGGL(k_nu_advance, dim3(1), dim3(1), 0, st, a);
