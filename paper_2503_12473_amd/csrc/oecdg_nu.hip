@@ -282,16 +282,24 @@ template <int NC>
 __device__ inline void nu_statistics(const NuArgs &a, double *sh, double (&avg)[2][NC], double (&sig)[2][NC]) {
     constexpr int NV = 3 * NC, NW = NB / WAVE;
     const int t = threadIdx.x, lane = t % WAVE, wave = t / WAVE;
+    // first partial of every row per thread: unconditional loads of valid
+    // elements and a select, so that all 2 NV loads are in flight together
+    double v[2 * NV];
+    const int b0 = min(t, a.nblk - 1);
 #pragma unroll
-    for (int M = 0; M < 2; ++M)
+    for (int j = 0; j < 2 * NV; ++j) {
+        const double x = a.part[(long long)j * a.nblk + b0];
+        v[j] = t < a.nblk ? x : stat_identity(j % 3);
+    }
+    for (int b = t + NB; b < a.nblk; b += NB) {     // meshes of more than NB * NB cells
 #pragma unroll
-        for (int r = 0; r < NV; ++r) {
-            const int kd = r % 3;
-            double v = stat_identity(kd);
-            for (int b = t; b < a.nblk; b += NB) v = stat_op(kd, v, a.part[((long long)M * NV + r) * a.nblk + b]);
-            v = wave_reduce(kd, v);
-            if (lane == WAVE - 1) sh[(M * NV + r) * NW + wave] = v;
-        }
+        for (int j = 0; j < 2 * NV; ++j) v[j] = stat_op(j % 3, v[j], a.part[(long long)j * a.nblk + b]);
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * NV; ++j) {
+        v[j] = wave_reduce(j % 3, v[j]);
+        if (lane == WAVE - 1) sh[j * NW + wave] = v[j];
+    }
     __syncthreads();
 #pragma unroll
     for (int M = 0; M < 2; ++M)
