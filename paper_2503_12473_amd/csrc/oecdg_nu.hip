@@ -6,7 +6,9 @@
 // its own geometry (centre, width, and the point where the other mesh has its
 // edge); the Legendre values at the mapped quadrature nodes are evaluated at run
 // time.  One thread per cell of either mesh (a 2D grid, y = mesh); per step:
-//   k_nu_wave + k_nu_dt      beta over the cell averages -> tau (device-side slot)
+//   k_nu_dt                  beta over the cell averages -> tau (device-side slot);
+//                            the wave-speed partials come from k_nu_wave before the
+//                            first step and from the last stage's k_nu_oe after it
 //   per stage:
 //     k_nu_stage             operator of eq:1D_H + the c/d combination of eq:RKCDG,
 //                            and per-block statistics of the undamped result
@@ -54,6 +56,7 @@ struct NuArgs {
     double *wpart;                       // wave-speed partials [2 nblk]
     Slot *slot;
     long long *nexec;                    // steps executed
+    int wave_out;                        // last stage: also write the wave-speed partials of its output
     int *err;                            // [0] non-finite, [1] non-physical, [2] bad wave speed
     int nblk;
 };
@@ -327,67 +330,86 @@ __global__ void __launch_bounds__(NB) k_nu_oe(NuArgs a) {
     if (a.slot->done) return;            // uniform over the grid
     double avg[2][NC], sigall[2][NC];
     if (a.oe && K > 0) nu_statistics<NC>(a, sh, avg, sigall);
-    if (i >= a.n) return;
-    const double *own = M == 0 ? a.tC : a.tD, *oth = M == 0 ? a.tD : a.tC;
-    double *dst = M == 0 ? a.oC : a.oD;
-    double u[NC][K1];
-    load_cell<K, NC>(own, a.n, i, u);
-    if (a.oe && K > 0) {
-        const double tau = a.slot->tau;
-        const double c = M == 0 ? a.cC[i] : a.cD[i], w = M == 0 ? a.wC[i] : a.wD[i];
-        double lo, split, hi;
-        pieces(a, M, i, lo, split, hi);
-        double nb[2][NC][K1], cnb[2], wnb[2];
+    double bw = 0.0;                     // wave speed at the damped cell average (last stage)
+    if (i < a.n) {
+        const double *own = M == 0 ? a.tC : a.tD, *oth = M == 0 ? a.tD : a.tC;
+        double *dst = M == 0 ? a.oC : a.oD;
+        double u[NC][K1];
+        load_cell<K, NC>(own, a.n, i, u);
+        if (a.oe && K > 0) {
+            const double tau = a.slot->tau;
+            const double c = M == 0 ? a.cC[i] : a.cD[i], w = M == 0 ? a.wC[i] : a.wD[i];
+            double lo, split, hi;
+            pieces(a, M, i, lo, split, hi);
+            double nb[2][NC][K1], cnb[2], wnb[2];
 #pragma unroll
-        for (int p = 0; p < 2; ++p) {
-            int j;
-            neighbour(a, M, i, p, j, cnb[p], wnb[p]);
-            load_cell<K, NC>(oth, a.n, j, nb[p]);
+            for (int p = 0; p < 2; ++p) {
+                int j;
+                neighbour(a, M, i, p, j, cnb[p], wnb[p]);
+                load_cell<K, NC>(oth, a.n, j, nb[p]);
+            }
+            double ub[NC], sig[NC];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) ub[q] = u[q][0], sig[q] = sigall[M][q];
+            const double beta = F::speed(ub, a.p0);
+            double S = 0.0, fact = 1.0, wp = 1.0 / w;         // w^{m-1}
+#pragma unroll
+            for (int m = 0; m <= K; ++m) {
+                if (m > 1) fact *= m;
+                const double so = pow(2.0 / w, m), sl = pow(2.0 / wnb[0], m), sr = pow(2.0 / wnb[1], m);
+                double oL[NC], oR[NC], vL[NC], vR[NC];
+                eval<K, NC>(u, m, 2.0 * (lo - c) / w, so, oL);
+                eval<K, NC>(u, m, 2.0 * (hi - c) / w, so, oR);
+                eval<K, NC>(nb[0], m, 2.0 * (lo - cnb[0]) / wnb[0], sl, vL);
+                eval<K, NC>(nb[1], m, 2.0 * (hi - cnb[1]) / wnb[1], sr, vR);
+                const double cm = (2.0 * m + 1.0) * wp / ((2.0 * K - 1.0) * fact);
+                double dm = 0.0;
+#pragma unroll
+                for (int q = 0; q < NC; ++q) {
+                    if (sig[q] == 0.0) continue;
+                    const double val = cm * beta * (fabs(oL[q] - vL[q]) + fabs(oR[q] - vR[q])) / sig[q];
+                    dm = fmax(dm, val);
+                }
+                S += dm;
+                wp *= w;
+                if (m >= 1) {
+                    const double fac = exp(-tau * S);
+#pragma unroll
+                    for (int q = 0; q < NC; ++q) u[q][m] *= fac;
+                }
+            }
         }
-        double ub[NC], sig[NC];
+        bool finite = true;
 #pragma unroll
-        for (int q = 0; q < NC; ++q) ub[q] = u[q][0], sig[q] = sigall[M][q];
-        const double beta = F::speed(ub, a.p0);
-        double S = 0.0, fact = 1.0, wp = 1.0 / w;         // w^{m-1}
+        for (int q = 0; q < NC; ++q)
 #pragma unroll
-        for (int m = 0; m <= K; ++m) {
-            if (m > 1) fact *= m;
-            const double so = pow(2.0 / w, m), sl = pow(2.0 / wnb[0], m), sr = pow(2.0 / wnb[1], m);
-            double oL[NC], oR[NC], vL[NC], vR[NC];
-            eval<K, NC>(u, m, 2.0 * (lo - c) / w, so, oL);
-            eval<K, NC>(u, m, 2.0 * (hi - c) / w, so, oR);
-            eval<K, NC>(nb[0], m, 2.0 * (lo - cnb[0]) / wnb[0], sl, vL);
-            eval<K, NC>(nb[1], m, 2.0 * (hi - cnb[1]) / wnb[1], sr, vR);
-            const double cm = (2.0 * m + 1.0) * wp / ((2.0 * K - 1.0) * fact);
-            double dm = 0.0;
-#pragma unroll
-            for (int q = 0; q < NC; ++q) {
-                if (sig[q] == 0.0) continue;
-                const double val = cm * beta * (fabs(oL[q] - vL[q]) + fabs(oR[q] - vR[q])) / sig[q];
-                dm = fmax(dm, val);
+            for (int m = 0; m < K1; ++m) {
+                finite = finite && isfinite(u[q][m]);
+                dst[(long long)(q * K1 + m) * a.n + i] = u[q][m];
             }
-            S += dm;
-            wp *= w;
-            if (m >= 1) {
-                const double fac = exp(-tau * S);
+        double ub[NC];
 #pragma unroll
-                for (int q = 0; q < NC; ++q) u[q][m] *= fac;
-            }
+        for (int q = 0; q < NC; ++q) ub[q] = u[q][0];
+        if (!finite) __hip_atomic_store(&a.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else if (!F::physical(ub, a.p0)) __hip_atomic_store(&a.err[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a.wave_out) {
+            bw = F::speed(ub, a.p0);
+            if (!(bw >= 0.0)) bw = INFINITY;             // NaN: reported by k_nu_dt
         }
     }
-    bool finite = true;
-#pragma unroll
-    for (int q = 0; q < NC; ++q)
-#pragma unroll
-        for (int m = 0; m < K1; ++m) {
-            finite = finite && isfinite(u[q][m]);
-            dst[(long long)(q * K1 + m) * a.n + i] = u[q][m];
+    // the next step's beta: per-workgroup maxima of the damped averages (every
+    // thread of the workgroup reaches this point)
+    if (a.wave_out) {
+        __shared__ double shw[NB / WAVE];
+        bw = wave_reduce(1, bw);
+        if (threadIdx.x % WAVE == WAVE - 1) shw[threadIdx.x / WAVE] = bw;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double b = shw[0];
+            for (int w = 1; w < NB / WAVE; ++w) b = fmax(b, shw[w]);
+            a.wpart[M * a.nblk + blockIdx.x] = b;
         }
-    double ub[NC];
-#pragma unroll
-    for (int q = 0; q < NC; ++q) ub[q] = u[q][0];
-    if (!finite) __hip_atomic_store(&a.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else if (!F::physical(ub, a.p0)) __hip_atomic_store(&a.err[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 struct NuState {
@@ -538,7 +560,7 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
             if (s->slot_h->done) break;
         }
         a.unC = uC, a.unD = uD;
-        launch_wave(a, grid, st);
+        if (step == 0) launch_wave(a, grid, st);     // later steps: written by the last stage's k_nu_oe
         hipLaunchKernelGGL(k_nu_dt, dim3(1), dim3(WAVE), 0, st, a);
         for (int l = 0; l < ns; ++l) {
             const RKStage r = rk_stage(rk, l);
@@ -546,6 +568,7 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
             a.ulC = l == 0 ? uC : (l == 1 ? S1C : S2C);
             a.ulD = l == 0 ? uD : (l == 1 ? S1D : S2D);
             const bool lastst = l == ns - 1;
+            a.wave_out = lastst;
             a.oC = lastst ? uC : (l == 0 ? S1C : S2C);
             a.oD = lastst ? uD : (l == 0 ? S1D : S2D);
             launch_kind(0, a, grid, st);
