@@ -156,3 +156,15 @@ def test_errors():
         a, b = s.empty_state()
         with pytest.raises(_lib.OECDGError, match="unsupported"):
             s.run_nonuniform(edges, a, b, nsteps=1)
+
+
+def test_bench_workload_full_size():
+    """The measured non-uniform workload itself: periodic Euler density wave on
+    the seed-0 random mesh of N = 16384 cells (width ratio <= 1.5), P2, SSP-RK3,
+    CFL 0.1, 10 steps through the same entry point."""
+    edges = inputs.quasi_uniform_edges(16384, 0.0, 1.0, 1.5, seed=0)
+    prob, uC, uD = _euler(edges, 2)
+    gC, gD, t, n = _gpu(prob, edges, uC, uD, 0.1, nsteps=10)
+    rC, rD, rt, rn = ora.run1n(prob, edges, uC, uD, nsteps=10, cfl=0.1)
+    assert n == rn == 10 and abs(t - rt) <= 1e-13 * rt
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
