@@ -168,3 +168,14 @@ def test_bench_workload_full_size():
     rC, rD, rt, rn = ora.run1n(prob, edges, uC, uD, nsteps=10, cfl=0.1)
     assert n == rn == 10 and abs(t - rt) <= 1e-13 * rt
     assert _rel(gC, gD, rC, rD) <= RUN_TOL
+
+
+def test_more_workgroups_than_threads():
+    """N = 70000: 274 workgroups per mesh, more than the 256 threads that reduce
+    their statistics, so the strided part of that reduction runs too."""
+    edges = _mesh("random", 70000, seed=13)
+    prob, uC, uD = inputs.advection_sine_edges(edges, 1, freq=3)
+    gC, gD, t, n = _gpu(prob, edges, uC, uD, 0.2, nsteps=5)
+    rC, rD, rt, rn = ora.run1n(prob, edges, uC, uD, nsteps=5, cfl=0.2)
+    assert (n, t) == (rn, rt)
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
