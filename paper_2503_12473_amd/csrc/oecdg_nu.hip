@@ -17,7 +17,7 @@
 //                            width-weighted, and sigma per mesh), then delta_K^m
 //                            (Sec. 2.2, h_{e,K} = the width of K) and the exact
 //                            damping F_tau into the stage's output
-//   k_nu_advance             t += tau
+//   (the step ends in the next step's k_nu_dt; k_nu_advance ends the last one)
 // No host synchronisation inside a step; the host polls the slot every few
 // steps when it marches to a final time.
 #include "oecdg_device.h"
@@ -57,6 +57,7 @@ struct NuArgs {
     Slot *slot;
     long long *nexec;                    // steps executed
     int wave_out;                        // last stage: also write the wave-speed partials of its output
+    int pending;                         // k_nu_dt first ends the previous step
     int *err;                            // [0] non-finite, [1] non-physical, [2] bad wave speed
     int nblk;
 };
@@ -144,35 +145,54 @@ __global__ void __launch_bounds__(NB) k_nu_wave(NuArgs a) {
     if (threadIdx.x == 0) a.wpart[M * a.nblk + blockIdx.x] = v[0];
 }
 
-// One wave: beta (max over the wave-speed partials), then tau_max and tau of
-// this step (a.slot->t is its start time), written by the last lane.
+// One wave: first the previous step's end (t += tau, the step count, the stop
+// at t_end or on an error) when a.pending, then beta (max over the wave-speed
+// partials) and tau_max and tau of this step.  Every lane reads the slot and
+// computes the same values; the last lane writes them.
 __global__ void __launch_bounds__(WAVE) k_nu_dt(NuArgs a) {
     Slot *s = a.slot;
-    if (s->done) return;                 // uniform over the wave
+    Slot v = *s;
+    long long inc = 0;
+    if (a.pending && !v.done) {
+        inc = 1;
+        v.t = v.last ? a.t_end : v.t + v.tau;
+        if (v.last) v.done = 1;
+        v.done |= 2 * (a.err[0] | a.err[1] | a.err[2]);
+    }
     double b = 0.0;
     for (int j = threadIdx.x; j < 2 * a.nblk; j += WAVE) b = fmax(b, a.wpart[j]);
     b = wave_reduce(1, b);
     if (threadIdx.x != WAVE - 1) return;
-    if (s->t >= a.t_end) { s->done = 1; return; }
-    double tau_max = a.dt_fixed;
-    if (!(a.dt_fixed > 0.0)) {
-        if (!(b > 0.0) || !isfinite(b)) { a.err[2] = 1; s->done = 1; return; }
-        tau_max = a.cfl * a.hmax / b;
+    *a.nexec += inc;
+    if (!v.done && v.t >= a.t_end) v.done = 1;
+    if (!v.done) {
+        double tau_max = a.dt_fixed;
+        if (!(a.dt_fixed > 0.0)) {
+            if (!(b > 0.0) || !isfinite(b)) {
+                a.err[2] = 1;
+                v.done = 1;
+            }
+            tau_max = a.cfl * a.hmax / b;
+        }
+        if (!v.done) {
+            double tau = tau_max;
+            v.last = 0;
+            if (v.t + tau >= a.t_end) { tau = a.t_end - v.t; v.last = 1; }
+            v.tau = tau;
+            v.tau_max = tau_max;
+        }
     }
-    double tau = tau_max;
-    s->last = 0;
-    if (s->t + tau >= a.t_end) { tau = a.t_end - s->t; s->last = 1; }
-    s->tau = tau;
-    s->tau_max = tau_max;
+    *s = v;
 }
 
+// The end of the last step of a call (the others end in the next k_nu_dt).
 __global__ void k_nu_advance(NuArgs a) {
     Slot *s = a.slot;
     if (s->done) return;
     *a.nexec += 1;
     s->t = s->last ? a.t_end : s->t + s->tau;
     if (s->last) s->done = 1;
-    s->done |= 2 * (a.err[0] | a.err[1] | a.err[2]);  // an error stops the march
+    s->done |= 2 * (a.err[0] | a.err[1] | a.err[2]);
 }
 
 // Operator of eq:1D_H on cell i of mesh M, combined with u^n, and the block's
@@ -561,6 +581,7 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
         }
         a.unC = uC, a.unD = uD;
         if (step == 0) launch_wave(a, grid, st);     // later steps: written by the last stage's k_nu_oe
+        a.pending = step > 0;
         hipLaunchKernelGGL(k_nu_dt, dim3(1), dim3(WAVE), 0, st, a);
         for (int l = 0; l < ns; ++l) {
             const RKStage r = rk_stage(rk, l);
@@ -574,9 +595,10 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
             launch_kind(0, a, grid, st);
             launch_kind(1, a, grid, st);
         }
-        hipLaunchKernelGGL(k_nu_advance, dim3(1), dim3(1), 0, st, a);
         NUCHK(h, hipGetLastError());
     }
+    if (step > 0) hipLaunchKernelGGL(k_nu_advance, dim3(1), dim3(1), 0, st, a);
+    NUCHK(h, hipGetLastError());
     NUCHK(h, hipMemcpyAsync(s->slot_h, s->slot, sizeof(Slot), hipMemcpyDeviceToHost, st));
     NUCHK(h, hipMemcpyAsync(s->err_h, s->err, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
     NUCHK(h, hipMemcpyAsync(s->nexec_h, s->nexec, sizeof(long long), hipMemcpyDeviceToHost, st));
