@@ -30,7 +30,7 @@
 namespace oecdg {
 namespace {
 
-constexpr int NB = 256;                 // threads per workgroup (4 waves)
+constexpr int NB = 128;                 // threads per workgroup (2 waves: 256 workgroups at N = 16384)
 constexpr int POLL = 16;                // steps between host checks of the slot when marching to t_end
 
 // Run-time Legendre values: d-th derivative of P_m at x, m <= 3.
