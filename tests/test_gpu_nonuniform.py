@@ -76,13 +76,14 @@ def test_burgers_through_shock(kind, rk, k, cfl):
     assert _rel(gC, gD, rC, rD) <= RUN_TOL
 
 
-@pytest.mark.parametrize("oe", [True, False])
-def test_euler_smooth(oe):
-    """Smooth periodic Euler density wave, N = 513, k = 2, 40 steps."""
+@pytest.mark.parametrize("k,oe", [(2, True), (2, False), (1, True), (3, True)])
+def test_euler_smooth(k, oe):
+    """Smooth periodic Euler density wave, N = 513, 40 steps."""
     edges = _mesh("random", 513, 0.0, 1.0, seed=7)
-    prob, uC, uD = _euler(edges, 2)
-    gC, gD, t, n = _gpu(prob, edges, uC, uD, 0.1, oe=oe, nsteps=40)
-    rC, rD, rt, rn = ora.run1n(prob, edges, uC, uD, nsteps=40, cfl=0.1, oe=oe)
+    prob, uC, uD = _euler(edges, k)
+    cfl = {1: 0.15, 2: 0.1, 3: 0.08}[k]
+    gC, gD, t, n = _gpu(prob, edges, uC, uD, cfl, oe=oe, nsteps=40)
+    rC, rD, rt, rn = ora.run1n(prob, edges, uC, uD, nsteps=40, cfl=cfl, oe=oe)
     # the Euler wave speed goes through a square root and divisions, so the
     # summed steps agree to rounding (a final time t_end is hit exactly)
     assert n == rn == 40 and abs(t - rt) <= 1e-13 * rt
