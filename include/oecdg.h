@@ -82,7 +82,13 @@ enum {
     OECDG_OPT_MODE = 1,         /* OECDG_MODE_* */
     OECDG_OPT_TILE = 2,         /* primal cells per workgroup tile: 32, 64 or 128 (1D) */
     OECDG_OPT_GRAPH_STEPS = 3,  /* steps per captured graph (>= 1) */
-    OECDG_OPT_GRID = 4          /* workgroups of the persistent launch (0: library choice) */
+    OECDG_OPT_GRID = 4,         /* workgroups of the persistent launch (0: library choice) */
+    OECDG_OPT_FOLD = 5          /* where the global statistics of Sec. 2.2 (avg, sigma) and the wave
+                                 * speed are reduced before each 1D stage: 0 library choice (a
+                                 * per-instance fold kernel for batches, inside every stage
+                                 * workgroup for single instances), 1 inside the stage kernel,
+                                 * 2 the fold kernel (not with the extra-wave tail mode, which then
+                                 * reduces inside).  The same bits either way. */
 };
 
 /* Problem descriptor (one instance).  Sec. 2.1 defines the meshes and the
@@ -128,8 +134,9 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
 int oecdg_batch_offsets(oecdg_handle *h, int64_t *off_primal, int64_t *off_dual);
 
 /* Set an OECDG_OPT_* tuning option (execution mode, tile size, graph length,
- * persistent grid).  The execution mode, graph length and persistent grid
- * change speed only (the same bits); the tile also sets the order in which the
+ * persistent grid, statistics fold).  The execution mode, graph length,
+ * persistent grid and fold change speed only (the same bits); the tile also
+ * sets the order in which the
  * per-tile statistics are summed, so results for different tiles agree to
  * rounding.  EINVAL for an unknown key or a value out of range; setting the
  * tile rebuilds the tile list (and may return ENOMEM). */

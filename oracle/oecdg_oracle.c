@@ -296,6 +296,23 @@ static int sigma_points(int k, double *xs)
     return c;
 }
 
+#ifdef ORA_PAIRWISE_MEAN
+/* Test-only build variant: the sum of the cell averages of cells [lo, hi) in
+ * pairwise order instead of left to right.  Both are valid FP64 evaluations of
+ * the same mean; the variant measures how far such rounding differences grow
+ * over a long run. */
+static double pairwise_sum(const ora1d *p, const double *uC, const double *uD, int mesh, int q, long lo, long hi)
+{
+    if (hi - lo <= 8) {
+        double s = 0.0;
+        for (long i = lo; i < hi; ++i) s += coef(p, uC, uD, mesh, i, q, 0);
+        return s;
+    }
+    long mid = lo + (hi - lo) / 2;
+    return pairwise_sum(p, uC, uD, mesh, q, lo, mid) + pairwise_sum(p, uC, uD, mesh, q, mid, hi);
+}
+#endif
+
 /* avg(u^M_q) = domain mean of the cell averages; sigma = max |u^M_q - avg|
  * over the sample points of every cell of mesh M.  avg/sigma: [mesh][q]. */
 void ora1d_stats(const ora1d *p, const double *uC, const double *uD, double *avg, double *sigma)
@@ -306,8 +323,12 @@ void ora1d_stats(const ora1d *p, const double *uC, const double *uD, double *avg
     for (int mesh = 0; mesh < 2; ++mesh) {
         long nk = ora1d_ncell(p, mesh);
         for (int q = 0; q < p->nc; ++q) {
+#ifdef ORA_PAIRWISE_MEAN
+            double sum = pairwise_sum(p, uC, uD, mesh, q, 0, nk);
+#else
             double sum = 0.0;
             for (long i = 0; i < nk; ++i) sum += coef(p, uC, uD, mesh, i, q, 0);
+#endif
             avg[mesh * 3 + q] = sum / (double)nk;
         }
         for (int q = 0; q < p->nc; ++q) sigma[mesh * 3 + q] = 0.0;

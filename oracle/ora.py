@@ -35,15 +35,27 @@ class Ora2D(C.Structure):
 
 
 _lib = None
+_variant = None
 _DP = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def use_variant(name=None):
+    """Switch to a test-only build variant of the oracle (oracle/build.py
+    VARIANTS: different, equally valid FP64 rounding), or back (None)."""
+    global _lib, _variant
+    if name is not None and name not in _build.VARIANTS:
+        raise ValueError(f"unknown oracle variant {name!r}")
+    _variant = name
+    _lib = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
-            _build.build()
-        L = C.CDLL(_build.LIB)
+        path = _build.lib_path(_variant)
+        if not os.path.exists(path):
+            _build.build(variant=_variant)
+        L = C.CDLL(path)
         P1 = C.POINTER(Ora1D)
         L.ora_legendre.restype = C.c_double
         L.ora_legendre.argtypes = [C.c_int, C.c_double]

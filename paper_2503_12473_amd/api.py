@@ -136,6 +136,8 @@ class OECDG:
         values); advances in place and returns (t, steps)."""
         import numpy as np
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.float64))
+        if e.ndim != 1 or e.size != self.probs[0].n + 1:
+            raise ValueError(f"edges must be a 1-D array of nx + 1 = {self.probs[0].n + 1} values, got shape {e.shape}")
         t = C.c_double()
         n = C.c_int64()
         rc = self._L.oecdg_run_nonuniform(self._h, C.c_void_p(e.ctypes.data), _ptr(uC, "uC"), _ptr(uD, "uD"),

@@ -407,8 +407,11 @@ __device__ inline bool cell_of(const Inst1D &I, int tile, int i0, int tid, int &
 // Thread tid works on cell tid/2 of the tile (primal cells first) and on the
 // half cell tid%2 of it.
 
+// folded: the instance's statistics were reduced by k_fold into a.red (batched
+// launches); otherwise every workgroup reduces the partial columns itself.
 template <int K, int FLUX, int T>
-__device__ void stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl) {
+__device__ void stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
+                           bool folded) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1, W = T + 2, PER = NC * K1 * W, NT = nthreads(T);
     constexpr int NLD = (2 * PER + NT - 1) / NT;
@@ -458,7 +461,14 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
         }
     }
     Partials<NC> pv;
-    if (need_red) load_partials<NT, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, pv, xwl);
+    double redv = 0.0;                       // folded: row tid of the instance's reduced statistics
+    if (need_red) {
+        if (folded) {
+            if (tid < NSTAT) redv = a.red[(long long)tl.inst * NSTAT + tid];
+        } else {
+            load_partials<NT, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, pv, xwl);
+        }
+    }
 
     if (!single) {
         if (l == 0 && cur.t >= a.t_end) {    // a step that is not taken: carry the time over
@@ -470,7 +480,14 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
         }
         if (l > 0 && cur.done) return;
     }
-    if (need_red) finish_partials<NT, NC>(pv, a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, red, scratch, xwl);
+    if (need_red) {
+        if (folded) {
+            if (tid < NSTAT) red[tid] = redv;
+            __syncthreads();
+        } else {
+            finish_partials<NT, NC>(pv, a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, red, scratch, xwl);
+        }
+    }
 
     double tau, taumax;
     int last = 0;
@@ -711,8 +728,9 @@ struct Disp {
 };
 
 template <int K, int FLUX, int T> struct StageFn {
-    __device__ static void go(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl) {
-        stage_tile<K, FLUX, T>(a, l, par, first, tile, smem, xwl);
+    __device__ static void go(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
+                              bool folded) {
+        stage_tile<K, FLUX, T>(a, l, par, first, tile, smem, xwl, folded);
     }
 };
 template <int K, int FLUX, int T> struct StatsFn {
@@ -732,8 +750,37 @@ __global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_stage(Sta
     __shared__ double smem[D::LDS];
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
         const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-        D::template run<StageFn>(k, a, a.l, a.par, a.first, tile, smem, XW);
+        D::template run<StageFn>(k, a, a.l, a.par, a.first, tile, smem, XW, false);
     }
+}
+
+// The stage kernel of batched launches: the instance's statistics come
+// reduced from k_fold (one fixed-order reduction per instance and stage)
+// instead of every workgroup reducing all of its instance's partial columns.
+template <int KM, int FLUX, int T>
+__global__ __launch_bounds__(nthreads(T)) void k_stage_folded(StageArgs a) {
+    using D = Disp<KM, FLUX, T>;
+    __shared__ double smem[D::LDS];
+    for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
+        const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
+        D::template run<StageFn>(k, a, a.l, a.par, a.first, tile, smem, false, true);
+    }
+}
+
+// One workgroup per instance: the partial columns of the state the next stage
+// reads (part[src]) reduced in the same fixed order as a stage kernel's own
+// reduction (same thread count, same tree), so batched instances keep the bits
+// of single-instance runs.  All NSTAT rows go to red[instance][row].
+template <int NC, int T>
+__global__ __launch_bounds__(nthreads(T)) void k_fold(StageArgs a, int src) {
+    __shared__ double red[NSTAT];
+    __shared__ double scratch[scratch_doubles(T)];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    if (tid < NSTAT) red[tid] = 0.0;
+    __syncthreads();
+    const Inst1D I = a.ninst == 1 ? a.inst0 : a.inst[b];
+    reduce_instance<nthreads(T), NC>(a.part[src], a.ntiles, I.tile0, I.npart, true, red, scratch);
+    if (tid < NSTAT) a.red[(long long)b * NSTAT + tid] = red[tid];
 }
 
 template <int KM, int FLUX, int T, bool XW>
@@ -796,7 +843,7 @@ __global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_persisten
         for (int l = 0; l < a.ns; ++l) {
             for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
                 const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-                D::template run<StageFn>(k, a, l, par, n == 0, tile, smem, XW);
+                D::template run<StageFn>(k, a, l, par, n == 0, tile, smem, XW, false);
             }
             grid_barrier(a);
             if (l == 0 && single_instance && ld_i(&a.slots[par].done, true)) return;
@@ -827,34 +874,42 @@ __global__ void k_init(StageArgs a, int ninst) {
 
 // ------------------------------------------------------------ host side ---
 
-hipError_t upload_tables_1d() { return hipSuccess; }   // tables are compile-time constants (oecdg_tables.h)
-
 static int tile_index(int tile) { return tile == 32 ? 0 : (tile == 64 ? 1 : (tile == 128 ? 2 : -1)); }
-// kernel table index: the tile, or 3 / 4 for tiles of 32 / 64 launched with the extra wave
+// kernel table index: the tile (0, 1, 2 for 32, 64, 128), or 3 / 4 for tiles
+// of 32 / 64 launched with the extra wave
 static int kernel_index(int tile, bool tailwave) {
     const int ti = tile_index(tile);
     return (ti >= 0 && tailwave && tail_threads(tile) > 0) ? ti + 3 : ti;
 }
 
-// kernel pointer tables [kidx][flux][tile]: kidx 0..3 = fixed k, 4 = mixed
-// XW: launches with the extra wave (tail tiles) use kernels whose launch bounds
-// allow it; the others keep the bounds of four waves per tile of T.
+// Kernel pointers by (kernel, degree, flux, tile).  XW: launches with the extra
+// wave (tail tiles) use kernels whose launch bounds allow it; the others keep
+// the bounds of four waves per tile of T.  WHICH 4: the folded stage kernel.
 template <int WHICH, int KM, int FLUX, int T, bool XW>
 static void *kptr() {
     if constexpr (WHICH == 0) return (void *)k_stage<KM, FLUX, T, XW>;
     else if constexpr (WHICH == 1) return (void *)k_stats<KM, FLUX, T, XW>;
     else if constexpr (WHICH == 2) return (void *)k_final<KM, FLUX, T, XW>;
-    else return (void *)k_persistent<KM, FLUX, T, XW>;
+    else if constexpr (WHICH == 3) return (void *)k_persistent<KM, FLUX, T, XW>;
+    else return (void *)k_stage_folded<KM, FLUX, T>;
 }
 
 template <int WHICH, int KM, int FLUX>
 static void *pick_t(int ti) {
-    switch (ti) {
-    case 0: return kptr<WHICH, KM, FLUX, 32, false>();
-    case 1: return kptr<WHICH, KM, FLUX, 64, false>();
-    case 3: return kptr<WHICH, KM, FLUX, 32, true>();
-    case 4: return kptr<WHICH, KM, FLUX, 64, true>();
-    default: return kptr<WHICH, KM, FLUX, 128, false>();
+    if constexpr (WHICH == 4) {              // no extra-wave variants
+        switch (ti) {
+        case 0: return kptr<WHICH, KM, FLUX, 32, false>();
+        case 1: return kptr<WHICH, KM, FLUX, 64, false>();
+        default: return kptr<WHICH, KM, FLUX, 128, false>();
+        }
+    } else {
+        switch (ti) {
+        case 0: return kptr<WHICH, KM, FLUX, 32, false>();
+        case 1: return kptr<WHICH, KM, FLUX, 64, false>();
+        case 3: return kptr<WHICH, KM, FLUX, 32, true>();
+        case 4: return kptr<WHICH, KM, FLUX, 64, true>();
+        default: return kptr<WHICH, KM, FLUX, 128, false>();
+        }
     }
 }
 
@@ -869,8 +924,7 @@ static void *pick_f(int flux, int ti) {
 }
 
 template <int WHICH>
-static void *pick(int k, bool mixed, int flux, int ti) {
-    (void)mixed;   // batches of mixed degree launch one kernel per degree group
+static void *pick(int k, int flux, int ti) {   // batches of mixed degree launch one kernel per degree group
     switch (k) {
     case 0: return pick_f<WHICH, 0>(flux, ti);
     case 1: return pick_f<WHICH, 1>(flux, ti);
@@ -890,38 +944,56 @@ hipError_t launch_init_1d(const StageArgs &a, int ninst, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s) {
+hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, int tile, hipStream_t s) {
     int ti = kernel_index(tile, a.tailwave);
     if (ti < 0) return hipErrorInvalidValue;
-    return launch(pick<1>(kmax, mixed, flux, ti), a.tend - a.tbeg, tile, a, s);
+    return launch(pick<1>(kmax, flux, ti), a.tend - a.tbeg, tile, a, s);
 }
 
-hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid, hipStream_t s) {
+hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, int tile, int grid, hipStream_t s) {
     int ti = kernel_index(tile, a.tailwave);
     if (ti < 0) return hipErrorInvalidValue;
-    return launch(pick<0>(kmax, mixed, flux, ti), grid > 0 ? grid : a.tend - a.tbeg, tile, a, s);
+    if (a.red) {                             // statistics folded by launch_fold_1d
+        if (a.tailwave) return hipErrorInvalidValue;
+        return launch(pick<4>(kmax, flux, ti), grid > 0 ? grid : a.tend - a.tbeg, tile, a, s);
+    }
+    return launch(pick<0>(kmax, flux, ti), grid > 0 ? grid : a.tend - a.tbeg, tile, a, s);
 }
 
-hipError_t launch_final_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s) {
+hipError_t launch_fold_1d(const StageArgs &a, int flux, int tile, hipStream_t s) {
+    if (!a.red || a.tailwave || tile_index(tile) < 0) return hipErrorInvalidValue;
+    // the partials the stage (a.l, a.par) reads: those of the previous global stage
+    const int src = ((((a.ns & 1) ? a.par : 0) + a.l) & 1) ^ 1;
+    void *fn = nullptr;
+    const int nc = flux == 0 || flux == 1 ? 1 : 3;
+    if (nc == 1) fn = tile == 32 ? (void *)k_fold<1, 32> : (tile == 64 ? (void *)k_fold<1, 64> : (void *)k_fold<1, 128>);
+    else fn = tile == 32 ? (void *)k_fold<3, 32> : (tile == 64 ? (void *)k_fold<3, 64> : (void *)k_fold<3, 128>);
+    StageArgs copy = a;
+    int srcv = src;
+    void *args[] = {&copy, &srcv};
+    return hipLaunchKernel(fn, dim3(a.ninst), dim3(nthreads(tile)), args, 0, s);
+}
+
+hipError_t launch_final_1d(const StageArgs &a, int kmax, int flux, int tile, hipStream_t s) {
     int ti = kernel_index(tile, a.tailwave);
     if (ti < 0) return hipErrorInvalidValue;
-    return launch(pick<2>(kmax, mixed, flux, ti), a.tend - a.tbeg, tile, a, s);
+    return launch(pick<2>(kmax, flux, ti), a.tend - a.tbeg, tile, a, s);
 }
 
-int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile, bool tailwave) {
+int persistent_max_grid_1d(int kmax, int flux, int tile, bool tailwave) {
     int ti = kernel_index(tile, tailwave);
     if (ti < 0) return 0;
     int per_cu = 0, dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const int nthr = nthreads(tile) + (tailwave ? tail_threads(tile) : 0);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick<3>(kmax, mixed, flux, ti), nthr, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick<3>(kmax, flux, ti), nthr, 0) !=
         hipSuccess)
         return 0;
     return per_cu * ncu;
 }
 
-hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid,
+hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, int tile, int grid,
                                 long long nsteps, hipStream_t s) {
     int ti = kernel_index(tile, a.tailwave);
     if (ti < 0) return hipErrorInvalidValue;
@@ -929,7 +1001,7 @@ hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, bool mix
     int single = a.ninst == 1;
     void *args[] = {&copy, &nsteps, &single};
     const int nthr = nthreads(tile) + (a.tailwave ? tail_threads(tile) : 0);
-    return hipLaunchCooperativeKernel(pick<3>(kmax, mixed, flux, ti), dim3(grid), dim3(nthr), args, 0, s);
+    return hipLaunchCooperativeKernel(pick<3>(kmax, flux, ti), dim3(grid), dim3(nthr), args, 0, s);
 }
 
 }  // namespace oecdg

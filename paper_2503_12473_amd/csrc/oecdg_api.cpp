@@ -33,13 +33,13 @@ struct oecdg_handle {
     int64_t totC = 0, totD = 0;
     int kmax = 0, flux = 0;  // flux: kernel flux id (OECDG_FLUX_*, or 3 = Euler with reflective walls)
     int rk = 3;              // RK method of every instance (rk_stage)
-    bool mixed = false;
     bool tailwave = false;   // some instance's last tile updates the extra dual cell (launches carry one more wave)
     int ncol = 0;            // partial-statistics columns (the tiles, plus one per tail)
     int tile = 64;
     int mode = OECDG_MODE_AUTO;
     int graph_steps = 64;
     int grid = 0;
+    int fold = 0;            // OECDG_OPT_FOLD: 0 auto (batches), 1 in-kernel, 2 fold kernel
 
     // device memory (library-owned)
     Inst1D *inst_d = nullptr;
@@ -52,15 +52,24 @@ struct oecdg_handle {
     double *A = nullptr;     // AC | AD: classical RK4 only (sum of earlier stages for the last one)
     int *err = nullptr;
     unsigned *bar = nullptr;
+    double *red = nullptr;   // [nbatch][NSTAT] statistics folded by k_fold
     // pinned host mirrors
     Final *fin_h = nullptr;
     int *err_h = nullptr;
 
-    // captured graph of graph_steps steps
+    // captured graphs, all for one key (t_end, dt_fixed, tile, graph_steps, fold):
+    // graph_steps steps, and 2^j steps (the remainder of a run), both from an
+    // odd step index; a whole short run (copies in, steps, final OE, the
+    // host copies of the step record and the error flags) for given state
+    // pointers and step count
     hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t ladder[13] = {};
+    hipGraphExec_t whole = nullptr;
+    double *w_uC = nullptr, *w_uD = nullptr;
+    long long w_limit = -1;
     hipStream_t cap = nullptr;   // capture stream (the caller's stream may be the null stream)
     double g_tend = 0, g_dt = 0;
-    int g_tile = 0, g_steps = 0;
+    int g_tile = 0, g_steps = 0, g_fold = -1;
 
     double *adj_ws = nullptr;    // adjoint workspace (checkpoints, segment states, adjoint buffers)
     size_t adj_bytes = 0;
@@ -86,9 +95,20 @@ int fail(oecdg_handle *h, int code, const std::string &msg) {
             return fail((h), OECDG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
     } while (0)
 
-int nc_of(int flux, int dim) { return flux == OECDG_FLUX_EULER ? (dim == 1 ? 3 : 4) : 1; }
+void drop_graphs(oecdg_handle *h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec), h->gexec = nullptr;
+    for (hipGraphExec_t &g : h->ladder)
+        if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+    if (h->whole) (void)hipGraphExecDestroy(h->whole), h->whole = nullptr;
+    h->w_uC = h->w_uD = nullptr;
+    h->w_limit = -1;
+}
 
-int validate(const oecdg_desc &d, std::string &why) {
+}  // namespace
+
+int oecdg::nc_of(int flux, int dim) { return flux == OECDG_FLUX_EULER ? (dim == 1 ? 3 : 4) : 1; }
+
+int oecdg::validate(const oecdg_desc &d, const char *&why) {   // why: a static string
     if (d.dim != 1 && d.dim != 2) return why = "dim must be 1 or 2", OECDG_EINVAL;
     if (d.rk < 0 || d.rk > 4) return why = "rk must be 0 (SSP-RK3), 1, 2, 3 or 4", OECDG_EINVAL;
     if (d.space != 0 && d.space != 1) return why = "space must be 0 (Q^k) or 1 (P^k)", OECDG_EINVAL;
@@ -115,7 +135,7 @@ int validate(const oecdg_desc &d, std::string &why) {
     return OECDG_OK;
 }
 
-void sizes(const oecdg_desc &d, int64_t &np, int64_t &nd) {
+void oecdg::sizes(const oecdg_desc &d, int64_t &np, int64_t &nd) {
     const int64_t nc = nc_of(d.flux, d.dim);
     if (d.dim == 1) {
         np = nc * (d.k + 1) * d.nx;
@@ -125,18 +145,32 @@ void sizes(const oecdg_desc &d, int64_t &np, int64_t &nd) {
     }
 }
 
-// Tables are uploaded once per device.
-int ensure_tables(oecdg_handle *h) {
-    static int done_dev[64] = {0};
-    int dev = 0;
-    HIPCHK(h, hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return fail(h, OECDG_EHIP, "device index out of range");
-    if (!done_dev[dev]) {
-        HIPCHK(h, upload_tables_1d());
-        done_dev[dev] = 1;
-    }
-    return OECDG_OK;
+// One instance of the descriptor (offsets and tiles are set by the caller).
+Inst1D oecdg::make_inst(const oecdg_desc &e) {
+    Inst1D I;
+    memset(&I, 0, sizeof(I));
+    I.k = e.k;
+    I.nc = nc_of(e.flux, 1);
+    I.flux = e.flux;
+    I.bc = e.bc;
+    I.np = (int)e.nx;
+    I.nd = (int)(e.bc == OECDG_BC_PERIODIC ? e.nx : e.nx + 1);
+    I.h = (e.xhi - e.xlo) / (double)e.nx;
+    I.cfl = e.cfl;
+    I.p0 = e.flux_param[0];
+    I.oe = e.oe;
+    return I;
 }
+
+// Default tile: 64 primal + 64 dual cells per workgroup unless the mesh is
+// small (32: more workgroups) or very large (128: fewer partial statistics).
+int oecdg::default_tile(int64_t maxn, int nbatch) { return maxn <= 4096 && nbatch == 1 ? 32 : (maxn <= 65536 ? 64 : 128); }
+
+// An outflow/walled mesh whose primal count is a multiple of T has its dual
+// cell np beyond np / T full tiles.
+bool oecdg::tail_candidate(const Inst1D &I, int T) { return I.nd == I.np + 1 && I.np % T == 0 && tail_threads(T) > 0; }
+
+namespace {
 
 int build_tiles(oecdg_handle *h) {
     h->tiles_h.clear();
@@ -156,9 +190,8 @@ int build_tiles(oecdg_handle *h) {
         ncu = 0;
     long long plain = 0, merged = 0;
     for (const Inst1D &I : h->inst_h) {
-        const bool t = I.nd == I.np + 1 && I.np % T == 0 && tail_threads(T) > 0;
         plain += (I.nd + T - 1) / T;
-        merged += t ? I.np / T : (I.nd + T - 1) / T;
+        merged += tail_candidate(I, T) ? I.np / T : (I.nd + T - 1) / T;
     }
     const bool use_tail = h->nbatch == 1 && plain > ncu && merged <= ncu && merged < plain;
     int ncol = 0;
@@ -168,7 +201,7 @@ int build_tiles(oecdg_handle *h) {
             Inst1D &I = h->inst_h[b];
             if (I.k != k) continue;
             I.tile0 = (int)h->tiles_h.size();
-            I.tail = use_tail && I.nd == I.np + 1 && I.np % T == 0 && tail_threads(T) > 0;
+            I.tail = use_tail && tail_candidate(I, T);
             if (I.tail) h->tailwave = true;
             I.ntiles = I.tail ? I.np / T : (I.nd + T - 1) / T;
             I.npart = I.ntiles + (I.tail ? 1 : 0);
@@ -185,8 +218,15 @@ int build_tiles(oecdg_handle *h) {
     h->ncol = ncol;
     HIPCHK(h, hipMalloc(&h->part, sizeof(double) * 2 * NSTAT * ncol));
     HIPCHK(h, hipMemset(h->part, 0, sizeof(double) * 2 * NSTAT * ncol));
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec), h->gexec = nullptr;
+    drop_graphs(h);
     return OECDG_OK;
+}
+
+// Statistics folded by a separate per-instance kernel (k_fold) before each
+// stage launch, instead of every workgroup reducing its instance's partials:
+// the default for batches; single instances reduce in-kernel unless asked.
+bool fold_on(const oecdg_handle *h) {
+    return !h->tailwave && (h->fold == 2 || (h->fold == 0 && h->nbatch > 1));
 }
 
 StageArgs base_args(oecdg_handle *h) {
@@ -221,13 +261,12 @@ StageArgs base_args(oecdg_handle *h) {
     a.damp_input = 1;
     a.ninst = h->nbatch;
     if (h->nbatch == 1) a.inst0 = h->inst_h[0];
+    a.red = fold_on(h) ? h->red : nullptr;
     a.t_end = INFINITY;
     return a;
 }
 
-int check_errors(oecdg_handle *h) {
-    HIPCHK(h, hipMemcpyAsync(h->err_h, h->err, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+int errors_from_host(oecdg_handle *h) {
     if (h->err_h[2]) return fail(h, OECDG_ETIMEOUT, "grid barrier spin limit exceeded");
     if (h->err_h[0])
         return fail(h, OECDG_ENONFINITE, "non-finite coefficient produced at step " + std::to_string(h->err_h[3] - 1));
@@ -237,13 +276,21 @@ int check_errors(oecdg_handle *h) {
     return OECDG_OK;
 }
 
-// One launch per degree group (tiles [tbeg, tend) of equal k).
+int check_errors(oecdg_handle *h) {
+    HIPCHK(h, hipMemcpyAsync(h->err_h, h->err, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return errors_from_host(h);
+}
+
+// One launch per degree group (tiles [tbeg, tend) of equal k), after the
+// per-instance fold of the statistics when the stage kernels read it.
 int stage_all(oecdg_handle *h, const StageArgs &a) {
+    if (a.red) HIPCHK(h, launch_fold_1d(a, h->flux, h->tile, h->stream));
     for (const auto &g : h->groups) {
         StageArgs b = a;
         b.tbeg = g.tbeg;
         b.tend = g.tend;
-        HIPCHK(h, launch_stage_1d(b, g.k, h->flux, false, h->tile, 0, h->stream));
+        HIPCHK(h, launch_stage_1d(b, g.k, h->flux, h->tile, 0, h->stream));
     }
     return OECDG_OK;
 }
@@ -253,7 +300,7 @@ int stats_all(oecdg_handle *h, const StageArgs &a) {
         StageArgs b = a;
         b.tbeg = g.tbeg;
         b.tend = g.tend;
-        HIPCHK(h, launch_stats_1d(b, g.k, h->flux, false, h->tile, h->stream));
+        HIPCHK(h, launch_stats_1d(b, g.k, h->flux, h->tile, h->stream));
     }
     return OECDG_OK;
 }
@@ -263,7 +310,7 @@ int final_all(oecdg_handle *h, const StageArgs &a) {
         StageArgs b = a;
         b.tbeg = g.tbeg;
         b.tend = g.tend;
-        HIPCHK(h, launch_final_1d(b, g.k, h->flux, false, h->tile, h->stream));
+        HIPCHK(h, launch_final_1d(b, g.k, h->flux, h->tile, h->stream));
     }
     return OECDG_OK;
 }
@@ -282,30 +329,67 @@ int launch_steps(oecdg_handle *h, const StageArgs &base, long long n0, long long
     return OECDG_OK;
 }
 
-// A graph of graph_steps (even) steps that starts at an odd step index: the
-// parities baked into its nodes hold for every replay after step 0.
-int ensure_graph(oecdg_handle *h, const StageArgs &base) {
-    if (h->gexec && h->g_tend == base.t_end && h->g_dt == base.dt_fixed && h->g_tile == h->tile &&
-        h->g_steps == h->graph_steps)
-        return OECDG_OK;
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec), h->gexec = nullptr;
-    hipGraph_t g = nullptr;
+// Capture what body() enqueues on the handle's stream into an executable graph.
+template <class F>
+int capture(oecdg_handle *h, F &&body, hipGraphExec_t *out) {
     if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
     hipStream_t user = h->stream;
     h->stream = h->cap;
     HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    int rc = launch_steps(h, base, 1, h->graph_steps);
+    int rc = body();
     hipError_t e = hipStreamEndCapture(h->cap, &g);
     h->stream = user;
-    if (rc != OECDG_OK) return rc;
+    if (rc != OECDG_OK) {
+        if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+        return rc;
+    }
     if (e != hipSuccess) return fail(h, OECDG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(h, OECDG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return OECDG_OK;
+}
+
+// Graphs depend on (t_end, dt_fixed, tile, graph_steps, fold): drop them when these change.
+void key_graphs(oecdg_handle *h, const StageArgs &base) {
+    const int fold = base.red ? 1 : 0;
+    if (h->g_tend == base.t_end && h->g_dt == base.dt_fixed && h->g_tile == h->tile &&
+        h->g_steps == h->graph_steps && h->g_fold == fold)
+        return;
+    drop_graphs(h);
     h->g_tend = base.t_end;
     h->g_dt = base.dt_fixed;
     h->g_tile = h->tile;
     h->g_steps = h->graph_steps;
+    h->g_fold = fold;
+}
+
+// A graph of graph_steps (even) steps that starts at an odd step index: the
+// parities baked into its nodes hold for every replay after step 0.
+int ensure_graph(oecdg_handle *h, const StageArgs &base) {
+    key_graphs(h, base);
+    if (h->gexec) return OECDG_OK;
+    return capture(h, [&] { return launch_steps(h, base, 1, h->graph_steps); }, &h->gexec);
+}
+
+// 2^j steps from an odd step index (any power of two: starting at an odd index
+// with pieces of even length, or ending with the single step, keeps the parity).
+int ensure_ladder(oecdg_handle *h, const StageArgs &base, int j) {
+    key_graphs(h, base);
+    if (h->ladder[j]) return OECDG_OK;
+    return capture(h, [&] { return launch_steps(h, base, 1, 1LL << j); }, &h->ladder[j]);
+}
+
+// The remainder of a run, count < 2^13 steps from an odd step index, as
+// power-of-two graphs, largest first (the single step, if any, comes last).
+int launch_remainder(oecdg_handle *h, const StageArgs &base, long long count) {
+    for (int j = 12; j >= 0; --j)
+        if (count & (1LL << j)) {
+            int rc = ensure_ladder(h, base, j);
+            if (rc != OECDG_OK) return rc;
+            HIPCHK(h, hipGraphLaunch(h->ladder[j], h->stream));
+        }
     return OECDG_OK;
 }
 
@@ -322,6 +406,49 @@ int all_done(oecdg_handle *h, const StageArgs &a, bool &done, long long &exec0) 
     return OECDG_OK;
 }
 
+// Copy the initial data into the stage buffer, clear the step records and
+// take the statistics that the first stage reads.
+int run_prologue(oecdg_handle *h, const StageArgs &a, const double *uC, const double *uD) {
+    HIPCHK(h, hipMemcpyAsync(a.BC[0], uC, sizeof(double) * h->totC, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(a.BD[0], uD, sizeof(double) * h->totD, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(h, launch_init_1d(a, h->nbatch, h->stream));
+    StageArgs st = a;
+    st.srcC = a.BC[0];
+    st.srcD = a.BD[0];
+    return stats_all(h, st);
+}
+
+// Runs of at most this many steps are replayed as one captured graph.
+constexpr long long kWholeRunSteps = 256;
+
+// A whole short run as one graph: prologue, every step, the final OE into
+// (uC, uD) and the host copies of the step record and the error flags.
+int run_whole(oecdg_handle *h, const StageArgs &a, double *uC, double *uD, long long limit) {
+    key_graphs(h, a);
+    if (!h->whole || h->w_uC != uC || h->w_uD != uD || h->w_limit != limit) {
+        if (h->whole) (void)hipGraphExecDestroy(h->whole), h->whole = nullptr;
+        int rc = capture(h, [&] {
+            int r = run_prologue(h, a, uC, uD);
+            if (r == OECDG_OK) r = launch_steps(h, a, 0, limit);
+            StageArgs f = a;
+            f.dstC = uC;
+            f.dstD = uD;
+            if (r == OECDG_OK) r = final_all(h, f);
+            if (r != OECDG_OK) return r;
+            HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, sizeof(Final) * h->nbatch, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipMemcpyAsync(h->err_h, h->err, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+            return (int)OECDG_OK;
+        }, &h->whole);
+        if (rc != OECDG_OK) return rc;
+        h->w_uC = uC;
+        h->w_uD = uD;
+        h->w_limit = limit;
+    }
+    HIPCHK(h, hipGraphLaunch(h->whole, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return OECDG_OK;
+}
+
 int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps, double dt_fixed, double *t_out,
            int64_t *steps_out) {
     if (nsteps < 0 && !(t_end < INFINITY)) return fail(h, OECDG_EINVAL, "run needs a finite t_end or nsteps >= 0");
@@ -330,27 +457,30 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
     a.t_end = t_end;
     a.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
     const long long limit = nsteps >= 0 ? nsteps : LLONG_MAX;
-    HIPCHK(h, hipMemcpyAsync(a.BC[0], uC, sizeof(double) * h->totC, hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(a.BD[0], uD, sizeof(double) * h->totD, hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(h, launch_init_1d(a, h->nbatch, h->stream));
-    StageArgs st = a;
-    st.srcC = a.BC[0];
-    st.srcD = a.BD[0];
-    int rc0 = stats_all(h, st);
-    if (rc0 != OECDG_OK) return rc0;
 
     int mode = h->mode;
     if (mode == OECDG_MODE_AUTO) mode = OECDG_MODE_GRAPH;
     if (mode == OECDG_MODE_PERSISTENT && ((h->nbatch > 1 && nsteps < 0) || h->groups.size() != 1))
         mode = OECDG_MODE_GRAPH;   // one cooperative launch serves one degree
+    if (mode == OECDG_MODE_GRAPH && limit <= kWholeRunSteps) {
+        int rc = run_whole(h, a, uC, uD, limit);
+        if (rc != OECDG_OK) return rc;
+        rc = errors_from_host(h);
+        if (t_out) *t_out = h->fin_h[0].t;
+        if (steps_out) *steps_out = h->fin_h[0].nexec;
+        return rc;
+    }
+    int rc0 = run_prologue(h, a, uC, uD);
+    if (rc0 != OECDG_OK) return rc0;
     if (mode == OECDG_MODE_PERSISTENT) {
-        int maxg = persistent_max_grid_1d(h->kmax, h->flux, false, h->tile, h->tailwave);
+        int maxg = persistent_max_grid_1d(h->kmax, h->flux, h->tile, h->tailwave);
         int grid = h->grid > 0 ? h->grid : (int)h->tiles_h.size();
         if (grid > maxg) grid = maxg;
         if (grid <= 0) return fail(h, OECDG_EHIP, "persistent kernel cannot be made co-resident");
         StageArgs p = a;
         p.coherent = 1;
-        HIPCHK(h, launch_persistent_1d(p, h->kmax, h->flux, false, h->tile, grid, limit, h->stream));
+        p.red = nullptr;                   // the persistent kernel reduces in-kernel
+        HIPCHK(h, launch_persistent_1d(p, h->kmax, h->flux, h->tile, grid, limit, h->stream));
     } else if (limit > 0) {
         int rc;
         if ((rc = launch_steps(h, a, 0, 1)) != OECDG_OK) return rc;   // step 0: no OE on the initial data
@@ -361,6 +491,8 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
             const long long chunk = std::min(G, limit - n);
             if (mode == OECDG_MODE_GRAPH && chunk == G) {
                 HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
+            } else if (mode == OECDG_MODE_GRAPH) {
+                if ((rc = launch_remainder(h, a, chunk)) != OECDG_OK) return rc;
             } else if ((rc = launch_steps(h, a, n, chunk)) != OECDG_OK) {
                 return rc;
             }
@@ -442,6 +574,7 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
     StageArgs base = base_args(h);
     base.dt_fixed = dt;
     base.t_end = INFINITY;
+    base.red = nullptr;                                      // the recomputation reduces in-kernel
     StageArgs baux = base;                                   // the second stream keeps its own step slots
     baux.slots = (Slot *)slotmem;
     baux.fin = (Final *)((Slot *)slotmem + 2);
@@ -471,7 +604,7 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
             StageArgs c = a;
             c.tbeg = g.tbeg;
             c.tend = g.tend;
-            HIPCHK(h, launch_stage_1d(c, g.k, h->flux, false, h->tile, 0, s));
+            HIPCHK(h, launch_stage_1d(c, g.k, h->flux, h->tile, 0, s));
         }
         return (int)OECDG_OK;
     };
@@ -638,7 +771,7 @@ extern "C" {
 
 int oecdg_state_size(const oecdg_desc *d, int64_t *n_primal, int64_t *n_dual) {
     if (!d || !n_primal || !n_dual) return OECDG_EINVAL;
-    std::string why;
+    const char *why = "";
     int rc = validate(*d, why);
     if (rc != OECDG_OK) return rc;
     sizes(*d, *n_primal, *n_dual);
@@ -655,7 +788,7 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
     h->desc.assign(d, d + nbatch);
     h->dim = d[0].dim;
     for (int b = 0; b < nbatch; ++b) {
-        std::string why;
+        const char *why = "";
         int rc = validate(d[b], why);
         if (rc == OECDG_OK && d[b].dim != h->dim) rc = OECDG_EINVAL, why = "mixed dimensions in one batch";
         if (rc == OECDG_OK && nbatch > 1 && d[b].dim != 1) rc = OECDG_EUNSUPPORTED, why = "batches are 1D only";
@@ -667,11 +800,7 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
             return rc;
         }
     }
-    int rc = ensure_tables(h);
-    if (rc != OECDG_OK) {
-        delete h;
-        return rc;
-    }
+    int rc = OECDG_OK;
     if (h->dim == 2) {
         rc = oecdg::create_2d(h, d);
         if (rc != OECDG_OK) {
@@ -690,18 +819,7 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
     h->offD.assign(nbatch + 1, 0);
     for (int b = 0; b < nbatch; ++b) {
         const oecdg_desc &e = d[b];
-        Inst1D I;
-        memset(&I, 0, sizeof(I));
-        I.k = e.k;
-        I.nc = nc_of(e.flux, 1);
-        I.flux = e.flux;
-        I.bc = e.bc;
-        I.np = (int)e.nx;
-        I.nd = (int)(e.bc == OECDG_BC_PERIODIC ? e.nx : e.nx + 1);
-        I.h = (e.xhi - e.xlo) / (double)e.nx;
-        I.cfl = e.cfl;
-        I.p0 = e.flux == OECDG_FLUX_EULER ? e.flux_param[0] : e.flux_param[0];
-        I.oe = e.oe;
+        Inst1D I = make_inst(e);
         int64_t np, nd;
         sizes(e, np, nd);
         I.offC = h->offC[b];
@@ -710,16 +828,12 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
         h->offD[b + 1] = h->offD[b] + nd;
         h->inst_h.push_back(I);
         if (e.k > h->kmax) h->kmax = e.k;
-        if (e.k != d[0].k) h->mixed = true;
     }
     h->totC = h->offC[nbatch];
     h->totD = h->offD[nbatch];
-    // default tile: small tiles for small problems (more workgroups), larger otherwise
     int64_t maxn = 0;
     for (auto &I : h->inst_h) maxn = I.nd > maxn ? I.nd : maxn;
-    // tiles of 64 primal + 64 dual cells unless the mesh is small (more
-    // workgroups) or very large (fewer partial statistics to reduce)
-    h->tile = maxn <= 4096 && nbatch == 1 ? 32 : (maxn <= 65536 ? 64 : 128);
+    h->tile = default_tile(maxn, nbatch);
 #define ALLOC(ptr, bytes)                                                    \
     do {                                                                     \
         if (hipMalloc(&(ptr), (bytes)) != hipSuccess) {                      \
@@ -735,6 +849,7 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
     if (h->rk == 4) ALLOC(h->A, sizeof(double) * (h->totC + h->totD));
     ALLOC(h->err, sizeof(int) * 4);
     ALLOC(h->bar, sizeof(unsigned) * 2);
+    ALLOC(h->red, sizeof(double) * NSTAT * nbatch);
 #undef ALLOC
     if (hipHostMalloc((void **)&h->fin_h, sizeof(Final) * nbatch, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&h->err_h, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
@@ -787,6 +902,10 @@ int oecdg_set_option(oecdg_handle *h, int32_t key, int64_t value) {
         if (value < 0 || value > (1 << 20)) return fail(h, OECDG_EINVAL, "grid out of range");
         h->grid = (int)value;
         return OECDG_OK;
+    case OECDG_OPT_FOLD:
+        if (value < 0 || value > 2) return fail(h, OECDG_EINVAL, "fold must be 0 (auto), 1 (in-kernel) or 2 (fold kernel)");
+        h->fold = (int)value;
+        return OECDG_OK;
     }
     return fail(h, OECDG_EINVAL, "unknown option");
 }
@@ -836,6 +955,7 @@ int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max, const
     a.tau_override = dt;
     a.taumax_override = tau_max;
     a.damp_input = 0;
+    a.red = nullptr;                          // no statistics enter a single stage
     a.BC[sp] = const_cast<double *>(stage == 0 ? uC_n : uC_l);
     a.BD[sp] = const_cast<double *>(stage == 0 ? uD_n : uD_l);
     a.UC = const_cast<double *>(uC_n);
@@ -885,7 +1005,7 @@ int oecdg_adjoint(oecdg_handle *h, const double *uC0, const double *uD0, int64_t
 
 void oecdg_destroy(oecdg_handle *h) {
     if (!h) return;
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    drop_graphs(h);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     if (h->aux) (void)hipStreamSynchronize(h->aux), (void)hipStreamDestroy(h->aux);
     for (hipEvent_t e : h->adj_ev)
@@ -901,6 +1021,7 @@ void oecdg_destroy(oecdg_handle *h) {
     (void)hipFree(h->A);
     (void)hipFree(h->err);
     (void)hipFree(h->bar);
+    (void)hipFree(h->red);
     if (h->fin_h) (void)hipHostFree(h->fin_h);
     if (h->err_h) (void)hipHostFree(h->err_h);
     if (h->ext2d) {

@@ -101,6 +101,7 @@ struct StageArgs {
     double *UC, *UD;         // damped u^n of the current step
     double *DC, *DD;         // optional: damped input of stages 1 and 2 (adjoint recomputation)
     double *AC, *AD;         // classical RK4: weighted sum of the damped inputs of stages 1 and 2
+    double *red;             // batched launches: [ninst][NSTAT] statistics reduced by k_fold (else null)
     int *err;                // [0] non-finite, [1] non-physical, [2] barrier timeout, [3] step+1 of an error
     int rk, ns;              // RK method (rk_stage) and its stages per step
     int tailwave;            // launches carry one more wave, for the dual cell np of tail tiles
@@ -148,20 +149,28 @@ int adj_block_partials();
 int adj_waves();
 
 // Host-side launchers (oecdg_1d.hip).
-hipError_t upload_tables_1d();
 hipError_t launch_init_1d(const StageArgs &a, int ninst, hipStream_t s);
-hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s);
-hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid, hipStream_t s);
-hipError_t launch_final_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, hipStream_t s);
-hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, bool mixed, int tile, int grid,
+hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, int tile, hipStream_t s);
+hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, int tile, int grid, hipStream_t s);
+hipError_t launch_fold_1d(const StageArgs &a, int flux, int tile, hipStream_t s);
+hipError_t launch_final_1d(const StageArgs &a, int kmax, int flux, int tile, hipStream_t s);
+hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, int tile, int grid,
                                 long long nsteps, hipStream_t s);
-int persistent_max_grid_1d(int kmax, int flux, bool mixed, int tile, bool tailwave);
+int persistent_max_grid_1d(int kmax, int flux, int tile, bool tailwave);
 
 }  // namespace oecdg
 
 #include "oecdg.h"
 
 namespace oecdg {
+
+// Descriptor helpers shared by the entry points (oecdg_api.cpp).
+int nc_of(int flux, int dim);
+int validate(const oecdg_desc &d, const char *&why);                  // why: a static string
+void sizes(const oecdg_desc &d, int64_t &np, int64_t &nd);             // state array lengths
+Inst1D make_inst(const oecdg_desc &e);                                 // offsets and tiles left zero
+int default_tile(int64_t maxn, int nbatch);                            // primal cells per workgroup
+bool tail_candidate(const Inst1D &I, int T);                           // dual cell np beyond np / T full tiles
 
 // Handle accessors for the 2D path (defined in oecdg_api.cpp).
 hipStream_t handle_stream(oecdg_handle *h);

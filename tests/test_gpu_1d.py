@@ -1,8 +1,9 @@
 """GPU parity of the 1D HIP path against the CPU oracle (through the C ABI).
 
-Floating-point bar: relative L-infinity error (max |gpu - oracle| over all
-coefficients of both meshes divided by max |oracle|) <= 1e-10 after a full
-run, <= 1e-12 for a single stage; step counts and final times equal.
+Floating-point bar, per component (tests/parity.py): relative L-infinity
+error (max |gpu - oracle| over all coefficients of both meshes divided by
+max |oracle| of that component) <= 1e-10 after a full run, <= 1e-12 for a
+single stage; step counts and final times equal.
 """
 import math
 
@@ -15,6 +16,7 @@ from paper_2503_12473_amd import inputs
 from paper_2503_12473_amd import _lib
 from paper_2503_12473_amd.api import OECDG, to_device
 from paper_2503_12473_amd.inputs import Problem1D, BC_OUTFLOW, BC_PERIODIC, FLUX_ADVECTION, FLUX_BURGERS, FLUX_EULER
+from tests.parity import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -23,8 +25,7 @@ STAGE_TOL = 1e-12
 
 
 def _rel(gC, gD, rC, rD):
-    err = max(np.abs(gC - rC).max(), np.abs(gD - rD).max())
-    return err / max(np.abs(rC).max(), np.abs(rD).max())
+    return rel(gC, gD, rC, rD)
 
 
 def gpu_run(prob, uC, uD, cfl, mode=None, tile=None, oe=True, rk=3, **kw):
@@ -81,6 +82,45 @@ def test_single_stage_parity(flux, bc, k, n):
                                         unD if l == 0 else ulD)
             e = _rel(oC.cpu().numpy().reshape(rC.shape), oD.cpu().numpy().reshape(rD.shape), rC, rD)
             assert e <= STAGE_TOL, (l, e)
+
+
+def _uniform_density_state(prob):
+    """Euler data with density exactly 1 and momentum exactly 0 (every mode), the
+    energy a smooth wave plus a jump: the first stage leaves the density exactly
+    constant, so its sigma vanishes."""
+    f = lambda x: inputs.euler_conserved(1.0 + 0 * x, 0 * x, 1.0 + 0.5 * np.sin(2 * np.pi * x) + 0.7 * (x > 0.3))
+    uC, uD = inputs.project_1d(f, prob)
+    for u in (uC, uD):
+        u[0] = 0.0
+        u[0, 0] = 1.0
+        u[1] = 0.0
+    return np.ascontiguousarray(uC), np.ascontiguousarray(uD)
+
+
+@pytest.mark.parametrize("bc", [BC_OUTFLOW, BC_PERIODIC])
+def test_zero_sigma_component_is_skipped(bc):
+    """sigma_q = 0 (Sec. 2.2: delta_K^m is zero when the component equals its
+    mean everywhere; with several components the max runs over the others).
+    P1 Euler, N = 300 (ragged tiles): the undamped output of the first stage has
+    an exactly uniform density on both meshes in the oracle, and the library
+    must skip that component as the oracle does: a single stage and two full
+    steps (the second step's first stage damps that output) against the oracle."""
+    prob = Problem1D(k=1, nc=3, flux=FLUX_EULER, bc=bc, n=300, xlo=0.0, xhi=1.0)
+    uC, uD = _uniform_density_state(prob)
+    tau = 0.15 * prob.h / ora.max_wavespeed1d(prob, uC, uD)
+    hC, hD = ora.ssprk3_stage1d(prob, 0, tau, tau, uC, uD, uC, uD, oe=False)
+    _, sig = ora.stats1d(prob, hC, hD)
+    assert sig[0, 0] == 0.0 and sig[1, 0] == 0.0 and np.all(sig[:, 1:] > 0.0)
+    print(f"[sigma0] bc={bc} stage 0", flush=True)
+    with OECDG(prob, 0.15) as s:
+        g = (to_device(uC), to_device(uD))
+        oC, oD = s.stage(0, tau, tau, g[0], g[1])
+    rC, rD = ora.ssprk3_stage1d(prob, 0, tau, tau, uC, uD, uC, uD)
+    assert _rel(oC.cpu().numpy(), oD.cpu().numpy(), rC, rD) <= STAGE_TOL
+    gC, gD, t, n = gpu_run(prob, uC, uD, 0.15, nsteps=2)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, nsteps=2, cfl=0.15)
+    assert n == rn == 2 and t == pytest.approx(rt, rel=1e-14)
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
 
 
 @pytest.mark.parametrize("seed", range(5))

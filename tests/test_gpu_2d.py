@@ -5,6 +5,8 @@ import math
 
 import numpy as np
 import pytest
+
+from tests.parity import rel
 import torch
 
 from oracle import ora
@@ -18,7 +20,7 @@ TOL = 1e-10
 
 
 def _rel(g, r):
-    return max(np.abs(g[0] - r[0]).max(), np.abs(g[1] - r[1]).max()) / max(np.abs(r[0]).max(), np.abs(r[1]).max())
+    return rel(g[0], g[1], r[0], r[1])
 
 
 def _gpu_run(prob, uC, uD, cfl, oe=True, **kw):

@@ -4,6 +4,8 @@ checked against the oracle instance by instance and, bitwise, against the
 same instances run one at a time on the GPU."""
 import numpy as np
 import pytest
+
+from tests.parity import rel
 import torch
 
 from oracle import ora
@@ -17,7 +19,7 @@ TOL = 1e-10
 
 
 def _rel(gC, gD, rC, rD):
-    return max(np.abs(gC - rC).max(), np.abs(gD - rD).max()) / max(np.abs(rC).max(), np.abs(rD).max())
+    return rel(gC, gD, rC, rD)
 
 
 def _build(specs):

@@ -11,6 +11,8 @@ import os
 import numpy as np
 import pytest
 
+from tests.parity import rel
+
 from paper_2503_12473_amd import inputs
 from paper_2503_12473_amd.api import OECDG, to_device
 
@@ -28,7 +30,7 @@ def _golden(name):
 
 
 def _rel(gC, gD, rC, rD):
-    return max(np.abs(gC - rC).max(), np.abs(gD - rD).max()) / max(np.abs(rC).max(), np.abs(rD).max())
+    return rel(gC, gD, rC, rD)
 
 
 # (k, T, bar).  The bar is 1e-10 wherever two equally valid FP64 evaluations

@@ -2,7 +2,7 @@
 against the non-uniform oracle.
 
 Meshes: the seeded random mesh (widths ratio <= 1.5) and the smooth grading of
-amplitude 0.3; sizes span several workgroups of 256 cells with a ragged tail.
+amplitude 0.3; sizes span several workgroups of 128 cells with a ragged tail.
 Bar: relative L-infinity error <= 1e-10 after the run, equal step counts and
 final times.
 """
@@ -55,7 +55,7 @@ def _euler(edges, k):
 @pytest.mark.parametrize("kind", ["graded", "random"])
 @pytest.mark.parametrize("k,cfl", [(1, 0.2), (2, 0.1), (3, 0.08)])
 def test_advection_run(kind, k, cfl):
-    """sin x on [0, 2 pi], N = 600 (two full workgroups and a ragged one), to T = 1."""
+    """sin x on [0, 2 pi], N = 600 (four full workgroups of 128 cells and a ragged one), to T = 1."""
     edges = _mesh(kind, 600)
     prob, uC, uD = inputs.advection_sine_edges(edges, k)
     gC, gD, t, n = _gpu(prob, edges, uC, uD, cfl, t_end=1.0)
@@ -152,6 +152,12 @@ def test_errors():
     with OECDG(prob, 0.2, rk=4) as s:
         with pytest.raises(_lib.OECDGError, match="unsupported"):
             s.run_nonuniform(edges, to_device(uC), to_device(uD), nsteps=1)
+    with OECDG(prob, 0.2) as s:
+        a, b = to_device(uC), to_device(uD)
+        with pytest.raises(ValueError, match="edges"):       # the wrapper checks the length (nx + 1)
+            s.run_nonuniform(edges[:-1], a, b, nsteps=1)
+        with pytest.raises(ValueError, match="edges"):
+            s.run_nonuniform(edges[None], a, b, nsteps=1)
     out = inputs.Problem1D(k=1, nc=1, flux=0, bc=inputs.BC_OUTFLOW, n=64, xlo=prob.xlo, xhi=prob.xhi)
     with OECDG(out, 0.2) as s:
         a, b = s.empty_state()
@@ -172,7 +178,7 @@ def test_bench_workload_full_size():
 
 
 def test_more_workgroups_than_threads():
-    """N = 70000: 274 workgroups per mesh, more than the 256 threads that reduce
+    """N = 70000: 547 workgroups per mesh, more than the 128 threads that reduce
     their statistics, so the strided part of that reduction runs too."""
     edges = _mesh("random", 70000, seed=13)
     prob, uC, uD = inputs.advection_sine_edges(edges, 1, freq=3)

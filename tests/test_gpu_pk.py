@@ -9,6 +9,8 @@ over both meshes, all components and modes.
 import numpy as np
 import pytest
 
+from tests.parity import rel
+
 from oracle import ora
 from paper_2503_12473_amd import inputs
 from paper_2503_12473_amd.api import OECDG, to_device
@@ -20,7 +22,7 @@ HIGH = [(1, 2), (2, 1), (2, 2)]          # the tensor slots outside P^2
 
 
 def _rel(g, r):
-    return max(np.abs(g[0] - r[0]).max(), np.abs(g[1] - r[1]).max()) / max(np.abs(r[0]).max(), np.abs(r[1]).max())
+    return rel(g[0], g[1], r[0], r[1])
 
 
 def _gpu_run(prob, uC, uD, cfl, oe=True, **kw):

@@ -341,6 +341,43 @@ def test_delta_invariances(k):
     np.testing.assert_allclose(d3D, 0.5 * d0D, rtol=1e-13)
 
 
+@pytest.mark.parametrize("rho,u,p,gamma", [(0.8, -0.3, 0.6, 1.4), (1.0, 0.0, 1.0, 1.4),
+                                            (0.125, 0.75, 0.1, 5.0 / 3.0), (2.0, -1.5, 7.0, 1.2)])
+def test_euler_wave_speed_of_a_constant_state(rho, u, p, gamma):
+    """The spectral radius of the Euler flux Jacobian at a state is |v| + c with
+    c = sqrt(gamma p / rho) (remark on systems, Sec. 2.2; the time step of Sec. 2.1
+    takes its maximum over the cell averages).  Written here from the primitive
+    variables, not from the oracle's conserved-variable formula: a dropped gamma,
+    a sign of v or p recovered from the wrong energy split fails."""
+    prob = Problem1D(k=2, nc=3, flux=FLUX_EULER, bc=BC_OUTFLOW, n=6, xlo=0.0, xhi=1.0, gamma=gamma)
+    uC = np.zeros((3, 3, prob.n))
+    uD = np.zeros((3, 3, prob.n + 1))
+    cons = np.array([rho, rho * u, p / (gamma - 1.0) + 0.5 * rho * u * u])
+    uC[:, 0, :] = cons[:, None]
+    uD[:, 0, :] = cons[:, None]
+    uC[:, 1, :] = 0.01          # higher modes do not enter: the speed is taken at the cell averages
+    assert ora.max_wavespeed1d(prob, uC, uD) == pytest.approx(abs(u) + math.sqrt(gamma * p / rho), rel=1e-14)
+    # the time step of a run is C h / beta with that beta
+    cfl = 0.15
+    _, _, t, n = ora.run1d(prob, uC, uD, nsteps=1, cfl=cfl)
+    assert n == 1 and t == pytest.approx(cfl * prob.h / (abs(u) + math.sqrt(gamma * p / rho)), rel=1e-14)
+
+
+def test_euler_wave_speed_is_the_max_over_both_meshes():
+    """beta for tau_max is the largest |v| + c over the cell averages of both
+    meshes (Sec. 2.1), here attained on one dual cell."""
+    g = 1.4
+    prob = Problem1D(k=1, nc=3, flux=FLUX_EULER, bc=BC_PERIODIC, n=8, xlo=0.0, xhi=1.0, gamma=g)
+    def cons(rho, u, p):
+        return np.array([rho, rho * u, p / (g - 1.0) + 0.5 * rho * u * u])
+    uC = np.zeros((3, 2, 8))
+    uD = np.zeros((3, 2, 8))
+    uC[:, 0, :] = cons(1.0, 0.1, 1.0)[:, None]
+    uD[:, 0, :] = cons(1.0, 0.1, 1.0)[:, None]
+    uD[:, 0, 5] = cons(0.5, -0.4, 2.0)
+    assert ora.max_wavespeed1d(prob, uC, uD) == pytest.approx(0.4 + math.sqrt(g * 2.0 / 0.5), rel=1e-14)
+
+
 def test_delta_system_takes_max_over_components():
     """Systems: one delta per cell, the max over components, each with its own
     sigma (remark on hyperbolic systems, Sec. 2.2)."""
