@@ -29,6 +29,7 @@ BYTES_PER_DOF_UPDATE = 64.0    # 5 reads + 3 writes of one FP64 coefficient per 
 N_CELLS, DEGREE, CFL, T_END, SEED = 16384, 2, 0.15, 0.2, 0
 FULL_STEPS = 33354             # steps to T = 0.2 for seed 0
 BATCH_COUNT, BATCH_STEPS, LOOP_SAMPLE = 512, 1000, 24
+WHOLE_RUN_STEPS = 256          # runs of up to this many steps replay one captured graph (library constant)
 ADJ_N, ADJ_K, ADJ_STEPS, ADJ_CKPT = 16384, 2, 400, 20
 E2D_N, E2D_STEPS, E2D_CFL = 1024, 500, 0.3
 
@@ -40,6 +41,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2000, help="untimed warm-up steps")
     ap.add_argument("--mode", type=int, default=0, help="execution mode (0 auto, 1 eager, 2 graph, 3 persistent)")
     ap.add_argument("--tile", type=int, default=0, help="primal cells per workgroup (0: library default)")
+    ap.add_argument("--fold", type=int, default=0,
+                    help="statistics reduction of the headline run (0 library choice, 1 in-kernel, 2 fold kernel)")
+    ap.add_argument("--batched-fold", type=int, default=0,
+                    help="statistics reduction of the batched runs (0 library choice, 1 in-kernel, 2 fold kernel)")
     ap.add_argument("--repeats", type=int, default=5, help="timed repetitions (median reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU-oracle sample length")
@@ -60,19 +65,20 @@ KERNEL_SOURCES = ["paper_2503_12473_amd/csrc/oecdg_1d.hip", "paper_2503_12473_am
                   "paper_2503_12473_amd/csrc/oecdg_internal.h", "paper_2503_12473_amd/csrc/oecdg_device.h"]
 
 
-def measured_traffic():
-    """HBM bytes per stage-kernel launch from the committed counter profile
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if the kernel sources
-    changed since the counters were taken."""
+def stage_profile():
+    """The committed rocprofv3 results of the headline stage kernel: average
+    kernel duration (kernel trace) and HBM bytes per launch (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated), or {} if the kernel sources changed since the
+    profile was taken."""
     import hashlib
     try:
         meta = json.load(open(PROFILE_JSON))
     except OSError:
-        return None
+        return {}
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    return meta["traffic_bytes_per_launch"] if meta.get("source_sha256") == h.hexdigest() else None
+    return meta if meta.get("source_sha256") == h.hexdigest() else {}
 
 
 PROFILE2D_JSON = os.path.join(ROOT, "profiles", "k_stage2d_euler2d_q2_n1024.json")
@@ -95,14 +101,16 @@ def profile_2d():
     return meta if meta.get("source_sha256") == h.hexdigest() else {}
 
 
-def batched_bench(k_fixed=None):
+def batched_bench(k_fixed=None, fold=0):
     """Batched form: 512 independent 1D Euler Riemann instances (seed 0: N ~
     U{128..8192}, k ~ U{1,2,3} or k = k_fixed, seeded states), BATCH_STEPS steps
-    each with its own CFL step, advanced together (graph-captured stages, one
-    launch per degree group, autotuned tile) versus a loop of plain per-instance
-    runs (the first LOOP_SAMPLE instances, same steps and tile)."""
+    each with its own CFL step, advanced together (graph-captured stages: a
+    per-instance fold of the statistics, then one launch per degree group;
+    autotuned tile) versus a loop of plain per-instance runs (LOOP_SAMPLE
+    instances spread evenly over the batch, same steps and tile).  fold: the
+    OECDG_OPT_FOLD value (0 library choice, 1 in-kernel reduction, 2 fold)."""
     import torch
-    from paper_2503_12473_amd import inputs
+    from paper_2503_12473_amd import inputs, _lib
     from paper_2503_12473_amd.api import OECDG, to_device
     from paper_2503_12473_amd.autotune import tune_tile
     specs = inputs.batch_instances(seed=SEED, count=BATCH_COUNT, k_fixed=k_fixed)
@@ -126,6 +134,8 @@ def batched_bench(k_fixed=None):
     icC = torch.cat([to_device(u[0]) for u in states])
     icD = torch.cat([to_device(u[1]) for u in states])
     with OECDG(probs, CFL, stream=stream) as solver:
+        if fold:
+            solver.set_option(_lib.OPT_FOLD, fold)
         tile = tune_tile(solver, icC, icD, steps=5)
         a, b = icC.clone(), icD.clone()
         solver.run(a, b, t_end=math.inf, nsteps=20)
@@ -138,18 +148,29 @@ def batched_bench(k_fixed=None):
         wall = sorted(walls)[2]                               # median of 5
     batched = sum(dofs) * BATCH_STEPS / wall
     loop_wall, loop_dofs = 0.0, 0
-    for p, (uC, uD) in list(zip(probs, states))[:LOOP_SAMPLE]:
+    sample = [round(i * (BATCH_COUNT - 1) / (LOOP_SAMPLE - 1)) for i in range(LOOP_SAMPLE)]
+    for i in sample:
+        p, (uC, uD) = probs[i], states[i]
         with OECDG(p, CFL, stream=stream) as solver:
-            solver.set_option(2, tile)
+            solver.set_option(_lib.OPT_TILE, tile)
             a, b = to_device(uC), to_device(uD)
             solver.run(a.clone(), b.clone(), t_end=math.inf, nsteps=20)
             loop_wall += timed(solver, a, b)
             loop_dofs += p.dofs()
     loop = loop_dofs * BATCH_STEPS / loop_wall
+    mean_all = sum(dofs) / len(dofs)
+    bytes_per_stage = BYTES_PER_DOF_UPDATE / 3.0 * sum(dofs)
+    stage_s = wall / (3 * BATCH_STEPS)
     return {"instances": BATCH_COUNT, "steps": BATCH_STEPS, "dofs": sum(dofs), "tile": tile,
-            "k": "U{1,2,3}" if k_fixed is None else k_fixed,
+            "k": "U{1,2,3}" if k_fixed is None else k_fixed, "fold": {0: "auto", 1: "in-kernel", 2: "fold"}[fold],
             "batched_dof_updates_per_s": batched, "batched_wall_s": wall,
+            "hbm": {"achieved": bytes_per_stage / stage_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": bytes_per_stage / stage_s / 1e9 / HBM_PEAK_GBS, "stage_us": 1e6 * stage_s,
+                    "algorithmic_bytes_per_stage": bytes_per_stage,
+                    "note": "per RK stage: fold + one stage launch per degree group"},
             "loop_dof_updates_per_s": loop, "loop_sample_instances": LOOP_SAMPLE,
+            "loop_sample": f"instances {sample[0]}, {sample[1]}, ..., {sample[-1]} (evenly spaced); mean DOFs "
+                           f"{loop_dofs / LOOP_SAMPLE:.0f} against {mean_all:.0f} over the batch",
             "speedup_vs_loop": batched / loop}
 
 
@@ -415,6 +436,8 @@ def main():
         solver.set_option(_lib.OPT_MODE, args.mode)
     if args.tile:
         solver.set_option(_lib.OPT_TILE, args.tile)
+    if args.fold:
+        solver.set_option(_lib.OPT_FOLD, args.fold)
     if args.calibrate_copy_mib > 0:
         src = torch.ones(args.calibrate_copy_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -425,9 +448,13 @@ def main():
     ic = (to_device(uC), to_device(uD))
     work = (ic[0].clone(), ic[1].clone())
 
-    # warm-up: graph capture, code loading, caches
+    # warm-up: code loading, caches; then one untimed run of the timed length,
+    # which captures the graph the library replays for runs of that length
     if args.warmup > 0:
         solver.run(work[0], work[1], t_end=T_END, nsteps=args.warmup)
+    work[0].copy_(ic[0])
+    work[1].copy_(ic[1])
+    solver.run(work[0], work[1], t_end=T_END, nsteps=min(args.steps, WHOLE_RUN_STEPS))
     torch.cuda.synchronize()
 
     times, steps = [], None
@@ -447,10 +474,16 @@ def main():
     value = dofs * steps / wall
 
     # dominant kernel: the stage kernel, 3 launches per step; algorithmic bytes
-    # per launch = (64 B per DOF-update / 3 stages) x DOFs
+    # per launch = (64 B per DOF-update / 3 stages) x DOFs.  Its average launch
+    # time is measured live: the timed region (HIP events on the stream the
+    # library launches on, which is torch's current stream here) over the
+    # number of stage launches.  Runs of up to WHOLE_RUN_STEPS steps replay one
+    # captured graph, so the region is the stage kernels back to back plus the
+    # copies in, the statistics of the initial data and the final OE.
     bytes_per_launch = BYTES_PER_DOF_UPDATE / 3.0 * dofs
     launch_s = wall / (3 * steps)
     achieved = bytes_per_launch / launch_s / 1e9
+    prof = stage_profile()
     out = {
         "metric": "DOF-updates/s at P2 (plain vs batched) and adjoint/forward time ratio",
         "value": value,
@@ -466,19 +499,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1D Euler two-state Riemann problem, outflow, N=16384 primal + 16385 dual cells, "
                                "P2 Legendre modal, SSP-RK3 + OE, CFL 0.15, T=0.2, seed 0",
-                   "dofs": dofs, "t_end": t, "mode": args.mode, "tile": args.tile},
+                   "dofs": dofs, "t_end": t, "mode": args.mode, "tile": args.tile, "fold": args.fold},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": prof.get("traffic_bytes_per_launch"),
                      "kernel": "k_stage (one RK stage + OE of the previous stage)",
                      "launch_us": 1e6 * launch_s,
+                     "launch_us_rocprof": prof.get("avg_duration_us"),
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
                      "note": "state of 2.4 MB per array, resident in L2/MALL: each stage is bound by its "
                              "dependency chain (global statistics of the previous stage, damping, operator), "
                              "not by HBM bandwidth"},
     }
     solver.close()
     if not args.no_batched:
-        out["batched"] = batched_bench()
-        out["batched_k2"] = batched_bench(k_fixed=2)
+        out["batched"] = batched_bench(fold=args.batched_fold)
+        out["batched_k2"] = batched_bench(k_fixed=2, fold=args.batched_fold)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench()
     if not args.no_2d:

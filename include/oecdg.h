@@ -30,7 +30,10 @@
  *    example of Sec. 4) make them the mirror images of cells 0 and nx-1 about
  *    the wall: mode m times (-1)^m, the momentum negated once more.  The dual
  *    cells on the walls then reach half a cell outside the domain; their
- *    initial data are the mirror extension of the data inside.
+ *    initial data are the mirror extension of the data inside.  Inflow
+ *    boundaries (1D Euler; the examples of Sec. 4 that prescribe an incoming
+ *    state) make the ghosts constant states set with oecdg_set_inflow and
+ *    held for the whole run; the dual mesh has nx+1 cells as with outflow.
  *  - 2D layout (tensor-product modes; a P^k state keeps the same slots with
  *    the modes a + b > k zero): u[(((q*(k+1) + a)*(k+1) + b)*ny
  *    + iy)*nx + ix], mode a in x, b in y.  Primal cell (ix, iy) is
@@ -67,7 +70,15 @@ enum {
 };
 
 enum { OECDG_FLUX_ADVECTION = 0, OECDG_FLUX_BURGERS = 1, OECDG_FLUX_EULER = 2 };
-enum { OECDG_BC_PERIODIC = 0, OECDG_BC_OUTFLOW = 1, OECDG_BC_REFLECTIVE = 2 };
+enum { OECDG_BC_PERIODIC = 0, OECDG_BC_OUTFLOW = 1, OECDG_BC_REFLECTIVE = 2, OECDG_BC_INFLOW = 3 };
+
+/* Descriptor flags. */
+enum {
+    OECDG_FLAG_ALLOW_NEGATIVE_PRESSURE = 1   /* 1D Euler: a cell average with non-positive pressure is not
+                                              * an error (ENONPHYSICAL then means density <= 0 only); the
+                                              * wave speeds use |v| + sqrt(gamma |p| / rho) throughout,
+                                              * which is |v| + c for every physical state */
+};
 
 /* Execution modes of oecdg_run (oecdg_set_option(OECDG_OPT_MODE, ...)). */
 enum {
@@ -97,7 +108,7 @@ enum {
  * maxima over the cell averages of both meshes. */
 typedef struct {
     int32_t dim;                /* 1 or 2 */
-    int32_t k;                  /* polynomial degree: 0..3 in 1D; 2 (tensor Q2) in 2D */
+    int32_t k;                  /* polynomial degree: 0..3 in 1D; 1..3 in 2D */
     int32_t flux;               /* OECDG_FLUX_*: 1D any; 2D advection or Euler */
     int32_t bc;                 /* OECDG_BC_*; 2D: periodic only */
     int64_t nx, ny;             /* primal cells per direction (ny = 1 in 1D) */
@@ -110,12 +121,12 @@ typedef struct {
                                  * 0 or 3: SSP-RK3 (Shu-Osher), 1: forward Euler, 2: SSP-RK2 (Heun),
                                  * 4: classical fourth-order RK, whose last stage
                                  * -u^n/3 + u^1/3 + 2u^2/3 + u^3/3 + tau/6 L(u^3) uses the damped stage
-                                 * values (library-owned buffer of one state).  2D: 0 or 3 only
-                                 * (EUNSUPPORTED otherwise); all instances of a batch use one method. */
+                                 * values (library-owned buffer of one state).  All instances of a
+                                 * batch use one method. */
     int32_t space;              /* 2D space: 0 = tensor Q^k, 1 = the paper's total-degree P^k (Sec. 2.1):
                                  * same layout; the modes with a + b > k are ignored on input and zero on
                                  * output (oecdg_run, oecdg_stage).  1D: either value (the spaces coincide). */
-    int32_t reserved;           /* must be 0 */
+    int32_t flags;              /* OECDG_FLAG_* bits (0: none) */
 } oecdg_desc;
 
 /* Number of doubles of the primal and dual state arrays of one instance. */
@@ -142,6 +153,14 @@ int oecdg_batch_offsets(oecdg_handle *h, int64_t *off_primal, int64_t *off_dual)
  * tile rebuilds the tile list (and may return ENOMEM). */
 int oecdg_set_option(oecdg_handle *h, int32_t key, int64_t value);
 
+/* Ghost states of an inflow instance (bc = OECDG_BC_INFLOW): left and right
+ * each hold nc = 3 conserved variables (rho, m, E), the cell averages of the
+ * constant ghost cells left of primal cell 0 and right of cell nx-1.  Host
+ * arrays, copied.  Must be called for every inflow instance before
+ * oecdg_run (EINVAL from oecdg_run otherwise); EINVAL for an instance index
+ * out of range or an instance without inflow boundaries. */
+int oecdg_set_inflow(oecdg_handle *h, int32_t instance, const double *left, const double *right);
+
 /* tau_max of instance 0 for the state (uC, uD) (Sec. 2.1; cell averages of
  * both meshes).  Device inputs, host output; synchronises the stream. */
 int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out);
@@ -152,8 +171,7 @@ int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out
  * e.g. SSP-RK3: (c_{00}, d_{00}) = (1, 1), (c_{10}, c_{11}, d_{11}) = (3/4, 1/4, 1/4),
  * (c_{20}, c_{22}, d_{22}) = (1/3, 2/3, 2/3); at stage 0, u^n is u_sigma^{n,0}
  * and c_{00} multiplies it once.  stage in 0 .. s-1 (EINVAL otherwise); the last
- * stage of classical RK4, which reads the earlier stages, is EUNSUPPORTED.  2D
- * handles run SSP-RK3 stages.  dt = tau,
+ * stage of classical RK4, which reads the earlier stages, is EUNSUPPORTED.  dt = tau,
  * tau_max = the coupling parameter of the operator.  uC_n/uD_n = u_sigma^n,
  * uC_l/uD_l = u_sigma^{n,l} (ignored/aliasable for stage 0); outputs must not
  * alias inputs.  Single instance handles only.  Device pointers. */

@@ -28,7 +28,9 @@
  * of cells 0 and n-1.  Reflective walls (Euler only; the two-blast-wave example
  * of Sec. 4) make the ghosts the mirror images of cells 0 and n-1 about the
  * wall: the polynomial u(2 x_wall - x) with the momentum negated, i.e. mode m
- * of component q times (-1)^m, and times -1 more for the momentum.
+ * of component q times (-1)^m, and times -1 more for the momentum.  Inflow
+ * boundaries (the examples of Sec. 4 that prescribe an incoming state) make
+ * the ghosts constant states given by the caller, held for the whole run.
  *
  * Compile: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math).
  */
@@ -38,7 +40,7 @@
 
 enum { ORA_OK = 0, ORA_EINVAL = -1, ORA_ENOMEM = -2, ORA_ENONFINITE = -4, ORA_ENONPHYSICAL = -5 };
 enum { FLUX_ADVECTION = 0, FLUX_BURGERS = 1, FLUX_EULER = 2 };
-enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECTIVE = 2 };
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECTIVE = 2, BC_INFLOW = 3 };
 
 typedef struct {
     int k;          /* polynomial degree */
@@ -49,6 +51,10 @@ typedef struct {
     double xlo, xhi;
     double a;       /* advection speed */
     double gamma;   /* adiabatic index */
+    int allow_negative_pressure;   /* Euler: a cell average with p <= 0 is not an error */
+    int pad;
+    double inflow[2][3];           /* BC_INFLOW: cell averages of the ghost cells left of cell 0
+                                    * and right of cell n-1, held fixed */
 } ora1d;
 
 /* ------------------------------------------------------------------------ */
@@ -129,6 +135,8 @@ static double coef(const ora1d *p, const double *uC, const double *uD, int mesh,
             double sign = (m % 2 == 1) ? -1.0 : 1.0;
             if (q == 1) sign = -sign;                                 /* momentum */
             return sign * uC[(long)(q * K1 + m) * p->n + src];
+        } else if (p->bc == BC_INFLOW && (idx < 0 || idx >= p->n)) {
+            return m == 0 ? p->inflow[idx < 0 ? 0 : 1][q] : 0.0;
         } else if (idx < 0 || idx >= p->n) {
             long src = idx < 0 ? 0 : p->n - 1;
             return m == 0 ? uC[(long)(q * K1) * p->n + src] : 0.0;
@@ -186,7 +194,10 @@ static void flux1d(const ora1d *p, const double *w, double *f)
     }
 }
 
-/* Spectral radius of f'(u) at a state (the local maximum wave speed). */
+/* Spectral radius of f'(u) at a state (the local maximum wave speed).  Euler:
+ * |v| + sqrt(gamma |p| / rho); the same as |v| + c for every physical state,
+ * and finite where a cell average carries a non-positive pressure that the
+ * problem tolerates (allow_negative_pressure). */
 double ora1d_wavespeed(const ora1d *p, const double *ubar)
 {
     if (p->flux == FLUX_ADVECTION) return fabs(p->a);
@@ -194,14 +205,17 @@ double ora1d_wavespeed(const ora1d *p, const double *ubar)
     double rho = ubar[0], mom = ubar[1], E = ubar[2];
     double v = mom / rho;
     double pr = (p->gamma - 1.0) * (E - 0.5 * mom * v);
-    return fabs(v) + sqrt(p->gamma * pr / rho);
+    return fabs(v) + sqrt(p->gamma * fabs(pr) / rho);
 }
 
+/* A cell average is physical with positive density and pressure; with
+ * allow_negative_pressure only the density is required to be positive. */
 static int physical(const ora1d *p, const double *ubar)
 {
     if (p->flux != FLUX_EULER) return 1;
     double rho = ubar[0], mom = ubar[1], E = ubar[2];
     if (!(rho > 0.0)) return 0;
+    if (p->allow_negative_pressure) return 1;
     double pr = (p->gamma - 1.0) * (E - 0.5 * mom * mom / rho);
     return pr > 0.0;
 }

@@ -41,6 +41,8 @@ typedef struct {
     int k, nc, flux, bc;
     long n;
     double xlo, xhi, a, gamma;
+    int allow_negative_pressure, pad;
+    double inflow[2][3];
 } ora1d;
 
 double ora_legendre_deriv(int n, int m, double x);

@@ -25,7 +25,8 @@ class OracleError(RuntimeError):
 
 class Ora1D(C.Structure):
     _fields_ = [("k", C.c_int), ("nc", C.c_int), ("flux", C.c_int), ("bc", C.c_int), ("n", C.c_long),
-                ("xlo", C.c_double), ("xhi", C.c_double), ("a", C.c_double), ("gamma", C.c_double)]
+                ("xlo", C.c_double), ("xhi", C.c_double), ("a", C.c_double), ("gamma", C.c_double),
+                ("allow_negative_pressure", C.c_int), ("pad", C.c_int), ("inflow", (C.c_double * 3) * 2)]
 
 
 class Ora2D(C.Structure):
@@ -100,7 +101,12 @@ def lib():
 
 
 def _p1(prob):
-    return Ora1D(prob.k, prob.nc, prob.flux, prob.bc, prob.n, prob.xlo, prob.xhi, prob.a, prob.gamma)
+    p = Ora1D(prob.k, prob.nc, prob.flux, prob.bc, prob.n, prob.xlo, prob.xhi, prob.a, prob.gamma,
+              int(prob.allow_negative_pressure), 0)
+    for side in range(2):
+        for q, v in enumerate(prob.inflow[side] if prob.inflow else ()):
+            p.inflow[side][q] = float(v)
+    return p
 
 
 def _arr(u):

@@ -14,11 +14,12 @@ LIB_PATH = os.path.join(HERE, "liboecdg.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ENONPHYSICAL, EUNSUPPORTED, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
 MODE_AUTO, MODE_EAGER, MODE_GRAPH, MODE_PERSISTENT = 0, 1, 2, 3
-OPT_MODE, OPT_TILE, OPT_GRAPH_STEPS, OPT_GRID = 1, 2, 3, 4
+FLAG_ALLOW_NEGATIVE_PRESSURE = 1
+OPT_MODE, OPT_TILE, OPT_GRAPH_STEPS, OPT_GRID, OPT_FOLD = 1, 2, 3, 4, 5
 
 # every symbol include/oecdg.h declares
 EXPORTS = ("oecdg_state_size", "oecdg_init", "oecdg_batch_offsets", "oecdg_set_option", "oecdg_dt",
-           "oecdg_stage", "oecdg_run", "oecdg_run_nonuniform", "oecdg_adjoint", "oecdg_destroy", "oecdg_strerror",
+           "oecdg_stage", "oecdg_run", "oecdg_run_nonuniform", "oecdg_set_inflow", "oecdg_adjoint", "oecdg_destroy", "oecdg_strerror",
            "oecdg_last_error")
 
 
@@ -28,7 +29,7 @@ class Desc(C.Structure):
                 ("xlo", C.c_double), ("xhi", C.c_double), ("ylo", C.c_double), ("yhi", C.c_double),
                 ("flux_param", C.c_double * 2), ("cfl", C.c_double),
                 ("oe", C.c_int32), ("rk", C.c_int32),
-                ("space", C.c_int32), ("reserved", C.c_int32)]
+                ("space", C.c_int32), ("flags", C.c_int32)]
 
 
 class OECDGError(RuntimeError):
@@ -55,6 +56,7 @@ def lib():
     L.oecdg_batch_offsets.argtypes = [H, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.oecdg_set_option.argtypes = [H, C.c_int32, C.c_int64]
     L.oecdg_dt.argtypes = [H, D, D, C.POINTER(C.c_double)]
+    L.oecdg_set_inflow.argtypes = [H, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.oecdg_stage.argtypes = [H, C.c_int32, C.c_double, C.c_double, D, D, D, D, D, D]
     L.oecdg_run.argtypes = [H, D, D, C.c_double, C.c_int64, C.c_double, C.POINTER(C.c_double),
                             C.POINTER(C.c_int64)]

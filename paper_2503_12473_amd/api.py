@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 from ._lib import Desc, OECDGError, check
-from .inputs import Problem1D, Problem2D, FLUX_EULER
+from .inputs import Problem1D, Problem2D, FLUX_EULER, BC_INFLOW
 
 
 def make_desc(prob, cfl: float, oe: bool = True, rk: int = 3) -> Desc:
@@ -39,7 +39,7 @@ def make_desc(prob, cfl: float, oe: bool = True, rk: int = 3) -> Desc:
     d.oe = 1 if oe else 0
     d.rk = int(rk)
     d.space = int(getattr(prob, "space", 0))
-    d.reserved = 0
+    d.flags = _lib.FLAG_ALLOW_NEGATIVE_PRESSURE if getattr(prob, "allow_negative_pressure", False) else 0
     return d
 
 
@@ -76,6 +76,11 @@ class OECDG:
         check(self._L.oecdg_batch_offsets(self._h, offC, offD), self._h, "oecdg_batch_offsets")
         self.off_primal = list(offC)
         self.off_dual = list(offD)
+        for b, p in enumerate(probs):
+            if isinstance(p, Problem1D) and p.bc == BC_INFLOW and p.inflow:
+                left = (C.c_double * 3)(*[float(v) for v in p.inflow[0]])
+                right = (C.c_double * 3)(*[float(v) for v in p.inflow[1]])
+                check(self._L.oecdg_set_inflow(self._h, b, left, right), self._h, "oecdg_set_inflow")
 
     # ------------------------------------------------------------------
     def close(self):

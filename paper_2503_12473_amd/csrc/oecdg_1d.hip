@@ -108,17 +108,20 @@ __device__ inline void oe_factors(const double (&own)[NC][K + 1], const double (
     }
 }
 
-// Contribution of one half of a cell to the time derivative of its modal
-// coefficients (equcdg), without the cell's own coupling term -a_m / tau_max:
-//   (2m+1)/2/tau_max int_half w P_m + (2m+1)/h (int_half f(w) P_m' + edge term)
-// Right half (hf = 1): nb is the overlapping cell on the right, nodes
-// xi_g = (s_g+1)/2, edge term -f(w(x_R)).  Left half (hf = 0): evaluated as the
-// mirror image with the same nodes through P_n(-x) = (-1)^n P_n(x): the
-// neighbour's odd modes, the test functions P_m (odd m) and P_m' (even m) change
-// sign, and the edge term is +(-1)^m f(w(x_L)).
+// Contribution of one half of a cell to tau_max times the time derivative of
+// its modal coefficients (equcdg), without the cell's own coupling term -a_m:
+//   (2m+1)/2 int_half w P_m + tau_max (2m+1)/h (int_half f(w) P_m' + edge term)
+// The projection of w uses the exact overlap integrals of the Legendre modes
+// (OV), so a component that is one constant on both meshes and carries no
+// flux gets exactly zero rate once the caller subtracts a_m.  Right half
+// (hf = 1): nb is the overlapping cell on the right, nodes xi_g = (s_g+1)/2,
+// edge term -f(w(x_R)).  Left half (hf = 0): evaluated as the mirror image with
+// the same nodes through P_n(-x) = (-1)^n P_n(x): the neighbour's odd modes,
+// the test functions P_m (odd m) and P_m' (even m) change sign, and the edge
+// term is +(-1)^m f(w(x_L)).  ft = tau_max / h.
 template <int K, int FLUX>
-__device__ inline void cdg_rate_half(const double (&nb)[FluxT<FLUX>::NC][K + 1], int hf, double p0, double inv_tm,
-                                     double hinv, double (&r)[FluxT<FLUX>::NC][K + 1]) {
+__device__ inline void cdg_rate_half(const double (&nb)[FluxT<FLUX>::NC][K + 1], int hf, double p0, double ft,
+                                     double (&r)[FluxT<FLUX>::NC][K + 1]) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC;
     constexpr Tab<K> tb = make_tab<K>();
@@ -128,11 +131,11 @@ __device__ inline void cdg_rate_half(const double (&nb)[FluxT<FLUX>::NC][K + 1],
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int n = 0; n <= K; ++n) c[q][n] = (n & 1) ? flip * nb[q][n] : nb[q][n];
-    double accw[NC][K + 1], accf[NC][K + 1];
+    double accf[NC][K + 1];
 #pragma unroll
     for (int q = 0; q < NC; ++q)
 #pragma unroll
-        for (int m = 0; m <= K; ++m) accw[q][m] = accf[q][m] = 0.0;
+        for (int m = 0; m <= K; ++m) accf[q][m] = 0.0;
 #pragma unroll
     for (int g = 0; g <= K; ++g) {
         double w[NC], fw[NC];
@@ -147,10 +150,7 @@ __device__ inline void cdg_rate_half(const double (&nb)[FluxT<FLUX>::NC][K + 1],
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 0; m <= K; ++m) {
-                accw[q][m] += tb.WP[1][g][m] * w[q];
-                accf[q][m] += tb.WD[1][g][m] * fw[q];
-            }
+            for (int m = 0; m <= K; ++m) accf[q][m] += tb.WD[1][g][m] * fw[q];
     }
     double wc[NC], fc[NC];
 #pragma unroll
@@ -168,7 +168,10 @@ __device__ inline void cdg_rate_half(const double (&nb)[FluxT<FLUX>::NC][K + 1],
         for (int m = 0; m <= K; ++m) {
             const double sw = (m & 1) ? flip : 1.0;
             const double sf = (m & 1) ? 1.0 : flip;
-            r[q][m] = inv_tm * ((m + 0.5) * (sw * accw[q][m])) + (2.0 * m + 1.0) * hinv * (sf * accf[q][m] + sw * edge);
+            double pw = 0.0;
+#pragma unroll
+            for (int n = 0; n <= K; ++n) pw += tb.OV[m][n] * c[q][n];
+            r[q][m] = (m + 0.5) * (sw * pw) + (2.0 * m + 1.0) * ft * (sf * accf[q][m] + sw * edge);
         }
     }
 }
@@ -186,13 +189,15 @@ __device__ inline void lds_cell(const double *s, int li, double (&c)[NC][K + 1])
 // Element e of the tile's LDS image of the pre-damping input: primal cells
 // [i0-1, i0+T] (rows q*(k+1)+m of length T+2), then dual cells [i0-1, i0+T].
 // Periodic wrap; outflow: constant-extension ghosts for primal -1 and np
-// (reflective walls load the same and mirror_ghosts overwrites them); zeros
-// for dual cells that do not exist.
+// (reflective walls load the same and mirror_ghosts overwrites them); inflow:
+// the instance's fixed ghost states; zeros for dual cells that do not exist.
 // Sign of coefficient (q, m) of a reflective ghost: (-1)^m, and -1 more for
 // the momentum (q = 1 of the Euler system).
 __device__ inline double mirror_sign(int q, int m) { return ((m & 1) ^ (q == 1)) ? -1.0 : 1.0; }
 
-template <int K, int NC, int T>
+// GH: kernels of the Euler flux with wall or inflow ghosts (FluxT<3>), the
+// only ones that carry the inflow ghost states.
+template <int K, int NC, int T, bool GH>
 __device__ inline double tile_elem(const Inst1D &I, int i0, const double *__restrict__ inC,
                                    const double *__restrict__ inD, int e) {
     constexpr int W = T + 2, K1 = K + 1, PER = NC * K1 * W;
@@ -208,7 +213,13 @@ __device__ inline double tile_elem(const Inst1D &I, int i0, const double *__rest
             if (gi < 0 || gi >= np) gi = ((gi % np) + np) % np;   // mesh shorter than a tile
             return inC[(long long)qm * np + gi];
         }
-        if (gi < 0 || gi >= np) return (qm % K1 == 0) ? inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)] : 0.0;
+        if (gi < 0 || gi >= np) {
+            if (qm % K1 != 0) return 0.0;
+            if constexpr (GH) {
+                if (I.bc == 3) return I.gin[gi < 0 ? 0 : 1][qm / K1];
+            }
+            return inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)];
+        }
         return inC[(long long)qm * np + gi];
     }
     const int nd = I.nd;
@@ -241,12 +252,12 @@ __device__ inline void mirror_ghosts(const Inst1D &I, int i0, double *sC) {
     }
 }
 
-template <int K, int NC, int T>
+template <int K, int NC, int T, bool GH>
 __device__ inline void load_tile(const Inst1D &I, int i0, const double *__restrict__ inC,
                                  const double *__restrict__ inD, double *s, bool xwl) {
     constexpr int PER = NC * (K + 1) * (T + 2);
     if (!xwl || threadIdx.x < nthreads(T))
-        for (int e = threadIdx.x; e < 2 * PER; e += nthreads(T)) s[e] = tile_elem<K, NC, T>(I, i0, inC, inD, e);
+        for (int e = threadIdx.x; e < 2 * PER; e += nthreads(T)) s[e] = tile_elem<K, NC, T, GH>(I, i0, inC, inD, e);
 }
 
 // Apply F_tau in LDS to primal cells [i0-1, i0+T-1] and dual cells [i0, i0+T]
@@ -457,7 +468,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
 #pragma unroll
         for (int i = 0; i < NLD; ++i) {
             const int e = tid + i * NT;
-            pre[i] = (e < 2 * PER && mainthr) ? tile_elem<K, NC, T>(I, i0, inC, inD, e) : 0.0;
+            pre[i] = (e < 2 * PER && mainthr) ? tile_elem<K, NC, T, FLUX == 3>(I, i0, inC, inD, e) : 0.0;
         }
     }
     Partials<NC> pv;
@@ -580,7 +591,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
 
         const double inv_tm = 1.0 / taumax;
         double r[NC][K1];
-        cdg_rate_half<K, FLUX>(nb, hf, I.p0, inv_tm, 1.0 / I.h, r);
+        cdg_rate_half<K, FLUX>(nb, hf, I.p0, taumax * (1.0 / I.h), r);
 
         // eq:RKCDG: out = c_{l0} u^n [+ accumulated earlier stages] + c_{ll} u^l + tau d_{ll} L(u^l)
         const RKStage rs = rk_stage(a.rk, l);
@@ -593,7 +604,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
 #pragma unroll
             for (int m = 0; m < K1; ++m) {
                 const double both = r[q][m] + pair_swap(r[q][m]);   // the two halves (a + b == b + a)
-                const double rate = both - inv_tm * own[q][m];
+                const double rate = inv_tm * (both - own[q][m]);
                 const double v = fma(td, rate, rs.cw * own[q][m]);
                 double o = v;
                 if (l > 0) {
@@ -624,7 +635,8 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
             double ubar[NC];
 #pragma unroll
             for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
-            const bool phys = F::physical(ubar, I.p0);
+            // a tolerated non-positive pressure (OECDG_FLAG_ALLOW_NEGATIVE_PRESSURE) leaves the density
+            const bool phys = (I.flags & OECDG_FLAG_ALLOW_NEGATIVE_PRESSURE) ? ubar[0] > 0.0 : F::physical(ubar, I.p0);
             if (hf == 0 && (!finite || !phys)) {
                 if (!finite) a.err[0] = 1;
                 if (!phys) a.err[1] = 1;
@@ -680,7 +692,7 @@ __device__ void final_tile(const StageArgs &a, int tile, double *smem, bool xwl)
                                          scratch, xwl);
         finish_stats<NC>(I, red, sig);
     }
-    load_tile<K, NC, T>(I, tl.i0, a.BC[bp] + I.offC, a.BD[bp] + I.offD, smem, xwl);
+    load_tile<K, NC, T, FLUX == 3>(I, tl.i0, a.BC[bp] + I.offC, a.BD[bp] + I.offD, smem, xwl);
     __syncthreads();
     if constexpr (FLUX == 3) {
         if (has_wall_ghost<K, NC, T>(I, tl.i0)) {

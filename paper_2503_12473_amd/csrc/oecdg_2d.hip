@@ -1,5 +1,6 @@
 // oecdg_2d.hip -- 2D RK-OECDG on periodic Cartesian primal and dual meshes,
-// tensor-product Q^k Legendre modes (k = 2), linear advection or Euler.
+// tensor-product Q^k Legendre modes or the total-degree P^k (k = 1, 2, 3),
+// linear advection or Euler.
 //
 // Per RK stage (eq:RKCDG) one tile kernel and one statistics kernel:
 //   k_reduce2d  one workgroup folds the per-tile partial statistics of the
@@ -13,8 +14,11 @@
 //               OE step of the previous stage in place (OEstep2D solved
 //               exactly, delta_K^m from the edge integrals of Sec. 2.2),
 //               evaluates the operator of eq:2D_H on its cells, takes the
-//               SSP-RK3 combination, writes the undamped stage output and
-//               the tile's partial statistics of it.
+//               RK combination (the c/d table of eq:RKCDG: SSP-RK3 by
+//               default, forward Euler, SSP-RK2 or classical RK4) and writes
+//               the undamped stage output;
+//   k_delta2d   the damping numerators and the tile's partial statistics of
+//               that output.
 // The same tile kernel, in other modes, damps a state without a stage (the
 // end of a run or of a single stage) or only computes statistics.
 //
@@ -160,10 +164,21 @@ struct Stage2Args {
     double *UC, *UD;              // damped u^n: written at stage 0 (write_u), read at stages 1, 2
     double *part;                 // [row][tile] partial statistics (k_delta2d)
     double *numC, *numD;          // damping numerators [m*NC + q][ny][nx]: written by k_delta2d, read by k_stage2d
+    double *AC, *AD;              // classical RK4: weighted sum of the damped inputs of stages 1 and 2
     const Stats2 *st;
     int *err;                     // [0] non-finite, [1] non-physical, [2] no admissible step
     int l, mode, damp, write_u;
+    RKStage rs;                   // c/d coefficients of stage l of the RK method (eq:RKCDG)
 };
+
+// Stage output of eq:RKCDG from the damped input s0, its rate Lv and (l > 0)
+// the damped u^n un and the accumulated earlier stages acc (classical RK4):
+//   c_{l0} u^n [+ acc] + c_{ll} s0 + tau d_{ll} L(s0)
+__device__ inline double rk_out(const RKStage &rs, int l, double s0, double Lv, double tau, double un, double acc) {
+    const double v = fma(tau * rs.d, Lv, rs.cw * s0);
+    if (l == 0) return v;
+    return (rs.acc_read ? rs.cn * un + acc : rs.cn * un) + v;
+}
 
 struct Red2Args {
     const double *part;
@@ -255,7 +270,7 @@ __device__ inline void stage_tile2d(double *tile, const double *inC, const doubl
 
 // Stage kernel: OE step of the previous stage on the staged input (from the
 // damping numerators of k_delta2d and sigma), then the operator of eq:2D_H
-// and the SSP-RK3 combination on the owned cells (stage mode), or only the
+// and the RK combination on the owned cells (stage mode), or only the
 // damped owned cells (final mode).
 // PK: the total-degree space P^K.  Modes with a + b > K are zero in every
 // state, so the unrolled loops skip them at compile time (kept()).
@@ -364,6 +379,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
     const double hx = a.hx, hy = a.hy;
     const double *UM = mesh == 0 ? a.UC : a.UD;
     double *OM = mesh == 0 ? a.outC : a.outD;
+    double *AM = mesh == 0 ? a.AC : a.AD;
     bool finite = true;
     if constexpr (NC == 4) {
         // lane q accumulates component q over all quadrants and edges; the
@@ -499,7 +515,7 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                     else Rq[n][t] -= x;
                 }
         }
-        // own part of the coupling, mass inverse, SSP-RK3
+        // own part of the coupling, mass inverse, RK combination
 #pragma unroll
         for (int i = 0; i < K1; ++i)
 #pragma unroll
@@ -509,11 +525,17 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                 const double s0 = town[e * NCELL + cell];
                 const double Lv = (Rq[i][j] - mass * itm * s0) / mass;
                 const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
-                const double v = s0 + tau * Lv;
-                double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
+                const double ac = (a.rs.acc_read && valid) ? AM[e * a.plane + gofs] : 0.0;
+                double o = rk_out(a.rs, a.l, s0, Lv, tau, un, ac);
                 if (!kept<K, PK>(i, j)) o = 0.0;
                 finite = finite && isfinite(o);
-                if (valid) OM[e * a.plane + gofs] = o;
+                if (valid) {
+                    OM[e * a.plane + gofs] = o;
+                    if (a.rs.ca != 0.0) {     // classical RK4: this stage's damped input joins the sum
+                        double *p = AM + e * a.plane + gofs;
+                        *p = a.rs.acc_first ? a.rs.ca * s0 : fma(a.rs.ca, s0, *p);
+                    }
+                }
             }
     } else {
         // one component: lane t takes quadrant t and edge t, the quad sums
@@ -653,10 +675,16 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
                     const double Lv = (quad_sum(R[q][i][j]) - mass * itm * s0) / mass;
                     if ((e & 3) == lane4) {
                         const double un = (a.l > 0 && valid) ? UM[e * a.plane + gofs] : 0.0;
-                        const double v = s0 + tau * Lv;
-                        double o = a.l == 0 ? v : (a.l == 1 ? 0.75 * un + 0.25 * v : (1.0 / 3.0) * un + (2.0 / 3.0) * v);
+                        const double ac = (a.rs.acc_read && valid) ? AM[e * a.plane + gofs] : 0.0;
+                        const double o = rk_out(a.rs, a.l, s0, Lv, tau, un, ac);
                         finite = finite && isfinite(o);
-                        if (valid) OM[e * a.plane + gofs] = o;
+                        if (valid) {
+                            OM[e * a.plane + gofs] = o;
+                            if (a.rs.ca != 0.0) {
+                                double *p = AM + e * a.plane + gofs;
+                                *p = a.rs.acc_first ? a.rs.ca * s0 : fma(a.rs.ca, s0, *p);
+                            }
+                        }
                     }
                 }
     }
@@ -984,11 +1012,38 @@ __global__ __launch_bounds__(RED2_NT) void k_reduce2d(Red2Args r) {
 
 namespace {
 
-constexpr int TX2 = 8, TY2 = 8;
+// Tiles of 8 x 8 primal cells for k = 1, 2; 4 x 4 for k = 3, whose 64
+// coefficients per cell would make an 8 x 8 tile with its halo overflow LDS.
+template <int K> struct Tile2 {
+    static constexpr int TX = K == 3 ? 4 : 8, TY = K == 3 ? 4 : 8;
+};
+constexpr int tile2(int k) { return k == 3 ? 4 : 8; }
+
+template <int K, int FLUX, bool PK>
+void *stage2d_fn(bool delta) {
+    constexpr int TX = Tile2<K>::TX, TY = Tile2<K>::TY;
+    return delta ? (void *)k_delta2d<K, FLUX, TX, TY, PK> : (void *)k_stage2d<K, FLUX, TX, TY, PK>;
+}
+
+template <int K>
+void *pick2_k(int flux, bool pk, bool delta) {
+    if (flux == OECDG_FLUX_EULER) return pk ? stage2d_fn<K, OECDG_FLUX_EULER, true>(delta) : stage2d_fn<K, OECDG_FLUX_EULER, false>(delta);
+    return pk ? stage2d_fn<K, OECDG_FLUX_ADVECTION, true>(delta) : stage2d_fn<K, OECDG_FLUX_ADVECTION, false>(delta);
+}
+
+void *pick2(int k, int flux, bool pk, bool delta) {
+    switch (k) {
+    case 1: return pick2_k<1>(flux, pk, delta);
+    case 2: return pick2_k<2>(flux, pk, delta);
+    default: return pick2_k<3>(flux, pk, delta);
+    }
+}
 
 struct Ext2D {
     int k, nc, flux, oe;
     int pk;                      // total-degree space P^k
+    int tx, ty;                  // primal cells per tile and direction
+    int rk, ns;                  // RK method (rk_stage) and its stages per step
     int nx, ny, ntx, nty, ntiles;
     double hx, hy, cfl;
     FPar2 fp;
@@ -997,6 +1052,7 @@ struct Ext2D {
     double *B[2] = {nullptr, nullptr};      // stage states, both meshes each
     double *num[2] = {nullptr, nullptr};    // damping numerators of B[i], both meshes each
     double *U = nullptr;
+    double *A = nullptr;         // classical RK4: accumulated damped inputs of stages 1 and 2 (both meshes)
     double *part[2] = {nullptr, nullptr};
     double *fold = nullptr;      // [row][nfold] first-level partials
     int nfold = 1, fold_per = 1;
@@ -1016,25 +1072,15 @@ Ext2D *ext(oecdg_handle *h) { return static_cast<Ext2D *>(handle_ext2d(h)); }
 hipError_t launch_tile(void *fn, const Ext2D &x, const Stage2Args &a, hipStream_t s) {
     Stage2Args copy = a;
     void *args[] = {&copy};
-    return hipLaunchKernel(fn, dim3(x.ntiles), dim3(8 * TX2 * TY2), args, 0, s);
+    return hipLaunchKernel(fn, dim3(x.ntiles), dim3(8 * x.tx * x.ty), args, 0, s);
 }
 
 hipError_t launch_stage2d(const Ext2D &x, const Stage2Args &a, hipStream_t s) {
-    void *fn = x.flux == OECDG_FLUX_EULER
-                   ? (x.pk ? (void *)k_stage2d<2, OECDG_FLUX_EULER, TX2, TY2, true>
-                           : (void *)k_stage2d<2, OECDG_FLUX_EULER, TX2, TY2, false>)
-                   : (x.pk ? (void *)k_stage2d<2, OECDG_FLUX_ADVECTION, TX2, TY2, true>
-                           : (void *)k_stage2d<2, OECDG_FLUX_ADVECTION, TX2, TY2, false>);
-    return launch_tile(fn, x, a, s);
+    return launch_tile(pick2(x.k, x.flux, x.pk, false), x, a, s);
 }
 
 hipError_t launch_delta2d(const Ext2D &x, const Stage2Args &a, hipStream_t s) {
-    void *fn = x.flux == OECDG_FLUX_EULER
-                   ? (x.pk ? (void *)k_delta2d<2, OECDG_FLUX_EULER, TX2, TY2, true>
-                           : (void *)k_delta2d<2, OECDG_FLUX_EULER, TX2, TY2, false>)
-                   : (x.pk ? (void *)k_delta2d<2, OECDG_FLUX_ADVECTION, TX2, TY2, true>
-                           : (void *)k_delta2d<2, OECDG_FLUX_ADVECTION, TX2, TY2, false>);
-    return launch_tile(fn, x, a, s);
+    return launch_tile(pick2(x.k, x.flux, x.pk, true), x, a, s);
 }
 
 // Fold r.part (per-tile partials) into the global scalars: first level into
@@ -1068,6 +1114,11 @@ Stage2Args stage_args(const Ext2D &x) {
     a.fp = x.fp;
     a.st = x.st;
     a.err = x.err;
+    if (x.A) {
+        a.AC = x.A;
+        a.AD = x.A + x.S1;
+    }
+    a.rs = rk_stage(x.rk, 0);
     return a;
 }
 
@@ -1133,8 +1184,11 @@ int create_2d(oecdg_handle *h, const oecdg_desc *d) {
     x->pk = d->space == 1;
     x->nx = (int)d->nx;
     x->ny = (int)d->ny;
-    x->ntx = (x->nx + TX2 - 1) / TX2;
-    x->nty = (x->ny + TY2 - 1) / TY2;
+    x->tx = x->ty = tile2(x->k);
+    x->rk = d->rk == 0 ? 3 : d->rk;
+    x->ns = rk_stages(x->rk);
+    x->ntx = (x->nx + x->tx - 1) / x->tx;
+    x->nty = (x->ny + x->ty - 1) / x->ty;
     x->ntiles = x->ntx * x->nty;
     x->hx = (d->xhi - d->xlo) / d->nx;
     x->hy = (d->yhi - d->ylo) / d->ny;
@@ -1151,6 +1205,7 @@ int create_2d(oecdg_handle *h, const oecdg_desc *d) {
         HIPCHK2(h, hipMalloc(&x->part[i], sizeof(double) * nrow * x->ntiles));
     }
     HIPCHK2(h, hipMalloc(&x->U, sizeof(double) * 2 * x->S1));
+    if (x->rk == 4) HIPCHK2(h, hipMalloc(&x->A, sizeof(double) * 2 * x->S1));
     x->nfold = x->ntiles < FOLD2_MAXB ? x->ntiles : FOLD2_MAXB;
     x->fold_per = (x->ntiles + x->nfold - 1) / x->nfold;
     HIPCHK2(h, hipMalloc(&x->fold, sizeof(double) * nrow * x->nfold));
@@ -1170,6 +1225,7 @@ void destroy_2d(oecdg_handle *h) {
         if (x->part[i]) (void)hipFree(x->part[i]);
     }
     if (x->U) (void)hipFree(x->U);
+    if (x->A) (void)hipFree(x->A);
     if (x->fold) (void)hipFree(x->fold);
     if (x->st) (void)hipFree(x->st);
     if (x->st_h) (void)hipHostFree(x->st_h);
@@ -1209,6 +1265,7 @@ int stage_2d(oecdg_handle *h, int stage, double dt, double tau_max, const double
     Stage2Args a = stage_args(x);
     a.mode = M2_STAGE;
     a.l = stage;
+    a.rs = rk_stage(x.rk, stage);
     a.damp = 0;
     a.write_u = 0;
     a.inC = stage == 0 ? uCn : uCl;
@@ -1259,8 +1316,8 @@ int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
     while (nsteps < 0 || n < nsteps) {
         const long long m = nsteps < 0 ? chunk : std::min<long long>(chunk, nsteps - n);
         for (long long j = 0; j < m; ++j)
-            for (int l = 0; l < 3; ++l) {
-                const long long g = 3 * (n + j) + l;
+            for (int l = 0; l < x.ns; ++l) {
+                const long long g = (long long)x.ns * (n + j) + l;
                 const int ib = (int)(g & 1), ob = (int)((g + 1) & 1);
                 Red2Args r = red_args(x, x.part[ib], l == 0 ? R2_STEP : R2_STAGE);
                 r.t_end = t_end;
@@ -1269,6 +1326,7 @@ int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
                 Stage2Args a = stage_args(x);
                 a.mode = M2_STAGE;
                 a.l = l;
+                a.rs = rk_stage(x.rk, l);
                 a.damp = x.oe && x.k > 0 && !(n + j == 0 && l == 0);
                 a.write_u = l == 0;
                 a.inC = x.B[ib];
@@ -1288,7 +1346,7 @@ int run_2d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
         if (x.st_h->done) break;
     }
     const long long N = x.st_h->nexec + x.st_h->pending;   // executed steps
-    const int fb = (int)(N & 1);
+    const int fb = (int)((x.ns * N) & 1);                  // buffer of the last stage's output
     Red2Args r = red_args(x, x.part[fb], R2_FINAL);
     r.t_end = t_end;
     HIPCHK2(h, launch_reduce2d(x, r, s));

@@ -24,6 +24,7 @@ struct oecdg_handle {
 
     // 1D batch bookkeeping
     std::vector<Inst1D> inst_h;
+    std::vector<char> inflow_set;   // oecdg_set_inflow was called for the instance
     std::vector<Tile1D> tiles_h;
     struct Group {
         int k, tbeg, tend;
@@ -112,11 +113,13 @@ int oecdg::validate(const oecdg_desc &d, const char *&why) {   // why: a static 
     if (d.dim != 1 && d.dim != 2) return why = "dim must be 1 or 2", OECDG_EINVAL;
     if (d.rk < 0 || d.rk > 4) return why = "rk must be 0 (SSP-RK3), 1, 2, 3 or 4", OECDG_EINVAL;
     if (d.space != 0 && d.space != 1) return why = "space must be 0 (Q^k) or 1 (P^k)", OECDG_EINVAL;
-    if (d.reserved != 0) return why = "reserved must be 0", OECDG_EINVAL;
+    if (d.flags & ~OECDG_FLAG_ALLOW_NEGATIVE_PRESSURE) return why = "unknown flag", OECDG_EINVAL;
     if (d.flux < 0 || d.flux > 2) return why = "unknown flux", OECDG_EINVAL;
-    if (d.bc < 0 || d.bc > 2) return why = "unknown boundary condition", OECDG_EINVAL;
+    if (d.bc < 0 || d.bc > 3) return why = "unknown boundary condition", OECDG_EINVAL;
     if (d.bc == OECDG_BC_REFLECTIVE && d.flux != OECDG_FLUX_EULER)
         return why = "reflective walls need the Euler flux", OECDG_EUNSUPPORTED;
+    if (d.bc == OECDG_BC_INFLOW && d.flux != OECDG_FLUX_EULER)
+        return why = "inflow boundaries need the Euler flux", OECDG_EUNSUPPORTED;
     if (!(d.xhi > d.xlo)) return why = "xhi must exceed xlo", OECDG_EINVAL;
     if (!(d.cfl > 0.0)) return why = "cfl must be positive", OECDG_EINVAL;
     if (d.flux == OECDG_FLUX_EULER && !(d.flux_param[0] > 1.0)) return why = "Euler needs gamma > 1", OECDG_EINVAL;
@@ -125,10 +128,10 @@ int oecdg::validate(const oecdg_desc &d, const char *&why) {   // why: a static 
         if (d.nx < 2 || d.nx > (1LL << 30)) return why = "1D nx out of range", OECDG_EINVAL;
         if (d.ny != 1 && d.ny != 0) return why = "1D ny must be 1", OECDG_EINVAL;
     } else {
-        if (d.k != 2) return why = "2D supports the tensor Q2 space only (k = 2)", OECDG_EUNSUPPORTED;
+        if (d.k < 1 || d.k > MAXK) return why = "2D degree must be 1..3", OECDG_EUNSUPPORTED;
         if (d.flux == OECDG_FLUX_BURGERS) return why = "2D Burgers is not implemented", OECDG_EUNSUPPORTED;
         if (d.bc != OECDG_BC_PERIODIC) return why = "2D supports periodic boundaries only", OECDG_EUNSUPPORTED;
-        if (d.rk != 0 && d.rk != 3) return why = "2D runs SSP-RK3 only", OECDG_EUNSUPPORTED;
+        if (d.flags != 0) return why = "descriptor flags are 1D only", OECDG_EUNSUPPORTED;
         if (d.nx < 2 || d.ny < 2 || d.nx > 65536 || d.ny > 65536) return why = "2D nx, ny out of range", OECDG_EINVAL;
         if (!(d.yhi > d.ylo)) return why = "yhi must exceed ylo", OECDG_EINVAL;
     }
@@ -159,6 +162,7 @@ Inst1D oecdg::make_inst(const oecdg_desc &e) {
     I.cfl = e.cfl;
     I.p0 = e.flux_param[0];
     I.oe = e.oe;
+    I.flags = e.flags;
     return I;
 }
 
@@ -453,6 +457,9 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
            int64_t *steps_out) {
     if (nsteps < 0 && !(t_end < INFINITY)) return fail(h, OECDG_EINVAL, "run needs a finite t_end or nsteps >= 0");
     if (!(t_end > 0.0)) return fail(h, OECDG_EINVAL, "t_end must be positive");
+    for (int b = 0; b < h->nbatch; ++b)
+        if (h->inst_h[b].bc == OECDG_BC_INFLOW && !h->inflow_set[b])
+            return fail(h, OECDG_EINVAL, "inflow instance " + std::to_string(b) + " has no ghost states (oecdg_set_inflow)");
     StageArgs a = base_args(h);
     a.t_end = t_end;
     a.dt_fixed = dt_fixed > 0.0 ? dt_fixed : 0.0;
@@ -801,6 +808,7 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
         }
     }
     int rc = OECDG_OK;
+    h->rk = d[0].rk == 0 ? 3 : d[0].rk;
     if (h->dim == 2) {
         rc = oecdg::create_2d(h, d);
         if (rc != OECDG_OK) {
@@ -812,8 +820,9 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
         return OECDG_OK;
     }
     h->flux = d[0].flux;
-    for (int b = 0; b < nbatch; ++b)       // kernels with the wall-ghost code only where an instance has walls
-        if (d[b].bc == OECDG_BC_REFLECTIVE) h->flux = 3;
+    for (int b = 0; b < nbatch; ++b)       // kernels with the ghost code only where an instance has walls or inflow
+        if (d[b].bc == OECDG_BC_REFLECTIVE || d[b].bc == OECDG_BC_INFLOW) h->flux = 3;
+    h->inflow_set.assign(nbatch, 0);
     h->rk = d[0].rk == 0 ? 3 : d[0].rk;
     h->offC.assign(nbatch + 1, 0);
     h->offD.assign(nbatch + 1, 0);
@@ -910,6 +919,21 @@ int oecdg_set_option(oecdg_handle *h, int32_t key, int64_t value) {
     return fail(h, OECDG_EINVAL, "unknown option");
 }
 
+int oecdg_set_inflow(oecdg_handle *h, int32_t instance, const double *left, const double *right) {
+    if (!h || !left || !right) return OECDG_EINVAL;
+    if (h->dim != 1 || instance < 0 || instance >= h->nbatch) return fail(h, OECDG_EINVAL, "instance out of range");
+    Inst1D &I = h->inst_h[instance];
+    if (I.bc != OECDG_BC_INFLOW) return fail(h, OECDG_EINVAL, "the instance has no inflow boundaries");
+    for (int q = 0; q < I.nc; ++q) {
+        I.gin[0][q] = left[q];
+        I.gin[1][q] = right[q];
+    }
+    HIPCHK(h, hipMemcpy(h->inst_d + instance, &I, sizeof(Inst1D), hipMemcpyHostToDevice));
+    h->inflow_set[instance] = 1;
+    drop_graphs(h);                          // single-instance graphs hold the instance in their arguments
+    return OECDG_OK;
+}
+
 int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out) {
     if (!h || !uC || !uD || !dt_out) return OECDG_EINVAL;
     if (h->dim != 1) {
@@ -937,9 +961,9 @@ int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out
 int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max, const double *uC_n, const double *uD_n,
                 const double *uC_l, const double *uD_l, double *uC_out, double *uD_out) {
     if (!h || !uC_n || !uD_n || !uC_out || !uD_out) return OECDG_EINVAL;
-    const int ns = h->dim == 1 ? rk_stages(h->rk) : 3;
+    const int ns = rk_stages(h->rk);
     if (stage < 0 || stage >= ns) return fail(h, OECDG_EINVAL, "stage out of range for the RK method");
-    if (h->dim == 1 && h->rk == 4 && stage == 3)
+    if (h->rk == 4 && stage == 3)
         return fail(h, OECDG_EUNSUPPORTED, "the last stage of classical RK4 reads the earlier stages");
     if (!(dt > 0.0) || !(tau_max > 0.0)) return fail(h, OECDG_EINVAL, "dt and tau_max must be positive");
     if (stage > 0 && (!uC_l || !uD_l)) return fail(h, OECDG_EINVAL, "stages after the first need u_l");

@@ -38,10 +38,12 @@ template <> struct FluxT<2> {          // Euler (rho, m, E), ideal gas
         o[1] = w[1] * v + p;
         o[2] = (w[2] + p) * v;
     }
+    // |v| + sqrt(gamma |p| / rho): |v| + c for every physical state, finite
+    // where a tolerated non-positive pressure sits at a cell average
     __device__ static inline double speed(const double *u, double g) {
         const double v = u[1] / u[0];
         const double p = (g - 1.0) * (u[2] - 0.5 * u[1] * v);
-        return fabs(v) + sqrt(g * p / u[0]);
+        return fabs(v) + sqrt(g * fabs(p) / u[0]);
     }
     __device__ static inline bool physical(const double *u, double g) {
         if (!(u[0] > 0.0)) return false;

@@ -29,7 +29,8 @@ struct Inst1D {
     int oe;
     int tail;                // the last tile also updates dual cell np (outflow/walls, np a multiple of T)
     int npart;               // partial-statistics columns [tile0, tile0 + npart): ntiles, plus one with a tail
-    int pad;
+    int flags;               // OECDG_FLAG_* of the descriptor
+    double gin[2][3];        // inflow boundaries: cell averages of the ghost cells left of 0 and right of np-1
 };
 
 // A tile: primal cells [i0, i0 + T) and dual cells [i0, i0 + T) of instance inst.

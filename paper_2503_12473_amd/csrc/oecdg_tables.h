@@ -89,6 +89,74 @@ constexpr Gauss<Q> gauss() {
     return g;
 }
 
+// Exact rational arithmetic for the overlap integrals (small integers only).
+struct Rat {
+    long long p, q;      // p / q, q > 0, reduced
+};
+
+constexpr long long cgcd(long long a, long long b) {
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+        const long long t = a % b;
+        a = b;
+        b = t;
+    }
+    return a ? a : 1;
+}
+constexpr Rat rat(long long p, long long q) {
+    if (q < 0) p = -p, q = -q;
+    const long long g = cgcd(p, q);
+    return Rat{p / g, q / g};
+}
+constexpr Rat radd(Rat a, Rat b) { return rat(a.p * b.q + b.p * a.q, a.q * b.q); }
+constexpr Rat rmul(Rat a, Rat b) { return rat(a.p * b.p, a.q * b.q); }
+
+// Monomial coefficients of P_n (n <= 3), P_n(x) = sum_j c[j] x^j, from
+// (n+1) P_{n+1} = (2n+1) x P_n - n P_{n-1}.
+struct Poly {
+    Rat c[8];
+};
+constexpr Poly legpoly(int n) {
+    Poly a{}, b{};
+    for (int j = 0; j < 8; ++j) a.c[j] = b.c[j] = Rat{0, 1};
+    a.c[0] = Rat{1, 1};                  // P_0
+    if (n == 0) return a;
+    b.c[1] = Rat{1, 1};                  // P_1
+    for (int m = 1; m < n; ++m) {
+        Poly nx{};
+        for (int j = 0; j < 8; ++j) nx.c[j] = Rat{0, 1};
+        for (int j = 0; j < 7; ++j) nx.c[j + 1] = rmul(b.c[j], rat(2 * m + 1, m + 1));
+        for (int j = 0; j < 8; ++j) nx.c[j] = radd(nx.c[j], rmul(a.c[j], rat(-m, m + 1)));
+        a = b;
+        b = nx;
+    }
+    return b;
+}
+// P_n(x - 1) in monomials of x.
+constexpr Poly shifted(const Poly &p) {
+    Poly r{};
+    for (int j = 0; j < 8; ++j) r.c[j] = Rat{0, 1};
+    for (int j = 0; j < 8; ++j) {
+        long long binom = 1;             // C(j, i) (-1)^(j-i) x^i
+        for (int i = j; i >= 0; --i) {
+            const long long sg = ((j - i) & 1) ? -1 : 1;
+            r.c[i] = radd(r.c[i], rmul(p.c[j], Rat{sg * binom, 1}));
+            binom = binom * i / (j - i + 1);
+        }
+    }
+    return r;
+}
+// int_0^1 P_n(x - 1) P_m(x) dx, exactly.
+constexpr Rat overlap(int m, int n) {
+    const Poly a = legpoly(m), b = shifted(legpoly(n));
+    Rat s{0, 1};
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j + i < 8; ++j)
+            if (a.c[i].p != 0 && b.c[j].p != 0) s = radd(s, rmul(rmul(a.c[i], b.c[j]), rat(1, i + j + 1)));
+    return s;
+}
+
 }  // namespace ct
 
 // Tables of degree K.
@@ -102,6 +170,8 @@ struct Tab {
     double D1[K1][K1];     // d-th derivative of P_n at xi = 1: [d][n]
     double SP[NSP][K1];    // P_n at the sigma sample points (edges and both halves' nodes)
     double C[K1];          // (2m+1) 2^m / ((2K-1) m!)
+    double OV[K1][K1];     // int_0^1 P_n(xi - 1) P_m(xi) dxi, [m][n]: the right neighbour's mode n
+                           // projected on the test function P_m over the right half (exact rationals)
 };
 
 template <int K>
@@ -140,6 +210,11 @@ constexpr Tab<K> make_tab() {
         }
         t.C[m] = K > 0 ? (2.0 * m + 1.0) * pow2 / ((2.0 * K - 1.0) * fact) : 0.0;
     }
+    for (int m = 0; m <= K; ++m)
+        for (int n = 0; n <= K; ++n) {
+            const ct::Rat r = ct::overlap(m, n);
+            t.OV[m][n] = (double)r.p / (double)r.q;
+        }
     return t;
 }
 

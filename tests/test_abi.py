@@ -45,7 +45,7 @@ def test_state_size_host_only():
 @pytest.mark.parametrize("field,value,code", [
     ("k", 4, _lib.EINVAL), ("nx", 1, _lib.EINVAL), ("cfl", 0.0, _lib.EINVAL), ("flux", 7, _lib.EINVAL),
     ("rk", 5, _lib.EINVAL), ("rk", -1, _lib.EINVAL), ("dim", 3, _lib.EINVAL), ("space", 2, _lib.EINVAL),
-    ("reserved", 1, _lib.EINVAL),
+    ("flags", 2, _lib.EINVAL), ("bc", 4, _lib.EINVAL),
 ])
 def test_invalid_descriptors_are_rejected_before_any_gpu_work(field, value, code):
     L = _lib.lib()
@@ -59,12 +59,17 @@ def test_invalid_descriptors_are_rejected_before_any_gpu_work(field, value, code
     assert L.oecdg_state_size(C.byref(d), C.byref(npr), C.byref(ndu)) == code
 
 
-def test_2d_degrees_other_than_two_are_unsupported():
+def test_2d_degrees():
+    """2D handles take k = 1, 2, 3 (the paper's P^k and the tensor Q^k); k = 0 has
+    no damping and no 2D kernel."""
     L = _lib.lib()
-    p2 = inputs.Problem2D(k=1, nc=1, flux=inputs.FLUX_ADVECTION, nx=8, ny=8, xlo=0, xhi=1, ylo=0, yhi=1)
-    d2 = make_desc(p2, 0.3)
     npr, ndu = C.c_int64(), C.c_int64()
-    assert L.oecdg_state_size(C.byref(d2), C.byref(npr), C.byref(ndu)) == _lib.EUNSUPPORTED
+    for k, code in ((0, _lib.EUNSUPPORTED), (1, 0), (2, 0), (3, 0)):
+        p2 = inputs.Problem2D(k=k, nc=1, flux=inputs.FLUX_ADVECTION, nx=8, ny=8, xlo=0, xhi=1, ylo=0, yhi=1)
+        d2 = make_desc(p2, 0.3)
+        assert L.oecdg_state_size(C.byref(d2), C.byref(npr), C.byref(ndu)) == code, k
+        if code == 0:
+            assert npr.value == ndu.value == (k + 1) ** 2 * 64
 
 
 def test_descriptor_layout_matches_the_header():
@@ -72,11 +77,12 @@ def test_descriptor_layout_matches_the_header():
     assert _lib.Desc.rk.offset == 92 and _lib.Desc.space.offset == 96
 
 
-def test_2d_runs_ssp_rk3_only():
+def test_2d_rk_methods():
+    """2D handles take every RK method of eq:RKCDG that 1D takes; rk 5 is refused."""
     L = _lib.lib()
     p2 = inputs.Problem2D(k=2, nc=1, flux=inputs.FLUX_ADVECTION, nx=8, ny=8, xlo=0, xhi=1, ylo=0, yhi=1)
     npr, ndu = C.c_int64(), C.c_int64()
-    for rk, code in ((0, 0), (3, 0), (1, _lib.EUNSUPPORTED), (2, _lib.EUNSUPPORTED), (4, _lib.EUNSUPPORTED)):
+    for rk, code in ((0, 0), (1, 0), (2, 0), (3, 0), (4, 0), (5, _lib.EINVAL)):
         d2 = make_desc(p2, 0.3, rk=rk)
         assert L.oecdg_state_size(C.byref(d2), C.byref(npr), C.byref(ndu)) == code, rk
 
@@ -107,3 +113,4 @@ def test_missing_library_fails_loudly(monkeypatch):
     prob, _, _ = inputs.advection_sine(16, 2)
     with pytest.raises(ImportError):
         api.OECDG(prob, 0.2)
+

@@ -97,21 +97,24 @@ def _uniform_density_state(prob):
     return np.ascontiguousarray(uC), np.ascontiguousarray(uD)
 
 
+@pytest.mark.parametrize("k", [1, 2, 3])
 @pytest.mark.parametrize("bc", [BC_OUTFLOW, BC_PERIODIC])
-def test_zero_sigma_component_is_skipped(bc):
+def test_zero_sigma_component_is_skipped(bc, k):
     """sigma_q = 0 (Sec. 2.2: delta_K^m is zero when the component equals its
     mean everywhere; with several components the max runs over the others).
-    P1 Euler, N = 300 (ragged tiles): the undamped output of the first stage has
-    an exactly uniform density on both meshes in the oracle, and the library
-    must skip that component as the oracle does: a single stage and two full
-    steps (the second step's first stage damps that output) against the oracle."""
-    prob = Problem1D(k=1, nc=3, flux=FLUX_EULER, bc=bc, n=300, xlo=0.0, xhi=1.0)
+    Euler, N = 300 (ragged tiles): the undamped output of the first stage has
+    an exactly uniform density on both meshes in the oracle and in the library
+    (whose coupling integrates the overlap exactly, so a constant with no flux
+    has exactly zero rate), and the library must skip that component as the
+    oracle does: a single stage and two full steps (the second step's first
+    stage damps that output) against the oracle."""
+    prob = Problem1D(k=k, nc=3, flux=FLUX_EULER, bc=bc, n=300, xlo=0.0, xhi=1.0)
     uC, uD = _uniform_density_state(prob)
     tau = 0.15 * prob.h / ora.max_wavespeed1d(prob, uC, uD)
     hC, hD = ora.ssprk3_stage1d(prob, 0, tau, tau, uC, uD, uC, uD, oe=False)
     _, sig = ora.stats1d(prob, hC, hD)
     assert sig[0, 0] == 0.0 and sig[1, 0] == 0.0 and np.all(sig[:, 1:] > 0.0)
-    print(f"[sigma0] bc={bc} stage 0", flush=True)
+    print(f"[sigma0] bc={bc} k={k} stage 0", flush=True)
     with OECDG(prob, 0.15) as s:
         g = (to_device(uC), to_device(uD))
         oC, oD = s.stage(0, tau, tau, g[0], g[1])

@@ -11,7 +11,7 @@ import os
 import numpy as np
 import pytest
 
-from tests.parity import rel
+from tests.parity import rel, rel_per_component
 
 from paper_2503_12473_amd import inputs
 from paper_2503_12473_amd.api import OECDG, to_device
@@ -61,6 +61,24 @@ def test_riemann_run_matches_golden(k, T, bar):
     e = _rel(oC[..., ::st], oD[..., ::st], g["uC"], g["uD"])
     print(f"[golden] k={k} T={T:g} steps={n} rel err {e:.3e} (bar {bar:.0e})", flush=True)
     assert e <= bar
+
+
+@pytest.mark.timeout(300)
+def test_paper_blast_waves_match_golden():
+    """The paper's two-blast-wave example (Sec. 4): rho = 1, p = 1000, 0.01, 100,
+    reflective walls, P2, 960 cells, CFL 0.3, to t = 0.038 (5140 steps)."""
+    g = _golden("blast_waves_N960_k2_T0.038.npz")
+    prob, uC, uD = inputs.euler_blast_waves(960, 2)
+    print("[golden] blast waves P2 N=960 T=0.038", flush=True)
+    with OECDG(prob, 0.3) as s:
+        a, b = to_device(uC), to_device(uD)
+        t, n = s.run(a, b, t_end=0.038)
+        oC, oD = a.cpu().numpy().reshape(uC.shape), b.cpu().numpy().reshape(uD.shape)
+    st = int(g["stride"])
+    assert n == int(g["steps"]) and t == float(g["t"])
+    e = rel_per_component(oC[..., ::st], oD[..., ::st], g["uC"], g["uD"])
+    print(f"[golden] blast waves steps={n} rel err per component {e}", flush=True)
+    assert e.max() <= TOL
 
 
 @pytest.mark.timeout(300)
