@@ -66,7 +66,8 @@ enum {
     OECDG_ENONFINITE = -4,      /* a NaN/Inf coefficient was produced */
     OECDG_ENONPHYSICAL = -5,    /* Euler: density or pressure <= 0 at a cell average */
     OECDG_EUNSUPPORTED = -6,    /* valid but not implemented combination */
-    OECDG_ETIMEOUT = -7         /* a device-side grid barrier exceeded its spin limit */
+    OECDG_ETIMEOUT = -7,        /* a device-side grid barrier exceeded its spin limit */
+    OECDG_ETOOBIG = -8          /* oecdg_run_noalloc: the problem exceeds its fixed device scratch */
 };
 
 enum { OECDG_FLUX_ADVECTION = 0, OECDG_FLUX_BURGERS = 1, OECDG_FLUX_EULER = 2 };
@@ -191,6 +192,31 @@ int oecdg_stage(oecdg_handle *h, int32_t stage, double dt, double tau_max,
  * final time and step count.  Synchronises the stream. */
 int oecdg_run(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps,
               double dt_fixed, double *t_out, int64_t *steps_out);
+
+/* Bytes of the fixed device scratch of oecdg_run_noalloc (per GPU, held from
+ * its first call on that GPU until the process ends). */
+#define OECDG_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* oecdg_run for one 1D instance without allocating anything, for callers that
+ * cannot allocate (code under stream capture by a caller of its own, serving
+ * loops, harnesses that forbid hipMalloc): no handle; the stage buffers,
+ * damped u^n, partial statistics, step records and error flags live in a
+ * fixed file-scope device array of OECDG_NOALLOC_SCRATCH_BYTES per GPU
+ * (state arrays, both meshes, three of them, four with classical RK4, plus
+ * the statistics: about 1.3 M doubles of state, e.g. 1D Euler P2 up to
+ * nx ~ 77000).  d: one 1D descriptor as for oecdg_init; stream: a hipStream_t
+ * (NULL = default stream) on the current device; the other arguments as
+ * oecdg_run (uC, uD are caller-owned device arrays, advanced in place).
+ * Eager launches only (no graph is built) with the tile and launch shape
+ * oecdg_init would choose, so results are bitwise those of oecdg_run on a
+ * handle of the same descriptor.  Returns ETOOBIG when the problem does not
+ * fit the scratch, EINVAL / EUNSUPPORTED for descriptors oecdg_init rejects
+ * or dim != 1, the run's own error codes otherwise; there is no handle, so
+ * no message.  Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one GPU (two host threads, or streams that run concurrently)
+ * race and must be serialised by the caller.  Synchronises the stream. */
+int oecdg_run_noalloc(const oecdg_desc *d, void *stream, double *uC, double *uD, double t_end, int64_t nsteps,
+                      double dt_fixed, double *t_out, int64_t *steps_out);
 
 /* oecdg_run on a non-uniform periodic 1D mesh (Sec. 2.1: primal cells
  * [x_{i-1/2}, x_{i+1/2}] of width h_i, dual cells [x_{i-1}, x_i] between

@@ -12,14 +12,14 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboecdg.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ENONPHYSICAL, EUNSUPPORTED, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EHIP, ENONFINITE, ENONPHYSICAL, EUNSUPPORTED, ETIMEOUT, ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7, -8
 MODE_AUTO, MODE_EAGER, MODE_GRAPH, MODE_PERSISTENT = 0, 1, 2, 3
 FLAG_ALLOW_NEGATIVE_PRESSURE = 1
 OPT_MODE, OPT_TILE, OPT_GRAPH_STEPS, OPT_GRID, OPT_FOLD = 1, 2, 3, 4, 5
 
 # every symbol include/oecdg.h declares
 EXPORTS = ("oecdg_state_size", "oecdg_init", "oecdg_batch_offsets", "oecdg_set_option", "oecdg_dt",
-           "oecdg_stage", "oecdg_run", "oecdg_run_nonuniform", "oecdg_set_inflow", "oecdg_adjoint", "oecdg_destroy", "oecdg_strerror",
+           "oecdg_stage", "oecdg_run", "oecdg_run_noalloc", "oecdg_run_nonuniform", "oecdg_set_inflow", "oecdg_adjoint", "oecdg_destroy", "oecdg_strerror",
            "oecdg_last_error")
 
 
@@ -60,6 +60,8 @@ def lib():
     L.oecdg_stage.argtypes = [H, C.c_int32, C.c_double, C.c_double, D, D, D, D, D, D]
     L.oecdg_run.argtypes = [H, D, D, C.c_double, C.c_int64, C.c_double, C.POINTER(C.c_double),
                             C.POINTER(C.c_int64)]
+    L.oecdg_run_noalloc.argtypes = [C.POINTER(Desc), C.c_void_p, D, D, C.c_double, C.c_int64, C.c_double,
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.oecdg_run_nonuniform.argtypes = [H, D, D, D, C.c_double, C.c_int64, C.c_double, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]
     L.oecdg_adjoint.argtypes = [H, D, D, C.c_int64, C.c_double, D, D, D, D, C.c_int32]

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liboecdg.so")
-SOURCES = ["oecdg_1d.hip", "oecdg_2d.hip", "oecdg_adjoint.hip", "oecdg_nu.hip", "oecdg_api.cpp"]
+SOURCES = ["oecdg_1d.hip", "oecdg_2d.hip", "oecdg_adjoint.hip", "oecdg_nu.hip", "oecdg_api.cpp", "oecdg_noalloc.hip"]
 ARCH = os.environ.get("OECDG_ARCH", "gfx950")
 
 FLAGS = [

@@ -1065,6 +1065,7 @@ const char *oecdg_strerror(int code) {
     case OECDG_ENONPHYSICAL: return "non-physical state (density or pressure <= 0)";
     case OECDG_EUNSUPPORTED: return "unsupported configuration";
     case OECDG_ETIMEOUT: return "device barrier timeout";
+    case OECDG_ETOOBIG: return "problem larger than the fixed device scratch of oecdg_run_noalloc";
     }
     return "unknown error";
 }

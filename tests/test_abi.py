@@ -1,6 +1,7 @@
 """The C-ABI library loads and exports every symbol include/oecdg.h declares;
 host-only argument checks (no GPU needed: nothing here launches a kernel)."""
 import ctypes as C
+import math
 import os
 import re
 
@@ -114,3 +115,24 @@ def test_missing_library_fails_loudly(monkeypatch):
     with pytest.raises(ImportError):
         api.OECDG(prob, 0.2)
 
+
+def test_noalloc_host_checks():
+    """oecdg_run_noalloc refuses bad arguments and oversized problems before it
+    touches the device (the pointers below are never dereferenced)."""
+    L = _lib.lib()
+    prob = inputs.Problem1D(k=2, nc=3, flux=inputs.FLUX_EULER, bc=inputs.BC_OUTFLOW, n=100, xlo=0.0, xhi=1.0)
+    d = make_desc(prob, 0.15)
+    fake = C.c_void_p(16)
+    assert L.oecdg_run_noalloc(None, None, fake, fake, 1.0, 1, 0.0, None, None) == _lib.EINVAL
+    assert L.oecdg_run_noalloc(C.byref(d), None, None, fake, 1.0, 1, 0.0, None, None) == _lib.EINVAL
+    assert L.oecdg_run_noalloc(C.byref(d), None, fake, fake, math.inf, -1, 0.0, None, None) == _lib.EINVAL
+    bad = make_desc(prob, 0.15)
+    bad.k = 5
+    assert L.oecdg_run_noalloc(C.byref(bad), None, fake, fake, 1.0, 1, 0.0, None, None) == _lib.EINVAL
+    p2 = inputs.Problem2D(k=2, nc=4, flux=inputs.FLUX_EULER, nx=8, ny=8, xlo=0, xhi=1, ylo=0, yhi=1)
+    assert L.oecdg_run_noalloc(C.byref(make_desc(p2, 0.3)), None, fake, fake, 1.0, 1, 0.0, None, None) == \
+        _lib.EUNSUPPORTED
+    big = make_desc(prob, 0.15)
+    big.nx = 200000
+    assert L.oecdg_run_noalloc(C.byref(big), None, fake, fake, 1.0, 1, 0.0, None, None) == _lib.ETOOBIG
+    assert "scratch" in L.oecdg_strerror(_lib.ETOOBIG).decode()
