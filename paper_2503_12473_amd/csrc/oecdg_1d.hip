@@ -770,7 +770,10 @@ __global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_stage(Sta
 // reduced from k_fold (one fixed-order reduction per instance and stage)
 // instead of every workgroup reducing all of its instance's partial columns.
 template <int KM, int FLUX, int T>
-__global__ __launch_bounds__(nthreads(T)) void k_stage_folded(StageArgs a) {
+#ifndef OECDG_FOLDED_WAVES
+#define OECDG_FOLDED_WAVES 1
+#endif
+__global__ __launch_bounds__(nthreads(T), OECDG_FOLDED_WAVES) void k_stage_folded(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
