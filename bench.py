@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--tile", type=int, default=0, help="primal cells per workgroup (0: library default)")
     ap.add_argument("--fold", type=int, default=0,
                     help="statistics reduction of the headline run (0 library choice, 1 in-kernel, 2 fold kernel)")
+    ap.add_argument("--batched-steps", type=int, default=BATCH_STEPS, help="steps of the batched runs")
+    ap.add_argument("--batched-repeats", type=int, default=5, help="timed repetitions of the batched runs")
+    ap.add_argument("--no-loop", action="store_true", help="skip the per-instance loop the batched form is compared with")
     ap.add_argument("--batched-fold", type=int, default=0,
                     help="statistics reduction of the batched runs (0 library choice, 1 in-kernel, 2 fold kernel)")
     ap.add_argument("--repeats", type=int, default=5, help="timed repetitions (median reported)")
@@ -101,7 +104,7 @@ def profile_2d():
     return meta if meta.get("source_sha256") == h.hexdigest() else {}
 
 
-def batched_bench(k_fixed=None, fold=0):
+def batched_bench(k_fixed=None, fold=0, steps=BATCH_STEPS, repeats=5, loop_baseline=True):
     """Batched form: 512 independent 1D Euler Riemann instances (seed 0: N ~
     U{128..8192}, k ~ U{1,2,3} or k = k_fixed, seeded states), BATCH_STEPS steps
     each with its own CFL step, advanced together (graph-captured stages: a
@@ -126,7 +129,7 @@ def batched_bench(k_fixed=None, fold=0):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        solver.run(a, b, t_end=math.inf, nsteps=BATCH_STEPS)
+        solver.run(a, b, t_end=math.inf, nsteps=steps)
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3
@@ -140,16 +143,16 @@ def batched_bench(k_fixed=None, fold=0):
         a, b = icC.clone(), icD.clone()
         solver.run(a, b, t_end=math.inf, nsteps=20)
         walls = []
-        for _ in range(5):
+        for _ in range(max(1, repeats)):
             a.copy_(icC)
             b.copy_(icD)
             torch.cuda.synchronize()
             walls.append(timed(solver, a, b))
-        wall = sorted(walls)[2]                               # median of 5
-    batched = sum(dofs) * BATCH_STEPS / wall
+        wall = sorted(walls)[len(walls) // 2]                 # median
+    batched = sum(dofs) * steps / wall
     loop_wall, loop_dofs = 0.0, 0
     sample = [round(i * (BATCH_COUNT - 1) / (LOOP_SAMPLE - 1)) for i in range(LOOP_SAMPLE)]
-    for i in sample:
+    for i in (sample if loop_baseline else []):
         p, (uC, uD) = probs[i], states[i]
         with OECDG(p, CFL, stream=stream) as solver:
             solver.set_option(_lib.OPT_TILE, tile)
@@ -157,11 +160,11 @@ def batched_bench(k_fixed=None, fold=0):
             solver.run(a.clone(), b.clone(), t_end=math.inf, nsteps=20)
             loop_wall += timed(solver, a, b)
             loop_dofs += p.dofs()
-    loop = loop_dofs * BATCH_STEPS / loop_wall
+    loop = loop_dofs * steps / loop_wall if loop_wall > 0 else None
     mean_all = sum(dofs) / len(dofs)
     bytes_per_stage = BYTES_PER_DOF_UPDATE / 3.0 * sum(dofs)
-    stage_s = wall / (3 * BATCH_STEPS)
-    return {"instances": BATCH_COUNT, "steps": BATCH_STEPS, "dofs": sum(dofs), "tile": tile,
+    stage_s = wall / (3 * steps)
+    return {"instances": BATCH_COUNT, "steps": steps, "dofs": sum(dofs), "tile": tile,
             "k": "U{1,2,3}" if k_fixed is None else k_fixed, "fold": {0: "auto", 1: "in-kernel", 2: "fold"}[fold],
             "batched_dof_updates_per_s": batched, "batched_wall_s": wall,
             "hbm": {"achieved": bytes_per_stage / stage_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -171,7 +174,7 @@ def batched_bench(k_fixed=None, fold=0):
             "loop_dof_updates_per_s": loop, "loop_sample_instances": LOOP_SAMPLE,
             "loop_sample": f"instances {sample[0]}, {sample[1]}, ..., {sample[-1]} (evenly spaced); mean DOFs "
                            f"{loop_dofs / LOOP_SAMPLE:.0f} against {mean_all:.0f} over the batch",
-            "speedup_vs_loop": batched / loop}
+            "speedup_vs_loop": batched / loop if loop else None}
 
 
 def adjoint_bench(repeats: int = 5):
@@ -512,8 +515,10 @@ def main():
     }
     solver.close()
     if not args.no_batched:
-        out["batched"] = batched_bench(fold=args.batched_fold)
-        out["batched_k2"] = batched_bench(k_fixed=2, fold=args.batched_fold)
+        kw = dict(fold=args.batched_fold, steps=args.batched_steps, repeats=args.batched_repeats,
+                  loop_baseline=not args.no_loop)
+        out["batched"] = batched_bench(**kw)
+        out["batched_k2"] = batched_bench(k_fixed=2, **kw)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench()
     if not args.no_2d:

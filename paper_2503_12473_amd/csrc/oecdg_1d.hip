@@ -418,14 +418,38 @@ __device__ inline bool cell_of(const Inst1D &I, int tile, int i0, int tid, int &
 // Thread tid works on cell tid/2 of the tile (primal cells first) and on the
 // half cell tid%2 of it.
 
+// Doubles of a tile's LDS image (with its halo) that each thread loads.
+template <int K, int FLUX, int T>
+constexpr int tile_loads() { return (2 * FluxT<FLUX>::NC * (K + 1) * (T + 2) + nthreads(T) - 1) / nthreads(T); }
+
+// Issue the loads of tile `tile`'s LDS image (stage input of parity sp) into pre.
+template <int K, int FLUX, int T>
+__device__ inline void load_pre(const StageArgs &a, int tile, int sp, double (&pre)[tile_loads<K, FLUX, T>()]) {
+    constexpr int NC = FluxT<FLUX>::NC, PER = NC * (K + 1) * (T + 2), NT = nthreads(T);
+    const Tile1D tl = a.tiles[tile];
+    const Inst1D I = a.inst[tl.inst];
+    const double *inC = a.BC[sp] + I.offC, *inD = a.BD[sp] + I.offD;
+#pragma unroll
+    for (int i = 0; i < tile_loads<K, FLUX, T>(); ++i) {
+        const int e = threadIdx.x + i * NT;
+        pre[i] = e < 2 * PER ? tile_elem<K, NC, T, FLUX == 3>(I, tl.i0, inC, inD, e) : 0.0;
+    }
+}
+
 // folded: the instance's statistics were reduced by k_fold into a.red (batched
 // launches); otherwise every workgroup reduces the partial columns itself.
+// have_pre: the tile's LDS image is already in pre (loaded while the previous
+// tile of this workgroup was computed); next_tile >= 0: once this tile's image
+// is in LDS, the loads of next_tile's image are issued into pre, so they are in
+// flight while this tile is damped and updated (batched launches).
+// Returns whether next_tile's loads were issued.
 template <int K, int FLUX, int T>
-__device__ void stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
-                           bool folded) {
+__device__ bool stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
+                           bool folded, double (&pre)[tile_loads<K, FLUX, T>()], bool have_pre = false,
+                           int next_tile = -1) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1, W = T + 2, PER = NC * K1 * W, NT = nthreads(T);
-    constexpr int NLD = (2 * PER + NT - 1) / NT;
+    constexpr int NLD = tile_loads<K, FLUX, T>();
     const int tid = threadIdx.x;
     const bool coh = a.coherent;
     Tile1D tl;
@@ -462,8 +486,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     // step's and the previous step's scalars, the tile's pre-damping input and
     // the previous stage's partial statistics (issued before any test on them).
     const Slot cur = ld_slot(&S[par], coh), prev = ld_slot(&S[par ^ 1], coh);
-    double pre[NLD];
-    {
+    if (!have_pre) {
         const double *inC = a.BC[sp] + I.offC, *inD = a.BD[sp] + I.offD;
 #pragma unroll
         for (int i = 0; i < NLD; ++i) {
@@ -487,9 +510,9 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
                 S[par].done = 1;
                 S[par ^ 1].t = cur.t;
             }
-            return;
+            return false;
         }
-        if (l > 0 && cur.done) return;
+        if (l > 0 && cur.done) return false;
     }
     if (need_red) {
         if (folded) {
@@ -547,6 +570,8 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int m = 0; m < K1; ++m) un[q][m] = (l > 0 && valid) ? UM[(long long)(q * K1 + m) * ncell + gi] : 0.0;
+    const bool prefetched = next_tile >= 0;    // workgroup-uniform
+    if (prefetched) load_pre<K, FLUX, T>(a, next_tile, sp, pre);
     __syncthreads();
     if constexpr (FLUX == 3) {
         if (has_wall_ghost<K, NC, T>(I, i0)) {
@@ -646,6 +671,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     }
     tile_partials<K, FLUX, T>(I, valid, mesh, hf, out, a.part[sp], a.ntiles, tile, scratch, xwl && tail_tile, xwl);
     __syncthreads();
+    return prefetched;
 }
 
 // Statistics of a given state (srcC/srcD) into part[1]: the partials that the
@@ -742,7 +768,8 @@ struct Disp {
 template <int K, int FLUX, int T> struct StageFn {
     __device__ static void go(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
                               bool folded) {
-        stage_tile<K, FLUX, T>(a, l, par, first, tile, smem, xwl, folded);
+        double pre[tile_loads<K, FLUX, T>()];
+        stage_tile<K, FLUX, T>(a, l, par, first, tile, smem, xwl, folded, pre);
     }
 };
 template <int K, int FLUX, int T> struct StatsFn {
@@ -766,19 +793,20 @@ __global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_stage(Sta
     }
 }
 
-// The stage kernel of batched launches: the instance's statistics come
-// reduced from k_fold (one fixed-order reduction per instance and stage)
-// instead of every workgroup reducing all of its instance's partial columns.
-template <int KM, int FLUX, int T>
-#ifndef OECDG_FOLDED_WAVES
-#define OECDG_FOLDED_WAVES 1
-#endif
-__global__ __launch_bounds__(nthreads(T), OECDG_FOLDED_WAVES) void k_stage_folded(StageArgs a) {
-    using D = Disp<KM, FLUX, T>;
-    __shared__ double smem[D::LDS];
+// The stage kernel of batched launches (one degree per launch): the
+// instance's statistics come reduced from k_fold (one fixed-order reduction
+// per instance and stage) instead of every workgroup reducing all of its
+// instance's partial columns, and a workgroup walks the tiles tbeg +
+// blockIdx.x, + gridDim.x, ..., loading each tile's input while the previous
+// one is damped and updated.
+template <int K, int FLUX, int T>
+__global__ __launch_bounds__(nthreads(T)) void k_stage_folded(StageArgs a) {
+    __shared__ double smem[lds_doubles(K, FluxT<FLUX>::NC, T) + scratch_doubles(T)];
+    double pre[tile_loads<K, FLUX, T>()];
+    bool have = false;
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
-        const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-        D::template run<StageFn>(k, a, a.l, a.par, a.first, tile, smem, false, true);
+        const int next = tile + (int)gridDim.x < a.tend ? tile + (int)gridDim.x : -1;
+        have = stage_tile<K, FLUX, T>(a, a.l, a.par, a.first, tile, smem, false, true, pre, have, next);
     }
 }
 
@@ -975,8 +1003,22 @@ hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, int tile, int
     return launch(pick<0>(kmax, flux, ti), grid > 0 ? grid : a.tend - a.tbeg, tile, a, s);
 }
 
+int folded_grid_1d(int k, int flux, int tile) {
+    const int ti = tile_index(tile);
+    if (ti < 0) return 0;
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick<4>(k, flux, ti), nthreads(tile), 0) !=
+        hipSuccess)
+        return 0;
+    return per_cu * ncu;
+}
+
 hipError_t launch_fold_1d(const StageArgs &a, int flux, int tile, hipStream_t s) {
-    if (!a.red || a.tailwave || tile_index(tile) < 0) return hipErrorInvalidValue;
+    // the reduction uses nthreads(tile) threads, as a stage workgroup does
+    // (an extra-wave launch's fifth wave takes no part in it either)
+    if (!a.red || tile_index(tile) < 0) return hipErrorInvalidValue;
     // the partials the stage (a.l, a.par) reads: those of the previous global stage
     const int src = ((((a.ns & 1) ? a.par : 0) + a.l) & 1) ^ 1;
     void *fn = nullptr;

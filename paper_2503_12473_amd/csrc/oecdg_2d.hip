@@ -701,8 +701,9 @@ __global__ __launch_bounds__(8 * TX * TY) void k_stage2d(Stage2Args a) {
 template <int K, int FLUX, int TX, int TY, bool PK>
 // Two workgroups per CU (4 waves per SIMD; the LDS tile allows no more): the
 // register cap spills a few values to scratch, which costs less than running
-// one workgroup per CU (6.86 -> 6.32 ms per step on the 1024^2 workload).
-__global__ __launch_bounds__(8 * TX * TY, 4) void k_delta2d(Stage2Args a) {
+// one workgroup per CU (6.86 -> 6.32 ms per step on the 1024^2 workload).  At
+// k = 3 the LDS tile allows 2 waves per SIMD only, so no register cap.
+__global__ __launch_bounds__(8 * TX * TY, K == 3 ? 2 : 4) void k_delta2d(Stage2Args a) {
     using F = Flux2D<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1, Q = K + 1, NE = NC * K1 * K1, NSP = 2 * K + 4;
     constexpr int W = TX + 2, NCELL = W * (TY + 2), NT = 8 * TX * TY, NW = NT / WAVE;

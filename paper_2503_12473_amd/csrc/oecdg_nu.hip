@@ -443,6 +443,11 @@ struct NuState {
     long long *nexec_h = nullptr;
     Slot *slot_h = nullptr;
     int *err_h = nullptr;
+    // POLL steps after the first, captured once per (state arrays, t_end, fixed step, h_max)
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const double *g_uC = nullptr, *g_uD = nullptr;
+    double g_tend = 0.0, g_dt = 0.0, g_hmax = 0.0;
 };
 
 void free_state(NuState *s) {
@@ -457,6 +462,8 @@ void free_state(NuState *s) {
     if (s->nexec_h) (void)hipHostFree(s->nexec_h);
     if (s->slot_h) (void)hipHostFree(s->slot_h);
     if (s->err_h) (void)hipHostFree(s->err_h);
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
     delete s;
 }
 
@@ -572,28 +579,57 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
     a.tC = TC, a.tD = TD;
     const dim3 grid(nblk, 2);
     const int ns = rk == 1 ? 1 : rk == 2 ? 2 : 3;
+    // the kernels of one step; every step after the first has the same arguments
+    auto enqueue_step = [&](bool first, hipStream_t q) {
+        NuArgs b = a;
+        b.unC = uC, b.unD = uD;
+        if (first) launch_wave(b, grid, q);          // later steps: written by the last stage's k_nu_oe
+        b.pending = !first;
+        hipLaunchKernelGGL(k_nu_dt, dim3(1), dim3(WAVE), 0, q, b);
+        for (int l = 0; l < ns; ++l) {
+            const RKStage r = rk_stage(rk, l);
+            b.cn = l == 0 ? 0.0 : r.cn, b.cw = r.cw, b.dd = r.d;
+            b.ulC = l == 0 ? uC : (l == 1 ? S1C : S2C);
+            b.ulD = l == 0 ? uD : (l == 1 ? S1D : S2D);
+            const bool lastst = l == ns - 1;
+            b.wave_out = lastst;
+            b.oC = lastst ? uC : (l == 0 ? S1C : S2C);
+            b.oD = lastst ? uD : (l == 0 ? S1D : S2D);
+            launch_kind(0, b, grid, q);
+            launch_kind(1, b, grid, q);
+        }
+    };
+    // whole blocks of POLL steps (from a multiple of POLL) replay a captured graph
+    if (s->gexec && (s->g_uC != uC || s->g_uD != uD || s->g_tend != t_end || s->g_dt != dt_fixed || s->g_hmax != hmax))
+        (void)hipGraphExecDestroy(s->gexec), s->gexec = nullptr;
+    auto ensure_graph = [&]() -> int {
+        if (s->gexec) return OECDG_OK;
+        if (!s->cap) NUCHK(h, hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
+        hipGraph_t gr = nullptr;
+        NUCHK(h, hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+        for (int j = 0; j < POLL; ++j) enqueue_step(false, s->cap);
+        NUCHK(h, hipStreamEndCapture(s->cap, &gr));
+        const hipError_t e = hipGraphInstantiate(&s->gexec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        NUCHK(h, e);
+        s->g_uC = uC, s->g_uD = uD, s->g_tend = t_end, s->g_dt = dt_fixed, s->g_hmax = hmax;
+        return OECDG_OK;
+    };
     int64_t step = 0;
-    for (; nsteps < 0 || step < nsteps; ++step) {
+    while (nsteps < 0 || step < nsteps) {
         if (step > 0 && step % POLL == 0 && !std::isinf(t_end)) {
             NUCHK(h, hipMemcpyAsync(s->slot_h, s->slot, sizeof(Slot), hipMemcpyDeviceToHost, st));
             NUCHK(h, hipStreamSynchronize(st));
             if (s->slot_h->done) break;
         }
-        a.unC = uC, a.unD = uD;
-        if (step == 0) launch_wave(a, grid, st);     // later steps: written by the last stage's k_nu_oe
-        a.pending = step > 0;
-        hipLaunchKernelGGL(k_nu_dt, dim3(1), dim3(WAVE), 0, st, a);
-        for (int l = 0; l < ns; ++l) {
-            const RKStage r = rk_stage(rk, l);
-            a.cn = l == 0 ? 0.0 : r.cn, a.cw = r.cw, a.dd = r.d;
-            a.ulC = l == 0 ? uC : (l == 1 ? S1C : S2C);
-            a.ulD = l == 0 ? uD : (l == 1 ? S1D : S2D);
-            const bool lastst = l == ns - 1;
-            a.wave_out = lastst;
-            a.oC = lastst ? uC : (l == 0 ? S1C : S2C);
-            a.oD = lastst ? uD : (l == 0 ? S1D : S2D);
-            launch_kind(0, a, grid, st);
-            launch_kind(1, a, grid, st);
+        if (step > 0 && step % POLL == 0 && (nsteps < 0 || nsteps - step >= POLL)) {
+            const int rc = ensure_graph();
+            if (rc != OECDG_OK) return rc;
+            NUCHK(h, hipGraphLaunch(s->gexec, st));
+            step += POLL;
+        } else {
+            enqueue_step(step == 0, st);
+            ++step;
         }
         NUCHK(h, hipGetLastError());
     }

@@ -378,3 +378,33 @@ def test_single_stage_and_dt_with_tail_tile():
             rC, rD = ora.ssprk3_stage1d(prob, l, tau, dt, uC, uD, ulC, ulD)
             gC, gD = o[0].cpu().numpy().reshape(rC.shape), o[1].cpu().numpy().reshape(rD.shape)
             assert _rel(gC, gD, rC, rD) <= STAGE_TOL, l
+
+
+@pytest.mark.parametrize("n,k", [(16384, 2), (1000, 3), (130, 1)])
+def test_statistics_fold_modes_give_the_same_bits(n, k):
+    """The global statistics reduced inside every stage workgroup (1) or by a
+    separate per-instance kernel (2) follow one fixed order: identical results,
+    eager and graph launches (N = 16384 uses the extra-wave tail tiles, where
+    mode 2 reduces in-kernel)."""
+    prob, uC, uD = inputs.euler_riemann(n, k, inputs.riemann_states(2))
+    outs = []
+    for fold in (1, 2):
+        for mode in (_lib.MODE_EAGER, _lib.MODE_GRAPH):
+            print(f"[fold] n={n} k={k} fold={fold} mode={mode}", flush=True)
+            with OECDG(prob, 0.15) as s:
+                s.set_option(_lib.OPT_FOLD, fold)
+                s.set_option(_lib.OPT_MODE, mode)
+                a, b = to_device(uC), to_device(uD)
+                t, ns = s.run(a, b, nsteps=300)
+                outs.append((a.cpu().numpy(), b.cpu().numpy(), t, ns))
+    for o in outs[1:]:
+        assert o[2:] == outs[0][2:]
+        np.testing.assert_array_equal(o[0], outs[0][0])
+        np.testing.assert_array_equal(o[1], outs[0][1])
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, nsteps=40, cfl=0.15) if n <= 1000 else (None, None, None, None)
+    if rC is not None:
+        with OECDG(prob, 0.15) as s:
+            s.set_option(_lib.OPT_FOLD, 2)
+            a, b = to_device(uC), to_device(uD)
+            s.run(a, b, nsteps=40)
+            assert _rel(a.cpu().numpy(), b.cpu().numpy(), rC, rD) <= RUN_TOL
