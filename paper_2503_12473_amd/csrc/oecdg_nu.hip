@@ -5,21 +5,31 @@
 // dual cell holds the primal edge x_{i-1/2} off its centre.  Every cell carries
 // its own geometry (centre, width, and the point where the other mesh has its
 // edge); the Legendre values at the mapped quadrature nodes are evaluated at run
-// time.  One thread per cell of either mesh (a 2D grid, y = mesh); per step:
-//   k_nu_dt                  beta over the cell averages -> tau (device-side slot);
-//                            the wave-speed partials come from k_nu_wave before the
-//                            first step and from the last stage's k_nu_oe after it
-//   per stage:
-//     k_nu_stage             operator of eq:1D_H + the c/d combination of eq:RKCDG,
-//                            and per-block statistics of the undamped result
-//     k_nu_oe                every workgroup first reduces the block statistics
-//                            (the same fixed order everywhere: avg = domain mean,
-//                            width-weighted, and sigma per mesh), then delta_K^m
-//                            (Sec. 2.2, h_{e,K} = the width of K) and the exact
-//                            damping F_tau into the stage's output
-//   (the step ends in the next step's k_nu_dt; k_nu_advance ends the last one)
-// No host synchronisation inside a step; the host polls the slot every few
-// steps when it marches to a final time.
+// time.
+//
+// One launch per RK stage (k_nu_step), as the uniform stage kernel: a workgroup
+// owns CPB = 64 consecutive indices of both meshes, one thread per cell (wave 0
+// primal, wave 1 dual; two lanes of wave 2 take the primal cell left of the
+// range and the dual cell right of it, which the operator of the owned cells
+// reads; 256 workgroups at N = 16384, one per CU).  In order:
+//   - the statistics of the stage input (the previous stage's undamped output)
+//     from the per-workgroup partials, in the same fixed order in every
+//     workgroup: avg = width-weighted domain mean and sigma per mesh and
+//     component (Sec. 2.2), and at a step's first stage the wave speed beta,
+//     tau_max = C h_max / beta and tau (every workgroup computes the same tau;
+//     the first workgroup records the step);
+//   - delta_K^m (h_{e,K} = the width of K) and the exact damping F_tau of each
+//     thread's cell into LDS (not at the run's first stage: the initial data
+//     enter undamped); at the first stage the damped u^n is also stored;
+//   - the operator of eq:1D_H on the owned cells from the damped cells in LDS,
+//     the c/d combination of eq:RKCDG, the undamped output, and the partials of
+//     its statistics (one DPP wave reduction per mesh).
+// A step's last output stays undamped until the next step's first stage (or
+// k_nu_final at the end of the call) damps it.  Stage inputs and outputs
+// alternate between two buffers with the parity of the global stage index; the
+// step record alternates with the parity of the step index.  No host
+// synchronisation inside a step; the host polls the record every few steps when
+// it marches to a final time.
 #include "oecdg_device.h"
 #include "oecdg_tables.h"
 
@@ -30,8 +40,9 @@
 namespace oecdg {
 namespace {
 
-constexpr int NB = 128;                 // threads per workgroup (2 waves: 256 workgroups at N = 16384)
-constexpr int POLL = 16;                // steps between host checks of the slot when marching to t_end
+constexpr int NB = 3 * WAVE;            // threads per workgroup: a wave per mesh, and one for the two end cells
+constexpr int CPB = WAVE;               // owned indices per workgroup
+constexpr int POLL = 16;                // steps between host checks of the record when marching to t_end
 
 // Run-time Legendre values: d-th derivative of P_m at x, m <= 3.
 __device__ inline double legr(int m, int d, double x) {
@@ -41,25 +52,30 @@ __device__ inline double legr(int m, int d, double x) {
     return m == 3 ? 15.0 : 0.0;
 }
 
+// The start of a step (t, stop) and, once its first stage has run, the step
+// itself (tau, tau_max, run).  Two records, by the parity of the step index.
+struct NuSlot {
+    double t, tau, tau_max;
+    int stop, run;
+};
+
 struct NuArgs {
-    int n, k, flux, oe;
+    int n, k, flux, oe, ns;
     double L, hmax, cfl, p0, t_end, dt_fixed;
     const double *edges;                 // [n+1]
     const double *cC, *wC;               // primal centres and widths [n]
     const double *cD, *wD;               // dual centres and widths [n] (dual 0 starts below xlo)
-    // stage
-    const double *unC, *unD, *ulC, *ulD; // u^n and the stage input u^{n,l}
-    double *tC, *tD;                     // undamped stage output
-    double *oC, *oD;                     // damped stage output
-    double cn, cw, dd;                   // c_{l0}, c_{ll}, d_{ll} (l = 0: cn = 0)
-    double *part;                        // [mesh][3 NC][nblk]
-    double *wpart;                       // wave-speed partials [2 nblk]
-    Slot *slot;
+    double *TC[2], *TD[2];               // undamped stage states, by the parity of the global stage index
+    double *UC, *UD;                     // damped u^n of the current step
+    double *dstC, *dstD;                 // k_nu_final: the caller's arrays
+    double *part;                        // partial statistics [2 parities][2 meshes][RW rows][nblk]
+    NuSlot *slot;                        // [2]
     long long *nexec;                    // steps executed
-    int wave_out;                        // last stage: also write the wave-speed partials of its output
-    int pending;                         // k_nu_dt first ends the previous step
     int *err;                            // [0] non-finite, [1] non-physical, [2] bad wave speed
     int nblk;
+    // per launch
+    int l, gp, sp, first;                // stage, parity of the global stage index, parity of the step, step 0
+    double cn, cw, dd;                   // c_{l0}, c_{ll}, d_{ll} (l = 0: cn = 0)
 };
 
 // Geometry of the cell of the other mesh that overlaps piece p of cell i of mesh
@@ -108,124 +124,355 @@ __device__ inline void eval(const double (&c)[NC][K + 1], int d, double xi, doub
     }
 }
 
-// In-block reduction of NV values per thread in a fixed tree order (kind per value).
-template <int NV>
-__device__ inline void block_reduce(double (&v)[NV], const int (&kind)[NV], double *sh) {
-    const int t = threadIdx.x;
-    for (int s = NB / 2; s > 0; s >>= 1) {
+template <int NC>
+struct Rows {
+    static constexpr int RW = 3 * NC + 1;   // per mesh: (sum, max, min) per component, then max beta
+};
+
+// Kind of partial row j (both meshes): sum, max, min per component, then max beta.
+template <int NC>
+__device__ constexpr int nu_row_kind(int j) {
+    return j % Rows<NC>::RW == Rows<NC>::RW - 1 ? 1 : (j % Rows<NC>::RW) % 3;
+}
+
+// This thread's share of the partials of parity gp: partials t and t + NB of
+// every row, loaded together (unconditional loads of valid elements, then
+// selects).
+template <int NC>
+struct NuPart {
+    double x[2 * Rows<NC>::RW], y[2 * Rows<NC>::RW];
+};
+template <int NC>
+__device__ inline void nu_stat_load(const NuArgs &a, int gp, NuPart<NC> &pt) {
+    constexpr int NR = 2 * Rows<NC>::RW;
+    const double *part = a.part + (long long)gp * NR * a.nblk;
+    const int b0 = min((int)threadIdx.x, a.nblk - 1), b1 = min((int)threadIdx.x + NB, a.nblk - 1);
 #pragma unroll
-        for (int r = 0; r < NV; ++r) sh[r * NB + t] = v[r];
-        __syncthreads();
-        if (t < s) {
-#pragma unroll
-            for (int r = 0; r < NV; ++r) v[r] = stat_op(kind[r], v[r], sh[r * NB + t + s]);
-        }
-        __syncthreads();
+    for (int j = 0; j < NR; ++j) {
+        pt.x[j] = part[(long long)j * a.nblk + b0];
+        pt.y[j] = part[(long long)j * a.nblk + b1];
     }
 }
 
-template <int FLUX>
-__global__ void __launch_bounds__(NB) k_nu_wave(NuArgs a) {
+// Reduce the partials into avg and sigma of both meshes ([mesh][q]) and the
+// largest wave speed: this thread's share, a DPP tree per wave, then the waves
+// in order; every workgroup gets the same bits.  All threads must take part.
+template <int NC>
+__device__ inline void nu_statistics(const NuArgs &a, int gp, const NuPart<NC> &pt, double *sh,
+                                     double (&avg)[2][NC], double (&sig)[2][NC], double &beta) {
+    constexpr int RW = Rows<NC>::RW, NR = 2 * RW, NW = NB / WAVE;
+    const int t = threadIdx.x, lane = t % WAVE, wave = t / WAVE;
+    const double *part = a.part + (long long)gp * NR * a.nblk;
+    double v[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int kd = nu_row_kind<NC>(j);
+        v[j] = t < a.nblk ? pt.x[j] : stat_identity(kd);
+        v[j] = t + NB < a.nblk ? stat_op(kd, v[j], pt.y[j]) : v[j];
+    }
+    for (int b = t + 2 * NB; b < a.nblk; b += NB) {  // meshes of more than 2 NB CPB cells
+#pragma unroll
+        for (int j = 0; j < NR; ++j) v[j] = stat_op(nu_row_kind<NC>(j), v[j], part[(long long)j * a.nblk + b]);
+    }
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int kd = nu_row_kind<NC>(j);
+        v[j] = wave_reduce(kd, v[j]);
+        if (lane == WAVE - 1) sh[j * NW + wave] = v[j];
+    }
+    __syncthreads();
+    double r[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const int kd = nu_row_kind<NC>(j);
+        r[j] = sh[j * NW];
+        for (int w = 1; w < NW; ++w) r[j] = stat_op(kd, r[j], sh[j * NW + w]);
+    }
+#pragma unroll
+    for (int M = 0; M < 2; ++M)
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            avg[M][q] = r[M * RW + 3 * q] / a.L;
+            sig[M][q] = fmax(r[M * RW + 3 * q + 1] - avg[M][q], avg[M][q] - r[M * RW + 3 * q + 2]);
+        }
+    beta = fmax(r[RW - 1], r[2 * RW - 1]);
+}
+
+// Geometry of cell i of mesh M: centre, width, its ends and split point, and
+// the overlapping cells of the other mesh (indices, centres shifted across the
+// seam, widths), with the reciprocal widths.
+struct NuGeo {
+    double c, w, iw, lo, split, hi, cn[2], wn[2], iwn[2];
+    int j[2];
+};
+__device__ inline NuGeo nu_geo(const NuArgs &a, int M, int i) {
+    NuGeo g;
+    g.c = M == 0 ? a.cC[i] : a.cD[i];
+    g.w = M == 0 ? a.wC[i] : a.wD[i];
+    pieces(a, M, i, g.lo, g.split, g.hi);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) neighbour(a, M, i, p, g.j[p], g.cn[p], g.wn[p]);
+    g.iw = 1.0 / g.w;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) g.iwn[p] = 1.0 / g.wn[p];
+    return g;
+}
+
+// delta_K^m of a cell (Sec. 2.2) from its undamped coefficients u and those of
+// the two overlapping cells of the other mesh (nb), and the exact damping
+// F_tau of u in place.  isig: 1 / sigma per component (0 where sigma = 0,
+// whose component then takes no part).
+template <int K, int FLUX>
+__device__ inline void nu_damp(const NuArgs &a, const NuGeo &g, const double (&nb)[2][FluxT<FLUX>::NC][K + 1],
+                               double tau, const double (&isig)[FluxT<FLUX>::NC],
+                               double (&u)[FluxT<FLUX>::NC][K + 1]) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC;
-    __shared__ double sh[NB];
-    const int M = blockIdx.y, i = blockIdx.x * NB + threadIdx.x;
-    double b = 0.0;
-    if (i < a.n && !a.slot->done) {
-        const double *u = M == 0 ? a.unC : a.unD;
-        double ub[NC];
+    double ub[NC];
 #pragma unroll
-        for (int q = 0; q < NC; ++q) ub[q] = u[(long long)(q * (a.k + 1)) * a.n + i];
-        b = F::speed(ub, a.p0);
-        if (!(b >= 0.0)) b = INFINITY;               // NaN: reported by k_nu_dt
-    }
-    double v[1] = {b};
-    const int kind[1] = {1};
-    block_reduce<1>(v, kind, sh);
-    if (threadIdx.x == 0) a.wpart[M * a.nblk + blockIdx.x] = v[0];
-}
-
-// One wave: first the previous step's end (t += tau, the step count, the stop
-// at t_end or on an error) when a.pending, then beta (max over the wave-speed
-// partials) and tau_max and tau of this step.  Every lane reads the slot and
-// computes the same values; the last lane writes them.
-__global__ void __launch_bounds__(WAVE) k_nu_dt(NuArgs a) {
-    Slot *s = a.slot;
-    Slot v = *s;
-    long long inc = 0;
-    if (a.pending && !v.done) {
-        inc = 1;
-        v.t = v.last ? a.t_end : v.t + v.tau;
-        if (v.last) v.done = 1;
-        v.done |= 2 * (a.err[0] | a.err[1] | a.err[2]);
-    }
-    double b = 0.0;
-    for (int j = threadIdx.x; j < 2 * a.nblk; j += WAVE) b = fmax(b, a.wpart[j]);
-    b = wave_reduce(1, b);
-    if (threadIdx.x != WAVE - 1) return;
-    *a.nexec += inc;
-    if (!v.done && v.t >= a.t_end) v.done = 1;
-    if (!v.done) {
-        double tau_max = a.dt_fixed;
-        if (!(a.dt_fixed > 0.0)) {
-            if (!(b > 0.0) || !isfinite(b)) {
-                a.err[2] = 1;
-                v.done = 1;
-            }
-            tau_max = a.cfl * a.hmax / b;
+    for (int q = 0; q < NC; ++q) ub[q] = u[q][0];
+    const double beta = F::speed(ub, a.p0);
+    const double xl = 2.0 * (g.lo - g.c) * g.iw, xr = 2.0 * (g.hi - g.c) * g.iw;
+    const double yl = 2.0 * (g.lo - g.cn[0]) * g.iwn[0], yr = 2.0 * (g.hi - g.cn[1]) * g.iwn[1];
+    double S = 0.0, wp = g.iw;                        // w^{m-1}
+    double so = 1.0, sl = 1.0, sr = 1.0;              // (2/w)^m of the cell and of both neighbours
+    double fact = 1.0;
+#pragma unroll
+    for (int m = 0; m <= K; ++m) {
+        if (m > 0) {
+            so *= 2.0 * g.iw;
+            sl *= 2.0 * g.iwn[0];
+            sr *= 2.0 * g.iwn[1];
         }
-        if (!v.done) {
-            double tau = tau_max;
-            v.last = 0;
-            if (v.t + tau >= a.t_end) { tau = a.t_end - v.t; v.last = 1; }
-            v.tau = tau;
-            v.tau_max = tau_max;
+        if (m > 1) fact *= m;
+        double oL[NC], oR[NC], vL[NC], vR[NC];
+        eval<K, NC>(u, m, xl, so, oL);
+        eval<K, NC>(u, m, xr, so, oR);
+        eval<K, NC>(nb[0], m, yl, sl, vL);
+        eval<K, NC>(nb[1], m, yr, sr, vR);
+        const double cm = (2.0 * m + 1.0) / ((2.0 * K - 1.0) * fact) * wp;
+        double dm = 0.0;
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+            dm = fmax(dm, cm * beta * (fabs(oL[q] - vL[q]) + fabs(oR[q] - vR[q])) * isig[q]);
+        S += dm;
+        wp *= g.w;
+        if (m >= 1) {
+            const double fac = exp(-tau * S);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) u[q][m] *= fac;
         }
     }
-    *s = v;
 }
 
-// The end of the last step of a call (the others end in the next k_nu_dt).
-__global__ void k_nu_advance(NuArgs a) {
-    Slot *s = a.slot;
-    if (s->done) return;
-    *a.nexec += 1;
-    s->t = s->last ? a.t_end : s->t + s->tau;
-    if (s->last) s->done = 1;
-    s->done |= 2 * (a.err[0] | a.err[1] | a.err[2]);
-}
-
-// Operator of eq:1D_H on cell i of mesh M, combined with u^n, and the block's
-// statistics of the undamped result.
+// Partial statistics of one cell's undamped coefficients o: width-weighted
+// average, max and min at the ends and the quadrature nodes of both pieces, and
+// the wave speed at the average; plus the error flags.
 template <int K, int FLUX>
-__global__ void __launch_bounds__(NB) k_nu_stage(NuArgs a) {
+__device__ inline void nu_cell_stats(const NuArgs &a, const NuGeo &g, const double (&o)[FluxT<FLUX>::NC][K + 1],
+                                     double *st, bool flag) {
     using F = FluxT<FLUX>;
-    constexpr int NC = F::NC, K1 = K + 1, Q = K + 1, NV = 3 * NC;
+    constexpr int NC = F::NC, K1 = K + 1, Q = K + 1;
     constexpr ct::Gauss<Q> G = ct::gauss<Q>();
-    __shared__ double sh[NV * NB];
-    const int M = blockIdx.y, i = blockIdx.x * NB + threadIdx.x;
-    const bool live = i < a.n && !a.slot->done;
-    double st[NV];
-    int kind[NV];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) st[3 * q] = g.w * o[q][0], st[3 * q + 1] = -INFINITY, st[3 * q + 2] = INFINITY;
+    double xs[2 * Q + 2];
+    xs[0] = g.lo;
+    xs[2 * Q + 1] = g.hi;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        xs[1 + k] = 0.5 * (g.lo + g.split) + 0.5 * (g.split - g.lo) * G.s[k];
+        xs[1 + Q + k] = 0.5 * (g.split + g.hi) + 0.5 * (g.hi - g.split) * G.s[k];
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * Q + 2; ++j) {
+        double v[NC];
+        eval<K, NC>(o, 0, 2.0 * (xs[j] - g.c) * g.iw, 1.0, v);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            st[3 * q + 1] = fmax(st[3 * q + 1], v[q]);
+            st[3 * q + 2] = fmin(st[3 * q + 2], v[q]);
+        }
+    }
+    double ub[NC];
+    bool finite = true;
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-        kind[3 * q] = 0, kind[3 * q + 1] = 1, kind[3 * q + 2] = 2;
-        st[3 * q] = 0.0, st[3 * q + 1] = -INFINITY, st[3 * q + 2] = INFINITY;
+        ub[q] = o[q][0];
+#pragma unroll
+        for (int m = 0; m < K1; ++m) finite = finite && isfinite(o[q][m]);
     }
-    if (live) {
-        const double tau = a.slot->tau, itm = 1.0 / a.slot->tau_max;
-        const double *own = M == 0 ? a.ulC : a.ulD, *oth = M == 0 ? a.ulD : a.ulC;
-        const double c = M == 0 ? a.cC[i] : a.cD[i], w = M == 0 ? a.wC[i] : a.wD[i];
-        double lo, split, hi;
-        pieces(a, M, i, lo, split, hi);
-        double u[NC][K1], nb[2][NC][K1], cnb[2], wnb[2];
-        load_cell<K, NC>(own, a.n, i, u);
+    double b = F::speed(ub, a.p0);
+    if (!(b >= 0.0)) b = INFINITY;       // NaN: a bad wave speed at the next step
+    st[3 * NC] = b;
+    if (flag) {
+        if (!finite) __hip_atomic_store(&a.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else if (!F::physical(ub, a.p0)) __hip_atomic_store(&a.err[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// One wave's reduction of its cells' partial rows (waves 0 and 1 hold one mesh
+// each; wave 2 owns no cell) into the workgroup's column of the partials of
+// parity gp.
+template <int NC>
+__device__ inline void nu_store_partials(const NuArgs &a, int gp, int M, double *st) {
+    constexpr int RW = Rows<NC>::RW;
+    if (threadIdx.x >= 2 * WAVE) return;             // uniform over the wave
+    double *part = a.part + (long long)gp * 2 * RW * a.nblk;
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+        const int kd = r == RW - 1 ? 1 : r % 3;
+        const double v = wave_reduce(kd, st[r]);
+        if (threadIdx.x % WAVE == WAVE - 1) part[((long long)M * RW + r) * a.nblk + blockIdx.x] = v;
+    }
+}
+
+// This thread's cell and its LDS slot, for the owned range [i0, i1): wave 0
+// the primal cells i0 + lane (slot lane + 1), wave 1 the dual cells i0 + lane
+// (slot lane); wave 2 lane 0 the primal cell i0 - 1 (slot 0), lane 1 the dual
+// cell i1 (slot i1 - i0); periodic wrap.  owned: the operator's cells.
+struct NuCell {
+    int M, s, i;
+    bool has, owned;
+};
+__device__ inline NuCell nu_cell(const NuArgs &a) {
+    NuCell c;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int i0 = blockIdx.x * CPB, span = min(a.n, i0 + CPB) - i0;
+    int i;
+    if (wave < 2) {
+        c.M = wave;
+        c.has = c.owned = lane < span;
+        c.s = wave == 0 ? lane + 1 : lane;
+        i = i0 + lane;
+    } else {
+        c.M = lane == 1 ? 1 : 0;
+        c.has = lane < 2;
+        c.owned = false;
+        c.s = lane == 0 ? 0 : span;
+        i = lane == 0 ? i0 - 1 : i0 + span;
+    }
+    i = i < 0 ? i + a.n : (i >= a.n ? i - a.n : i);
+    c.i = c.has ? i : i0;                // threads without a cell read a valid one and store nothing
+    return c;
+}
+
+// Statistics of the initial data (stage input of step 0).
+template <int K, int FLUX>
+__global__ void __launch_bounds__(NB) k_nu_init(NuArgs a) {
+    constexpr int NC = FluxT<FLUX>::NC, K1 = K + 1, RW = Rows<NC>::RW;
+    const NuCell c = nu_cell(a);
+    const NuGeo g = nu_geo(a, c.M, c.i);
+    double u[NC][K1];
+    load_cell<K, NC>(c.M == 0 ? a.TC[0] : a.TD[0], a.n, c.i, u);
+    double st[RW];
+    nu_cell_stats<K, FLUX>(a, g, u, st, false);
+    if (!c.owned) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) st[r] = stat_identity(r == RW - 1 ? 1 : r % 3);
+    }
+    nu_store_partials<NC>(a, 0, c.M, st);
+}
+
+// One RK stage (see the top of the file).
+template <int K, int FLUX>
+__global__ void __launch_bounds__(NB) k_nu_step(NuArgs a) {
+    using F = FluxT<FLUX>;
+    constexpr int NC = F::NC, K1 = K + 1, Q = K + 1, RW = Rows<NC>::RW;
+    constexpr ct::Gauss<Q> G = ct::gauss<Q>();
+    __shared__ double dmp[2][NC * K1][WAVE + 1];     // damped input of the workgroup's cells, [mesh][coefficient][slot]
+    __shared__ double sh[2 * RW * (NB / WAVE)];
+    // every independent load before the first test on any of them: the step
+    // record, the error flags, the partial statistics of the input, geometry,
+    // the cell, the two overlapping cells of the other mesh, u^n (later stages)
+    const NuSlot cur = a.slot[a.sp];
+    const double tau_prev = a.slot[a.sp ^ 1].tau;    // the previous step's (damps the input of its first stage)
+    const int errs = a.err[0] | a.err[1] | a.err[2];
+    NuPart<NC> pt;
+    nu_stat_load<NC>(a, a.gp, pt);
+    const NuCell c = nu_cell(a);
+    const int M = c.M, i = c.i;
+    const double *own = M == 0 ? a.TC[a.gp] : a.TD[a.gp], *oth = M == 0 ? a.TD[a.gp] : a.TC[a.gp];
+    const NuGeo g = nu_geo(a, M, i);
+    double u[NC][K1], nb[2][NC][K1], un[NC][K1];
+    load_cell<K, NC>(own, a.n, i, u);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) load_cell<K, NC>(oth, a.n, g.j[p], nb[p]);
+    if (a.l > 0) load_cell<K, NC>(M == 0 ? a.UC : a.UD, a.n, i, un);
+    if (a.l > 0 && !cur.run) return;                 // uniform over the grid
+    if (a.l == 0 && (cur.stop || errs || cur.t >= a.t_end)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.slot[a.sp].run = 0;
+            a.slot[a.sp ^ 1].t = cur.t;
+            a.slot[a.sp ^ 1].stop = 1;
+        }
+        return;
+    }
+    double avg[2][NC], sig[2][NC], beta;
+    nu_statistics<NC>(a, a.gp, pt, sh, avg, sig, beta);
+    double tau = cur.tau, tau_max = cur.tau_max;
+    if (a.l == 0) {                                  // the step's tau, the same in every workgroup
+        tau_max = a.dt_fixed;
+        if (!(a.dt_fixed > 0.0)) {
+            if (!(beta > 0.0) || !isfinite(beta)) {
+                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                    a.err[2] = 1;
+                    a.slot[a.sp].run = 0;
+                    a.slot[a.sp ^ 1].t = cur.t;
+                    a.slot[a.sp ^ 1].stop = 1;
+                }
+                return;
+            }
+            tau_max = a.cfl * a.hmax / beta;
+        }
+        tau = tau_max;
+        bool last = false;
+        if (cur.t + tau >= a.t_end) tau = a.t_end - cur.t, last = true;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.slot[a.sp].tau = tau;
+            a.slot[a.sp].tau_max = tau_max;
+            a.slot[a.sp].run = 1;
+            a.slot[a.sp ^ 1].t = last ? a.t_end : cur.t + tau;
+            a.slot[a.sp ^ 1].stop = last;
+            *a.nexec += 1;
+        }
+    }
+    if (a.oe && K > 0 && !a.first) {
+        double isig[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) isig[q] = sig[M][q] != 0.0 ? 1.0 / sig[M][q] : 0.0;
+        nu_damp<K, FLUX>(a, g, nb, a.l == 0 ? tau_prev : tau, isig, u);
+    }
+    if (c.has) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 0; m < K1; ++m) dmp[M][q * K1 + m][c.s] = u[q][m];
+    }
+    if (a.l == 0 && c.owned) {                       // u^n, damped, for the later stages
+        double *dn = M == 0 ? a.UC : a.UD;
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 0; m < K1; ++m) dn[(long long)(q * K1 + m) * a.n + i] = u[q][m];
+    }
+    __syncthreads();
+    // operator of eq:1D_H on the owned cell, from the damped cells in LDS: primal
+    // i in slot s has dual i, i+1 in dual slots s-1, s; dual i in slot s has
+    // primal i-1, i in primal slots s, s+1
+    double st[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) st[r] = stat_identity(r == RW - 1 ? 1 : r % 3);
+    if (c.owned) {
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            int j;
-            neighbour(a, M, i, p, j, cnb[p], wnb[p]);
-            load_cell<K, NC>(oth, a.n, j, nb[p]);
+            const int ns = M == 0 ? c.s - 1 + p : c.s + p;
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int m = 0; m < K1; ++m) nb[p][q][m] = dmp[1 - M][q * K1 + m][ns];
         }
+        const double itm = 1.0 / tau_max;
         double R[NC][K1];
 #pragma unroll
         for (int q = 0; q < NC; ++q)
@@ -233,11 +480,11 @@ __global__ void __launch_bounds__(NB) k_nu_stage(NuArgs a) {
             for (int m = 0; m < K1; ++m) R[q][m] = 0.0;
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            const double x0 = p == 0 ? lo : split, x1 = p == 0 ? split : hi;
+            const double x0 = p == 0 ? g.lo : g.split, x1 = p == 0 ? g.split : g.hi;
 #pragma unroll
-            for (int g = 0; g < Q; ++g) {
-                const double x = 0.5 * (x0 + x1) + 0.5 * (x1 - x0) * G.s[g], jac = 0.5 * (x1 - x0) * G.w[g];
-                const double xi = 2.0 * (x - c) / w, xn = 2.0 * (x - cnb[p]) / wnb[p];
+            for (int k = 0; k < Q; ++k) {
+                const double x = 0.5 * (x0 + x1) + 0.5 * (x1 - x0) * G.s[k], jac = 0.5 * (x1 - x0) * G.w[k];
+                const double xi = 2.0 * (x - g.c) * g.iw, xn = 2.0 * (x - g.cn[p]) * g.iwn[p];
                 double v[NC], uk[NC], fv[NC];
                 eval<K, NC>(nb[p], 0, xn, 1.0, v);
                 eval<K, NC>(u, 0, xi, 1.0, uk);
@@ -246,207 +493,79 @@ __global__ void __launch_bounds__(NB) k_nu_stage(NuArgs a) {
                 for (int q = 0; q < NC; ++q)
 #pragma unroll
                     for (int m = 0; m < K1; ++m)
-                        R[q][m] += jac * ((v[q] - uk[q]) * itm * legr(m, 0, xi) + fv[q] * (2.0 / w) * legr(m, 1, xi));
+                        R[q][m] += jac * ((v[q] - uk[q]) * itm * legr(m, 0, xi) + fv[q] * (2.0 * g.iw) * legr(m, 1, xi));
             }
         }
         double vl[NC], vr[NC], fl[NC], fr[NC];
-        eval<K, NC>(nb[0], 0, 2.0 * (lo - cnb[0]) / wnb[0], 1.0, vl);
-        eval<K, NC>(nb[1], 0, 2.0 * (hi - cnb[1]) / wnb[1], 1.0, vr);
+        eval<K, NC>(nb[0], 0, 2.0 * (g.lo - g.cn[0]) * g.iwn[0], 1.0, vl);
+        eval<K, NC>(nb[1], 0, 2.0 * (g.hi - g.cn[1]) * g.iwn[1], 1.0, vr);
         F::f(vl, fl, a.p0);
         F::f(vr, fr, a.p0);
-        const double *un = M == 0 ? a.unC : a.unD;
-        double *out = M == 0 ? a.tC : a.tD;
+        double *out = M == 0 ? a.TC[a.gp ^ 1] : a.TD[a.gp ^ 1];
         double o[NC][K1];
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
             for (int m = 0; m < K1; ++m) {
                 const double sgn = (m % 2 == 0) ? 1.0 : -1.0;
-                const double Lm = (2.0 * m + 1.0) / w * (R[q][m] - (fr[q] - fl[q] * sgn));
-                const long long e = (long long)(q * K1 + m) * a.n + i;
-                const double base = a.cn != 0.0 ? a.cn * un[e] : 0.0;
+                const double Lm = (2.0 * m + 1.0) * g.iw * (R[q][m] - (fr[q] - fl[q] * sgn));
+                const double base = a.l > 0 ? a.cn * un[q][m] : 0.0;
                 o[q][m] = base + (a.cw * u[q][m] + tau * a.dd * Lm);
-                out[e] = o[q][m];
+                out[(long long)(q * K1 + m) * a.n + i] = o[q][m];
             }
-        // statistics of the undamped result: width-weighted sum of the averages,
-        // max and min at the ends and the quadrature nodes of both pieces
-#pragma unroll
-        for (int q = 0; q < NC; ++q) st[3 * q] = w * o[q][0];
-        double xs[2 * Q + 2];
-        xs[0] = lo;
-        xs[2 * Q + 1] = hi;
-#pragma unroll
-        for (int g = 0; g < Q; ++g) {
-            xs[1 + g] = 0.5 * (lo + split) + 0.5 * (split - lo) * G.s[g];
-            xs[1 + Q + g] = 0.5 * (split + hi) + 0.5 * (hi - split) * G.s[g];
-        }
-#pragma unroll
-        for (int j = 0; j < 2 * Q + 2; ++j) {
-            double v[NC];
-            eval<K, NC>(o, 0, 2.0 * (xs[j] - c) / w, 1.0, v);
-#pragma unroll
-            for (int q = 0; q < NC; ++q) {
-                st[3 * q + 1] = fmax(st[3 * q + 1], v[q]);
-                st[3 * q + 2] = fmin(st[3 * q + 2], v[q]);
-            }
-        }
+        nu_cell_stats<K, FLUX>(a, g, o, st, true);
     }
-    block_reduce<NV>(st, kind, sh);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int r = 0; r < NV; ++r) a.part[((long long)M * NV + r) * a.nblk + blockIdx.x] = st[r];
-    }
+    nu_store_partials<NC>(a, a.gp ^ 1, M, st);
 }
 
-// avg and sigma of both meshes ([mesh][q] in avg, sig) from the block
-// partials: strided accumulation, a DPP tree per wave, then the waves in
-// order; every workgroup gets the same bits.  All threads must take part.
-template <int NC>
-__device__ inline void nu_statistics(const NuArgs &a, double *sh, double (&avg)[2][NC], double (&sig)[2][NC]) {
-    constexpr int NV = 3 * NC, NW = NB / WAVE;
-    const int t = threadIdx.x, lane = t % WAVE, wave = t / WAVE;
-    // first partial of every row per thread: unconditional loads of valid
-    // elements and a select, so that all 2 NV loads are in flight together
-    double v[2 * NV];
-    const int b0 = min(t, a.nblk - 1);
-#pragma unroll
-    for (int j = 0; j < 2 * NV; ++j) {
-        const double x = a.part[(long long)j * a.nblk + b0];
-        v[j] = t < a.nblk ? x : stat_identity(j % 3);
-    }
-    for (int b = t + NB; b < a.nblk; b += NB) {     // meshes of more than NB * NB cells
-#pragma unroll
-        for (int j = 0; j < 2 * NV; ++j) v[j] = stat_op(j % 3, v[j], a.part[(long long)j * a.nblk + b]);
-    }
-#pragma unroll
-    for (int j = 0; j < 2 * NV; ++j) {
-        v[j] = wave_reduce(j % 3, v[j]);
-        if (lane == WAVE - 1) sh[j * NW + wave] = v[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int M = 0; M < 2; ++M)
-#pragma unroll
-        for (int q = 0; q < NC; ++q) {
-            double v[3];
-#pragma unroll
-            for (int kd = 0; kd < 3; ++kd) {
-                const int r = 3 * q + kd;
-                v[kd] = sh[(M * NV + r) * NW];
-                for (int w = 1; w < NW; ++w) v[kd] = stat_op(kd, v[kd], sh[(M * NV + r) * NW + w]);
-            }
-            avg[M][q] = v[0] / a.L;
-            sig[M][q] = fmax(v[1] - avg[M][q], avg[M][q] - v[2]);
-        }
-}
-
-// delta_K^m from the undamped stage output, then F_tau into the stage output.
+// The end of a call: the state after the executed steps, damped unless no step
+// ran, into the caller's arrays.
 template <int K, int FLUX>
-__global__ void __launch_bounds__(NB) k_nu_oe(NuArgs a) {
-    using F = FluxT<FLUX>;
-    constexpr int NC = F::NC, K1 = K + 1;
-    __shared__ double sh[2 * 3 * NC * (NB / WAVE)];
-    const int M = blockIdx.y, i = blockIdx.x * NB + threadIdx.x;
-    if (a.slot->done) return;            // uniform over the grid
-    double avg[2][NC], sigall[2][NC];
-    if (a.oe && K > 0) nu_statistics<NC>(a, sh, avg, sigall);
-    double bw = 0.0;                     // wave speed at the damped cell average (last stage)
-    if (i < a.n) {
-        const double *own = M == 0 ? a.tC : a.tD, *oth = M == 0 ? a.tD : a.tC;
-        double *dst = M == 0 ? a.oC : a.oD;
-        double u[NC][K1];
-        load_cell<K, NC>(own, a.n, i, u);
-        if (a.oe && K > 0) {
-            const double tau = a.slot->tau;
-            const double c = M == 0 ? a.cC[i] : a.cD[i], w = M == 0 ? a.wC[i] : a.wD[i];
-            double lo, split, hi;
-            pieces(a, M, i, lo, split, hi);
-            double nb[2][NC][K1], cnb[2], wnb[2];
+__global__ void __launch_bounds__(NB) k_nu_final(NuArgs a) {
+    constexpr int NC = FluxT<FLUX>::NC, K1 = K + 1;
+    __shared__ double sh[2 * Rows<NC>::RW * (NB / WAVE)];
+    const long long done = *a.nexec;
+    const int gp = (int)((done * a.ns) & 1);
+    const NuCell c = nu_cell(a);
+    const int M = c.M, i = c.i;
+    const double *own = M == 0 ? a.TC[gp] : a.TD[gp], *oth = M == 0 ? a.TD[gp] : a.TC[gp];
+    const NuGeo g = nu_geo(a, M, i);
+    double u[NC][K1], nb[2][NC][K1];
+    load_cell<K, NC>(own, a.n, i, u);
+    if (a.oe && K > 0 && done > 0) {                 // uniform over the grid
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                int j;
-                neighbour(a, M, i, p, j, cnb[p], wnb[p]);
-                load_cell<K, NC>(oth, a.n, j, nb[p]);
-            }
-            double ub[NC], sig[NC];
+        for (int p = 0; p < 2; ++p) load_cell<K, NC>(oth, a.n, g.j[p], nb[p]);
+        NuPart<NC> pt;
+        nu_stat_load<NC>(a, gp, pt);
+        double avg[2][NC], sig[2][NC], beta;
+        nu_statistics<NC>(a, gp, pt, sh, avg, sig, beta);
+        double isig[NC];
 #pragma unroll
-            for (int q = 0; q < NC; ++q) ub[q] = u[q][0], sig[q] = sigall[M][q];
-            const double beta = F::speed(ub, a.p0);
-            double S = 0.0, fact = 1.0, wp = 1.0 / w;         // w^{m-1}
-#pragma unroll
-            for (int m = 0; m <= K; ++m) {
-                if (m > 1) fact *= m;
-                const double so = pow(2.0 / w, m), sl = pow(2.0 / wnb[0], m), sr = pow(2.0 / wnb[1], m);
-                double oL[NC], oR[NC], vL[NC], vR[NC];
-                eval<K, NC>(u, m, 2.0 * (lo - c) / w, so, oL);
-                eval<K, NC>(u, m, 2.0 * (hi - c) / w, so, oR);
-                eval<K, NC>(nb[0], m, 2.0 * (lo - cnb[0]) / wnb[0], sl, vL);
-                eval<K, NC>(nb[1], m, 2.0 * (hi - cnb[1]) / wnb[1], sr, vR);
-                const double cm = (2.0 * m + 1.0) * wp / ((2.0 * K - 1.0) * fact);
-                double dm = 0.0;
-#pragma unroll
-                for (int q = 0; q < NC; ++q) {
-                    if (sig[q] == 0.0) continue;
-                    const double val = cm * beta * (fabs(oL[q] - vL[q]) + fabs(oR[q] - vR[q])) / sig[q];
-                    dm = fmax(dm, val);
-                }
-                S += dm;
-                wp *= w;
-                if (m >= 1) {
-                    const double fac = exp(-tau * S);
-#pragma unroll
-                    for (int q = 0; q < NC; ++q) u[q][m] *= fac;
-                }
-            }
-        }
-        bool finite = true;
-#pragma unroll
-        for (int q = 0; q < NC; ++q)
-#pragma unroll
-            for (int m = 0; m < K1; ++m) {
-                finite = finite && isfinite(u[q][m]);
-                dst[(long long)(q * K1 + m) * a.n + i] = u[q][m];
-            }
-        double ub[NC];
-#pragma unroll
-        for (int q = 0; q < NC; ++q) ub[q] = u[q][0];
-        if (!finite) __hip_atomic_store(&a.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else if (!F::physical(ub, a.p0)) __hip_atomic_store(&a.err[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (a.wave_out) {
-            bw = F::speed(ub, a.p0);
-            if (!(bw >= 0.0)) bw = INFINITY;             // NaN: reported by k_nu_dt
-        }
+        for (int q = 0; q < NC; ++q) isig[q] = sig[M][q] != 0.0 ? 1.0 / sig[M][q] : 0.0;
+        nu_damp<K, FLUX>(a, g, nb, a.slot[(int)(done & 1) ^ 1].tau, isig, u);
     }
-    // the next step's beta: per-workgroup maxima of the damped averages (every
-    // thread of the workgroup reaches this point)
-    if (a.wave_out) {
-        __shared__ double shw[NB / WAVE];
-        bw = wave_reduce(1, bw);
-        if (threadIdx.x % WAVE == WAVE - 1) shw[threadIdx.x / WAVE] = bw;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double b = shw[0];
-            for (int w = 1; w < NB / WAVE; ++w) b = fmax(b, shw[w]);
-            a.wpart[M * a.nblk + blockIdx.x] = b;
-        }
-    }
+    if (!c.owned) return;
+    double *dst = M == 0 ? a.dstC : a.dstD;
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m < K1; ++m) dst[(long long)(q * K1 + m) * a.n + i] = u[q][m];
 }
 
 struct NuState {
     int n = 0, nc = 0, k = 0;
     double *geo = nullptr;          // edges [n+1] | cC | wC | cD | wD
-    double *buf = nullptr;          // S1 (C|D) | S2 (C|D) | T (C|D)
-    double *part = nullptr, *wpart = nullptr;
-    Slot *slot = nullptr;
+    double *buf = nullptr;          // T0 (C|D) | T1 (C|D) | U (C|D)
+    double *part = nullptr;
+    NuSlot *slot = nullptr;
     long long *nexec = nullptr;
     int *err = nullptr;
     long long *nexec_h = nullptr;
-    Slot *slot_h = nullptr;
+    NuSlot *slot_h = nullptr;
     int *err_h = nullptr;
-    // POLL steps after the first, captured once per (state arrays, t_end, fixed step, h_max)
+    // POLL steps from an even step index, captured once per (t_end, fixed step, h_max)
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec = nullptr;
-    const double *g_uC = nullptr, *g_uD = nullptr;
     double g_tend = 0.0, g_dt = 0.0, g_hmax = 0.0;
 };
 
@@ -455,7 +574,6 @@ void free_state(NuState *s) {
     (void)hipFree(s->geo);
     (void)hipFree(s->buf);
     (void)hipFree(s->part);
-    (void)hipFree(s->wpart);
     (void)hipFree(s->slot);
     (void)hipFree(s->nexec);
     (void)hipFree(s->err);
@@ -467,38 +585,31 @@ void free_state(NuState *s) {
     delete s;
 }
 
-template <int K, int FLUX>
-void launch_stage(const NuArgs &a, dim3 grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_nu_stage<K, FLUX>), grid, dim3(NB), 0, st, a);
-}
-template <int K, int FLUX>
-void launch_oe(const NuArgs &a, dim3 grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_nu_oe<K, FLUX>), grid, dim3(NB), 0, st, a);
-}
-
+// which: 0 initial statistics, 1 stage, 2 final
 template <int FLUX>
-void launch_step_kernels(int which, const NuArgs &a, dim3 grid, hipStream_t st) {
-    // which: 0 stage, 1 oe
+void launch_flux(int which, const NuArgs &a, hipStream_t st) {
+    const dim3 grid(a.nblk), block(NB);
     switch (a.k) {
-    case 0: which == 0 ? launch_stage<0, FLUX>(a, grid, st) : launch_oe<0, FLUX>(a, grid, st); break;
-    case 1: which == 0 ? launch_stage<1, FLUX>(a, grid, st) : launch_oe<1, FLUX>(a, grid, st); break;
-    case 2: which == 0 ? launch_stage<2, FLUX>(a, grid, st) : launch_oe<2, FLUX>(a, grid, st); break;
-    default: which == 0 ? launch_stage<3, FLUX>(a, grid, st) : launch_oe<3, FLUX>(a, grid, st); break;
+#define NU_CASE(K)                                                                              \
+    case K:                                                                                     \
+        if (which == 0) hipLaunchKernelGGL((k_nu_init<K, FLUX>), grid, block, 0, st, a);        \
+        else if (which == 1) hipLaunchKernelGGL((k_nu_step<K, FLUX>), grid, block, 0, st, a);   \
+        else hipLaunchKernelGGL((k_nu_final<K, FLUX>), grid, block, 0, st, a);                  \
+        break;
+    NU_CASE(0)
+    NU_CASE(1)
+    NU_CASE(2)
+    default:
+    NU_CASE(3)
+#undef NU_CASE
     }
 }
 
-void launch_kind(int which, const NuArgs &a, dim3 grid, hipStream_t st) {
-    if (a.flux == OECDG_FLUX_ADVECTION) launch_step_kernels<0>(which, a, grid, st);
-    else if (a.flux == OECDG_FLUX_BURGERS) launch_step_kernels<1>(which, a, grid, st);
-    else launch_step_kernels<2>(which, a, grid, st);
+void launch_kind(int which, const NuArgs &a, hipStream_t st) {
+    if (a.flux == OECDG_FLUX_ADVECTION) launch_flux<0>(which, a, st);
+    else if (a.flux == OECDG_FLUX_BURGERS) launch_flux<1>(which, a, st);
+    else launch_flux<2>(which, a, st);
 }
-
-void launch_wave(const NuArgs &a, dim3 grid, hipStream_t st) {
-    if (a.flux == OECDG_FLUX_ADVECTION) hipLaunchKernelGGL(k_nu_wave<0>, grid, dim3(NB), 0, st, a);
-    else if (a.flux == OECDG_FLUX_BURGERS) hipLaunchKernelGGL(k_nu_wave<1>, grid, dim3(NB), 0, st, a);
-    else hipLaunchKernelGGL(k_nu_wave<2>, grid, dim3(NB), 0, st, a);
-}
-
 
 }  // namespace
 
@@ -534,7 +645,8 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
     }
     hipStream_t st = handle_stream(h);
     NuState *s = static_cast<NuState *>(handle_extnu(h));
-    const int nblk = (n + NB - 1) / NB;
+    const int nblk = (n + CPB - 1) / CPB;
+    const int rows = 2 * (3 * nc + 1);          // partial rows of both meshes
     const size_t S1 = (size_t)nc * K1 * n;      // one mesh
     if (!s) {
         s = new NuState();
@@ -542,12 +654,11 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
         handle_extnu(h) = s;
         if (hipMalloc(&s->geo, sizeof(double) * (5 * (size_t)n + 1)) != hipSuccess ||
             hipMalloc(&s->buf, sizeof(double) * 6 * S1) != hipSuccess ||
-            hipMalloc(&s->part, sizeof(double) * 2 * 9 * (size_t)nblk) != hipSuccess ||
-            hipMalloc(&s->wpart, sizeof(double) * 2 * (size_t)nblk) != hipSuccess ||
-            hipMalloc(&s->slot, sizeof(Slot)) != hipSuccess || hipMalloc(&s->err, sizeof(int) * 4) != hipSuccess ||
+            hipMalloc(&s->part, sizeof(double) * 2 * rows * (size_t)nblk) != hipSuccess ||
+            hipMalloc(&s->slot, 2 * sizeof(NuSlot)) != hipSuccess || hipMalloc(&s->err, sizeof(int) * 4) != hipSuccess ||
             hipMalloc(&s->nexec, sizeof(long long)) != hipSuccess ||
             hipHostMalloc(&s->nexec_h, sizeof(long long)) != hipSuccess ||
-            hipHostMalloc(&s->slot_h, sizeof(Slot)) != hipSuccess ||
+            hipHostMalloc(&s->slot_h, 2 * sizeof(NuSlot)) != hipSuccess ||
             hipHostMalloc(&s->err_h, sizeof(int) * 4) != hipSuccess) {
             destroy_nu(h);
             return handle_fail(h, OECDG_ENOMEM, "non-uniform mesh buffers");
@@ -563,64 +674,64 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
         cD[j] = 0.5 * (cl + cC[j]);
         wD[j] = 0.5 * (wl + wC[j]);
     }
-    NUCHK(h, hipMemcpyAsync(s->geo, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice, st));
-    Slot s0{0.0, 0.0, 0.0, 0, 0};
-    NUCHK(h, hipMemcpyAsync(s->slot, &s0, sizeof(Slot), hipMemcpyHostToDevice, st));
-    NUCHK(h, hipMemsetAsync(s->err, 0, sizeof(int) * 4, st));
-    NUCHK(h, hipMemsetAsync(s->nexec, 0, sizeof(long long), st));
-
     NuArgs a{};
     a.n = n, a.k = k, a.flux = d.flux, a.oe = d.oe;
+    const int ns = rk == 1 ? 1 : rk == 2 ? 2 : 3;
+    a.ns = ns;
     a.L = L, a.hmax = hmax, a.cfl = d.cfl, a.t_end = t_end, a.dt_fixed = dt_fixed;
     a.p0 = d.flux_param[0];                      // advection speed or gamma
     a.edges = s->geo, a.cC = s->geo + n + 1, a.wC = a.cC + n, a.cD = a.wC + n, a.wD = a.cD + n;
-    a.part = s->part, a.wpart = s->wpart, a.slot = s->slot, a.nexec = s->nexec, a.err = s->err, a.nblk = nblk;
-    double *S1C = s->buf, *S1D = S1C + S1, *S2C = S1D + S1, *S2D = S2C + S1, *TC = S2D + S1, *TD = TC + S1;
-    a.tC = TC, a.tD = TD;
-    const dim3 grid(nblk, 2);
-    const int ns = rk == 1 ? 1 : rk == 2 ? 2 : 3;
-    // the kernels of one step; every step after the first has the same arguments
-    auto enqueue_step = [&](bool first, hipStream_t q) {
+    a.part = s->part, a.slot = s->slot, a.nexec = s->nexec, a.err = s->err, a.nblk = nblk;
+    a.TC[0] = s->buf, a.TD[0] = a.TC[0] + S1, a.TC[1] = a.TD[0] + S1, a.TD[1] = a.TC[1] + S1;
+    a.UC = a.TD[1] + S1, a.UD = a.UC + S1;
+    a.dstC = uC, a.dstD = uD;
+
+    NUCHK(h, hipMemcpyAsync(s->geo, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice, st));
+    const NuSlot s0[2] = {{0.0, 0.0, 0.0, 0, 0}, {0.0, 0.0, 0.0, 0, 0}};
+    NUCHK(h, hipMemcpyAsync(s->slot, s0, sizeof(s0), hipMemcpyHostToDevice, st));
+    NUCHK(h, hipMemsetAsync(s->err, 0, sizeof(int) * 4, st));
+    NUCHK(h, hipMemsetAsync(s->nexec, 0, sizeof(long long), st));
+    NUCHK(h, hipMemcpyAsync(a.TC[0], uC, sizeof(double) * S1, hipMemcpyDeviceToDevice, st));
+    NUCHK(h, hipMemcpyAsync(a.TD[0], uD, sizeof(double) * S1, hipMemcpyDeviceToDevice, st));
+    launch_kind(0, a, st);                       // statistics of the initial data (parity 0)
+
+    // the stage launches of step n; they depend on n only through the parities
+    // of n and of n * ns, and through n == 0
+    auto enqueue_step = [&](int64_t n_step, hipStream_t q) {
         NuArgs b = a;
-        b.unC = uC, b.unD = uD;
-        if (first) launch_wave(b, grid, q);          // later steps: written by the last stage's k_nu_oe
-        b.pending = !first;
-        hipLaunchKernelGGL(k_nu_dt, dim3(1), dim3(WAVE), 0, q, b);
+        b.sp = (int)(n_step & 1);
+        b.first = n_step == 0;
         for (int l = 0; l < ns; ++l) {
             const RKStage r = rk_stage(rk, l);
+            b.l = l;
+            b.gp = (int)((n_step * ns + l) & 1);
             b.cn = l == 0 ? 0.0 : r.cn, b.cw = r.cw, b.dd = r.d;
-            b.ulC = l == 0 ? uC : (l == 1 ? S1C : S2C);
-            b.ulD = l == 0 ? uD : (l == 1 ? S1D : S2D);
-            const bool lastst = l == ns - 1;
-            b.wave_out = lastst;
-            b.oC = lastst ? uC : (l == 0 ? S1C : S2C);
-            b.oD = lastst ? uD : (l == 0 ? S1D : S2D);
-            launch_kind(0, b, grid, q);
-            launch_kind(1, b, grid, q);
+            b.first = n_step == 0 && l == 0;
+            launch_kind(1, b, q);
         }
     };
-    // whole blocks of POLL steps (from a multiple of POLL) replay a captured graph
-    if (s->gexec && (s->g_uC != uC || s->g_uD != uD || s->g_tend != t_end || s->g_dt != dt_fixed || s->g_hmax != hmax))
+    // whole blocks of POLL steps from a multiple of POLL (even, > 0) replay a captured graph
+    if (s->gexec && (s->g_tend != t_end || s->g_dt != dt_fixed || s->g_hmax != hmax))
         (void)hipGraphExecDestroy(s->gexec), s->gexec = nullptr;
     auto ensure_graph = [&]() -> int {
         if (s->gexec) return OECDG_OK;
         if (!s->cap) NUCHK(h, hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
         hipGraph_t gr = nullptr;
         NUCHK(h, hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
-        for (int j = 0; j < POLL; ++j) enqueue_step(false, s->cap);
+        for (int j = 0; j < POLL; ++j) enqueue_step(POLL + j, s->cap);
         NUCHK(h, hipStreamEndCapture(s->cap, &gr));
         const hipError_t e = hipGraphInstantiate(&s->gexec, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         NUCHK(h, e);
-        s->g_uC = uC, s->g_uD = uD, s->g_tend = t_end, s->g_dt = dt_fixed, s->g_hmax = hmax;
+        s->g_tend = t_end, s->g_dt = dt_fixed, s->g_hmax = hmax;
         return OECDG_OK;
     };
     int64_t step = 0;
     while (nsteps < 0 || step < nsteps) {
         if (step > 0 && step % POLL == 0 && !std::isinf(t_end)) {
-            NUCHK(h, hipMemcpyAsync(s->slot_h, s->slot, sizeof(Slot), hipMemcpyDeviceToHost, st));
+            NUCHK(h, hipMemcpyAsync(s->slot_h, s->slot, 2 * sizeof(NuSlot), hipMemcpyDeviceToHost, st));
             NUCHK(h, hipStreamSynchronize(st));
-            if (s->slot_h->done) break;
+            if (s->slot_h[step & 1].stop) break;
         }
         if (step > 0 && step % POLL == 0 && (nsteps < 0 || nsteps - step >= POLL)) {
             const int rc = ensure_graph();
@@ -628,21 +739,21 @@ int run_nonuniform(oecdg_handle *h, const double *edges_h, double *uC, double *u
             NUCHK(h, hipGraphLaunch(s->gexec, st));
             step += POLL;
         } else {
-            enqueue_step(step == 0, st);
+            enqueue_step(step, st);
             ++step;
         }
         NUCHK(h, hipGetLastError());
     }
-    if (step > 0) hipLaunchKernelGGL(k_nu_advance, dim3(1), dim3(1), 0, st, a);
+    launch_kind(2, a, st);                       // the state reached, damped, into (uC, uD)
     NUCHK(h, hipGetLastError());
-    NUCHK(h, hipMemcpyAsync(s->slot_h, s->slot, sizeof(Slot), hipMemcpyDeviceToHost, st));
+    NUCHK(h, hipMemcpyAsync(s->slot_h, s->slot, 2 * sizeof(NuSlot), hipMemcpyDeviceToHost, st));
     NUCHK(h, hipMemcpyAsync(s->err_h, s->err, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
     NUCHK(h, hipMemcpyAsync(s->nexec_h, s->nexec, sizeof(long long), hipMemcpyDeviceToHost, st));
     NUCHK(h, hipStreamSynchronize(st));
     if (s->err_h[2]) return handle_fail(h, OECDG_EINVAL, "wave speed is zero or not finite");
     if (s->err_h[0]) return handle_fail(h, OECDG_ENONFINITE, "non-finite coefficient");
     if (s->err_h[1]) return handle_fail(h, OECDG_ENONPHYSICAL, "non-physical cell average");
-    if (t_out) *t_out = s->slot_h->t;
+    if (t_out) *t_out = s->slot_h[step & 1].t;
     if (steps_out) *steps_out = *s->nexec_h;
     return OECDG_OK;
 }

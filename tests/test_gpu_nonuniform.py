@@ -2,7 +2,7 @@
 against the non-uniform oracle.
 
 Meshes: the seeded random mesh (widths ratio <= 1.5) and the smooth grading of
-amplitude 0.3; sizes span several workgroups of 128 cells with a ragged tail.
+amplitude 0.3; sizes span several workgroups of 64 cells with a ragged tail.
 Bar: relative L-infinity error <= 1e-10 after the run, equal step counts and
 final times.
 """
@@ -55,7 +55,7 @@ def _euler(edges, k):
 @pytest.mark.parametrize("kind", ["graded", "random"])
 @pytest.mark.parametrize("k,cfl", [(1, 0.2), (2, 0.1), (3, 0.08)])
 def test_advection_run(kind, k, cfl):
-    """sin x on [0, 2 pi], N = 600 (four full workgroups of 128 cells and a ragged one), to T = 1."""
+    """sin x on [0, 2 pi], N = 600 (nine full workgroups of 64 cells and a ragged one), to T = 1."""
     edges = _mesh(kind, 600)
     prob, uC, uD = inputs.advection_sine_edges(edges, k)
     gC, gD, t, n = _gpu(prob, edges, uC, uD, cfl, t_end=1.0)
@@ -178,8 +178,9 @@ def test_bench_workload_full_size():
 
 
 def test_more_workgroups_than_threads():
-    """N = 70000: 547 workgroups per mesh, more than the 128 threads that reduce
-    their statistics, so the strided part of that reduction runs too."""
+    """N = 70000: 1094 workgroups, more than the 384 partials per row that the
+    192 threads reducing their statistics load at first, so the strided part of
+    that reduction runs too."""
     edges = _mesh("random", 70000, seed=13)
     prob, uC, uD = inputs.advection_sine_edges(edges, 1, freq=3)
     gC, gD, t, n = _gpu(prob, edges, uC, uD, 0.2, nsteps=5)
