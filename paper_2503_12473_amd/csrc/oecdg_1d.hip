@@ -2,21 +2,28 @@
 //
 // One workgroup owns a tile of T primal cells [i0, i0+T) and the T dual cells
 // [i0, i0+T) that interleave with them (dual cell j is centred on the left
-// edge of primal cell j).  A stage kernel for stage l of step n
-//   1. reduces the per-tile partial statistics left by the previous stage
-//      (fixed order, so every workgroup gets bit-identical avg/sigma/beta),
-//      and at l = 0 derives tau^n and tau_max^n (Sec. 2.1, tau = C h / beta);
-//   2. stages its tile plus a two-cell halo of the pre-damping input into LDS
-//      (coalesced structure-of-arrays loads);
-//   3. applies the OE step F_tau of the previous stage in LDS (Sec. 2.2,
-//      OEstep2D: delta_K^m from the primal/dual difference at the cell edges,
-//      then the exact exponential a_j *= exp(-tau sum_{m<=j} delta^m));
-//   4. evaluates the CDG operator (equcdg): the overlap coupling with
-//      1/tau_max, the volume integral of f(w) with k+1 Gauss nodes on each
-//      half cell, and the point fluxes of the other mesh at the cell edges;
+// edge of primal cell j), one thread per cell, and one more wave whose lanes
+// take the cells next to the tile that its operator reads (the primal cells
+// i0-1 and i0+T, the dual cell i0+T).  A stage kernel for stage l of step n
+//   1. issues every independent load at once: the step records, the previous
+//      stage's per-tile partial statistics, and each thread's cell and the two
+//      cells of the other mesh that overlap it, all undamped (ghost cells at
+//      non-periodic ends built from the end cells);
+//   2. reduces the partial statistics (fixed order, so every workgroup gets
+//      bit-identical avg/sigma/beta), and at l = 0 derives tau^n and
+//      tau_max^n (Sec. 2.1, tau = C h / beta);
+//   3. applies the OE step F_tau of the previous stage to its cell in
+//      registers (Sec. 2.2, OEstep2D: delta_K^m from the primal/dual
+//      difference at the cell edges, then the exact exponential
+//      a_j *= exp(-tau sum_{m<=j} delta^m)) and puts the damped cell in LDS;
+//   4. evaluates the CDG operator (equcdg) on its cell from the damped cells in
+//      LDS: the overlap coupling with 1/tau_max, the volume integral of f(w)
+//      with k+1 Gauss nodes on each half cell, and the point fluxes of the other
+//      mesh at the cell edges;
 //   5. forms the RK combination of eq:RKCDG (SSP-RK3 by default; forward
 //      Euler, SSP-RK2 or classical RK4 on request) and writes the stage output;
-//   6. writes the tile's partial statistics of that output for the next stage.
+//   6. writes the tile's partial statistics of that output for the next stage
+//      (DPP reductions within the waves that hold each mesh).
 // The OE of the last stage of a run is applied by the final kernel.
 #include "oecdg_device.h"
 #include "oecdg_internal.h"
@@ -27,49 +34,9 @@
 
 namespace oecdg {
 
-// Threads per workgroup: two per cell (one per half cell) for the T primal
-// and the T dual cells of a tile.
-__host__ __device__ constexpr int nthreads(int T) { return 4 * T; }
-// A mesh with nd = np + 1 dual cells and np a multiple of T has one dual cell
-// (np) beyond np / T full tiles.  Rather than a tile of its own (one
-// workgroup more than there are CUs for the 16384-cell workload: 15.0 instead
-// of 12.8 us per stage), launches of such handles carry one more wave, whose
-// first lane pair updates that cell in the instance's last tile.  Tiles of
-// 128 keep the extra tile (a fifth wave per SIMD would cap the registers).
-__host__ __device__ constexpr int max_threads(int T) { return nthreads(T) + tail_threads(T); }
-
-// Segmented reduction over the two halves of a workgroup (primal threads
-// [0, H), dual threads [H, 2H)), H a multiple of the wave size.  NV values per
-// thread, kinds given.  On return the threads tid == 0 (primal) and tid == H
-// (dual) hold the half's result (waves combined in order).  xwave: the
-// launch's extra wave (threads [2H, 2H + WAVE)) carries a cell and reduces its
-// own values, left in scratch at wave 2H / WAVE; otherwise it does no work here.
-// scratch: NV * (2H / WAVE + 1) doubles of LDS.
-template <int H, int NV>
-__device__ void reduce_halves(double (&v)[NV], const int (&kind)[NV], double *scratch, bool xwave, bool xwl) {
-    static_assert(H % WAVE == 0, "halves are whole waves");
-    constexpr int WPH = H / WAVE;          // waves per half
-    const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
-    if (!xwl || tid < 2 * H || xwave) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) v[j] = wave_reduce(kind[j], v[j]);
-        if (lane == WAVE - 1) {
-#pragma unroll
-            for (int j = 0; j < NV; ++j) scratch[wave * NV + j] = v[j];
-        }
-    }
-    __syncthreads();
-    if (tid == 0 || tid == H) {
-        const int w0 = tid / WAVE;
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            double x = scratch[w0 * NV + j];
-            for (int w = 1; w < WPH; ++w) x = stat_op(kind[j], x, scratch[(w0 + w) * NV + j]);
-            v[j] = x;
-        }
-    }
-    __syncthreads();
-}
+// Threads per workgroup: one per cell for the T primal and the T dual cells of
+// a tile, and one wave for the cells next to it.
+__host__ __device__ constexpr int nthreads(int T) { return 2 * T + WAVE; }
 
 // ------------------------------------------------------------ cell kernels ---
 
@@ -178,203 +145,279 @@ __device__ inline void cdg_rate_half(const double (&nb)[FluxT<FLUX>::NC][K + 1],
 
 // ------------------------------------------------------------ tile pieces ---
 
-template <int K, int NC, int W>
-__device__ inline void lds_cell(const double *s, int li, double (&c)[NC][K + 1]) {
-#pragma unroll
-    for (int q = 0; q < NC; ++q)
-#pragma unroll
-        for (int m = 0; m <= K; ++m) c[q][m] = s[(q * (K + 1) + m) * W + li];
-}
-
-// Element e of the tile's LDS image of the pre-damping input: primal cells
-// [i0-1, i0+T] (rows q*(k+1)+m of length T+2), then dual cells [i0-1, i0+T].
-// Periodic wrap; outflow: constant-extension ghosts for primal -1 and np
-// (reflective walls load the same and mirror_ghosts overwrites them); inflow:
-// the instance's fixed ghost states; zeros for dual cells that do not exist.
 // Sign of coefficient (q, m) of a reflective ghost: (-1)^m, and -1 more for
 // the momentum (q = 1 of the Euler system).
 __device__ inline double mirror_sign(int q, int m) { return ((m & 1) ^ (q == 1)) ? -1.0 : 1.0; }
 
-// GH: kernels of the Euler flux with wall or inflow ghosts (FluxT<3>), the
-// only ones that carry the inflow ghost states.
-template <int K, int NC, int T, bool GH>
-__device__ inline double tile_elem(const Inst1D &I, int i0, const double *__restrict__ inC,
-                                   const double *__restrict__ inD, int e) {
-    constexpr int W = T + 2, K1 = K + 1, PER = NC * K1 * W;
-    const int mesh = e >= PER;
-    const int r = e - mesh * PER;
-    const int qm = r / W;
-    const int li = r - qm * W;
-    int gi = i0 - 1 + li;
-    if (mesh == 0) {
-        const int np = I.np;
-        if (I.bc == 0) {
-            gi = gi < 0 ? gi + np : (gi >= np ? gi - np : gi);
-            if (gi < 0 || gi >= np) gi = ((gi % np) + np) % np;   // mesh shorter than a tile
-            return inC[(long long)qm * np + gi];
-        }
-        if (gi < 0 || gi >= np) {
-            if (qm % K1 != 0) return 0.0;
-            if constexpr (GH) {
-                if (I.bc == 3) return I.gin[gi < 0 ? 0 : 1][qm / K1];
+// Pre-damping coefficients of cell g of mesh `mesh` of instance I (input
+// arrays inC, inD of the instance).  A primal index outside [0, np) (the ends
+// of non-periodic meshes) is the ghost next to the end cell e: outflow the
+// mean of e with zero higher modes, inflow the instance's fixed ghost state,
+// reflective walls the mirror image of e (kernels of the walled Euler flux,
+// FLUX == 3, which alone carry the wall and inflow ghosts).  A dual index
+// outside [0, nd) reads as zeros.  Every load is of a valid element, with no
+// branch between the loads.
+template <int K, int FLUX>
+__device__ inline void cell_pre(const Inst1D &I, int mesh, int g, const double *__restrict__ inC,
+                                const double *__restrict__ inD, double (&u)[FluxT<FLUX>::NC][K + 1]) {
+    constexpr int NC = FluxT<FLUX>::NC, K1 = K + 1;
+    const int n = mesh == 0 ? I.np : I.nd;
+    const bool in = g >= 0 && g < n;
+    const int e = g < 0 ? 0 : (g >= n ? n - 1 : g);
+    const double *src = mesh == 0 ? inC : inD;
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m < K1; ++m) {
+            const double x = src[(long long)(q * K1 + m) * n + e];
+            double v = m == 0 ? x : 0.0;                 // outflow ghost: constant extension
+            if constexpr (FLUX == 3) {
+                if (I.bc == 2) v = mirror_sign(q, m) * x;
+                else if (I.bc == 3) v = m == 0 ? I.gin[g < 0 ? 0 : 1][q] : 0.0;
             }
-            return inC[(long long)qm * np + (gi < 0 ? 0 : np - 1)];
+            u[q][m] = in ? x : (mesh == 1 ? 0.0 : v);
         }
-        return inC[(long long)qm * np + gi];
+}
+
+// The cell of this thread in the tile of instance I that starts at index i0,
+// and its LDS column (both meshes: column g - i0 + 1 of cell g).  Threads
+// [0, T): primal cell i0 + tid; [T, 2T): dual cell i0 + tid - T; the last
+// wave: lane 0 the primal cell i0 - 1, lane 1 the dual cell i0 + T, lane 2 the
+// primal cell i0 + T (the neighbours that the tile's operator reads).  g is
+// wrapped on periodic meshes; elsewhere a primal g of -1 or np is a ghost and a
+// dual g of nd or more no cell.  owned: the thread updates its cell (the dual
+// cell i0 + T only as the instance's dual cell np carried by its last tile in a
+// launch with xwl).
+struct TCell {
+    int mesh, col, g;
+    bool has, owned;
+};
+template <int T>
+__device__ inline TCell tile_cell(const Inst1D &I, int tile, int i0, bool xwl) {
+    const int tid = threadIdx.x;
+    TCell c;
+    int g;
+    if (tid < 2 * T) {
+        c.mesh = tid < T ? 0 : 1;
+        const int s = tid - c.mesh * T;
+        g = i0 + s;
+        c.col = s + 1;
+        c.has = true;
+        c.owned = g < (c.mesh == 0 ? I.np : I.nd);
+    } else {
+        const int lane = tid - 2 * T;
+        c.mesh = lane == 1 ? 1 : 0;
+        g = lane == 0 ? i0 - 1 : i0 + T;
+        c.col = lane == 0 ? 0 : T + 1;
+        c.has = lane < 3;
+        c.owned = xwl && lane == 1 && I.tail && tile == I.tile0 + I.ntiles - 1 && g < I.nd;
     }
-    const int nd = I.nd;
-    if (I.bc == 0) {
-        gi = gi < 0 ? gi + nd : (gi >= nd ? gi - nd : gi);
-        if (gi < 0 || gi >= nd) gi = ((gi % nd) + nd) % nd;
+    if (I.bc == 0) {                         // periodic (meshes shorter than a tile too)
+        const int n = c.mesh == 0 ? I.np : I.nd;
+        g = g < 0 ? g + n : (g >= n ? g - n : g);
+        if (g < 0 || g >= n) g = ((g % n) + n) % n;
     }
-    return (gi >= 0 && gi < nd) ? inD[(long long)qm * nd + gi] : 0.0;
+    c.g = g;
+    return c;
 }
 
-// Reflective walls (Euler): primal ghosts -1 and np in the LDS tile become the
-// mirror images of cells 0 and np-1 (mode m times (-1)^m, the momentum
-// negated).  Only kernels of the walled Euler flux (FluxT<3>) contain this,
-// and only their tiles that hold a ghost call it (a workgroup-uniform test),
-// followed by a barrier; damp_tile mirrors the damped end cells again.
-template <int K, int NC, int T>
-__device__ inline bool has_wall_ghost(const Inst1D &I, int i0) {
-    return I.bc == 2 && (i0 == 0 || I.np - i0 <= T);
-}
-
-template <int K, int NC, int T>
-__device__ inline void mirror_ghosts(const Inst1D &I, int i0, double *sC) {
-    constexpr int W = T + 2, K1 = K + 1;
-    const int t = threadIdx.x;
-    if (t < NC * K1) {
-        const double sg = mirror_sign(t / K1, t % K1);
-        if (i0 == 0) sC[t * W] = sg * sC[t * W + 1];
-        const int lr = I.np - i0;                  // LDS column of cell np-1; its ghost is the next one
-        if (lr >= 0 && lr <= T) sC[t * W + lr + 1] = sg * sC[t * W + lr];
+// Indices of the two cells of the other mesh that overlap cell g of `mesh`
+// (left, right): primal g -> dual g, g + 1; dual g -> primal g - 1, g
+// (periodic meshes wrapped; a primal -1 or np is a ghost for cell_pre).
+__device__ inline void overlap_cells(const Inst1D &I, int mesh, int g, int &l, int &r) {
+    if (mesh == 0) {
+        l = g;
+        r = g + 1;
+        if (I.bc == 0 && r >= I.nd) r -= I.nd;
+    } else {
+        l = g - 1;
+        r = g;
+        if (I.bc == 0 && l < 0) l += I.np;
     }
 }
 
-template <int K, int NC, int T, bool GH>
-__device__ inline void load_tile(const Inst1D &I, int i0, const double *__restrict__ inC,
-                                 const double *__restrict__ inD, double *s, bool xwl) {
-    constexpr int PER = NC * (K + 1) * (T + 2);
-    if (!xwl || threadIdx.x < nthreads(T))
-        for (int e = threadIdx.x; e < 2 * PER; e += nthreads(T)) s[e] = tile_elem<K, NC, T, GH>(I, i0, inC, inD, e);
+// This thread's cell, damped: its undamped coefficients and those of the two
+// cells of the other mesh that overlap it are loaded (issued together), and
+// after the caller has the statistics, damp_cell applies F_tau.  A primal ghost
+// of a reflective wall is the mirror image of the damped end cell, so its
+// thread damps the end cell and mirrors it; the other ghosts need no damping
+// (their only nonzero mode is the mean).
+template <int K, int FLUX>
+struct CellIn {
+    static constexpr int NC = FluxT<FLUX>::NC;
+    double own[NC][K + 1], nl[NC][K + 1], nr[NC][K + 1];
+    bool real;                               // a cell of the mesh (not a ghost, not beyond nd)
+    bool mirror;                             // a reflective-wall ghost: damp the end cell, then mirror it
+};
+
+template <int K, int FLUX>
+__device__ inline void load_cell_in(const Inst1D &I, const TCell &c, const double *__restrict__ inC,
+                                    const double *__restrict__ inD, CellIn<K, FLUX> &ci) {
+    const int n = c.mesh == 0 ? I.np : I.nd;
+    ci.real = c.has && c.g >= 0 && c.g < n;
+    ci.mirror = false;
+    if constexpr (FLUX == 3) ci.mirror = c.has && c.mesh == 0 && !ci.real && I.bc == 2;
+    // the cell whose values (and neighbours) are loaded: itself, or the end
+    // cell next to a wall ghost
+    const int sg = ci.mirror ? (c.g < 0 ? 0 : I.np - 1) : c.g;
+    cell_pre<K, FLUX>(I, c.mesh, sg, inC, inD, ci.own);
+    int l, r;
+    overlap_cells(I, c.mesh, ci.real || ci.mirror ? sg : 0, l, r);
+    cell_pre<K, FLUX>(I, 1 - c.mesh, l, inC, inD, ci.nl);
+    cell_pre<K, FLUX>(I, 1 - c.mesh, r, inC, inD, ci.nr);
 }
 
-// Apply F_tau in LDS to primal cells [i0-1, i0+T-1] and dual cells [i0, i0+T]
-// (the cells whose damped values the tile's operator needs), one cell per
-// thread, all damping factors computed from the pre-damping values first.
-template <int K, int FLUX, int T>
-__device__ inline void damp_tile(const Inst1D &I, int i0, double *sC, double *sD, const double (*sig)[3],
-                                 double tau) {
+template <int K, int FLUX>
+__device__ inline void damp_cell(const Inst1D &I, const TCell &c, CellIn<K, FLUX> &ci, const double (*sig)[3],
+                                 double tau, bool damp) {
     using F = FluxT<FLUX>;
-    constexpr int NC = F::NC, W = T + 2, K1 = K + 1;
-    static_assert(nthreads(T) >= 2 * T + 2, "one damping item per thread");
-    const double hinv = 1.0 / I.h;
-    double fac[K1];
-    const int w = threadIdx.x;
-    const int mesh = w < T + 1 ? 0 : 1;
-    const int li = mesh == 0 ? w : w - T;          // primal 0..T, dual 1..T+1
-    const int gi = i0 - 1 + li;
-    bool active = w < 2 * T + 2;
-    if (active && I.bc != 0) active = mesh == 0 ? (gi >= 0 && gi < I.np) : (gi >= 0 && gi < I.nd);
-    if (active) {
-        double own[NC][K1], nl[NC][K1], nr[NC][K1];
-        if (mesh == 0) {
-            lds_cell<K, NC, W>(sC, li, own);
-            lds_cell<K, NC, W>(sD, li, nl);
-            lds_cell<K, NC, W>(sD, li + 1, nr);
-        } else {
-            lds_cell<K, NC, W>(sD, li, own);
-            lds_cell<K, NC, W>(sC, li - 1, nl);
-            lds_cell<K, NC, W>(sC, li, nr);
-        }
+    constexpr int NC = F::NC, K1 = K + 1;
+    if (damp && (ci.real || ci.mirror)) {
         double ubar[NC];
 #pragma unroll
-        for (int q = 0; q < NC; ++q) ubar[q] = own[q][0];
+        for (int q = 0; q < NC; ++q) ubar[q] = ci.own[q][0];
         const double beta = F::speed(ubar, I.p0);
-        oe_factors<K, NC>(own, nl, nr, beta, sig[mesh], hinv, tau, fac);
-    }
-    __syncthreads();
-    if (active) {
-        double *s = mesh == 0 ? sC : sD;
+        double fac[K1];
+        oe_factors<K, NC>(ci.own, ci.nl, ci.nr, beta, sig[c.mesh], 1.0 / I.h, tau, fac);
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 1; m <= K; ++m) s[(q * K1 + m) * W + li] *= fac[m];
-        // reflective walls: the ghost next to an end cell mirrors its damped values
-        if constexpr (FLUX == 3) {
-            if (I.bc == 2 && mesh == 0 && (gi == 0 || gi == I.np - 1)) {
-                const int lg = gi == 0 ? li - 1 : li + 1;
-#pragma unroll
-                for (int q = 0; q < NC; ++q)
-#pragma unroll
-                    for (int m = 1; m <= K; ++m)
-                        s[(q * K1 + m) * W + lg] = mirror_sign(q, m) * s[(q * K1 + m) * W + li];
-            }
-        }
+            for (int m = 1; m <= K; ++m) ci.own[q][m] *= fac[m];
     }
-    __syncthreads();
+    if (ci.mirror) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 0; m <= K; ++m) ci.own[q][m] *= mirror_sign(q, m);
+    }
 }
 
-// Partial statistics of the tile's output: each thread of a cell's pair takes
-// half of the sigma sample points (hf = 1: the right-half nodes and xi = 1;
-// hf = 0: their mirror images, through the sign flip of odd modes); the cell
-// average counts once (hf = 0).  Reduced over the primal and dual halves of the
-// workgroup and written to column tile of part[row][tile].
-template <int K, int FLUX, int T>
-__device__ inline void tile_partials(const Inst1D &I, bool valid, int mesh, int hf,
-                                     const double (&out)[FluxT<FLUX>::NC][K + 1], double *part, long long ntot,
-                                     int tile, double *scratch, bool xwave, bool xwl) {
+template <int K, int NC, int W>
+__device__ inline void lds_cell(const double *s, int col, double (&c)[NC][K + 1]) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m <= K; ++m) c[q][m] = s[(q * (K + 1) + m) * W + col];
+}
+
+template <int K, int NC, int W>
+__device__ inline void lds_put(double *s, int col, const double (&c)[NC][K + 1]) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m <= K; ++m) s[(q * (K + 1) + m) * W + col] = c[q][m];
+}
+
+// Partial statistics of one cell's output (valid: an owned cell; otherwise the
+// identities): the cell average, max and min over the sigma sample points
+// (both halves: the right-half nodes and xi = 1, and their mirror images
+// through the sign flip of odd modes), and the wave speed at the average.
+template <int K, int FLUX>
+__device__ inline void cell_stats(const Inst1D &I, bool valid, const double (&out)[FluxT<FLUX>::NC][K + 1],
+                                  double (&v)[3 * FluxT<FLUX>::NC + 1]) {
     using F = FluxT<FLUX>;
-    constexpr int NC = F::NC, NV = 3 * NC + 1;
+    constexpr int NC = F::NC;
     constexpr Tab<K> tb = make_tab<K>();
-    const double flip = hf ? 1.0 : -1.0;
-    double v[NV];
-    int kind[NV];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-        kind[3 * q] = 0;
-        kind[3 * q + 1] = 1;
-        kind[3 * q + 2] = 2;
         double mx = -INFINITY, mn = INFINITY;
 #pragma unroll
-        for (int sidx = K + 2; sidx < 2 * K + 4; ++sidx) {
-            double x = 0.0;
+        for (int hf = 0; hf < 2; ++hf) {
+            const double flip = hf ? 1.0 : -1.0;
 #pragma unroll
-            for (int n = 0; n <= K; ++n) x += ((n & 1) ? flip * out[q][n] : out[q][n]) * tb.SP[sidx][n];
-            mx = fmax(mx, x);
-            mn = fmin(mn, x);
+            for (int sidx = K + 2; sidx < 2 * K + 4; ++sidx) {
+                double x = 0.0;
+#pragma unroll
+                for (int n = 0; n <= K; ++n) x += ((n & 1) ? flip * out[q][n] : out[q][n]) * tb.SP[sidx][n];
+                mx = fmax(mx, x);
+                mn = fmin(mn, x);
+            }
         }
-        v[3 * q] = (valid && hf == 0) ? out[q][0] : 0.0;
+        v[3 * q] = valid ? out[q][0] : 0.0;
         v[3 * q + 1] = valid ? mx : -INFINITY;
         v[3 * q + 2] = valid ? mn : INFINITY;
     }
     double ubar[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
-    kind[NV - 1] = 1;
-    v[NV - 1] = valid ? F::speed(ubar, I.p0) : -INFINITY;
-    reduce_halves<2 * T, NV>(v, kind, scratch, xwave, xwl);
-    if (threadIdx.x == 0 || threadIdx.x == 2 * T) {
+    v[3 * NC] = valid ? F::speed(ubar, I.p0) : -INFINITY;
+}
+
+// Kind of value j of cell_stats: sum, max, min per component, then max.
+template <int NC>
+__device__ constexpr int cell_stat_kind(int j) { return j == 3 * NC ? 1 : j % 3; }
+
+// Reduction over the 32 lanes of each half of a wave (the first five levels
+// of wave_reduce); the results are in lanes 31 and 63.
+__device__ inline double half_wave_reduce(int kind, double v) {
+    const double id = stat_identity(kind);
+    v = stat_op(kind, v, dpp_all<0xB1>(v));
+    v = stat_op(kind, v, dpp_all<0x4E>(v));
+    v = stat_op(kind, v, dpp_all<0x141>(v));
+    v = stat_op(kind, v, dpp_all<0x140>(v));
+    v = stat_op(kind, v, dpp_d<0x142, 0xa>(v, id));
+    return v;
+}
+
+// The tile's partial statistics (cell_stats of its owned cells) reduced per
+// mesh in a fixed order and written to column `tile` of part[row][tile]: the T
+// cells of a mesh are half a wave (T = 32), a wave (T = 64) or two waves
+// (T = 128, combined in order through LDS).  The instance's dual cell np, when
+// the last tile carries it (lane 1 of the last wave, xcell), gets the next
+// column, as a tile of its own would have written it.
+template <int K, int FLUX, int T>
+__device__ inline void tile_partials(const Inst1D &I, const TCell &c, const double (&out)[FluxT<FLUX>::NC][K + 1],
+                                     double *part, long long ntot, int tile, double *scratch, bool xcell) {
+    constexpr int NC = FluxT<FLUX>::NC, NV = 3 * NC + 1;
+    const int tid = threadIdx.x, lane = tid % WAVE;
+    double v[NV];
+    cell_stats<K, FLUX>(I, c.owned, out, v);
+    auto put = [&](int mesh, int j, double x) {
+        const int row = j == 3 * NC ? ST_BETA + mesh : stat_index(mesh, j / 3, j % 3);
+        part[row * ntot + tile] = x;
+    };
+    if constexpr (T == 32) {
+        if (tid < WAVE) {
 #pragma unroll
-        for (int q = 0; q < NC; ++q)
-#pragma unroll
-            for (int kd = 0; kd < 3; ++kd) part[stat_index(mesh, q, kd) * ntot + tile] = v[3 * q + kd];
-        part[(ST_BETA + mesh) * ntot + tile] = v[NV - 1];
-    }
-    // the extra wave's dual cell np gets the next column, as the separate
-    // tile of that cell would have written it (no primal cells: identities)
-    if (xwave && threadIdx.x == 4 * T) {
-        const double *xs = scratch + (4 * T / WAVE) * NV;
-#pragma unroll
-        for (int q = 0; q < NC; ++q)
-#pragma unroll
-            for (int kd = 0; kd < 3; ++kd) {
-                part[stat_index(0, q, kd) * ntot + tile + 1] = stat_identity(kd);
-                part[stat_index(1, q, kd) * ntot + tile + 1] = xs[3 * q + kd];
+            for (int j = 0; j < NV; ++j) {
+                const double x = half_wave_reduce(cell_stat_kind<NC>(j), v[j]);
+                if (lane == 31) put(0, j, x);
+                if (lane == 63) put(1, j, x);
             }
-        part[ST_BETA * ntot + tile + 1] = -INFINITY;
-        part[(ST_BETA + 1) * ntot + tile + 1] = xs[NV - 1];
+        }
+    } else if constexpr (T == 64) {
+        if (tid < 2 * WAVE) {
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const double x = wave_reduce(cell_stat_kind<NC>(j), v[j]);
+                if (lane == WAVE - 1) put(tid / WAVE, j, x);
+            }
+        }
+    } else {
+        const int wave = tid / WAVE;
+        if (tid < 2 * T) {
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const double x = wave_reduce(cell_stat_kind<NC>(j), v[j]);
+                if (lane == WAVE - 1) scratch[wave * NV + j] = x;
+            }
+        }
+        __syncthreads();
+        if (tid < 2 * NV) {                  // one thread per (mesh, value): waves 2 mesh, 2 mesh + 1
+            const int mesh = tid / NV, j = tid % NV;
+            const double x = stat_op(cell_stat_kind<NC>(j), scratch[(2 * mesh) * NV + j],
+                                     scratch[(2 * mesh + 1) * NV + j]);
+            put(mesh, j, x);
+        }
+    }
+    if (xcell && tid == 2 * T + 1) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int row1 = j == 3 * NC ? ST_BETA + 1 : stat_index(1, j / 3, j % 3);
+            const int row0 = j == 3 * NC ? ST_BETA : stat_index(0, j / 3, j % 3);
+            part[row1 * ntot + tile + 1] = v[j];
+            part[row0 * ntot + tile + 1] = j == 3 * NC ? -INFINITY : stat_identity(j % 3);
+        }
     }
 }
 
@@ -393,63 +436,17 @@ __device__ inline void finish_stats(const Inst1D &I, const double *red, double (
 }
 
 constexpr int lds_doubles(int K, int NC, int T) { return 2 * NC * (K + 1) * (T + 2); }
-constexpr int scratch_doubles(int T) { return NSTAT * ((max_threads(T) + WAVE - 1) / WAVE) + NSTAT; }
-
-// Cell of thread tid in a tile: primal cell tid/2 < T, dual cell tid/2 - T < T
-// (both relative to i0); the extra wave's first lane pair takes dual cell T of
-// a tail tile (the instance's dual cell np), its other lanes no cell.  c is
-// kept within the LDS tile; returns whether the thread has a cell.
-template <int T>
-__device__ inline bool cell_of(const Inst1D &I, int tile, int i0, int tid, int &mesh, int &c, int &gi, bool xwl) {
-    const int cidx = tid >> 1;
-    mesh = cidx < T ? 0 : 1;
-    c = cidx - mesh * T;
-    if (xwl && c >= T) {
-        const bool tail = I.tail && tile == I.tile0 + I.ntiles - 1 && c == T;
-        c = T;
-        gi = i0 + T;
-        return tail && gi < I.nd;
-    }
-    gi = i0 + c;
-    return gi < (mesh == 0 ? I.np : I.nd);
-}
+constexpr int scratch_doubles(int T) { return NSTAT * ((nthreads(T) + WAVE - 1) / WAVE) + NSTAT; }
 
 // ---------------------------------------------------------- stage tile ---
-// Thread tid works on cell tid/2 of the tile (primal cells first) and on the
-// half cell tid%2 of it.
-
-// Doubles of a tile's LDS image (with its halo) that each thread loads.
-template <int K, int FLUX, int T>
-constexpr int tile_loads() { return (2 * FluxT<FLUX>::NC * (K + 1) * (T + 2) + nthreads(T) - 1) / nthreads(T); }
-
-// Issue the loads of tile `tile`'s LDS image (stage input of parity sp) into pre.
-template <int K, int FLUX, int T>
-__device__ inline void load_pre(const StageArgs &a, int tile, int sp, double (&pre)[tile_loads<K, FLUX, T>()]) {
-    constexpr int NC = FluxT<FLUX>::NC, PER = NC * (K + 1) * (T + 2), NT = nthreads(T);
-    const Tile1D tl = a.tiles[tile];
-    const Inst1D I = a.inst[tl.inst];
-    const double *inC = a.BC[sp] + I.offC, *inD = a.BD[sp] + I.offD;
-#pragma unroll
-    for (int i = 0; i < tile_loads<K, FLUX, T>(); ++i) {
-        const int e = threadIdx.x + i * NT;
-        pre[i] = e < 2 * PER ? tile_elem<K, NC, T, FLUX == 3>(I, tl.i0, inC, inD, e) : 0.0;
-    }
-}
 
 // folded: the instance's statistics were reduced by k_fold into a.red (batched
 // launches); otherwise every workgroup reduces the partial columns itself.
-// have_pre: the tile's LDS image is already in pre (loaded while the previous
-// tile of this workgroup was computed); next_tile >= 0: once this tile's image
-// is in LDS, the loads of next_tile's image are issued into pre, so they are in
-// flight while this tile is damped and updated (batched launches).
-// Returns whether next_tile's loads were issued.
 template <int K, int FLUX, int T>
-__device__ bool stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
-                           bool folded, double (&pre)[tile_loads<K, FLUX, T>()], bool have_pre = false,
-                           int next_tile = -1) {
+__device__ void stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
+                           bool folded) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1, W = T + 2, PER = NC * K1 * W, NT = nthreads(T);
-    constexpr int NLD = tile_loads<K, FLUX, T>();
     const int tid = threadIdx.x;
     const bool coh = a.coherent;
     Tile1D tl;
@@ -468,41 +465,45 @@ __device__ bool stage_tile(const StageArgs &a, int l, int par, int first, int ti
     const bool single = a.tau_override > 0.0;
     const int sp = ((a.ns & 1 ? par : 0) + l) & 1;   // parity of the global stage index ns n + l
     double *sC = smem, *sD = smem + PER;
-    double *red = smem + lds_doubles(K, NC, T);
-    double *scratch = red + NSTAT;
+    double *scratch = smem + lds_doubles(K, NC, T) + NSTAT;
 
-    const int hf = tid & 1;
-    int mesh, c, gi;
-    const bool valid = cell_of<T>(I, tile, i0, tid, mesh, c, gi, xwl);
-    const bool mainthr = !xwl || tid < NT;      // not the launch's extra wave
-    const int ncell = mesh == 0 ? I.np : I.nd;
-    double *UM = (mesh == 0 ? a.UC + I.offC : a.UD + I.offD);
+    const TCell c = tile_cell<T>(I, tile, i0, xwl);
+    const bool xcell = xwl && I.tail && tile == I.tile0 + I.ntiles - 1;
+    const int ncell = c.mesh == 0 ? I.np : I.nd;
+    const int gi = c.owned ? c.g : 0;        // a valid index for the owned-cell loads and stores
+    double *UM = (c.mesh == 0 ? a.UC + I.offC : a.UD + I.offD);
     const bool damp = a.damp_input && I.oe && K > 0 && !(l == 0 && first);
     const bool need_beta = l == 0 && !single && a.dt_fixed <= 0.0;
     const bool need_red = damp || need_beta;
     const int ns = need_beta ? Partials<NC>::NS : Partials<NC>::NS - 2;
+    const RKStage rs = rk_stage(a.rk, l);
+    double *AM = (rs.acc_read || rs.ca != 0.0) ? (c.mesh == 0 ? a.AC + I.offC : a.AD + I.offD) : nullptr;
 
     // One round trip for every load that does not depend on another: this
-    // step's and the previous step's scalars, the tile's pre-damping input and
-    // the previous stage's partial statistics (issued before any test on them).
+    // step's and the previous step's scalars, the previous stage's partial
+    // statistics, the thread's cell and its overlapping cells, u^n and the RK4
+    // sum of the cell (issued before any test on them).
     const Slot cur = ld_slot(&S[par], coh), prev = ld_slot(&S[par ^ 1], coh);
-    if (!have_pre) {
-        const double *inC = a.BC[sp] + I.offC, *inD = a.BD[sp] + I.offD;
-#pragma unroll
-        for (int i = 0; i < NLD; ++i) {
-            const int e = tid + i * NT;
-            pre[i] = (e < 2 * PER && mainthr) ? tile_elem<K, NC, T, FLUX == 3>(I, i0, inC, inD, e) : 0.0;
-        }
-    }
     Partials<NC> pv;
     double redv = 0.0;                       // folded: row tid of the instance's reduced statistics
     if (need_red) {
         if (folded) {
             if (tid < NSTAT) redv = a.red[(long long)tl.inst * NSTAT + tid];
         } else {
-            load_partials<NT, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, pv, xwl);
+            load_partials<NT, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, pv);
         }
     }
+    CellIn<K, FLUX> ci;
+    load_cell_in<K, FLUX>(I, c, a.BC[sp] + I.offC, a.BD[sp] + I.offD, ci);
+    double un[NC][K1], acc[NC][K1];
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m < K1; ++m) {
+            const long long e = (long long)(q * K1 + m) * ncell + gi;
+            un[q][m] = (l > 0 && c.owned) ? UM[e] : 0.0;
+            acc[q][m] = (rs.acc_read && c.owned) ? AM[e] : 0.0;
+        }
 
     if (!single) {
         if (l == 0 && cur.t >= a.t_end) {    // a step that is not taken: carry the time over
@@ -510,16 +511,19 @@ __device__ bool stage_tile(const StageArgs &a, int l, int par, int first, int ti
                 S[par].done = 1;
                 S[par ^ 1].t = cur.t;
             }
-            return false;
+            return;
         }
-        if (l > 0 && cur.done) return false;
+        if (l > 0 && cur.done) return;
     }
+    double red[NSTAT];                       // the reduced statistics, in every thread
     if (need_red) {
         if (folded) {
-            if (tid < NSTAT) red[tid] = redv;
+            if (tid < NSTAT) scratch[tid] = redv;
             __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NSTAT; ++i) red[i] = scratch[i];
         } else {
-            finish_partials<NT, NC>(pv, a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, red, scratch, xwl);
+            finish_partials_all<NT, NC>(pv, a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, red, scratch);
         }
     }
 
@@ -557,121 +561,85 @@ __device__ bool stage_tile(const StageArgs &a, int l, int par, int first, int ti
 
     double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
     if (damp) finish_stats<NC>(I, red, sig);
-    const double tau_in = (l == 0) ? prev.tau : tau;
-
-#pragma unroll
-    for (int i = 0; i < NLD; ++i) {
-        const int e = tid + i * NT;
-        if (e < 2 * PER && mainthr) smem[e] = pre[i];
-    }
-    // u^n of this thread's cell: its latency overlaps the damping below
-    double un[NC][K1];
-#pragma unroll
-    for (int q = 0; q < NC; ++q)
-#pragma unroll
-        for (int m = 0; m < K1; ++m) un[q][m] = (l > 0 && valid) ? UM[(long long)(q * K1 + m) * ncell + gi] : 0.0;
-    const bool prefetched = next_tile >= 0;    // workgroup-uniform
-    if (prefetched) load_pre<K, FLUX, T>(a, next_tile, sp, pre);
+    damp_cell<K, FLUX>(I, c, ci, sig, (l == 0) ? prev.tau : tau, damp);
+    if (c.has) lds_put<K, NC, W>(c.mesh == 0 ? sC : sD, c.col, ci.own);
     __syncthreads();
-    if constexpr (FLUX == 3) {
-        if (has_wall_ghost<K, NC, T>(I, i0)) {
-            mirror_ghosts<K, NC, T>(I, i0, sC);
-            __syncthreads();
-        }
-    }
-    if (damp) damp_tile<K, FLUX, T>(I, i0, sC, sD, sig, tau_in);
 
-    // A launch's extra wave computes only in the tile that carries dual cell np.
-    const bool tail_tile = I.tail && tile == I.tile0 + I.ntiles - 1;
     double out[NC][K1];
 #pragma unroll
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int m = 0; m < K1; ++m) out[q][m] = 0.0;
-    if (mainthr || tail_tile) {
-        // own cell; the overlapping cell of this thread's half
-        double own[NC][K1], nb[NC][K1];
-        if (mesh == 0) {
-            lds_cell<K, NC, W>(sC, c + 1, own);
-            lds_cell<K, NC, W>(sD, c + 1 + hf, nb);
-        } else {
-            lds_cell<K, NC, W>(sD, c + 1, own);
-            lds_cell<K, NC, W>(sC, c + hf, nb);
-        }
-        if (l == 0 && !single && valid) {
+    if (c.owned) {
+        const double(&own)[NC][K1] = ci.own;
+        if (l == 0 && !single) {
 #pragma unroll
             for (int q = 0; q < NC; ++q)
 #pragma unroll
-                for (int m = 0; m < K1; ++m)
-                    if (((q * K1 + m) & 1) == hf) UM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
+                for (int m = 0; m < K1; ++m) UM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
         }
-        if (l > 0 && a.DC && valid) {          // damped stage input, kept for the adjoint
-            double *DM = mesh == 0 ? a.DC + I.offC : a.DD + I.offD;
+        if (l > 0 && a.DC) {                 // damped stage input, kept for the adjoint
+            double *DM = c.mesh == 0 ? a.DC + I.offC : a.DD + I.offD;
 #pragma unroll
             for (int q = 0; q < NC; ++q)
 #pragma unroll
-                for (int m = 0; m < K1; ++m)
-                    if (((q * K1 + m) & 1) == hf) DM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
+                for (int m = 0; m < K1; ++m) DM[(long long)(q * K1 + m) * ncell + gi] = own[q][m];
         }
-
-        const double inv_tm = 1.0 / taumax;
-        double r[NC][K1];
-        cdg_rate_half<K, FLUX>(nb, hf, I.p0, taumax * (1.0 / I.h), r);
+        // the damped cells of the other mesh that overlap this one (left, right)
+        double nb[NC][K1], rl[NC][K1], rr[NC][K1];
+        const double ft = taumax * (1.0 / I.h);
+        lds_cell<K, NC, W>(c.mesh == 0 ? sD : sC, c.mesh == 0 ? c.col : c.col - 1, nb);
+        cdg_rate_half<K, FLUX>(nb, 0, I.p0, ft, rl);
+        lds_cell<K, NC, W>(c.mesh == 0 ? sD : sC, c.mesh == 0 ? c.col + 1 : c.col, nb);
+        cdg_rate_half<K, FLUX>(nb, 1, I.p0, ft, rr);
 
         // eq:RKCDG: out = c_{l0} u^n [+ accumulated earlier stages] + c_{ll} u^l + tau d_{ll} L(u^l)
-        const RKStage rs = rk_stage(a.rk, l);
+        const double inv_tm = 1.0 / taumax;
         const double td = tau * rs.d;
-        double *AM = nullptr;
-        if (rs.acc_read || rs.ca != 0.0) AM = mesh == 0 ? a.AC + I.offC : a.AD + I.offD;
         bool finite = true;
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
             for (int m = 0; m < K1; ++m) {
-                const double both = r[q][m] + pair_swap(r[q][m]);   // the two halves (a + b == b + a)
+                const double both = rl[q][m] + rr[q][m];      // the two halves of the cell
                 const double rate = inv_tm * (both - own[q][m]);
                 const double v = fma(td, rate, rs.cw * own[q][m]);
                 double o = v;
                 if (l > 0) {
                     double base = rs.cn * un[q][m];
-                    if (rs.acc_read) base += valid ? AM[(long long)(q * K1 + m) * ncell + gi] : 0.0;
+                    if (rs.acc_read) base += acc[q][m];
                     o = base + v;
                 }
                 out[q][m] = o;
                 finite = finite && isfinite(o);
             }
-        if (rs.ca != 0.0 && valid) {           // classical RK4: this stage's damped input joins the sum
+        if (rs.ca != 0.0) {                  // classical RK4: this stage's damped input joins the sum
 #pragma unroll
             for (int q = 0; q < NC; ++q)
 #pragma unroll
-                for (int m = 0; m < K1; ++m)
-                    if (((q * K1 + m) & 1) == hf) {
-                        double *p = AM + (long long)(q * K1 + m) * ncell + gi;
-                        *p = rs.acc_first ? rs.ca * own[q][m] : fma(rs.ca, own[q][m], *p);
-                    }
+                for (int m = 0; m < K1; ++m) {
+                    double *p = AM + (long long)(q * K1 + m) * ncell + gi;
+                    *p = rs.acc_first ? rs.ca * own[q][m] : fma(rs.ca, own[q][m], *p);
+                }
         }
-        double *OM = (mesh == 0 ? a.BC[sp ^ 1] + I.offC : a.BD[sp ^ 1] + I.offD);
-        if (valid) {
+        double *OM = (c.mesh == 0 ? a.BC[sp ^ 1] + I.offC : a.BD[sp ^ 1] + I.offD);
 #pragma unroll
-            for (int q = 0; q < NC; ++q)
+        for (int q = 0; q < NC; ++q)
 #pragma unroll
-                for (int m = 0; m < K1; ++m)
-                    if (((q * K1 + m) & 1) == hf) OM[(long long)(q * K1 + m) * ncell + gi] = out[q][m];
-            double ubar[NC];
+            for (int m = 0; m < K1; ++m) OM[(long long)(q * K1 + m) * ncell + gi] = out[q][m];
+        double ubar[NC];
 #pragma unroll
-            for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
-            // a tolerated non-positive pressure (OECDG_FLAG_ALLOW_NEGATIVE_PRESSURE) leaves the density
-            const bool phys = (I.flags & OECDG_FLAG_ALLOW_NEGATIVE_PRESSURE) ? ubar[0] > 0.0 : F::physical(ubar, I.p0);
-            if (hf == 0 && (!finite || !phys)) {
-                if (!finite) a.err[0] = 1;
-                if (!phys) a.err[1] = 1;
-                a.err[3] = (int)(a.fin[tl.inst].nexec + 1);
-            }
+        for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
+        // a tolerated non-positive pressure (OECDG_FLAG_ALLOW_NEGATIVE_PRESSURE) leaves the density
+        const bool phys = (I.flags & OECDG_FLAG_ALLOW_NEGATIVE_PRESSURE) ? ubar[0] > 0.0 : F::physical(ubar, I.p0);
+        if (!finite || !phys) {
+            if (!finite) a.err[0] = 1;
+            if (!phys) a.err[1] = 1;
+            a.err[3] = (int)(a.fin[tl.inst].nexec + 1);
         }
     }
-    tile_partials<K, FLUX, T>(I, valid, mesh, hf, out, a.part[sp], a.ntiles, tile, scratch, xwl && tail_tile, xwl);
+    tile_partials<K, FLUX, T>(I, c, out, a.part[sp], a.ntiles, tile, scratch, xcell);
     __syncthreads();
-    return prefetched;
 }
 
 // Statistics of a given state (srcC/srcD) into part[1]: the partials that the
@@ -682,18 +650,16 @@ __device__ void stats_tile(const StageArgs &a, int tile, double *smem, bool xwl)
     constexpr int NC = F::NC, K1 = K + 1;
     const Tile1D tl = a.ninst == 1 ? Tile1D{0, tile * T} : a.tiles[tile];
     const Inst1D I = a.ninst == 1 ? a.inst0 : a.inst[tl.inst];
-    const int tid = threadIdx.x, hf = tid & 1;
-    int mesh, c, gi;
-    const bool valid = cell_of<T>(I, tile, tl.i0, tid, mesh, c, gi, xwl);
-    const int ncell = mesh == 0 ? I.np : I.nd;
-    const double *src = mesh == 0 ? a.srcC + I.offC : a.srcD + I.offD;
+    const TCell c = tile_cell<T>(I, tile, tl.i0, xwl);
+    const int ncell = c.mesh == 0 ? I.np : I.nd;
+    const double *src = c.mesh == 0 ? a.srcC + I.offC : a.srcD + I.offD;
     double u[NC][K1];
 #pragma unroll
     for (int q = 0; q < NC; ++q)
 #pragma unroll
-        for (int m = 0; m < K1; ++m) u[q][m] = valid ? src[(long long)(q * K1 + m) * ncell + gi] : 1.0;
-    tile_partials<K, FLUX, T>(I, valid, mesh, hf, u, a.part[1], a.ntiles, tile, smem + NSTAT,
-                              xwl && I.tail && tile == I.tile0 + I.ntiles - 1, xwl);
+        for (int m = 0; m < K1; ++m) u[q][m] = c.owned ? src[(long long)(q * K1 + m) * ncell + c.g] : 1.0;
+    tile_partials<K, FLUX, T>(I, c, u, a.part[1], a.ntiles, tile, smem + NSTAT,
+                              xwl && I.tail && tile == I.tile0 + I.ntiles - 1);
     __syncthreads();
 }
 
@@ -701,75 +667,52 @@ __device__ void stats_tile(const StageArgs &a, int tile, double *smem, bool xwl)
 template <int K, int FLUX, int T>
 __device__ void final_tile(const StageArgs &a, int tile, double *smem, bool xwl) {
     using F = FluxT<FLUX>;
-    constexpr int NC = F::NC, K1 = K + 1, W = T + 2;
-    const int tid = threadIdx.x;
+    constexpr int NC = F::NC, K1 = K + 1;
     const Tile1D tl = a.ninst == 1 ? Tile1D{0, tile * T} : a.tiles[tile];
     const Inst1D I = a.ninst == 1 ? a.inst0 : a.inst[tl.inst];
     const long long N = a.fin[tl.inst].nexec;
     const double tau = a.fin[tl.inst].tau;
     const int bp = (int)((a.ns * N) & 1);   // buffer holding the last stage's output (or the input when N = 0)
-    double *sC = smem, *sD = smem + NC * K1 * W;
     double *red = smem + lds_doubles(K, NC, T);
     double *scratch = red + NSTAT;
     const bool damp = N > 0 && I.oe && K > 0;
+    const TCell c = tile_cell<T>(I, tile, tl.i0, xwl);
+    CellIn<K, FLUX> ci;
+    load_cell_in<K, FLUX>(I, c, a.BC[bp] + I.offC, a.BD[bp] + I.offD, ci);
     double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
     if (damp) {
         reduce_instance<nthreads(T), NC>(a.part[(int)((a.ns * N - 1) & 1)], a.ntiles, I.tile0, I.npart, false, red,
-                                         scratch, xwl);
+                                         scratch);
         finish_stats<NC>(I, red, sig);
     }
-    load_tile<K, NC, T, FLUX == 3>(I, tl.i0, a.BC[bp] + I.offC, a.BD[bp] + I.offD, smem, xwl);
-    __syncthreads();
-    if constexpr (FLUX == 3) {
-        if (has_wall_ghost<K, NC, T>(I, tl.i0)) {
-            mirror_ghosts<K, NC, T>(I, tl.i0, sC);
-            __syncthreads();
-        }
-    }
-    if (damp) damp_tile<K, FLUX, T>(I, tl.i0, sC, sD, sig, tau);
-    const int hf = tid & 1;
-    int mesh, c, gi;
-    const bool valid = cell_of<T>(I, tile, tl.i0, tid, mesh, c, gi, xwl);
-    const int ncell = mesh == 0 ? I.np : I.nd;
-    if (valid) {
-        const double *s = mesh == 0 ? sC : sD;
-        double *dst = mesh == 0 ? a.dstC + I.offC : a.dstD + I.offD;
+    damp_cell<K, FLUX>(I, c, ci, sig, tau, damp);
+    if (c.owned) {
+        const int ncell = c.mesh == 0 ? I.np : I.nd;
+        double *dst = c.mesh == 0 ? a.dstC + I.offC : a.dstD + I.offD;
 #pragma unroll
         for (int q = 0; q < NC; ++q)
 #pragma unroll
-            for (int m = 0; m < K1; ++m)
-                if (((q * K1 + m) & 1) == hf) dst[(long long)(q * K1 + m) * ncell + gi] = s[(q * K1 + m) * W + c + 1];
+            for (int m = 0; m < K1; ++m) dst[(long long)(q * K1 + m) * ncell + c.g] = ci.own[q][m];
     }
     __syncthreads();
 }
 
 // --------------------------------------------------------------- kernels ---
 
-// KM < 0: mixed-degree batch, dispatch on the instance's k per tile.
+// Kernels of one degree KM, flux and tile.
 template <int KM, int FLUX, int T>
 struct Disp {
-    static constexpr int KL = KM < 0 ? MAXK : KM;
-    static constexpr int LDS = lds_doubles(KL, FluxT<FLUX>::NC, T) + scratch_doubles(T);
+    static constexpr int LDS = lds_doubles(KM, FluxT<FLUX>::NC, T) + scratch_doubles(T);
     template <template <int, int, int> class Fn, typename... Args>
-    __device__ static void run(int k, Args &&...args) {
-        if constexpr (KM >= 0) {
-            Fn<KM, FLUX, T>::go(args...);
-        } else {
-            switch (k) {
-            case 0: Fn<0, FLUX, T>::go(args...); break;
-            case 1: Fn<1, FLUX, T>::go(args...); break;
-            case 2: Fn<2, FLUX, T>::go(args...); break;
-            default: Fn<3, FLUX, T>::go(args...); break;
-            }
-        }
+    __device__ static void run(Args &&...args) {
+        Fn<KM, FLUX, T>::go(args...);
     }
 };
 
 template <int K, int FLUX, int T> struct StageFn {
     __device__ static void go(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
                               bool folded) {
-        double pre[tile_loads<K, FLUX, T>()];
-        stage_tile<K, FLUX, T>(a, l, par, first, tile, smem, xwl, folded, pre);
+        stage_tile<K, FLUX, T>(a, l, par, first, tile, smem, xwl, folded);
     }
 };
 template <int K, int FLUX, int T> struct StatsFn {
@@ -784,12 +727,11 @@ template <int K, int FLUX, int T> struct FinalFn {
 };
 
 template <int KM, int FLUX, int T, bool XW>
-__global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_stage(StageArgs a) {
+__global__ __launch_bounds__(nthreads(T)) void k_stage(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
-        const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-        D::template run<StageFn>(k, a, a.l, a.par, a.first, tile, smem, XW, false);
+        D::template run<StageFn>(a, a.l, a.par, a.first, tile, smem, XW, false);
     }
 }
 
@@ -797,17 +739,12 @@ __global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_stage(Sta
 // instance's statistics come reduced from k_fold (one fixed-order reduction
 // per instance and stage) instead of every workgroup reducing all of its
 // instance's partial columns, and a workgroup walks the tiles tbeg +
-// blockIdx.x, + gridDim.x, ..., loading each tile's input while the previous
-// one is damped and updated.
+// blockIdx.x, + gridDim.x, ...
 template <int K, int FLUX, int T>
 __global__ __launch_bounds__(nthreads(T)) void k_stage_folded(StageArgs a) {
     __shared__ double smem[lds_doubles(K, FluxT<FLUX>::NC, T) + scratch_doubles(T)];
-    double pre[tile_loads<K, FLUX, T>()];
-    bool have = false;
-    for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
-        const int next = tile + (int)gridDim.x < a.tend ? tile + (int)gridDim.x : -1;
-        have = stage_tile<K, FLUX, T>(a, a.l, a.par, a.first, tile, smem, false, true, pre, have, next);
-    }
+    for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x)
+        stage_tile<K, FLUX, T>(a, a.l, a.par, a.first, tile, smem, false, true);
 }
 
 // One workgroup per instance: the partial columns of the state the next stage
@@ -827,22 +764,20 @@ __global__ __launch_bounds__(nthreads(T)) void k_fold(StageArgs a, int src) {
 }
 
 template <int KM, int FLUX, int T, bool XW>
-__global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_stats(StageArgs a) {
+__global__ __launch_bounds__(nthreads(T)) void k_stats(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
-        const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-        D::template run<StatsFn>(k, a, tile, smem, XW);
+        D::template run<StatsFn>(a, tile, smem, XW);
     }
 }
 
 template <int KM, int FLUX, int T, bool XW>
-__global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_final(StageArgs a) {
+__global__ __launch_bounds__(nthreads(T)) void k_final(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
-        const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-        D::template run<FinalFn>(k, a, tile, smem, XW);
+        D::template run<FinalFn>(a, tile, smem, XW);
     }
 }
 
@@ -878,15 +813,14 @@ __device__ inline void grid_barrier(const StageArgs &a) {
 // barrier separates consecutive stages.  The statistics a workgroup reads after
 // a barrier are read coherently (a.coherent).
 template <int KM, int FLUX, int T, bool XW>
-__global__ __launch_bounds__(XW ? max_threads(T) : nthreads(T)) void k_persistent(StageArgs a, long long nsteps, int single_instance) {
+__global__ __launch_bounds__(nthreads(T)) void k_persistent(StageArgs a, long long nsteps, int single_instance) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
     for (long long n = 0; n < nsteps; ++n) {
         const int par = (int)(n & 1);
         for (int l = 0; l < a.ns; ++l) {
             for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
-                const int k = a.ninst == 1 ? a.inst0.k : a.inst[a.tiles[tile].inst].k;
-                D::template run<StageFn>(k, a, l, par, n == 0, tile, smem, XW, false);
+                D::template run<StageFn>(a, l, par, n == 0, tile, smem, XW, false);
             }
             grid_barrier(a);
             if (l == 0 && single_instance && ld_i(&a.slots[par].done, true)) return;
@@ -919,10 +853,10 @@ __global__ void k_init(StageArgs a, int ninst) {
 
 static int tile_index(int tile) { return tile == 32 ? 0 : (tile == 64 ? 1 : (tile == 128 ? 2 : -1)); }
 // kernel table index: the tile (0, 1, 2 for 32, 64, 128), or 3 / 4 for tiles
-// of 32 / 64 launched with the extra wave
+// of 32 / 64 whose launches carry the dual cell np in an instance's last tile
 static int kernel_index(int tile, bool tailwave) {
     const int ti = tile_index(tile);
-    return (ti >= 0 && tailwave && tail_threads(tile) > 0) ? ti + 3 : ti;
+    return (ti >= 0 && tailwave && tail_mode(tile)) ? ti + 3 : ti;
 }
 
 // Kernel pointers by (kernel, degree, flux, tile).  XW: launches with the extra
@@ -979,7 +913,7 @@ static void *pick(int k, int flux, int ti) {   // batches of mixed degree launch
 static hipError_t launch(void *fn, int grid, int tile, const StageArgs &a, hipStream_t s) {
     StageArgs copy = a;
     void *args[] = {&copy};
-    return hipLaunchKernel(fn, dim3(grid), dim3(nthreads(tile) + (a.tailwave ? tail_threads(tile) : 0)), args, 0, s);
+    return hipLaunchKernel(fn, dim3(grid), dim3(nthreads(tile)), args, 0, s);
 }
 
 hipError_t launch_init_1d(const StageArgs &a, int ninst, hipStream_t s) {
@@ -1043,7 +977,7 @@ int persistent_max_grid_1d(int kmax, int flux, int tile, bool tailwave) {
     int per_cu = 0, dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const int nthr = nthreads(tile) + (tailwave ? tail_threads(tile) : 0);
+    const int nthr = nthreads(tile);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick<3>(kmax, flux, ti), nthr, 0) !=
         hipSuccess)
         return 0;
@@ -1057,7 +991,7 @@ hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, int tile
     StageArgs copy = a;
     int single = a.ninst == 1;
     void *args[] = {&copy, &nsteps, &single};
-    const int nthr = nthreads(tile) + (a.tailwave ? tail_threads(tile) : 0);
+    const int nthr = nthreads(tile);
     return hipLaunchCooperativeKernel(pick<3>(kmax, flux, ti), dim3(grid), dim3(nthr), args, 0, s);
 }
 

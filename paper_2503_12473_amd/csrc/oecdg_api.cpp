@@ -173,7 +173,7 @@ int oecdg::default_tile(int64_t maxn, int nbatch) { return maxn <= 4096 && nbatc
 
 // An outflow/walled mesh whose primal count is a multiple of T has its dual
 // cell np beyond np / T full tiles.
-bool oecdg::tail_candidate(const Inst1D &I, int T) { return I.nd == I.np + 1 && I.np % T == 0 && tail_threads(T) > 0; }
+bool oecdg::tail_candidate(const Inst1D &I, int T) { return I.nd == I.np + 1 && I.np % T == 0 && tail_mode(T); }
 
 namespace {
 

@@ -151,13 +151,10 @@ struct Partials {
     double v[2][NS];
 };
 
-// xwl: the launch carries an extra wave (threads from NT on), which takes no
-// part; a compile-time constant once inlined, so other launches test nothing.
 template <int NT, int NC>
 __device__ inline void load_partials(const double *part, long long ntot, int tile0, int ntiles, int ns,
-                                     Partials<NC> &p, bool xwl = false) {
+                                     Partials<NC> &p) {
     const int tid = threadIdx.x;
-    if (xwl && tid >= NT) return;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int t = tid + u * NT;
@@ -174,11 +171,11 @@ __device__ inline void load_partials(const double *part, long long ntot, int til
 
 template <int NT, int NC>
 __device__ void finish_partials(const Partials<NC> &p, const double *part, long long ntot, int tile0, int ntiles,
-                                int ns, double *red, double *scratch, bool xwl = false) {
+                                int ns, double *red, double *scratch) {
     constexpr int NS = Partials<NC>::NS;
     constexpr int NW = (NT + WAVE - 1) / WAVE;
     const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
-    if (!xwl || tid < NT) {                 // a launch's extra wave only meets the barriers
+    {
         double acc[NS];
 #pragma unroll
         for (int i = 0; i < NS; ++i) acc[i] = stat_op(stat_kind(stat_row<NC>(i)), p.v[0][i], p.v[1][i]);
@@ -208,13 +205,54 @@ __device__ void finish_partials(const Partials<NC> &p, const double *part, long 
     __syncthreads();
 }
 
+// The same reduction, with every thread combining the per-wave results itself
+// (the order of finish_partials), so that all of them hold all NSTAT rows (rows
+// beyond ns are not computed) after one barrier.
+template <int NT, int NC>
+__device__ void finish_partials_all(const Partials<NC> &p, const double *part, long long ntot, int tile0, int ntiles,
+                                    int ns, double (&red)[NSTAT], double *scratch) {
+    constexpr int NS = Partials<NC>::NS;
+    constexpr int NW = (NT + WAVE - 1) / WAVE;
+    const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
+    double acc[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) acc[i] = stat_op(stat_kind(stat_row<NC>(i)), p.v[0][i], p.v[1][i]);
+    for (int t = tid + 2 * NT; t < ntiles; t += NT) {   // more than two tiles per thread
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            if (i < ns) {
+                const int j = stat_row<NC>(i);
+                acc[i] = stat_op(stat_kind(j), acc[i], part[(long long)j * ntot + tile0 + t]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) acc[i] = wave_reduce(stat_kind(stat_row<NC>(i)), acc[i]);
+    if (lane == WAVE - 1) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) scratch[wave * NS + i] = acc[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NSTAT; ++i) red[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        if (i < ns) {
+            const int kd = stat_kind(stat_row<NC>(i));
+            double v = scratch[i];
+            for (int w = 1; w < NW; ++w) v = stat_op(kd, v, scratch[w * NS + i]);
+            red[stat_row<NC>(i)] = v;
+        }
+    }
+}
+
 template <int NT, int NC>
 __device__ void reduce_instance(const double *part, long long ntot, int tile0, int ntiles, bool beta, double *red,
-                                double *scratch, bool xwl = false) {
+                                double *scratch) {
     const int ns = beta ? Partials<NC>::NS : Partials<NC>::NS - 2;
     Partials<NC> p;
-    load_partials<NT, NC>(part, ntot, tile0, ntiles, ns, p, xwl);
-    finish_partials<NT, NC>(p, part, ntot, tile0, ntiles, ns, red, scratch, xwl);
+    load_partials<NT, NC>(part, ntot, tile0, ntiles, ns, p);
+    finish_partials<NT, NC>(p, part, ntot, tile0, ntiles, ns, red, scratch);
 }
 
 }  // namespace oecdg

@@ -50,9 +50,10 @@ struct Final {
     long long nexec;
 };
 
-// Threads of the extra wave that 1D launches carry when an instance's last
-// tile also updates its dual cell np (one wave; none for tiles of 128).
-__host__ __device__ constexpr int tail_threads(int T) { return T <= 64 ? 64 : 0; }
+// Tiles of up to 64 cells can take an instance's dual cell np in its last
+// tile (a lane of the wave that holds the tile's neighbour cells) instead of
+// in a tile of its own.
+__host__ __device__ constexpr bool tail_mode(int T) { return T <= 64; }
 
 // One stage of an RK method in the c/d form of eq:RKCDG,
 //   u_h^{n,l+1} = sum_{m<=l} c_{lm} u_sigma^{n,m} + tau d_{lm} L(u_sigma^{n,m}).
