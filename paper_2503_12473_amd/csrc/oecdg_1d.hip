@@ -367,14 +367,15 @@ __device__ inline double half_wave_reduce(int kind, double v) {
 // column, as a tile of its own would have written it.
 template <int K, int FLUX, int T>
 __device__ inline void tile_partials(const Inst1D &I, const TCell &c, const double (&out)[FluxT<FLUX>::NC][K + 1],
-                                     double *part, long long ntot, int tile, double *scratch, bool xcell) {
+                                     double *part, long long ntot, int tile, double *scratch, bool xcell,
+                                     bool write = true) {
     constexpr int NC = FluxT<FLUX>::NC, NV = 3 * NC + 1;
     const int tid = threadIdx.x, lane = tid % WAVE;
     double v[NV];
     cell_stats<K, FLUX>(I, c.owned, out, v);
     auto put = [&](int mesh, int j, double x) {
         const int row = j == 3 * NC ? ST_BETA + mesh : stat_index(mesh, j / 3, j % 3);
-        part[row * ntot + tile] = x;
+        if (write) part[row * ntot + tile] = x;
     };
     if constexpr (T == 32) {
         if (tid < WAVE) {
@@ -410,7 +411,7 @@ __device__ inline void tile_partials(const Inst1D &I, const TCell &c, const doub
             put(mesh, j, x);
         }
     }
-    if (xcell && tid == 2 * T + 1) {
+    if (write && xcell && tid == 2 * T + 1) {
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
             const int row1 = j == 3 * NC ? ST_BETA + 1 : stat_index(1, j / 3, j % 3);
@@ -442,19 +443,24 @@ constexpr int scratch_doubles(int T) { return NSTAT * ((nthreads(T) + WAVE - 1) 
 
 // folded: the instance's statistics were reduced by k_fold into a.red (batched
 // launches); otherwise every workgroup reduces the partial columns itself.
-template <int K, int FLUX, int T>
+// COH: the persistent launch, whose step records other workgroups of the same
+// launch write (read with device-scope atomic loads after the grid barrier).
+template <int K, int FLUX, int T, bool COH = false>
 __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
                            bool folded) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1, W = T + 2, PER = NC * K1 * W, NT = nthreads(T);
     const int tid = threadIdx.x;
-    const bool coh = a.coherent;
+    constexpr bool coh = COH;
     Tile1D tl;
     Inst1D I;
     if (a.ninst == 1) {                      // single instance: everything from the kernel arguments
         tl.inst = 0;
         tl.i0 = tile * T;
         I = a.inst0;
+        // keeps the two branches apart: merged, they become one load through a
+        // selected pointer (vector loads, waited for before anything else)
+        asm volatile("" ::: "memory");
     } else {
         tl = a.tiles[tile];
         I = a.inst[tl.inst];
@@ -479,20 +485,11 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     const RKStage rs = rk_stage(a.rk, l);
     double *AM = (rs.acc_read || rs.ca != 0.0) ? (c.mesh == 0 ? a.AC + I.offC : a.AD + I.offD) : nullptr;
 
-    // One round trip for every load that does not depend on another: this
-    // step's and the previous step's scalars, the previous stage's partial
-    // statistics, the thread's cell and its overlapping cells, u^n and the RK4
-    // sum of the cell (issued before any test on them).
+    // One round trip for every load that does not depend on another (issued
+    // before any test on them, the selects after): this step's and the
+    // previous step's scalars, the thread's cell and its overlapping cells, u^n
+    // and the RK4 sum of the cell, the previous stage's partial statistics.
     const Slot cur = ld_slot(&S[par], coh), prev = ld_slot(&S[par ^ 1], coh);
-    Partials<NC> pv;
-    double redv = 0.0;                       // folded: row tid of the instance's reduced statistics
-    if (need_red) {
-        if (folded) {
-            if (tid < NSTAT) redv = a.red[(long long)tl.inst * NSTAT + tid];
-        } else {
-            load_partials<NT, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, pv);
-        }
-    }
     CellIn<K, FLUX> ci;
     load_cell_in<K, FLUX>(I, c, a.BC[sp] + I.offC, a.BD[sp] + I.offD, ci);
     double un[NC][K1], acc[NC][K1];
@@ -500,20 +497,32 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int m = 0; m < K1; ++m) {
-            const long long e = (long long)(q * K1 + m) * ncell + gi;
-            un[q][m] = (l > 0 && c.owned) ? UM[e] : 0.0;
-            acc[q][m] = (rs.acc_read && c.owned) ? AM[e] : 0.0;
+            un[q][m] = UM[(long long)(q * K1 + m) * ncell + gi];   // gi: a valid index
+            acc[q][m] = 0.0;
         }
+    if (rs.acc_read) {
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 0; m < K1; ++m) acc[q][m] = AM[(long long)(q * K1 + m) * ncell + gi];
+    }
+    Partials<NC> pv;
+    double redv = 0.0;                       // folded: row tid of the instance's reduced statistics
+    if (need_red) {
+        if (folded) {
+            if (tid < NSTAT) redv = a.red[(long long)tl.inst * NSTAT + tid];
+        } else {
+            load_partials_raw<NT, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, pv);
+        }
+    }
 
-    if (!single) {
-        if (l == 0 && cur.t >= a.t_end) {    // a step that is not taken: carry the time over
-            if (lead) {
-                S[par].done = 1;
-                S[par ^ 1].t = cur.t;
-            }
-            return;
-        }
-        if (l > 0 && cur.done) return;
+    // A step that is not taken (t_end reached) carries the time over; its
+    // stages compute but store nothing.  (No early return: a return here would
+    // let the compiler sink the loads above below it, one round trip later.)
+    const bool skip = !single && ((l == 0 && cur.t >= a.t_end) || (l > 0 && cur.done));
+    if (!single && l == 0 && skip && lead) {
+        S[par].done = 1;
+        S[par ^ 1].t = cur.t;
     }
     double red[NSTAT];                       // the reduced statistics, in every thread
     if (need_red) {
@@ -539,7 +548,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
             tau = a.t_end - cur.t;
             last = 1;
         }
-        if (lead) {
+        if (lead && !skip) {
             S[par].tau = tau;
             S[par].tau_max = taumax;
             S[par].done = 0;
@@ -550,7 +559,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
         taumax = cur.tau_max;
         last = cur.last;
     }
-    if (!single && l == a.ns - 1 && lead) {   // the step's last stage: time and step count
+    if (!single && l == a.ns - 1 && lead && !skip) {   // the step's last stage: time and step count
         const double tnext = last ? a.t_end : cur.t + tau;
         S[par ^ 1].t = tnext;
         Final *f = a.fin + tl.inst;
@@ -570,7 +579,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int m = 0; m < K1; ++m) out[q][m] = 0.0;
-    if (c.owned) {
+    if (c.owned && !skip) {
         const double(&own)[NC][K1] = ci.own;
         if (l == 0 && !single) {
 #pragma unroll
@@ -605,7 +614,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
                 const double rate = inv_tm * (both - own[q][m]);
                 const double v = fma(td, rate, rs.cw * own[q][m]);
                 double o = v;
-                if (l > 0) {
+                if (l > 0) {                 // (u^n at stage 0 is the input itself)
                     double base = rs.cn * un[q][m];
                     if (rs.acc_read) base += acc[q][m];
                     o = base + v;
@@ -638,7 +647,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
             a.err[3] = (int)(a.fin[tl.inst].nexec + 1);
         }
     }
-    tile_partials<K, FLUX, T>(I, c, out, a.part[sp], a.ntiles, tile, scratch, xcell);
+    tile_partials<K, FLUX, T>(I, c, out, a.part[sp], a.ntiles, tile, scratch, xcell, !skip);
     __syncthreads();
 }
 
@@ -713,6 +722,12 @@ template <int K, int FLUX, int T> struct StageFn {
     __device__ static void go(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
                               bool folded) {
         stage_tile<K, FLUX, T>(a, l, par, first, tile, smem, xwl, folded);
+    }
+};
+template <int K, int FLUX, int T> struct StageCohFn {
+    __device__ static void go(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
+                              bool folded) {
+        stage_tile<K, FLUX, T, true>(a, l, par, first, tile, smem, xwl, folded);
     }
 };
 template <int K, int FLUX, int T> struct StatsFn {
@@ -811,7 +826,7 @@ __device__ inline void grid_barrier(const StageArgs &a) {
 
 // Persistent launch: every workgroup walks all steps and stages; a grid
 // barrier separates consecutive stages.  The statistics a workgroup reads after
-// a barrier are read coherently (a.coherent).
+// a barrier are read coherently (stage_tile with COH).
 template <int KM, int FLUX, int T, bool XW>
 __global__ __launch_bounds__(nthreads(T)) void k_persistent(StageArgs a, long long nsteps, int single_instance) {
     using D = Disp<KM, FLUX, T>;
@@ -820,7 +835,7 @@ __global__ __launch_bounds__(nthreads(T)) void k_persistent(StageArgs a, long lo
         const int par = (int)(n & 1);
         for (int l = 0; l < a.ns; ++l) {
             for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
-                D::template run<StageFn>(a, l, par, n == 0, tile, smem, XW, false);
+                D::template run<StageCohFn>(a, l, par, n == 0, tile, smem, XW, false);
             }
             grid_barrier(a);
             if (l == 0 && single_instance && ld_i(&a.slots[par].done, true)) return;

@@ -151,6 +151,21 @@ struct Partials {
     double v[2][NS];
 };
 
+// The loads of load_partials without the selects (applied by
+// finish_partials_all), so that no wait follows them before the kernel's other
+// independent loads are issued.
+template <int NT, int NC>
+__device__ inline void load_partials_raw(const double *part, long long ntot, int tile0, int ntiles, Partials<NC> &p) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int t = tid + u * NT;
+#pragma unroll
+        for (int i = 0; i < Partials<NC>::NS; ++i)
+            p.v[u][i] = part[(long long)stat_row<NC>(i) * ntot + tile0 + min(t, ntiles - 1)];
+    }
+}
+
 template <int NT, int NC>
 __device__ inline void load_partials(const double *part, long long ntot, int tile0, int ntiles, int ns,
                                      Partials<NC> &p) {
@@ -216,7 +231,12 @@ __device__ void finish_partials_all(const Partials<NC> &p, const double *part, l
     const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
     double acc[NS];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) acc[i] = stat_op(stat_kind(stat_row<NC>(i)), p.v[0][i], p.v[1][i]);
+    for (int i = 0; i < NS; ++i) {           // p from load_partials_raw: the selects of load_partials here
+        const double id = stat_identity(stat_kind(stat_row<NC>(i)));
+        const double x0 = (i < ns && tid < ntiles) ? p.v[0][i] : id;
+        const double x1 = (i < ns && tid + NT < ntiles) ? p.v[1][i] : id;
+        acc[i] = stat_op(stat_kind(stat_row<NC>(i)), x0, x1);
+    }
     for (int t = tid + 2 * NT; t < ntiles; t += NT) {   // more than two tiles per thread
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
