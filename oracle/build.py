@@ -1,10 +1,11 @@
 """Build the C oracle library with the host compiler (plain FP64, no contraction).
 
-Two test-only variants evaluate the same oracle with different, equally valid
+Three test-only variants evaluate the same oracle with different, equally valid
 FP64 rounding, to measure how far last-bit differences grow over a long run:
 "fma" lets the compiler contract a*b+c into fused multiply-adds, "pairwise"
-sums the cell averages of the domain mean in pairwise order.  The product
-never loads any of these libraries.
+sums the cell averages of the domain mean in pairwise order, "mixed" does both
+and evaluates the damping exponential in long double before rounding it.  The
+product never loads any of these libraries.
 """
 from __future__ import annotations
 
@@ -17,6 +18,7 @@ LIB = os.path.join(HERE, "liboecdg_oracle.so")
 VARIANTS = {
     "fma": ["-ffp-contract=fast", "-mfma"],
     "pairwise": ["-ffp-contract=off", "-DORA_PAIRWISE_MEAN"],
+    "mixed": ["-ffp-contract=fast", "-mfma", "-DORA_PAIRWISE_MEAN", "-DORA_EXP_LONG_DOUBLE"],
 }
 
 

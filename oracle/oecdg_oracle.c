@@ -429,7 +429,11 @@ int ora1d_oe(const ora1d *p, double tau, double *uC, double *uD)
             for (int j = 1; j <= k; ++j) {
                 double S = 0.0;
                 for (int m = 0; m <= j; ++m) S += d[(long)m * nk + i];
+#ifdef ORA_EXP_LONG_DOUBLE
+                double fac = (double)expl(-(long double)tau * S);   /* test-only variant */
+#else
                 double fac = exp(-tau * S);
+#endif
                 for (int q = 0; q < nc; ++q) u[(long)(q * K1 + j) * nk + i] *= fac;
             }
     }

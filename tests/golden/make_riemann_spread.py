@@ -3,8 +3,8 @@
 make_riemann_golden.py).
 
 The variants (oracle/build.py VARIANTS) evaluate the same scheme with other,
-equally valid FP64 rounding: FMA contraction, or the domain mean summed in
-pairwise order.  Their distance to the plain oracle's stored result on the same
+equally valid FP64 rounding: FMA contraction, the domain mean summed in
+pairwise order, or both with the damping exponential taken in long double.  Their distance to the plain oracle's stored result on the same
 cells measures how far last-bit differences grow over the ~33k steps of the
 run, which is what the full-horizon parity bar of the HIP path rests on.
 Calls only the CPU oracle; about an hour of serial CPU per degree for T = 0.2.
