@@ -360,14 +360,14 @@ __device__ inline double half_wave_reduce(int kind, double v) {
 }
 
 // The tile's partial statistics (cell_stats of its owned cells) reduced per
-// mesh in a fixed order and written to column `tile` of part[row][tile]: the T
+// mesh in a fixed order and written to the record of `tile` in part: the T
 // cells of a mesh are half a wave (T = 32), a wave (T = 64) or two waves
 // (T = 128, combined in order through LDS).  The instance's dual cell np, when
 // the last tile carries it (lane 1 of the last wave, xcell), gets the next
 // column, as a tile of its own would have written it.
 template <int K, int FLUX, int T>
 __device__ inline void tile_partials(const Inst1D &I, const TCell &c, const double (&out)[FluxT<FLUX>::NC][K + 1],
-                                     double *part, long long ntot, int tile, double *scratch, bool xcell,
+                                     double *part, int tile, double *scratch, bool xcell,
                                      bool write = true) {
     constexpr int NC = FluxT<FLUX>::NC, NV = 3 * NC + 1;
     const int tid = threadIdx.x, lane = tid % WAVE;
@@ -375,7 +375,7 @@ __device__ inline void tile_partials(const Inst1D &I, const TCell &c, const doub
     cell_stats<K, FLUX>(I, c.owned, out, v);
     auto put = [&](int mesh, int j, double x) {
         const int row = j == 3 * NC ? ST_BETA + mesh : stat_index(mesh, j / 3, j % 3);
-        if (write) part[row * ntot + tile] = x;
+        if (write) part[(long long)tile * NSTAT + row] = x;
     };
     if constexpr (T == 32) {
         if (tid < WAVE) {
@@ -416,8 +416,8 @@ __device__ inline void tile_partials(const Inst1D &I, const TCell &c, const doub
         for (int j = 0; j < NV; ++j) {
             const int row1 = j == 3 * NC ? ST_BETA + 1 : stat_index(1, j / 3, j % 3);
             const int row0 = j == 3 * NC ? ST_BETA : stat_index(0, j / 3, j % 3);
-            part[row1 * ntot + tile + 1] = v[j];
-            part[row0 * ntot + tile + 1] = j == 3 * NC ? -INFINITY : stat_identity(j % 3);
+            part[(long long)(tile + 1) * NSTAT + row1] = v[j];
+            part[(long long)(tile + 1) * NSTAT + row0] = j == 3 * NC ? -INFINITY : stat_identity(j % 3);
         }
     }
 }
@@ -512,7 +512,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
         if (folded) {
             if (tid < NSTAT) redv = a.red[(long long)tl.inst * NSTAT + tid];
         } else {
-            load_partials_raw<NT, NC>(a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, pv);
+            load_partials_raw<NT, NC>(a.part[sp ^ 1], I.tile0, I.npart, pv);
         }
     }
 
@@ -532,7 +532,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
 #pragma unroll
             for (int i = 0; i < NSTAT; ++i) red[i] = scratch[i];
         } else {
-            finish_partials_all<NT, NC>(pv, a.part[sp ^ 1], a.ntiles, I.tile0, I.npart, ns, red, scratch);
+            finish_partials_all<NT, NC>(pv, a.part[sp ^ 1], I.tile0, I.npart, ns, red, scratch);
         }
     }
 
@@ -647,7 +647,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
             a.err[3] = (int)(a.fin[tl.inst].nexec + 1);
         }
     }
-    tile_partials<K, FLUX, T>(I, c, out, a.part[sp], a.ntiles, tile, scratch, xcell, !skip);
+    tile_partials<K, FLUX, T>(I, c, out, a.part[sp], tile, scratch, xcell, !skip);
     __syncthreads();
 }
 
@@ -667,7 +667,7 @@ __device__ void stats_tile(const StageArgs &a, int tile, double *smem, bool xwl)
     for (int q = 0; q < NC; ++q)
 #pragma unroll
         for (int m = 0; m < K1; ++m) u[q][m] = c.owned ? src[(long long)(q * K1 + m) * ncell + c.g] : 1.0;
-    tile_partials<K, FLUX, T>(I, c, u, a.part[1], a.ntiles, tile, smem + NSTAT,
+    tile_partials<K, FLUX, T>(I, c, u, a.part[1], tile, smem + NSTAT,
                               xwl && I.tail && tile == I.tile0 + I.ntiles - 1);
     __syncthreads();
 }
@@ -690,7 +690,7 @@ __device__ void final_tile(const StageArgs &a, int tile, double *smem, bool xwl)
     load_cell_in<K, FLUX>(I, c, a.BC[bp] + I.offC, a.BD[bp] + I.offD, ci);
     double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
     if (damp) {
-        reduce_instance<nthreads(T), NC>(a.part[(int)((a.ns * N - 1) & 1)], a.ntiles, I.tile0, I.npart, false, red,
+        reduce_instance<nthreads(T), NC>(a.part[(int)((a.ns * N - 1) & 1)], I.tile0, I.npart, false, red,
                                          scratch);
         finish_stats<NC>(I, red, sig);
     }
@@ -774,7 +774,7 @@ __global__ __launch_bounds__(nthreads(T)) void k_fold(StageArgs a, int src) {
     if (tid < NSTAT) red[tid] = 0.0;
     __syncthreads();
     const Inst1D I = a.ninst == 1 ? a.inst0 : a.inst[b];
-    reduce_instance<nthreads(T), NC>(a.part[src], a.ntiles, I.tile0, I.npart, true, red, scratch);
+    reduce_instance<nthreads(T), NC>(a.part[src], I.tile0, I.npart, true, red, scratch);
     if (tid < NSTAT) a.red[(long long)b * NSTAT + tid] = red[tid];
 }
 

@@ -257,11 +257,11 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
     if constexpr (PREP) {
 #pragma unroll
         for (int kd = 0; kd < 3; ++kd) {
-            const double *row = a.fpart + (long long)stat_index(mesh, 0, kd) * a.fntot + a.ftile0;
+            const double *col = a.fpart + (long long)a.ftile0 * NSTAT + stat_index(mesh, 0, kd);   // [tile][row]
 #pragma unroll
             for (int r = 0; r < ADJ_PRE; ++r) {
                 const int tt = tid + r * ADJ_NT;
-                efs[kd][r] = row[tt < a.fntiles ? tt : 0];
+                efs[kd][r] = col[(long long)(tt < a.fntiles ? tt : 0) * NSTAT];
             }
         }
     }
@@ -301,8 +301,9 @@ __global__ __launch_bounds__(ADJ_NT) void k_adj(AdjArgs a) {
 #pragma unroll
             for (int r = 0; r < ADJ_PRE; ++r)
                 if (tid + r * ADJ_NT < a.fntiles) fs[kd] = stat_op(kd, fs[kd], efs[kd][r]);
-            const double *row = a.fpart + (long long)stat_index(mesh, 0, kd) * a.fntot + a.ftile0;
-            for (int tt = tid + ADJ_PRE * ADJ_NT; tt < a.fntiles; tt += ADJ_NT) fs[kd] = stat_op(kd, fs[kd], row[tt]);
+            const double *col = a.fpart + (long long)a.ftile0 * NSTAT + stat_index(mesh, 0, kd);
+            for (int tt = tid + ADJ_PRE * ADJ_NT; tt < a.fntiles; tt += ADJ_NT)
+                fs[kd] = stat_op(kd, fs[kd], col[(long long)tt * NSTAT]);
         }
     }
 

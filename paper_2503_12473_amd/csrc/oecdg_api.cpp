@@ -704,7 +704,6 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
     q.tau = dt;
     q.inv_tm = 1.0 / dt;
     q.inv_n = 1.0 / n;
-    q.fntot = (long long)ntile;
     q.ftile0 = I.tile0;
     q.fntiles = I.npart;
     q.acc = acc;
@@ -953,14 +952,13 @@ int oecdg_dt(oecdg_handle *h, const double *uC, const double *uD, double *dt_out
     int rcs = stats_all(h, a);
     if (rcs != OECDG_OK) return rcs;
     const Inst1D &I = h->inst_h[0];
-    std::vector<double> rows((size_t)2 * I.npart);
-    const size_t ntot = h->ncol;
-    for (int j = 0; j < 2; ++j)
-        HIPCHK(h, hipMemcpyAsync(rows.data() + (size_t)j * I.npart, a.part[1] + (ST_BETA + j) * ntot + I.tile0,
-                                 sizeof(double) * I.npart, hipMemcpyDeviceToHost, h->stream));
+    std::vector<double> recs((size_t)NSTAT * I.npart);        // the instance's tile records
+    HIPCHK(h, hipMemcpyAsync(recs.data(), a.part[1] + (size_t)I.tile0 * NSTAT, sizeof(double) * recs.size(),
+                             hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     double beta = 0.0;
-    for (double b : rows) beta = std::fmax(beta, b);
+    for (int t = 0; t < I.npart; ++t)
+        for (int j = 0; j < 2; ++j) beta = std::fmax(beta, recs[(size_t)t * NSTAT + ST_BETA + j]);
     if (!(beta > 0.0) || !std::isfinite(beta)) return fail(h, OECDG_ENONFINITE, "wave speed is zero or not finite");
     *dt_out = I.cfl * I.h / beta;
     return OECDG_OK;

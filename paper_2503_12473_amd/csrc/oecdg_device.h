@@ -139,77 +139,94 @@ __device__ inline int stat_row(int i) {
     return stat_index(mesh, r / 3, r % 3);
 }
 
+// Per-tile partial statistics are stored [tile][NSTAT]: the NSTAT values of a
+// tile are contiguous (one 160-byte record, read with 16-byte loads).
+__device__ inline const double *part_tile(const double *part, long long tile) { return part + tile * NSTAT; }
+
 // Reduction of the per-tile partial statistics of tiles [tile0, tile0+ntiles)
-// (layout [row][tile], ntot tiles per row) in a fixed order: per-thread strided
-// accumulation over tiles, a butterfly within each wave, then the waves in
-// order.  Split in two so that the loads of the first two tiles per thread can
-// be issued together with the kernel's other independent loads.  The
-// wave-speed rows take part only when ns = 6 NC + 2.
+// in a fixed order: per-thread strided accumulation over tiles, a butterfly
+// within each wave, then the waves in order.  Split in two so that the loads of
+// the first two tiles per thread can be issued together with the kernel's other
+// independent loads.  The wave-speed rows take part only when ns = 6 NC + 2.
 template <int NC>
 struct Partials {
     static constexpr int NS = 6 * NC + 2;
     double v[2][NS];
 };
 
-// The loads of load_partials without the selects (applied by
-// finish_partials_all), so that no wait follows them before the kernel's other
-// independent loads are issued.
+// One tile's record into v (consumer order i -> row stat_row<NC>(i)).
+template <int NC>
+__device__ inline void load_tile_record(const double *rec, double (&v)[Partials<NC>::NS]) {
+    double r[NSTAT];
+    const double2 *q = reinterpret_cast<const double2 *>(rec);
+#pragma unroll
+    for (int j = 0; j < NSTAT / 2; ++j) {
+        const double2 x = q[j];
+        r[2 * j] = x.x;
+        r[2 * j + 1] = x.y;
+    }
+#pragma unroll
+    for (int i = 0; i < Partials<NC>::NS; ++i) v[i] = r[stat_row<NC>(i)];
+}
+
+// The loads of the first two tiles per thread (t and t + NT, clamped to a valid
+// tile; the selects are applied in the reduction, so that no wait follows the
+// loads before the kernel's other independent loads are issued).  A wave none
+// of whose threads has a second tile skips those loads.
 template <int NT, int NC>
-__device__ inline void load_partials_raw(const double *part, long long ntot, int tile0, int ntiles, Partials<NC> &p) {
+__device__ inline void load_partials_raw(const double *part, int tile0, int ntiles, Partials<NC> &p) {
     const int tid = threadIdx.x;
+    load_tile_record<NC>(part_tile(part, tile0 + min(tid, ntiles - 1)), p.v[0]);
+    if (__builtin_amdgcn_readfirstlane(tid) + NT < ntiles) {
+        load_tile_record<NC>(part_tile(part, tile0 + min(tid + NT, ntiles - 1)), p.v[1]);
+    } else {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int t = tid + u * NT;
-#pragma unroll
-        for (int i = 0; i < Partials<NC>::NS; ++i)
-            p.v[u][i] = part[(long long)stat_row<NC>(i) * ntot + tile0 + min(t, ntiles - 1)];
+        for (int i = 0; i < Partials<NC>::NS; ++i) p.v[1][i] = 0.0;   // not used (tid + NT >= ntiles)
     }
 }
 
+// Per-wave part of the reduction: the thread's tiles (selects of the first
+// two, the rest strided), then a fixed-order butterfly; lane WAVE-1 writes
+// scratch[wave][NS].
 template <int NT, int NC>
-__device__ inline void load_partials(const double *part, long long ntot, int tile0, int ntiles, int ns,
-                                     Partials<NC> &p) {
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int t = tid + u * NT;
-#pragma unroll
-        for (int i = 0; i < Partials<NC>::NS; ++i) {
-            const int j = stat_row<NC>(i);
-            // unconditional load of a valid element, then a select: no branch
-            // (and no wait) between the loads
-            const double x = part[(long long)j * ntot + tile0 + min(t, ntiles - 1)];
-            p.v[u][i] = (i < ns && t < ntiles) ? x : stat_identity(stat_kind(j));
-        }
-    }
-}
-
-template <int NT, int NC>
-__device__ void finish_partials(const Partials<NC> &p, const double *part, long long ntot, int tile0, int ntiles,
-                                int ns, double *red, double *scratch) {
+__device__ inline void wave_partials(const Partials<NC> &p, const double *part, int tile0, int ntiles, int ns,
+                                     double *scratch) {
     constexpr int NS = Partials<NC>::NS;
-    constexpr int NW = (NT + WAVE - 1) / WAVE;
     const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
-    {
-        double acc[NS];
+    double acc[NS];
 #pragma unroll
-        for (int i = 0; i < NS; ++i) acc[i] = stat_op(stat_kind(stat_row<NC>(i)), p.v[0][i], p.v[1][i]);
-        for (int t = tid + 2 * NT; t < ntiles; t += NT) {   // more than two tiles per thread
+    for (int i = 0; i < NS; ++i) {
+        const double id = stat_identity(stat_kind(stat_row<NC>(i)));
+        const double x0 = (i < ns && tid < ntiles) ? p.v[0][i] : id;
+        const double x1 = (i < ns && tid + NT < ntiles) ? p.v[1][i] : id;
+        acc[i] = stat_op(stat_kind(stat_row<NC>(i)), x0, x1);
+    }
+    for (int t = tid + 2 * NT; t < ntiles; t += NT) {   // more than two tiles per thread
+        const double *rec = part_tile(part, tile0 + t);
 #pragma unroll
-            for (int i = 0; i < NS; ++i) {
-                if (i < ns) {
-                    const int j = stat_row<NC>(i);
-                    acc[i] = stat_op(stat_kind(j), acc[i], part[(long long)j * ntot + tile0 + t]);
-                }
+        for (int i = 0; i < NS; ++i) {
+            if (i < ns) {
+                const int j = stat_row<NC>(i);
+                acc[i] = stat_op(stat_kind(j), acc[i], rec[j]);
             }
         }
-#pragma unroll
-        for (int i = 0; i < NS; ++i) acc[i] = wave_reduce(stat_kind(stat_row<NC>(i)), acc[i]);
-        if (lane == WAVE - 1) {
-#pragma unroll
-            for (int i = 0; i < NS; ++i) scratch[wave * NS + i] = acc[i];
-        }
     }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) acc[i] = wave_reduce(stat_kind(stat_row<NC>(i)), acc[i]);
+    if (lane == WAVE - 1) {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) scratch[wave * NS + i] = acc[i];
+    }
+}
+
+// The waves' results combined in order by thread i < NS into red[row] (LDS).
+template <int NT, int NC>
+__device__ void finish_partials(const Partials<NC> &p, const double *part, int tile0, int ntiles, int ns, double *red,
+                                double *scratch) {
+    constexpr int NS = Partials<NC>::NS;
+    constexpr int NW = (NT + WAVE - 1) / WAVE;
+    const int tid = threadIdx.x;
+    wave_partials<NT, NC>(p, part, tile0, ntiles, ns, scratch);
     __syncthreads();
     if (tid < NS) {
         const int kd = stat_kind(stat_row<NC>(tid));
@@ -222,36 +239,13 @@ __device__ void finish_partials(const Partials<NC> &p, const double *part, long 
 
 // The same reduction, with every thread combining the per-wave results itself
 // (the order of finish_partials), so that all of them hold all NSTAT rows (rows
-// beyond ns are not computed) after one barrier.
+// beyond ns are zero) after one barrier.
 template <int NT, int NC>
-__device__ void finish_partials_all(const Partials<NC> &p, const double *part, long long ntot, int tile0, int ntiles,
-                                    int ns, double (&red)[NSTAT], double *scratch) {
+__device__ void finish_partials_all(const Partials<NC> &p, const double *part, int tile0, int ntiles, int ns,
+                                    double (&red)[NSTAT], double *scratch) {
     constexpr int NS = Partials<NC>::NS;
     constexpr int NW = (NT + WAVE - 1) / WAVE;
-    const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
-    double acc[NS];
-#pragma unroll
-    for (int i = 0; i < NS; ++i) {           // p from load_partials_raw: the selects of load_partials here
-        const double id = stat_identity(stat_kind(stat_row<NC>(i)));
-        const double x0 = (i < ns && tid < ntiles) ? p.v[0][i] : id;
-        const double x1 = (i < ns && tid + NT < ntiles) ? p.v[1][i] : id;
-        acc[i] = stat_op(stat_kind(stat_row<NC>(i)), x0, x1);
-    }
-    for (int t = tid + 2 * NT; t < ntiles; t += NT) {   // more than two tiles per thread
-#pragma unroll
-        for (int i = 0; i < NS; ++i) {
-            if (i < ns) {
-                const int j = stat_row<NC>(i);
-                acc[i] = stat_op(stat_kind(j), acc[i], part[(long long)j * ntot + tile0 + t]);
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NS; ++i) acc[i] = wave_reduce(stat_kind(stat_row<NC>(i)), acc[i]);
-    if (lane == WAVE - 1) {
-#pragma unroll
-        for (int i = 0; i < NS; ++i) scratch[wave * NS + i] = acc[i];
-    }
+    wave_partials<NT, NC>(p, part, tile0, ntiles, ns, scratch);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NSTAT; ++i) red[i] = 0.0;
@@ -267,12 +261,11 @@ __device__ void finish_partials_all(const Partials<NC> &p, const double *part, l
 }
 
 template <int NT, int NC>
-__device__ void reduce_instance(const double *part, long long ntot, int tile0, int ntiles, bool beta, double *red,
-                                double *scratch) {
+__device__ void reduce_instance(const double *part, int tile0, int ntiles, bool beta, double *red, double *scratch) {
     const int ns = beta ? Partials<NC>::NS : Partials<NC>::NS - 2;
     Partials<NC> p;
-    load_partials<NT, NC>(part, ntot, tile0, ntiles, ns, p);
-    finish_partials<NT, NC>(p, part, ntot, tile0, ntiles, ns, red, scratch);
+    load_partials_raw<NT, NC>(part, tile0, ntiles, p);
+    finish_partials<NT, NC>(p, part, tile0, ntiles, ns, red, scratch);
 }
 
 }  // namespace oecdg

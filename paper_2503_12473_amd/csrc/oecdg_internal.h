@@ -10,8 +10,8 @@ namespace oecdg {
 constexpr int MAXK = 3;
 
 // Per-tile partial statistics written by every stage kernel (and by the
-// statistics kernel) for the state it produced, stored [row][tile].  Row
-// (mesh*3 + q)*3 + kind,
+// statistics kernel) for the state it produced, stored [tile][row] (one
+// record of NSTAT doubles per tile).  Row (mesh*3 + q)*3 + kind,
 // kind 0 = sum of cell averages, 1 = max, 2 = min of the point values at the
 // sigma sample points; ST_BETA = largest wave speed at a cell average.
 constexpr int NSTAT = 20;
@@ -98,7 +98,7 @@ struct StageArgs {
     int tbeg, tend;          // tiles [tbeg, tend) handled by this launch (one degree group)
     Slot *slots;             // [ninst][2]
     Final *fin;              // [ninst]
-    double *part[2];         // [NSTAT][ntiles] each (row-major by statistic)
+    double *part[2];         // [ntiles][NSTAT] each (one record per tile)
     double *BC[2], *BD[2];   // rotating pre-damping stage states
     double *UC, *UD;         // damped u^n of the current step
     double *DC, *DD;         // optional: damped input of stages 1 and 2 (adjoint recomputation)
@@ -134,7 +134,6 @@ struct AdjArgs {
     double hinv, p0, tau, inv_tm;  // 1/h, flux parameter, tau, 1/tau_max
     double inv_n;                  // 1/n (derivative of the mesh average)
     const double *fpart;           // forward per-tile partial statistics of h (the stage prepared here)
-    long long fntot;
     int ftile0, fntiles;
     const double *h;               // undamped output h_l of the stage prepared here
     const double *s;               // damped input s_l of the stage reversed here
