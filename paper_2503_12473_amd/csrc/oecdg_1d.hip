@@ -183,14 +183,16 @@ __device__ inline void cell_pre(const Inst1D &I, int mesh, int g, const double *
 // and its LDS column (both meshes: column g - i0 + 1 of cell g).  Threads
 // [0, T): primal cell i0 + tid; [T, 2T): dual cell i0 + tid - T; the last
 // wave: lane 0 the primal cell i0 - 1, lane 1 the dual cell i0 + T, lane 2 the
-// primal cell i0 + T (the neighbours that the tile's operator reads).  g is
-// wrapped on periodic meshes; elsewhere a primal g of -1 or np is a ghost and a
-// dual g of nd or more no cell.  owned: the thread updates its cell (the dual
-// cell i0 + T only as the instance's dual cell np carried by its last tile in a
-// launch with xwl).
+// primal cell i0 + T (the neighbours that the tile's operator reads, damped),
+// lanes 3 and 4 the dual cells i0 - 1 and i0 + T + 1 (which the damping of
+// lanes 0 and 2 reads, undamped).  g is wrapped on periodic meshes; elsewhere a
+// primal g of -1 or np is a ghost and a dual g of nd or more no cell.  damps:
+// the thread damps its cell; owned: it also updates it (the dual cell i0 + T
+// only as the instance's dual cell np carried by its last tile in a launch
+// with xwl).
 struct TCell {
     int mesh, col, g;
-    bool has, owned;
+    bool has, damps, owned;
 };
 template <int T>
 __device__ inline TCell tile_cell(const Inst1D &I, int tile, int i0, bool xwl) {
@@ -202,14 +204,15 @@ __device__ inline TCell tile_cell(const Inst1D &I, int tile, int i0, bool xwl) {
         const int s = tid - c.mesh * T;
         g = i0 + s;
         c.col = s + 1;
-        c.has = true;
+        c.has = c.damps = true;
         c.owned = g < (c.mesh == 0 ? I.np : I.nd);
     } else {
         const int lane = tid - 2 * T;
-        c.mesh = lane == 1 ? 1 : 0;
-        g = lane == 0 ? i0 - 1 : i0 + T;
-        c.col = lane == 0 ? 0 : T + 1;
-        c.has = lane < 3;
+        c.mesh = (lane == 1 || lane == 3 || lane == 4) ? 1 : 0;
+        g = (lane == 0 || lane == 3) ? i0 - 1 : (lane == 4 ? i0 + T + 1 : i0 + T);
+        c.col = (lane == 0 || lane == 3) ? 0 : (lane == 4 ? T + 2 : T + 1);
+        c.has = lane < 5;
+        c.damps = lane < 3;
         c.owned = xwl && lane == 1 && I.tail && tile == I.tile0 + I.ntiles - 1 && g < I.nd;
     }
     if (I.bc == 0) {                         // periodic (meshes shorter than a tile too)
@@ -234,6 +237,22 @@ __device__ inline void overlap_cells(const Inst1D &I, int mesh, int g, int &l, i
         r = g;
         if (I.bc == 0 && l < 0) l += I.np;
     }
+}
+
+template <int K, int NC, int W>
+__device__ inline void lds_cell(const double *s, int col, double (&c)[NC][K + 1]) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m <= K; ++m) c[q][m] = s[(q * (K + 1) + m) * W + col];
+}
+
+template <int K, int NC, int W>
+__device__ inline void lds_put(double *s, int col, const double (&c)[NC][K + 1]) {
+#pragma unroll
+    for (int q = 0; q < NC; ++q)
+#pragma unroll
+        for (int m = 0; m <= K; ++m) s[(q * (K + 1) + m) * W + col] = c[q][m];
 }
 
 // This thread's cell, damped: its undamped coefficients and those of the two
@@ -267,12 +286,40 @@ __device__ inline void load_cell_in(const Inst1D &I, const TCell &c, const doubl
     cell_pre<K, FLUX>(I, 1 - c.mesh, r, inC, inD, ci.nr);
 }
 
+// The stage kernel's variant: only the thread's own cell from memory (a wall
+// ghost's thread: the end cell); the overlapping cells come from the tile's
+// undamped image in LDS (lds_overlaps).
+template <int K, int FLUX>
+__device__ inline void load_own(const Inst1D &I, const TCell &c, const double *__restrict__ inC,
+                                const double *__restrict__ inD, CellIn<K, FLUX> &ci) {
+    const int n = c.mesh == 0 ? I.np : I.nd;
+    ci.real = c.has && c.g >= 0 && c.g < n;
+    ci.mirror = false;
+    if constexpr (FLUX == 3)
+        ci.mirror = c.damps && c.mesh == 0 && I.bc == 2 && (c.g == -1 || c.g == I.np);
+    cell_pre<K, FLUX>(I, c.mesh, ci.mirror ? (c.g < 0 ? 0 : I.np - 1) : c.g, inC, inD, ci.own);
+}
+
+// The overlapping cells of the cell that the thread damps, from the undamped
+// image (uo: the other mesh's image, columns g - i0 + 1): a primal cell in
+// column x has dual x, x + 1; a dual cell in column x has primal x - 1, x; a
+// wall ghost's end cell sits next to the ghost's column.
+template <int K, int FLUX, int W>
+__device__ inline void lds_overlaps(const TCell &c, const double *uo, CellIn<K, FLUX> &ci) {
+    constexpr int NC = FluxT<FLUX>::NC;
+    int x = c.col;
+    if (c.mesh == 0 && ci.mirror) x = c.g < 0 ? x + 1 : x - 1;
+    const int l = c.mesh == 0 ? x : x - 1;
+    lds_cell<K, NC, W>(uo, l, ci.nl);
+    lds_cell<K, NC, W>(uo, l + 1, ci.nr);
+}
+
 template <int K, int FLUX>
 __device__ inline void damp_cell(const Inst1D &I, const TCell &c, CellIn<K, FLUX> &ci, const double (*sig)[3],
                                  double tau, bool damp) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC, K1 = K + 1;
-    if (damp && (ci.real || ci.mirror)) {
+    if (damp && c.damps && (ci.real || ci.mirror)) {
         double ubar[NC];
 #pragma unroll
         for (int q = 0; q < NC; ++q) ubar[q] = ci.own[q][0];
@@ -290,22 +337,6 @@ __device__ inline void damp_cell(const Inst1D &I, const TCell &c, CellIn<K, FLUX
 #pragma unroll
             for (int m = 0; m <= K; ++m) ci.own[q][m] *= mirror_sign(q, m);
     }
-}
-
-template <int K, int NC, int W>
-__device__ inline void lds_cell(const double *s, int col, double (&c)[NC][K + 1]) {
-#pragma unroll
-    for (int q = 0; q < NC; ++q)
-#pragma unroll
-        for (int m = 0; m <= K; ++m) c[q][m] = s[(q * (K + 1) + m) * W + col];
-}
-
-template <int K, int NC, int W>
-__device__ inline void lds_put(double *s, int col, const double (&c)[NC][K + 1]) {
-#pragma unroll
-    for (int q = 0; q < NC; ++q)
-#pragma unroll
-        for (int m = 0; m <= K; ++m) s[(q * (K + 1) + m) * W + col] = c[q][m];
 }
 
 // Partial statistics of one cell's output (valid: an owned cell; otherwise the
@@ -436,7 +467,10 @@ __device__ inline void finish_stats(const Inst1D &I, const double *red, double (
     }
 }
 
-constexpr int lds_doubles(int K, int NC, int T) { return 2 * NC * (K + 1) * (T + 2); }
+// LDS of a tile: the damped and the undamped image of both meshes, columns
+// 0 .. T + 2 (cells i0 - 1 .. i0 + T + 1).
+constexpr int lds_width(int T) { return T + 3; }
+constexpr int lds_doubles(int K, int NC, int T) { return 4 * NC * (K + 1) * lds_width(T); }
 constexpr int scratch_doubles(int T) { return NSTAT * ((nthreads(T) + WAVE - 1) / WAVE) + NSTAT; }
 
 // ---------------------------------------------------------- stage tile ---
@@ -449,7 +483,7 @@ template <int K, int FLUX, int T, bool COH = false>
 __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int tile, double *smem, bool xwl,
                            bool folded) {
     using F = FluxT<FLUX>;
-    constexpr int NC = F::NC, K1 = K + 1, W = T + 2, PER = NC * K1 * W, NT = nthreads(T);
+    constexpr int NC = F::NC, K1 = K + 1, W = lds_width(T), PER = NC * K1 * W, NT = nthreads(T);
     const int tid = threadIdx.x;
     constexpr bool coh = COH;
     Tile1D tl;
@@ -470,7 +504,8 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     Slot *S = a.slots + 2 * tl.inst;
     const bool single = a.tau_override > 0.0;
     const int sp = ((a.ns & 1 ? par : 0) + l) & 1;   // parity of the global stage index ns n + l
-    double *sC = smem, *sD = smem + PER;
+    // LDS images, [damped C, damped D, undamped C, undamped D] x PER (offsets,
+    // not selected pointers: the compiler mishandles a select of LDS pointers)
     double *scratch = smem + lds_doubles(K, NC, T) + NSTAT;
 
     const TCell c = tile_cell<T>(I, tile, i0, xwl);
@@ -491,7 +526,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     // and the RK4 sum of the cell, the previous stage's partial statistics.
     const Slot cur = ld_slot(&S[par], coh), prev = ld_slot(&S[par ^ 1], coh);
     CellIn<K, FLUX> ci;
-    load_cell_in<K, FLUX>(I, c, a.BC[sp] + I.offC, a.BD[sp] + I.offD, ci);
+    load_own<K, FLUX>(I, c, a.BC[sp] + I.offC, a.BD[sp] + I.offD, ci);
     double un[NC][K1], acc[NC][K1];
 #pragma unroll
     for (int q = 0; q < NC; ++q)
@@ -524,6 +559,17 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
         S[par].done = 1;
         S[par ^ 1].t = cur.t;
     }
+    // the undamped image (a wall ghost: the mirror image of its end cell), for
+    // the overlapping cells of every damped cell; the barrier of the
+    // reduction below covers it
+    if (c.has) {
+        double g[NC][K1];
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int m = 0; m < K1; ++m) g[q][m] = ci.mirror ? mirror_sign(q, m) * ci.own[q][m] : ci.own[q][m];
+        lds_put<K, NC, W>(smem + (2 + c.mesh) * PER, c.col, g);
+    }
     double red[NSTAT];                       // the reduced statistics, in every thread
     if (need_red) {
         if (folded) {
@@ -534,6 +580,8 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
         } else {
             finish_partials_all<NT, NC>(pv, a.part[sp ^ 1], I.tile0, I.npart, ns, red, scratch);
         }
+    } else {
+        __syncthreads();
     }
 
     double tau, taumax;
@@ -569,9 +617,12 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     }
 
     double sig[2][3] = {{0, 0, 0}, {0, 0, 0}};
-    if (damp) finish_stats<NC>(I, red, sig);
+    if (damp) {
+        finish_stats<NC>(I, red, sig);
+        if (c.damps && (ci.real || ci.mirror)) lds_overlaps<K, FLUX, W>(c, smem + (3 - c.mesh) * PER, ci);
+    }
     damp_cell<K, FLUX>(I, c, ci, sig, (l == 0) ? prev.tau : tau, damp);
-    if (c.has) lds_put<K, NC, W>(c.mesh == 0 ? sC : sD, c.col, ci.own);
+    if (c.damps) lds_put<K, NC, W>(smem + c.mesh * PER, c.col, ci.own);
     __syncthreads();
 
     double out[NC][K1];
@@ -597,9 +648,9 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
         // the damped cells of the other mesh that overlap this one (left, right)
         double nb[NC][K1], rl[NC][K1], rr[NC][K1];
         const double ft = taumax * (1.0 / I.h);
-        lds_cell<K, NC, W>(c.mesh == 0 ? sD : sC, c.mesh == 0 ? c.col : c.col - 1, nb);
+        lds_cell<K, NC, W>(smem + (1 - c.mesh) * PER, c.mesh == 0 ? c.col : c.col - 1, nb);
         cdg_rate_half<K, FLUX>(nb, 0, I.p0, ft, rl);
-        lds_cell<K, NC, W>(c.mesh == 0 ? sD : sC, c.mesh == 0 ? c.col + 1 : c.col, nb);
+        lds_cell<K, NC, W>(smem + (1 - c.mesh) * PER, c.mesh == 0 ? c.col + 1 : c.col, nb);
         cdg_rate_half<K, FLUX>(nb, 1, I.p0, ft, rr);
 
         // eq:RKCDG: out = c_{l0} u^n [+ accumulated earlier stages] + c_{ll} u^l + tau d_{ll} L(u^l)
