@@ -92,15 +92,17 @@ enum {
 /* Option keys for oecdg_set_option. */
 enum {
     OECDG_OPT_MODE = 1,         /* OECDG_MODE_* */
-    OECDG_OPT_TILE = 2,         /* primal cells per workgroup tile: 32, 64 or 128 (1D) */
+    OECDG_OPT_TILE = 2,         /* primal cells per workgroup tile: 32, 64 or 128 (1D; 128 spills
+                                 * registers and is never the library's choice) */
     OECDG_OPT_GRAPH_STEPS = 3,  /* steps per captured graph (>= 1) */
     OECDG_OPT_GRID = 4,         /* workgroups of the persistent launch (0: library choice) */
     OECDG_OPT_FOLD = 5          /* where the global statistics of Sec. 2.2 (avg, sigma) and the wave
                                  * speed are reduced before each 1D stage: 0 library choice (a
-                                 * per-instance fold kernel for batches, inside every stage
-                                 * workgroup for single instances), 1 inside the stage kernel,
-                                 * 2 the fold kernel (not with the extra-wave tail mode, which then
-                                 * reduces inside).  The same bits either way. */
+                                 * per-instance fold kernel for batches and for meshes of more
+                                 * than 1024 tiles, inside every stage workgroup otherwise),
+                                 * 1 inside the stage kernel, 2 the fold kernel (not when the
+                                 * last tile carries the dual cell np, which then reduces
+                                 * inside).  The same bits either way. */
 };
 
 /* Problem descriptor (one instance).  Sec. 2.1 defines the meshes and the

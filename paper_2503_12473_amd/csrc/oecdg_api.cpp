@@ -168,8 +168,10 @@ Inst1D oecdg::make_inst(const oecdg_desc &e) {
 }
 
 // Default tile: 64 primal + 64 dual cells per workgroup unless the mesh is
-// small (32: more workgroups) or very large (128: fewer partial statistics).
-int oecdg::default_tile(int64_t maxn, int nbatch) { return maxn <= 4096 && nbatch == 1 ? 32 : (maxn <= 65536 ? 64 : 128); }
+// small (32: more workgroups).  (Tiles of 128 run five waves per workgroup,
+// which caps the registers at 256 and spills; large meshes fold their
+// statistics instead, fold_on.)
+int oecdg::default_tile(int64_t maxn, int nbatch) { return maxn <= 4096 && nbatch == 1 ? 32 : 64; }
 
 // An outflow/walled mesh whose primal count is a multiple of T has its dual
 // cell np beyond np / T full tiles.
@@ -229,9 +231,11 @@ int build_tiles(oecdg_handle *h) {
 
 // Statistics folded by a separate per-instance kernel (k_fold) before each
 // stage launch, instead of every workgroup reducing its instance's partials:
-// the default for batches; single instances reduce in-kernel unless asked.
+// the default for batches and for meshes of more than 1024 tiles (whose
+// in-kernel reduction would read every tile's record in every workgroup);
+// other single instances reduce in-kernel unless asked.
 bool fold_on(const oecdg_handle *h) {
-    return !h->tailwave && (h->fold == 2 || (h->fold == 0 && h->nbatch > 1));
+    return !h->tailwave && (h->fold == 2 || (h->fold == 0 && (h->nbatch > 1 || h->ncol > 1024)));
 }
 
 StageArgs base_args(oecdg_handle *h) {
