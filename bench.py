@@ -84,6 +84,18 @@ def stage_profile():
     return meta if meta.get("source_sha256") == h.hexdigest() else {}
 
 
+OPCOUNT_JSON = os.path.join(ROOT, "profiles", "oracle_opcount.json")
+
+
+def oracle_opcount(phase):
+    """Operations per DOF of the oracle's plain evaluation (the committed output
+    of oracle/opcount/run.py; a stored file, the oracle is not run here)."""
+    try:
+        return json.load(open(OPCOUNT_JSON)).get(phase, {}).get("flops_per_dof")
+    except OSError:
+        return None
+
+
 PROFILE2D_JSON = os.path.join(ROOT, "profiles", "k_stage2d_euler2d_q2_n1024.json")
 KERNEL2D_SOURCES = ["paper_2503_12473_amd/csrc/oecdg_2d.hip", "paper_2503_12473_amd/csrc/oecdg_tables.h",
                     "paper_2503_12473_amd/csrc/oecdg_device.h"]
@@ -266,6 +278,10 @@ def euler2d_bench(repeats: int = 5, steps: int = E2D_STEPS):
             "roofline": {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": tflops / FP64_PEAK_TFLOPS if tflops else None,
                          "flops": "executed FP64 (counted wave instructions x 64 lanes, FMA = 2)",
+                         "executed_flops_per_dof_update": 3 * flops / dofs if flops else None,
+                         "oracle_flops_per_dof_update": oracle_opcount("2d_euler_q2.step"),
+                         "oracle_note": "operations of the oracle's plain evaluation (no sum factorisation), counted "
+                                        "by oracle/opcount; the kernels execute fewer",
                          "hbm": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": achieved / HBM_PEAK_GBS, "traffic": prof.get("traffic_bytes_per_stage")},
                          "kernel": "per RK stage: k_stage2d (OE of the previous stage + operator + SSP-RK3) "
@@ -508,10 +524,18 @@ def main():
                      "kernel": "k_stage (one RK stage + OE of the previous stage)",
                      "launch_us": 1e6 * launch_s,
                      "launch_us_rocprof": prof.get("avg_duration_us"),
+                     "frac_rocprof": (bytes_per_launch / (prof["avg_duration_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+                                      if prof.get("avg_duration_us") else None),
                      "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "fp64": {"executed_tflops": (prof["fp64_flops_per_launch"] / launch_s / 1e12
+                                                  if prof.get("fp64_flops_per_launch") else None),
+                              "peak": FP64_PEAK_TFLOPS,
+                              "executed_flops_per_dof_update": (3 * prof["fp64_flops_per_launch"] / dofs
+                                                                if prof.get("fp64_flops_per_launch") else None),
+                              "oracle_flops_per_dof_update": oracle_opcount("1d_euler_p2.step")},
                      "note": "state of 2.4 MB per array, resident in L2/MALL: each stage is bound by its "
                              "dependency chain (global statistics of the previous stage, damping, operator), "
-                             "not by HBM bandwidth"},
+                             "not by HBM bandwidth or FP64 issue"},
     }
     solver.close()
     if not args.no_batched:

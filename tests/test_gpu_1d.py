@@ -408,3 +408,27 @@ def test_statistics_fold_modes_give_the_same_bits(n, k):
             a, b = to_device(uC), to_device(uD)
             s.run(a, b, nsteps=40)
             assert _rel(a.cpu().numpy(), b.cpu().numpy(), rC, rD) <= RUN_TOL
+
+
+def test_large_mesh_folds_its_statistics():
+    """N = 80000 (1251 tiles of 64): the library folds the statistics with the
+    per-instance kernel (more than 1024 tiles) and gives the bits of the
+    in-kernel reduction, and the oracle's result to the run bar."""
+    prob, uC, uD = inputs.euler_riemann(80000, 2, inputs.riemann_states(4))
+    outs = []
+    for fold in (0, 1):
+        print(f"[large] n=80000 fold={fold}", flush=True)
+        with OECDG(prob, 0.15) as s:
+            if fold:
+                s.set_option(_lib.OPT_FOLD, fold)
+            a, b = to_device(uC), to_device(uD)
+            t, ns = s.run(a, b, nsteps=8)
+            outs.append((a.cpu().numpy(), b.cpu().numpy(), t, ns))
+    assert outs[0][2:] == outs[1][2:]
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, nsteps=8, cfl=0.15)
+    # tau comes from the largest wave speed at a cell average, which both sides
+    # evaluate on states that agree to rounding: the time agrees to rounding
+    assert outs[0][3] == rn and abs(outs[0][2] - rt) <= 1e-12 * rt
+    assert _rel(outs[0][0], outs[0][1], rC, rD) <= RUN_TOL
