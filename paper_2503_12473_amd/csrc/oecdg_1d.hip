@@ -807,7 +807,7 @@ __global__ __launch_bounds__(nthreads(T)) void k_stage(StageArgs a) {
 // instance's partial columns, and a workgroup walks the tiles tbeg +
 // blockIdx.x, + gridDim.x, ...
 template <int K, int FLUX, int T>
-__global__ __launch_bounds__(nthreads(T)) void k_stage_folded(StageArgs a) {
+__global__ __launch_bounds__(nthreads(T), T == 64 && K <= 2 ? 3 : 1) void k_stage_folded(StageArgs a) {
     __shared__ double smem[lds_doubles(K, FluxT<FLUX>::NC, T) + scratch_doubles(T)];
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x)
         stage_tile<K, FLUX, T>(a, a.l, a.par, a.first, tile, smem, false, true);
