@@ -342,10 +342,11 @@ __device__ inline void damp_cell(const Inst1D &I, const TCell &c, CellIn<K, FLUX
 // Partial statistics of one cell's output (valid: an owned cell; otherwise the
 // identities): the cell average, max and min over the sigma sample points
 // (both halves: the right-half nodes and xi = 1, and their mirror images
-// through the sign flip of odd modes), and the wave speed at the average.
+// through the sign flip of odd modes), and the wave speed at the average (beta:
+// only a step's last stage, whose output gives the next step's tau).
 template <int K, int FLUX>
 __device__ inline void cell_stats(const Inst1D &I, bool valid, const double (&out)[FluxT<FLUX>::NC][K + 1],
-                                  double (&v)[3 * FluxT<FLUX>::NC + 1]) {
+                                  double (&v)[3 * FluxT<FLUX>::NC + 1], bool beta = true) {
     using F = FluxT<FLUX>;
     constexpr int NC = F::NC;
     constexpr Tab<K> tb = make_tab<K>();
@@ -371,7 +372,7 @@ __device__ inline void cell_stats(const Inst1D &I, bool valid, const double (&ou
     double ubar[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) ubar[q] = out[q][0];
-    v[3 * NC] = valid ? F::speed(ubar, I.p0) : -INFINITY;
+    v[3 * NC] = valid && beta ? F::speed(ubar, I.p0) : -INFINITY;
 }
 
 // Kind of value j of cell_stats: sum, max, min per component, then max.
@@ -399,11 +400,11 @@ __device__ inline double half_wave_reduce(int kind, double v) {
 template <int K, int FLUX, int T>
 __device__ inline void tile_partials(const Inst1D &I, const TCell &c, const double (&out)[FluxT<FLUX>::NC][K + 1],
                                      double *part, int tile, double *scratch, bool xcell,
-                                     bool write = true) {
+                                     bool write = true, bool beta = true) {
     constexpr int NC = FluxT<FLUX>::NC, NV = 3 * NC + 1;
     const int tid = threadIdx.x, lane = tid % WAVE;
     double v[NV];
-    cell_stats<K, FLUX>(I, c.owned, out, v);
+    cell_stats<K, FLUX>(I, c.owned, out, v, beta);
     auto put = [&](int mesh, int j, double x) {
         const int row = j == 3 * NC ? ST_BETA + mesh : stat_index(mesh, j / 3, j % 3);
         if (write) part[(long long)tile * NSTAT + row] = x;
@@ -698,8 +699,10 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
             a.err[3] = (int)(a.fin[tl.inst].nexec + 1);
         }
     }
-    tile_partials<K, FLUX, T>(I, c, out, a.part[sp], tile, scratch, xcell, !skip);
-    __syncthreads();
+    // the wave speeds only where a step's tau reads them: after its last stage
+    // (a single-stage call writes them always)
+    tile_partials<K, FLUX, T>(I, c, out, a.part[sp], tile, scratch, xcell, !skip, single || l == a.ns - 1);
+    if (tile + (int)gridDim.x < a.tend) __syncthreads();   // the workgroup's next tile reuses the LDS
 }
 
 // Statistics of a given state (srcC/srcD) into part[1]: the partials that the
