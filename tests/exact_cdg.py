@@ -97,21 +97,36 @@ def _piece(coeffs, mesh, p, n, k):
     return out
 
 
-def bilinear(u, phi, n, k, a, tau_max):
-    """H(u, phi) of eq:1D_H with f(u) = a u (exact).
+def linear_flux(a):
+    """f(u) = a u, as (polynomial map, value map)."""
+    a = F(a)
+    return (lambda p: pscale(p, a)), (lambda v: a * v)
+
+
+def burgers_flux():
+    """f(u) = u^2 / 2, as (polynomial map, value map): the composition of a
+    piecewise polynomial with f stays a polynomial, so H stays exact."""
+    return (lambda p: pscale(pmul(p, p), F(1, 2))), (lambda v: v * v / 2)
+
+
+def bilinear(u, phi, n, k, a, tau_max, flux=None):
+    """H(u, phi) of eq:1D_H (exact), with f(u) = a u unless flux = (polynomial
+    map, value map) names another polynomial flux.
 
     u, phi: nested lists [mesh][m][cell] of rationals."""
+    fpoly, fval = flux if flux is not None else linear_flux(a)
     H = F(0)
-    a = F(a)
     tm = F(tau_max)
     for p in range(2 * n):
         lo, hi = F(p, 2), F(p + 1, 2)
-        u1, u2 = _piece(u, 0, p, n, k), _piece(u, 1, p, n, k)
         f1, f2 = _piece(phi, 0, p, n, k), _piece(phi, 1, p, n, k)
+        if not any(f1) and not any(f2):
+            continue                                # phi vanishes on this piece
+        u1, u2 = _piece(u, 0, p, n, k), _piece(u, 1, p, n, k)
         d = padd(u1, pscale(u2, -1))
         e = padd(f1, pscale(f2, -1))
         integrand = padd(pscale(pmul(d, e), -1 / tm),
-                         padd(pscale(pmul(u2, pder(f1)), a), pscale(pmul(u1, pder(f2)), a)))
+                         padd(pmul(fpoly(u2), pder(f1)), pmul(fpoly(u1), pder(f2))))
         H += pint(integrand, lo, hi)
     # primal edges X = 0..n-1: f(u2)(X) [phi1(X^-) - phi1(X^+)]
     for X in range(n):
@@ -119,14 +134,25 @@ def bilinear(u, phi, n, k, a, tau_max):
         xl = F(X) if pl != 2 * n - 1 else F(n)      # left limit taken on the wrapped piece
         u2 = peval(_piece(u, 1, pr, n, k), F(X))
         jump = peval(_piece(phi, 0, pl, n, k), xl) - peval(_piece(phi, 0, pr, n, k), F(X))
-        H -= a * u2 * jump
+        H -= fval(u2) * jump
     # dual edges Y = X + 1/2: f(u1)(Y) [phi2(Y^-) - phi2(Y^+)]
     for X in range(n):
         Y = F(2 * X + 1, 2)
         u1 = peval(_piece(u, 0, 2 * X, n, k), Y)
         jump = peval(_piece(phi, 1, 2 * X, n, k), Y) - peval(_piece(phi, 1, 2 * X + 1, n, k), Y)
-        H -= a * u1 * jump
+        H -= fval(u1) * jump
     return H
+
+
+def operator_rhs(u, n, k, tau_max, flux):
+    """L(u) of M dL/dt = H(u, .) (exact): L[mesh][m][cell] = H(u, e) / int e^2
+    for every basis function e (h = 1, so int P_m(2(x - c))^2 = 1 / (2m + 1))."""
+    out = [[[F(0)] * n for _ in range(k + 1)] for _ in range(2)]
+    for idx in range(2 * (k + 1) * n):
+        mesh, rem = divmod(idx, (k + 1) * n)
+        m, cell = divmod(rem, n)
+        out[mesh][m][cell] = bilinear(u, unit(idx, n, k), n, k, 0, tau_max, flux) * (2 * m + 1)
+    return out
 
 
 def gram(u, phi, n, k):

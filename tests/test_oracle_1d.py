@@ -78,6 +78,54 @@ def test_rhs_matches_exact_bilinear_form(k, a):
 
 
 @pytest.mark.parametrize("k", [0, 1, 2])
+def test_burgers_rhs_matches_exact_bilinear_form(k):
+    """Nonlinear flux f(u) = u^2/2 on generic discontinuous data: the oracle's
+    per-cell equations (equcdg, Gauss quadrature with k+1 nodes per half cell)
+    against the global bilinear form of eq:1D_H in exact rational arithmetic.
+    f(u_h) phi' has degree 3k - 1 <= 2k + 1 for k <= 2, so the quadrature is
+    exact there and the two agree to rounding: this pins the volume terms, the
+    edge terms of both meshes and the coupling for a nonlinear flux."""
+    n, tau_max = 3, 0.25
+    prob = Problem1D(k=k, nc=1, flux=FLUX_BURGERS, bc=BC_PERIODIC, n=n, xlo=0.0, xhi=float(n))
+    uC, uD = _random_state(prob)
+    uC[0, 0] += 0.7                                                 # a mean flow, so f' does not vanish
+    u = [[[F(float(v)) for v in row] for row in arr[0]] for arr in (uC, uD)]
+    L = exact_cdg.operator_rhs(u, n, k, F(1, 4), exact_cdg.burgers_flux())
+    LC, LD = ora.rhs1d(prob, tau_max, uC, uD)
+    for mesh, got in enumerate((LC, LD)):
+        ref = np.array([[float(v) for v in row] for row in L[mesh]])
+        np.testing.assert_allclose(got[0], ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_five_steps_match_a_40_digit_brute_force(k):
+    """Five full SSP-RK3 steps of eq:RKCDG with F_tau after every stage
+    (Burgers, periodic, n = 5, generic discontinuous data, OE active) against a
+    40-digit evaluation by a route of its own (tests/brute_cdg.py: exact
+    polynomial integrals instead of Gauss quadrature, the convex-combination
+    form of SSP-RK3, delta from x-derivatives of the piecewise polynomials,
+    F_tau as the matrix exponential of the damping ODE in a monomial basis).
+    The oracle must sit at FP64 rounding distance from it."""
+    from tests import brute_cdg
+    n, tau = 5, 0.1
+    prob = Problem1D(k=k, nc=1, flux=FLUX_BURGERS, bc=BC_PERIODIC, n=n, xlo=0.0, xhi=float(n))
+    uC, uD = _random_state(prob)
+    uC[0, 0] += 0.7
+    uD[0, 0] += 0.7
+    if k >= 1:
+        dC, _ = ora.delta1d(prob, uC, uD)
+        assert dC.max() > 1.0                                       # the damping is doing something
+    vC, vD = uC.copy(), uD.copy()
+    for _ in range(5):
+        vC, vD = ora.step1d(prob, tau, tau, vC, vD)
+    bC, bD = brute_cdg.run(uC[0], uD[0], n, k, tau, tau, 5)
+    scale = max(np.abs(vC).max(), np.abs(vD).max())
+    assert np.abs(vC - uC).max() > 0.1 * scale                     # the state has moved
+    np.testing.assert_allclose(vC[0], np.array(bC), rtol=0, atol=1e-13 * scale)
+    np.testing.assert_allclose(vD[0], np.array(bD), rtol=0, atol=1e-13 * scale)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
 def test_skew_symmetry_lemma_exact(k):
     """lem:skew-symm: H(h,g) + H(g,h) = -(2/tau_max) int (h1-h2)(g1-g2), exactly."""
     n, tm = 3, F(1, 3)
