@@ -432,7 +432,46 @@ def cpu_baseline(target_seconds: float):
     return {"value": prob.dofs() * done / wall, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"first {done} of {FULL_STEPS} steps of the same workload, serial C oracle "
                       f"(-O2, no FP contraction), {wall:.1f} s",
-            "cpu": model, "host_cpus": os.cpu_count()}
+            "cpu": model, "host_cpus": os.cpu_count(),
+            "all_cores": cpu_all_cores(target_seconds / 3, min(16, os.cpu_count() or 1))}
+
+
+_CPU_WORKER = """
+import sys, time
+sys.path.insert(0, {root!r})
+from oracle import ora
+from paper_2503_12473_amd import inputs
+prob, uC, uD = inputs.euler_riemann({n}, {k}, inputs.riemann_states({seed}))
+t0 = time.perf_counter()
+ora.run1d(prob, uC, uD, nsteps=2, cfl={cfl}, t_end={t_end})
+steps = max(2, int({seconds} / max((time.perf_counter() - t0) / 2, 1e-6)))
+t0 = time.perf_counter()
+_, _, _, done = ora.run1d(prob, uC, uD, nsteps=steps, cfl={cfl}, t_end={t_end})
+print(prob.dofs() * done / (time.perf_counter() - t0), done)
+"""
+
+
+def cpu_all_cores(seconds: float, nproc: int):
+    """Secondary CPU figure: the same serial oracle sample in nproc independent
+    processes at once (one copy of the workload each, as independent instances
+    of a batch would run), summed.  The children are CPU-only programs (no GPU
+    library is loaded in them)."""
+    import subprocess
+    code = _CPU_WORKER.format(root=ROOT, n=N_CELLS, k=DEGREE, seed=SEED, cfl=CFL, t_end=T_END, seconds=seconds)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                              text=True, env=env) for _ in range(nproc)]
+    rates, steps = [], []
+    for p in procs:
+        out, err = p.communicate(timeout=600)
+        if p.returncode != 0:
+            return {"error": f"worker exited with {p.returncode}: {err.strip()[-200:]}"}
+        r, d = out.split()
+        rates.append(float(r))
+        steps.append(int(d))
+    return {"value": sum(rates), "unit": "DOF-updates/s", "cores": nproc, "kind": "oracle",
+            "sample": f"{nproc} processes, each the first {min(steps)}-{max(steps)} steps of its own copy of the "
+                      f"workload (about {seconds:.0f} s each), rates summed"}
 
 
 def main():
