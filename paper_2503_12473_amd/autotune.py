@@ -1,8 +1,9 @@
 """Tile-size autotuner for the 1D stage kernels.
 
-A workgroup owns T primal + T dual cells with two threads per cell.  Small
-tiles give more workgroups (good for small meshes and latency), large tiles
-fewer partial statistics to reduce (good for large meshes).  The tuner times
+A workgroup owns T primal + T dual cells, one thread per cell, plus one wave
+for the cells next to the tile.  Small tiles give more workgroups (good for
+small meshes and latency), large tiles fewer partial statistics to reduce and a
+smaller share of neighbour cells (good for large meshes).  The tuner times
 a few RK steps of the real batch for each candidate T on scratch copies of
 the state and keeps the fastest; results are cached per batch shape (flux,
 degrees, mesh-size bucket, batch-size bucket, GPU architecture), in memory and
