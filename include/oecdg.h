@@ -136,8 +136,8 @@ typedef struct {
 int oecdg_state_size(const oecdg_desc *d, int64_t *n_primal, int64_t *n_dual);
 
 /* Create a handle for nbatch >= 1 instances described by d[0..nbatch-1]
- * (nbatch > 1: 1D instances only, each with its own nx, k, flux, bc and
- * cfl).  With nbatch > 1 the state arrays passed to the other entry points
+ * (nbatch > 1: 1D instances only, each with its own nx, k, bc and cfl;
+ * one flux and one RK method per batch, EUNSUPPORTED otherwise).  With nbatch > 1 the state arrays passed to the other entry points
  * are the concatenation of the instances' arrays in order (offsets from
  * oecdg_batch_offsets).  stream: a hipStream_t (NULL = default stream). */
 int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle **out);

@@ -13,7 +13,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oecdg_oracle.c", "oecdg_oracle_2d.c", "oecdg_oracle_nu.c"]
+SOURCES = ["oecdg_oracle.c", "oecdg_oracle_2d.c", "oecdg_oracle_nu.c", "oecdg_ref.c"]
 LIB = os.path.join(HERE, "liboecdg_oracle.so")
 VARIANTS = {
     "fma": ["-ffp-contract=fast", "-mfma"],

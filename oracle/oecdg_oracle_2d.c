@@ -523,6 +523,44 @@ int ora2d_step(const ora2d *p, int rk, int oe, double tau, double tau_max, doubl
     return rc;
 }
 
+/* One stage l of the RK table rk in the c/d form of eq:RKCDG from u_sigma^n and
+ * u_sigma^{n,l}, then F_tau: out = F_tau(c_{l0} u^n + c_{ll} u^l + tau d_{ll} L(u^l)),
+ * for the stages whose other c_{lm}, d_{lm} vanish (as the 1D single stage);
+ * EINVAL for the others.  Under P^k the combination is truncated first, as in
+ * a step. */
+int ora2d_rk_stage(const ora2d *p, int rk, int l, int oe, double tau, double tau_max,
+                   const double *unC, const double *unD, const double *ulC, const double *ulD,
+                   double *outC, double *outD)
+{
+    double c[4][4], d[4][4];
+    const int s = ora_rk_table(rk, c, d);
+    if (s == 0 || l < 0 || l >= s) return ORA_EINVAL;
+    for (int m = 0; m < l; ++m)
+        if ((m > 0 && c[l][m] != 0.0) || d[l][m] != 0.0) return ORA_EINVAL;
+    const long sz1 = (long)p->nc * (p->k + 1) * (p->k + 1) * p->nx * p->ny;
+    double *LC = malloc(sizeof(double) * sz1), *LD = malloc(sizeof(double) * sz1);
+    if (!LC || !LD) { free(LC); free(LD); return ORA_ENOMEM; }
+    int rc = ora2d_rhs(p, tau_max, ulC, ulD, LC, LD);
+    for (long e = 0; e < sz1; ++e) {
+        if (l == 0) {   /* c_{00} multiplies u^n = u^{n,0} itself */
+            outC[e] = c[0][0] * ulC[e] + tau * d[0][0] * LC[e];
+            outD[e] = c[0][0] * ulD[e] + tau * d[0][0] * LD[e];
+        } else {
+            outC[e] = c[l][0] * unC[e] + (c[l][l] * ulC[e] + tau * d[l][l] * LC[e]);
+            outD[e] = c[l][0] * unD[e] + (c[l][l] * ulD[e] + tau * d[l][l] * LD[e]);
+        }
+    }
+    if (p->space == 1) {
+        truncate_pk(p, outC);
+        truncate_pk(p, outD);
+    }
+    if (oe && rc == ORA_OK) rc = ora2d_oe(p, tau, outC, outD);
+    if (rc == ORA_OK) rc = check_state(p, outC, outD);
+    free(LC);
+    free(LD);
+    return rc;
+}
+
 /* March until t_end (last step clipped) or nsteps steps (< 0: no limit);
  * tau_max = cfl / (bx/hx + by/hy) from u^n, or dt_fixed when positive. */
 int ora2d_run(const ora2d *p, double cfl, int rk, int oe, double t_end, long nsteps, double dt_fixed,

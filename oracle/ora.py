@@ -94,6 +94,8 @@ def lib():
         L.ora2d_wavespeed.argtypes = [P2, C.c_int, _DP]
         L.ora2d_wavespeed.restype = C.c_double
         L.ora2d_step.argtypes = [P2, C.c_int, C.c_int, C.c_double, C.c_double, _DP, _DP]
+        L.ora2d_rk_stage.argtypes = [P2, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                     _DP, _DP, _DP, _DP, _DP, _DP]
         L.ora2d_run.argtypes = [P2, C.c_double, C.c_int, C.c_int, C.c_double, C.c_long, C.c_double,
                                 _DP, _DP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
         _lib = L
@@ -288,6 +290,16 @@ def step2d(prob, tau, tau_max, uC, uD, rk=3, oe=True):
     uC, uD = _arr(uC).copy(), _arr(uD).copy()
     _check(lib().ora2d_step(C.byref(_p2(prob)), rk, int(oe), tau, tau_max, uC, uD), "step2d")
     return uC, uD
+
+
+def rk_stage2d(prob, rk, l, tau, tau_max, unC, unD, ulC, ulD, oe=True):
+    """One stage l of RK table rk from u^n and u^{n,l}, then F_tau (2D; stages
+    that read only u^n, u^{n,l} and L(u^{n,l}))."""
+    unC, unD, ulC, ulD = _arr(unC), _arr(unD), _arr(ulC), _arr(ulD)
+    oC, oD = np.zeros_like(unC), np.zeros_like(unD)
+    _check(lib().ora2d_rk_stage(C.byref(_p2(prob)), rk, l, int(oe), tau, tau_max, unC, unD, ulC, ulD, oC, oD),
+           "rk_stage2d")
+    return oC, oD
 
 
 def run2d(prob, uC, uD, t_end=float("inf"), nsteps=-1, cfl=0.3, dt_fixed=0.0, rk=3, oe=True):

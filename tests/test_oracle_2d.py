@@ -410,3 +410,24 @@ def test_pk_advection_converges_at_order_k_plus_1(k, rk):
         errs.append(math.sqrt((e ** 2 * (w[:, None] * w[None, :] / 4)).sum() / n ** 2))
     rate = math.log2(errs[0] / errs[1])
     assert rate >= k + 1 - 0.25, (errs, rate)
+
+
+@pytest.mark.parametrize("rk", [1, 2, 3, 4])
+@pytest.mark.parametrize("space", [0, 1])
+def test_single_stages_compose_to_a_step_2d(rk, space):
+    """eq:RKCDG stage by stage in 2D: chaining the single-stage function over
+    the stages of forward Euler, SSP-RK2 and SSP-RK3 gives the oracle's step
+    (both spaces); the last stage of classical RK4 is refused."""
+    prob, uC, uD = inputs.advection2d_sine(6, 2, space=space)
+    tau_max = 0.02
+    tau = 0.9 * tau_max
+    ul = (uC, uD)
+    for l in range(rk):
+        if rk == 4 and l == 3:
+            with pytest.raises(ora.OracleError):
+                ora.rk_stage2d(prob, rk, l, tau, tau_max, uC, uD, *ul)
+            return
+        ul = ora.rk_stage2d(prob, rk, l, tau, tau_max, uC, uD, *ul)
+    rC, rD = ora.step2d(prob, tau, tau_max, uC, uD, rk=rk)
+    np.testing.assert_allclose(ul[0], rC, rtol=1e-14, atol=1e-14 * np.abs(rC).max())
+    np.testing.assert_allclose(ul[1], rD, rtol=1e-14, atol=1e-14 * np.abs(rD).max())
