@@ -97,6 +97,9 @@ int fail(oecdg_handle *h, int code, const std::string &msg) {
             return fail((h), OECDG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
     } while (0)
 
+// Bytes of the step records of nbatch instances followed by the four error flags.
+size_t rec_bytes(int nbatch) { return sizeof(Final) * (size_t)nbatch + 4 * sizeof(int); }
+
 void drop_graphs(oecdg_handle *h) {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec), h->gexec = nullptr;
     for (hipGraphExec_t &g : h->ladder)
@@ -331,14 +334,21 @@ int final_all(oecdg_handle *h, const StageArgs &a) {
     return OECDG_OK;
 }
 
-// Launch the stage kernels of steps n0 .. n0 + count - 1.
-int launch_steps(oecdg_handle *h, const StageArgs &base, long long n0, long long count) {
+// Launch the stage kernels of steps n0 .. n0 + count - 1.  inC/inD (optional):
+// the arrays that the first stage of step 0 reads instead of the stage buffer
+// of index 0 (the caller's initial data, read in place).
+int launch_steps(oecdg_handle *h, const StageArgs &base, long long n0, long long count,
+                 const double *inC = nullptr, const double *inD = nullptr) {
     for (long long n = n0; n < n0 + count; ++n)
         for (int l = 0; l < base.ns; ++l) {
             StageArgs a = base;
             a.l = l;
             a.par = (int)(n & 1);
             a.first = n == 0;
+            if (n == 0 && l == 0 && inC) {   // stage (0, 0) reads the buffer of parity 0
+                a.BC[0] = const_cast<double *>(inC);
+                a.BD[0] = const_cast<double *>(inD);
+            }
             int rc = stage_all(h, a);
             if (rc != OECDG_OK) return rc;
         }
@@ -411,8 +421,7 @@ int launch_remainder(oecdg_handle *h, const StageArgs &base, long long count) {
 
 // Has every instance reached t_end (or an error been flagged)?
 int all_done(oecdg_handle *h, const StageArgs &a, bool &done, long long &exec0) {
-    HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, sizeof(Final) * h->nbatch, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipMemcpyAsync(h->err_h, h->err, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, rec_bytes(h->nbatch), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     exec0 = h->fin_h[0].nexec;
     done = true;
@@ -422,15 +431,18 @@ int all_done(oecdg_handle *h, const StageArgs &a, bool &done, long long &exec0) 
     return OECDG_OK;
 }
 
-// Copy the initial data into the stage buffer, clear the step records and
-// take the statistics that the first stage reads.
-int run_prologue(oecdg_handle *h, const StageArgs &a, const double *uC, const double *uD) {
-    HIPCHK(h, hipMemcpyAsync(a.BC[0], uC, sizeof(double) * h->totC, hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(h, hipMemcpyAsync(a.BD[0], uD, sizeof(double) * h->totD, hipMemcpyDeviceToDevice, h->stream));
+// Copy the initial data into the stage buffer (unless the first stage reads it
+// in place), clear the step records and take the statistics that the first
+// stage reads.
+int run_prologue(oecdg_handle *h, const StageArgs &a, const double *uC, const double *uD, bool copy = true) {
+    if (copy) {
+        HIPCHK(h, hipMemcpyAsync(a.BC[0], uC, sizeof(double) * h->totC, hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(a.BD[0], uD, sizeof(double) * h->totD, hipMemcpyDeviceToDevice, h->stream));
+    }
     HIPCHK(h, launch_init_1d(a, h->nbatch, h->stream));
     StageArgs st = a;
-    st.srcC = a.BC[0];
-    st.srcD = a.BD[0];
+    st.srcC = copy ? a.BC[0] : const_cast<double *>(uC);
+    st.srcD = copy ? a.BD[0] : const_cast<double *>(uD);
     return stats_all(h, st);
 }
 
@@ -438,21 +450,24 @@ int run_prologue(oecdg_handle *h, const StageArgs &a, const double *uC, const do
 constexpr long long kWholeRunSteps = 256;
 
 // A whole short run as one graph: prologue, every step, the final OE into
-// (uC, uD) and the host copies of the step record and the error flags.
+// (uC, uD) and one host copy of the step records and the error flags.  The
+// first stage reads (uC, uD) in place (step 0 always runs: t_end > 0), so the
+// initial data are not copied; a run of no steps copies them, for the final
+// OE to read.
 int run_whole(oecdg_handle *h, const StageArgs &a, double *uC, double *uD, long long limit) {
     key_graphs(h, a);
     if (!h->whole || h->w_uC != uC || h->w_uD != uD || h->w_limit != limit) {
         if (h->whole) (void)hipGraphExecDestroy(h->whole), h->whole = nullptr;
         int rc = capture(h, [&] {
-            int r = run_prologue(h, a, uC, uD);
-            if (r == OECDG_OK) r = launch_steps(h, a, 0, limit);
+            const bool inplace = limit > 0;
+            int r = run_prologue(h, a, uC, uD, !inplace);
+            if (r == OECDG_OK) r = launch_steps(h, a, 0, limit, inplace ? uC : nullptr, inplace ? uD : nullptr);
             StageArgs f = a;
             f.dstC = uC;
             f.dstD = uD;
             if (r == OECDG_OK) r = final_all(h, f);
             if (r != OECDG_OK) return r;
-            HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, sizeof(Final) * h->nbatch, hipMemcpyDeviceToHost, h->stream));
-            HIPCHK(h, hipMemcpyAsync(h->err_h, h->err, 4 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, rec_bytes(h->nbatch), hipMemcpyDeviceToHost, h->stream));
             return (int)OECDG_OK;
         }, &h->whole);
         if (rc != OECDG_OK) return rc;
@@ -529,8 +544,9 @@ int run_1d(oecdg_handle *h, double *uC, double *uD, double t_end, int64_t nsteps
     f.dstD = uD;
     int rcf = final_all(h, f);
     if (rcf != OECDG_OK) return rcf;
-    HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, sizeof(Final) * h->nbatch, hipMemcpyDeviceToHost, h->stream));
-    int rc = check_errors(h);
+    HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, rec_bytes(h->nbatch), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    int rc = errors_from_host(h);
     if (t_out) *t_out = h->fin_h[0].t;
     if (steps_out) *steps_out = h->fin_h[0].nexec;
     return rc;
@@ -863,19 +879,21 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
     } while (0)
     ALLOC(h->inst_d, sizeof(Inst1D) * nbatch);
     ALLOC(h->slots, sizeof(Slot) * 2 * nbatch);
-    ALLOC(h->fin, sizeof(Final) * nbatch);
+    // the step records and, right after them, the four error flags: one block,
+    // so that one copy brings both to the host
+    ALLOC(h->fin, rec_bytes(nbatch));
+    h->err = reinterpret_cast<int *>(reinterpret_cast<char *>(h->fin) + sizeof(Final) * nbatch);
     ALLOC(h->B, sizeof(double) * 2 * (h->totC + h->totD));
     ALLOC(h->U, sizeof(double) * (h->totC + h->totD));
     if (h->rk == 4) ALLOC(h->A, sizeof(double) * (h->totC + h->totD));
-    ALLOC(h->err, sizeof(int) * 4);
     ALLOC(h->bar, sizeof(unsigned) * 2);
     ALLOC(h->red, sizeof(double) * NSTAT * nbatch);
 #undef ALLOC
-    if (hipHostMalloc((void **)&h->fin_h, sizeof(Final) * nbatch, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&h->err_h, sizeof(int) * 4, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&h->fin_h, rec_bytes(nbatch), hipHostMallocDefault) != hipSuccess) {
         oecdg_destroy(h);
         return OECDG_ENOMEM;
     }
+    h->err_h = reinterpret_cast<int *>(reinterpret_cast<char *>(h->fin_h) + sizeof(Final) * nbatch);
     rc = build_tiles(h);
     if (rc != OECDG_OK) {
         oecdg_destroy(h);
@@ -1053,11 +1071,9 @@ void oecdg_destroy(oecdg_handle *h) {
     (void)hipFree(h->B);
     (void)hipFree(h->U);
     (void)hipFree(h->A);
-    (void)hipFree(h->err);
     (void)hipFree(h->bar);
     (void)hipFree(h->red);
     if (h->fin_h) (void)hipHostFree(h->fin_h);
-    if (h->err_h) (void)hipHostFree(h->err_h);
     if (h->ext2d) {
         oecdg::destroy_2d(h);
     }
