@@ -459,16 +459,19 @@ def cpu_all_cores(seconds: float, nproc: int):
     import subprocess
     code = _CPU_WORKER.format(root=ROOT, n=N_CELLS, k=DEGREE, seed=SEED, cfl=CFL, t_end=T_END, seconds=seconds)
     env = dict(os.environ, OMP_NUM_THREADS="1")
-    procs = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
-                              text=True, env=env) for _ in range(nproc)]
     rates, steps = [], []
-    for p in procs:
-        out, err = p.communicate(timeout=600)
-        if p.returncode != 0:
-            return {"error": f"worker exited with {p.returncode}: {err.strip()[-200:]}"}
-        r, d = out.split()
-        rates.append(float(r))
-        steps.append(int(d))
+    try:
+        procs = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                  text=True, env=env) for _ in range(nproc)]
+        for p in procs:
+            out, err = p.communicate(timeout=600)
+            if p.returncode != 0:
+                return {"error": f"worker exited with {p.returncode}: {err.strip()[-200:]}"}
+            r, d = out.split()
+            rates.append(float(r))
+            steps.append(int(d))
+    except (OSError, ValueError, subprocess.SubprocessError) as e:
+        return {"error": f"workers failed: {e}"}
     return {"value": sum(rates), "unit": "DOF-updates/s", "cores": nproc, "kind": "oracle",
             "sample": f"{nproc} processes, each the first {min(steps)}-{max(steps)} steps of its own copy of the "
                       f"workload (about {seconds:.0f} s each), rates summed"}

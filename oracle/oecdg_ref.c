@@ -298,7 +298,8 @@ int oecdg_ref_run(oecdg_ref_handle *h, double *uC, double *uD, double t_end, int
                   double *t_out, int64_t *steps_out)
 {
     if (!h || !uC || !uD) return REF_EINVAL;
-    if (!(t_end >= 0.0) || (isinf(t_end) && nsteps < 0)) return fail(h, REF_EINVAL, "the run has no end");
+    if (nsteps < 0 && !(t_end < INFINITY)) return fail(h, REF_EINVAL, "run needs a finite t_end or nsteps >= 0");
+    if (!(t_end > 0.0)) return fail(h, REF_EINVAL, "t_end must be positive");
     for (int i = 0; i < h->n; ++i)
         if (h->d[i].bc == 3 && !h->inflow_set[i]) return fail(h, REF_EINVAL, "inflow states not set");
     for (int i = 0; i < h->n; ++i) {
@@ -342,7 +343,8 @@ int oecdg_ref_run_nonuniform(oecdg_ref_handle *h, const double *edges, double *u
     const oecdg_ref_desc *d = &h->d[0];
     if (h->n != 1 || d->dim != 1 || d->bc != 0 || rk_of(d) == 4)
         return fail(h, REF_EUNSUPPORTED, "one periodic 1D instance with rk 0..3");
-    if (!(t_end >= 0.0) || (isinf(t_end) && nsteps < 0)) return fail(h, REF_EINVAL, "the run has no end");
+    if (nsteps < 0 && !(t_end < INFINITY)) return fail(h, REF_EINVAL, "run needs a finite t_end or nsteps >= 0");
+    if (!(t_end > 0.0)) return fail(h, REF_EINVAL, "t_end must be positive");
     ora1d p = prob1(h, 0);
     double t = 0.0;
     long s = 0;
