@@ -4,11 +4,13 @@
 // [i0, i0+T) that interleave with them (dual cell j is centred on the left
 // edge of primal cell j), one thread per cell, and one more wave whose lanes
 // take the cells next to the tile that its operator reads (the primal cells
-// i0-1 and i0+T, the dual cell i0+T).  A stage kernel for stage l of step n
+// i0-1 and i0+T, the dual cell i0+T) and the dual cells i0-1 and i0+T+1 that
+// the damping of those primal cells reads.  A stage kernel for stage l of step n
 //   1. issues every independent load at once: the step records, the previous
-//      stage's per-tile partial statistics, and each thread's cell and the two
-//      cells of the other mesh that overlap it, all undamped (ghost cells at
-//      non-periodic ends built from the end cells);
+//      stage's per-tile partial statistics, each thread's cell, undamped (ghost
+//      cells at non-periodic ends built from the end cells), and its u^n; the
+//      undamped cells go to an LDS image, from which each thread takes the two
+//      cells of the other mesh that overlap its own;
 //   2. reduces the partial statistics (fixed order, so every workgroup gets
 //      bit-identical avg/sigma/beta), and at l = 0 derives tau^n and
 //      tau_max^n (Sec. 2.1, tau = C h / beta);
@@ -23,7 +25,8 @@
 //   5. forms the RK combination of eq:RKCDG (SSP-RK3 by default; forward
 //      Euler, SSP-RK2 or classical RK4 on request) and writes the stage output;
 //   6. writes the tile's partial statistics of that output for the next stage
-//      (DPP reductions within the waves that hold each mesh).
+//      (DPP reductions within the waves that hold each mesh; the wave speeds
+//      only after a step's last stage, the one whose output sets the next tau).
 // The OE of the last stage of a run is applied by the final kernel.
 #include "oecdg_device.h"
 #include "oecdg_internal.h"
@@ -477,7 +480,7 @@ constexpr int scratch_doubles(int T) { return NSTAT * ((nthreads(T) + WAVE - 1) 
 // ---------------------------------------------------------- stage tile ---
 
 // folded: the instance's statistics were reduced by k_fold into a.red (batched
-// launches); otherwise every workgroup reduces the partial columns itself.
+// launches); otherwise every workgroup reduces the per-tile records itself.
 // COH: the persistent launch, whose step records other workgroups of the same
 // launch write (read with device-scope atomic loads after the grid barrier).
 template <int K, int FLUX, int T, bool COH = false>
