@@ -212,6 +212,37 @@ def test_execution_modes_bitwise_identical(tile):
     assert _rel(outs[0][0], outs[0][1], rC, rD) <= RUN_TOL
 
 
+@pytest.mark.parametrize("nsteps", [1, 30, 256])
+def test_short_run_graph_matches_eager_bitwise(nsteps):
+    """Runs of at most 256 steps replay one captured graph whose first stage
+    reads the caller's arrays in place (no copy of the initial data); eager
+    launches copy them first.  Same bits, same steps and time, and the
+    oracle's result; the graph is replayed on the same arrays a second time."""
+    prob, uC, uD = inputs.euler_riemann(2500, 2, inputs.riemann_states(6))
+    ref = gpu_run(prob, uC, uD, 0.15, mode=_lib.MODE_EAGER, nsteps=nsteps)
+    with OECDG(prob, 0.15) as s:
+        gC, gD = to_device(uC), to_device(uD)
+        for rep in range(2):
+            gC.copy_(to_device(uC))
+            gD.copy_(to_device(uD))
+            t, n = s.run(gC, gD, nsteps=nsteps)
+            oC, oD = gC.cpu().numpy().reshape(uC.shape), gD.cpu().numpy().reshape(uD.shape)
+            assert (t, n) == (ref[2], ref[3]) and n == nsteps
+            assert np.array_equal(oC, ref[0]) and np.array_equal(oD, ref[1]), rep
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, nsteps=nsteps, cfl=0.15)
+    assert rn == nsteps and _rel(ref[0], ref[1], rC, rD) <= RUN_TOL
+
+
+@pytest.mark.parametrize("mode", [_lib.MODE_EAGER, _lib.MODE_GRAPH])
+def test_zero_steps_leave_the_state_unchanged(mode):
+    """nsteps = 0: no stage runs, so no OE is applied either (the initial data
+    are u_sigma^0); the arrays come back bitwise, at t = 0 and no steps."""
+    prob, uC, uD = inputs.euler_riemann(700, 3, inputs.riemann_states(8))
+    oC, oD, t, n = gpu_run(prob, uC, uD, 0.15, mode=mode, nsteps=0, t_end=0.1)
+    assert (t, n) == (0.0, 0)
+    assert np.array_equal(oC, uC) and np.array_equal(oD, uD)
+
+
 def test_repeat_runs_are_deterministic():
     prob, uC, uD = inputs.euler_riemann(4096, 3, inputs.riemann_states(3))
     a = gpu_run(prob, uC, uD, 0.15, nsteps=40)
