@@ -835,10 +835,33 @@ __global__ __launch_bounds__(nthreads(T)) void k_fold(StageArgs a, int src) {
     if (tid < NSTAT) a.red[(long long)b * NSTAT + tid] = red[tid];
 }
 
+// Step records (both parities), final record of instance i, and with i = 0
+// the error flags and the grid-barrier counters, cleared: the start of a run.
+__device__ inline void clear_records(const StageArgs &a, int i, int ninst) {
+    if (i < ninst) {
+        a.slots[2 * i].t = 0.0;
+        a.slots[2 * i].tau = 0.0;
+        a.slots[2 * i].tau_max = 0.0;
+        a.slots[2 * i].done = 0;
+        a.slots[2 * i].last = 0;
+        a.slots[2 * i + 1] = a.slots[2 * i];
+        a.fin[i].t = 0.0;
+        a.fin[i].tau = 0.0;
+        a.fin[i].nexec = 0;
+    }
+    if (i == 0) {
+        a.err[0] = a.err[1] = a.err[2] = a.err[3] = 0;
+        a.bar[0] = 0;
+        a.bar[1] = 0;
+    }
+}
+
 template <int KM, int FLUX, int T, bool XW>
 __global__ __launch_bounds__(nthreads(T)) void k_stats(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
+    if (a.init_records && blockIdx.x == 0)   // a run's start: no kernel of its own for the records
+        for (int i = threadIdx.x; i < a.ninst; i += blockDim.x) clear_records(a, i, a.ninst);
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
         D::template run<StatsFn>(a, tile, smem, XW);
     }
@@ -848,6 +871,10 @@ template <int KM, int FLUX, int T, bool XW>
 __global__ __launch_bounds__(nthreads(T)) void k_final(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
+    if (a.fin_host && blockIdx.x == 0) {     // the run's records (complete: the stages wrote them) to the host
+        for (int i = threadIdx.x; i < a.ninst; i += blockDim.x) a.fin_host[i] = a.fin[i];
+        if (threadIdx.x < 4) a.err_host[threadIdx.x] = a.err[threadIdx.x];
+    }
     for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
         D::template run<FinalFn>(a, tile, smem, XW);
     }
@@ -902,23 +929,7 @@ __global__ __launch_bounds__(nthreads(T)) void k_persistent(StageArgs a, long lo
 }
 
 __global__ void k_init(StageArgs a, int ninst) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ninst) {
-        a.slots[2 * i].t = 0.0;
-        a.slots[2 * i].tau = 0.0;
-        a.slots[2 * i].tau_max = 0.0;
-        a.slots[2 * i].done = 0;
-        a.slots[2 * i].last = 0;
-        a.slots[2 * i + 1] = a.slots[2 * i];
-        a.fin[i].t = 0.0;
-        a.fin[i].tau = 0.0;
-        a.fin[i].nexec = 0;
-    }
-    if (i == 0) {
-        a.err[0] = a.err[1] = a.err[2] = a.err[3] = 0;
-        a.bar[0] = 0;
-        a.bar[1] = 0;
-    }
+    clear_records(a, blockIdx.x * blockDim.x + threadIdx.x, ninst);
 }
 
 // ------------------------------------------------------------ host side ---

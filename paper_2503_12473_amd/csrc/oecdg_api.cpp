@@ -55,9 +55,12 @@ struct oecdg_handle {
     int *err = nullptr;
     unsigned *bar = nullptr;
     double *red = nullptr;   // [nbatch][NSTAT] statistics folded by k_fold
-    // pinned host mirrors
+    // pinned host mirrors (one block: records, then flags), host-coherent and
+    // mapped: the final kernel of a short run writes them directly
     Final *fin_h = nullptr;
     int *err_h = nullptr;
+    Final *fin_hd = nullptr;     // device addresses of the same memory
+    int *err_hd = nullptr;
 
     // captured graphs, all for one key (t_end, dt_fixed, tile, graph_steps, fold):
     // graph_steps steps, and 2^j steps (the remainder of a run), both from an
@@ -314,21 +317,29 @@ int stage_all(oecdg_handle *h, const StageArgs &a) {
     return OECDG_OK;
 }
 
+// (a.init_records: the first launch also clears the step records)
 int stats_all(oecdg_handle *h, const StageArgs &a) {
+    bool first = true;
     for (const auto &g : h->groups) {
         StageArgs b = a;
         b.tbeg = g.tbeg;
         b.tend = g.tend;
+        b.init_records = first ? a.init_records : 0;
+        first = false;
         HIPCHK(h, launch_stats_1d(b, g.k, h->flux, h->tile, h->stream));
     }
     return OECDG_OK;
 }
 
+// (a.fin_host: the first launch also copies the records to the host)
 int final_all(oecdg_handle *h, const StageArgs &a) {
+    bool first = true;
     for (const auto &g : h->groups) {
         StageArgs b = a;
         b.tbeg = g.tbeg;
         b.tend = g.tend;
+        if (!first) b.fin_host = nullptr, b.err_host = nullptr;
+        first = false;
         HIPCHK(h, launch_final_1d(b, g.k, h->flux, h->tile, h->stream));
     }
     return OECDG_OK;
@@ -439,21 +450,22 @@ int run_prologue(oecdg_handle *h, const StageArgs &a, const double *uC, const do
         HIPCHK(h, hipMemcpyAsync(a.BC[0], uC, sizeof(double) * h->totC, hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(a.BD[0], uD, sizeof(double) * h->totD, hipMemcpyDeviceToDevice, h->stream));
     }
-    HIPCHK(h, launch_init_1d(a, h->nbatch, h->stream));
     StageArgs st = a;
     st.srcC = copy ? a.BC[0] : const_cast<double *>(uC);
     st.srcD = copy ? a.BD[0] : const_cast<double *>(uD);
+    st.init_records = 1;                     // the step records cleared by the statistics kernel
     return stats_all(h, st);
 }
 
 // Runs of at most this many steps are replayed as one captured graph.
 constexpr long long kWholeRunSteps = 256;
 
-// A whole short run as one graph: prologue, every step, the final OE into
-// (uC, uD) and one host copy of the step records and the error flags.  The
-// first stage reads (uC, uD) in place (step 0 always runs: t_end > 0), so the
-// initial data are not copied; a run of no steps copies them, for the final
-// OE to read.
+// A whole short run as one graph: the statistics of u^0 (whose kernel also
+// clears the step records), every step, and the final OE into (uC, uD), whose
+// kernel also writes the step records and the error flags into the host's
+// mapped copy of them.  The first stage reads (uC, uD) in place (step 0 always
+// runs: t_end > 0), so the initial data are not copied; a run of no steps
+// copies them, for the final OE to read.
 int run_whole(oecdg_handle *h, const StageArgs &a, double *uC, double *uD, long long limit) {
     key_graphs(h, a);
     if (!h->whole || h->w_uC != uC || h->w_uD != uD || h->w_limit != limit) {
@@ -465,10 +477,10 @@ int run_whole(oecdg_handle *h, const StageArgs &a, double *uC, double *uD, long 
             StageArgs f = a;
             f.dstC = uC;
             f.dstD = uD;
+            f.fin_host = h->fin_hd;          // the final kernel writes the records to the host
+            f.err_host = h->err_hd;
             if (r == OECDG_OK) r = final_all(h, f);
-            if (r != OECDG_OK) return r;
-            HIPCHK(h, hipMemcpyAsync(h->fin_h, h->fin, rec_bytes(h->nbatch), hipMemcpyDeviceToHost, h->stream));
-            return (int)OECDG_OK;
+            return r;
         }, &h->whole);
         if (rc != OECDG_OK) return rc;
         h->w_uC = uC;
@@ -889,11 +901,14 @@ int oecdg_init(const oecdg_desc *d, int32_t nbatch, void *stream, oecdg_handle *
     ALLOC(h->bar, sizeof(unsigned) * 2);
     ALLOC(h->red, sizeof(double) * NSTAT * nbatch);
 #undef ALLOC
-    if (hipHostMalloc((void **)&h->fin_h, rec_bytes(nbatch), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&h->fin_h, rec_bytes(nbatch), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&h->fin_hd, h->fin_h, 0) != hipSuccess) {
         oecdg_destroy(h);
         return OECDG_ENOMEM;
     }
     h->err_h = reinterpret_cast<int *>(reinterpret_cast<char *>(h->fin_h) + sizeof(Final) * nbatch);
+    h->err_hd = reinterpret_cast<int *>(reinterpret_cast<char *>(h->fin_hd) + sizeof(Final) * nbatch);
     rc = build_tiles(h);
     if (rc != OECDG_OK) {
         oecdg_destroy(h);

@@ -120,6 +120,9 @@ struct StageArgs {
     // final / statistics kernels
     const double *srcC, *srcD;
     double *dstC, *dstD;
+    int init_records;        // statistics kernel: also clear the step records and error flags (a run's start)
+    Final *fin_host;         // final kernel, when set: the step records and error flags copied to these
+    int *err_host;           //   host-mapped arrays (device addresses of pinned host memory)
     // persistent launch
     unsigned *bar;           // [0] arrival count, [1] generation
     long long spin_limit;
