@@ -521,7 +521,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     const bool need_beta = l == 0 && !single && a.dt_fixed <= 0.0;
     const bool need_red = damp || need_beta;
     const int ns = need_beta ? Partials<NC>::NS : Partials<NC>::NS - 2;
-    const RKStage rs = rk_stage(a.rk, l);
+    const RKStage rs = COH ? rk_stage(a.rk, l) : a.rs;   // (l = a.l outside the persistent launch)
     double *AM = (rs.acc_read || rs.ca != 0.0) ? (c.mesh == 0 ? a.AC + I.offC : a.AD + I.offD) : nullptr;
 
     // One round trip for every load that does not depend on another (issued
@@ -1013,11 +1013,13 @@ hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, int tile, hip
 hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, int tile, int grid, hipStream_t s) {
     int ti = kernel_index(tile, a.tailwave);
     if (ti < 0) return hipErrorInvalidValue;
+    StageArgs b = a;
+    b.rs = rk_stage(a.rk, a.l);              // the stage's coefficients, ready in the kernel arguments
     if (a.red) {                             // statistics folded by launch_fold_1d
         if (a.tailwave) return hipErrorInvalidValue;
-        return launch(pick<4>(kmax, flux, ti), grid > 0 ? grid : a.tend - a.tbeg, tile, a, s);
+        return launch(pick<4>(kmax, flux, ti), grid > 0 ? grid : b.tend - b.tbeg, tile, b, s);
     }
-    return launch(pick<0>(kmax, flux, ti), grid > 0 ? grid : a.tend - a.tbeg, tile, a, s);
+    return launch(pick<0>(kmax, flux, ti), grid > 0 ? grid : b.tend - b.tbeg, tile, b, s);
 }
 
 int folded_grid_1d(int k, int flux, int tile) {

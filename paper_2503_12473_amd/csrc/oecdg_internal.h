@@ -106,6 +106,7 @@ struct StageArgs {
     double *red;             // batched launches: [ninst][NSTAT] statistics reduced by k_fold (else null)
     int *err;                // [0] non-finite, [1] non-physical, [2] barrier timeout, [3] step+1 of an error
     int rk, ns;              // RK method (rk_stage) and its stages per step
+    RKStage rs;              // rk_stage(rk, l), set by the stage launcher (the persistent launch forms its own)
     int tailwave;            // launches carry one more wave, for the dual cell np of tail tiles
     int l;                   // stage of the step (0 .. ns-1)
     int par;                 // parity of the step index n
