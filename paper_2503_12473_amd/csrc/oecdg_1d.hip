@@ -705,7 +705,7 @@ __device__ void stage_tile(const StageArgs &a, int l, int par, int first, int ti
     // the wave speeds only where a step's tau reads them: after its last stage
     // (a single-stage call writes them always)
     tile_partials<K, FLUX, T>(I, c, out, a.part[sp], tile, scratch, xcell, !skip, single || l == a.ns - 1);
-    if (tile + (int)gridDim.x < a.tend) __syncthreads();   // the workgroup's next tile reuses the LDS
+    if (tile + (int)gridDim.x < a.tend) __syncthreads();   // (persistent launch) the next tile reuses the LDS
 }
 
 // Statistics of a given state (srcC/srcD) into part[1]: the partials that the
@@ -798,25 +798,28 @@ template <int K, int FLUX, int T> struct FinalFn {
     }
 };
 
+// One tile per workgroup (launched with one workgroup per tile): no loop
+// keeps the stage's uniform values alive across tiles, which had spilled them
+// from scalar registers into vector lanes.
 template <int KM, int FLUX, int T, bool XW>
 __global__ __launch_bounds__(nthreads(T)) void k_stage(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
-    for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x) {
-        D::template run<StageFn>(a, a.l, a.par, a.first, tile, smem, XW, false);
-    }
+    const int tile = a.tbeg + blockIdx.x;
+    if (tile < a.tend) D::template run<StageFn>(a, a.l, a.par, a.first, tile, smem, XW, false);
 }
 
 // The stage kernel of batched launches (one degree per launch): the
 // instance's statistics come reduced from k_fold (one fixed-order reduction
 // per instance and stage) instead of every workgroup reducing all of its
-// instance's partial columns, and a workgroup walks the tiles tbeg +
-// blockIdx.x, + gridDim.x, ...
+// instance's per-tile records.  One tile per workgroup, as in k_stage: a
+// loop over tiles kept the stage's uniform values alive across iterations
+// and spilled them from scalar registers into vector lanes.
 template <int K, int FLUX, int T>
 __global__ __launch_bounds__(nthreads(T), T == 64 && K <= 2 ? 3 : 1) void k_stage_folded(StageArgs a) {
     __shared__ double smem[lds_doubles(K, FluxT<FLUX>::NC, T) + scratch_doubles(T)];
-    for (int tile = a.tbeg + blockIdx.x; tile < a.tend; tile += gridDim.x)
-        stage_tile<K, FLUX, T>(a, a.l, a.par, a.first, tile, smem, false, true);
+    const int tile = a.tbeg + blockIdx.x;     // one tile per workgroup
+    if (tile < a.tend) stage_tile<K, FLUX, T>(a, a.l, a.par, a.first, tile, smem, false, true);
 }
 
 // One workgroup per instance: the partial columns of the state the next stage
@@ -1010,28 +1013,16 @@ hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, int tile, hip
     return launch(pick<1>(kmax, flux, ti), a.tend - a.tbeg, tile, a, s);
 }
 
-hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, int tile, int grid, hipStream_t s) {
+hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, int tile, hipStream_t s) {
     int ti = kernel_index(tile, a.tailwave);
     if (ti < 0) return hipErrorInvalidValue;
     StageArgs b = a;
     b.rs = rk_stage(a.rk, a.l);              // the stage's coefficients, ready in the kernel arguments
     if (a.red) {                             // statistics folded by launch_fold_1d
         if (a.tailwave) return hipErrorInvalidValue;
-        return launch(pick<4>(kmax, flux, ti), grid > 0 ? grid : b.tend - b.tbeg, tile, b, s);
+        return launch(pick<4>(kmax, flux, ti), b.tend - b.tbeg, tile, b, s);   // one workgroup per tile
     }
-    return launch(pick<0>(kmax, flux, ti), grid > 0 ? grid : b.tend - b.tbeg, tile, b, s);
-}
-
-int folded_grid_1d(int k, int flux, int tile) {
-    const int ti = tile_index(tile);
-    if (ti < 0) return 0;
-    int per_cu = 0, dev = 0, ncu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick<4>(k, flux, ti), nthreads(tile), 0) !=
-        hipSuccess)
-        return 0;
-    return per_cu * ncu;
+    return launch(pick<0>(kmax, flux, ti), b.tend - b.tbeg, tile, b, s);   // one workgroup per tile
 }
 
 hipError_t launch_fold_1d(const StageArgs &a, int flux, int tile, hipStream_t s) {

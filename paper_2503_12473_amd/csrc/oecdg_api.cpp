@@ -28,7 +28,6 @@ struct oecdg_handle {
     std::vector<Tile1D> tiles_h;
     struct Group {
         int k, tbeg, tend;
-        int fgrid;           // workgroups of the folded stage launch (0: not yet known)
     };
     std::vector<Group> groups;   // tiles ordered by degree: one launch per degree
     std::vector<int64_t> offC, offD;
@@ -221,7 +220,7 @@ int build_tiles(oecdg_handle *h) {
             ncol += I.npart;
             for (int t = 0; t < I.ntiles; ++t) h->tiles_h.push_back(Tile1D{b, t * T});
         }
-        if ((int)h->tiles_h.size() > tbeg) h->groups.push_back({k, tbeg, (int)h->tiles_h.size(), 0});
+        if ((int)h->tiles_h.size() > tbeg) h->groups.push_back({k, tbeg, (int)h->tiles_h.size()});
     }
     if (h->tiles_d) (void)hipFree(h->tiles_d), h->tiles_d = nullptr;
     if (h->part) (void)hipFree(h->part), h->part = nullptr;
@@ -298,21 +297,15 @@ int check_errors(oecdg_handle *h) {
 }
 
 // One launch per degree group (tiles [tbeg, tend) of equal k), after the
-// per-instance fold of the statistics when the stage kernels read it.
-// The folded stage kernel walks its tiles with as many workgroups as fit the
-// GPU at once (each loads its next tile while computing the current one).
+// per-instance fold of the statistics when the stage kernels read it; one
+// workgroup per tile.
 int stage_all(oecdg_handle *h, const StageArgs &a) {
     if (a.red) HIPCHK(h, launch_fold_1d(a, h->flux, h->tile, h->stream));
     for (auto &g : h->groups) {
         StageArgs b = a;
         b.tbeg = g.tbeg;
         b.tend = g.tend;
-        int grid = 0;
-        if (a.red) {
-            if (g.fgrid == 0) g.fgrid = folded_grid_1d(g.k, h->flux, h->tile);
-            grid = std::min(g.fgrid, g.tend - g.tbeg);
-        }
-        HIPCHK(h, launch_stage_1d(b, g.k, h->flux, h->tile, grid, h->stream));
+        HIPCHK(h, launch_stage_1d(b, g.k, h->flux, h->tile, h->stream));
     }
     return OECDG_OK;
 }
@@ -651,7 +644,7 @@ int oecdg::adjoint_1d(oecdg_handle *h, const double *uC0, const double *uD0, int
             StageArgs c = a;
             c.tbeg = g.tbeg;
             c.tend = g.tend;
-            HIPCHK(h, launch_stage_1d(c, g.k, h->flux, h->tile, 0, s));
+            HIPCHK(h, launch_stage_1d(c, g.k, h->flux, h->tile, s));
         }
         return (int)OECDG_OK;
     };

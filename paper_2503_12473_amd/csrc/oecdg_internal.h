@@ -156,9 +156,8 @@ int adj_waves();
 // Host-side launchers (oecdg_1d.hip).
 hipError_t launch_init_1d(const StageArgs &a, int ninst, hipStream_t s);
 hipError_t launch_stats_1d(const StageArgs &a, int kmax, int flux, int tile, hipStream_t s);
-hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, int tile, int grid, hipStream_t s);
+hipError_t launch_stage_1d(const StageArgs &a, int kmax, int flux, int tile, hipStream_t s);   // one workgroup per tile
 hipError_t launch_fold_1d(const StageArgs &a, int flux, int tile, hipStream_t s);
-int folded_grid_1d(int k, int flux, int tile);   // resident workgroups of the folded stage kernel (0: unknown)
 hipError_t launch_final_1d(const StageArgs &a, int kmax, int flux, int tile, hipStream_t s);
 hipError_t launch_persistent_1d(const StageArgs &a, int kmax, int flux, int tile, int grid,
                                 long long nsteps, hipStream_t s);

@@ -156,7 +156,7 @@ int oecdg_run_noalloc(const oecdg_desc *d, void *stream, double *uC, double *uD,
                 b.l = l;
                 b.par = (int)(j & 1);
                 b.first = j == 0;
-                NACHK(launch_stage_1d(b, I.k, flux, T, 0, s));
+                NACHK(launch_stage_1d(b, I.k, flux, T, s));
             }
         n += chunk;
         NACHK(hipMemcpyAsync(&fh, fin, sizeof(Final), hipMemcpyDeviceToHost, s));
