@@ -805,7 +805,7 @@ template <int KM, int FLUX, int T, bool XW>
 __global__ __launch_bounds__(nthreads(T)) void k_stage(StageArgs a) {
     using D = Disp<KM, FLUX, T>;
     __shared__ double smem[D::LDS];
-    const int tile = a.tbeg + blockIdx.x;
+    const int tile = a.tbeg + xcd_tile(blockIdx.x, a.tend - a.tbeg);
     if (tile < a.tend) D::template run<StageFn>(a, a.l, a.par, a.first, tile, smem, XW, false);
 }
 
@@ -818,7 +818,7 @@ __global__ __launch_bounds__(nthreads(T)) void k_stage(StageArgs a) {
 template <int K, int FLUX, int T>
 __global__ __launch_bounds__(nthreads(T), T == 64 && K <= 2 ? 3 : 1) void k_stage_folded(StageArgs a) {
     __shared__ double smem[lds_doubles(K, FluxT<FLUX>::NC, T) + scratch_doubles(T)];
-    const int tile = a.tbeg + blockIdx.x;     // one tile per workgroup
+    const int tile = a.tbeg + xcd_tile(blockIdx.x, a.tend - a.tbeg);     // one tile per workgroup
     if (tile < a.tend) stage_tile<K, FLUX, T>(a, a.l, a.par, a.first, tile, smem, false, true);
 }
 

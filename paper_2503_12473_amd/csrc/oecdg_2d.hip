@@ -230,12 +230,8 @@ __device__ inline double edge_val(double v1, int n, int d, int side) { return (s
 // ---------------------------------------------------------- tile kernels ---
 
 // Tile of primal cells [i0, i0+TX) x [j0, j0+TY) and the dual cells with the
-// same indices; a band of consecutive tiles per XCD (workgroups are dealt to
-// the 8 XCDs round robin, neighbouring tiles then share an L2).
-__device__ inline int tile_of_block(int nt) {
-    const int b = blockIdx.x;
-    return (nt % 8 == 0) ? (b % 8) * (nt / 8) + b / 8 : b;
-}
+// same indices; a band of consecutive tiles per XCD (xcd_tile).
+__device__ inline int tile_of_block(int nt) { return xcd_tile(blockIdx.x, nt); }
 
 // Both meshes' state of a tile with a one-cell halo into LDS:
 // tile[(mesh*NE + entry)*NCELL + ly*W + lx], global cell (i0-1+lx, j0-1+ly).

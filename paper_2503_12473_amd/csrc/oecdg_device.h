@@ -80,6 +80,19 @@ __device__ inline Slot ld_slot(const Slot *p, bool coherent) {
     return s;
 }
 
+// ------------------------------------------------------ tiles and XCDs ---
+// Workgroup b of a launch over n tiles -> its tile (offset from the first).
+// Workgroups are dealt to the 8 XCDs in turn (XCD b mod 8), so XCD x gets
+// the band of consecutive tiles that starts at x*q + min(x, r) (q = n / 8,
+// r = n mod 8; a bijection on [0, n)).  Neighbouring tiles read the cache
+// lines at their common edge (planes whose length is not a multiple of 16
+// doubles share a line at every tile edge); in one band they fetch them into
+// one L2.
+__device__ inline int xcd_tile(int b, int n) {
+    const int x = b & 7, j = b >> 3, q = n >> 3, r = n & 7;
+    return x * q + (x < r ? x : r) + j;
+}
+
 // ------------------------------------------------------------- reductions ---
 
 __device__ inline int stat_kind(int j) { return j >= ST_BETA ? 1 : j % 3; }

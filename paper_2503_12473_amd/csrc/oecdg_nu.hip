@@ -311,6 +311,10 @@ __device__ inline void nu_cell_stats(const NuArgs &a, const NuGeo &g, const doub
     }
 }
 
+// The block of CPB cells of this workgroup (a band of consecutive blocks per
+// XCD); it also names the workgroup's column of the partial statistics.
+__device__ inline int nu_block(const NuArgs &a) { return xcd_tile(blockIdx.x, a.nblk); }
+
 // One wave's reduction of its cells' partial rows (waves 0 and 1 hold one mesh
 // each; wave 2 owns no cell) into the workgroup's column of the partials of
 // parity gp.
@@ -323,7 +327,7 @@ __device__ inline void nu_store_partials(const NuArgs &a, int gp, int M, double 
     for (int r = 0; r < RW; ++r) {
         const int kd = r == RW - 1 ? 1 : r % 3;
         const double v = wave_reduce(kd, st[r]);
-        if (threadIdx.x % WAVE == WAVE - 1) part[((long long)M * RW + r) * a.nblk + blockIdx.x] = v;
+        if (threadIdx.x % WAVE == WAVE - 1) part[((long long)M * RW + r) * a.nblk + nu_block(a)] = v;
     }
 }
 
@@ -338,7 +342,7 @@ struct NuCell {
 __device__ inline NuCell nu_cell(const NuArgs &a) {
     NuCell c;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int i0 = blockIdx.x * CPB, span = min(a.n, i0 + CPB) - i0;
+    const int i0 = nu_block(a) * CPB, span = min(a.n, i0 + CPB) - i0;
     int i;
     if (wave < 2) {
         c.M = wave;
