@@ -101,8 +101,25 @@ __device__ inline double stat_identity(int kind) {
     return kind == 0 ? 0.0 : (kind == 1 ? -INFINITY : INFINITY);
 }
 
+// Maximum and minimum of two doubles as the bare v_max_f64 / v_min_f64.
+// fmax and fmin first canonicalize each operand that the compiler cannot prove
+// canonical (every DPP move and every load: one more dependent instruction per
+// level of a reduction tree).  For all inputs except signalling NaNs, which no
+// arithmetic here produces, the bare instruction returns what fmax and fmin
+// return.
+__device__ inline double max_d(double x, double y) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
+    return r;
+}
+__device__ inline double min_d(double x, double y) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
+    return r;
+}
+
 __device__ inline double stat_op(int kind, double x, double y) {
-    return kind == 0 ? x + y : (kind == 1 ? fmax(x, y) : fmin(x, y));
+    return kind == 0 ? x + y : (kind == 1 ? max_d(x, y) : min_d(x, y));
 }
 
 // Cross-lane data movement with DPP (plain VALU operations, no LDS round
