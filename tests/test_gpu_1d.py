@@ -463,3 +463,16 @@ def test_large_mesh_folds_its_statistics():
     # evaluate on states that agree to rounding: the time agrees to rounding
     assert outs[0][3] == rn and abs(outs[0][2] - rt) <= 1e-12 * rt
     assert _rel(outs[0][0], outs[0][1], rC, rD) <= RUN_TOL
+
+
+@pytest.mark.parametrize("ntiles", range(9, 17))
+def test_every_tile_count_mod_8(ntiles):
+    """Workgroups are mapped to tiles in one band of consecutive tiles per XCD
+    (8 bands, the first n mod 8 of them one tile longer): tile counts 9..16
+    cover every residue mod 8.  Euler, outflow, P2, N = 64 ntiles - 5 (the last
+    tile ragged on both meshes), 4 steps against the oracle."""
+    prob, uC, uD = inputs.euler_riemann(64 * ntiles - 5, 2, inputs.riemann_states(ntiles))
+    gC, gD, t, n = gpu_run(prob, uC, uD, 0.15, tile=64, nsteps=4)
+    rC, rD, rt, rn = ora.run1d(prob, uC, uD, nsteps=4, cfl=0.15)
+    assert n == rn == 4 and t == pytest.approx(rt, rel=1e-14)
+    assert _rel(gC, gD, rC, rD) <= RUN_TOL
