@@ -860,9 +860,12 @@ __global__ __launch_bounds__(8 * TX * TY, K == 3 ? 2 : 4) void k_delta2d(Stage2A
             vals[3 * q + 2] = mn;
         }
         if (lane4 == 0) {
-            vals[NM] = F::speed(0, ubar, a.fp);
-            vals[NM + 1] = F::speed(1, ubar, a.fp);
-            if (!F::physical(ubar, a.fp)) a.err[1] = 1;
+            double ub[NC];                // the cell averages again from LDS: not kept live across the numerators
+#pragma unroll
+            for (int q = 0; q < NC; ++q) ub[q] = own[(q * K1 * K1) * NCELL + cell];
+            vals[NM] = F::speed(0, ub, a.fp);
+            vals[NM + 1] = F::speed(1, ub, a.fp);
+            if (!F::physical(ub, a.fp)) a.err[1] = 1;
         }
     }
     {
